@@ -1,0 +1,211 @@
+"""Seeded synthetic problem data for the two-level BPJD eigensolver.
+
+This module only *generates inputs*: uniform right-triangle meshes with every
+cell cut by its "/" diagonal, the nested coarse mesh (its grid lines), the P1
+stiffness and consistent mass matrices of the fine mesh (Section 2.2 of the
+paper: a(u,v) = int a grad u . grad v, b(u,v) = int u v, homogeneous Dirichlet
+data), optional piecewise-constant coefficients, and seeded random blocks.
+It holds no step of the eigensolver itself (no restriction, coarse space,
+preconditioner, orthogonalisation or Rayleigh-Ritz): the library and the test
+oracle each implement those on their own and both read what is made here.
+
+Matrices are returned as scipy CSR on the *union* pattern of K and M: the
+hypotenuse couplings of the right triangles are exact zeros in K but not in M,
+so K stores them as explicit zeros.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "Mesh", "p1_mesh", "coarse_lines", "config_mesh", "CONFIGS",
+    "block_coefficient", "seeded_block", "serving_requests",
+]
+
+
+@dataclass
+class Mesh:
+    """A uniform fine mesh of [0,Lx]x[0,Ly] with its nested coarse grid lines."""
+    Lx: float
+    Ly: float
+    Nx: int
+    Ny: int
+    K: sp.csr_matrix            # stiffness, union pattern, float64
+    M: sp.csr_matrix            # consistent mass, union pattern, float64
+    coords: np.ndarray          # (n, 2) coordinates of the interior (free) nodes
+    cx: np.ndarray              # coarse grid lines in x (ascending, incl. 0 and Lx)
+    cy: np.ndarray              # coarse grid lines in y
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.K.shape[0]
+
+    @property
+    def hx(self) -> float:
+        return self.Lx / self.Nx
+
+    @property
+    def hy(self) -> float:
+        return self.Ly / self.Ny
+
+
+def coarse_lines(L: float, N: int, cells_per_coarse: int) -> np.ndarray:
+    """Coarse grid lines of a fine grid of N cells on [0, L].
+
+    A coarse cell spans ``cells_per_coarse`` fine cells; a remainder of less
+    than half a coarse cell is merged into the last coarse cell, a larger one
+    forms its own (smaller) cell.  Lines lie exactly on fine grid lines.
+    """
+    if cells_per_coarse <= 0 or N <= 0:
+        raise ValueError("cells_per_coarse and N must be positive")
+    nfull, rem = divmod(N, cells_per_coarse)
+    idx = [i * cells_per_coarse for i in range(nfull + 1)]
+    if rem:
+        if rem * 2 < cells_per_coarse and nfull >= 1:
+            idx[-1] = N
+        else:
+            idx.append(N)
+    idx = np.asarray(idx, dtype=np.int64)
+    return idx * (L / N)
+
+
+def p1_mesh(Lx: float, Ly: float, Nx: int, Ny: int, cells_per_coarse_x: int,
+            cells_per_coarse_y: Optional[int] = None,
+            coef: Optional[Callable[[np.ndarray, np.ndarray], np.ndarray]] = None) -> Mesh:
+    """P1 stiffness/mass on the uniform "/" mesh of [0,Lx]x[0,Ly].
+
+    Cell (i,j) = [i hx,(i+1)hx] x [j hy,(j+1)hy] is split into
+    T1 = {(i,j),(i+1,j),(i+1,j+1)} and T2 = {(i,j),(i+1,j+1),(i,j+1)}.
+    Interior node (i,j), 1<=i<Nx, 1<=j<Ny, has dof number (j-1)(Nx-1)+(i-1).
+    ``coef(xc, yc)`` gives the element coefficient at element centroids
+    (default 1).
+    """
+    if cells_per_coarse_y is None:
+        cells_per_coarse_y = cells_per_coarse_x
+    hx, hy = Lx / Nx, Ly / Ny
+    nxi, nyi = Nx - 1, Ny - 1
+    n = nxi * nyi
+
+    def dof(i, j):
+        inside = (i >= 1) & (i <= Nx - 1) & (j >= 1) & (j <= Ny - 1)
+        return np.where(inside, (j - 1) * nxi + (i - 1), -1)
+
+    ci, cj = np.meshgrid(np.arange(Nx), np.arange(Ny), indexing="xy")
+    ci = ci.ravel()
+    cj = cj.ravel()
+    # vertex index triples (i,j) for both triangle families
+    tri_i = np.concatenate([np.stack([ci, ci + 1, ci + 1], 1), np.stack([ci, ci + 1, ci], 1)])
+    tri_j = np.concatenate([np.stack([cj, cj, cj + 1], 1), np.stack([cj, cj + 1, cj + 1], 1)])
+    x = tri_i * hx
+    y = tri_j * hy
+    # gradients of the barycentric functions: grad phi_a = (y_b - y_c, x_c - x_b) / (2 area)
+    x0, x1, x2 = x[:, 0], x[:, 1], x[:, 2]
+    y0, y1, y2 = y[:, 0], y[:, 1], y[:, 2]
+    area2 = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)
+    gx = np.stack([y1 - y2, y2 - y0, y0 - y1], 1) / area2[:, None]
+    gy = np.stack([x2 - x1, x0 - x2, x1 - x0], 1) / area2[:, None]
+    area = 0.5 * area2
+    if coef is None:
+        a = np.ones_like(area)
+    else:
+        a = np.asarray(coef(x.mean(1), y.mean(1)), dtype=np.float64)
+    Ke = a[:, None, None] * area[:, None, None] * (gx[:, :, None] * gx[:, None, :] + gy[:, :, None] * gy[:, None, :])
+    Me = (area / 12.0)[:, None, None] * (np.ones((3, 3)) + np.eye(3))[None]
+    d = dof(tri_i, tri_j)
+    rows = np.repeat(d, 3, axis=1).ravel()
+    cols = np.tile(d, (1, 3)).ravel()
+    keep = (rows >= 0) & (cols >= 0)
+    r, c = rows[keep], cols[keep]
+    # K and M come from the same (row, col) list, so coo->csr gives both the
+    # same (union) pattern; K's hypotenuse couplings stay as explicit zeros.
+    K = sp.coo_matrix((Ke.reshape(-1)[keep], (r, c)), shape=(n, n)).tocsr()
+    M = sp.coo_matrix((Me.reshape(-1)[keep], (r, c)), shape=(n, n)).tocsr()
+    K.sort_indices()
+    M.sort_indices()
+    assert np.array_equal(K.indptr, M.indptr) and np.array_equal(K.indices, M.indices)
+    ii, jj = np.meshgrid(np.arange(1, Nx), np.arange(1, Ny), indexing="xy")
+    coords = np.stack([ii.ravel() * hx, jj.ravel() * hy], 1)
+    return Mesh(Lx, Ly, Nx, Ny, K, M, coords,
+                coarse_lines(Lx, Nx, cells_per_coarse_x),
+                coarse_lines(Ly, Ny, cells_per_coarse_y))
+
+
+def block_coefficient(Lx: float, Ly: float, values: np.ndarray):
+    """Piecewise-constant coefficient on a (by x bx) block grid over [0,Lx]x[0,Ly]."""
+    values = np.asarray(values, dtype=np.float64)
+    by, bx = values.shape
+
+    def coef(xc, yc):
+        ix = np.minimum((xc / Lx * bx).astype(np.int64), bx - 1)
+        iy = np.minimum((yc / Ly * by).astype(np.int64), by - 1)
+        return values[iy, ix]
+    return coef
+
+
+def seeded_block(n: int, s: int, seed) -> np.ndarray:
+    """(n, s) standard-normal block from numpy's default generator."""
+    return np.random.default_rng(seed).standard_normal((n, s))
+
+
+# ----------------------------------------------------------------------------
+# Named workloads.  H is the coarse cell side, L the overlap in element layers
+# (delta = L h), k the wanted eigenpairs, guard the extra block columns.
+CONFIGS = {
+    "c1": dict(Lx=1.0, Ly=1.0, Nx=32, Ny=32, coarse=8, L=2, k=4, guard=0, seed_block=0,
+               desc="Laplacian P1 unit square h=1/32, 4x4 subdomains, delta=2h, k=4, seeded initial block"),
+    "c2": dict(Lx=1.0, Ly=1.0, Nx=512, Ny=512, coarse=32, L=4, k=8, guard=0, seed_block=None,
+               desc="Laplacian P1 unit square h=1/512, 16x16 subdomains, delta=4h, k=8"),
+    "c3": dict(Lx=1.0, Ly=1.01, Nx=1024, Ny=1034, coarse=32, L=4, k=12, guard=1, seed_block=None,
+               desc="Laplacian P1 [0,1]x[0,1.01] h=1/1024, 32x32 subdomains, delta=4h, k=12"),
+    # small cases of the same families (test sizes)
+    "t8": dict(Lx=1.0, Ly=1.0, Nx=8, Ny=8, coarse=2, L=1, k=2, guard=0, seed_block=None,
+               desc="tiny 8x8 mesh, 4x4 subdomains"),
+    "t16": dict(Lx=1.0, Ly=1.0, Nx=16, Ny=16, coarse=4, L=1, k=3, guard=0, seed_block=None,
+                desc="16x16 mesh, 4x4 subdomains"),
+    "t64": dict(Lx=1.0, Ly=1.0, Nx=64, Ny=64, coarse=16, L=2, k=6, guard=0, seed_block=None,
+                desc="64x64 mesh, 4x4 subdomains"),
+    "t128": dict(Lx=1.0, Ly=1.0, Nx=128, Ny=128, coarse=16, L=2, k=8, guard=0, seed_block=None,
+                 desc="h=1/128 (the 16129-dof mesh of the first Table 1 column), 8x8 subdomains"),
+    "r96": dict(Lx=1.0, Ly=1.01, Nx=96, Ny=97, coarse=12, L=2, k=6, guard=1, seed_block=None,
+                desc="rectangle [0,1]x[0,1.01], uneven last coarse row"),
+}
+
+
+def config_mesh(name: str) -> tuple[Mesh, dict]:
+    """Build the mesh of a named workload; returns (mesh, config dict)."""
+    cfg = dict(CONFIGS[name])
+    mesh = p1_mesh(cfg["Lx"], cfg["Ly"], cfg["Nx"], cfg["Ny"], cfg["coarse"])
+    return mesh, cfg
+
+
+def serving_requests(count: int = 256, base_seed: int = 2203, h_choices=(64, 128, 256, 512),
+                     k_range=(4, 16), coarse_H: float = 1.0 / 8.0, L: int = 2, guard: int = 2):
+    """Parameters of the served workload: one dict per request (meshes are built lazily).
+
+    Request j draws from numpy.random.default_rng([base_seed, j]): the rectangle
+    height r ~ U[1,2], a 4x4 block coefficient with values log-uniform in
+    [0.1, 10], the mesh level 1/h from ``h_choices`` and k uniform in k_range.
+    """
+    reqs = []
+    for j in range(count):
+        rng = np.random.default_rng([base_seed, j])
+        r = float(rng.uniform(1.0, 2.0))
+        vals = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=(4, 4)))
+        inv_h = int(rng.choice(np.asarray(h_choices)))
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        Nx = inv_h
+        Ny = int(round(r * inv_h))
+        cpc = int(round(coarse_H * inv_h))
+        reqs.append(dict(j=j, Lx=1.0, Ly=r, Nx=Nx, Ny=Ny, coarse=cpc, L=L, k=k, guard=guard,
+                         coef_values=vals))
+    return reqs
+
+
+def request_mesh(req: dict) -> Mesh:
+    coef = block_coefficient(req["Lx"], req["Ly"], req["coef_values"])
+    return p1_mesh(req["Lx"], req["Ly"], req["Nx"], req["Ny"], req["coarse"], coef=coef)
