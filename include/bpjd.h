@@ -1,0 +1,213 @@
+/*
+ * bpjd.h -- C ABI of the MI355X (gfx950) two-level block preconditioned
+ * Jacobi-Davidson eigensolver.
+ *
+ * Problem (Section 2.2, eq. DiscreteVariational, and Algorithm 3.1 of Liang,
+ * Wang, Xu, "A Two-Level Block Preconditioned Jacobi-Davidson Method for
+ * Multiple and Clustered Eigenvalues of Elliptic Operators"): given the
+ * finite-element stiffness matrix K (the form a(.,.)) and mass matrix M (the
+ * form b(.,.)), both symmetric, M positive definite, find the k smallest
+ * eigenpairs  K x_i = lambda_i M x_i  with  X^T M X = I  (b(u_i,u_j) =
+ * delta_ij).  The two-level preconditioner of Section 3 (eq.
+ * Preconditioner) needs a coarse space V^H (given by a prolongation P whose
+ * range is V^H) and overlapping subdomains (local dof sets of V^(l),
+ * Section 2.3); they are passed explicitly (bpjd_dd) or built from a
+ * structured coarse grid (bpjd_dd_geom).
+ *
+ * Conventions
+ *   - every function returns an int status: BPJD_OK (0), BPJD_PENDING (>0)
+ *     or a negative BPJD_ERR_* code; nothing throws across the ABI;
+ *     bpjd_last_error() gives a human-readable detail for the calling thread.
+ *   - CSR matrices are 0-based, square, with sorted column indices and no
+ *     duplicates; K and M store the full symmetric pattern.  K and M may have
+ *     different patterns: the library works on their union.
+ *   - block vectors (X_init, eigvecs) are row-major n x ncols arrays (the
+ *     ncols values of one dof are contiguous).
+ *   - "mem" fields say where a pointer lives: BPJD_MEM_HOST or
+ *     BPJD_MEM_DEVICE (device memory of the context's GPU).
+ *   - input arrays are borrowed for the duration of a call and copied; the
+ *     caller may free them on return.  Output buffers are caller-allocated.
+ *     Handles are freed only by their *_destroy call.
+ *   - all device work of a context is ordered on its HIP stream; a call
+ *     that returns results in host memory synchronises that stream.
+ *   - one thread per problem; a context may be shared by several problems.
+ */
+#ifndef BPJD_H
+#define BPJD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BPJD_OK                0
+#define BPJD_PENDING           1   /* serving: result not ready yet */
+#define BPJD_ERR_ARG          -1   /* bad argument (NULL, size, option) */
+#define BPJD_ERR_CSR          -2   /* malformed CSR (bounds, order, not square, asymmetric pattern) */
+#define BPJD_ERR_DD           -3   /* bad decomposition: uncovered dof, empty subdomain, s >= dim V^H, band too wide */
+#define BPJD_ERR_NOT_SPD      -4   /* M, M_H or a Gram matrix not positive definite; singular local pivot */
+#define BPJD_ERR_NOCONV       -5   /* max_iter reached; outputs hold the last iterate */
+#define BPJD_ERR_OOM          -6   /* device allocation failed */
+#define BPJD_ERR_HIP          -7   /* HIP runtime error */
+#define BPJD_ERR_OVER_BUDGET  -8   /* serving: request can never fit the HBM budget */
+#define BPJD_ERR_STATE        -9   /* call not valid in the object's current state */
+
+#define BPJD_MEM_HOST    0
+#define BPJD_MEM_DEVICE  1
+
+/* stop rule (Algorithm 3.1, Step 4, and the residual rule of the configs) */
+#define BPJD_STOP_RESIDUAL  0   /* max_{i<k} ||K x_i - lambda_i M x_i||_2 / (lambda_i ||M x_i||_2) <= tol */
+#define BPJD_STOP_PAPER     1   /* sum_{i<s} |lambda_i^{k+1} - lambda_i^k| < tol */
+
+/* subspace W^{k+1} (remark after Algorithm 3.1) */
+#define BPJD_SUBSPACE_UU  0     /* W^{k+1} = U^{k-1} + U^k + span{t_i}  (fixed dimension 3s) */
+#define BPJD_SUBSPACE_U   1     /* W^{k+1} = U^k + span{t_i}            (fixed dimension 2s) */
+
+/* precision of the local subdomain factorisations and solves */
+#define BPJD_PREC_FP64   0      /* everything in FP64 */
+#define BPJD_PREC_MIXED  1      /* local factor/solve in FP32; residual, projection, coarse solve, RR in FP64 */
+
+typedef struct bpjd_ctx bpjd_ctx;
+typedef struct bpjd_problem bpjd_problem;
+typedef struct bpjd_server bpjd_server;
+
+typedef struct {
+    int32_t n_rows, n_cols;
+    int64_t nnz;
+    const int32_t* rowptr;      /* n_rows + 1 */
+    const int32_t* col;         /* nnz */
+    const double*  val;         /* nnz */
+    int32_t mem;                /* BPJD_MEM_HOST or BPJD_MEM_DEVICE (all three arrays) */
+} bpjd_csr;
+
+/* Explicit decomposition (Section 2.3).  P: n x n_H prolongation, range(P) =
+ * V^H; subdomain l holds the dofs sub_idx[sub_ptr[l] .. sub_ptr[l+1]) (any
+ * order; they are the dofs interior to the enlarged subdomain Omega'_l).
+ * Every dof must lie in at least one subdomain.  sub_ptr/sub_idx: host. */
+typedef struct {
+    bpjd_csr P;
+    int32_t n_sub;
+    const int32_t* sub_ptr;     /* n_sub + 1 */
+    const int32_t* sub_idx;
+} bpjd_dd;
+
+/* Structured decomposition for P1 on a rectangle whose fine mesh refines a
+ * coarse grid of lines cx[0..n_cx) x cy[0..n_cy) (each coarse cell cut by its
+ * "/" diagonal, like the fine cells).  The library builds P (nodal
+ * interpolation of the coarse P1 hat functions at the dof coordinates) and
+ * the subdomains: closed coarse cell + (overlap_layers - 1) graph layers of
+ * the union pattern of K and M, i.e. overlap delta = overlap_layers * h.
+ * All arrays: host. */
+typedef struct {
+    const double* coords;       /* n x 2, row-major (x, y) of each dof */
+    int32_t n_cx, n_cy;
+    const double* cx;
+    const double* cy;
+    int32_t overlap_layers;     /* >= 1 */
+} bpjd_dd_geom;
+
+typedef struct {
+    int32_t k;                  /* eigenpairs wanted (>= 1) */
+    int32_t guard;              /* extra block columns: block size s = k + guard (Assumption 1 remark) */
+    int32_t max_iter;           /* outer iterations before BPJD_ERR_NOCONV */
+    double  tol;                /* tolerance of the stop rule */
+    int32_t stop_rule;          /* BPJD_STOP_* */
+    int32_t subspace;           /* BPJD_SUBSPACE_* */
+    int32_t precision;          /* BPJD_PREC_* */
+    int32_t n_init;             /* 0, or columns of X_init added to the coarse start (Step 1) */
+    const double* X_init;       /* host, n x n_init row-major, or NULL */
+    int32_t profile;            /* 1: time every phase with HIP events (bpjd_stats.phase_ms) */
+} bpjd_opts;
+
+/* phases timed when bpjd_opts.profile = 1 */
+#define BPJD_PHASE_LOCAL     0  /* batched local factor + solve kernel */
+#define BPJD_PHASE_SPMM      1  /* fused K/M SpMM */
+#define BPJD_PHASE_COARSE    2  /* restriction + coarse eigenbasis apply */
+#define BPJD_PHASE_GATHER    3  /* subdomain gather + overlap scatter/prolongation */
+#define BPJD_PHASE_ORTHO     4  /* projection + M-orthonormalisation */
+#define BPJD_PHASE_RR        5  /* Rayleigh-Ritz (Gram, small eigenproblem, basis update) */
+#define BPJD_PHASE_RESIDUAL  6  /* residual block and norms */
+#define BPJD_PHASE_SETUP     7  /* Galerkin + coarse eigenproblem + start block */
+#define BPJD_NUM_PHASES      8
+
+typedef struct {
+    int32_t iterations;         /* outer iterations performed */
+    int32_t converged;          /* 1 if the stop rule was met */
+    double  stop_value;         /* sum_{i<s} |lambda_i^{k+1} - lambda_i^k| of the last iteration */
+    double  max_residual;       /* max_{i<k} rho_i of the returned pairs */
+    double  setup_ms;           /* device numeric setup (Galerkin, coarse eigenproblem, start block) */
+    double  iterate_ms;         /* outer iterations */
+    int32_t n_sub;              /* subdomains */
+    int32_t n_coarse;           /* dim V^H */
+    int32_t max_local;          /* largest subdomain */
+    int32_t max_band;           /* largest local half-bandwidth */
+    double  residuals[64];      /* rho_i of the returned pairs, i < min(k, 64) */
+    double  phase_ms[8];        /* device time per phase (profile = 1), summed over the solve */
+    int32_t phase_count[8];     /* launches timed per phase */
+} bpjd_stats;
+
+/* Default options: k as given, guard 0, max_iter 500, tol 1e-8, residual
+ * stop rule, UU subspace, mixed precision, no initial block. */
+void bpjd_opts_default(bpjd_opts* o, int32_t k);
+
+/* ---- context ----------------------------------------------------------- */
+/* device: HIP device ordinal.  hip_stream: a hipStream_t to order all work
+ * on, or NULL for a stream the context creates (default priority). */
+int  bpjd_ctx_create(int device, void* hip_stream, bpjd_ctx** out);
+void bpjd_ctx_destroy(bpjd_ctx* ctx);
+
+/* ---- problems ---------------------------------------------------------- */
+/* Validates K, M and the decomposition, builds the structural data (union
+ * pattern, subdomain maps, local band layout, coarse pattern) on the host
+ * and uploads it together with the matrix values.  Device memory for the
+ * whole solve is allocated here; bpjd_solve allocates nothing.
+ * Errors: BPJD_ERR_ARG, _CSR, _DD, _OOM, _HIP. */
+int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M,
+                        const bpjd_dd* dd, const bpjd_opts* opts, bpjd_problem** out);
+int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M,
+                             const bpjd_dd_geom* geom, const bpjd_opts* opts, bpjd_problem** out);
+void bpjd_problem_destroy(bpjd_problem* p);
+
+/* Replace the values of K and M (same patterns as at creation), host or
+ * device arrays of the original nnz of each matrix. */
+int bpjd_problem_set_values(bpjd_problem* p, const double* Kval, const double* Mval, int32_t mem);
+
+/* Size queries: n (dofs), n_H, number of subdomains, block size s. */
+int bpjd_problem_dims(const bpjd_problem* p, int32_t* n, int32_t* n_coarse, int32_t* n_sub, int32_t* s);
+
+/* Subdomain sizes n_l and local half-bandwidths w_l (arrays of n_sub, host). */
+int bpjd_problem_local_sizes(const bpjd_problem* p, int32_t* n_l, int32_t* bw);
+
+/* Run Algorithm 3.1: device numeric setup (Galerkin coarse operators, coarse
+ * generalized eigenproblem, start block, Step 1) and outer iterations (Steps
+ * 2-4) until the stop rule holds.  eigvals: k doubles ascending; eigvecs:
+ * n x k row-major, M-orthonormal; either may be NULL.  mem says where both
+ * live.  st may be NULL.  Returns BPJD_OK, or BPJD_ERR_NOCONV with the last
+ * iterate in the outputs, or another error. */
+int bpjd_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int32_t mem, bpjd_stats* st);
+
+/* ---- stage entry points (one piece of an outer iteration each) ---------- */
+/* Two-level preconditioner (eq. Preconditioner) applied to the residual
+ * block of (X, lambda): with F = M X diag(lambda) - K X,
+ *   Z_i = P (B_0,i)^{-1} Q^H_{s+1} Q^H r_i + sum_l R_l^T (K_l - lambda_i M_l)^{-1} R_l F_i.
+ * Needs the coarse eigenbasis: call bpjd_setup first (bpjd_solve does).
+ * X, Z: n x s row-major; lambda: s values.  All three in `mem`. */
+int bpjd_setup(bpjd_problem* p);
+int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* lambda,
+                              double* Z, int32_t mem);
+/* Fused SpMM  KX = K X, MX = M X  for an n x ncols block (ncols <= 64). */
+int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, double* MX, int32_t mem);
+/* Coarse eigenvalues (ascending, n_H values) from the last setup. */
+int bpjd_coarse_eigenvalues(bpjd_problem* p, double* lamH, int32_t mem);
+
+/* ---- errors ------------------------------------------------------------ */
+const char* bpjd_strerror(int code);
+const char* bpjd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPJD_H */

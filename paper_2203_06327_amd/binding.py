@@ -1,0 +1,275 @@
+"""Thin ctypes binding of libbpjd.so (include/bpjd.h).
+
+Argument marshalling only: every numeric step runs in the HIP library.  Host
+arrays are numpy arrays; device arrays are any object with ``data_ptr()``
+(a torch tensor on the GPU), passed with ``mem=MEM_DEVICE``.  If the built
+library is missing, importing the functions raises ``LibraryNotBuilt``; there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libbpjd.so")
+
+OK, PENDING = 0, 1
+ERR_ARG, ERR_CSR, ERR_DD, ERR_NOT_SPD, ERR_NOCONV, ERR_OOM, ERR_HIP, ERR_OVER_BUDGET, ERR_STATE = \
+    -1, -2, -3, -4, -5, -6, -7, -8, -9
+MEM_HOST, MEM_DEVICE = 0, 1
+STOP_RESIDUAL, STOP_PAPER = 0, 1
+SUBSPACE_UU, SUBSPACE_U = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+class BPJDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Csr(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p), ("mem", C.c_int32)]
+
+
+class DD(C.Structure):
+    _fields_ = [("P", Csr), ("n_sub", C.c_int32), ("sub_ptr", C.c_void_p), ("sub_idx", C.c_void_p)]
+
+
+class DDGeom(C.Structure):
+    _fields_ = [("coords", C.c_void_p), ("n_cx", C.c_int32), ("n_cy", C.c_int32),
+                ("cx", C.c_void_p), ("cy", C.c_void_p), ("overlap_layers", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("guard", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("stop_rule", C.c_int32), ("subspace", C.c_int32), ("precision", C.c_int32),
+                ("n_init", C.c_int32), ("X_init", C.c_void_p), ("profile", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("stop_value", C.c_double),
+                ("max_residual", C.c_double), ("setup_ms", C.c_double), ("iterate_ms", C.c_double),
+                ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("max_local", C.c_int32),
+                ("max_band", C.c_int32), ("residuals", C.c_double * 64),
+                ("phase_ms", C.c_double * 8), ("phase_count", C.c_int32 * 8)]
+
+    def to_dict(self) -> dict:
+        arrays = ("residuals", "phase_ms", "phase_count")
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name not in arrays}
+        for a in arrays:
+            d[a] = list(getattr(self, a))
+        return d
+
+
+PHASES = ["local", "spmm", "coarse", "gather_scatter", "ortho", "rr", "residual", "setup"]
+
+
+_lib = None
+
+EXPORTS = {
+    "bpjd_opts_default": (None, [C.POINTER(Opts), C.c_int32]),
+    "bpjd_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "bpjd_ctx_destroy": (None, [C.c_void_p]),
+    "bpjd_problem_create": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.POINTER(Csr), C.POINTER(DD), C.POINTER(Opts),
+                                      C.POINTER(C.c_void_p)]),
+    "bpjd_problem_create_geom": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.POINTER(Csr), C.POINTER(DDGeom),
+                                           C.POINTER(Opts), C.POINTER(C.c_void_p)]),
+    "bpjd_problem_destroy": (None, [C.c_void_p]),
+    "bpjd_problem_set_values": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "bpjd_problem_dims": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "bpjd_problem_local_sizes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bpjd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Stats)]),
+    "bpjd_setup": (C.c_int, [C.c_void_p]),
+    "bpjd_apply_preconditioner": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "bpjd_spmm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    "bpjd_coarse_eigenvalues": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "bpjd_strerror": (C.c_char_p, [C.c_int]),
+    "bpjd_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libbpjd.so (raises LibraryNotBuilt if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryNotBuilt(f"{LIB_PATH} not found: run `python -m paper_2203_06327_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code < 0:
+        L = lib()
+        raise BPJDError(code, f"{L.bpjd_strerror(code).decode()}: {L.bpjd_last_error().decode()}")
+    return code
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+@dataclass
+class _Keep:
+    arrays: list
+
+
+class Context:
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        h = C.c_void_p()
+        _check(lib().bpjd_ctx_create(device, stream, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().bpjd_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _csr(A, keep: list) -> Csr:
+    """scipy CSR (host) -> bpjd_csr with int32 indices and float64 values."""
+    rowptr = np.ascontiguousarray(A.indptr, dtype=np.int32)
+    col = np.ascontiguousarray(A.indices, dtype=np.int32)
+    val = np.ascontiguousarray(A.data, dtype=np.float64)
+    keep += [rowptr, col, val]
+    return Csr(A.shape[0], A.shape[1], A.nnz, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, MEM_HOST)
+
+
+def make_opts(k: int, guard: int = 0, tol: float = 1e-8, max_iter: int = 500, stop_rule: int = STOP_RESIDUAL,
+              subspace: int = SUBSPACE_UU, precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None,
+              keep: Optional[list] = None, profile: bool = False) -> Opts:
+    o = Opts()
+    lib().bpjd_opts_default(C.byref(o), k)
+    o.guard, o.tol, o.max_iter, o.stop_rule, o.subspace, o.precision = guard, tol, max_iter, stop_rule, subspace, precision
+    o.profile = 1 if profile else 0
+    if X_init is not None:
+        Xi = np.ascontiguousarray(X_init, dtype=np.float64)
+        if keep is not None:
+            keep.append(Xi)
+        o.n_init = Xi.shape[1]
+        o.X_init = Xi.ctypes.data
+    return o
+
+
+class Problem:
+    """A BPJD problem on one GPU (wraps bpjd_problem)."""
+
+    def __init__(self, ctx: Context, K, M, *, dd=None, geom=None, k: int, guard: int = 0, tol: float = 1e-8,
+                 max_iter: int = 500, stop_rule: int = STOP_RESIDUAL, subspace: int = SUBSPACE_UU,
+                 precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None, profile: bool = False):
+        keep: list = []
+        Kc, Mc = _csr(K, keep), _csr(M, keep)
+        opts = make_opts(k, guard, tol, max_iter, stop_rule, subspace, precision, X_init, keep, profile)
+        h = C.c_void_p()
+        if geom is not None:
+            coords, cx, cy, layers = geom
+            coords = np.ascontiguousarray(coords, dtype=np.float64)
+            cx = np.ascontiguousarray(cx, dtype=np.float64)
+            cy = np.ascontiguousarray(cy, dtype=np.float64)
+            keep += [coords, cx, cy]
+            g = DDGeom(coords.ctypes.data, len(cx), len(cy), cx.ctypes.data, cy.ctypes.data, int(layers))
+            _check(lib().bpjd_problem_create_geom(ctx.handle, C.byref(Kc), C.byref(Mc), C.byref(g), C.byref(opts),
+                                                  C.byref(h)))
+        elif dd is not None:
+            P, subs = dd
+            Pc = _csr(P, keep)
+            sub_ptr = np.zeros(len(subs) + 1, dtype=np.int32)
+            sub_ptr[1:] = np.cumsum([len(S) for S in subs])
+            sub_idx = np.ascontiguousarray(np.concatenate([np.asarray(S) for S in subs]), dtype=np.int32)
+            keep += [sub_ptr, sub_idx]
+            d = DD(Pc, len(subs), sub_ptr.ctypes.data, sub_idx.ctypes.data)
+            _check(lib().bpjd_problem_create(ctx.handle, C.byref(Kc), C.byref(Mc), C.byref(d), C.byref(opts),
+                                             C.byref(h)))
+        else:
+            raise ValueError("give dd=(P, subdomains) or geom=(coords, cx, cy, layers)")
+        self.ctx = ctx
+        self.handle = h
+        self.k = k
+        n, nH, nsub, s = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().bpjd_problem_dims(h, C.byref(n), C.byref(nH), C.byref(nsub), C.byref(s)))
+        self.n, self.n_coarse, self.n_sub, self.s = n.value, nH.value, nsub.value, s.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bpjd_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, eigvals=None, eigvecs=None, mem: int = MEM_HOST, raise_noconv: bool = True):
+        """Run Algorithm 3.1; returns (eigvals, eigvecs, stats dict).  Host outputs are allocated
+        when not given; device outputs must be given (torch tensors)."""
+        if mem == MEM_HOST:
+            if eigvals is None:
+                eigvals = np.empty(self.k)
+            if eigvecs is None:
+                eigvecs = np.empty((self.n, self.k))
+        st = Stats()
+        code = lib().bpjd_solve(self.handle, _ptr(eigvals), _ptr(eigvecs), mem, C.byref(st))
+        if code != ERR_NOCONV or raise_noconv:
+            _check(code)
+        return eigvals, eigvecs, st.to_dict()
+
+    def local_sizes(self):
+        nl = np.empty(self.n_sub, dtype=np.int32)
+        bw = np.empty(self.n_sub, dtype=np.int32)
+        _check(lib().bpjd_problem_local_sizes(self.handle, _ptr(nl), _ptr(bw)))
+        return nl, bw
+
+    def setup(self):
+        _check(lib().bpjd_setup(self.handle))
+
+    def apply_preconditioner(self, X: np.ndarray, lam: np.ndarray) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        Z = np.empty_like(X)
+        _check(lib().bpjd_apply_preconditioner(self.handle, _ptr(X), _ptr(lam), _ptr(Z), MEM_HOST))
+        return Z
+
+    def spmm(self, X: np.ndarray):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        KX = np.empty_like(X)
+        MX = np.empty_like(X)
+        _check(lib().bpjd_spmm(self.handle, _ptr(X), X.shape[1], _ptr(KX), _ptr(MX), MEM_HOST))
+        return KX, MX
+
+    def coarse_eigenvalues(self) -> np.ndarray:
+        out = np.empty(self.n_coarse)
+        _check(lib().bpjd_coarse_eigenvalues(self.handle, _ptr(out), MEM_HOST))
+        return out
+
+
+def problem_from_mesh(ctx: Context, mesh, layers: int, **kw) -> Problem:
+    """Problem on a structured P1 mesh (coarse grid lines and coordinates from the mesh)."""
+    return Problem(ctx, mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers), **kw)

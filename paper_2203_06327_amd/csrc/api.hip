@@ -1,0 +1,1035 @@
+// C ABI, structural setup on the host, and the outer iteration of Algorithm 3.1.
+//
+// Host work is limited to structure: validating the CSR input, the union
+// pattern of K and M, subdomain dof sets, the local band layout, the coarse
+// prolongation P for structured grids and the symbolic patterns of the
+// Galerkin products.  Every numeric step of a solve (Galerkin coarse
+// operators, the coarse eigenproblem, SpMM, residuals, the preconditioner,
+// orthonormalisation, Rayleigh-Ritz) runs in the HIP kernels of this library.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+namespace bpjd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+struct HostCSR {
+    int n = 0;
+    std::vector<int> ptr, col;
+    std::vector<double> val;
+};
+
+static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out) {
+    if (!A || !A->rowptr || !A->col || !A->val) return fail(BPJD_ERR_ARG, std::string(name) + ": NULL array");
+    if (A->n_rows <= 0 || A->n_rows != A->n_cols) return fail(BPJD_ERR_CSR, std::string(name) + ": not square");
+    const int n = A->n_rows;
+    out.n = n;
+    out.ptr.resize(n + 1);
+    if (A->mem == BPJD_MEM_DEVICE) {
+        BPJD_HIP(hipMemcpy(out.ptr.data(), A->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(out.ptr.data(), A->rowptr, sizeof(int) * (n + 1));
+    }
+    if (out.ptr[0] != 0 || (long long)out.ptr[n] != A->nnz)
+        return fail(BPJD_ERR_CSR, std::string(name) + ": rowptr[0] != 0 or rowptr[n] != nnz");
+    for (int i = 0; i < n; ++i)
+        if (out.ptr[i + 1] < out.ptr[i]) return fail(BPJD_ERR_CSR, std::string(name) + ": rowptr not monotone");
+    out.col.resize(A->nnz);
+    out.val.resize(A->nnz);
+    if (A->mem == BPJD_MEM_DEVICE) {
+        BPJD_HIP(hipMemcpy(out.col.data(), A->col, sizeof(int) * A->nnz, hipMemcpyDeviceToHost));
+        BPJD_HIP(hipMemcpy(out.val.data(), A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(out.col.data(), A->col, sizeof(int) * A->nnz);
+        std::memcpy(out.val.data(), A->val, sizeof(double) * A->nnz);
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int p = out.ptr[i]; p < out.ptr[i + 1]; ++p) {
+            const int c = out.col[p];
+            if (c < 0 || c >= n) return fail(BPJD_ERR_CSR, std::string(name) + ": column index out of range");
+            if (p > out.ptr[i] && c <= out.col[p - 1])
+                return fail(BPJD_ERR_CSR, std::string(name) + ": columns not strictly increasing in a row");
+            if (!std::isfinite(out.val[p])) return fail(BPJD_ERR_CSR, std::string(name) + ": non-finite value");
+        }
+    }
+    return BPJD_OK;
+}
+
+// Union pattern of K and M with the position maps of both inputs.
+struct Pattern {
+    int n = 0;
+    std::vector<int> ptr, col;
+    std::vector<long long> Kmap, Mmap;
+};
+
+static int build_union(const HostCSR& K, const HostCSR& M, Pattern& U) {
+    const int n = K.n;
+    U.n = n;
+    U.ptr.assign(n + 1, 0);
+    U.col.clear();
+    U.col.reserve(std::max(K.col.size(), M.col.size()));
+    U.Kmap.resize(K.col.size());
+    U.Mmap.resize(M.col.size());
+    for (int i = 0; i < n; ++i) {
+        int a = K.ptr[i], b = M.ptr[i];
+        const int ae = K.ptr[i + 1], be = M.ptr[i + 1];
+        while (a < ae || b < be) {
+            int c;
+            if (b >= be || (a < ae && K.col[a] < M.col[b])) c = K.col[a];
+            else c = M.col[b];
+            const long long pos = (long long)U.col.size();
+            if (a < ae && K.col[a] == c) U.Kmap[a++] = pos;
+            if (b < be && M.col[b] == c) U.Mmap[b++] = pos;
+            U.col.push_back(c);
+        }
+        U.ptr[i + 1] = (int)U.col.size();
+    }
+    // structural symmetry of the union pattern
+    for (int i = 0; i < n; ++i) {
+        for (int p = U.ptr[i]; p < U.ptr[i + 1]; ++p) {
+            const int j = U.col[p];
+            if (!std::binary_search(U.col.begin() + U.ptr[j], U.col.begin() + U.ptr[j + 1], i))
+                return fail(BPJD_ERR_CSR, "pattern of K + M is not symmetric");
+        }
+    }
+    return BPJD_OK;
+}
+
+// ---- structured P1 decomposition ----------------------------------------------
+// Coarse P1 on the grid cx x cy, each coarse cell cut by its "/" diagonal;
+// nodal interpolation at the dof coordinates (same rule as the fine mesh).
+static void build_p1_prolongation(int n, const double* xy, const std::vector<double>& cx,
+                                  const std::vector<double>& cy, HostCSR& P, int& nH) {
+    const int ncx = (int)cx.size() - 1, ncy = (int)cy.size() - 1;
+    nH = (ncx - 1) * (ncy - 1);
+    P.n = n;
+    P.ptr.assign(n + 1, 0);
+    P.col.clear();
+    P.val.clear();
+    for (int d = 0; d < n; ++d) {
+        const double x = xy[2 * d], y = xy[2 * d + 1];
+        int a = (int)(std::upper_bound(cx.begin(), cx.end(), x) - cx.begin()) - 1;
+        int b = (int)(std::upper_bound(cy.begin(), cy.end(), y) - cy.begin()) - 1;
+        a = std::min(std::max(a, 0), ncx - 1);
+        b = std::min(std::max(b, 0), ncy - 1);
+        const double xi = (x - cx[a]) / (cx[a + 1] - cx[a]);
+        const double eta = (y - cy[b]) / (cy[b + 1] - cy[b]);
+        int va[3], vb[3];
+        double w[3];
+        if (xi >= eta) {
+            va[0] = a; vb[0] = b; w[0] = 1.0 - xi;
+            va[1] = a + 1; vb[1] = b; w[1] = xi - eta;
+            va[2] = a + 1; vb[2] = b + 1; w[2] = eta;
+        } else {
+            va[0] = a; vb[0] = b; w[0] = 1.0 - eta;
+            va[1] = a + 1; vb[1] = b + 1; w[1] = xi;
+            va[2] = a; vb[2] = b + 1; w[2] = eta - xi;
+        }
+        std::vector<std::pair<int, double>> ent;
+        for (int k = 0; k < 3; ++k) {
+            if (va[k] >= 1 && va[k] <= ncx - 1 && vb[k] >= 1 && vb[k] <= ncy - 1 && w[k] != 0.0)
+                ent.push_back({(vb[k] - 1) * (ncx - 1) + (va[k] - 1), w[k]});
+        }
+        std::sort(ent.begin(), ent.end());
+        for (auto& e : ent) {
+            P.col.push_back(e.first);
+            P.val.push_back(e.second);
+        }
+        P.ptr[d + 1] = (int)P.col.size();
+    }
+}
+
+// Closed coarse cell plus (layers - 1) graph layers of the union pattern.
+static int build_geom_subdomains(const Pattern& U, const double* xy, const std::vector<double>& cx,
+                                 const std::vector<double>& cy, int layers, std::vector<int>& sptr,
+                                 std::vector<int>& sidx) {
+    if (layers < 1) return fail(BPJD_ERR_ARG, "overlap_layers must be >= 1");
+    const int n = U.n;
+    const int ncx = (int)cx.size() - 1, ncy = (int)cy.size() - 1;
+    double hmin = 1e300;
+    for (int i = 0; i < ncx; ++i) hmin = std::min(hmin, cx[i + 1] - cx[i]);
+    for (int i = 0; i < ncy; ++i) hmin = std::min(hmin, cy[i + 1] - cy[i]);
+    const double tol = 1e-9 * hmin;
+    // closed-cell membership: each dof lies in at most two closed cells per axis
+    std::vector<std::vector<int>> cell(ncx * ncy);
+    for (int d = 0; d < n; ++d) {
+        const double x = xy[2 * d], y = xy[2 * d + 1];
+        int a0 = (int)(std::upper_bound(cx.begin(), cx.end(), x) - cx.begin()) - 1;
+        int b0 = (int)(std::upper_bound(cy.begin(), cy.end(), y) - cy.begin()) - 1;
+        for (int B = std::max(0, b0 - 1); B <= std::min(ncy - 1, b0 + 1); ++B) {
+            if (!(y >= cy[B] - tol && y <= cy[B + 1] + tol)) continue;
+            for (int A = std::max(0, a0 - 1); A <= std::min(ncx - 1, a0 + 1); ++A) {
+                if (!(x >= cx[A] - tol && x <= cx[A + 1] + tol)) continue;
+                cell[B * ncx + A].push_back(d);
+            }
+        }
+    }
+    std::vector<int> mark(n, -1), frontier, next;
+    sptr.assign(1, 0);
+    sidx.clear();
+    for (int c = 0; c < ncx * ncy; ++c) {
+        std::vector<int> members = cell[c];
+        for (int d : members) mark[d] = c;
+        frontier = members;
+        for (int layer = 1; layer < layers; ++layer) {
+            next.clear();
+            for (int d : frontier) {
+                for (int q = U.ptr[d]; q < U.ptr[d + 1]; ++q) {
+                    const int e = U.col[q];
+                    if (mark[e] != c) {
+                        mark[e] = c;
+                        members.push_back(e);
+                        next.push_back(e);
+                    }
+                }
+            }
+            frontier.swap(next);
+        }
+        if (members.empty()) continue;
+        std::sort(members.begin(), members.end());
+        sidx.insert(sidx.end(), members.begin(), members.end());
+        sptr.push_back((int)sidx.size());
+    }
+    return BPJD_OK;
+}
+
+static int upload(bpjd_problem* p, void** dst, const void* src, size_t bytes) {
+    void* d = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&d, bytes) != hipSuccess) return fail(BPJD_ERR_OOM, "device allocation failed");
+    p->allocations.push_back(d);
+    if (src) BPJD_HIP(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+    *dst = d;
+    return BPJD_OK;
+}
+
+template <typename T>
+static int upload_vec(bpjd_problem* p, T** dst, const std::vector<T>& v) {
+    return upload(p, (void**)dst, v.empty() ? nullptr : v.data(), v.size() * sizeof(T));
+}
+
+template <typename T>
+static int alloc_dev(bpjd_problem* p, T** dst, size_t count) {
+    return upload(p, (void**)dst, nullptr, count * sizeof(T));
+}
+
+// Everything after the decomposition is known: local band layout, reverse
+// map, Galerkin patterns, device allocations.
+static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, const Pattern& U, const HostCSR& P,
+                         int nH, std::vector<int>& sptr, std::vector<int>& sidx, const bpjd_opts* opts,
+                         bpjd_problem** out) {
+    const int n = U.n;
+    const int nsub = (int)sptr.size() - 1;
+    if (nsub < 1) return fail(BPJD_ERR_DD, "no subdomains");
+    const int s = opts->k + opts->guard;
+    if (opts->k < 1 || opts->guard < 0 || s > 21) return fail(BPJD_ERR_ARG, "need 1 <= k and k + guard <= 21");
+    if (s >= nH) return fail(BPJD_ERR_DD, "block size s must be smaller than dim V^H");
+    if (opts->n_init != 0 && opts->n_init != s) return fail(BPJD_ERR_ARG, "n_init must be 0 or k + guard");
+    if (opts->n_init && !opts->X_init) return fail(BPJD_ERR_ARG, "X_init is NULL");
+    if (opts->stop_rule != BPJD_STOP_RESIDUAL && opts->stop_rule != BPJD_STOP_PAPER)
+        return fail(BPJD_ERR_ARG, "unknown stop rule");
+    if (opts->subspace != BPJD_SUBSPACE_UU && opts->subspace != BPJD_SUBSPACE_U)
+        return fail(BPJD_ERR_ARG, "unknown subspace choice");
+    if (opts->precision != BPJD_PREC_FP64 && opts->precision != BPJD_PREC_MIXED)
+        return fail(BPJD_ERR_ARG, "unknown precision");
+    if (!(opts->tol > 0.0) || opts->max_iter < 0) return fail(BPJD_ERR_ARG, "bad tol or max_iter");
+
+    // coverage and local orderings (ascending global index)
+    std::vector<int> cover(n, 0);
+    for (int l = 0; l < nsub; ++l) {
+        if (sptr[l + 1] <= sptr[l]) return fail(BPJD_ERR_DD, "empty subdomain");
+        std::sort(sidx.begin() + sptr[l], sidx.begin() + sptr[l + 1]);
+        for (int q = sptr[l]; q < sptr[l + 1]; ++q) {
+            if (sidx[q] < 0 || sidx[q] >= n) return fail(BPJD_ERR_DD, "subdomain index out of range");
+            if (q > sptr[l] && sidx[q] == sidx[q - 1]) return fail(BPJD_ERR_DD, "duplicate dof in a subdomain");
+            cover[sidx[q]]++;
+        }
+    }
+    for (int d = 0; d < n; ++d)
+        if (!cover[d]) return fail(BPJD_ERR_DD, "dof " + std::to_string(d) + " lies in no subdomain");
+
+    const long long sumN = sptr[nsub];
+    std::vector<int> lptr(sumN + 1, 0), ldd, lpos, bw(nsub, 0);
+    std::vector<int> gl(n, -1);
+    int maxN = 0, maxBW = 0;
+    for (int l = 0; l < nsub; ++l) {
+        const int off = sptr[l], nl = sptr[l + 1] - off;
+        maxN = std::max(maxN, nl);
+        for (int r = 0; r < nl; ++r) gl[sidx[off + r]] = r;
+        for (int r = 0; r < nl; ++r) {
+            const int g = sidx[off + r];
+            for (int p = U.ptr[g]; p < U.ptr[g + 1]; ++p) {
+                const int c = gl[U.col[p]];
+                if (c >= 0 && c <= r) {
+                    ldd.push_back(r - c);
+                    lpos.push_back(p);
+                    bw[l] = std::max(bw[l], r - c);
+                }
+            }
+            lptr[off + r + 1] = (int)ldd.size();
+        }
+        for (int r = 0; r < nl; ++r) gl[sidx[off + r]] = -1;
+        maxBW = std::max(maxBW, bw[l]);
+    }
+    hipDeviceProp_t prop;
+    BPJD_HIP(hipGetDeviceProperties(&prop, ctx->device));
+    const size_t elt = opts->precision == BPJD_PREC_MIXED ? sizeof(float) : sizeof(double);
+    const int maxC = maxBW + 1;
+    const size_t shmem = (size_t)(maxC * maxC + 2 * maxC) * elt;
+    if (shmem > prop.sharedMemPerBlock)
+        return fail(BPJD_ERR_DD, "local half-bandwidth " + std::to_string(maxBW) + " too wide for the local solver");
+
+    // reverse map dof -> positions in subdomain order
+    std::vector<int> rptr(n + 1, 0), ridx(sumN);
+    for (long long q = 0; q < sumN; ++q) rptr[sidx[q] + 1]++;
+    for (int d = 0; d < n; ++d) rptr[d + 1] += rptr[d];
+    {
+        std::vector<int> fillp(rptr.begin(), rptr.end() - 1);
+        for (long long q = 0; q < sumN; ++q) ridx[fillp[sidx[q]]++] = (int)q;
+    }
+    std::vector<long long> Loff(nsub, 0);
+    long long Ltot = 0;
+    for (int l = 0; l < nsub; ++l) {
+        Loff[l] = Ltot;
+        Ltot += (long long)s * (sptr[l + 1] - sptr[l]) * (bw[l] + 1);
+    }
+
+    // P^T and Galerkin patterns
+    std::vector<int> PTptr(nH + 1, 0), PTcol(P.col.size());
+    std::vector<double> PTval(P.col.size());
+    for (int c : P.col) {
+        if (c < 0 || c >= nH) return fail(BPJD_ERR_DD, "P column index out of range");
+        PTptr[c + 1]++;
+    }
+    for (int a = 0; a < nH; ++a) PTptr[a + 1] += PTptr[a];
+    {
+        std::vector<int> fillp(PTptr.begin(), PTptr.end() - 1);
+        for (int d = 0; d < n; ++d)
+            for (int q = P.ptr[d]; q < P.ptr[d + 1]; ++q) {
+                const int e = fillp[P.col[q]]++;
+                PTcol[e] = d;
+                PTval[e] = P.val[q];
+            }
+    }
+    for (int a = 0; a < nH; ++a)
+        if (PTptr[a + 1] == PTptr[a]) return fail(BPJD_ERR_DD, "coarse basis function with empty support");
+    std::vector<int> kpptr(n + 1, 0), kpcol;
+    std::vector<int> tmp;
+    for (int i = 0; i < n; ++i) {
+        tmp.clear();
+        for (int q = U.ptr[i]; q < U.ptr[i + 1]; ++q) {
+            const int j = U.col[q];
+            for (int r = P.ptr[j]; r < P.ptr[j + 1]; ++r) tmp.push_back(P.col[r]);
+        }
+        std::sort(tmp.begin(), tmp.end());
+        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+        kpcol.insert(kpcol.end(), tmp.begin(), tmp.end());
+        kpptr[i + 1] = (int)kpcol.size();
+    }
+    std::vector<int> khptr(nH + 1, 0), khcol;
+    for (int a = 0; a < nH; ++a) {
+        tmp.clear();
+        for (int q = PTptr[a]; q < PTptr[a + 1]; ++q) {
+            const int i = PTcol[q];
+            tmp.insert(tmp.end(), kpcol.begin() + kpptr[i], kpcol.begin() + kpptr[i + 1]);
+        }
+        std::sort(tmp.begin(), tmp.end());
+        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+        khcol.insert(khcol.end(), tmp.begin(), tmp.end());
+        khptr[a + 1] = (int)khcol.size();
+    }
+
+    bpjd_problem* p = new bpjd_problem();
+    p->ctx = ctx;
+    p->opts = *opts;
+    p->opts.X_init = nullptr;
+    p->n = n;
+    p->nH = nH;
+    p->nsub = nsub;
+    p->s = s;
+    p->k = opts->k;
+    p->nnz = (long long)U.col.size();
+    p->sumN = sumN;
+    p->maxN = maxN;
+    p->maxBW = maxBW;
+    p->maxC = maxC;
+    p->nnzK = (long long)K.col.size();
+    p->nnzM = (long long)M.col.size();
+    p->Kmap = U.Kmap;
+    p->Mmap = U.Mmap;
+    p->n_init = opts->n_init;
+    p->nnzKH = (int)khcol.size();
+    p->trace = std::getenv("BPJD_TRACE") != nullptr;
+    p->h_bw = bw;
+    p->h_nl.resize(nsub);
+    for (int l = 0; l < nsub; ++l) p->h_nl[l] = sptr[l + 1] - sptr[l];
+    if (opts->n_init) p->X_init.assign(opts->X_init, opts->X_init + (size_t)n * s);
+
+    std::vector<double2> km(p->nnz, make_double2(0.0, 0.0));
+    for (size_t q = 0; q < K.col.size(); ++q) km[U.Kmap[q]].x = K.val[q];
+    for (size_t q = 0; q < M.col.size(); ++q) km[U.Mmap[q]].y = M.val[q];
+
+    int rc = BPJD_OK;
+    auto chk = [&](int r) {
+        if (r < 0 && rc == BPJD_OK) rc = r;
+    };
+    BPJD_HIP(hipSetDevice(ctx->device));
+    chk(upload_vec(p, &p->rowptr, U.ptr));
+    chk(upload_vec(p, &p->col, U.col));
+    chk(upload_vec(p, &p->km, km));
+    chk(upload_vec(p, &p->Pptr, P.ptr));
+    chk(upload_vec(p, &p->Pcol, P.col));
+    chk(upload_vec(p, &p->Pval, P.val));
+    chk(upload_vec(p, &p->PTptr, PTptr));
+    chk(upload_vec(p, &p->PTcol, PTcol));
+    chk(upload_vec(p, &p->PTval, PTval));
+    chk(upload_vec(p, &p->kpptr, kpptr));
+    chk(upload_vec(p, &p->kpcol, kpcol));
+    chk(alloc_dev(p, &p->kpval, kpcol.size()));
+    chk(upload_vec(p, &p->khptr, khptr));
+    chk(upload_vec(p, &p->khcol, khcol));
+    chk(upload_vec(p, &p->subptr, sptr));
+    chk(upload_vec(p, &p->subidx, sidx));
+    chk(upload_vec(p, &p->bw, bw));
+    chk(upload_vec(p, &p->lptr, lptr));
+    chk(upload_vec(p, &p->ldd, ldd));
+    chk(upload_vec(p, &p->lpos, lpos));
+    chk(upload_vec(p, &p->rptr, rptr));
+    chk(upload_vec(p, &p->ridx, ridx));
+    chk(upload_vec(p, &p->Loff, Loff));
+    const size_t nH2 = (size_t)nH * nH;
+    chk(alloc_dev(p, &p->KH, nH2));
+    chk(alloc_dev(p, &p->MH, nH2));
+    chk(alloc_dev(p, &p->Ccoarse, nH2));
+    chk(alloc_dev(p, &p->Y, nH2));
+    chk(alloc_dev(p, &p->jwork, nH2));
+    chk(alloc_dev(p, &p->lamH, nH));
+    const size_t blk = (size_t)n * 3 * s;
+    for (int b = 0; b < 2; ++b) {
+        chk(alloc_dev(p, &p->W[b], blk));
+        chk(alloc_dev(p, &p->KW[b], blk));
+        chk(alloc_dev(p, &p->MW[b], blk));
+    }
+    chk(alloc_dev(p, &p->F, (size_t)n * s));
+    chk(alloc_dev(p, &p->Z, (size_t)n * s));
+    chk(alloc_dev(p, &p->Zhat, (size_t)nH * s));
+    chk(alloc_dev(p, &p->G, (size_t)nH * s));
+    chk(alloc_dev(p, &p->Cw, (size_t)nH * s));
+    chk(upload(p, &p->Floc, nullptr, elt * s * sumN));
+    chk(upload(p, &p->zloc, nullptr, elt * s * sumN));
+    chk(upload(p, &p->Lwork, nullptr, elt * Ltot));
+    p->npart = num_partials(n);
+    chk(alloc_dev(p, &p->partial, (size_t)p->npart * 4096));
+    chk(alloc_dev(p, &p->colsq, 128));
+    chk(alloc_dev(p, &p->lam, 64));
+    chk(alloc_dev(p, &p->gsmall, 64 * 64));
+    chk(alloc_dev(p, &p->csmall, 64 * 64));
+    chk(alloc_dev(p, &p->Hm, 64 * 64));
+    chk(alloc_dev(p, &p->theta, 64));
+    chk(alloc_dev(p, &p->Cfull, 64 * 128));
+    chk(alloc_dev(p, &p->dropped[0], 64));
+    chk(alloc_dev(p, &p->dropped[1], 64));
+    chk(alloc_dev(p, &p->status, 4));
+    if (rc == BPJD_OK && hipHostMalloc((void**)&p->hbuf, 4096 * sizeof(double)) != hipSuccess)
+        rc = fail(BPJD_ERR_OOM, "pinned host allocation failed");
+    if (rc != BPJD_OK) {
+        bpjd_problem_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return BPJD_OK;
+}
+
+static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR& hM, Pattern& U) {
+    BPJD_TRY(read_csr(K, "K", hK));
+    BPJD_TRY(read_csr(M, "M", hM));
+    if (hK.n != hM.n) return fail(BPJD_ERR_CSR, "K and M differ in size");
+    return build_union(hK, hM, U);
+}
+
+// ---- numeric pieces ------------------------------------------------------------
+static inline double* colp(double* base, int c) { return base + c; }
+
+// HIP-event timing of solve phases (bpjd_opts.profile).  Events come from a
+// pool; elapsed times are collected at the host synchronisation point of
+// every outer iteration.
+struct PhaseTimer {
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> phase;
+    size_t used = 0;
+    double ms[BPJD_NUM_PHASES] = {0};
+    int count[BPJD_NUM_PHASES] = {0};
+    int open = -1;
+    ~PhaseTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    void begin(int ph) {
+        if (used + 2 > ev.size()) {
+            for (int i = 0; i < 32; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                ev.push_back(e);
+            }
+            phase.resize(ev.size() / 2);
+        }
+        (void)hipEventRecord(ev[used], st);
+        phase[used / 2] = ph;
+        open = ph;
+    }
+    void end() {
+        if (open < 0) return;
+        (void)hipEventRecord(ev[used + 1], st);
+        used += 2;
+        open = -1;
+    }
+    void collect() {   // call after the stream has been synchronised
+        for (size_t i = 0; i < used; i += 2) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) {
+                ms[phase[i / 2]] += t;
+                count[phase[i / 2]] += 1;
+            }
+        }
+        used = 0;
+    }
+};
+
+#define PH_BEGIN(T, ph) do { if (T) (T)->begin(ph); } while (0)
+#define PH_END(T) do { if (T) (T)->end(); } while (0)
+
+static int check_status(bpjd_problem* p) {
+    int st = 0;
+    BPJD_HIP(hipMemcpyAsync(&st, p->status, sizeof(int), hipMemcpyDeviceToHost, p->ctx->stream));
+    BPJD_HIP(hipStreamSynchronize(p->ctx->stream));
+    if (st & STATUS_COARSE_NOT_SPD) return fail(BPJD_ERR_NOT_SPD, "coarse mass matrix M_H is not positive definite");
+    if (st & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
+    return BPJD_OK;
+}
+
+// Galerkin coarse operators and the full coarse generalized eigenproblem
+// K_H y = lambda^H M_H y, Y^T M_H Y = I (Cholesky M_H = L L^T, Jacobi on
+// L^{-1} K_H L^{-T}, back-transformation).
+static void coarse_setup(bpjd_problem* p) {
+    hipStream_t st = p->ctx->stream;
+    const int nH = p->nH;
+    launch_galerkin(st, p->n, nH, p->rowptr, p->col, p->km, p->Pptr, p->Pcol, p->Pval, p->PTptr, p->PTcol, p->PTval,
+                    p->kpptr, p->kpcol, p->kpval, p->khptr, p->khcol, p->nnzKH, p->KH, p->MH);
+    launch_cholesky(st, nH, p->MH, p->status, STATUS_COARSE_NOT_SPD);              // MH <- L
+    launch_copy_cols(st, nH, nH, p->KH, nH, p->Ccoarse, nH);
+    launch_trsm_lower(st, nH, nH, p->MH, p->Ccoarse, nH, false);                    // L^{-1} K_H
+    launch_transpose(st, nH, p->Ccoarse, p->jwork);                                 // K_H L^{-T}
+    launch_trsm_lower(st, nH, nH, p->MH, p->jwork, nH, false);                      // L^{-1} K_H L^{-T}
+    launch_jacobi_eig(st, nH, p->jwork, p->lamH, p->Ccoarse, p->Y);                 // eigvecs -> Ccoarse
+    launch_copy_cols(st, nH, nH, p->Ccoarse, nH, p->Y, nH);
+    launch_trsm_lower(st, nH, nH, p->MH, p->Y, nH, true);                           // Y = L^{-T} V
+}
+
+// Apply the two-level preconditioner to F (n x s, ld s) with shifts p->lam; Z (ld s).
+static void apply_precond(bpjd_problem* p, const double* F, double* Z, PhaseTimer* T) {
+    hipStream_t st = p->ctx->stream;
+    const int s = p->s;
+    PH_BEGIN(T, BPJD_PHASE_COARSE);
+    launch_coarse_apply(st, p->n, p->nH, s, p->PTptr, p->PTcol, p->PTval, F, s, p->Y, p->lamH, p->lam, p->G, p->Cw,
+                        p->Zhat);
+    PH_END(T);
+    const bool mixed = p->opts.precision == BPJD_PREC_MIXED;
+    PH_BEGIN(T, BPJD_PHASE_GATHER);
+    if (mixed) launch_gather_f32(st, (int)p->sumN, s, p->subidx, F, s, (float*)p->Floc);
+    else launch_gather_f64(st, (int)p->sumN, s, p->subidx, F, s, (double*)p->Floc);
+    PH_END(T);
+    PH_BEGIN(T, BPJD_PHASE_LOCAL);
+    if (mixed)
+        launch_local_solve_f32(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
+                               p->lam, (const float*)p->Floc, (float*)p->zloc, (float*)p->Lwork, p->Loff, p->status);
+    else
+        launch_local_solve_f64(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
+                               p->lam, (const double*)p->Floc, (double*)p->zloc, (double*)p->Lwork, p->Loff,
+                               p->status);
+    PH_END(T);
+    PH_BEGIN(T, BPJD_PHASE_GATHER);
+    if (mixed)
+        launch_scatter_f32(st, p->n, s, (int)p->sumN, p->Pptr, p->Pcol, p->Pval, p->Zhat, p->rptr, p->ridx,
+                           (const float*)p->zloc, Z, s);
+    else
+        launch_scatter_f64(st, p->n, s, (int)p->sumN, p->Pptr, p->Pcol, p->Pval, p->Zhat, p->rptr, p->ridx,
+                           (const double*)p->zloc, Z, s);
+    PH_END(T);
+}
+
+// M-orthonormalise the T block (columns ct..ct+s of buffer b) against the first
+// ct columns (classical Gram-Schmidt, two passes) and within itself
+// (Cholesky-QR, two passes).  K T and M T are updated by the same linear maps.
+static void orthonormalize_T(bpjd_problem* p, int b, int ct, PhaseTimer* T) {
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, ld = 3 * s;
+    double *W = p->W[b], *KW = p->KW[b], *MW = p->MW[b];
+    PH_BEGIN(T, BPJD_PHASE_ORTHO);
+    for (int pass = 0; pass < 2 && ct > 0; ++pass) {
+        launch_gram(st, n, ct, s, MW, ld, colp(W, ct), ld, p->partial, p->npart, p->csmall);
+        launch_gemm_small(st, n, ct, s, -1.0, W, ld, p->csmall, 1.0, colp(W, ct), ld);
+        launch_gemm_small(st, n, ct, s, -1.0, KW, ld, p->csmall, 1.0, colp(KW, ct), ld);
+        launch_gemm_small(st, n, ct, s, -1.0, MW, ld, p->csmall, 1.0, colp(MW, ct), ld);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        launch_gram(st, n, s, s, colp(W, ct), ld, colp(MW, ct), ld, p->partial, p->npart, p->gsmall);
+        launch_cholqr_coef(st, s, p->gsmall, p->csmall, p->dropped[b] + ct, p->status);
+        launch_rightmul_inplace(st, n, s, colp(W, ct), ld, p->csmall);
+        launch_rightmul_inplace(st, n, s, colp(KW, ct), ld, p->csmall);
+        launch_rightmul_inplace(st, n, s, colp(MW, ct), ld, p->csmall);
+    }
+    PH_END(T);
+}
+
+// Rayleigh-Ritz on W = buffer a (m columns), new X (and P when with_p) into buffer b.
+static void rayleigh_ritz(bpjd_problem* p, int a, int b, int m, int with_p, PhaseTimer* T) {
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, ld = 3 * s;
+    PH_BEGIN(T, BPJD_PHASE_RR);
+    launch_gram(st, n, m, m, p->W[a], ld, p->KW[a], ld, p->partial, p->npart, p->Hm);
+    launch_rr_coef(st, m, s, with_p, p->Hm, p->dropped[a], p->dropped[b], p->theta, p->Cfull);
+    const int cw = with_p ? 2 * s : s;
+    launch_gemm_small(st, n, m, cw, 1.0, p->W[a], ld, p->Cfull, 0.0, p->W[b], ld);
+    launch_gemm_small(st, n, m, cw, 1.0, p->KW[a], ld, p->Cfull, 0.0, p->KW[b], ld);
+    launch_gemm_small(st, n, m, cw, 1.0, p->MW[a], ld, p->Cfull, 0.0, p->MW[b], ld);
+    launch_copy_cols(st, 1, s, p->theta, s, p->lam, s);
+    PH_END(T);
+}
+
+}  // namespace bpjd
+
+// ======================================================================================
+// numeric driver
+// ======================================================================================
+namespace bpjd {
+
+static int run_setup(bpjd_problem* p) {
+    hipStream_t st = p->ctx->stream;
+    BPJD_HIP(hipSetDevice(p->ctx->device));
+    BPJD_HIP(hipMemsetAsync(p->status, 0, sizeof(int), st));
+    coarse_setup(p);
+    BPJD_TRY(check_status(p));
+    p->setup_done = true;
+    return BPJD_OK;
+}
+
+// Start block (Step 1 with H~ = H): X = P Y_s, Lambda = lambda^H_{1..s}; with a
+// caller block X_init, W^0 = span{P Y_s, X_init} and a Rayleigh-Ritz step.
+static int start_block(bpjd_problem* p) {
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, ld = 3 * s;
+    BPJD_HIP(hipMemsetAsync(p->dropped[0], 0, 64 * sizeof(int), st));
+    BPJD_HIP(hipMemsetAsync(p->dropped[1], 0, 64 * sizeof(int), st));
+    launch_csr_dense(st, n, p->Pptr, p->Pcol, p->Pval, p->Y, p->nH, s, p->W[0], ld, false);
+    launch_copy_cols(st, 1, s, p->lamH, s, p->lam, s);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0], ld, s, p->KW[0], ld, p->MW[0], ld);
+    if (p->n_init) {
+        BPJD_HIP(hipMemcpyAsync(p->Z, p->X_init.data(), sizeof(double) * n * s, hipMemcpyHostToDevice, st));
+        launch_copy_cols(st, n, s, p->Z, s, p->W[0] + s, ld);
+        launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0] + s, ld, s, p->KW[0] + s, ld, p->MW[0] + s, ld);
+        orthonormalize_T(p, 0, s, nullptr);
+        rayleigh_ritz(p, 0, 1, 2 * s, 0, nullptr);
+        // result in buffer 1: move it back to buffer 0 (the iteration starts from buffer 0)
+        launch_copy_cols(st, n, s, p->W[1], ld, p->W[0], ld);
+        launch_copy_cols(st, n, s, p->KW[1], ld, p->KW[0], ld);
+        launch_copy_cols(st, n, s, p->MW[1], ld, p->MW[0], ld);
+        BPJD_HIP(hipMemsetAsync(p->dropped[0], 0, 64 * sizeof(int), st));
+    }
+    return BPJD_OK;
+}
+
+struct IterState {
+    int cur = 0;        // buffer holding X (and P)
+    int np = 0;         // columns of P in use (0 or s)
+};
+
+static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem, bpjd_stats* stats) {
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, k = p->k, ld = 3 * s;
+    const bool uu = p->opts.subspace == BPJD_SUBSPACE_UU;
+    hipEvent_t e0, e1, e2;
+    BPJD_HIP(hipEventCreate(&e0));
+    BPJD_HIP(hipEventCreate(&e1));
+    BPJD_HIP(hipEventCreate(&e2));
+    PhaseTimer timer;
+    timer.st = st;
+    PhaseTimer* T = p->opts.profile ? &timer : nullptr;
+    BPJD_HIP(hipEventRecord(e0, st));
+    PH_BEGIN(T, BPJD_PHASE_SETUP);
+    BPJD_TRY(run_setup(p));
+    BPJD_TRY(start_block(p));
+    PH_END(T);
+    BPJD_HIP(hipEventRecord(e1, st));
+
+    IterState S;
+    std::vector<double> lam_prev(s, 0.0), lam_now(s, 0.0), rho(s, 0.0);
+    bool converged = false;
+    int iters = 0;
+    double stop_value = NAN;
+    double* h = p->hbuf;
+    int* hstatus = reinterpret_cast<int*>(h + 3 * 64);
+    for (int it = 0; it <= p->opts.max_iter; ++it) {
+        const int a = S.cur;
+        // residual block F = M X Lambda - K X and its column norms
+        PH_BEGIN(T, BPJD_PHASE_RESIDUAL);
+        launch_residual(st, n, s, p->KW[a], ld, p->MW[a], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq);
+        PH_END(T);
+        BPJD_HIP(hipMemcpyAsync(h, p->colsq, sizeof(double) * 2 * s, hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipMemcpyAsync(h + 2 * 64, p->lam, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipMemcpyAsync(hstatus, p->status, sizeof(int), hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipStreamSynchronize(st));
+        if (T) T->collect();
+        if (*hstatus & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
+        for (int i = 0; i < s; ++i) {
+            lam_now[i] = h[128 + i];
+            rho[i] = std::sqrt(h[i]) / (std::fabs(lam_now[i]) * std::sqrt(h[s + i]));
+        }
+        double rmax = 0.0;
+        bool finite = true;
+        for (int i = 0; i < k; ++i) {
+            rmax = std::max(rmax, rho[i]);
+            finite = finite && std::isfinite(rho[i]);
+        }
+        if (p->trace) {
+            std::fprintf(stderr, "[bpjd] it %d rho_max %.3e lam:", it, rmax);
+            for (int i = 0; i < s; ++i) std::fprintf(stderr, " %.12g", lam_now[i]);
+            std::fprintf(stderr, "\n");
+        }
+        if (!finite) return fail(BPJD_ERR_NOT_SPD, "non-finite residual (breakdown)");
+        if (it > 0) {
+            stop_value = 0.0;
+            for (int i = 0; i < s; ++i) stop_value += std::fabs(lam_now[i] - lam_prev[i]);
+        }
+        if (p->opts.stop_rule == BPJD_STOP_RESIDUAL && rmax <= p->opts.tol) {
+            converged = true;
+            break;
+        }
+        if (p->opts.stop_rule == BPJD_STOP_PAPER && it > 0 && stop_value < p->opts.tol) {
+            converged = true;
+            break;
+        }
+        if (it == p->opts.max_iter) break;
+        lam_prev = lam_now;
+
+        // Step 2: t_i = (I - X X^T M) (B_i)^{-1} r_i
+        apply_precond(p, p->F, p->Z, T);
+        const int ct = s + S.np;
+        PH_BEGIN(T, BPJD_PHASE_ORTHO);
+        launch_gram(st, n, s, s, p->MW[a], ld, p->Z, s, p->partial, p->npart, p->csmall);
+        launch_copy_cols(st, n, s, p->Z, s, p->W[a] + ct, ld);
+        launch_gemm_small(st, n, s, s, -1.0, p->W[a], ld, p->csmall, 1.0, p->W[a] + ct, ld);
+        PH_END(T);
+        PH_BEGIN(T, BPJD_PHASE_SPMM);
+        launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[a] + ct, ld, s, p->KW[a] + ct, ld, p->MW[a] + ct, ld);
+        PH_END(T);
+        // Step 3: Rayleigh-Ritz on W = [X | P | T]
+        orthonormalize_T(p, a, ct, T);
+        rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, T);
+        if (p->trace) {
+            int fl[128];
+            BPJD_HIP(hipMemcpyAsync(fl, p->dropped[a], sizeof(int) * (ct + s), hipMemcpyDeviceToHost, st));
+            BPJD_HIP(hipMemcpyAsync(fl + 64, p->dropped[1 - a], sizeof(int) * 2 * s, hipMemcpyDeviceToHost, st));
+            double th[64];
+            BPJD_HIP(hipMemcpyAsync(th, p->theta, sizeof(double) * (ct + s), hipMemcpyDeviceToHost, st));
+            BPJD_HIP(hipStreamSynchronize(st));
+            std::fprintf(stderr, "[bpjd]   m=%d drop_in:", ct + s);
+            for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, "%d", fl[q]);
+            std::fprintf(stderr, " drop_out:");
+            for (int q = 0; q < 2 * s; ++q) std::fprintf(stderr, "%d", fl[64 + q]);
+            std::fprintf(stderr, " theta:");
+            for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, " %.6g", th[q]);
+            std::fprintf(stderr, "\n");
+        }
+        S.cur = 1 - a;
+        S.np = uu ? s : 0;
+        iters = it + 1;
+    }
+    BPJD_HIP(hipEventRecord(e2, st));
+    BPJD_HIP(hipEventSynchronize(e2));
+    if (T) T->collect();
+    float ms_setup = 0.f, ms_iter = 0.f;
+    BPJD_HIP(hipEventElapsedTime(&ms_setup, e0, e1));
+    BPJD_HIP(hipEventElapsedTime(&ms_iter, e1, e2));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+
+    const int a = S.cur;
+    if (eigvals) {
+        if (mem == BPJD_MEM_DEVICE) {
+            BPJD_HIP(hipMemcpyAsync(eigvals, p->lam, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+        } else {
+            std::memcpy(eigvals, lam_now.data(), sizeof(double) * k);
+        }
+    }
+    if (eigvecs) {
+        if (mem == BPJD_MEM_DEVICE) {
+            launch_copy_cols(st, n, k, p->W[a], ld, eigvecs, k);
+        } else {
+            launch_copy_cols(st, n, k, p->W[a], ld, p->Z, k);
+            BPJD_HIP(hipMemcpyAsync(eigvecs, p->Z, sizeof(double) * n * k, hipMemcpyDeviceToHost, st));
+        }
+    }
+    BPJD_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = iters;
+        stats->converged = converged ? 1 : 0;
+        stats->stop_value = stop_value;
+        double rmax = 0.0;
+        for (int i = 0; i < k; ++i) rmax = std::max(rmax, rho[i]);
+        stats->max_residual = rmax;
+        for (int i = 0; i < k && i < 64; ++i) stats->residuals[i] = rho[i];
+        stats->setup_ms = ms_setup;
+        stats->iterate_ms = ms_iter;
+        stats->n_sub = p->nsub;
+        stats->n_coarse = p->nH;
+        stats->max_local = p->maxN;
+        stats->max_band = p->maxBW;
+        for (int q = 0; q < BPJD_NUM_PHASES; ++q) {
+            stats->phase_ms[q] = timer.ms[q];
+            stats->phase_count[q] = timer.count[q];
+        }
+    }
+    if (!converged) return fail(BPJD_ERR_NOCONV, "maximum number of iterations reached");
+    return BPJD_OK;
+}
+
+}  // namespace bpjd
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+using namespace bpjd;
+
+extern "C" {
+
+void bpjd_opts_default(bpjd_opts* o, int32_t k) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->k = k;
+    o->guard = 0;
+    o->max_iter = 500;
+    o->tol = 1e-8;
+    o->stop_rule = BPJD_STOP_RESIDUAL;
+    o->subspace = BPJD_SUBSPACE_UU;
+    o->precision = BPJD_PREC_MIXED;
+    o->n_init = 0;
+    o->X_init = nullptr;
+}
+
+int bpjd_ctx_create(int device, void* hip_stream, bpjd_ctx** out) {
+    if (!out) return fail(BPJD_ERR_ARG, "out is NULL");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(BPJD_ERR_HIP, "no HIP device");
+    if (device < 0 || device >= count) return fail(BPJD_ERR_ARG, "device ordinal out of range");
+    BPJD_HIP(hipSetDevice(device));
+    bpjd_ctx* c = new bpjd_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return fail(BPJD_ERR_HIP, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return BPJD_OK;
+}
+
+void bpjd_ctx_destroy(bpjd_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
+                        const bpjd_opts* opts, bpjd_problem** out) {
+    if (!ctx || !K || !M || !dd || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+    HostCSR hK, hM, P;
+    Pattern U;
+    BPJD_TRY(read_pair(K, M, hK, hM, U));
+    if (dd->P.n_rows != U.n || dd->P.n_cols < 1) return fail(BPJD_ERR_DD, "P must be n x n_H");
+    {
+        // P is rectangular: read it without the square check
+        bpjd_csr Pc = dd->P;
+        const int nH = Pc.n_cols;
+        Pc.n_cols = Pc.n_rows;
+        HostCSR tmp;
+        // reuse the reader for bounds/order checks against n_rows, then re-check columns against n_H
+        int rc = read_csr(&Pc, "P", tmp);
+        if (rc < 0 && rc != BPJD_ERR_CSR) return rc;
+        if (rc == BPJD_ERR_CSR) return fail(BPJD_ERR_DD, "P: " + std::string(g_last_error));
+        for (int c : tmp.col)
+            if (c >= nH) return fail(BPJD_ERR_DD, "P column index out of range");
+        P = tmp;
+        if (dd->n_sub < 1 || !dd->sub_ptr || !dd->sub_idx) return fail(BPJD_ERR_DD, "no subdomains");
+        std::vector<int> sptr(dd->sub_ptr, dd->sub_ptr + dd->n_sub + 1);
+        if (sptr[0] != 0) return fail(BPJD_ERR_DD, "sub_ptr[0] must be 0");
+        for (int l = 0; l < dd->n_sub; ++l)
+            if (sptr[l + 1] < sptr[l]) return fail(BPJD_ERR_DD, "sub_ptr not monotone");
+        std::vector<int> sidx(dd->sub_idx, dd->sub_idx + sptr[dd->n_sub]);
+        return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out);
+    }
+}
+
+int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd_geom* g,
+                             const bpjd_opts* opts, bpjd_problem** out) {
+    if (!ctx || !K || !M || !g || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+    if (!g->coords || !g->cx || !g->cy || g->n_cx < 2 || g->n_cy < 2) return fail(BPJD_ERR_ARG, "bad coarse grid");
+    HostCSR hK, hM, P;
+    Pattern U;
+    BPJD_TRY(read_pair(K, M, hK, hM, U));
+    std::vector<double> cx(g->cx, g->cx + g->n_cx), cy(g->cy, g->cy + g->n_cy);
+    for (size_t i = 0; i + 1 < cx.size(); ++i)
+        if (!(cx[i + 1] > cx[i])) return fail(BPJD_ERR_ARG, "cx not increasing");
+    for (size_t i = 0; i + 1 < cy.size(); ++i)
+        if (!(cy[i + 1] > cy[i])) return fail(BPJD_ERR_ARG, "cy not increasing");
+    int nH = 0;
+    build_p1_prolongation(U.n, g->coords, cx, cy, P, nH);
+    if (nH < 1) return fail(BPJD_ERR_DD, "coarse grid has no interior vertex");
+    std::vector<int> sptr, sidx;
+    BPJD_TRY(build_geom_subdomains(U, g->coords, cx, cy, g->overlap_layers, sptr, sidx));
+    return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out);
+}
+
+void bpjd_problem_destroy(bpjd_problem* p) {
+    if (!p) return;
+    for (void* d : p->allocations) (void)hipFree(d);
+    if (p->hbuf) (void)hipHostFree(p->hbuf);
+    delete p;
+}
+
+int bpjd_problem_set_values(bpjd_problem* p, const double* Kval, const double* Mval, int32_t mem) {
+    if (!p || !Kval || !Mval) return fail(BPJD_ERR_ARG, "NULL argument");
+    std::vector<double> kv(p->nnzK), mv(p->nnzM);
+    if (mem == BPJD_MEM_DEVICE) {
+        BPJD_HIP(hipMemcpy(kv.data(), Kval, sizeof(double) * p->nnzK, hipMemcpyDeviceToHost));
+        BPJD_HIP(hipMemcpy(mv.data(), Mval, sizeof(double) * p->nnzM, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(kv.data(), Kval, sizeof(double) * p->nnzK);
+        std::memcpy(mv.data(), Mval, sizeof(double) * p->nnzM);
+    }
+    std::vector<double2> km(p->nnz, make_double2(0.0, 0.0));
+    for (long long q = 0; q < p->nnzK; ++q) km[p->Kmap[q]].x = kv[q];
+    for (long long q = 0; q < p->nnzM; ++q) km[p->Mmap[q]].y = mv[q];
+    BPJD_HIP(hipMemcpy(p->km, km.data(), sizeof(double2) * p->nnz, hipMemcpyHostToDevice));
+    p->setup_done = false;
+    return BPJD_OK;
+}
+
+int bpjd_problem_dims(const bpjd_problem* p, int32_t* n, int32_t* n_coarse, int32_t* n_sub, int32_t* s) {
+    if (!p) return fail(BPJD_ERR_ARG, "NULL problem");
+    if (n) *n = p->n;
+    if (n_coarse) *n_coarse = p->nH;
+    if (n_sub) *n_sub = p->nsub;
+    if (s) *s = p->s;
+    return BPJD_OK;
+}
+
+int bpjd_problem_local_sizes(const bpjd_problem* p, int32_t* n_l, int32_t* bw) {
+    if (!p || !n_l || !bw) return fail(BPJD_ERR_ARG, "NULL argument");
+    for (int l = 0; l < p->nsub; ++l) {
+        n_l[l] = p->h_nl[l];
+        bw[l] = p->h_bw[l];
+    }
+    return BPJD_OK;
+}
+
+int bpjd_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int32_t mem, bpjd_stats* st) {
+    if (!p) return fail(BPJD_ERR_ARG, "NULL problem");
+    if (mem != BPJD_MEM_HOST && mem != BPJD_MEM_DEVICE) return fail(BPJD_ERR_ARG, "bad mem");
+    return run_solve(p, eigvals, eigvecs, mem, st);
+}
+
+int bpjd_setup(bpjd_problem* p) {
+    if (!p) return fail(BPJD_ERR_ARG, "NULL problem");
+    return run_setup(p);
+}
+
+int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* lambda, double* Z, int32_t mem) {
+    if (!p || !X || !lambda || !Z) return fail(BPJD_ERR_ARG, "NULL argument");
+    if (!p->setup_done) return fail(BPJD_ERR_STATE, "call bpjd_setup first");
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, ld = 3 * s;
+    const hipMemcpyKind kin = mem == BPJD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    BPJD_HIP(hipMemcpyAsync(p->Z, X, sizeof(double) * n * s, kin, st));
+    BPJD_HIP(hipMemcpyAsync(p->lam, lambda, sizeof(double) * s, kin, st));
+    launch_copy_cols(st, n, s, p->Z, s, p->W[1], ld);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[1], ld, s, p->KW[1], ld, p->MW[1], ld);
+    BPJD_HIP(hipMemsetAsync(p->status, 0, sizeof(int), st));
+    launch_residual(st, n, s, p->KW[1], ld, p->MW[1], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq);
+    apply_precond(p, p->F, p->Z, nullptr);
+    const hipMemcpyKind kout = mem == BPJD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    BPJD_HIP(hipMemcpyAsync(Z, p->Z, sizeof(double) * n * s, kout, st));
+    BPJD_HIP(hipStreamSynchronize(st));
+    return check_status(p);
+}
+
+int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, double* MX, int32_t mem) {
+    if (!p || !X || !KX || !MX) return fail(BPJD_ERR_ARG, "NULL argument");
+    if (ncols < 1 || ncols > 3 * p->s) return fail(BPJD_ERR_ARG, "ncols must be in [1, 3s]");
+    hipStream_t st = p->ctx->stream;
+    const size_t bytes = sizeof(double) * (size_t)p->n * ncols;
+    const double* dX = X;
+    if (mem == BPJD_MEM_HOST) {
+        BPJD_HIP(hipMemcpyAsync(p->W[1], X, bytes, hipMemcpyHostToDevice, st));
+        dX = p->W[1];
+    }
+    double* dK = mem == BPJD_MEM_HOST ? p->KW[1] : KX;
+    double* dM = mem == BPJD_MEM_HOST ? p->MW[1] : MX;
+    launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, dX, ncols, ncols, dK, ncols, dM, ncols);
+    if (mem == BPJD_MEM_HOST) {
+        BPJD_HIP(hipMemcpyAsync(KX, dK, bytes, hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipMemcpyAsync(MX, dM, bytes, hipMemcpyDeviceToHost, st));
+    }
+    BPJD_HIP(hipStreamSynchronize(st));
+    return BPJD_OK;
+}
+
+int bpjd_coarse_eigenvalues(bpjd_problem* p, double* lamH, int32_t mem) {
+    if (!p || !lamH) return fail(BPJD_ERR_ARG, "NULL argument");
+    if (!p->setup_done) return fail(BPJD_ERR_STATE, "call bpjd_setup first");
+    const hipMemcpyKind k = mem == BPJD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    BPJD_HIP(hipMemcpyAsync(lamH, p->lamH, sizeof(double) * p->nH, k, p->ctx->stream));
+    BPJD_HIP(hipStreamSynchronize(p->ctx->stream));
+    return BPJD_OK;
+}
+
+const char* bpjd_strerror(int code) {
+    switch (code) {
+        case BPJD_OK: return "ok";
+        case BPJD_PENDING: return "pending";
+        case BPJD_ERR_ARG: return "invalid argument";
+        case BPJD_ERR_CSR: return "malformed CSR matrix";
+        case BPJD_ERR_DD: return "invalid domain decomposition";
+        case BPJD_ERR_NOT_SPD: return "matrix not positive definite / breakdown";
+        case BPJD_ERR_NOCONV: return "not converged";
+        case BPJD_ERR_OOM: return "out of device memory";
+        case BPJD_ERR_HIP: return "HIP runtime error";
+        case BPJD_ERR_OVER_BUDGET: return "request exceeds the memory budget";
+        case BPJD_ERR_STATE: return "invalid state";
+        default: return "unknown error";
+    }
+}
+
+const char* bpjd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

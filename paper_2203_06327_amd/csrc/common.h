@@ -1,0 +1,168 @@
+// Internal declarations shared by the library's translation units.
+// Every kernel is launched through a host launcher defined next to it, so the
+// .hip files link without relocatable device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bpjd.h"
+
+namespace bpjd {
+
+// ---- error plumbing ---------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define BPJD_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::bpjd::fail(BPJD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define BPJD_TRY(expr)              \
+    do {                            \
+        int r_ = (expr);            \
+        if (r_ < 0) return r_;      \
+    } while (0)
+
+// Device status word bits raised by kernels (read back by the host).
+enum : int {
+    STATUS_LOCAL_PIVOT = 1,       // zero/non-finite pivot in a local LDL^T factorisation
+    STATUS_COARSE_NOT_SPD = 2,    // M_H not positive definite
+    STATUS_GRAM_DROP = 4,         // a new direction was linearly dependent and dropped
+    STATUS_NONFINITE = 8,         // NaN/Inf met in a reduction
+};
+
+inline int grid_for(long long work, int block) {
+    long long g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 2147483647LL) g = 2147483647LL;
+    return (int)g;
+}
+
+// ---- launchers: block linear algebra (blas.hip) -------------------------------
+// KX = K X, MX = M X on the union pattern (km holds (K, M) value pairs).
+void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, const double2* km,
+                    const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm);
+// Y = A * B with A CSR (rows x ?) and B dense (row-major, ldb), ncols columns; Y(ldy).
+// accumulate: Y += instead of Y =.
+void launch_csr_dense(hipStream_t st, int rows, const int* ptr, const int* col, const double* val,
+                      const double* B, int ldb, int ncols, double* Y, int ldy, bool accumulate);
+// F = MX diag(lam) - KX; colsq[0..s) = ||F_i||^2, colsq[s..2s) = ||MX_i||^2 (two-pass, deterministic).
+void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, const double* MX, int ldm,
+                     const double* lam, double* F, int ldf, double* partial, int npart, double* colsq);
+// C (a x b, row-major) = A^T B with A: n x a (lda), B: n x b (ldb); deterministic two-pass.
+void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, const double* B, int ldb,
+                 double* partial, int npart, double* C);
+// Y(:, 0..b) = beta*Y + alpha * A(:, 0..a) * C, C a x b row-major (ldc = b).
+void launch_gemm_small(hipStream_t st, int n, int a, int b, double alpha, const double* A, int lda,
+                       const double* C, double beta, double* Y, int ldy);
+// In place: Y(:, 0..b) = Y(:, 0..b) * C, C b x b row-major.
+void launch_rightmul_inplace(hipStream_t st, int n, int b, double* Y, int ldy, const double* C);
+// Copy/convert helpers.
+void launch_copy_cols(hipStream_t st, int n, int ncols, const double* src, int lds, double* dst, int ldd);
+void launch_fill(hipStream_t st, long long count, double* dst, double value);
+int  num_partials(int n);
+
+// ---- launchers: preconditioner (precond.hip) --------------------------------
+void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int* col, const double2* km,
+                     const int* Pptr, const int* Pcol, const double* Pval,
+                     const int* PTptr, const int* PTcol, const double* PTval,
+                     const int* kpptr, const int* kpcol, double2* kpval,
+                     const int* khptr, const int* khcol, int nnzKH, double* KH, double* MH);
+// Zhat = Y (C / (lamH_j - lam_i), rows j < s zeroed) with C = Y^T G; G = P^T F.
+void launch_coarse_apply(hipStream_t st, int n, int nH, int s,
+                         const int* PTptr, const int* PTcol, const double* PTval,
+                         const double* F, int ldf, const double* Y, const double* lamH, const double* lam,
+                         double* G, double* Cw, double* Zhat);
+void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, double* Floc);
+void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc);
+// Batched local LDL^T factor + solve, one wavefront per (subdomain, shift).
+// Floc/zloc: [s][sumN]; Lwork: per (l,i) n_l*(bw_l+1) entries at Loff[l] + i*n_l*(bw_l+1).
+void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
+                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            const double* lam, const double* Floc, double* zloc, double* Lwork,
+                            const long long* Loff, int* status);
+void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
+                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            const double* lam, const float* Floc, float* zloc, float* Lwork,
+                            const long long* Loff, int* status);
+// Z(d, i) = sum_b P(d,b) Zhat(b,i) + sum_{(l,r) covering d} zloc_i(l,r)  (deterministic order).
+void launch_scatter_f64(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
+                        const double* Zhat, const int* rptr, const int* ridx, const double* zloc, double* Z, int ldz);
+void launch_scatter_f32(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
+                        const double* Zhat, const int* rptr, const int* ridx, const float* zloc, double* Z, int ldz);
+
+// ---- launchers: small dense kernels (dense.hip) -----------------------------
+// Lower Cholesky of an n x n SPD matrix (row-major, in place, lower part); status bit on failure.
+void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_bit);
+// Solve L X = B for X (L lower n x n, B n x nrhs row-major with ldb), in place in B.
+void launch_trsm_lower(hipStream_t st, int n, int nrhs, const double* L, double* B, int ldb, bool transposeL);
+// Symmetric eigensolver (cyclic Jacobi, one workgroup): A n x n (destroyed), eigenvalues
+// ascending in w, eigenvectors as columns of V (n x n row-major). work: 2 n^2 doubles.
+void launch_jacobi_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work);
+// Transpose-copy helpers for the coarse eigenproblem.
+void launch_transpose(hipStream_t st, int n, const double* A, double* AT);
+// CholQR coefficients: G (b x b) -> C = D^{-1/2} L^{-T} (G scaled by D = diag(G) = L L^T);
+// directions with a pivot below the drop tolerance get a zero column and dropped[j] = 1.
+void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* dropped, int* status);
+// Rayleigh-Ritz coefficient step: given H (m x m) and the dropped flags of all m columns
+// of W, returns theta (m), Cfull (m x 2s) = [Q_s | orthonormal basis of span{E_x, Q_s}
+// minus Q_s] and the dropped flags of the new basis' first 2s (or s) columns.
+void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
+                    double* theta, double* Cfull);
+
+}  // namespace bpjd
+
+// ---- the opaque objects ---------------------------------------------------------
+struct bpjd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+};
+
+struct bpjd_problem {
+    bpjd_ctx* ctx = nullptr;
+    bpjd_opts opts{};
+    int n = 0, nH = 0, nsub = 0, s = 0, k = 0;
+    long long nnz = 0;                 // union pattern
+    long long sumN = 0;                // sum of subdomain sizes
+    int maxN = 0, maxBW = 0, maxC = 0;
+    long long nnzK = 0, nnzM = 0;
+    std::vector<long long> Kmap, Mmap; // original nnz position -> union position
+    std::vector<double> X_init;        // n x s (host copy), optional
+    int n_init = 0;
+
+    // device structural data
+    int *rowptr = nullptr, *col = nullptr;
+    double2* km = nullptr;
+    int *Pptr = nullptr, *Pcol = nullptr; double* Pval = nullptr;
+    int *PTptr = nullptr, *PTcol = nullptr; double* PTval = nullptr;
+    int *kpptr = nullptr, *kpcol = nullptr; double2* kpval = nullptr;
+    int *khptr = nullptr, *khcol = nullptr;
+    int *subptr = nullptr, *subidx = nullptr, *bw = nullptr;
+    int *lptr = nullptr, *ldd = nullptr, *lpos = nullptr;
+    int *rptr = nullptr, *ridx = nullptr;
+    long long* Loff = nullptr;
+
+    // device numeric workspace
+    double *KH = nullptr, *MH = nullptr, *Ccoarse = nullptr, *Y = nullptr, *lamH = nullptr, *jwork = nullptr;
+    double *W[2] = {nullptr, nullptr}, *KW[2] = {nullptr, nullptr}, *MW[2] = {nullptr, nullptr};
+    double *F = nullptr, *Z = nullptr, *Zhat = nullptr, *G = nullptr, *Cw = nullptr;
+    void *Floc = nullptr, *zloc = nullptr, *Lwork = nullptr;
+    double *partial = nullptr, *colsq = nullptr, *lam = nullptr;
+    double *gsmall = nullptr, *csmall = nullptr, *Hm = nullptr, *theta = nullptr, *Cfull = nullptr, *rrwork = nullptr;
+    int *dropped[2] = {nullptr, nullptr}, *status = nullptr;   // per-buffer flags of W's columns
+    double* hbuf = nullptr;            // pinned host mirror for per-iteration scalars
+    int npart = 0;
+    int nnzKH = 0;
+    bool trace = false;
+    std::vector<int> h_nl, h_bw;     // host copies of subdomain sizes / half-bandwidths
+    bool setup_done = false;
+    std::vector<void*> allocations;
+};

@@ -1,0 +1,349 @@
+// Two-level additive Schwarz preconditioner of Section 3 (eq. Preconditioner):
+//   Z_i = P (B_0,i)^{-1} Q^H_{s+1} Q^H r_i  +  sum_l R_l^T (K_l - lambda_i M_l)^{-1} R_l F_i
+// with F_i = lambda_i M x_i - K x_i the residual in the dual (load-vector) form.
+//
+// Coarse term: G = P^T F; on the coarse eigenbasis (Y, lambda^H), components
+// j < s are removed (Q^H_{s+1}) and the others divided by lambda^H_j - lambda_i.
+// Local term: per (subdomain l, shift i) an LDL^T factorisation of the banded
+// local matrix K_l - lambda_i M_l and one solve.  Subdomain values are
+// gathered into a contiguous per-shift array, solved, and summed back in a
+// fixed order per dof (gather form of the overlapping scatter).
+#include "common.h"
+
+namespace bpjd {
+
+// ---------------------------------------------------------------------------
+// Galerkin coarse operators K_H = P^T K P, M_H = P^T M P on a host-computed
+// pattern: first KP (fine rows, coarse columns), then one thread per nonzero
+// of the coarse pattern.  Every sum runs in a fixed order.
+__global__ void galerkin_kp_kernel(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                   const double2* __restrict__ km, const int* __restrict__ Pptr,
+                                   const int* __restrict__ Pcol, const double* __restrict__ Pval,
+                                   const int* __restrict__ kpptr, const int* __restrict__ kpcol,
+                                   double2* __restrict__ kpval) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e0 = kpptr[i], e1 = kpptr[i + 1];
+    for (int e = e0; e < e1; ++e) kpval[e] = make_double2(0.0, 0.0);
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        const int j = col[p];
+        const double2 v = km[p];
+        for (int q = Pptr[j]; q < Pptr[j + 1]; ++q) {
+            const int b = Pcol[q];
+            const double w = Pval[q];
+            for (int e = e0; e < e1; ++e) {
+                if (kpcol[e] == b) {
+                    kpval[e].x = fma(v.x, w, kpval[e].x);
+                    kpval[e].y = fma(v.y, w, kpval[e].y);
+                    break;
+                }
+            }
+        }
+    }
+}
+
+__global__ void galerkin_kh_kernel(int nH, int nnzKH, const int* __restrict__ PTptr, const int* __restrict__ PTcol,
+                                   const double* __restrict__ PTval, const int* __restrict__ kpptr,
+                                   const int* __restrict__ kpcol, const double2* __restrict__ kpval,
+                                   const int* __restrict__ khptr, const int* __restrict__ khcol,
+                                   double* __restrict__ KH, double* __restrict__ MH) {
+    const int e2 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e2 >= nnzKH) return;
+    // coarse row a of this pattern entry (binary search in khptr)
+    int lo = 0, hi = nH;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (khptr[mid] <= e2) lo = mid; else hi = mid;
+    }
+    const int a = lo;
+    const int b = khcol[e2];
+    double ak = 0.0, am = 0.0;
+    for (int q = PTptr[a]; q < PTptr[a + 1]; ++q) {
+        const int i = PTcol[q];
+        const double w = PTval[q];
+        for (int e = kpptr[i]; e < kpptr[i + 1]; ++e) {
+            if (kpcol[e] == b) {
+                ak = fma(w, kpval[e].x, ak);
+                am = fma(w, kpval[e].y, am);
+                break;
+            }
+        }
+    }
+    KH[(long long)a * nH + b] = ak;
+    MH[(long long)a * nH + b] = am;
+}
+
+void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int* col, const double2* km,
+                     const int* Pptr, const int* Pcol, const double* Pval,
+                     const int* PTptr, const int* PTcol, const double* PTval,
+                     const int* kpptr, const int* kpcol, double2* kpval,
+                     const int* khptr, const int* khcol, int nnzKH, double* KH, double* MH) {
+    launch_fill(st, (long long)nH * nH, KH, 0.0);
+    launch_fill(st, (long long)nH * nH, MH, 0.0);
+    hipLaunchKernelGGL(galerkin_kp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, n, rowptr, col, km, Pptr, Pcol,
+                       Pval, kpptr, kpcol, kpval);
+    hipLaunchKernelGGL(galerkin_kh_kernel, dim3(grid_for(nnzKH, 256)), dim3(256), 0, st, nH, nnzKH, PTptr,
+                       PTcol, PTval, kpptr, kpcol, kpval, khptr, khcol, KH, MH);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse term.
+// G = P^T F: one workgroup per coarse dof a; threads stride over the support of
+// the coarse basis function and reduce per column in a fixed tree order.
+__global__ void restrict_kernel(int nH, int s, const int* __restrict__ PTptr, const int* __restrict__ PTcol,
+                                const double* __restrict__ PTval, const double* __restrict__ F, int ldf,
+                                double* __restrict__ G) {
+    __shared__ double red[256 * 8];
+    const int a = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int i0 = 0; i0 < s; i0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+        for (int q = PTptr[a] + t; q < PTptr[a + 1]; q += blockDim.x) {
+            const double w = PTval[q];
+            const double* frow = F + (long long)PTcol[q] * ldf + i0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < s) acc[u] = fma(w, frow[u], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) red[u * 256 + t] = acc[u];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) red[u * 256 + t] += red[u * 256 + t + o];
+            }
+            __syncthreads();
+        }
+        if (t < 8 && i0 + t < s) G[a * s + i0 + t] = red[t * 256];
+        __syncthreads();
+    }
+}
+
+__global__ void coarse_coef_kernel(int nH, int s, const double* __restrict__ Y, const double* __restrict__ G,
+                                   const double* __restrict__ lamH, const double* __restrict__ lam,
+                                   double* __restrict__ Cw) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nH * s) return;
+    const int j = t / s, i = t % s;
+    if (j < s) {            // Q^H_{s+1} removes the first s coarse eigenvectors
+        Cw[t] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int b = 0; b < nH; ++b) acc = fma(Y[(long long)b * nH + j], G[b * s + i], acc);
+    Cw[t] = acc / (lamH[j] - lam[i]);
+}
+
+__global__ void coarse_back_kernel(int nH, int s, const double* __restrict__ Y, const double* __restrict__ Cw,
+                                   double* __restrict__ Zhat) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nH * s) return;
+    const int b = t / s, i = t % s;
+    const double* yrow = Y + (long long)b * nH;
+    double acc = 0.0;
+    for (int j = s; j < nH; ++j) acc = fma(yrow[j], Cw[j * s + i], acc);
+    Zhat[t] = acc;
+}
+
+void launch_coarse_apply(hipStream_t st, int n, int nH, int s, const int* PTptr, const int* PTcol,
+                         const double* PTval, const double* F, int ldf, const double* Y, const double* lamH,
+                         const double* lam, double* G, double* Cw, double* Zhat) {
+    (void)n;
+    const int work = nH * s;
+    hipLaunchKernelGGL(restrict_kernel, dim3(nH), dim3(256), 0, st, nH, s, PTptr, PTcol, PTval, F, ldf, G);
+    hipLaunchKernelGGL(coarse_coef_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, nH, s, Y, G, lamH, lam, Cw);
+    hipLaunchKernelGGL(coarse_back_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, nH, s, Y, Cw, Zhat);
+}
+
+// ---------------------------------------------------------------------------
+// Gather R_l F into per-shift contiguous arrays Floc[i][pos] (pos runs over
+// all subdomains' dofs in subdomain order), converting to the solve precision.
+template <typename T>
+__global__ void gather_kernel(int sumN, int s, const int* __restrict__ subidx, const double* __restrict__ F, int ldf,
+                              T* __restrict__ Floc) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= sumN) return;
+    const double* frow = F + (long long)subidx[pos] * ldf;
+    for (int i = 0; i < s; ++i) Floc[(long long)i * sumN + pos] = (T)frow[i];
+}
+
+void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, double* Floc) {
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(grid_for(sumN, 256)), dim3(256), 0, st, sumN, s, subidx, F, ldf,
+                       Floc);
+}
+void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc) {
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(grid_for(sumN, 256)), dim3(256), 0, st, sumN, s, subidx, F, ldf,
+                       Floc);
+}
+
+// ---------------------------------------------------------------------------
+// Local solves.  One 64-lane workgroup per (subdomain l, shift i).  The local
+// matrix A = K_l - lambda_i M_l has half-bandwidth w in the subdomain's dof
+// order; its active window (rows j..j+w, band offsets 0..w) lives in LDS as a
+// circular buffer of C = w+1 rows.  Right-looking LDL^T: at step j the pivot
+// d_j = A_jj, the column l_{j+a,j} = A_{j+a,j}/d_j is stored, and the window is
+// updated A_{j+a,j+a-b} -= l_{j+a,j} A_{j+b,j}.  The forward substitution with
+// the unit lower factor runs in the same sweep; the backward sweep reads the
+// stored columns back.  Rows enter the window from the sparse lower pattern of
+// the union matrix (lptr/ldd/lpos: local row -> band offset, union nnz index).
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void local_ldlt_kernel(
+    int s, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ lptr,
+    const int* __restrict__ ldd, const int* __restrict__ lpos, const double2* __restrict__ km,
+    const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
+    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
+    extern __shared__ unsigned char smem_raw[];
+    T* win = reinterpret_cast<T*>(smem_raw);
+    const int sys = blockIdx.x;
+    const int l = sys / s;
+    const int i = sys - l * s;
+    const int off = subptr[l];
+    const int nl = subptr[l + 1] - off;
+    const int w = bwv[l];
+    const int C = w + 1;
+    T* ywin = win + C * C;
+    T* zwin = ywin + C;
+    const double lamd = lam[i];
+    T* Lc = Lwork + Loff[l] + (long long)i * nl * C;
+    const T* f = Floc + (long long)i * ldF + off;
+    T* z = zloc + (long long)i * ldF + off;
+    const int lane = threadIdx.x;
+
+    for (int e = lane; e < C * C + 2 * C; e += 64) win[e] = T(0);
+    __syncthreads();
+    const int r0max = min(C, nl);
+    for (int r = lane; r < r0max; r += 64) {
+        T* row = win + r * C;
+        for (int e = lptr[off + r]; e < lptr[off + r + 1]; ++e) {
+            const double2 v = km[lpos[e]];
+            row[ldd[e]] = (T)(v.x - lamd * v.y);
+        }
+        ywin[r] = f[r];
+    }
+    __syncthreads();
+
+    int bad = 0;
+    for (int j = 0; j < nl; ++j) {
+        const int sj = j % C;
+        T dj = win[sj * C];
+        if (!(dj == dj) || dj == T(0) || !isfinite((double)dj)) {
+            bad = 1;
+            dj = T(1);
+        }
+        const T inv = T(1) / dj;
+        const T yj = ywin[sj];
+        for (int a = lane + 1; a <= w && j + a < nl; a += 64) {
+            const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
+            T* rowa = win + ra * C;
+            const T lsc = rowa[a] * inv;
+            int rb = sj + 1 - (sj + 1 >= C ? C : 0);           // slot of row j + b, b = 1
+            for (int b = 1; b <= a; ++b) {
+                rowa[a - b] -= lsc * win[rb * C + b];
+                rb = (rb + 1 == C) ? 0 : rb + 1;
+            }
+            ywin[ra] -= lsc * yj;
+            Lc[(long long)j * C + a] = lsc;
+        }
+        if (lane == 0) {
+            Lc[(long long)j * C] = dj;
+            z[j] = yj * inv;
+        }
+        __syncthreads();
+        T* row = win + sj * C;
+        for (int e = lane; e < C; e += 64) row[e] = T(0);
+        __syncthreads();
+        const int rn = j + C;
+        if (rn < nl) {
+            for (int e = lptr[off + rn] + lane; e < lptr[off + rn + 1]; e += 64) {
+                const double2 v = km[lpos[e]];
+                row[ldd[e]] = (T)(v.x - lamd * v.y);
+            }
+            if (lane == 0) ywin[sj] = f[rn];
+        }
+        __syncthreads();
+    }
+    // backward sweep with the unit upper factor L^T
+    for (int j = nl - 1; j >= 0; --j) {
+        const int sj = j % C;
+        T part = T(0);
+        for (int a = lane + 1; a <= w && j + a < nl; a += 64) {
+            const int ra = sj + a - (sj + a >= C ? C : 0);
+            part += Lc[(long long)j * C + a] * zwin[ra];
+        }
+        part = wave_sum(part);
+        if (lane == 0) {
+            const T zj = z[j] - part;
+            zwin[sj] = zj;
+            z[j] = zj;
+        }
+        __syncthreads();
+    }
+    if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
+}
+
+template <typename T>
+static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr, const int* bw,
+                         const int* lptr, const int* ldd, const int* lpos, const double2* km, const double* lam,
+                         const T* Floc, T* zloc, T* Lwork, const long long* Loff, int* status) {
+    const size_t shmem = (size_t)(maxC * maxC + 2 * maxC) * sizeof(T);
+    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(64), shmem, st, s, subptr, bw, lptr, ldd, lpos, km,
+                       lam, Floc, sumN, zloc, Lwork, Loff, status);
+}
+
+void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
+                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            const double* lam, const double* Floc, double* zloc, double* Lwork,
+                            const long long* Loff, int* status) {
+    launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
+                         status);
+}
+
+void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
+                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            const double* lam, const float* Floc, float* zloc, float* Lwork,
+                            const long long* Loff, int* status) {
+    launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
+                        status);
+}
+
+// ---------------------------------------------------------------------------
+// Z(d, i) = sum_b P(d,b) Zhat(b,i) + sum over the (subdomain, local row) copies
+// of dof d of zloc_i, in the order of the reverse map (deterministic).
+template <typename T>
+__global__ void scatter_kernel(int n, int s, long long sumN, const int* __restrict__ Pptr,
+                               const int* __restrict__ Pcol, const double* __restrict__ Pval,
+                               const double* __restrict__ Zhat, const int* __restrict__ rptr,
+                               const int* __restrict__ ridx, const T* __restrict__ zloc, double* __restrict__ Z,
+                               int ldz) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n * s) return;
+    const int d = (int)(t / s), i = (int)(t % s);
+    double acc = 0.0;
+    for (int q = Pptr[d]; q < Pptr[d + 1]; ++q) acc = fma(Pval[q], Zhat[Pcol[q] * s + i], acc);
+    for (int e = rptr[d]; e < rptr[d + 1]; ++e) acc += (double)zloc[(long long)i * sumN + ridx[e]];
+    Z[(long long)d * ldz + i] = acc;
+}
+
+void launch_scatter_f64(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
+                        const double* Zhat, const int* rptr, const int* ridx, const double* zloc, double* Z, int ldz) {
+    hipLaunchKernelGGL(scatter_kernel<double>, dim3(grid_for((long long)n * s, 256)), dim3(256), 0, st, n, s,
+                       (long long)sumN, Pptr, Pcol, Pval, Zhat, rptr, ridx, zloc, Z, ldz);
+}
+
+void launch_scatter_f32(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
+                        const double* Zhat, const int* rptr, const int* ridx, const float* zloc, double* Z, int ldz) {
+    hipLaunchKernelGGL(scatter_kernel<float>, dim3(grid_for((long long)n * s, 256)), dim3(256), 0, st, n, s,
+                       (long long)sumN, Pptr, Pcol, Pval, Zhat, rptr, ridx, zloc, Z, ldz);
+}
+
+}  // namespace bpjd

@@ -1,0 +1,157 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every test compares the library with the oracle on the same seeded inputs:
+SpMM, the coarse eigenvalues, the two-level preconditioner (FP64 and mixed),
+and whole solves (eigenvalues, M-orthonormality, eigenspace gap, residuals).
+"""
+import numpy as np
+import pytest
+
+from oracle import bpjd_oracle as o
+from paper_2203_06327_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_06327_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def _case(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("name", ["t8", "c1", "r96"])
+def test_spmm_parity(B, ctx, name):
+    _case(f"spmm {name}")
+    mesh, cfg = w.config_mesh(name)
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=B.PREC_FP64)
+    X = np.random.default_rng(1).standard_normal((mesh.n, prob.s * 3))
+    KX, MX = prob.spmm(X)
+    np.testing.assert_allclose(KX, mesh.K @ X, rtol=0, atol=1e-13 * np.abs(mesh.K @ X).max())
+    np.testing.assert_allclose(MX, mesh.M @ X, rtol=0, atol=1e-13 * np.abs(mesh.M @ X).max())
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96"])
+def test_coarse_eigenvalues(B, ctx, name):
+    _case(f"coarse eigenvalues {name}")
+    mesh, cfg = w.config_mesh(name)
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=B.PREC_FP64)
+    prob.setup()
+    lamH = prob.coarse_eigenvalues()
+    dd = o.build_dd(mesh, cfg["L"])
+    cs = o.coarse_setup(mesh.K, mesh.M, dd.P)
+    np.testing.assert_allclose(lamH, cs.lamH, rtol=1e-12)
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_preconditioner_parity(B, ctx, name, prec):
+    _case(f"preconditioner {name} {prec}")
+    mesh, cfg = w.config_mesh(name)
+    s = cfg["k"] + cfg["guard"]
+    precision = B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=precision)
+    prob.setup()
+    dd = o.build_dd(mesh, cfg["L"])
+    cs = o.coarse_setup(mesh.K, mesh.M, dd.P)
+    ls = o.local_setup(mesh.K, mesh.M, dd.subs)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((mesh.n, s))
+    lam = cs.lamH[:s] * (1.0 - 0.05 * rng.random(s))
+    Zg = prob.apply_preconditioner(X, lam)
+    F = (mesh.M @ X) * lam - mesh.K @ X
+    Zo = o.precondition(F, lam, cs, ls, s)
+    err = np.abs(Zg - Zo).max() / np.abs(Zo).max()
+    print(f"  max rel err {err:.3e}", flush=True)
+    assert err < (1e-12 if prec == "fp64" else 2e-5)
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("subspace", ["UU", "U"])
+def test_solve_c1(B, ctx, prec, subspace):
+    _case(f"solve c1 {prec} {subspace}")
+    mesh, cfg = w.config_mesh("c1")
+    k, s = cfg["k"], cfg["k"] + cfg["guard"]
+    X0 = w.seeded_block(mesh.n, s, cfg["seed_block"])
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
+                               precision=B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED,
+                               subspace=B.SUBSPACE_UU if subspace == "UU" else B.SUBSPACE_U, X_init=X0)
+    lam, X, st = prob.solve()
+    ref, Xref = o.reference_eigs(mesh.K, mesh.M, k)
+    rel = np.abs(lam - ref) / ref
+    print(f"  iterations {st['iterations']}  max rel err {rel.max():.3e}  max rho {st['max_residual']:.3e}",
+          flush=True)
+    assert st["converged"]
+    assert rel.max() < 1e-10
+    assert st["max_residual"] <= 1e-8
+    np.testing.assert_allclose(X.T @ (mesh.M @ X), np.eye(k), atol=1e-10)
+    assert o.subspace_gap_b(X, Xref, mesh.M) < 1e-6
+    # same iteration as the oracle (same subspace choice): same count up to rounding.
+    # W = U^k + span{t} converges slowly (about 110 steps here) and its tail amplifies
+    # rounding differences, and FP32 local solves perturb the trajectory itself:
+    # those runs get a 10 % allowance, the UU/FP64 run 3 %.
+    dd = o.build_dd(mesh, cfg["L"])
+    res = o.bpjd(mesh.K, mesh.M, dd, k, cfg["guard"], tol=1e-8, subspace=subspace, X_init=X0)
+    it_o, it_g = int(res.iterations), int(st["iterations"])
+    slack = 0.03 if (prec == "fp64" and subspace == "UU") else 0.10
+    assert abs(it_o - it_g) <= max(1, int(np.ceil(slack * it_o))), (it_o, it_g)
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["t64", "r96"])
+def test_solve_small_paper_rule(B, ctx, name):
+    _case(f"solve {name} paper stop rule")
+    mesh, cfg = w.config_mesh(name)
+    k = cfg["k"]
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-10 * np.pi ** 2,
+                               stop_rule=B.STOP_PAPER, precision=B.PREC_FP64)
+    lam, X, st = prob.solve()
+    ref, _ = o.reference_eigs(mesh.K, mesh.M, k)
+    assert st["converged"]
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    dd = o.build_dd(mesh, cfg["L"])
+    res = o.bpjd(mesh.K, mesh.M, dd, k, cfg["guard"], tol=1e-10 * np.pi ** 2, stop_rule="paper")
+    it_o, it_g = int(res.iterations), int(st["iterations"])
+    assert abs(it_o - it_g) <= 1, (it_o, it_g)
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_solve_c2_full_size(B, ctx, table1, prec):
+    """261,121 dofs, 16 x 16 subdomains, delta = 4h, k = 8: eigenvalues against the
+    third column of Table 1 (printed to 8 decimals, (0,pi)^2 units) and against
+    the oracle's reference eigenpairs."""
+    _case(f"solve c2 {prec}")
+    mesh, cfg = w.config_mesh("c2")
+    k = cfg["k"]
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
+                               precision=B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED)
+    lam, X, st = prob.solve()
+    print(f"  iterations {st['iterations']}  max rho {st['max_residual']:.3e}  setup {st['setup_ms']:.1f} ms  "
+          f"iterate {st['iterate_ms']:.1f} ms", flush=True)
+    assert st["converged"] and st["max_residual"] <= 1e-8
+    np.testing.assert_allclose(lam / np.pi ** 2, table1[:k, 2], rtol=0, atol=5.1e-9)
+    ref, Xref = o.reference_eigs(mesh.K, mesh.M, k)
+    np.testing.assert_allclose(lam, ref, rtol=1e-10)
+    np.testing.assert_allclose(X.T @ (mesh.M @ X), np.eye(k), atol=1e-10)
+    # residual recomputed on the host from the returned pairs
+    rho = o.residual_norms(mesh.K, mesh.M, X, lam)
+    assert rho.max() <= 1.5e-8
+    prob.close()
