@@ -20,6 +20,9 @@ namespace bpjd {
 
 static thread_local std::string g_last_error;
 
+// largest half-bandwidth handled by the blocked (MFMA) local solver
+static constexpr int kBlockedMaxBand = 48;
+
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 int fail(int code, const std::string& msg) {
@@ -238,6 +241,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     const int s = opts->k + opts->guard;
     if (opts->k < 1 || opts->guard < 0 || s > 21) return fail(BPJD_ERR_ARG, "need 1 <= k and k + guard <= 21");
     if (s >= nH) return fail(BPJD_ERR_DD, "block size s must be smaller than dim V^H");
+    if (nH > 1024) return fail(BPJD_ERR_DD, "coarse space larger than 1024 is not supported");
     if (opts->n_init != 0 && opts->n_init != s) return fail(BPJD_ERR_ARG, "n_init must be 0 or k + guard");
     if (opts->n_init && !opts->X_init) return fail(BPJD_ERR_ARG, "X_init is NULL");
     if (opts->stop_rule != BPJD_STOP_RESIDUAL && opts->stop_rule != BPJD_STOP_PAPER)
@@ -301,11 +305,15 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
         std::vector<int> fillp(rptr.begin(), rptr.end() - 1);
         for (long long q = 0; q < sumN; ++q) ridx[fillp[sidx[q]]++] = (int)q;
     }
+    // factor storage per (subdomain, shift): the blocked solver keeps 64 x 16 panels,
+    // the windowed solver one band column per row
+    const bool blocked = maxBW <= kBlockedMaxBand;
     std::vector<long long> Loff(nsub, 0);
     long long Ltot = 0;
     for (int l = 0; l < nsub; ++l) {
         Loff[l] = Ltot;
-        Ltot += (long long)s * (sptr[l + 1] - sptr[l]) * (bw[l] + 1);
+        const long long nl = sptr[l + 1] - sptr[l];
+        Ltot += blocked ? (long long)s * ((nl + 15) / 16) * 64 * 16 : (long long)s * nl * (bw[l] + 1);
     }
 
     // P^T and Galerkin patterns
@@ -418,6 +426,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(alloc_dev(p, &p->Y, nH2));
     chk(alloc_dev(p, &p->jwork, nH2));
     chk(alloc_dev(p, &p->lamH, nH));
+    chk(alloc_dev(p, &p->esmall, 3 * (size_t)nH));
     const size_t blk = (size_t)n * 3 * s;
     for (int b = 0; b < 2; ++b) {
         chk(alloc_dev(p, &p->W[b], blk));
@@ -522,8 +531,8 @@ static int check_status(bpjd_problem* p) {
 }
 
 // Galerkin coarse operators and the full coarse generalized eigenproblem
-// K_H y = lambda^H M_H y, Y^T M_H Y = I (Cholesky M_H = L L^T, Jacobi on
-// L^{-1} K_H L^{-T}, back-transformation).
+// K_H y = lambda^H M_H y, Y^T M_H Y = I (Cholesky M_H = L L^T, symmetric
+// eigensolver on L^{-1} K_H L^{-T}, Y = L^{-T} V).
 static void coarse_setup(bpjd_problem* p) {
     hipStream_t st = p->ctx->stream;
     const int nH = p->nH;
@@ -534,7 +543,7 @@ static void coarse_setup(bpjd_problem* p) {
     launch_trsm_lower(st, nH, nH, p->MH, p->Ccoarse, nH, false);                    // L^{-1} K_H
     launch_transpose(st, nH, p->Ccoarse, p->jwork);                                 // K_H L^{-T}
     launch_trsm_lower(st, nH, nH, p->MH, p->jwork, nH, false);                      // L^{-1} K_H L^{-T}
-    launch_jacobi_eig(st, nH, p->jwork, p->lamH, p->Ccoarse, p->Y);                 // eigvecs -> Ccoarse
+    launch_sym_eig(st, nH, p->jwork, p->lamH, p->Ccoarse, p->Y, p->esmall, p->status);   // eigvecs -> Ccoarse
     launch_copy_cols(st, nH, nH, p->Ccoarse, nH, p->Y, nH);
     launch_trsm_lower(st, nH, nH, p->MH, p->Y, nH, true);                           // Y = L^{-T} V
 }

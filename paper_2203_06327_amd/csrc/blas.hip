@@ -75,14 +75,27 @@ int num_partials(int n) {
     return p;
 }
 
-// Sum a [npart][len] array of partials over its first index (fixed order).
+// out[o] = sum_p partial[o][p] for a [len][npart] array of partials: one
+// workgroup per output, strided per-thread sums and a fixed tree (deterministic).
 __global__ void reduce_partials_kernel(int npart, int len, const double* __restrict__ partial,
                                        double* __restrict__ out) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= len) return;
+    __shared__ double red[256];
+    const int o = blockIdx.x;
+    const int t = threadIdx.x;
+    const double* src = partial + (long long)o * npart;
     double acc = 0.0;
-    for (int p = 0; p < npart; ++p) acc += partial[(long long)p * len + o];
-    out[o] = acc;
+    for (int p = t; p < npart; p += 256) acc += src[p];
+    red[t] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) red[t] += red[t + k];
+        __syncthreads();
+    }
+    if (t == 0) out[o] = red[0];
+}
+
+static void launch_reduce(hipStream_t st, int npart, int len, const double* partial, double* out) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(len), dim3(256), 0, st, npart, len, partial, out);
 }
 
 // Residual block and column sums of squares.  Thread t works on column t % s
@@ -118,8 +131,8 @@ __global__ void residual_kernel(int n, int s, const double* __restrict__ KX, int
             a += red[0][k * s + t];
             b += red[1][k * s + t];
         }
-        partial[(long long)blockIdx.x * 2 * s + t] = a;
-        partial[(long long)blockIdx.x * 2 * s + s + t] = b;
+        partial[(long long)t * gridDim.x + blockIdx.x] = a;
+        partial[(long long)(s + t) * gridDim.x + blockIdx.x] = b;
     }
 }
 
@@ -128,8 +141,7 @@ void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, co
     const int chunk = (n + npart - 1) / npart;
     hipLaunchKernelGGL(residual_kernel, dim3(npart), dim3(256), 0, st, n, s, KX, ldk, MX, ldm, lam, F, ldf, chunk,
                        partial);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(grid_for(2 * s, 128)), dim3(128), 0, st, npart, 2 * s, partial,
-                       colsq);
+    launch_reduce(st, npart, 2 * s, partial, colsq);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,7 +183,7 @@ __global__ void gram_partial_kernel(int n, int a, int b, const double* __restric
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int o = t + u * 256;
-        if (o < nout) partial[(long long)blockIdx.x * nout + o] = acc[u];
+        if (o < nout) partial[(long long)o * gridDim.x + blockIdx.x] = acc[u];
     }
 }
 
@@ -179,7 +191,7 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, 
                  double* partial, int npart, double* C) {
     const int chunk = (n + npart - 1) / npart;
     hipLaunchKernelGGL(gram_partial_kernel, dim3(npart), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(grid_for(a * b, 128)), dim3(128), 0, st, npart, a * b, partial, C);
+    launch_reduce(st, npart, a * b, partial, C);
 }
 
 // ---------------------------------------------------------------------------

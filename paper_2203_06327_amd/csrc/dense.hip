@@ -48,29 +48,34 @@ void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_b
     hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, n, A, status, status_bit);
 }
 
-// One thread per right-hand side column.
+// Triangular solve with many right-hand sides, right-looking: a workgroup owns
+// 32 columns of B; for each row r it finishes x_r and updates the rows still to
+// come (coalesced along the rows of B).
 __global__ void trsm_lower_kernel(int n, int nrhs, const double* __restrict__ L, double* __restrict__ B, int ldb,
                                   int transposeL) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nrhs) return;
-    if (!transposeL) {
-        for (int r = 0; r < n; ++r) {
-            double acc = B[(long long)r * ldb + c];
-            const double* lrow = L + (long long)r * n;
-            for (int q = 0; q < r; ++q) acc -= lrow[q] * B[(long long)q * ldb + c];
-            B[(long long)r * ldb + c] = acc / lrow[r];
+    const int c0 = blockIdx.x * 32;
+    const int t = threadIdx.x, bd = blockDim.x;
+    const int nc = min(32, nrhs - c0);
+    for (int step = 0; step < n; ++step) {
+        const int r = transposeL ? (n - 1 - step) : step;
+        const double inv = 1.0 / L[(long long)r * n + r];
+        if (t < nc) B[(long long)r * ldb + c0 + t] *= inv;
+        __syncthreads();
+        // remaining rows q: forward q > r uses L[q][r]; backward (L^T) q < r uses L[r][q]
+        const int qn = transposeL ? r : (n - 1 - r);
+        for (int e = t; e < qn * 32; e += bd) {
+            const int qi = e >> 5, c = e & 31;
+            if (c >= nc) continue;
+            const int q = transposeL ? qi : (r + 1 + qi);
+            const double l = transposeL ? L[(long long)r * n + q] : L[(long long)q * n + r];
+            B[(long long)q * ldb + c0 + c] -= l * B[(long long)r * ldb + c0 + c];
         }
-    } else {
-        for (int r = n - 1; r >= 0; --r) {
-            double acc = B[(long long)r * ldb + c];
-            for (int q = r + 1; q < n; ++q) acc -= L[(long long)q * n + r] * B[(long long)q * ldb + c];
-            B[(long long)r * ldb + c] = acc / L[(long long)r * n + r];
-        }
+        __syncthreads();
     }
 }
 
 void launch_trsm_lower(hipStream_t st, int n, int nrhs, const double* L, double* B, int ldb, bool transposeL) {
-    hipLaunchKernelGGL(trsm_lower_kernel, dim3(grid_for(nrhs, 64)), dim3(64), 0, st, n, nrhs, L, B, ldb,
+    hipLaunchKernelGGL(trsm_lower_kernel, dim3(grid_for(nrhs, 32)), dim3(256), 0, st, n, nrhs, L, B, ldb,
                        transposeL ? 1 : 0);
 }
 
@@ -209,6 +214,243 @@ __global__ void jacobi_global_kernel(int n, double* __restrict__ A, double* __re
 
 void launch_jacobi_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work) {
     hipLaunchKernelGGL(jacobi_global_kernel, dim3(1), dim3(1024), 0, st, n, A, w, V, work);
+}
+
+// ---------------------------------------------------------------------------
+// Dense symmetric eigensolver for the coarse problem (n <= 1024), in three
+// single-workgroup kernels: Householder reduction to tridiagonal form, the
+// implicit QL iteration with Wilkinson shifts on the tridiagonal matrix, and
+// back-transformation by the stored reflectors.
+//
+// tridiag: A (n x n, full symmetric storage, row-major) is reduced in place;
+// reflector k (acting on rows k+1..n-1) is v_k with v_k[0] = 1, stored in
+// Vh[k][k+1..n) together with tau[k]; diag/off receive the tridiagonal matrix.
+__global__ void tridiag_kernel(int n, double* __restrict__ A, double* __restrict__ Vh, double* __restrict__ tau,
+                               double* __restrict__ diag, double* __restrict__ off) {
+    __shared__ double v[1024];
+    __shared__ double w[1024];
+    __shared__ double red[1024];
+    __shared__ double sc[4];
+    const int t = threadIdx.x, bd = blockDim.x;
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        const double* colk = A + (long long)(k + 1) * n + k;     // x_i = A[k+1+i][k]
+        double acc = 0.0;
+        for (int i = 1 + t; i < m; i += bd) {
+            const double x = colk[(long long)i * n];
+            acc += x * x;
+        }
+        red[t] = acc;
+        __syncthreads();
+        for (int o = bd / 2; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        if (t == 0) {
+            const double alpha = colk[0];
+            const double xn2 = red[0];
+            if (xn2 == 0.0) {
+                sc[0] = 0.0;                 // tau
+                sc[1] = 0.0;                 // scale
+                off[k] = alpha;
+            } else {
+                const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                sc[0] = (beta - alpha) / beta;
+                sc[1] = 1.0 / (alpha - beta);
+                off[k] = beta;
+            }
+            tau[k] = sc[0];
+        }
+        __syncthreads();
+        const double tk = sc[0], scale = sc[1];
+        for (int i = t; i < m; i += bd) {
+            const double vi = (i == 0) ? 1.0 : colk[(long long)i * n] * scale;
+            v[i] = vi;
+            Vh[(long long)k * n + k + 1 + i] = vi;
+        }
+        __syncthreads();
+        if (tk != 0.0) {
+            // p = tau A22 v; A22 is symmetric, so thread j reads column j (coalesced across threads)
+            for (int j = t; j < m; j += bd) {
+                const double* colj = A + (long long)(k + 1) * n + (k + 1) + j;
+                double pj = 0.0;
+                for (int i = 0; i < m; ++i) pj = fma(colj[(long long)i * n], v[i], pj);
+                w[j] = tk * pj;
+            }
+            __syncthreads();
+            double pv = 0.0;
+            for (int i = t; i < m; i += bd) pv += w[i] * v[i];
+            red[t] = pv;
+            __syncthreads();
+            for (int o = bd / 2; o > 0; o >>= 1) {
+                if (t < o) red[t] += red[t + o];
+                __syncthreads();
+            }
+            const double half_tpv = 0.5 * tk * red[0];
+            __syncthreads();
+            for (int i = t; i < m; i += bd) w[i] -= half_tpv * v[i];
+            __syncthreads();
+            // A22 -= v w^T + w v^T, row by row with threads along the row
+            for (int i = 0; i < m; ++i) {
+                double* row = A + (long long)(k + 1 + i) * n + (k + 1);
+                const double vi = v[i], wi = w[i];
+                for (int j = t; j < m; j += bd) row[j] -= vi * w[j] + wi * v[j];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < n; i += bd) diag[i] = A[(long long)i * n + i];
+    if (t == 0) {
+        if (n >= 2) off[n - 2] = A[(long long)(n - 1) * n + (n - 2)];
+        off[n - 1] = 0.0;
+    }
+}
+
+// Implicit QL with Wilkinson shifts on the symmetric tridiagonal matrix
+// (diag d, off-diagonal e with e[i] coupling i and i+1).  Thread 0 runs the
+// scalar recurrence of one sweep and records its Givens rotations in LDS; all
+// threads then apply them to their rows of Z (Z starts as the identity).  On
+// return d holds the eigenvalues (unordered) and the columns of Z the
+// eigenvectors of the tridiagonal matrix.
+__global__ void tridiag_ql_kernel(int n, double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ Z,
+                                  int* __restrict__ status) {
+    __shared__ double d[1024];
+    __shared__ double e[1024];
+    __shared__ double rc[1024];
+    __shared__ double rs[1024];
+    __shared__ int s_first, s_last, s_stop;
+    const int t = threadIdx.x, bd = blockDim.x;
+    for (int i = t; i < n; i += bd) {
+        d[i] = dg[i];
+        e[i] = eg[i];
+    }
+    for (long long q = t; q < (long long)n * n; q += bd) Z[q] = ((q / n) == (q % n)) ? 1.0 : 0.0;
+    __syncthreads();
+    int l = 0, iter = 0;    // thread 0's state
+    while (true) {
+        if (t == 0) {
+            s_stop = 1;
+            while (l < n) {
+                int m = l;
+                while (m < n - 1 && fabs(e[m]) > 2.3e-16 * (fabs(d[m]) + fabs(d[m + 1]))) ++m;
+                if (m == l) {
+                    ++l;
+                    iter = 0;
+                    continue;
+                }
+                if (++iter > 100) {
+                    atomicOr(status, STATUS_COARSE_NOT_SPD);
+                    l = n;
+                    break;
+                }
+                // shift from the leading 2 x 2 block of the unreduced part
+                const double theta = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                const double rad = sqrt(theta * theta + 1.0);
+                double g = d[m] - d[l] + e[l] / (theta + copysign(rad, theta));
+                double sn = 1.0, cs = 1.0, shift_acc = 0.0;
+                int i = m - 1;
+                bool split = false;
+                for (; i >= l; --i) {
+                    const double f = sn * e[i];
+                    const double b = cs * e[i];
+                    const double r = sqrt(f * f + g * g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {               // the block splits: undo the pending shift and restart
+                        d[i + 1] -= shift_acc;
+                        e[m] = 0.0;
+                        split = true;
+                        break;
+                    }
+                    sn = f / r;
+                    cs = g / r;
+                    const double gg = d[i + 1] - shift_acc;
+                    const double rr = (d[i] - gg) * sn + 2.0 * cs * b;
+                    shift_acc = sn * rr;
+                    d[i + 1] = gg + shift_acc;
+                    g = cs * rr - b;
+                    rc[i] = cs;
+                    rs[i] = sn;
+                }
+                if (!split) {
+                    d[l] -= shift_acc;
+                    e[l] = g;
+                    e[m] = 0.0;
+                }
+                s_first = m - 1;                  // rotations i = m-1 down to s_last were recorded
+                s_last = split ? i + 1 : l;
+                s_stop = 0;
+                break;
+            }
+        }
+        __syncthreads();
+        if (s_stop) break;
+        const int i0 = s_first, i1 = s_last;
+        for (int row = t; row < n; row += bd) {
+            double* zr = Z + (long long)row * n;
+            double carry = zr[i0 + 1];
+            for (int i = i0; i >= i1; --i) {
+                const double zi = zr[i];
+                zr[i + 1] = rs[i] * zi + rc[i] * carry;
+                carry = rc[i] * zi - rs[i] * carry;
+            }
+            zr[i1] = carry;
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < n; i += bd) dg[i] = d[i];
+}
+
+// Z <- H_0 H_1 ... H_{n-3} Z (eigenvectors of the reduced matrix back to the
+// original basis).  Per reflector: the row vector v^T Z (threads along a row of Z,
+// rows in sequence: coalesced), then the rank-one update.
+__global__ void tridiag_back_kernel(int n, const double* __restrict__ Vh, const double* __restrict__ tau,
+                                    double* __restrict__ Z) {
+    __shared__ double dot[1024];
+    const int t = threadIdx.x, bd = blockDim.x;
+    for (int k = n - 3; k >= 0; --k) {
+        const double tk = tau[k];
+        if (tk == 0.0) continue;
+        const double* vk = Vh + (long long)k * n;
+        for (int j = t; j < n; j += bd) {
+            double acc = 0.0;
+            for (int i = k + 1; i < n; ++i) acc = fma(vk[i], Z[(long long)i * n + j], acc);
+            dot[j] = tk * acc;
+        }
+        __syncthreads();
+        for (int i = k + 1; i < n; ++i) {
+            const double vi = vk[i];
+            double* zr = Z + (long long)i * n;
+            for (int j = t; j < n; j += bd) zr[j] -= vi * dot[j];
+        }
+        __syncthreads();
+    }
+}
+
+// Ascending order of d with the matching columns of Z.
+__global__ void sort_pairs_kernel(int n, const double* __restrict__ d, const double* __restrict__ Z,
+                                  double* __restrict__ w, double* __restrict__ Zout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double di = d[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+        const double dj = d[j];
+        rank += (dj < di) || (dj == di && j < i);
+    }
+    w[rank] = di;
+    for (int r = 0; r < n; ++r) Zout[(long long)r * n + rank] = Z[(long long)r * n + i];
+}
+
+void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
+                    int* status) {
+    // work: n*n (reflectors, then eigenvectors before sorting); small: 3n (tau, diag, off)
+    double* tau = small;
+    double* diag = small + n;
+    double* off = small + 2 * n;
+    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
+    hipLaunchKernelGGL(tridiag_ql_kernel, dim3(1), dim3(1024), 0, st, n, diag, off, A, status);
+    hipLaunchKernelGGL(tridiag_back_kernel, dim3(1), dim3(1024), 0, st, n, work, tau, A);
+    hipLaunchKernelGGL(sort_pairs_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, n, diag, A, w, V);
 }
 
 // ---------------------------------------------------------------------------

@@ -291,6 +291,212 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
     if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
 }
 
+// ---------------------------------------------------------------------------
+// Local solves, blocked: the same LDL^T of the banded K_l - lambda_i M_l, one
+// wavefront per (subdomain, shift), for half-bandwidths w <= 48.  The active
+// window is 64 rows = 4 tile-rows of 16; its lower tiles live in MFMA
+// accumulators.  Per panel of 16 columns: the panel is moved to one row per
+// lane and factored column by column (pivots by lane broadcast), the forward
+// substitution advances, the panel is stored for the backward sweep, and the
+// trailing window takes the update -L21 D L21^T with 16x16x4 MFMAs.  The
+// window then slides by 16 rows and a new tile-row enters from the sparse
+// lower pattern.  Rows past the end of the subdomain are identity padding.
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaTile;
+template <>
+struct MfmaTile<float> {
+    typedef floatx4_t acc;
+    __device__ static inline acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator element i of a lane sits at row 4*(lane/16) + i, column lane%16
+    __device__ static inline int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+    __device__ static inline float bcast(float v, int src) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+    }
+};
+template <>
+struct MfmaTile<double> {
+    typedef doublex4_t acc;
+    __device__ static inline acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // FP64: element i of a lane sits at row lane/16 + 4*i, column lane%16
+    __device__ static inline int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+    __device__ static inline double bcast(double v, int src) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+};
+
+constexpr int MFMA_WIN = 64;       // window rows
+constexpr int MFMA_MAX_BW = 48;    // supported half-bandwidth
+
+template <typename T>
+__global__ __launch_bounds__(64) void local_band_mfma_kernel(
+    int s, const int* __restrict__ subptr, const int* __restrict__ lptr, const int* __restrict__ ldd,
+    const int* __restrict__ lpos, const double2* __restrict__ km, const double* __restrict__ lam,
+    const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc, T* __restrict__ Lwork,
+    const long long* __restrict__ Loff, int* __restrict__ status) {
+    using MT = MfmaTile<T>;
+    using acc_t = typename MT::acc;
+    constexpr int NT = 4, R = MFMA_WIN;
+    __shared__ T pan[R][17];
+    __shared__ T nrow[16][R + 1];
+    __shared__ T vec[R];
+    const int sys = blockIdx.x;
+    const int l = sys / s;
+    const int i = sys - l * s;
+    const int off = subptr[l];
+    const int nl = subptr[l + 1] - off;
+    const int npan = (nl + 15) >> 4;
+    const double lamd = lam[i];
+    const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+    T* Lp = Lwork + Loff[l] + (long long)i * npan * (R * 16);
+    const T* f = Floc + (long long)i * ldF + off;
+    T* z = zloc + (long long)i * ldF + off;
+
+    acc_t A[NT][NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = 0; J < NT; ++J) A[I][J] = acc_t{T(0), T(0), T(0), T(0)};
+
+    // tile-row I of the window <- rows rb..rb+15 of K_l - lambda_i M_l, window column base cb
+    auto load_row = [&](const int I, const int rb, const int cb) {
+        for (int e = lane; e < 16 * (R + 1); e += 64) (&nrow[0][0])[e] = T(0);
+        __syncthreads();
+        const int q = lane >> 2, r = rb + q;
+        if (r < nl) {
+            for (int e = lptr[off + r] + (lane & 3); e < lptr[off + r + 1]; e += 4) {
+                const double2 v = km[lpos[e]];
+                nrow[q][r - ldd[e] - cb] = (T)(v.x - lamd * v.y);
+            }
+        } else if ((lane & 3) == 0) {
+            nrow[q][r - cb] = T(1);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int J = 0; J < NT; ++J) {
+            if (J <= I) {
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) A[I][J][ii] = nrow[MT::row(lane, ii)][16 * J + lr];
+            }
+        }
+        __syncthreads();
+    };
+
+#pragma unroll
+    for (int I = 0; I < NT; ++I) load_row(I, 16 * I, 0);
+    T y = (lane < nl) ? f[lane] : T(0);
+    int bad = 0;
+
+    for (int P = 0; P < npan; ++P) {
+        const int base = 16 * P;
+        // panel (tile column 0) -> one row per lane
+#pragma unroll
+        for (int I = 0; I < NT; ++I)
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) pan[16 * I + MT::row(lane, ii)][lr] = A[I][0][ii];
+        __syncthreads();
+        T a[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = pan[lane][c];
+        T dl = T(1);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const T u = a[c];
+            T dc = MT::bcast(u, c);
+            if (!(dc == dc) || dc == T(0) || !isfinite((double)dc)) {
+                bad = 1;
+                dc = T(1);
+            }
+            const T inv = T(1) / dc;
+            const T lt = u * inv;
+#pragma unroll
+            for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * MT::bcast(u, c2);
+            const T yc = MT::bcast(y, c);
+            if (lane > c) y -= lt * yc;
+            a[c] = (lane == c) ? dc : lt;
+            if (lane == c) dl = dc;
+        }
+        // store the factored panel (row per lane) and D^{-1} L^{-1} f of its 16 rows
+        T* Lpan = Lp + (long long)P * (R * 16) + lane * 16;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Lpan[c] = a[c];
+        if (lane < 16 && base + lane < nl) z[base + lane] = y / dl;
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) pan[lane][c] = a[c];
+        __syncthreads();
+        // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T
+        T aop[NT][4], bop[NT][4];
+#pragma unroll
+        for (int I = 1; I < NT; ++I)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int col = 4 * k + lg;
+                const T lv = pan[16 * I + lr][col];
+                bop[I][k] = lv;
+                aop[I][k] = -lv * pan[col][col];
+            }
+#pragma unroll
+        for (int I = 1; I < NT; ++I)
+#pragma unroll
+            for (int J = 1; J <= I; ++J)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[I][J] = MT::mma(aop[I][k], bop[J][k], A[I][J]);
+        __syncthreads();
+        // slide the window by 16 rows
+#pragma unroll
+        for (int I = 1; I < NT; ++I)
+#pragma unroll
+            for (int J = 1; J <= I; ++J) A[I - 1][J - 1] = A[I][J];
+        if (P + 1 < npan) load_row(NT - 1, base + 16 * NT, base + 16);
+        vec[lane] = y;
+        __syncthreads();
+        const int rnew = base + 16 + lane;
+        y = (lane < R - 16) ? vec[lane + 16] : ((rnew < nl) ? f[rnew] : T(0));
+        __syncthreads();
+    }
+
+    // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows
+    T zw = T(0);
+    for (int P = npan - 1; P >= 0; --P) {
+        const int base = 16 * P;
+        vec[lane] = zw;
+        __syncthreads();
+        zw = (lane >= 16) ? vec[lane - 16] : T(0);
+        __syncthreads();
+        const T* Lpan = Lp + (long long)P * (R * 16) + lane * 16;
+        T a[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = Lpan[c];
+        const T zc0 = (lane < 16 && base + lane < nl) ? z[base + lane] : T(0);
+#pragma unroll
+        for (int c = 15; c >= 0; --c) {
+            T part = (lane > c) ? a[c] * zw : T(0);
+            part = wave_sum(part);
+            if (lane == c) zw = zc0 - part;
+        }
+        if (lane < 16 && base + lane < nl) z[base + lane] = zw;
+    }
+    if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
+}
+
+template <typename T>
+static void launch_local_mfma(hipStream_t st, int nsub, int s, long long sumN, const int* subptr, const int* lptr,
+                              const int* ldd, const int* lpos, const double2* km, const double* lam, const T* Floc,
+                              T* zloc, T* Lwork, const long long* Loff, int* status) {
+    hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, subptr, lptr, ldd, lpos, km,
+                       lam, Floc, sumN, zloc, Lwork, Loff, status);
+}
+
 template <typename T>
 static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr, const int* bw,
                          const int* lptr, const int* ldd, const int* lpos, const double2* km, const double* lam,
@@ -304,6 +510,11 @@ void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status) {
+    if (maxC - 1 <= MFMA_MAX_BW) {
+        launch_local_mfma<double>(st, nsub, s, sumN, subptr, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
+                                  status);
+        return;
+    }
     launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
                          status);
 }
@@ -312,6 +523,11 @@ void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status) {
+    if (maxC - 1 <= MFMA_MAX_BW) {
+        launch_local_mfma<float>(st, nsub, s, sumN, subptr, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
+                                 status);
+        return;
+    }
     launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
                         status);
 }

@@ -59,7 +59,7 @@ def test_coarse_eigenvalues(B, ctx, name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96"])
+@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96", "w56"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_preconditioner_parity(B, ctx, name, prec):
     _case(f"preconditioner {name} {prec}")
@@ -154,4 +154,21 @@ def test_solve_c2_full_size(B, ctx, table1, prec):
     # residual recomputed on the host from the returned pairs
     rho = o.residual_norms(mesh.K, mesh.M, X, lam)
     assert rho.max() <= 1.5e-8
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_coarse_eigenvalues_large(B, ctx, name):
+    """Coarse generalized eigenproblem at n_H = 225 and 961 (the coarse grids of the
+    261k- and 1.06M-dof workloads) against the oracle's dense solve."""
+    _case(f"coarse eigenvalues {name}")
+    mesh, cfg = w.config_mesh(name)
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=B.PREC_MIXED)
+    prob.setup()
+    lamH = prob.coarse_eigenvalues()
+    P = o.coarse_prolongation(mesh.coords, mesh.cx, mesh.cy)
+    cs = o.coarse_setup(mesh.K, mesh.M, P)
+    err = np.max(np.abs(lamH - cs.lamH) / cs.lamH)
+    print(f"  n_H={lamH.size} max rel err {err:.3e}", flush=True)
+    assert err < 1e-11
     prob.close()
