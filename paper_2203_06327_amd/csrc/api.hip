@@ -427,6 +427,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(alloc_dev(p, &p->jwork, nH2));
     chk(alloc_dev(p, &p->lamH, nH));
     chk(alloc_dev(p, &p->esmall, 3 * (size_t)nH));
+    chk(alloc_dev(p, &p->escratch, std::max(5 * nH2, (size_t)32 * nH)));
     const size_t blk = (size_t)n * 3 * s;
     for (int b = 0; b < 2; ++b) {
         chk(alloc_dev(p, &p->W[b], blk));
@@ -543,8 +544,7 @@ static void coarse_setup(bpjd_problem* p) {
     launch_trsm_lower(st, nH, nH, p->MH, p->Ccoarse, nH, false);                    // L^{-1} K_H
     launch_transpose(st, nH, p->Ccoarse, p->jwork);                                 // K_H L^{-T}
     launch_trsm_lower(st, nH, nH, p->MH, p->jwork, nH, false);                      // L^{-1} K_H L^{-T}
-    launch_sym_eig(st, nH, p->jwork, p->lamH, p->Ccoarse, p->Y, p->esmall, p->status);   // eigvecs -> Ccoarse
-    launch_copy_cols(st, nH, nH, p->Ccoarse, nH, p->Y, nH);
+    launch_sym_eig(st, nH, p->jwork, p->lamH, p->Y, p->Ccoarse, p->esmall, p->escratch, p->status);  // V -> Y
     launch_trsm_lower(st, nH, nH, p->MH, p->Y, nH, true);                           // Y = L^{-T} V
 }
 

@@ -106,11 +106,12 @@ void launch_trsm_lower(hipStream_t st, int n, int nrhs, const double* L, double*
 // Symmetric eigensolver (cyclic Jacobi, one workgroup): A n x n (destroyed), eigenvalues
 // ascending in w, eigenvectors as columns of V (n x n row-major). work: 2 n^2 doubles.
 void launch_jacobi_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work);
-// Symmetric eigensolver for n <= 1024 (Householder tridiagonalisation, implicit QL,
-// back-transformation): A (n x n) destroyed, eigenvalues ascending in w, eigenvectors as
-// columns of V.  work: n*n doubles, small: 3n doubles.
+// Symmetric eigensolver for n <= 1024 (Householder tridiagonalisation, bisection,
+// inverse iteration with re-orthogonalised clusters, back-transformation): A (n x n)
+// destroyed, eigenvalues ascending in w, eigenvectors as columns of V.
+// work: n*n doubles, small: 3n doubles, scratch: 5 n*n doubles.
 void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
-                    int* status);
+                    double* scratch, int* status);
 // Transpose-copy helpers for the coarse eigenproblem.
 void launch_transpose(hipStream_t st, int n, const double* A, double* AT);
 // CholQR coefficients: G (b x b) -> C = D^{-1/2} L^{-T} (G scaled by D = diag(G) = L L^T);
@@ -158,6 +159,7 @@ struct bpjd_problem {
     // device numeric workspace
     double *KH = nullptr, *MH = nullptr, *Ccoarse = nullptr, *Y = nullptr, *lamH = nullptr, *jwork = nullptr;
     double* esmall = nullptr;
+    double* escratch = nullptr;
     double *W[2] = {nullptr, nullptr}, *KW[2] = {nullptr, nullptr}, *MW[2] = {nullptr, nullptr};
     double *F = nullptr, *Z = nullptr, *Zhat = nullptr, *G = nullptr, *Cw = nullptr;
     void *Floc = nullptr, *zloc = nullptr, *Lwork = nullptr;

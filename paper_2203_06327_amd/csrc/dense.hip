@@ -306,151 +306,329 @@ __global__ void tridiag_kernel(int n, double* __restrict__ A, double* __restrict
     }
 }
 
-// Implicit QL with Wilkinson shifts on the symmetric tridiagonal matrix
-// (diag d, off-diagonal e with e[i] coupling i and i+1).  Thread 0 runs the
-// scalar recurrence of one sweep and records its Givens rotations in LDS; all
-// threads then apply them to their rows of Z (Z starts as the identity).  On
-// return d holds the eigenvalues (unordered) and the columns of Z the
-// eigenvectors of the tridiagonal matrix.
-__global__ void tridiag_ql_kernel(int n, double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ Z,
-                                  int* __restrict__ status) {
+// Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e,
+// e[i] coupling i and i+1) by bisection on Sturm counts: thread j finds the
+// j-th smallest eigenvalue.  count(x) = number of negative pivots of the
+// LDL^T factorisation of T - x I.
+__device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+    for (int i = 1; i < n; ++i) {
+        q = d[i] - x - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0);
+    }
+    return cnt;
+}
+
+__global__ void tridiag_bisect_kernel(int n, const double* __restrict__ dg, const double* __restrict__ eg,
+                                      double* __restrict__ w) {
     __shared__ double d[1024];
-    __shared__ double e[1024];
-    __shared__ double rc[1024];
-    __shared__ double rs[1024];
-    __shared__ int s_first, s_last, s_stop;
+    __shared__ double e2[1024];
+    __shared__ double red[2][1024];
     const int t = threadIdx.x, bd = blockDim.x;
+    double lo = 1e300, hi = -1e300, emax = 0.0;
     for (int i = t; i < n; i += bd) {
         d[i] = dg[i];
-        e[i] = eg[i];
+        const double ei = (i + 1 < n) ? eg[i] : 0.0;
+        e2[i] = ei * ei;
+        const double el = (i > 0) ? fabs(eg[i - 1]) : 0.0;
+        const double er = fabs(ei);
+        lo = fmin(lo, dg[i] - el - er);
+        hi = fmax(hi, dg[i] + el + er);
+        emax = fmax(emax, er);
     }
-    for (long long q = t; q < (long long)n * n; q += bd) Z[q] = ((q / n) == (q % n)) ? 1.0 : 0.0;
+    red[0][t] = lo;
+    red[1][t] = hi;
     __syncthreads();
-    int l = 0, iter = 0;    // thread 0's state
-    while (true) {
-        if (t == 0) {
-            s_stop = 1;
-            while (l < n) {
-                int m = l;
-                while (m < n - 1 && fabs(e[m]) > 2.3e-16 * (fabs(d[m]) + fabs(d[m + 1]))) ++m;
-                if (m == l) {
-                    ++l;
-                    iter = 0;
-                    continue;
-                }
-                if (++iter > 100) {
-                    atomicOr(status, STATUS_COARSE_NOT_SPD);
-                    l = n;
-                    break;
-                }
-                // shift from the leading 2 x 2 block of the unreduced part
-                const double theta = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                const double rad = sqrt(theta * theta + 1.0);
-                double g = d[m] - d[l] + e[l] / (theta + copysign(rad, theta));
-                double sn = 1.0, cs = 1.0, shift_acc = 0.0;
-                int i = m - 1;
-                bool split = false;
-                for (; i >= l; --i) {
-                    const double f = sn * e[i];
-                    const double b = cs * e[i];
-                    const double r = sqrt(f * f + g * g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {               // the block splits: undo the pending shift and restart
-                        d[i + 1] -= shift_acc;
-                        e[m] = 0.0;
-                        split = true;
-                        break;
-                    }
-                    sn = f / r;
-                    cs = g / r;
-                    const double gg = d[i + 1] - shift_acc;
-                    const double rr = (d[i] - gg) * sn + 2.0 * cs * b;
-                    shift_acc = sn * rr;
-                    d[i + 1] = gg + shift_acc;
-                    g = cs * rr - b;
-                    rc[i] = cs;
-                    rs[i] = sn;
-                }
-                if (!split) {
-                    d[l] -= shift_acc;
-                    e[l] = g;
-                    e[m] = 0.0;
-                }
-                s_first = m - 1;                  // rotations i = m-1 down to s_last were recorded
-                s_last = split ? i + 1 : l;
-                s_stop = 0;
-                break;
-            }
-        }
-        __syncthreads();
-        if (s_stop) break;
-        const int i0 = s_first, i1 = s_last;
-        for (int row = t; row < n; row += bd) {
-            double* zr = Z + (long long)row * n;
-            double carry = zr[i0 + 1];
-            for (int i = i0; i >= i1; --i) {
-                const double zi = zr[i];
-                zr[i + 1] = rs[i] * zi + rc[i] * carry;
-                carry = rc[i] * zi - rs[i] * carry;
-            }
-            zr[i1] = carry;
+    for (int o = bd / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            red[0][t] = fmin(red[0][t], red[0][t + o]);
+            red[1][t] = fmax(red[1][t], red[1][t + o]);
         }
         __syncthreads();
     }
-    for (int i = t; i < n; i += bd) dg[i] = d[i];
+    const double glo = red[0][0], ghi = red[1][0];
+    const double tnorm = fmax(fabs(glo), fabs(ghi));
+    const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
+    for (int j = t; j < n; j += bd) {
+        double a = glo - 1e-14 * tnorm - 1e-300, b = ghi + 1e-14 * tnorm + 1e-300;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (a + b);
+            if (!(mid > a && mid < b) || (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))) break;
+            if (sturm_count(n, d, e2, mid, pivmin) > j) b = mid;
+            else a = mid;
+        }
+        w[j] = 0.5 * (a + b);
+    }
+}
+
+// Inverse iteration for every eigenvalue (one thread each): three solves of
+// (T - lambda_j I) x = b with a partial-pivoting LU of the tridiagonal matrix
+// (U has two superdiagonals), starting from a fixed vector.  Scratch and
+// result vectors are interleaved ([i][j]) so accesses coalesce across threads.
+// Output: X[i][j] = component i of eigenvector j (unit 2-norm).
+__global__ void tridiag_invit_kernel(int n, const double* __restrict__ dg, const double* __restrict__ eg,
+                                     const double* __restrict__ w, double* __restrict__ X,
+                                     double* __restrict__ scratch) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double* u0 = scratch;                        // U diagonal            [n][n]
+    double* u1 = scratch + (long long)n * n;     // U first superdiagonal
+    double* u2 = scratch + 2LL * n * n;          // U second superdiagonal
+    double* mu = scratch + 3LL * n * n;          // multipliers, sign bit of pivot flag folded into pv
+    double* pv = scratch + 4LL * n * n;          // 1.0 where rows were swapped
+#define IDX(i) ((long long)(i) * n + j)
+    const double lam = w[j];
+    double tn = 0.0;
+    for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(dg[i]) + (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < n ? fabs(eg[i]) : 0.0));
+    const double tiny = 2.3e-16 * fmax(tn, 1e-300);
+    // factorisation P (T - lam I) = L U
+    double a0 = dg[0] - lam, a1 = (n > 1) ? eg[0] : 0.0, a2 = 0.0;   // current row (cols i, i+1, i+2)
+    for (int i = 0; i + 1 < n; ++i) {
+        const double sub = eg[i];                                     // next row: (sub, d[i+1]-lam, e[i+1])
+        const double nd = dg[i + 1] - lam;
+        const double ne = (i + 2 < n) ? eg[i + 1] : 0.0;
+        if (fabs(sub) > fabs(a0)) {
+            const double m = a0 / sub;
+            u0[IDX(i)] = sub;
+            u1[IDX(i)] = nd;
+            u2[IDX(i)] = ne;
+            mu[IDX(i)] = m;
+            pv[IDX(i)] = 1.0;
+            const double na0 = a1 - m * nd, na1 = a2 - m * ne;
+            a0 = na0;
+            a1 = na1;
+            a2 = 0.0;
+        } else {
+            const double piv = (a0 == 0.0) ? tiny : a0;
+            const double m = sub / piv;
+            u0[IDX(i)] = piv;
+            u1[IDX(i)] = a1;
+            u2[IDX(i)] = a2;
+            mu[IDX(i)] = m;
+            pv[IDX(i)] = 0.0;
+            a0 = nd - m * a1;
+            a1 = ne - m * a2;
+            a2 = 0.0;
+        }
+    }
+    u0[IDX(n - 1)] = (fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0;
+    for (int i = 0; i + 1 < n; ++i)
+        if (fabs(u0[IDX(i)]) < tiny) u0[IDX(i)] = copysign(tiny, u0[IDX(i)] == 0.0 ? 1.0 : u0[IDX(i)]);
+    // right-hand side: a fixed vector with varying entries
+    for (int i = 0; i < n; ++i) X[IDX(i)] = 1.0 + 0.5 * sin(0.7 * i + 0.3 * j);
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        // apply the row operations: forward
+        for (int i = 0; i + 1 < n; ++i) {
+            double xi = X[IDX(i)], xn = X[IDX(i + 1)];
+            if (pv[IDX(i)] != 0.0) {
+                const double tmp = xi;
+                xi = xn;
+                xn = tmp;
+            }
+            X[IDX(i)] = xi;
+            X[IDX(i + 1)] = xn - mu[IDX(i)] * xi;
+        }
+        // back substitution with U
+        double x1 = 0.0, x2 = 0.0;
+        double nrm = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+            const double xi = (X[IDX(i)] - u1[IDX(i)] * x1 - u2[IDX(i)] * x2) / u0[IDX(i)];
+            X[IDX(i)] = xi;
+            x2 = x1;
+            x1 = xi;
+            nrm += xi * xi;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < n; ++i) X[IDX(i)] *= inv;
+    }
+#undef IDX
+}
+
+// Eigenvectors of clustered eigenvalues (consecutive gaps below 1e-3 |T|) from
+// inverse iteration span the cluster's invariant subspace but are not
+// individually accurate.  Per cluster: two Gram-Schmidt passes, then a
+// Rayleigh-Ritz step on the cluster (Jacobi on X_c^T T X_c by one thread) that
+// rotates the basis into eigenvectors and refines the eigenvalues.  One
+// workgroup, threads along the vectors; ytmp: n * 32 doubles.
+__global__ void tridiag_cluster_kernel(int n, const double* __restrict__ dg, const double* __restrict__ eg,
+                                       double* __restrict__ w, double* __restrict__ X, double* __restrict__ ytmp) {
+    __shared__ double red[1024];
+    __shared__ double Tc[32 * 32];
+    __shared__ double Qc[32 * 32];
+    const int t = threadIdx.x, bd = blockDim.x;
+    const double tn = fmax(fabs(w[0]), fabs(w[n - 1]));
+    const double gap_tol = 1e-3 * tn;
+    auto block_sum = [&](double v) -> double {
+        red[t] = v;
+        __syncthreads();
+        for (int o = bd / 2; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        return r;
+    };
+    int start = 0;
+    for (int jj = 1; jj <= n; ++jj) {
+        if (jj < n && w[jj] - w[jj - 1] <= gap_tol && jj - start < 32) continue;
+        const int cs = jj - start;
+        if (cs > 1) {
+            for (int j = start; j < jj; ++j) {
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int q = start; q < j; ++q) {
+                        double acc = 0.0;
+                        for (int i = t; i < n; i += bd) acc += X[(long long)i * n + q] * X[(long long)i * n + j];
+                        const double cq = block_sum(acc);
+                        for (int i = t; i < n; i += bd) X[(long long)i * n + j] -= cq * X[(long long)i * n + q];
+                        __syncthreads();
+                    }
+                }
+                double acc = 0.0;
+                for (int i = t; i < n; i += bd) acc += X[(long long)i * n + j] * X[(long long)i * n + j];
+                const double inv = 1.0 / sqrt(block_sum(acc));
+                for (int i = t; i < n; i += bd) X[(long long)i * n + j] *= inv;
+                __syncthreads();
+            }
+            // y_q = T x_q, Tc = X_c^T T X_c
+            for (int q = 0; q < cs; ++q) {
+                const int jq = start + q;
+                for (int i = t; i < n; i += bd) {
+                    double v = dg[i] * X[(long long)i * n + jq];
+                    if (i > 0) v += eg[i - 1] * X[(long long)(i - 1) * n + jq];
+                    if (i + 1 < n) v += eg[i] * X[(long long)(i + 1) * n + jq];
+                    ytmp[(long long)i * 32 + q] = v;
+                }
+            }
+            __syncthreads();
+            for (int pq = 0; pq < cs * cs; ++pq) {
+                const int pp = pq / cs, qq = pq % cs;
+                if (qq < pp) continue;
+                double acc = 0.0;
+                for (int i = t; i < n; i += bd) acc += X[(long long)i * n + start + pp] * ytmp[(long long)i * 32 + qq];
+                const double v = block_sum(acc);
+                if (t == 0) {
+                    Tc[pp * cs + qq] = v;
+                    Tc[qq * cs + pp] = v;
+                }
+            }
+            __syncthreads();
+            if (t == 0) {
+                // cyclic Jacobi on the cs x cs matrix, then ascending sort of the pairs
+                for (int e = 0; e < cs * cs; ++e) Qc[e] = (e / cs == e % cs) ? 1.0 : 0.0;
+                for (int sweep = 0; sweep < 50; ++sweep) {
+                    bool rot = false;
+                    for (int pp = 0; pp < cs; ++pp)
+                        for (int qq = pp + 1; qq < cs; ++qq) {
+                            const double apq = Tc[pp * cs + qq];
+                            const double app = Tc[pp * cs + pp], aqq = Tc[qq * cs + qq];
+                            if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
+                            rot = true;
+                            const double tau = (aqq - app) / (2.0 * apq);
+                            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                            const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+                            for (int k = 0; k < cs; ++k) {
+                                const double akp = Tc[k * cs + pp], akq = Tc[k * cs + qq];
+                                Tc[k * cs + pp] = c * akp - sn * akq;
+                                Tc[k * cs + qq] = sn * akp + c * akq;
+                            }
+                            for (int k = 0; k < cs; ++k) {
+                                const double apk = Tc[pp * cs + k], aqk = Tc[qq * cs + k];
+                                Tc[pp * cs + k] = c * apk - sn * aqk;
+                                Tc[qq * cs + k] = sn * apk + c * aqk;
+                            }
+                            Tc[pp * cs + qq] = 0.0;
+                            Tc[qq * cs + pp] = 0.0;
+                            for (int k = 0; k < cs; ++k) {
+                                const double vkp = Qc[k * cs + pp], vkq = Qc[k * cs + qq];
+                                Qc[k * cs + pp] = c * vkp - sn * vkq;
+                                Qc[k * cs + qq] = sn * vkp + c * vkq;
+                            }
+                        }
+                    if (!rot) break;
+                }
+                for (int pp = 0; pp < cs; ++pp) {          // selection sort of the pairs
+                    int best = pp;
+                    for (int qq = pp + 1; qq < cs; ++qq)
+                        if (Tc[qq * cs + qq] < Tc[best * cs + best]) best = qq;
+                    if (best != pp) {
+                        const double tmp = Tc[pp * cs + pp];
+                        Tc[pp * cs + pp] = Tc[best * cs + best];
+                        Tc[best * cs + best] = tmp;
+                        for (int k = 0; k < cs; ++k) {
+                            const double v = Qc[k * cs + pp];
+                            Qc[k * cs + pp] = Qc[k * cs + best];
+                            Qc[k * cs + best] = v;
+                        }
+                    }
+                    w[start + pp] = Tc[pp * cs + pp];
+                }
+            }
+            __syncthreads();
+            // rotate the cluster basis: X_c <- X_c Q_c (row-wise, old values staged in ytmp)
+            for (int i = t; i < n; i += bd) {
+                for (int q = 0; q < cs; ++q) ytmp[(long long)i * 32 + q] = X[(long long)i * n + start + q];
+                for (int q = 0; q < cs; ++q) {
+                    double v = 0.0;
+                    for (int pp = 0; pp < cs; ++pp) v += ytmp[(long long)i * 32 + pp] * Qc[pp * cs + q];
+                    X[(long long)i * n + start + q] = v;
+                }
+            }
+            __syncthreads();
+        }
+        start = jj;
+    }
 }
 
 // Z <- H_0 H_1 ... H_{n-3} Z (eigenvectors of the reduced matrix back to the
-// original basis).  Per reflector: the row vector v^T Z (threads along a row of Z,
-// rows in sequence: coalesced), then the rank-one update.
+// original basis).  Columns are independent: each workgroup owns 8 columns and
+// applies every reflector to them (threads split the rows for the dot products).
 __global__ void tridiag_back_kernel(int n, const double* __restrict__ Vh, const double* __restrict__ tau,
                                     double* __restrict__ Z) {
-    __shared__ double dot[1024];
-    const int t = threadIdx.x, bd = blockDim.x;
+    __shared__ double red[8][33];
+    __shared__ double dot[8];
+    const int t = threadIdx.x;
+    const int c = t & 7, rg = t >> 3;          // 8 columns x 32 row groups
+    const int j = blockIdx.x * 8 + c;
+    const bool live = j < n;
     for (int k = n - 3; k >= 0; --k) {
         const double tk = tau[k];
         if (tk == 0.0) continue;
         const double* vk = Vh + (long long)k * n;
-        for (int j = t; j < n; j += bd) {
-            double acc = 0.0;
-            for (int i = k + 1; i < n; ++i) acc = fma(vk[i], Z[(long long)i * n + j], acc);
-            dot[j] = tk * acc;
+        double acc = 0.0;
+        if (live)
+            for (int i = k + 1 + rg; i < n; i += 32) acc = fma(vk[i], Z[(long long)i * n + j], acc);
+        red[c][rg] = acc;
+        __syncthreads();
+        if (rg == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < 32; ++q) sum += red[c][q];
+            dot[c] = tk * sum;
         }
         __syncthreads();
-        for (int i = k + 1; i < n; ++i) {
-            const double vi = vk[i];
-            double* zr = Z + (long long)i * n;
-            for (int j = t; j < n; j += bd) zr[j] -= vi * dot[j];
-        }
+        const double dc = dot[c];
+        if (live)
+            for (int i = k + 1 + rg; i < n; i += 32) Z[(long long)i * n + j] -= dc * vk[i];
         __syncthreads();
     }
-}
-
-// Ascending order of d with the matching columns of Z.
-__global__ void sort_pairs_kernel(int n, const double* __restrict__ d, const double* __restrict__ Z,
-                                  double* __restrict__ w, double* __restrict__ Zout) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double di = d[i];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-        const double dj = d[j];
-        rank += (dj < di) || (dj == di && j < i);
-    }
-    w[rank] = di;
-    for (int r = 0; r < n; ++r) Zout[(long long)r * n + rank] = Z[(long long)r * n + i];
 }
 
 void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
-                    int* status) {
-    // work: n*n (reflectors, then eigenvectors before sorting); small: 3n (tau, diag, off)
+                    double* scratch, int* status) {
+    // work: n*n (reflectors); small: 3n (tau, diag, off); scratch: 5 n*n (inverse iteration)
+    (void)status;
     double* tau = small;
     double* diag = small + n;
     double* off = small + 2 * n;
     hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
-    hipLaunchKernelGGL(tridiag_ql_kernel, dim3(1), dim3(1024), 0, st, n, diag, off, A, status);
-    hipLaunchKernelGGL(tridiag_back_kernel, dim3(1), dim3(1024), 0, st, n, work, tau, A);
-    hipLaunchKernelGGL(sort_pairs_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, n, diag, A, w, V);
+    hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(1), dim3(1024), 0, st, n, diag, off, w);
+    hipLaunchKernelGGL(tridiag_invit_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, n, diag, off, w, V, scratch);
+    hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(1), dim3(256), 0, st, n, diag, off, w, V, scratch);
+    hipLaunchKernelGGL(tridiag_back_kernel, dim3(grid_for(n, 8)), dim3(256), 0, st, n, work, tau, V);
 }
 
 // ---------------------------------------------------------------------------
