@@ -20,8 +20,9 @@ namespace bpjd {
 
 static thread_local std::string g_last_error;
 
-// largest half-bandwidth handled by the blocked (MFMA) local solver
+// largest half-bandwidth and lower entries per row handled by the blocked (MFMA) local solver
 static constexpr int kBlockedMaxBand = 48;
+static constexpr int kBlockedMaxSlots = 8;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
@@ -239,7 +240,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     const int nsub = (int)sptr.size() - 1;
     if (nsub < 1) return fail(BPJD_ERR_DD, "no subdomains");
     const int s = opts->k + opts->guard;
-    if (opts->k < 1 || opts->guard < 0 || s > 21) return fail(BPJD_ERR_ARG, "need 1 <= k and k + guard <= 21");
+    if (opts->k < 1 || opts->guard < 0 || s > 16) return fail(BPJD_ERR_ARG, "need 1 <= k and k + guard <= 16");
     if (s >= nH) return fail(BPJD_ERR_DD, "block size s must be smaller than dim V^H");
     if (nH > 1024) return fail(BPJD_ERR_DD, "coarse space larger than 1024 is not supported");
     if (opts->n_init != 0 && opts->n_init != s) return fail(BPJD_ERR_ARG, "n_init must be 0 or k + guard");
@@ -307,7 +308,9 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     }
     // factor storage per (subdomain, shift): the blocked solver keeps 64 x 16 panels,
     // the windowed solver one band column per row
-    const bool blocked = maxBW <= kBlockedMaxBand;
+    int maxE = 0;
+    for (long long q = 0; q < sumN; ++q) maxE = std::max(maxE, lptr[q + 1] - lptr[q]);
+    const bool blocked = maxBW <= kBlockedMaxBand && maxE <= kBlockedMaxSlots;
     std::vector<long long> Loff(nsub, 0);
     long long Ltot = 0;
     for (int l = 0; l < nsub; ++l) {
@@ -419,6 +422,11 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(upload_vec(p, &p->rptr, rptr));
     chk(upload_vec(p, &p->ridx, ridx));
     chk(upload_vec(p, &p->Loff, Loff));
+    if (blocked) {
+        p->slotE = maxE;
+        chk(alloc_dev(p, &p->sd, (size_t)sumN * maxE));
+        chk(alloc_dev(p, &p->sv, (size_t)sumN * maxE));
+    }
     const size_t nH2 = (size_t)nH * nH;
     chk(alloc_dev(p, &p->KH, nH2));
     chk(alloc_dev(p, &p->MH, nH2));
@@ -427,6 +435,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(alloc_dev(p, &p->jwork, nH2));
     chk(alloc_dev(p, &p->lamH, nH));
     chk(alloc_dev(p, &p->esmall, 3 * (size_t)nH));
+    chk(alloc_dev(p, &p->YT, nH2));
     chk(alloc_dev(p, &p->escratch, std::max(5 * nH2, (size_t)32 * nH)));
     const size_t blk = (size_t)n * 3 * s;
     for (int b = 0; b < 2; ++b) {
@@ -537,6 +546,7 @@ static int check_status(bpjd_problem* p) {
 static void coarse_setup(bpjd_problem* p) {
     hipStream_t st = p->ctx->stream;
     const int nH = p->nH;
+    if (p->slotE) launch_extract_local(st, p->sumN, p->slotE, p->lptr, p->ldd, p->lpos, p->km, p->sd, p->sv);
     launch_galerkin(st, p->n, nH, p->rowptr, p->col, p->km, p->Pptr, p->Pcol, p->Pval, p->PTptr, p->PTcol, p->PTval,
                     p->kpptr, p->kpcol, p->kpval, p->khptr, p->khcol, p->nnzKH, p->KH, p->MH);
     launch_cholesky(st, nH, p->MH, p->status, STATUS_COARSE_NOT_SPD);              // MH <- L
@@ -546,6 +556,7 @@ static void coarse_setup(bpjd_problem* p) {
     launch_trsm_lower(st, nH, nH, p->MH, p->jwork, nH, false);                      // L^{-1} K_H L^{-T}
     launch_sym_eig(st, nH, p->jwork, p->lamH, p->Y, p->Ccoarse, p->esmall, p->escratch, p->status);  // V -> Y
     launch_trsm_lower(st, nH, nH, p->MH, p->Y, nH, true);                           // Y = L^{-T} V
+    launch_transpose(st, nH, p->Y, p->YT);
 }
 
 // Apply the two-level preconditioner to F (n x s, ld s) with shifts p->lam; Z (ld s).
@@ -553,8 +564,8 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, PhaseTime
     hipStream_t st = p->ctx->stream;
     const int s = p->s;
     PH_BEGIN(T, BPJD_PHASE_COARSE);
-    launch_coarse_apply(st, p->n, p->nH, s, p->PTptr, p->PTcol, p->PTval, F, s, p->Y, p->lamH, p->lam, p->G, p->Cw,
-                        p->Zhat);
+    launch_coarse_apply(st, p->n, p->nH, s, p->PTptr, p->PTcol, p->PTval, F, s, p->Y, p->YT, p->lamH, p->lam, p->G,
+                        p->Cw, p->Zhat);
     PH_END(T);
     const bool mixed = p->opts.precision == BPJD_PREC_MIXED;
     PH_BEGIN(T, BPJD_PHASE_GATHER);
@@ -564,10 +575,10 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, PhaseTime
     PH_BEGIN(T, BPJD_PHASE_LOCAL);
     if (mixed)
         launch_local_solve_f32(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
-                               p->lam, (const float*)p->Floc, (float*)p->zloc, (float*)p->Lwork, p->Loff, p->status);
+                               p->slotE, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc, (float*)p->Lwork, p->Loff, p->status);
     else
         launch_local_solve_f64(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
-                               p->lam, (const double*)p->Floc, (double*)p->zloc, (double*)p->Lwork, p->Loff,
+                               p->slotE, p->sd, p->sv, p->lam, (const double*)p->Floc, (double*)p->zloc, (double*)p->Lwork, p->Loff,
                                p->status);
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_GATHER);
@@ -587,19 +598,17 @@ static void orthonormalize_T(bpjd_problem* p, int b, int ct, PhaseTimer* T) {
     hipStream_t st = p->ctx->stream;
     const int n = p->n, s = p->s, ld = 3 * s;
     double *W = p->W[b], *KW = p->KW[b], *MW = p->MW[b];
+    const double* src3[3] = {W, KW, MW};
+    double* dst3[3] = {colp(W, ct), colp(KW, ct), colp(MW, ct)};
     PH_BEGIN(T, BPJD_PHASE_ORTHO);
     for (int pass = 0; pass < 2 && ct > 0; ++pass) {
         launch_gram(st, n, ct, s, MW, ld, colp(W, ct), ld, p->partial, p->npart, p->csmall);
-        launch_gemm_small(st, n, ct, s, -1.0, W, ld, p->csmall, 1.0, colp(W, ct), ld);
-        launch_gemm_small(st, n, ct, s, -1.0, KW, ld, p->csmall, 1.0, colp(KW, ct), ld);
-        launch_gemm_small(st, n, ct, s, -1.0, MW, ld, p->csmall, 1.0, colp(MW, ct), ld);
+        launch_gemm_rows(st, n, ct, s, -1.0, src3, dst3, 3, ld, p->csmall, 1.0, ld);
     }
     for (int pass = 0; pass < 2; ++pass) {
         launch_gram(st, n, s, s, colp(W, ct), ld, colp(MW, ct), ld, p->partial, p->npart, p->gsmall);
         launch_cholqr_coef(st, s, p->gsmall, p->csmall, p->dropped[b] + ct, p->status);
-        launch_rightmul_inplace(st, n, s, colp(W, ct), ld, p->csmall);
-        launch_rightmul_inplace(st, n, s, colp(KW, ct), ld, p->csmall);
-        launch_rightmul_inplace(st, n, s, colp(MW, ct), ld, p->csmall);
+        launch_rightmul_rows(st, n, s, dst3, 3, ld, p->csmall);
     }
     PH_END(T);
 }
@@ -612,9 +621,9 @@ static void rayleigh_ritz(bpjd_problem* p, int a, int b, int m, int with_p, Phas
     launch_gram(st, n, m, m, p->W[a], ld, p->KW[a], ld, p->partial, p->npart, p->Hm);
     launch_rr_coef(st, m, s, with_p, p->Hm, p->dropped[a], p->dropped[b], p->theta, p->Cfull);
     const int cw = with_p ? 2 * s : s;
-    launch_gemm_small(st, n, m, cw, 1.0, p->W[a], ld, p->Cfull, 0.0, p->W[b], ld);
-    launch_gemm_small(st, n, m, cw, 1.0, p->KW[a], ld, p->Cfull, 0.0, p->KW[b], ld);
-    launch_gemm_small(st, n, m, cw, 1.0, p->MW[a], ld, p->Cfull, 0.0, p->MW[b], ld);
+    const double* src3[3] = {p->W[a], p->KW[a], p->MW[a]};
+    double* dst3[3] = {p->W[b], p->KW[b], p->MW[b]};
+    launch_gemm_rows(st, n, m, cw, 1.0, src3, dst3, 3, ld, p->Cfull, 0.0, ld);
     launch_copy_cols(st, 1, s, p->theta, s, p->lam, s);
     PH_END(T);
 }
@@ -736,11 +745,11 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
 
         // Step 2: t_i = (I - X X^T M) (B_i)^{-1} r_i
         apply_precond(p, p->F, p->Z, T);
+        // The projection (I - X X^T M) of Step 2 is the first Gram-Schmidt pass of
+        // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
         const int ct = s + S.np;
         PH_BEGIN(T, BPJD_PHASE_ORTHO);
-        launch_gram(st, n, s, s, p->MW[a], ld, p->Z, s, p->partial, p->npart, p->csmall);
         launch_copy_cols(st, n, s, p->Z, s, p->W[a] + ct, ld);
-        launch_gemm_small(st, n, s, s, -1.0, p->W[a], ld, p->csmall, 1.0, p->W[a] + ct, ld);
         PH_END(T);
         PH_BEGIN(T, BPJD_PHASE_SPMM);
         launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[a] + ct, ld, s, p->KW[a] + ct, ld, p->MW[a] + ct, ld);

@@ -145,53 +145,155 @@ void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, co
 }
 
 // ---------------------------------------------------------------------------
-// Gram product C = A^T B, a, b <= 64.  Each block stages 16 rows of A and B in
-// LDS and accumulates up to 16 outputs per thread.
-__global__ void gram_partial_kernel(int n, int a, int b, const double* __restrict__ A, int lda,
-                                    const double* __restrict__ B, int ldb, int chunk,
-                                    double* __restrict__ partial) {
-    __shared__ double sA[16][64];
-    __shared__ double sB[16][64];
-    const int t = threadIdx.x;
+// Gram product C = A^T B (a, b <= 64) with FP64 16x16x4 MFMAs: the rows are the
+// contraction index.  One wave per chunk of rows; for a k-step of 4 rows, lane l
+// supplies A[r + l/16][16 tp + l%16] and B[r + l/16][16 tq + l%16] straight
+// from the row-major blocks.  Partials ([a*b][npart]) are reduced in a second
+// pass in a fixed order.
+typedef double dx4_t __attribute__((ext_vector_type(4)));
+
+template <int TA, int TB>
+__global__ __launch_bounds__(64) void gram_mfma_kernel(int n, int a, int b, const double* __restrict__ A, int lda,
+                                                       const double* __restrict__ B, int ldb, int chunk,
+                                                       double* __restrict__ partial) {
+    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
     const int r0 = blockIdx.x * chunk;
     const int r1 = min(n, r0 + chunk);
-    const int nout = a * b;
-    double acc[16];
+    dx4_t acc[TA][TB];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    for (int rb = r0; rb < r1; rb += 16) {
-        for (int idx = t; idx < 16 * 64; idx += blockDim.x) {
-            const int rr = idx >> 6, p = idx & 63;
-            const int r = rb + rr;
-            sA[rr][p] = (r < r1 && p < a) ? A[(long long)r * lda + p] : 0.0;
-            sB[rr][p] = (r < r1 && p < b) ? B[(long long)r * ldb + p] : 0.0;
-        }
-        __syncthreads();
+    for (int p = 0; p < TA; ++p)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int o = t + u * 256;
-            if (o < nout) {
-                const int p = o / b, q = o % b;
-                double v = acc[u];
+        for (int q = 0; q < TB; ++q) acc[p][q] = dx4_t{0.0, 0.0, 0.0, 0.0};
+    constexpr int U = 4;                        // k-steps whose loads are in flight together
+    for (int r = r0; r < r1; r += 4 * U) {
+        double av[U][TA], bv[U][TB];
 #pragma unroll
-                for (int rr = 0; rr < 16; ++rr) v = fma(sA[rr][p], sB[rr][q], v);
-                acc[u] = v;
+        for (int u = 0; u < U; ++u) {
+            const int rr = r + 4 * u + lk;
+            const bool rok = rr < r1;
+#pragma unroll
+            for (int p = 0; p < TA; ++p) {
+                const int c = 16 * p + lr;
+                av[u][p] = (rok && c < a) ? A[(long long)rr * lda + c] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < TB; ++q) {
+                const int c = 16 * q + lr;
+                bv[u][q] = (rok && c < b) ? B[(long long)rr * ldb + c] : 0.0;
             }
         }
-        __syncthreads();
-    }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int o = t + u * 256;
-        if (o < nout) partial[(long long)o * gridDim.x + blockIdx.x] = acc[u];
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int p = 0; p < TA; ++p)
+#pragma unroll
+                for (int q = 0; q < TB; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][p], bv[u][q], acc[p][q], 0, 0, 0);
+    }
+    // FP64 accumulator element i of lane l: row l/16 + 4 i, column l%16 of the 16x16 tile
+#pragma unroll
+    for (int p = 0; p < TA; ++p)
+#pragma unroll
+        for (int q = 0; q < TB; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * p + lk + 4 * i, col = 16 * q + lr;
+                if (row < a && col < b) partial[(long long)(row * b + col) * gridDim.x + blockIdx.x] = acc[p][q][i];
+            }
+}
+
+template <int TA>
+static void gram_dispatch_b(hipStream_t st, int TB, int grid, int n, int a, int b, const double* A, int lda,
+                            const double* B, int ldb, int chunk, double* partial) {
+    switch (TB) {
+        case 1: hipLaunchKernelGGL((gram_mfma_kernel<TA, 1>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 2: hipLaunchKernelGGL((gram_mfma_kernel<TA, 2>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 3: hipLaunchKernelGGL((gram_mfma_kernel<TA, 3>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        default: hipLaunchKernelGGL((gram_mfma_kernel<TA, 4>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
     }
 }
 
 void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, const double* B, int ldb,
                  double* partial, int npart, double* C) {
-    const int chunk = (n + npart - 1) / npart;
-    hipLaunchKernelGGL(gram_partial_kernel, dim3(npart), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial);
-    launch_reduce(st, npart, a * b, partial, C);
+    // 64 rows per wave (4 unrolled k-steps of 4 rows), at most npart waves
+    int chunk = 64;
+    while ((n + chunk - 1) / chunk > npart) chunk *= 2;
+    const int grid = (n + chunk - 1) / chunk;
+    const int TA = (a + 15) / 16, TB = (b + 15) / 16;
+    switch (TA) {
+        case 1: gram_dispatch_b<1>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 2: gram_dispatch_b<2>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 3: gram_dispatch_b<3>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        default: gram_dispatch_b<4>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
+    }
+    launch_reduce(st, grid, a * b, partial, C);
+}
+
+// ---------------------------------------------------------------------------
+// Tall-times-small products Y = beta Y + alpha A C (a <= 48, b <= 48): a block
+// stages 64 rows of A and the coefficients in LDS with coalesced loads, forms
+// the 64 x b result in LDS and writes it back row-contiguously.  Up to three
+// (A, Y) pairs share one launch (blockIdx.y); with A == Y (in-place Y = Y C)
+// every row is read before any is written.
+struct Triple {
+    const double* A[3];
+    double* Y[3];
+};
+
+constexpr int GR_ROWS = 64;
+constexpr int GR_MAXC = 48;
+
+__global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, double alpha, Triple T, int lda,
+                                                        const double* __restrict__ C, double beta, int ldy) {
+    __shared__ double sA[GR_ROWS][GR_MAXC + 1];
+    __shared__ double sC[GR_MAXC * GR_MAXC];
+    __shared__ double sY[GR_ROWS][GR_MAXC + 1];
+    const int t = threadIdx.x;
+    const int r0 = blockIdx.x * GR_ROWS;
+    const double* A = T.A[blockIdx.y];
+    double* Y = T.Y[blockIdx.y];
+    for (int e = t; e < a * b; e += 256) sC[e] = C[e];
+    for (int e = t; e < GR_ROWS * a; e += 256) {
+        const int rr = e / a, p = e - rr * a;
+        const int r = r0 + rr;
+        sA[rr][p] = (r < n) ? A[(long long)r * lda + p] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < GR_ROWS * b; e += 256) {
+        const int rr = e / b, q = e - rr * b;
+        double acc = 0.0;
+        for (int p = 0; p < a; ++p) acc = fma(sA[rr][p], sC[p * b + q], acc);
+        sY[rr][q] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < GR_ROWS * b; e += 256) {
+        const int rr = e / b, q = e - rr * b;
+        const int r = r0 + rr;
+        if (r >= n) continue;
+        double* y = Y + (long long)r * ldy + q;
+        *y = (beta == 0.0) ? alpha * sY[rr][q] : fma(beta, *y, alpha * sY[rr][q]);
+    }
+}
+
+void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
+                      int count, int lda, const double* C, double beta, int ldy) {
+    Triple T{};
+    for (int k = 0; k < count; ++k) {
+        T.A[k] = A[k];
+        T.Y[k] = Y[k];
+    }
+    hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), 0, st, n, a, b, alpha, T, lda,
+                       C, beta, ldy);
+}
+
+void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, int ldy, const double* C) {
+    Triple T{};
+    for (int k = 0; k < count; ++k) {
+        T.A[k] = Y[k];
+        T.Y[k] = Y[k];
+    }
+    hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), 0, st, n, b, b, 1.0, T, ldy, C,
+                       0.0, ldy);
 }
 
 // ---------------------------------------------------------------------------

@@ -62,6 +62,11 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, 
 // Y(:, 0..b) = beta*Y + alpha * A(:, 0..a) * C, C a x b row-major (ldc = b).
 void launch_gemm_small(hipStream_t st, int n, int a, int b, double alpha, const double* A, int lda,
                        const double* C, double beta, double* Y, int ldy);
+// Batched over up to three (A, Y) pairs sharing C: Y_k = beta Y_k + alpha A_k C (b <= 48).
+void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
+                      int count, int lda, const double* C, double beta, int ldy);
+// Batched in place Y_k = Y_k C (b <= 24).
+void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, int ldy, const double* C);
 // In place: Y(:, 0..b) = Y(:, 0..b) * C, C b x b row-major.
 void launch_rightmul_inplace(hipStream_t st, int n, int b, double* Y, int ldy, const double* C);
 // Copy/convert helpers.
@@ -78,20 +83,27 @@ void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int
 // Zhat = Y (C / (lamH_j - lam_i), rows j < s zeroed) with C = Y^T G; G = P^T F.
 void launch_coarse_apply(hipStream_t st, int n, int nH, int s,
                          const int* PTptr, const int* PTcol, const double* PTval,
-                         const double* F, int ldf, const double* Y, const double* lamH, const double* lam,
-                         double* G, double* Cw, double* Zhat);
+                         const double* F, int ldf, const double* Y, const double* YT, const double* lamH,
+                         const double* lam, double* G, double* Cw, double* Zhat);
 void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, double* Floc);
 void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc);
 // Batched local LDL^T factor + solve, one wavefront per (subdomain, shift).
-// Floc/zloc: [s][sumN]; Lwork: per (l,i) n_l*(bw_l+1) entries at Loff[l] + i*n_l*(bw_l+1).
+// Floc/zloc: [s][sumN].  With fixed-slot local rows (sd != NULL, E slots per row) the
+// blocked MFMA solver runs (Lwork: 64 x 16 panels per (l, i)); otherwise the windowed
+// solver (Lwork: n_l (bw_l + 1) per (l, i)).
 void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            int E, const int* sd, const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status);
 void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            int E, const int* sd, const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status);
+// Numeric local extraction: fixed-slot lower entries (offset, (K, M)) of every local row.
+void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr, const int* ldd, const int* lpos,
+                          const double2* km, int* sd, double2* sv);
 // Z(d, i) = sum_b P(d,b) Zhat(b,i) + sum_{(l,r) covering d} zloc_i(l,r)  (deterministic order).
 void launch_scatter_f64(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
                         const double* Zhat, const int* rptr, const int* ridx, const double* zloc, double* Z, int ldz);
@@ -155,10 +167,14 @@ struct bpjd_problem {
     int *lptr = nullptr, *ldd = nullptr, *lpos = nullptr;
     int *rptr = nullptr, *ridx = nullptr;
     long long* Loff = nullptr;
+    int slotE = 0;                     // fixed slots per local row (blocked solver), 0 = windowed solver
+    int* sd = nullptr;
+    double2* sv = nullptr;
 
     // device numeric workspace
     double *KH = nullptr, *MH = nullptr, *Ccoarse = nullptr, *Y = nullptr, *lamH = nullptr, *jwork = nullptr;
     double* esmall = nullptr;
+    double* YT = nullptr;              // coarse eigenvectors, transposed
     double* escratch = nullptr;
     double *W[2] = {nullptr, nullptr}, *KW[2] = {nullptr, nullptr}, *MW[2] = {nullptr, nullptr};
     double *F = nullptr, *Z = nullptr, *Zhat = nullptr, *G = nullptr, *Cw = nullptr;

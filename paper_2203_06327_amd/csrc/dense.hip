@@ -270,14 +270,23 @@ __global__ void tridiag_kernel(int n, double* __restrict__ A, double* __restrict
         }
         __syncthreads();
         if (tk != 0.0) {
-            // p = tau A22 v; A22 is symmetric, so thread j reads column j (coalesced across threads)
-            for (int j = t; j < m; j += bd) {
-                const double* colj = A + (long long)(k + 1) * n + (k + 1) + j;
-                double pj = 0.0;
-                for (int i = 0; i < m; ++i) pj = fma(colj[(long long)i * n], v[i], pj);
-                w[j] = tk * pj;
+            // p = tau A22 v; A22 is symmetric, so column j is read by 4 threads (row
+            // quarters), coalesced across neighbouring j, then summed in a fixed order
+            {
+                const int qtr = t >> 8, jt = t & 255;
+                for (int j0 = 0; j0 < m; j0 += 256) {
+                    const int j = j0 + jt;
+                    double pj = 0.0;
+                    if (j < m) {
+                        const double* colj = A + (long long)(k + 1) * n + (k + 1) + j;
+                        for (int i = qtr; i < m; i += 4) pj = fma(colj[(long long)i * n], v[i], pj);
+                    }
+                    red[t] = pj;
+                    __syncthreads();
+                    if (qtr == 0 && j < m) w[j] = tk * (((red[jt] + red[256 + jt]) + red[512 + jt]) + red[768 + jt]);
+                    __syncthreads();
+                }
             }
-            __syncthreads();
             double pv = 0.0;
             for (int i = t; i < m; i += bd) pv += w[i] * v[i];
             red[t] = pv;

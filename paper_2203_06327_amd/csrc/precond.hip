@@ -47,8 +47,9 @@ __global__ void galerkin_kh_kernel(int nH, int nnzKH, const int* __restrict__ PT
                                    const int* __restrict__ kpcol, const double2* __restrict__ kpval,
                                    const int* __restrict__ khptr, const int* __restrict__ khcol,
                                    double* __restrict__ KH, double* __restrict__ MH) {
-    const int e2 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e2 >= nnzKH) return;
+    __shared__ double rk[256], rm[256];
+    const int e2 = blockIdx.x;
+    const int t = threadIdx.x;
     // coarse row a of this pattern entry (binary search in khptr)
     int lo = 0, hi = nH;
     while (hi - lo > 1) {
@@ -58,7 +59,7 @@ __global__ void galerkin_kh_kernel(int nH, int nnzKH, const int* __restrict__ PT
     const int a = lo;
     const int b = khcol[e2];
     double ak = 0.0, am = 0.0;
-    for (int q = PTptr[a]; q < PTptr[a + 1]; ++q) {
+    for (int q = PTptr[a] + t; q < PTptr[a + 1]; q += 256) {
         const int i = PTcol[q];
         const double w = PTval[q];
         for (int e = kpptr[i]; e < kpptr[i + 1]; ++e) {
@@ -69,8 +70,20 @@ __global__ void galerkin_kh_kernel(int nH, int nnzKH, const int* __restrict__ PT
             }
         }
     }
-    KH[(long long)a * nH + b] = ak;
-    MH[(long long)a * nH + b] = am;
+    rk[t] = ak;
+    rm[t] = am;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            rk[t] += rk[t + o];
+            rm[t] += rm[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        KH[(long long)a * nH + b] = rk[0];
+        MH[(long long)a * nH + b] = rm[0];
+    }
 }
 
 void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int* col, const double2* km,
@@ -82,7 +95,7 @@ void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int
     launch_fill(st, (long long)nH * nH, MH, 0.0);
     hipLaunchKernelGGL(galerkin_kp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, n, rowptr, col, km, Pptr, Pcol,
                        Pval, kpptr, kpcol, kpval);
-    hipLaunchKernelGGL(galerkin_kh_kernel, dim3(grid_for(nnzKH, 256)), dim3(256), 0, st, nH, nnzKH, PTptr,
+    hipLaunchKernelGGL(galerkin_kh_kernel, dim3(nnzKH), dim3(256), 0, st, nH, nnzKH, PTptr,
                        PTcol, PTval, kpptr, kpcol, kpval, khptr, khcol, KH, MH);
 }
 
@@ -122,19 +135,34 @@ __global__ void restrict_kernel(int nH, int s, const int* __restrict__ PTptr, co
     }
 }
 
-__global__ void coarse_coef_kernel(int nH, int s, const double* __restrict__ Y, const double* __restrict__ G,
+// Cw[j][i] = (y_j^T G_i) / (lambda^H_j - lambda_i) for j >= s; one workgroup per
+// coarse eigenvector j reads row j of Y^T (contiguous) and reduces per column i.
+__global__ void coarse_coef_kernel(int nH, int s, const double* __restrict__ YT, const double* __restrict__ G,
                                    const double* __restrict__ lamH, const double* __restrict__ lam,
                                    double* __restrict__ Cw) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nH * s) return;
-    const int j = t / s, i = t % s;
-    if (j < s) {            // Q^H_{s+1} removes the first s coarse eigenvectors
-        Cw[t] = 0.0;
+    __shared__ double red[16][64];
+    const int j = blockIdx.x;
+    const int t = threadIdx.x;                 // 64 threads: 4 column groups x 16 row slots
+    const int ig = t & 3, rs = t >> 2;
+    if (j < s) {                               // Q^H_{s+1} removes the first s coarse eigenvectors
+        for (int i = t; i < s; i += 64) Cw[j * s + i] = 0.0;
         return;
     }
-    double acc = 0.0;
-    for (int b = 0; b < nH; ++b) acc = fma(Y[(long long)b * nH + j], G[b * s + i], acc);
-    Cw[t] = acc / (lamH[j] - lam[i]);
+    const double* yrow = YT + (long long)j * nH;
+    for (int i0 = 0; i0 < s; i0 += 4) {
+        const int i = i0 + ig;
+        double acc = 0.0;
+        if (i < s)
+            for (int b = rs; b < nH; b += 16) acc = fma(yrow[b], G[b * s + i], acc);
+        red[rs][ig] = acc;
+        __syncthreads();
+        if (rs == 0 && i < s) {
+            double sum = 0.0;
+            for (int k = 0; k < 16; ++k) sum += red[k][ig];
+            Cw[j * s + i] = sum / (lamH[j] - lam[i]);
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void coarse_back_kernel(int nH, int s, const double* __restrict__ Y, const double* __restrict__ Cw,
@@ -149,12 +177,12 @@ __global__ void coarse_back_kernel(int nH, int s, const double* __restrict__ Y, 
 }
 
 void launch_coarse_apply(hipStream_t st, int n, int nH, int s, const int* PTptr, const int* PTcol,
-                         const double* PTval, const double* F, int ldf, const double* Y, const double* lamH,
-                         const double* lam, double* G, double* Cw, double* Zhat) {
+                         const double* PTval, const double* F, int ldf, const double* Y, const double* YT,
+                         const double* lamH, const double* lam, double* G, double* Cw, double* Zhat) {
     (void)n;
     const int work = nH * s;
     hipLaunchKernelGGL(restrict_kernel, dim3(nH), dim3(256), 0, st, nH, s, PTptr, PTcol, PTval, F, ldf, G);
-    hipLaunchKernelGGL(coarse_coef_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, nH, s, Y, G, lamH, lam, Cw);
+    hipLaunchKernelGGL(coarse_coef_kernel, dim3(nH), dim3(64), 0, st, nH, s, YT, G, lamH, lam, Cw);
     hipLaunchKernelGGL(coarse_back_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, nH, s, Y, Cw, Zhat);
 }
 
@@ -301,6 +329,12 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
 // trailing window takes the update -L21 D L21^T with 16x16x4 MFMAs.  The
 // window then slides by 16 rows and a new tile-row enters from the sparse
 // lower pattern.  Rows past the end of the subdomain are identity padding.
+// The blocked solver's workgroup is a single wavefront: its LDS accesses execute
+// in issue order, so exchanging data through LDS only needs the compiler not to
+// reorder them (a wave barrier), not a workgroup barrier with its memory fence
+// (which would wait for the outstanding global loads and stores).
+__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
 
@@ -317,6 +351,8 @@ struct MfmaTile<float> {
     __device__ static inline float bcast(float v, int src) {
         return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
     }
+    // reciprocal of a pivot: hardware estimate (about 1 ulp in FP32)
+    __device__ static inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 };
 template <>
 struct MfmaTile<double> {
@@ -332,20 +368,26 @@ struct MfmaTile<double> {
         const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
         return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
     }
+    // reciprocal of a pivot: hardware estimate refined by two Newton steps
+    __device__ static inline double recip(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(r, fma(-x, r, 1.0), r);
+        r = fma(r, fma(-x, r, 1.0), r);
+        return r;
+    }
 };
 
 constexpr int MFMA_WIN = 64;       // window rows
-constexpr int MFMA_MAX_BW = 48;    // supported half-bandwidth
 
 template <typename T>
 __global__ __launch_bounds__(64) void local_band_mfma_kernel(
-    int s, const int* __restrict__ subptr, const int* __restrict__ lptr, const int* __restrict__ ldd,
-    const int* __restrict__ lpos, const double2* __restrict__ km, const double* __restrict__ lam,
-    const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc, T* __restrict__ Lwork,
-    const long long* __restrict__ Loff, int* __restrict__ status) {
+    int s, int E, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
+    const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
+    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
     constexpr int NT = 4, R = MFMA_WIN;
+    constexpr int EPL = 2;                  // slot entries a lane carries (E <= 4 * EPL)
     __shared__ T pan[R][17];
     __shared__ T nrow[16][R + 1];
     __shared__ T vec[R];
@@ -357,6 +399,7 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     const int npan = (nl + 15) >> 4;
     const double lamd = lam[i];
     const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+    const int q = lane >> 2, slot0 = lane & 3;
     T* Lp = Lwork + Loff[l] + (long long)i * npan * (R * 16);
     const T* f = Floc + (long long)i * ldF + off;
     T* z = zloc + (long long)i * ldF + off;
@@ -367,20 +410,37 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
 #pragma unroll
         for (int J = 0; J < NT; ++J) A[I][J] = acc_t{T(0), T(0), T(0), T(0)};
 
-    // tile-row I of the window <- rows rb..rb+15 of K_l - lambda_i M_l, window column base cb
-    auto load_row = [&](const int I, const int rb, const int cb) {
-        for (int e = lane; e < 16 * (R + 1); e += 64) (&nrow[0][0])[e] = T(0);
-        __syncthreads();
-        const int q = lane >> 2, r = rb + q;
-        if (r < nl) {
-            for (int e = lptr[off + r] + (lane & 3); e < lptr[off + r + 1]; e += 4) {
-                const double2 v = km[lpos[e]];
-                nrow[q][r - ldd[e] - cb] = (T)(v.x - lamd * v.y);
+    // fixed-slot lower entries of local row r: band offset sd (-1 = empty), (K, M) values sv
+    int pd[EPL];
+    T pv[EPL];
+    auto fetch = [&](const int rb) {       // entries of row rb + q for this lane's slots
+        const int r = rb + q;
+#pragma unroll
+        for (int u = 0; u < EPL; ++u) {
+            const int e = slot0 + 4 * u;
+            pd[u] = -1;
+            pv[u] = T(0);
+            if (r < nl && e < E) {
+                const long long k = (long long)(off + r) * E + e;
+                pd[u] = sd[k];
+                const double2 v = sv[k];
+                pv[u] = (T)(v.x - lamd * v.y);
             }
-        } else if ((lane & 3) == 0) {
+        }
+    };
+    // tile-row I of the window <- the fetched rows rb..rb+15, window column base cb
+    auto place = [&](const int I, const int rb, const int cb) {
+        for (int e = lane; e < 16 * (R + 1); e += 64) (&nrow[0][0])[e] = T(0);
+        wave_sync();
+        const int r = rb + q;
+        if (r < nl) {
+#pragma unroll
+            for (int u = 0; u < EPL; ++u)
+                if (pd[u] >= 0) nrow[q][r - pd[u] - cb] = pv[u];
+        } else if (slot0 == 0) {
             nrow[q][r - cb] = T(1);
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int J = 0; J < NT; ++J) {
             if (J <= I) {
@@ -388,52 +448,59 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
                 for (int ii = 0; ii < 4; ++ii) A[I][J][ii] = nrow[MT::row(lane, ii)][16 * J + lr];
             }
         }
-        __syncthreads();
+        wave_sync();
     };
 
 #pragma unroll
-    for (int I = 0; I < NT; ++I) load_row(I, 16 * I, 0);
+    for (int I = 0; I < NT; ++I) {
+        fetch(16 * I);
+        place(I, 16 * I, 0);
+    }
     T y = (lane < nl) ? f[lane] : T(0);
     int bad = 0;
 
     for (int P = 0; P < npan; ++P) {
         const int base = 16 * P;
+        // prefetch the tile-row entering after this panel and its right-hand side
+        fetch(base + 16 * NT);
+        const int rnew = base + 16 + lane;
+        const T fnew = (lane >= R - 16 && rnew < nl) ? f[rnew] : T(0);
         // panel (tile column 0) -> one row per lane
 #pragma unroll
         for (int I = 0; I < NT; ++I)
 #pragma unroll
             for (int ii = 0; ii < 4; ++ii) pan[16 * I + MT::row(lane, ii)][lr] = A[I][0][ii];
-        __syncthreads();
+        wave_sync();
         T a[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[c] = pan[lane][c];
-        T dl = T(1);
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const T u = a[c];
             T dc = MT::bcast(u, c);
-            if (!(dc == dc) || dc == T(0) || !isfinite((double)dc)) {
+            // a zero, tiny or non-finite pivot marks the factorisation as failed
+            if (!(fabs(dc) > T(1e-30)) || !(fabs(dc) < T(1e30))) {
                 bad = 1;
                 dc = T(1);
             }
-            const T inv = T(1) / dc;
+            const T inv = MT::recip(dc);
             const T lt = u * inv;
 #pragma unroll
             for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * MT::bcast(u, c2);
             const T yc = MT::bcast(y, c);
             if (lane > c) y -= lt * yc;
             a[c] = (lane == c) ? dc : lt;
-            if (lane == c) dl = dc;
         }
         // store the factored panel (row per lane) and D^{-1} L^{-1} f of its 16 rows
-        T* Lpan = Lp + (long long)P * (R * 16) + lane * 16;
+        // column-major panel storage: lanes write 64 consecutive values per column
+        T* Lpan = Lp + (long long)P * (R * 16) + lane;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) Lpan[c] = a[c];
-        if (lane < 16 && base + lane < nl) z[base + lane] = y / dl;
-        __syncthreads();
+        for (int c = 0; c < 16; ++c) Lpan[c * R] = a[c];
+        wave_sync();
 #pragma unroll
         for (int c = 0; c < 16; ++c) pan[lane][c] = a[c];
-        __syncthreads();
+        wave_sync();
+        if (lane < 16 && base + lane < nl) z[base + lane] = y * MT::recip(pan[lane][lane]);
         // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T
         T aop[NT][4], bop[NT][4];
 #pragma unroll
@@ -451,33 +518,46 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
             for (int J = 1; J <= I; ++J)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) A[I][J] = MT::mma(aop[I][k], bop[J][k], A[I][J]);
-        __syncthreads();
+        wave_sync();
         // slide the window by 16 rows
 #pragma unroll
         for (int I = 1; I < NT; ++I)
 #pragma unroll
             for (int J = 1; J <= I; ++J) A[I - 1][J - 1] = A[I][J];
-        if (P + 1 < npan) load_row(NT - 1, base + 16 * NT, base + 16);
+        if (P + 1 < npan) place(NT - 1, base + 16 * NT, base + 16);
         vec[lane] = y;
-        __syncthreads();
-        const int rnew = base + 16 + lane;
-        y = (lane < R - 16) ? vec[lane + 16] : ((rnew < nl) ? f[rnew] : T(0));
-        __syncthreads();
+        wave_sync();
+        y = (lane < R - 16) ? vec[lane + 16] : fnew;
+        wave_sync();
     }
 
     // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows
     T zw = T(0);
+    T an[16];
+    T zn = T(0);
+    {
+        const int P = npan - 1;
+        const T* Lpan = Lp + (long long)P * (R * 16) + lane;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) an[c] = Lpan[c * R];
+        zn = (lane < 16 && 16 * P + lane < nl) ? z[16 * P + lane] : T(0);
+    }
     for (int P = npan - 1; P >= 0; --P) {
         const int base = 16 * P;
-        vec[lane] = zw;
-        __syncthreads();
-        zw = (lane >= 16) ? vec[lane - 16] : T(0);
-        __syncthreads();
-        const T* Lpan = Lp + (long long)P * (R * 16) + lane * 16;
         T a[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] = Lpan[c];
-        const T zc0 = (lane < 16 && base + lane < nl) ? z[base + lane] : T(0);
+        for (int c = 0; c < 16; ++c) a[c] = an[c];
+        const T zc0 = zn;
+        if (P > 0) {      // prefetch the next panel down
+            const T* Lnext = Lp + (long long)(P - 1) * (R * 16) + lane;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) an[c] = Lnext[c * R];
+            zn = (lane < 16) ? z[base - 16 + lane] : T(0);
+        }
+        vec[lane] = zw;
+        wave_sync();
+        zw = (lane >= 16) ? vec[lane - 16] : T(0);
+        wave_sync();
 #pragma unroll
         for (int c = 15; c >= 0; --c) {
             T part = (lane > c) ? a[c] * zw : T(0);
@@ -489,12 +569,33 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
 }
 
+// Local extraction (numeric setup): the lower entries of every local row of
+// every subdomain in fixed slots, band offset and (K, M) value pair.
+__global__ void extract_local_kernel(long long sumN, int E, const int* __restrict__ lptr, const int* __restrict__ ldd,
+                                     const int* __restrict__ lpos, const double2* __restrict__ km,
+                                     int* __restrict__ sd, double2* __restrict__ sv) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= sumN) return;
+    const int e0 = lptr[r], e1 = lptr[r + 1];
+    for (int e = 0; e < E; ++e) {
+        const bool has = e0 + e < e1;
+        sd[r * E + e] = has ? ldd[e0 + e] : -1;
+        sv[r * E + e] = has ? km[lpos[e0 + e]] : make_double2(0.0, 0.0);
+    }
+}
+
+void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr, const int* ldd, const int* lpos,
+                          const double2* km, int* sd, double2* sv) {
+    hipLaunchKernelGGL(extract_local_kernel, dim3(grid_for(sumN, 256)), dim3(256), 0, st, sumN, E, lptr, ldd, lpos,
+                       km, sd, sv);
+}
+
 template <typename T>
-static void launch_local_mfma(hipStream_t st, int nsub, int s, long long sumN, const int* subptr, const int* lptr,
-                              const int* ldd, const int* lpos, const double2* km, const double* lam, const T* Floc,
-                              T* zloc, T* Lwork, const long long* Loff, int* status) {
-    hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, subptr, lptr, ldd, lpos, km,
-                       lam, Floc, sumN, zloc, Lwork, Loff, status);
+static void launch_local_mfma(hipStream_t st, int nsub, int s, int E, long long sumN, const int* subptr,
+                              const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
+                              T* Lwork, const long long* Loff, int* status) {
+    hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, E, subptr, sd, sv, lam, Floc,
+                       sumN, zloc, Lwork, Loff, status);
 }
 
 template <typename T>
@@ -508,11 +609,11 @@ static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long su
 
 void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            int E, const int* sd, const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status) {
-    if (maxC - 1 <= MFMA_MAX_BW) {
-        launch_local_mfma<double>(st, nsub, s, sumN, subptr, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
-                                  status);
+    if (sd) {
+        launch_local_mfma<double>(st, nsub, s, E, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
         return;
     }
     launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
@@ -521,11 +622,11 @@ void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long
 
 void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
+                            int E, const int* sd, const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status) {
-    if (maxC - 1 <= MFMA_MAX_BW) {
-        launch_local_mfma<float>(st, nsub, s, sumN, subptr, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
-                                 status);
+    if (sd) {
+        launch_local_mfma<float>(st, nsub, s, E, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
         return;
     }
     launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
