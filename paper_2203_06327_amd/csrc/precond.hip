@@ -335,6 +335,30 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
 // (which would wait for the outstanding global loads and stores).
 __device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// sum over the four lanes of a quad (lanes 4j .. 4j+3) with DPP quad permutations
+__device__ inline float quad_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));   // [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));   // [2,3,0,1]
+    return v;
+}
+__device__ inline double dpp_double(double v, const int ctrl_sel) {
+    const long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    if (ctrl_sel == 0) {
+        lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double quad_sum(double v) {
+    v += dpp_double(v, 0);
+    v += dpp_double(v, 1);
+    return v;
+}
+
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
 
@@ -348,6 +372,8 @@ struct MfmaTile<float> {
     }
     // accumulator element i of a lane sits at row 4*(lane/16) + i, column lane%16
     __device__ static inline int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+    // LDS position of tile row r such that the rows of one lane are adjacent
+    __device__ static inline int pos(int r) { return r; }
     __device__ static inline float bcast(float v, int src) {
         return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
     }
@@ -362,6 +388,8 @@ struct MfmaTile<double> {
     }
     // FP64: element i of a lane sits at row lane/16 + 4*i, column lane%16
     __device__ static inline int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+    // LDS position of tile row r such that the rows of one lane (r = g + 4 i) are adjacent
+    __device__ static inline int pos(int r) { return 4 * (r & 3) + (r >> 2); }
     __device__ static inline double bcast(double v, int src) {
         const long long b = __double_as_longlong(v);
         const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
@@ -388,9 +416,19 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     using acc_t = typename MT::acc;
     constexpr int NT = 4, R = MFMA_WIN;
     constexpr int EPL = 2;                  // slot entries a lane carries (E <= 4 * EPL)
-    __shared__ T pan[R][17];
-    __shared__ T nrow[16][R + 1];
+    // LDS: panT (column-major panel, accumulator -> row-per-lane), pan (row-major factored
+    // panel, -> MFMA operands; reused column-major by the backward sweep), nrowT (the
+    // tile-row entering the window, column-major with rows permuted so that the four
+    // accumulator rows of a lane are adjacent), vec (shift of the right-hand side)
+    // (strides keep 16-byte alignment and spread lanes over banks; the FP64 sizes keep a
+    // workgroup under 20 KB so that eight fit in one compute unit's LDS)
+    constexpr int PS = sizeof(T) == 4 ? 84 : 82, QS = sizeof(T) == 4 ? 20 : 18;
+    static_assert(16 * PS >= R * QS, "pan aliases panT");
+    __shared__ __align__(16) T panT[16][PS];
+    __shared__ __align__(16) T nrowT[R][QS];
+    T (*pan)[QS] = reinterpret_cast<T (*)[QS]>(&panT[0][0]);   // free once a[] is read
     __shared__ T vec[R];
+    __shared__ T colsum[16];
     const int sys = blockIdx.x;
     const int l = sys / s;
     const int i = sys - l * s;
@@ -409,45 +447,57 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     for (int I = 0; I < NT; ++I)
 #pragma unroll
         for (int J = 0; J < NT; ++J) A[I][J] = acc_t{T(0), T(0), T(0), T(0)};
+    for (int e = lane; e < R * QS; e += 64) (&nrowT[0][0])[e] = T(0);
 
-    // fixed-slot lower entries of local row r: band offset sd (-1 = empty), (K, M) values sv
-    int pd[EPL];
-    T pv[EPL];
+    // fixed-slot lower entries of local row r: band offset sd (-1 = empty), (K, M) values sv.
+    // The loads are issued unconditionally (from a clamped index) and consumed only when
+    // the rows are placed, so that they stay in flight across a whole panel step.
+    int pdr[EPL];
+    double2 pvr[EPL];
+    bool pok[EPL];
     auto fetch = [&](const int rb) {       // entries of row rb + q for this lane's slots
         const int r = rb + q;
 #pragma unroll
         for (int u = 0; u < EPL; ++u) {
             const int e = slot0 + 4 * u;
-            pd[u] = -1;
-            pv[u] = T(0);
-            if (r < nl && e < E) {
-                const long long k = (long long)(off + r) * E + e;
-                pd[u] = sd[k];
-                const double2 v = sv[k];
-                pv[u] = (T)(v.x - lamd * v.y);
-            }
+            pok[u] = (r < nl && e < E);
+            const long long k = pok[u] ? (long long)(off + r) * E + e : 0LL;
+            pdr[u] = sd[k];
+            pvr[u] = sv[k];
         }
     };
-    // tile-row I of the window <- the fetched rows rb..rb+15, window column base cb
+    // tile-row I of the window <- the fetched rows rb..rb+15, window column base cb.
+    // Entries are scattered into the zeroed nrowT, gathered in accumulator layout, and
+    // the scattered positions are zeroed again.
+    const int qpos = MT::pos(q);
     auto place = [&](const int I, const int rb, const int cb) {
-        for (int e = lane; e < 16 * (R + 1); e += 64) (&nrow[0][0])[e] = T(0);
-        wave_sync();
         const int r = rb + q;
-        if (r < nl) {
+        int col[EPL];
 #pragma unroll
-            for (int u = 0; u < EPL; ++u)
-                if (pd[u] >= 0) nrow[q][r - pd[u] - cb] = pv[u];
-        } else if (slot0 == 0) {
-            nrow[q][r - cb] = T(1);
+        for (int u = 0; u < EPL; ++u) {
+            col[u] = -1;
+            if (r < nl) {
+                if (pok[u] && pdr[u] >= 0) col[u] = r - pdr[u] - cb;
+            } else if (u == 0 && slot0 == 0) {
+                col[u] = r - cb;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < EPL; ++u)
+            if (col[u] >= 0) nrowT[col[u]][qpos] = (r < nl) ? (T)(pvr[u].x - lamd * pvr[u].y) : T(1);
         wave_sync();
 #pragma unroll
         for (int J = 0; J < NT; ++J) {
             if (J <= I) {
+                const T* src = &nrowT[16 * J + lr][4 * lg];
 #pragma unroll
-                for (int ii = 0; ii < 4; ++ii) A[I][J][ii] = nrow[MT::row(lane, ii)][16 * J + lr];
+                for (int ii = 0; ii < 4; ++ii) A[I][J][ii] = src[ii];
             }
         }
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < EPL; ++u)
+            if (col[u] >= 0) nrowT[col[u]][qpos] = T(0);
         wave_sync();
     };
 
@@ -464,27 +514,23 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         // prefetch the tile-row entering after this panel and its right-hand side
         fetch(base + 16 * NT);
         const int rnew = base + 16 + lane;
-        const T fnew = (lane >= R - 16 && rnew < nl) ? f[rnew] : T(0);
-        // panel (tile column 0) -> one row per lane
+        const T fraw = f[min(rnew, nl - 1)];
+        // panel (tile column 0) -> one row per lane, through the column-major panT
 #pragma unroll
         for (int I = 0; I < NT; ++I)
 #pragma unroll
-            for (int ii = 0; ii < 4; ++ii) pan[16 * I + MT::row(lane, ii)][lr] = A[I][0][ii];
+            for (int ii = 0; ii < 4; ++ii) panT[lr][16 * I + MT::row(lane, ii)] = A[I][0][ii];
         wave_sync();
         T a[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] = pan[lane][c];
+        for (int c = 0; c < 16; ++c) a[c] = panT[c][lane];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const T u = a[c];
-            T dc = MT::bcast(u, c);
+            const T dc = MT::bcast(u, c);
             // a zero, tiny or non-finite pivot marks the factorisation as failed
-            if (!(fabs(dc) > T(1e-30)) || !(fabs(dc) < T(1e30))) {
-                bad = 1;
-                dc = T(1);
-            }
-            const T inv = MT::recip(dc);
-            const T lt = u * inv;
+            bad |= !(fabs(dc) > T(1e-30) && fabs(dc) < T(1e30));
+            const T lt = u * MT::recip(dc);
 #pragma unroll
             for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * MT::bcast(u, c2);
             const T yc = MT::bcast(y, c);
@@ -501,17 +547,22 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         for (int c = 0; c < 16; ++c) pan[lane][c] = a[c];
         wave_sync();
         if (lane < 16 && base + lane < nl) z[base + lane] = y * MT::recip(pan[lane][lane]);
-        // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T
+        // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T; k-step k of a lane
+        // group lg covers panel column 4 lg + k, so each lane reads 4 adjacent columns
+        T dcol[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dcol[k] = pan[4 * lg + k][4 * lg + k];
         T aop[NT][4], bop[NT][4];
 #pragma unroll
-        for (int I = 1; I < NT; ++I)
+        for (int I = 1; I < NT; ++I) {
+            const T* src = &pan[16 * I + lr][4 * lg];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int col = 4 * k + lg;
-                const T lv = pan[16 * I + lr][col];
+                const T lv = src[k];
                 bop[I][k] = lv;
-                aop[I][k] = -lv * pan[col][col];
+                aop[I][k] = -lv * dcol[k];
             }
+        }
 #pragma unroll
         for (int I = 1; I < NT; ++I)
 #pragma unroll
@@ -527,44 +578,69 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         if (P + 1 < npan) place(NT - 1, base + 16 * NT, base + 16);
         vec[lane] = y;
         wave_sync();
-        y = (lane < R - 16) ? vec[lane + 16] : fnew;
+        y = (lane < R - 16) ? vec[lane + 16] : ((rnew < nl) ? fraw : T(0));
         wave_sync();
     }
 
-    // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows
+    // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows.
+    // Two register buffers alternate: a panel is read two steps before it is used, so
+    // the loads overlap two panel steps; indices are clamped so every load is in bounds.
     T zw = T(0);
-    T an[16];
-    T zn = T(0);
-    {
-        const int P = npan - 1;
-        const T* Lpan = Lp + (long long)P * (R * 16) + lane;
+    T (*bt)[PS] = panT;                     // column-major panel copy
+    T bufA[16], bufB[16];
+    T zA, zB;
+    auto load_panel = [&](const int P, T (&dst)[16], T& zdst) {
+        const int Pc = max(P, 0);
+        const T* Lpan = Lp + (long long)Pc * (R * 16) + lane;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) an[c] = Lpan[c * R];
-        zn = (lane < 16 && 16 * P + lane < nl) ? z[16 * P + lane] : T(0);
-    }
-    for (int P = npan - 1; P >= 0; --P) {
+        for (int c = 0; c < 16; ++c) dst[c] = Lpan[c * R];
+        zdst = z[min(16 * Pc + lr, nl - 1)];
+    };
+    auto back_step = [&](const int P, T (&a)[16], T& zb) {
         const int base = 16 * P;
-        T a[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] = an[c];
-        const T zc0 = zn;
-        if (P > 0) {      // prefetch the next panel down
-            const T* Lnext = Lp + (long long)(P - 1) * (R * 16) + lane;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) an[c] = Lnext[c * R];
-            zn = (lane < 16) ? z[base - 16 + lane] : T(0);
-        }
+        const T zc0 = (lane < 16 && base + lane < nl) ? zb : T(0);
         vec[lane] = zw;
         wave_sync();
         zw = (lane >= 16) ? vec[lane - 16] : T(0);
         wave_sync();
+        // column-major copy of the panel in LDS (reusing the panel buffer): rows below
+        // the panel hold L(r, c) z_r, the 16 panel rows hold L(r, c) itself
 #pragma unroll
-        for (int c = 15; c >= 0; --c) {
-            T part = (lane > c) ? a[c] * zw : T(0);
-            part = wave_sum(part);
-            if (lane == c) zw = zc0 - part;
+        for (int c = 0; c < 16; ++c) bt[c][lane] = (lane >= 16) ? a[c] * zw : a[c];
+        wave_sync();
+        // this buffer is free again: start reading the panel two steps further down
+        load_panel(P - 2, a, zb);
+        // contributions of the 48 rows below the panel: lane (c, quarter) sums 12 rows
+        // of column c, then the four quarters are added with quad permutations
+        {
+            const int c = lane >> 2, qq = lane & 3;
+            const T* src = &bt[c][16 + 12 * qq];
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 12; ++j) acc += src[j];
+            acc = quad_sum(acc);
+            if (qq == 0) colsum[c] = acc;
         }
-        if (lane < 16 && base + lane < nl) z[base + lane] = zw;
+        T lt[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lt[r] = bt[lr][r];
+        wave_sync();
+        // unit upper triangular solve with the panel's 16 x 16 block, one row per step
+        T val = zc0 - colsum[lr];
+#pragma unroll
+        for (int r = 15; r > 0; --r) {
+            const T zr = MT::bcast(val, r);
+            if (lane < r) val -= lt[r] * zr;
+        }
+        if (lane < 16) zw = val;
+        if (lane < 16 && base + lane < nl) z[base + lane] = val;
+        wave_sync();
+    };
+    load_panel(npan - 1, bufA, zA);
+    load_panel(npan - 2, bufB, zB);
+    for (int P = npan - 1; P >= 0; P -= 2) {
+        back_step(P, bufA, zA);
+        if (P >= 1) back_step(P - 1, bufB, zB);
     }
     if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
 }
