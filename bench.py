@@ -93,6 +93,52 @@ def cpu_baseline(mesh, cfg, gpu_iters: int, sample_iters: int):
     }
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "local_band_mfma_c2_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2203_06327_amd", "csrc", "precond.hip")
+
+
+def source_hash(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def counter_traffic(config: str):
+    """HBM bytes per launch of the local solve kernel from the committed counter
+    summary: FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by the factor a plain
+    copy kernel of known size gives for the same counter.  None when the summary is
+    missing, covers another workload, or was taken on another version of the kernel
+    source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    with open(COUNTERS) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                key, val = line.split("=", 1)
+                vals[key.strip()] = val.strip()
+    try:
+        if vals.get("workload") != config or vals.get("kernel_source_sha256") != source_hash(KERNEL_SRC):
+            return None
+        fetch = float(vals["fetch_kib_per_dispatch"]) * 1024.0 * float(vals["copy_fetch_factor"])
+        write = float(vals["write_kib_per_dispatch"]) * 1024.0 * float(vals["copy_write_factor"])
+    except (KeyError, ValueError):
+        return None
+    return fetch + write
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: 512 MiB read and 512 MiB written per launch, three launches."""
+    nbytes = 512 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,7 +147,10 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true", help="skip the untimed per-phase profile solve")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of known size (for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build (use --gpus 1)",
@@ -112,6 +161,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_2203_06327_amd import binding as B
     from paper_2203_06327_amd import workloads as w
 
@@ -119,21 +171,40 @@ def main():
     k, s = cfg["k"], cfg["k"] + cfg["guard"]
     print(f"[bench] {args.config}: n={mesh.n} nnz={mesh.K.nnz} k={k}", file=sys.stderr, flush=True)
     ctx = B.Context(0)
+    # timed solves: only the local-solve phase carries HIP events (two per iteration)
     prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8, precision=B.PREC_MIXED,
-                               profile=True)
+                               profile=2)
     secs, lat, stats, lam, X_d = time_solves(prob, args.steps, args.warmup, torch, k, mesh.n)
     print(f"[bench] mixed: {secs / args.steps * 1e3:.1f} ms/solve, iterations {stats[-1]['iterations']}",
           file=sys.stderr, flush=True)
     value = k * args.steps / secs
     st = stats[-1]
+    i_local = B.PHASES.index("local")
+    local_ms = sum(x["phase_ms"][i_local] for x in stats)
+    local_n = sum(x["phase_count"][i_local] for x in stats)
+    local_avg_ms = local_ms / max(1, local_n)
+
+    # per-phase breakdown from one extra, untimed solve with every phase timed
+    ph = cnt = None
+    if not args.no_breakdown:
+        probp = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
+                                    precision=B.PREC_MIXED, profile=1)
+        _, _, stp = probp.solve(torch.empty(k, dtype=torch.float64, device="cuda"),
+                                torch.empty((mesh.n, k), dtype=torch.float64, device="cuda"), mem=B.MEM_DEVICE)
+        torch.cuda.synchronize()
+        ph = dict(zip(B.PHASES, stp["phase_ms"]))
+        cnt = dict(zip(B.PHASES, stp["phase_count"]))
+        probp.close()
 
     fp64 = None
     if not args.no_fp64:
         prob64 = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
-                                     precision=B.PREC_FP64, profile=True)
+                                     precision=B.PREC_FP64, profile=2)
         secs64, lat64, stats64, lam64, _ = time_solves(prob64, max(1, args.steps // 2), 1, torch, k, mesh.n)
         fp64 = {"value": k * len(lat64) / secs64, "ms_per_solve": 1e3 * secs64 / len(lat64),
-                "iterations": stats64[-1]["iterations"], "max_residual": stats64[-1]["max_residual"]}
+                "iterations": stats64[-1]["iterations"], "max_residual": stats64[-1]["max_residual"],
+                "local_avg_launch_ms": sum(x["phase_ms"][i_local] for x in stats64)
+                / max(1, sum(x["phase_count"][i_local] for x in stats64))}
         print(f"[bench] fp64: {fp64['ms_per_solve']:.1f} ms/solve, iterations {fp64['iterations']}",
               file=sys.stderr, flush=True)
         gpu_iters = stats64[-1]["iterations"]
@@ -141,25 +212,25 @@ def main():
     else:
         gpu_iters = st["iterations"]
 
-    # dominant kernel of the mixed solve and its roofline (HIP-event times from the library)
-    ph = dict(zip(B.PHASES, st["phase_ms"]))
-    cnt = dict(zip(B.PHASES, st["phase_count"]))
+    # dominant kernel of the mixed solve (the batched local LDL^T factor + solve) and its
+    # roofline: algorithmic flops per launch over the average launch time measured with
+    # HIP events on the library's stream inside the timed solves
     nl, bw = prob.local_sizes()
-    local_avg_ms = ph["local"] / max(1, cnt["local"])
     local_flops = local_solve_flops(nl, bw, s)
-    spmm_avg_ms = ph["spmm"] / max(1, cnt["spmm"])
-    roof_local = {"bound": "alu", "achieved": local_flops / (local_avg_ms * 1e-3) / 1e12,
-                  "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s", "traffic": None,
-                  "kernel": "local_ldlt_kernel<float>", "avg_launch_ms": local_avg_ms,
-                  "algorithmic_per_launch": local_flops}
-    roof_local["frac"] = roof_local["achieved"] / roof_local["peak"]
-    sb = spmm_bytes(mesh.n, mesh.K.nnz, s)
-    roof_spmm = {"bound": "hbm", "achieved": sb / (spmm_avg_ms * 1e-3) / 1e9, "peak": PEAK["hbm_GBs"],
-                 "unit": "GB/s", "traffic": None, "kernel": "spmm_km_kernel", "avg_launch_ms": spmm_avg_ms,
-                 "algorithmic_per_launch": sb}
-    roof_spmm["frac"] = roof_spmm["achieved"] / roof_spmm["peak"]
-    dominant = max(("local", "spmm", "coarse", "gather_scatter", "ortho", "rr", "residual"), key=lambda q: ph[q])
-    roofline = roof_local if dominant == "local" else roof_spmm
+    roofline = {"bound": "alu", "achieved": local_flops / (local_avg_ms * 1e-3) / 1e12,
+                "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s", "traffic": None,
+                "kernel": "local_band_mfma_kernel<float>", "avg_launch_ms": local_avg_ms,
+                "launches_timed": local_n, "algorithmic_per_launch": local_flops}
+    roofline["frac"] = roofline["achieved"] / roofline["peak"]
+    roofline["traffic"] = counter_traffic(args.config)
+    roof_spmm = None
+    if ph is not None:
+        spmm_avg_ms = ph["spmm"] / max(1, cnt["spmm"])
+        sb = spmm_bytes(mesh.n, mesh.K.nnz, s)
+        roof_spmm = {"bound": "hbm", "achieved": sb / (spmm_avg_ms * 1e-3) / 1e9, "peak": PEAK["hbm_GBs"],
+                     "unit": "GB/s", "kernel": "spmm_km_kernel", "avg_launch_ms": spmm_avg_ms,
+                     "algorithmic_per_launch": sb, "source": "untimed profiled solve"}
+        roof_spmm["frac"] = roof_spmm["achieved"] / roof_spmm["peak"]
 
     # correctness of the returned pairs against the paper's printed values where they exist
     check = {}
@@ -182,9 +253,8 @@ def main():
                    "subspace": "UU", "stop": "max relative residual <= 1e-8"},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "iterations": st["iterations"], "max_residual": st["max_residual"],
-        "fp64": fp64, "phase_ms_per_solve": ph, "phase_launches": cnt, "dominant_phase": dominant,
-        "roofline": roofline, "roofline_spmm": roof_spmm, "roofline_local": roof_local,
-        "cpu_baseline": cpu, **check,
+        "fp64": fp64, "phase_ms_per_solve": ph, "phase_launches": cnt,
+        "roofline": roofline, "roofline_spmm": roof_spmm, "cpu_baseline": cpu, **check,
     }
     print(json.dumps(out), flush=True)
     prob.close()

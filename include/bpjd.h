@@ -119,10 +119,11 @@ typedef struct {
     int32_t precision;          /* BPJD_PREC_* */
     int32_t n_init;             /* 0, or columns of X_init added to the coarse start (Step 1) */
     const double* X_init;       /* host, n x n_init row-major, or NULL */
-    int32_t profile;            /* 1: time every phase with HIP events (bpjd_stats.phase_ms) */
+    int32_t profile;            /* 0: off; 1: time every phase with HIP events (bpjd_stats.phase_ms);
+                                   2: time only the local-solve phase (two events per iteration) */
 } bpjd_opts;
 
-/* phases timed when bpjd_opts.profile = 1 */
+/* phases timed when bpjd_opts.profile = 1 (profile = 2: BPJD_PHASE_LOCAL only) */
 #define BPJD_PHASE_LOCAL     0  /* batched local factor + solve kernel */
 #define BPJD_PHASE_SPMM      1  /* fused K/M SpMM */
 #define BPJD_PHASE_COARSE    2  /* restriction + coarse eigenbasis apply */

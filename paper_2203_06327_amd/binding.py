@@ -164,11 +164,11 @@ def _csr(A, keep: list) -> Csr:
 
 def make_opts(k: int, guard: int = 0, tol: float = 1e-8, max_iter: int = 500, stop_rule: int = STOP_RESIDUAL,
               subspace: int = SUBSPACE_UU, precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None,
-              keep: Optional[list] = None, profile: bool = False) -> Opts:
+              keep: Optional[list] = None, profile: int = 0) -> Opts:
     o = Opts()
     lib().bpjd_opts_default(C.byref(o), k)
     o.guard, o.tol, o.max_iter, o.stop_rule, o.subspace, o.precision = guard, tol, max_iter, stop_rule, subspace, precision
-    o.profile = 1 if profile else 0
+    o.profile = int(profile)
     if X_init is not None:
         Xi = np.ascontiguousarray(X_init, dtype=np.float64)
         if keep is not None:
@@ -183,7 +183,7 @@ class Problem:
 
     def __init__(self, ctx: Context, K, M, *, dd=None, geom=None, k: int, guard: int = 0, tol: float = 1e-8,
                  max_iter: int = 500, stop_rule: int = STOP_RESIDUAL, subspace: int = SUBSPACE_UU,
-                 precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None, profile: bool = False):
+                 precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None, profile: int = 0):
         keep: list = []
         Kc, Mc = _csr(K, keep), _csr(M, keep)
         opts = make_opts(k, guard, tol, max_iter, stop_rule, subspace, precision, X_init, keep, profile)

@@ -251,6 +251,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
         return fail(BPJD_ERR_ARG, "unknown subspace choice");
     if (opts->precision != BPJD_PREC_FP64 && opts->precision != BPJD_PREC_MIXED)
         return fail(BPJD_ERR_ARG, "unknown precision");
+    if (opts->profile < 0 || opts->profile > 2) return fail(BPJD_ERR_ARG, "profile must be 0, 1 or 2");
     if (!(opts->tol > 0.0) || opts->max_iter < 0) return fail(BPJD_ERR_ARG, "bad tol or max_iter");
 
     // coverage and local orderings (ascending global index)
@@ -488,6 +489,7 @@ static inline double* colp(double* base, int c) { return base + c; }
 // every outer iteration.
 struct PhaseTimer {
     hipStream_t st = nullptr;
+    unsigned mask = ~0u;           // phases that are timed
     std::vector<hipEvent_t> ev;
     std::vector<int> phase;
     size_t used = 0;
@@ -498,6 +500,7 @@ struct PhaseTimer {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
     void begin(int ph) {
+        if (!(mask & (1u << ph))) return;
         if (used + 2 > ev.size()) {
             for (int i = 0; i < 32; ++i) {
                 hipEvent_t e;
@@ -685,6 +688,7 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
     BPJD_HIP(hipEventCreate(&e2));
     PhaseTimer timer;
     timer.st = st;
+    if (p->opts.profile == 2) timer.mask = 1u << BPJD_PHASE_LOCAL;
     PhaseTimer* T = p->opts.profile ? &timer : nullptr;
     BPJD_HIP(hipEventRecord(e0, st));
     PH_BEGIN(T, BPJD_PHASE_SETUP);

@@ -243,37 +243,47 @@ struct Triple {
 constexpr int GR_ROWS = 64;
 constexpr int GR_MAXC = 48;
 
+// Dynamic LDS: the block's A rows (GR_ROWS x (a + 1), padded against bank conflicts)
+// and C (a x b).  Thread t owns the output column t % b of rows t / b, t / b + 256 / b,
+// ... (one integer division per thread), so the result is written straight from
+// registers with row-contiguous stores and no second LDS buffer is needed.
 __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, double alpha, Triple T, int lda,
                                                         const double* __restrict__ C, double beta, int ldy) {
-    __shared__ double sA[GR_ROWS][GR_MAXC + 1];
-    __shared__ double sC[GR_MAXC * GR_MAXC];
-    __shared__ double sY[GR_ROWS][GR_MAXC + 1];
+    extern __shared__ double gr_smem[];
+    double* sA = gr_smem;                      // [GR_ROWS][a + 1]
+    double* sC = gr_smem + GR_ROWS * (a + 1);  // [a][b]
     const int t = threadIdx.x;
     const int r0 = blockIdx.x * GR_ROWS;
     const double* A = T.A[blockIdx.y];
     double* Y = T.Y[blockIdx.y];
+    const int ap = a + 1;
     for (int e = t; e < a * b; e += 256) sC[e] = C[e];
-    for (int e = t; e < GR_ROWS * a; e += 256) {
-        const int rr = e / a, p = e - rr * a;
-        const int r = r0 + rr;
-        sA[rr][p] = (r < n) ? A[(long long)r * lda + p] : 0.0;
+    {
+        const int rpp = 256 / a;               // rows per pass of the load
+        const int p = t % a, rr0 = t / a;
+        if (rr0 < rpp) {
+            for (int rr = rr0; rr < GR_ROWS; rr += rpp) {
+                const int r = r0 + rr;
+                sA[rr * ap + p] = (r < n) ? A[(long long)r * lda + p] : 0.0;
+            }
+        }
     }
     __syncthreads();
-    for (int e = t; e < GR_ROWS * b; e += 256) {
-        const int rr = e / b, q = e - rr * b;
+    const int rpp = 256 / b;
+    const int q = t % b, rr0 = t / b;
+    if (rr0 >= rpp) return;
+    for (int rr = rr0; rr < GR_ROWS; rr += rpp) {
+        const int r = r0 + rr;
+        if (r >= n) break;
+        const double* arow = sA + rr * ap;
         double acc = 0.0;
-        for (int p = 0; p < a; ++p) acc = fma(sA[rr][p], sC[p * b + q], acc);
-        sY[rr][q] = acc;
-    }
-    __syncthreads();
-    for (int e = t; e < GR_ROWS * b; e += 256) {
-        const int rr = e / b, q = e - rr * b;
-        const int r = r0 + rr;
-        if (r >= n) continue;
+        for (int k = 0; k < a; ++k) acc = fma(arow[k], sC[k * b + q], acc);
         double* y = Y + (long long)r * ldy + q;
-        *y = (beta == 0.0) ? alpha * sY[rr][q] : fma(beta, *y, alpha * sY[rr][q]);
+        *y = (beta == 0.0) ? alpha * acc : fma(beta, *y, alpha * acc);
     }
 }
+
+static size_t gemm_rows_smem(int a, int b) { return sizeof(double) * ((size_t)GR_ROWS * (a + 1) + (size_t)a * b); }
 
 void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
                       int count, int lda, const double* C, double beta, int ldy) {
@@ -282,8 +292,8 @@ void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const d
         T.A[k] = A[k];
         T.Y[k] = Y[k];
     }
-    hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), 0, st, n, a, b, alpha, T, lda,
-                       C, beta, ldy);
+    hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(a, b), st, n, a,
+                       b, alpha, T, lda, C, beta, ldy);
 }
 
 void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, int ldy, const double* C) {
@@ -292,8 +302,8 @@ void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int co
         T.A[k] = Y[k];
         T.Y[k] = Y[k];
     }
-    hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), 0, st, n, b, b, 1.0, T, ldy, C,
-                       0.0, ldy);
+    hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(b, b), st, n, b,
+                       b, 1.0, T, ldy, C, 0.0, ldy);
 }
 
 // ---------------------------------------------------------------------------

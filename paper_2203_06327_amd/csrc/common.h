@@ -117,7 +117,6 @@ void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_b
 void launch_trsm_lower(hipStream_t st, int n, int nrhs, const double* L, double* B, int ldb, bool transposeL);
 // Symmetric eigensolver (cyclic Jacobi, one workgroup): A n x n (destroyed), eigenvalues
 // ascending in w, eigenvectors as columns of V (n x n row-major). work: 2 n^2 doubles.
-void launch_jacobi_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work);
 // Symmetric eigensolver for n <= 1024 (Householder tridiagonalisation, bisection,
 // inverse iteration with re-orthogonalised clusters, back-transformation): A (n x n)
 // destroyed, eigenvalues ascending in w, eigenvectors as columns of V.

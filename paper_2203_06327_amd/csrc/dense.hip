@@ -95,16 +95,34 @@ void launch_transpose(hipStream_t st, int n, const double* A, double* AT) {
 // N/2 disjoint rotations; a sweep is N-1 rounds.  A (n x n, symmetric) and V
 // (n x n) may live in LDS or global memory.  On return A is diagonal to
 // working precision and A_in = V diag(A) V^T.
-__device__ void jacobi_core(int n, double* A, double* V, double* cs, int* pr, double* red) {
+// Cyclic Jacobi on the symmetric n x n matrix A (row stride lda, shared memory) with
+// the round-robin ordering: each round rotates n/2 disjoint (p, q) pairs at once.
+// Threshold variant: a rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|); a
+// sweep without rotations ends the iteration (relative accuracy of every eigenvalue).
+// V (stride ldv) receives the eigenvectors as columns.  Thread t owns pairs
+// k0, k0 + kstep, ... and columns j0, j0 + jstep, ... (one integer division per
+// thread), so the inner loops carry no index arithmetic beyond additions.
+__device__ void jacobi_core(int n, double* A, int lda, double* V, int ldv, double* cs, int* pr) {
     __shared__ int rotated;
     const int t = threadIdx.x, bd = blockDim.x;
     const int N = n + (n & 1);
     const int half = N / 2;
-    (void)red;
-    for (long long e = t; e < (long long)n * n; e += bd) V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+    int k0, kstep, j0, jstep;
+    if (n <= bd) {
+        k0 = t / n;
+        kstep = bd / n;
+        j0 = t - k0 * n;
+        jstep = n;
+    } else {
+        k0 = 0;
+        kstep = 1;
+        j0 = t;
+        jstep = bd;
+    }
+    if (k0 >= kstep) k0 = half;                 // idle thread
+    for (int i = 0; i < n; ++i)
+        for (int j = t; j < n; j += bd) V[i * ldv + j] = (i == j) ? 1.0 : 0.0;
     __syncthreads();
-    // Threshold Jacobi: a rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|); a
-    // sweep without rotations ends the iteration (relative accuracy of every eigenvalue).
     for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
         if (t == 0) rotated = 0;
         __syncthreads();
@@ -115,68 +133,63 @@ __device__ void jacobi_core(int n, double* A, double* V, double* cs, int* pr, do
                     p = r;
                     q = N - 1;
                 } else {
-                    p = (r + k) % (N - 1);
-                    q = (r - k + N - 1) % (N - 1);
+                    p = r + k;
+                    if (p >= N - 1) p -= N - 1;
+                    q = r - k;
+                    if (q < 0) q += N - 1;
                 }
                 if (p > q) {
                     const int tmp = p;
                     p = q;
                     q = tmp;
                 }
-                double c = 1.0, s = 0.0;
+                double c = 1.0, sn = 0.0;
                 if (q < n) {
-                    const double apq = A[(long long)p * n + q];
-                    const double app = A[(long long)p * n + p], aqq = A[(long long)q * n + q];
+                    const double apq = A[p * lda + q];
+                    const double app = A[p * lda + p], aqq = A[q * lda + q];
                     if (fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq)) && apq != 0.0) {
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
+                        sn = tt * c;
                         rotated = 1;
                     }
                 }
                 cs[2 * k] = c;
-                cs[2 * k + 1] = s;
+                cs[2 * k + 1] = sn;
                 pr[2 * k] = p;
                 pr[2 * k + 1] = q;
             }
             __syncthreads();
             // rows p, q of A
-            for (long long e = t; e < (long long)half * n; e += bd) {
-                const int k = (int)(e / n), j = (int)(e % n);
-                const double s = cs[2 * k + 1];
+            for (int k = k0; k < half; k += kstep) {
+                const double sn = cs[2 * k + 1];
                 const int q = pr[2 * k + 1];
-                if (s == 0.0 || q >= n) continue;
+                if (sn == 0.0 || q >= n) continue;
                 const double c = cs[2 * k];
                 const int p = pr[2 * k];
-                const double apj = A[(long long)p * n + j], aqj = A[(long long)q * n + j];
-                A[(long long)p * n + j] = c * apj - s * aqj;
-                A[(long long)q * n + j] = s * apj + c * aqj;
+                for (int j = j0; j < n; j += jstep) {
+                    const double apj = A[p * lda + j], aqj = A[q * lda + j];
+                    A[p * lda + j] = c * apj - sn * aqj;
+                    A[q * lda + j] = sn * apj + c * aqj;
+                }
             }
             __syncthreads();
-            // columns p, q of A and of V
-            for (long long e = t; e < (long long)half * n; e += bd) {
-                const int k = (int)(e / n), i = (int)(e % n);
-                const double s = cs[2 * k + 1];
+            // columns p, q of A and of V; the rotation annihilates a_pq exactly, so the
+            // rounding residue at (p, q) and (q, p) is replaced by zero
+            for (int k = k0; k < half; k += kstep) {
+                const double sn = cs[2 * k + 1];
                 const int q = pr[2 * k + 1];
-                if (s == 0.0 || q >= n) continue;
+                if (sn == 0.0 || q >= n) continue;
                 const double c = cs[2 * k];
                 const int p = pr[2 * k];
-                const double aip = A[(long long)i * n + p], aiq = A[(long long)i * n + q];
-                A[(long long)i * n + p] = c * aip - s * aiq;
-                A[(long long)i * n + q] = s * aip + c * aiq;
-                const double vip = V[(long long)i * n + p], viq = V[(long long)i * n + q];
-                V[(long long)i * n + p] = c * vip - s * viq;
-                V[(long long)i * n + q] = s * vip + c * viq;
-            }
-            __syncthreads();
-            // the rotation annihilates a_pq exactly; drop the rounding residue
-            for (int k = t; k < half; k += bd) {
-                const int q = pr[2 * k + 1];
-                if (cs[2 * k + 1] != 0.0 && q < n) {
-                    const int p = pr[2 * k];
-                    A[(long long)p * n + q] = 0.0;
-                    A[(long long)q * n + p] = 0.0;
+                for (int i = j0; i < n; i += jstep) {
+                    const double aip = A[i * lda + p], aiq = A[i * lda + q];
+                    A[i * lda + p] = (i == q) ? 0.0 : c * aip - sn * aiq;
+                    A[i * lda + q] = (i == p) ? 0.0 : sn * aip + c * aiq;
+                    const double vip = V[i * ldv + p], viq = V[i * ldv + q];
+                    V[i * ldv + p] = c * vip - sn * viq;
+                    V[i * ldv + q] = sn * vip + c * viq;
                 }
             }
             __syncthreads();
@@ -185,35 +198,6 @@ __device__ void jacobi_core(int n, double* A, double* V, double* cs, int* pr, do
         __syncthreads();
         if (!any) break;
     }
-}
-
-// Ascending order of the diagonal of A; writes w and the permuted columns of V.
-__device__ void jacobi_sort(int n, const double* A, const double* V, double* w, double* Vout) {
-    const int t = threadIdx.x, bd = blockDim.x;
-    for (int i = t; i < n; i += bd) {
-        const double di = A[(long long)i * n + i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double dj = A[(long long)j * n + j];
-            rank += (dj < di) || (dj == di && j < i);
-        }
-        w[rank] = di;
-        for (int r = 0; r < n; ++r) Vout[(long long)r * n + rank] = V[(long long)r * n + i];
-    }
-}
-
-__global__ void jacobi_global_kernel(int n, double* __restrict__ A, double* __restrict__ w,
-                                     double* __restrict__ Vout, double* __restrict__ work) {
-    __shared__ double cs[2 * 1024];
-    __shared__ int pr[2 * 1024];
-    __shared__ double red[2 * 1024];
-    jacobi_core(n, A, work, cs, pr, red);
-    __syncthreads();
-    jacobi_sort(n, A, work, w, Vout);
-}
-
-void launch_jacobi_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work) {
-    hipLaunchKernelGGL(jacobi_global_kernel, dim3(1), dim3(1024), 0, st, n, A, w, V, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -712,29 +696,30 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz in coefficient space.  W = [X | P | T] (or [X | T]) is
 // M-orthonormal except for dropped (zero) columns, H = W^T K W (m x m, m <= 64).
-// Dropped columns (drop_in) are left out of the eigensolve and get an
-// infinite Ritz value, so they never enter the s lowest Ritz pairs.  Outputs theta (ascending) and Cfull =
-// [Q_s | C_p], where C_p spans the part of span{E_x, Q_s} orthogonal to Q_s
+// Rayleigh-Ritz coefficients on the m x m projected matrix H (m <= RR_MAX).
+// Dropped columns (drop_in) are left out of the eigensolve and get an infinite Ritz
+// value, so they never enter the s lowest Ritz pairs.  Outputs theta (ascending) and
+// Cfull = [Q_s | C_p], where C_p spans the part of span{E_x, Q_s} orthogonal to Q_s
 // (E_x = the old X coordinates), so that span{W Q_s, W C_p} = U^k + U^{k+1}.
-// A C_p direction whose norm before normalisation is below 1e-12 (the old
-// Ritz vector already lies in the new span) is dropped: zero column and
-// drop_out[s + j] = 1; drop_out[0..s) = 0.
-__global__ void rr_coef_kernel(int m, int s, int with_p, const double* __restrict__ H,
-                               const int* __restrict__ drop_in, int* __restrict__ drop_out,
-                               double* __restrict__ theta, double* __restrict__ Cfull) {
-    __shared__ double A[64 * 64];
-    __shared__ double V[64 * 64];
-    __shared__ double Q[64 * 64];
-    __shared__ double cs[128];
-    __shared__ int pr[128];
-    __shared__ double red[512];
-    __shared__ double wv[64];
-    __shared__ double nrm;
-    __shared__ int keep_idx[64];
+// Because Q is orthogonal, (I - Q_s Q_s^T) e_j = Q_{>s} g_j with g_j = (row j of
+// Q_{>s})^T, so C_p = Q_{>s} orth(g_0 .. g_{s-1}); a direction whose norm after two
+// Gram-Schmidt passes is below 1e-12 (the old Ritz vector already lies in the new
+// span) is dropped: zero column and drop_out[s + j] = 1; drop_out[0..s) = 0.
+constexpr int RR_MAX = 48;
+__global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, const double* __restrict__ H,
+                                                      const int* __restrict__ drop_in, int* __restrict__ drop_out,
+                                                      double* __restrict__ theta, double* __restrict__ Cfull) {
+    constexpr int LD = RR_MAX + 1;
+    __shared__ double A[RR_MAX * LD];
+    __shared__ double V[RR_MAX * LD];
+    __shared__ double Q[RR_MAX * LD];
+    __shared__ double cs[RR_MAX];
+    __shared__ int pr[RR_MAX];
+    __shared__ double wv[RR_MAX];
+    __shared__ double red[RR_MAX];
+    __shared__ int keep_idx[RR_MAX];
     __shared__ int mk;
     const int t = threadIdx.x, bd = blockDim.x;
-    // Dropped (zero) columns are removed before the eigensolve and come back as
-    // unit vectors with an infinite Ritz value after the kept pairs.
     if (t == 0) {
         int c = 0;
         for (int i = 0; i < m; ++i)
@@ -743,83 +728,88 @@ __global__ void rr_coef_kernel(int m, int s, int with_p, const double* __restric
     }
     __syncthreads();
     const int nk = mk;
-    for (int e = t; e < nk * nk; e += bd) {
-        const int i = keep_idx[e / nk], j = keep_idx[e % nk];
-        A[e] = 0.5 * (H[i * m + j] + H[j * m + i]);
-    }
+    for (int i = 0; i < nk; ++i)
+        for (int j = t; j < nk; j += bd) {
+            const int gi = keep_idx[i], gj = keep_idx[j];
+            A[i * LD + j] = 0.5 * (H[gi * m + gj] + H[gj * m + gi]);
+        }
     __syncthreads();
-    jacobi_core(nk, A, V, cs, pr, red);
+    if (nk > 0) jacobi_core(nk, A, LD, V, LD, cs, pr);
     __syncthreads();
-    jacobi_sort(nk, A, V, wv, Q);          // Q: nk x nk, stride nk
+    // ascending order of the kept Ritz values; Q (m x m) = eigenvectors placed back at the
+    // kept coordinates, followed by unit vectors (infinite value) for the dropped ones
+    for (int e = t; e < m * LD; e += bd) Q[e] = 0.0;
     __syncthreads();
-    for (int e = t; e < m * m; e += bd) V[e] = 0.0;
-    __syncthreads();
-    for (int e = t; e < nk * nk; e += bd) {
-        const int r = e / nk, c = e % nk;
-        V[keep_idx[r] * m + c] = Q[e];
+    for (int i = t; i < nk; i += bd) {
+        const double di = A[i * LD + i];
+        int rank = 0;
+        for (int j = 0; j < nk; ++j) {
+            const double dj = A[j * LD + j];
+            rank += (dj < di) || (dj == di && j < i);
+        }
+        wv[rank] = di;
+        for (int r = 0; r < nk; ++r) Q[keep_idx[r] * LD + rank] = V[r * LD + i];
     }
     if (t == 0) {
         int c = nk;
         for (int i = 0; i < m; ++i)
             if (drop_in[i]) {
-                V[i * m + c] = 1.0;
+                Q[i * LD + c] = 1.0;
                 wv[c] = INFINITY;
                 ++c;
             }
     }
     __syncthreads();
-    for (int e = t; e < m * m; e += bd) Q[e] = V[e];
-    __syncthreads();
     for (int i = t; i < m; i += bd) theta[i] = wv[i];
     const int cw = with_p ? 2 * s : s;
-    for (int e = t; e < m * s; e += bd) {
-        const int r = e / s, j = e % s;
-        Cfull[r * cw + j] = Q[r * m + j];
-    }
+    for (int r = 0; r < m; ++r)
+        for (int j = t; j < s; j += bd) Cfull[r * cw + j] = Q[r * LD + j];
     for (int j = t; j < cw; j += bd) drop_out[j] = 0;
     if (!with_p) return;
-    // C_p columns: b_j = sum_{k >= s} Q[:,k] Q[j,k] = (I - Q_s Q_s^T) e_j, orthogonalised
-    // (two classical Gram-Schmidt passes) against Q_s and the previous C_p columns.
-    double* Cp = V;   // reuse: m x s, row-major
+    // G (stored in A, (m - s) x s, stride LD): column j = g_j, then orthonormalised in
+    // place column by column with two classical Gram-Schmidt passes
+    const int mg = m - s;
+    for (int e = t; e < mg * s; e += bd) {
+        const int k = e / s, j = e - k * s;
+        A[k * LD + j] = Q[j * LD + s + k];
+    }
     __syncthreads();
     for (int j = 0; j < s; ++j) {
-        for (int r = t; r < m; r += bd) {
-            double acc = 0.0;
-            for (int k = s; k < m; ++k) acc += Q[r * m + k] * Q[j * m + k];
-            A[r] = acc;
-        }
-        __syncthreads();
         for (int pass = 0; pass < 2; ++pass) {
-            for (int q = t; q < s + j; q += bd) {
+            for (int q = t; q < j; q += bd) {
                 double acc = 0.0;
-                for (int r = 0; r < m; ++r) acc += A[r] * (q < s ? Q[r * m + q] : Cp[r * s + (q - s)]);
+                for (int k = 0; k < mg; ++k) acc = fma(A[k * LD + q], A[k * LD + j], acc);
                 red[q] = acc;
             }
             __syncthreads();
-            for (int r = t; r < m; r += bd) {
-                double v = A[r];
-                for (int q = 0; q < s + j; ++q) v -= red[q] * (q < s ? Q[r * m + q] : Cp[r * s + (q - s)]);
-                A[64 + r] = v;
+            for (int k = t; k < mg; k += bd) {
+                double v = A[k * LD + j];
+                for (int q = 0; q < j; ++q) v -= red[q] * A[k * LD + q];
+                A[k * LD + j] = v;
             }
             __syncthreads();
-            for (int r = t; r < m; r += bd) A[r] = A[64 + r];
-            __syncthreads();
         }
-        if (t == 0) {
+        if (t < 64) {
             double acc = 0.0;
-            for (int r = 0; r < m; ++r) acc += A[r] * A[r];
-            nrm = sqrt(acc);
+            for (int k = t; k < mg; k += 64) acc = fma(A[k * LD + j], A[k * LD + j], acc);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (t == 0) red[RR_MAX - 1] = sqrt(acc);
         }
         __syncthreads();
+        const double nrm = red[RR_MAX - 1];
         const bool keep = nrm > 1e-12;
         const double inv = keep ? 1.0 / nrm : 0.0;
-        for (int r = t; r < m; r += bd) Cp[r * s + j] = A[r] * inv;
+        for (int k = t; k < mg; k += bd) A[k * LD + j] *= inv;
         if (t == 0) drop_out[s + j] = keep ? 0 : 1;
         __syncthreads();
     }
+    // C_p = Q_{>s} G
     for (int e = t; e < m * s; e += bd) {
-        const int r = e / s, j = e % s;
-        Cfull[r * cw + s + j] = Cp[r * s + j];
+        const int r = e / s, j = e - r * s;
+        double acc = 0.0;
+        for (int k = 0; k < mg; ++k) acc = fma(Q[r * LD + s + k], A[k * LD + j], acc);
+        Cfull[r * cw + s + j] = acc;
     }
 }
 

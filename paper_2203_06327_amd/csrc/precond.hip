@@ -333,7 +333,10 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
 // in issue order, so exchanging data through LDS only needs the compiler not to
 // reorder them (a wave barrier), not a workgroup barrier with its memory fence
 // (which would wait for the outstanding global loads and stores).
-__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+__device__ inline void wave_sync() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);   // no compiler reordering of memory accesses
+    __builtin_amdgcn_wave_barrier();
+}
 
 // sum over the four lanes of a quad (lanes 4j .. 4j+3) with DPP quad permutations
 __device__ inline float quad_sum(float v) {
