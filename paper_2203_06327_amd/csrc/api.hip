@@ -435,9 +435,9 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(alloc_dev(p, &p->Y, nH2));
     chk(alloc_dev(p, &p->jwork, nH2));
     chk(alloc_dev(p, &p->lamH, nH));
-    chk(alloc_dev(p, &p->esmall, 3 * (size_t)nH));
+    chk(alloc_dev(p, &p->esmall, 4 * (size_t)nH));
     chk(alloc_dev(p, &p->YT, nH2));
-    chk(alloc_dev(p, &p->escratch, std::max(5 * nH2, (size_t)32 * nH)));
+    chk(alloc_dev(p, &p->escratch, 8 * nH2));
     const size_t blk = (size_t)n * 3 * s;
     for (int b = 0; b < 2; ++b) {
         chk(alloc_dev(p, &p->W[b], blk));
@@ -552,13 +552,17 @@ static void coarse_setup(bpjd_problem* p) {
     if (p->slotE) launch_extract_local(st, p->sumN, p->slotE, p->lptr, p->ldd, p->lpos, p->km, p->sd, p->sv);
     launch_galerkin(st, p->n, nH, p->rowptr, p->col, p->km, p->Pptr, p->Pcol, p->Pval, p->PTptr, p->PTcol, p->PTval,
                     p->kpptr, p->kpcol, p->kpval, p->khptr, p->khcol, p->nnzKH, p->KH, p->MH);
+    // K_H y = lambda M_H y  ->  C z = lambda z with C = L^{-1} K_H L^{-T}, y = L^{-T} z
+    const size_t nH2 = (size_t)nH * nH;
+    double* E0 = p->escratch;                  // L^{-1} K_H, then the eigenvectors z
+    double* E1 = p->escratch + nH2;            // Householder reflectors
+    double* E2 = p->escratch + 2 * nH2;        // inverse-iteration scratch (6 nH^2)
     launch_cholesky(st, nH, p->MH, p->status, STATUS_COARSE_NOT_SPD);              // MH <- L
-    launch_copy_cols(st, nH, nH, p->KH, nH, p->Ccoarse, nH);
-    launch_trsm_lower(st, nH, nH, p->MH, p->Ccoarse, nH, false);                    // L^{-1} K_H
-    launch_transpose(st, nH, p->Ccoarse, p->jwork);                                 // K_H L^{-T}
-    launch_trsm_lower(st, nH, nH, p->MH, p->jwork, nH, false);                      // L^{-1} K_H L^{-T}
-    launch_sym_eig(st, nH, p->jwork, p->lamH, p->Y, p->Ccoarse, p->esmall, p->escratch, p->status);  // V -> Y
-    launch_trsm_lower(st, nH, nH, p->MH, p->Y, nH, true);                           // Y = L^{-T} V
+    launch_trinv(st, nH, p->MH, p->Ccoarse);                                        // L^{-1}
+    launch_gemm_sq(st, nH, p->Ccoarse, false, p->KH, false, E0);                   // L^{-1} K_H
+    launch_gemm_sq(st, nH, E0, false, p->Ccoarse, true, p->jwork);                 // L^{-1} K_H L^{-T}
+    launch_sym_eig(st, nH, p->jwork, p->lamH, E0, E1, p->esmall, E2, p->status);   // z
+    launch_gemm_sq(st, nH, p->Ccoarse, true, E0, false, p->Y);                     // Y = L^{-T} Z
     launch_transpose(st, nH, p->Y, p->YT);
 }
 
@@ -597,17 +601,27 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, PhaseTime
 // M-orthonormalise the T block (columns ct..ct+s of buffer b) against the first
 // ct columns (classical Gram-Schmidt, two passes) and within itself
 // (Cholesky-QR, two passes).  K T and M T are updated by the same linear maps.
+// T (columns ct.. of buffer b) <- M-orthonormal basis of (I - [X P][X P]^T M) T:
+// two classical Gram-Schmidt passes against [X P] (Gram matrices (M [X P])^T T, so
+// only T itself is updated), then K T and M T by one SpMM, then two Cholesky-QR
+// passes applied to T, K T and M T alike.
 static void orthonormalize_T(bpjd_problem* p, int b, int ct, PhaseTimer* T) {
     hipStream_t st = p->ctx->stream;
     const int n = p->n, s = p->s, ld = 3 * s;
     double *W = p->W[b], *KW = p->KW[b], *MW = p->MW[b];
-    const double* src3[3] = {W, KW, MW};
+    const double* src1[1] = {W};
+    double* dst1[1] = {colp(W, ct)};
     double* dst3[3] = {colp(W, ct), colp(KW, ct), colp(MW, ct)};
     PH_BEGIN(T, BPJD_PHASE_ORTHO);
     for (int pass = 0; pass < 2 && ct > 0; ++pass) {
         launch_gram(st, n, ct, s, MW, ld, colp(W, ct), ld, p->partial, p->npart, p->csmall);
-        launch_gemm_rows(st, n, ct, s, -1.0, src3, dst3, 3, ld, p->csmall, 1.0, ld);
+        launch_gemm_rows(st, n, ct, s, -1.0, src1, dst1, 1, ld, p->csmall, 1.0, ld);
     }
+    PH_END(T);
+    PH_BEGIN(T, BPJD_PHASE_SPMM);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, colp(W, ct), ld, s, colp(KW, ct), ld, colp(MW, ct), ld);
+    PH_END(T);
+    PH_BEGIN(T, BPJD_PHASE_ORTHO);
     for (int pass = 0; pass < 2; ++pass) {
         launch_gram(st, n, s, s, colp(W, ct), ld, colp(MW, ct), ld, p->partial, p->npart, p->gsmall);
         launch_cholqr_coef(st, s, p->gsmall, p->csmall, p->dropped[b] + ct, p->status);
@@ -661,7 +675,6 @@ static int start_block(bpjd_problem* p) {
     if (p->n_init) {
         BPJD_HIP(hipMemcpyAsync(p->Z, p->X_init.data(), sizeof(double) * n * s, hipMemcpyHostToDevice, st));
         launch_copy_cols(st, n, s, p->Z, s, p->W[0] + s, ld);
-        launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0] + s, ld, s, p->KW[0] + s, ld, p->MW[0] + s, ld);
         orthonormalize_T(p, 0, s, nullptr);
         rayleigh_ritz(p, 0, 1, 2 * s, 0, nullptr);
         // result in buffer 1: move it back to buffer 0 (the iteration starts from buffer 0)
@@ -754,9 +767,6 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
         const int ct = s + S.np;
         PH_BEGIN(T, BPJD_PHASE_ORTHO);
         launch_copy_cols(st, n, s, p->Z, s, p->W[a] + ct, ld);
-        PH_END(T);
-        PH_BEGIN(T, BPJD_PHASE_SPMM);
-        launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[a] + ct, ld, s, p->KW[a] + ct, ld, p->MW[a] + ct, ld);
         PH_END(T);
         // Step 3: Rayleigh-Ritz on W = [X | P | T]
         orthonormalize_T(p, a, ct, T);

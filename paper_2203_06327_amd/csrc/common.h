@@ -114,7 +114,8 @@ void launch_scatter_f32(hipStream_t st, int n, int s, int sumN, const int* Pptr,
 // Lower Cholesky of an n x n SPD matrix (row-major, in place, lower part); status bit on failure.
 void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_bit);
 // Solve L X = B for X (L lower n x n, B n x nrhs row-major with ldb), in place in B.
-void launch_trsm_lower(hipStream_t st, int n, int nrhs, const double* L, double* B, int ldb, bool transposeL);
+void launch_trinv(hipStream_t st, int n, const double* L, double* X);
+void launch_gemm_sq(hipStream_t st, int n, const double* A, bool ta, const double* B, bool tb, double* C);
 // Symmetric eigensolver (cyclic Jacobi, one workgroup): A n x n (destroyed), eigenvalues
 // ascending in w, eigenvectors as columns of V (n x n row-major). work: 2 n^2 doubles.
 // Symmetric eigensolver for n <= 1024 (Householder tridiagonalisation, bisection,

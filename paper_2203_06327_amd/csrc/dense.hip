@@ -11,73 +11,168 @@ static constexpr int JACOBI_MAX_SWEEPS = 60;
 
 // ---------------------------------------------------------------------------
 // Right-looking Cholesky, lower, row-major, in place; upper part zeroed.
-__global__ void cholesky_kernel(int n, double* __restrict__ A, int* __restrict__ status, int status_bit) {
-    __shared__ double piv;
-    __shared__ int bad;
+// Block-wide sum with wave reductions (two barriers); every thread gets the result.
+__device__ inline double block_sum_fast(double v, double* red) {
+    const int t = threadIdx.x, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();                       // red may still be read by a previous call
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += red[w];   // same order in every thread
+    return r;
+}
+
+// Right-looking Cholesky M = L L^T in place (one workgroup): the current column is
+// staged in LDS, the trailing lower triangle is updated with a fixed (row, column)
+// map per thread, and the threads owning the next column write it to LDS as well,
+// so that no step waits on a global load.  The strict upper triangle is zeroed.
+__global__ __launch_bounds__(1024) void cholesky_kernel(int n, double* __restrict__ A, int* __restrict__ status,
+                                                        int status_bit) {
+    __shared__ double col[1024];     // column k of the trailing matrix (rows k..n-1)
+    __shared__ double lk[1024];      // column k of L
     const int t = threadIdx.x, bd = blockDim.x;
-    if (t == 0) bad = 0;
+    int bad = 0;
+    for (int i = t; i < n; i += bd) col[i] = A[i * n];
+    __syncthreads();
     for (int k = 0; k < n; ++k) {
-        if (t == 0) {
-            double d = A[(long long)k * n + k];
-            if (!(d > 0.0) || !isfinite(d)) {
-                bad = 1;
-                d = 1.0;
-            }
-            piv = sqrt(d);
-            A[(long long)k * n + k] = piv;
+        double d = col[k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            bad = 1;
+            d = 1.0;
         }
-        __syncthreads();
-        const double inv = 1.0 / piv;
-        for (int i = k + 1 + t; i < n; i += bd) A[(long long)i * n + k] *= inv;
+        const double piv = sqrt(d), inv = 1.0 / piv;
+        for (int i = k + 1 + t; i < n; i += bd) {
+            const double l = col[i] * inv;
+            lk[i] = l;
+            A[i * n + k] = l;
+        }
+        if (t == 0) A[k * n + k] = piv;
         __syncthreads();
         const int m = n - k - 1;
-        for (long long e = t; e < (long long)m * m; e += bd) {
-            const int i = k + 1 + (int)(e / m), j = k + 1 + (int)(e % m);
-            if (j <= i) A[(long long)i * n + j] -= A[(long long)i * n + k] * A[(long long)j * n + k];
+        if (m > 0) {
+            const int rs = bd / m, jj = t % m, r0 = t / m;
+            if (r0 < rs) {
+                const int j = k + 1 + jj;
+                const double lj = lk[j];
+                int ii = r0;
+                if (ii < jj) ii += ((jj - ii + rs - 1) / rs) * rs;   // first owned row on or below the diagonal
+                // batches of 8 rows: all loads are issued before the first store
+                for (; ii < m; ii += 8 * rs) {
+                    double a[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int iu = ii + u * rs;
+                        a[u] = (iu < m) ? A[(k + 1 + iu) * n + j] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int iu = ii + u * rs;
+                        if (iu < m) {
+                            const int i = k + 1 + iu;
+                            const double v = a[u] - lk[i] * lj;
+                            A[i * n + j] = v;
+                            if (jj == 0) col[i] = v;
+                        }
+                    }
+                }
+            }
         }
         __syncthreads();
     }
-    for (long long e = t; e < (long long)n * n; e += bd) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        if (j > i) A[e] = 0.0;
-    }
-    if (t == 0 && bad) atomicOr(status, status_bit);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1 + t; j < n; j += bd) A[i * n + j] = 0.0;
+    if (bad && t == 0) atomicOr(status, status_bit);
 }
 
 void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_bit) {
     hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, n, A, status, status_bit);
 }
 
-// Triangular solve with many right-hand sides, right-looking: a workgroup owns
-// 32 columns of B; for each row r it finishes x_r and updates the rows still to
-// come (coalesced along the rows of B).
-__global__ void trsm_lower_kernel(int n, int nrhs, const double* __restrict__ L, double* __restrict__ B, int ldb,
-                                  int transposeL) {
+// X = L^{-1} for lower triangular L (n x n): a workgroup owns 32 columns c0.. of X and
+// runs the forward substitution from row c0 (rows above are zero), right-looking.
+__global__ __launch_bounds__(256) void trinv_kernel(int n, const double* __restrict__ L, double* __restrict__ X) {
+    __shared__ double xr[32];
     const int c0 = blockIdx.x * 32;
-    const int t = threadIdx.x, bd = blockDim.x;
-    const int nc = min(32, nrhs - c0);
-    for (int step = 0; step < n; ++step) {
-        const int r = transposeL ? (n - 1 - step) : step;
-        const double inv = 1.0 / L[(long long)r * n + r];
-        if (t < nc) B[(long long)r * ldb + c0 + t] *= inv;
+    const int t = threadIdx.x;
+    const int c = t & 31, g = t >> 5;          // 8 row groups x 32 columns
+    const int nc = min(32, n - c0);
+    for (int i = g; i < n; i += 8)
+        if (c < nc) X[i * n + c0 + c] = (i == c0 + c) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int r = c0; r < n; ++r) {
+        if (t < nc) {
+            const double v = X[r * n + c0 + t] / L[r * n + r];
+            X[r * n + c0 + t] = v;
+            xr[t] = v;
+        }
         __syncthreads();
-        // remaining rows q: forward q > r uses L[q][r]; backward (L^T) q < r uses L[r][q]
-        const int qn = transposeL ? r : (n - 1 - r);
-        for (int e = t; e < qn * 32; e += bd) {
-            const int qi = e >> 5, c = e & 31;
-            if (c >= nc) continue;
-            const int q = transposeL ? qi : (r + 1 + qi);
-            const double l = transposeL ? L[(long long)r * n + q] : L[(long long)q * n + r];
-            B[(long long)q * ldb + c0 + c] -= l * B[(long long)r * ldb + c0 + c];
+        if (c < nc) {
+            const double x = xr[c];
+#pragma unroll 4
+            for (int q = r + 1 + g; q < n; q += 8) X[q * n + c0 + c] -= L[q * n + r] * x;
         }
         __syncthreads();
     }
 }
 
-void launch_trsm_lower(hipStream_t st, int n, int nrhs, const double* L, double* B, int ldb, bool transposeL) {
-    hipLaunchKernelGGL(trsm_lower_kernel, dim3(grid_for(nrhs, 32)), dim3(256), 0, st, n, nrhs, L, B, ldb,
-                       transposeL ? 1 : 0);
+void launch_trinv(hipStream_t st, int n, const double* L, double* X) {
+    hipLaunchKernelGGL(trinv_kernel, dim3(grid_for(n, 32)), dim3(256), 0, st, n, L, X);
 }
+
+// C = op(A) op(B) for n x n row-major matrices (op = transpose when ta / tb is set):
+// 64 x 64 output tiles, 16-deep panels staged in LDS, 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void gemm_sq_kernel(int n, const double* __restrict__ A, int ta,
+                                                      const double* __restrict__ B, int tb, double* __restrict__ C) {
+    __shared__ double As[16][64 + 1];     // As[kk][i] = op(A)[i0 + i][k0 + kk]
+    __shared__ double Bs[16][64 + 1];     // Bs[kk][j] = op(B)[k0 + kk][j0 + j]
+    const int t = threadIdx.x;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int ti = t >> 4, tj = t & 15;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        for (int e = t; e < 16 * 64; e += 256) {
+            // op(A)[i][k] = ta ? A[k][i] : A[i][k]; loads run along the contiguous index
+            int i, kk;
+            if (ta) { kk = e >> 6; i = e & 63; } else { i = e >> 4; kk = e & 15; }
+            const int gi = i0 + i, gk = k0 + kk;
+            As[kk][i] = (gi < n && gk < n) ? (ta ? A[gk * n + gi] : A[gi * n + gk]) : 0.0;
+            int j, kb;
+            if (tb) { j = e >> 4; kb = e & 15; } else { kb = e >> 6; j = e & 63; }
+            const int gj = j0 + j, gkb = k0 + kb;
+            Bs[kb][j] = (gj < n && gkb < n) ? (tb ? B[gj * n + gkb] : B[gkb * n + gj]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[kk][ti + 16 * u];
+                b[u] = Bs[kk][tj + 16 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int gi = i0 + ti + 16 * u, gj = j0 + tj + 16 * v;
+            if (gi < n && gj < n) C[gi * n + gj] = acc[u][v];
+        }
+}
+
+void launch_gemm_sq(hipStream_t st, int n, const double* A, bool ta, const double* B, bool tb, double* C) {
+    hipLaunchKernelGGL(gemm_sq_kernel, dim3(grid_for(n, 64), grid_for(n, 64)), dim3(256), 0, st, n, A, ta ? 1 : 0, B,
+                       tb ? 1 : 0, C);
+}
+
 
 __global__ void transpose_kernel(int n, const double* __restrict__ A, double* __restrict__ AT) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,92 +304,117 @@ __device__ void jacobi_core(int n, double* A, int lda, double* V, int ldv, doubl
 // tridiag: A (n x n, full symmetric storage, row-major) is reduced in place;
 // reflector k (acting on rows k+1..n-1) is v_k with v_k[0] = 1, stored in
 // Vh[k][k+1..n) together with tau[k]; diag/off receive the tridiagonal matrix.
-__global__ void tridiag_kernel(int n, double* __restrict__ A, double* __restrict__ Vh, double* __restrict__ tau,
-                               double* __restrict__ diag, double* __restrict__ off) {
+// Householder reduction of the symmetric A (n x n, one workgroup of 1024 threads) to
+// tridiagonal form T = Q^T A Q.  Step k: reflector H_k = I - tau_k v v^T (v_0 = 1)
+// annihilating A[k+2.., k]; A22 <- H_k A22 H_k as A22 - v w^T - w v^T with
+// p = tau A22 v, w = p - (tau/2)(p^T v) v.  The column that the next step reduces is
+// kept in LDS by the threads that update it, the rank-2 update uses a fixed
+// (row, column) map per thread, and block sums take two barriers.
+// Outputs: diag, off (T), the reflectors Vh (row k = v of step k, from column k+1)
+// and tau.
+__global__ __launch_bounds__(1024) void tridiag_kernel(int n, double* __restrict__ A, double* __restrict__ Vh,
+                                                       double* __restrict__ tau, double* __restrict__ diag,
+                                                       double* __restrict__ off) {
     __shared__ double v[1024];
     __shared__ double w[1024];
+    __shared__ double col[1024];     // column k of the current matrix, rows k..n-1 (col[i] = A[k + i][k])
     __shared__ double red[1024];
-    __shared__ double sc[4];
+    __shared__ double wred[16];
     const int t = threadIdx.x, bd = blockDim.x;
+    for (int i = t; i < n; i += bd) col[i] = A[i * n];
+    __syncthreads();
     for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;
-        const double* colk = A + (long long)(k + 1) * n + k;     // x_i = A[k+1+i][k]
+        const int m = n - k - 1;                 // size of A22 (rows/cols k+1..n-1)
         double acc = 0.0;
-        for (int i = 1 + t; i < m; i += bd) {
-            const double x = colk[(long long)i * n];
-            acc += x * x;
-        }
-        red[t] = acc;
-        __syncthreads();
-        for (int o = bd / 2; o > 0; o >>= 1) {
-            if (t < o) red[t] += red[t + o];
-            __syncthreads();
+        for (int i = 2 + t; i <= m; i += bd) acc = fma(col[i], col[i], acc);   // x_i = col[1 + i], i >= 1
+        const double xn2 = block_sum_fast(acc, wred);
+        const double alpha = col[1];
+        double tk, scale, beta;
+        if (xn2 == 0.0) {
+            tk = 0.0;
+            scale = 0.0;
+            beta = alpha;
+        } else {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tk = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
         }
         if (t == 0) {
-            const double alpha = colk[0];
-            const double xn2 = red[0];
-            if (xn2 == 0.0) {
-                sc[0] = 0.0;                 // tau
-                sc[1] = 0.0;                 // scale
-                off[k] = alpha;
-            } else {
-                const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                sc[0] = (beta - alpha) / beta;
-                sc[1] = 1.0 / (alpha - beta);
-                off[k] = beta;
-            }
-            tau[k] = sc[0];
+            tau[k] = tk;
+            off[k] = beta;
+            diag[k] = col[0];
         }
-        __syncthreads();
-        const double tk = sc[0], scale = sc[1];
         for (int i = t; i < m; i += bd) {
-            const double vi = (i == 0) ? 1.0 : colk[(long long)i * n] * scale;
+            const double vi = (i == 0) ? 1.0 : col[1 + i] * scale;
             v[i] = vi;
-            Vh[(long long)k * n + k + 1 + i] = vi;
+            Vh[k * n + k + 1 + i] = vi;
         }
         __syncthreads();
-        if (tk != 0.0) {
-            // p = tau A22 v; A22 is symmetric, so column j is read by 4 threads (row
-            // quarters), coalesced across neighbouring j, then summed in a fixed order
-            {
-                const int qtr = t >> 8, jt = t & 255;
-                for (int j0 = 0; j0 < m; j0 += 256) {
-                    const int j = j0 + jt;
-                    double pj = 0.0;
-                    if (j < m) {
-                        const double* colj = A + (long long)(k + 1) * n + (k + 1) + j;
-                        for (int i = qtr; i < m; i += 4) pj = fma(colj[(long long)i * n], v[i], pj);
-                    }
-                    red[t] = pj;
-                    __syncthreads();
-                    if (qtr == 0 && j < m) w[j] = tk * (((red[jt] + red[256 + jt]) + red[512 + jt]) + red[768 + jt]);
-                    __syncthreads();
-                }
-            }
-            double pv = 0.0;
-            for (int i = t; i < m; i += bd) pv += w[i] * v[i];
-            red[t] = pv;
+        const int rs = bd / m, jj = t % m, r0 = t / m;
+        const bool owner = r0 < rs;              // thread owns column jj, rows r0, r0 + rs, ...
+        if (tk == 0.0) {
+            // no reflection: the next column is read back as is
+            if (owner && jj == 0)
+                for (int ii = r0; ii < m; ii += rs) col[ii] = A[(k + 1 + ii) * n + k + 1];
             __syncthreads();
-            for (int o = bd / 2; o > 0; o >>= 1) {
-                if (t < o) red[t] += red[t + o];
+            continue;
+        }
+        // p = tau A22 v: column j read by 4 threads (row quarters), coalesced across j
+        {
+            const int qtr = t >> 8, jt = t & 255;
+            for (int j0 = 0; j0 < m; j0 += 256) {
+                const int j = j0 + jt;
+                double pj = 0.0;
+                if (j < m) {
+                    const double* colj = A + (k + 1) * n + (k + 1) + j;
+#pragma unroll 8
+                    for (int i = qtr; i < m; i += 4) pj = fma(colj[i * n], v[i], pj);
+                }
+                red[t] = pj;
+                __syncthreads();
+                if (qtr == 0 && j < m) w[j] = tk * (((red[jt] + red[256 + jt]) + red[512 + jt]) + red[768 + jt]);
                 __syncthreads();
             }
-            const double half_tpv = 0.5 * tk * red[0];
-            __syncthreads();
-            for (int i = t; i < m; i += bd) w[i] -= half_tpv * v[i];
-            __syncthreads();
-            // A22 -= v w^T + w v^T, row by row with threads along the row
-            for (int i = 0; i < m; ++i) {
-                double* row = A + (long long)(k + 1 + i) * n + (k + 1);
-                const double vi = v[i], wi = w[i];
-                for (int j = t; j < m; j += bd) row[j] -= vi * w[j] + wi * v[j];
+        }
+        double pv = 0.0;
+        for (int i = t; i < m; i += bd) pv = fma(w[i], v[i], pv);
+        const double half_tpv = 0.5 * tk * block_sum_fast(pv, wred);
+        for (int i = t; i < m; i += bd) w[i] -= half_tpv * v[i];
+        __syncthreads();
+        // A22 -= v w^T + w v^T; the owners of column 0 of A22 keep it for the next step
+        if (owner) {
+            const int j = k + 1 + jj;
+            const double vj = v[jj], wj = w[jj];
+            // batches of 8 rows: all loads are issued before the first store
+            for (int ii = r0; ii < m; ii += 8 * rs) {
+                double a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int iu = ii + u * rs;
+                    a[u] = (iu < m) ? A[(k + 1 + iu) * n + j] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int iu = ii + u * rs;
+                    if (iu < m) {
+                        const double val = a[u] - (v[iu] * wj + w[iu] * vj);
+                        A[(k + 1 + iu) * n + j] = val;
+                        if (jj == 0) col[iu] = val;
+                    }
+                }
             }
         }
         __syncthreads();
     }
-    for (int i = t; i < n; i += bd) diag[i] = A[(long long)i * n + i];
+    // the last 2 x 2 block
     if (t == 0) {
-        if (n >= 2) off[n - 2] = A[(long long)(n - 1) * n + (n - 2)];
+        if (n >= 2) {
+            diag[n - 2] = col[0];
+            off[n - 2] = col[1];
+            diag[n - 1] = A[(n - 1) * n + n - 1];
+        } else {
+            diag[0] = A[0];
+        }
         off[n - 1] = 0.0;
     }
 }
@@ -303,26 +423,40 @@ __global__ void tridiag_kernel(int n, double* __restrict__ A, double* __restrict
 // e[i] coupling i and i+1) by bisection on Sturm counts: thread j finds the
 // j-th smallest eigenvalue.  count(x) = number of negative pivots of the
 // LDL^T factorisation of T - x I.
+// The quotient e^2 / q uses the hardware reciprocal refined by two Newton steps
+// (within a few ulps of the rounded quotient): the count is that of a T whose
+// off-diagonal entries are perturbed by a few ulps, well inside the backward error
+// the recurrence has anyway; |q| >= pivmin keeps the reciprocal finite.
+__device__ inline double rcp_refined(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return r;
+}
 __device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
     int cnt = 0;
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (q < 0.0);
     for (int i = 1; i < n; ++i) {
-        q = d[i] - x - e2[i - 1] / q;
+        q = (d[i] - x) - e2[i - 1] * rcp_refined(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += (q < 0.0);
     }
     return cnt;
 }
 
-__global__ void tridiag_bisect_kernel(int n, const double* __restrict__ dg, const double* __restrict__ eg,
-                                      double* __restrict__ w) {
+// Bisection with G-way multisection: G threads per eigenvalue (G = 8, 4, 2 or 1, as
+// many as the block allows) evaluate Sturm counts at G interior points of the
+// current interval, which then shrinks by a factor G + 1 per round.  Eigenvalue j
+// (ascending) is the point where count(x) passes j.  d and e^2 live in LDS.
+__global__ __launch_bounds__(1024) void tridiag_bisect_kernel(int n, const double* __restrict__ dg,
+                                                              const double* __restrict__ eg, double* __restrict__ w) {
     __shared__ double d[1024];
     __shared__ double e2[1024];
     __shared__ double red[2][1024];
     const int t = threadIdx.x, bd = blockDim.x;
-    double lo = 1e300, hi = -1e300, emax = 0.0;
+    double lo = 1e300, hi = -1e300;
     for (int i = t; i < n; i += bd) {
         d[i] = dg[i];
         const double ei = (i + 1 < n) ? eg[i] : 0.0;
@@ -331,7 +465,6 @@ __global__ void tridiag_bisect_kernel(int n, const double* __restrict__ dg, cons
         const double er = fabs(ei);
         lo = fmin(lo, dg[i] - el - er);
         hi = fmax(hi, dg[i] + el + er);
-        emax = fmax(emax, er);
     }
     red[0][t] = lo;
     red[1][t] = hi;
@@ -346,94 +479,132 @@ __global__ void tridiag_bisect_kernel(int n, const double* __restrict__ dg, cons
     const double glo = red[0][0], ghi = red[1][0];
     const double tnorm = fmax(fabs(glo), fabs(ghi));
     const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
-    for (int j = t; j < n; j += bd) {
+    const int G = (bd >= 8 * n) ? 8 : (bd >= 4 * n) ? 4 : (bd >= 2 * n) ? 2 : 1;
+    const int lane = t & 63;
+    for (int base = 0; base < n * G; base += bd) {
+        const int tt = base + t;
+        const int j = tt / G, r = tt - (tt / G) * G;
+        const int gl = lane - r;                    // first lane of this thread's group
+        bool done = j >= n;
         double a = glo - 1e-14 * tnorm - 1e-300, b = ghi + 1e-14 * tnorm + 1e-300;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (a + b);
-            if (!(mid > a && mid < b) || (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))) break;
-            if (sturm_count(n, d, e2, mid, pivmin) > j) b = mid;
-            else a = mid;
+        for (int it = 0; it < 200 && __any(!done); ++it) {
+            if (!done && (!(0.5 * (a + b) > a && 0.5 * (a + b) < b) ||
+                          (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))))
+                done = true;
+            const double x = a + (b - a) * (double)(r + 1) / (double)(G + 1);
+            const int above = (!done && sturm_count(n, d, e2, x, pivmin) > j) ? 1 : 0;
+            // the first of the G points whose count exceeds j closes the interval
+            double na = a, nb = b;
+            bool found = false;
+            for (int q = 0; q < G; ++q) {
+                const int aq = __shfl(above, gl + q, 64);
+                const double xq = a + (b - a) * (double)(q + 1) / (double)(G + 1);
+                if (!found) {
+                    if (aq) {
+                        nb = xq;
+                        found = true;
+                    } else {
+                        na = xq;
+                    }
+                }
+            }
+            if (!done) {
+                a = na;
+                b = nb;
+            }
         }
-        w[j] = 0.5 * (a + b);
+        if (j < n && r == 0) w[j] = 0.5 * (a + b);
     }
 }
 
 // Inverse iteration for every eigenvalue (one thread each): three solves of
 // (T - lambda_j I) x = b with a partial-pivoting LU of the tridiagonal matrix
-// (U has two superdiagonals), starting from a fixed vector.  Scratch and
-// result vectors are interleaved ([i][j]) so accesses coalesce across threads.
+// (U has two superdiagonals), starting from a fixed vector.  Scratch and result
+// vectors are interleaved ([i][j]) so accesses coalesce across threads; every sweep
+// reads one array and writes another, so loads can run ahead of the stores.
 // Output: X[i][j] = component i of eigenvector j (unit 2-norm).
-__global__ void tridiag_invit_kernel(int n, const double* __restrict__ dg, const double* __restrict__ eg,
-                                     const double* __restrict__ w, double* __restrict__ X,
-                                     double* __restrict__ scratch) {
+__global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* __restrict__ dg,
+                                                           const double* __restrict__ eg,
+                                                           const double* __restrict__ w, double* __restrict__ X,
+                                                           double* __restrict__ scratch) {
+    __shared__ double d[1024];
+    __shared__ double e[1024];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        d[i] = dg[i];
+        e[i] = (i + 1 < n) ? eg[i] : 0.0;
+    }
+    __syncthreads();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    double* u0 = scratch;                        // U diagonal            [n][n]
-    double* u1 = scratch + (long long)n * n;     // U first superdiagonal
-    double* u2 = scratch + 2LL * n * n;          // U second superdiagonal
-    double* mu = scratch + 3LL * n * n;          // multipliers, sign bit of pivot flag folded into pv
-    double* pv = scratch + 4LL * n * n;          // 1.0 where rows were swapped
+    double* __restrict__ u0 = scratch;                        // 1 / U diagonal        [n][n]
+    double* __restrict__ u1 = scratch + (long long)n * n;     // U first superdiagonal
+    double* __restrict__ u2 = scratch + 2LL * n * n;          // U second superdiagonal
+    double* __restrict__ mu = scratch + 3LL * n * n;          // multipliers
+    double* __restrict__ pv = scratch + 4LL * n * n;          // 1.0 where rows were swapped
+    double* __restrict__ y = scratch + 5LL * n * n;           // forward-sweep result
 #define IDX(i) ((long long)(i) * n + j)
     const double lam = w[j];
     double tn = 0.0;
-    for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(dg[i]) + (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < n ? fabs(eg[i]) : 0.0));
+    for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + fabs(e[i]));
     const double tiny = 2.3e-16 * fmax(tn, 1e-300);
-    // factorisation P (T - lam I) = L U
-    double a0 = dg[0] - lam, a1 = (n > 1) ? eg[0] : 0.0, a2 = 0.0;   // current row (cols i, i+1, i+2)
+    // factorisation P (T - lam I) = L U; pv[i] = 1 where rows i and i+1 were swapped
+    double a0 = d[0] - lam, a1 = (n > 1) ? e[0] : 0.0, a2 = 0.0;   // current row (cols i, i+1, i+2)
     for (int i = 0; i + 1 < n; ++i) {
-        const double sub = eg[i];                                     // next row: (sub, d[i+1]-lam, e[i+1])
-        const double nd = dg[i + 1] - lam;
-        const double ne = (i + 2 < n) ? eg[i + 1] : 0.0;
-        if (fabs(sub) > fabs(a0)) {
-            const double m = a0 / sub;
-            u0[IDX(i)] = sub;
-            u1[IDX(i)] = nd;
-            u2[IDX(i)] = ne;
-            mu[IDX(i)] = m;
-            pv[IDX(i)] = 1.0;
+        const double sub = e[i];                                      // next row: (sub, d[i+1]-lam, e[i+1])
+        const double nd = d[i + 1] - lam;
+        const double ne = e[i + 1];
+        double p0, p1, p2, m;
+        const bool swap = fabs(sub) > fabs(a0);
+        if (swap) {
+            m = a0 / sub;
+            p0 = sub;
+            p1 = nd;
+            p2 = ne;
             const double na0 = a1 - m * nd, na1 = a2 - m * ne;
             a0 = na0;
             a1 = na1;
-            a2 = 0.0;
         } else {
-            const double piv = (a0 == 0.0) ? tiny : a0;
-            const double m = sub / piv;
-            u0[IDX(i)] = piv;
-            u1[IDX(i)] = a1;
-            u2[IDX(i)] = a2;
-            mu[IDX(i)] = m;
-            pv[IDX(i)] = 0.0;
+            p0 = (a0 == 0.0) ? tiny : a0;
+            m = sub / p0;
+            p1 = a1;
+            p2 = a2;
             a0 = nd - m * a1;
             a1 = ne - m * a2;
-            a2 = 0.0;
         }
+        a2 = 0.0;
+        u0[IDX(i)] = 1.0 / ((fabs(p0) < tiny) ? copysign(tiny, p0 == 0.0 ? 1.0 : p0) : p0);
+        pv[IDX(i)] = swap ? 1.0 : 0.0;
+        u1[IDX(i)] = p1;
+        u2[IDX(i)] = p2;
+        mu[IDX(i)] = m;
     }
-    u0[IDX(n - 1)] = (fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0;
-    for (int i = 0; i + 1 < n; ++i)
-        if (fabs(u0[IDX(i)]) < tiny) u0[IDX(i)] = copysign(tiny, u0[IDX(i)] == 0.0 ? 1.0 : u0[IDX(i)]);
+    u0[IDX(n - 1)] = 1.0 / ((fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0);
     // right-hand side: a fixed vector with varying entries
     for (int i = 0; i < n; ++i) X[IDX(i)] = 1.0 + 0.5 * sin(0.7 * i + 0.3 * j);
     for (int sweep = 0; sweep < 3; ++sweep) {
-        // apply the row operations: forward
+        // apply the row operations: X -> y
+        double cur = X[IDX(0)];
         for (int i = 0; i + 1 < n; ++i) {
-            double xi = X[IDX(i)], xn = X[IDX(i + 1)];
+            double nxt = X[IDX(i + 1)];
+            const double m = mu[IDX(i)];
             if (pv[IDX(i)] != 0.0) {
-                const double tmp = xi;
-                xi = xn;
-                xn = tmp;
+                const double tmp = cur;
+                cur = nxt;
+                nxt = tmp;
             }
-            X[IDX(i)] = xi;
-            X[IDX(i + 1)] = xn - mu[IDX(i)] * xi;
+            y[IDX(i)] = cur;
+            cur = nxt - m * cur;
         }
-        // back substitution with U
+        y[IDX(n - 1)] = cur;
+        // back substitution with U: y -> X
         double x1 = 0.0, x2 = 0.0;
         double nrm = 0.0;
         for (int i = n - 1; i >= 0; --i) {
-            const double xi = (X[IDX(i)] - u1[IDX(i)] * x1 - u2[IDX(i)] * x2) / u0[IDX(i)];
+            const double xi = (y[IDX(i)] - u1[IDX(i)] * x1 - u2[IDX(i)] * x2) * u0[IDX(i)];
             X[IDX(i)] = xi;
             x2 = x1;
             x1 = xi;
-            nrm += xi * xi;
+            nrm = fma(xi, xi, nrm);
         }
         const double inv = 1.0 / sqrt(nrm);
         for (int i = 0; i < n; ++i) X[IDX(i)] *= inv;
@@ -441,187 +612,198 @@ __global__ void tridiag_invit_kernel(int n, const double* __restrict__ dg, const
 #undef IDX
 }
 
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // Eigenvectors of clustered eigenvalues (consecutive gaps below 1e-3 |T|) from
-// inverse iteration span the cluster's invariant subspace but are not
-// individually accurate.  Per cluster: two Gram-Schmidt passes, then a
-// Rayleigh-Ritz step on the cluster (Jacobi on X_c^T T X_c by one thread) that
-// rotates the basis into eigenvectors and refines the eigenvalues.  One
-// workgroup, threads along the vectors; ytmp: n * 32 doubles.
-__global__ void tridiag_cluster_kernel(int n, const double* __restrict__ dg, const double* __restrict__ eg,
-                                       double* __restrict__ w, double* __restrict__ X, double* __restrict__ ytmp) {
-    __shared__ double red[1024];
-    __shared__ double Tc[32 * 32];
-    __shared__ double Qc[32 * 32];
-    const int t = threadIdx.x, bd = blockDim.x;
-    const double tn = fmax(fabs(w[0]), fabs(w[n - 1]));
+// inverse iteration span the cluster's invariant subspace but are not individually
+// accurate.  One wavefront per run of clustered eigenvalues (runs are found from the
+// unrefined values w_in, split into chunks of at most 32): two Gram-Schmidt passes,
+// then a Rayleigh-Ritz step on the chunk (Jacobi on X_c^T T X_c) that rotates the
+// basis into eigenvectors and refines the eigenvalues (written to w).  Xn: n x n
+// scratch for the rotated columns.
+__global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const double* __restrict__ dg,
+                                                              const double* __restrict__ eg,
+                                                              const double* __restrict__ w_in, double* __restrict__ w,
+                                                              double* __restrict__ X, double* __restrict__ Xn) {
+    __shared__ double Tc_all[4][32 * 33];
+    __shared__ double Qc_all[4][32 * 33];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + wave;
+    if (j >= n) return;
+    const double tn = fmax(fabs(w_in[0]), fabs(w_in[n - 1]));
     const double gap_tol = 1e-3 * tn;
-    auto block_sum = [&](double v) -> double {
-        red[t] = v;
-        __syncthreads();
-        for (int o = bd / 2; o > 0; o >>= 1) {
-            if (t < o) red[t] += red[t + o];
-            __syncthreads();
+    if (j > 0 && w_in[j] - w_in[j - 1] <= gap_tol) return;     // not the start of a run
+    int e = j + 1;
+    while (e < n && w_in[e] - w_in[e - 1] <= gap_tol) ++e;
+    if (e - j == 1) return;
+    double* Tc = Tc_all[wave];
+    double* Qc = Qc_all[wave];
+    for (int start = j; start < e; start += 32) {
+        const int cs = min(32, e - start);
+        if (cs < 2) break;
+        // two Gram-Schmidt passes over the chunk's columns
+        for (int c = start; c < start + cs; ++c) {
+            for (int pass = 0; pass < 2; ++pass)
+                for (int q = start; q < c; ++q) {
+                    double acc = 0.0;
+                    for (int i = lane; i < n; i += 64) acc = fma(X[i * n + q], X[i * n + c], acc);
+                    const double cq = wave_sum_d(acc);
+                    for (int i = lane; i < n; i += 64) X[i * n + c] -= cq * X[i * n + q];
+                }
+            double acc = 0.0;
+            for (int i = lane; i < n; i += 64) acc = fma(X[i * n + c], X[i * n + c], acc);
+            const double inv = 1.0 / sqrt(wave_sum_d(acc));
+            for (int i = lane; i < n; i += 64) X[i * n + c] *= inv;
         }
-        const double r = red[0];
-        __syncthreads();
-        return r;
-    };
-    int start = 0;
-    for (int jj = 1; jj <= n; ++jj) {
-        if (jj < n && w[jj] - w[jj - 1] <= gap_tol && jj - start < 32) continue;
-        const int cs = jj - start;
-        if (cs > 1) {
-            for (int j = start; j < jj; ++j) {
-                for (int pass = 0; pass < 2; ++pass) {
-                    for (int q = start; q < j; ++q) {
-                        double acc = 0.0;
-                        for (int i = t; i < n; i += bd) acc += X[(long long)i * n + q] * X[(long long)i * n + j];
-                        const double cq = block_sum(acc);
-                        for (int i = t; i < n; i += bd) X[(long long)i * n + j] -= cq * X[(long long)i * n + q];
-                        __syncthreads();
-                    }
-                }
+        // Tc = X_c^T T X_c
+        for (int pp = 0; pp < cs; ++pp)
+            for (int qq = pp; qq < cs; ++qq) {
+                const int cp = start + pp, cq = start + qq;
                 double acc = 0.0;
-                for (int i = t; i < n; i += bd) acc += X[(long long)i * n + j] * X[(long long)i * n + j];
-                const double inv = 1.0 / sqrt(block_sum(acc));
-                for (int i = t; i < n; i += bd) X[(long long)i * n + j] *= inv;
-                __syncthreads();
-            }
-            // y_q = T x_q, Tc = X_c^T T X_c
-            for (int q = 0; q < cs; ++q) {
-                const int jq = start + q;
-                for (int i = t; i < n; i += bd) {
-                    double v = dg[i] * X[(long long)i * n + jq];
-                    if (i > 0) v += eg[i - 1] * X[(long long)(i - 1) * n + jq];
-                    if (i + 1 < n) v += eg[i] * X[(long long)(i + 1) * n + jq];
-                    ytmp[(long long)i * 32 + q] = v;
+                for (int i = lane; i < n; i += 64) {
+                    double tx = dg[i] * X[i * n + cq];
+                    if (i > 0) tx = fma(eg[i - 1], X[(i - 1) * n + cq], tx);
+                    if (i + 1 < n) tx = fma(eg[i], X[(i + 1) * n + cq], tx);
+                    acc = fma(X[i * n + cp], tx, acc);
+                }
+                const double v = wave_sum_d(acc);
+                if (lane == 0) {
+                    Tc[pp * 33 + qq] = v;
+                    Tc[qq * 33 + pp] = v;
                 }
             }
-            __syncthreads();
-            for (int pq = 0; pq < cs * cs; ++pq) {
-                const int pp = pq / cs, qq = pq % cs;
-                if (qq < pp) continue;
-                double acc = 0.0;
-                for (int i = t; i < n; i += bd) acc += X[(long long)i * n + start + pp] * ytmp[(long long)i * 32 + qq];
-                const double v = block_sum(acc);
-                if (t == 0) {
-                    Tc[pp * cs + qq] = v;
-                    Tc[qq * cs + pp] = v;
-                }
-            }
-            __syncthreads();
-            if (t == 0) {
-                // cyclic Jacobi on the cs x cs matrix, then ascending sort of the pairs
-                for (int e = 0; e < cs * cs; ++e) Qc[e] = (e / cs == e % cs) ? 1.0 : 0.0;
-                for (int sweep = 0; sweep < 50; ++sweep) {
-                    bool rot = false;
-                    for (int pp = 0; pp < cs; ++pp)
-                        for (int qq = pp + 1; qq < cs; ++qq) {
-                            const double apq = Tc[pp * cs + qq];
-                            const double app = Tc[pp * cs + pp], aqq = Tc[qq * cs + qq];
-                            if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
-                            rot = true;
-                            const double tau = (aqq - app) / (2.0 * apq);
-                            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                            const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
-                            for (int k = 0; k < cs; ++k) {
-                                const double akp = Tc[k * cs + pp], akq = Tc[k * cs + qq];
-                                Tc[k * cs + pp] = c * akp - sn * akq;
-                                Tc[k * cs + qq] = sn * akp + c * akq;
-                            }
-                            for (int k = 0; k < cs; ++k) {
-                                const double apk = Tc[pp * cs + k], aqk = Tc[qq * cs + k];
-                                Tc[pp * cs + k] = c * apk - sn * aqk;
-                                Tc[qq * cs + k] = sn * apk + c * aqk;
-                            }
-                            Tc[pp * cs + qq] = 0.0;
-                            Tc[qq * cs + pp] = 0.0;
-                            for (int k = 0; k < cs; ++k) {
-                                const double vkp = Qc[k * cs + pp], vkq = Qc[k * cs + qq];
-                                Qc[k * cs + pp] = c * vkp - sn * vkq;
-                                Qc[k * cs + qq] = sn * vkp + c * vkq;
-                            }
-                        }
-                    if (!rot) break;
-                }
-                for (int pp = 0; pp < cs; ++pp) {          // selection sort of the pairs
-                    int best = pp;
-                    for (int qq = pp + 1; qq < cs; ++qq)
-                        if (Tc[qq * cs + qq] < Tc[best * cs + best]) best = qq;
-                    if (best != pp) {
-                        const double tmp = Tc[pp * cs + pp];
-                        Tc[pp * cs + pp] = Tc[best * cs + best];
-                        Tc[best * cs + best] = tmp;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            // cyclic Jacobi on the cs x cs matrix, then ascending sort of the pairs
+            for (int pp = 0; pp < cs; ++pp)
+                for (int qq = 0; qq < cs; ++qq) Qc[pp * 33 + qq] = (pp == qq) ? 1.0 : 0.0;
+            for (int sweep = 0; sweep < 50; ++sweep) {
+                bool rot = false;
+                for (int pp = 0; pp < cs; ++pp)
+                    for (int qq = pp + 1; qq < cs; ++qq) {
+                        const double apq = Tc[pp * 33 + qq];
+                        const double app = Tc[pp * 33 + pp], aqq = Tc[qq * 33 + qq];
+                        if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
+                        rot = true;
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
                         for (int k = 0; k < cs; ++k) {
-                            const double v = Qc[k * cs + pp];
-                            Qc[k * cs + pp] = Qc[k * cs + best];
-                            Qc[k * cs + best] = v;
+                            const double akp = Tc[k * 33 + pp], akq = Tc[k * 33 + qq];
+                            Tc[k * 33 + pp] = c * akp - sn * akq;
+                            Tc[k * 33 + qq] = sn * akp + c * akq;
+                        }
+                        for (int k = 0; k < cs; ++k) {
+                            const double apk = Tc[pp * 33 + k], aqk = Tc[qq * 33 + k];
+                            Tc[pp * 33 + k] = c * apk - sn * aqk;
+                            Tc[qq * 33 + k] = sn * apk + c * aqk;
+                        }
+                        Tc[pp * 33 + qq] = 0.0;
+                        Tc[qq * 33 + pp] = 0.0;
+                        for (int k = 0; k < cs; ++k) {
+                            const double vkp = Qc[k * 33 + pp], vkq = Qc[k * 33 + qq];
+                            Qc[k * 33 + pp] = c * vkp - sn * vkq;
+                            Qc[k * 33 + qq] = sn * vkp + c * vkq;
                         }
                     }
-                    w[start + pp] = Tc[pp * cs + pp];
-                }
+                if (!rot) break;
             }
-            __syncthreads();
-            // rotate the cluster basis: X_c <- X_c Q_c (row-wise, old values staged in ytmp)
-            for (int i = t; i < n; i += bd) {
-                for (int q = 0; q < cs; ++q) ytmp[(long long)i * 32 + q] = X[(long long)i * n + start + q];
-                for (int q = 0; q < cs; ++q) {
-                    double v = 0.0;
-                    for (int pp = 0; pp < cs; ++pp) v += ytmp[(long long)i * 32 + pp] * Qc[pp * cs + q];
-                    X[(long long)i * n + start + q] = v;
+            for (int pp = 0; pp < cs; ++pp) {          // selection sort of the pairs
+                int best = pp;
+                for (int qq = pp + 1; qq < cs; ++qq)
+                    if (Tc[qq * 33 + qq] < Tc[best * 33 + best]) best = qq;
+                if (best != pp) {
+                    const double tmp = Tc[pp * 33 + pp];
+                    Tc[pp * 33 + pp] = Tc[best * 33 + best];
+                    Tc[best * 33 + best] = tmp;
+                    for (int k = 0; k < cs; ++k) {
+                        const double v = Qc[k * 33 + pp];
+                        Qc[k * 33 + pp] = Qc[k * 33 + best];
+                        Qc[k * 33 + best] = v;
+                    }
                 }
+                w[start + pp] = Tc[pp * 33 + pp];
             }
-            __syncthreads();
         }
-        start = jj;
+        __builtin_amdgcn_wave_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // X_c <- X_c Q_c through the scratch Xn (same columns), then copied back
+        for (int i = lane; i < n; i += 64)
+            for (int q = 0; q < cs; ++q) {
+                double v = 0.0;
+                for (int pp = 0; pp < cs; ++pp) v = fma(X[i * n + start + pp], Qc[pp * 33 + q], v);
+                Xn[i * n + start + q] = v;
+            }
+        for (int i = lane; i < n; i += 64)
+            for (int q = 0; q < cs; ++q) X[i * n + start + q] = Xn[i * n + start + q];
     }
 }
 
-// Z <- H_0 H_1 ... H_{n-3} Z (eigenvectors of the reduced matrix back to the
-// original basis).  Columns are independent: each workgroup owns 8 columns and
-// applies every reflector to them (threads split the rows for the dot products).
-__global__ void tridiag_back_kernel(int n, const double* __restrict__ Vh, const double* __restrict__ tau,
-                                    double* __restrict__ Z) {
-    __shared__ double red[8][33];
-    __shared__ double dot[8];
-    const int t = threadIdx.x;
-    const int c = t & 7, rg = t >> 3;          // 8 columns x 32 row groups
-    const int j = blockIdx.x * 8 + c;
-    const bool live = j < n;
-    for (int k = n - 3; k >= 0; --k) {
-        const double tk = tau[k];
-        if (tk == 0.0) continue;
-        const double* vk = Vh + (long long)k * n;
-        double acc = 0.0;
-        if (live)
-            for (int i = k + 1 + rg; i < n; i += 32) acc = fma(vk[i], Z[(long long)i * n + j], acc);
-        red[c][rg] = acc;
-        __syncthreads();
-        if (rg == 0) {
-            double sum = 0.0;
-            for (int q = 0; q < 32; ++q) sum += red[c][q];
-            dot[c] = tk * sum;
+// Z <- H_0 H_1 ... H_{n-3} Z (eigenvectors of the reduced matrix back to the original
+// basis).  One wavefront per column: the column (n <= 1024) stays in registers, lane l
+// holding rows l, l + 64, ...; each reflector costs one coalesced read of v, a wave
+// reduction and an update.  The next reflector is read while the current one is applied.
+__global__ __launch_bounds__(256) void tridiag_back_kernel(int n, const double* __restrict__ Vh,
+                                                           const double* __restrict__ tau, double* __restrict__ Z) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    constexpr int RPL = 16;                      // rows per lane (n <= 1024)
+    double z[RPL], vc[RPL], vn[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        z[r] = (i < n) ? Z[i * n + j] : 0.0;
+    }
+    auto load_v = [&](int k, double* dst) {
+        const int kc = max(k, 0);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            dst[r] = (i > kc && i < n) ? Vh[kc * n + i] : 0.0;
         }
-        __syncthreads();
-        const double dc = dot[c];
-        if (live)
-            for (int i = k + 1 + rg; i < n; i += 32) Z[(long long)i * n + j] -= dc * vk[i];
-        __syncthreads();
+    };
+    int k = n - 3;
+    if (k >= 0) load_v(k, vn);
+    for (; k >= 0; --k) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) vc[r] = vn[r];
+        if (k > 0) load_v(k - 1, vn);
+        const double tk = tau[k];
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc = fma(vc[r], z[r], acc);
+        const double dk = tk * wave_sum_d(acc);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) z[r] = fma(-dk, vc[r], z[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < n) Z[i * n + j] = z[r];
     }
 }
 
 void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
                     double* scratch, int* status) {
-    // work: n*n (reflectors); small: 3n (tau, diag, off); scratch: 5 n*n (inverse iteration)
+    // work: n*n (reflectors); small: 4n (tau, diag, off, unrefined eigenvalues);
+    // scratch: 5 n*n (inverse iteration, then the cluster rotation)
     (void)status;
     double* tau = small;
     double* diag = small + n;
     double* off = small + 2 * n;
+    double* w0 = small + 3 * n;
     hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
-    hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(1), dim3(1024), 0, st, n, diag, off, w);
-    hipLaunchKernelGGL(tridiag_invit_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, n, diag, off, w, V, scratch);
-    hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(1), dim3(256), 0, st, n, diag, off, w, V, scratch);
-    hipLaunchKernelGGL(tridiag_back_kernel, dim3(grid_for(n, 8)), dim3(256), 0, st, n, work, tau, V);
+    hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(1), dim3(1024), 0, st, n, diag, off, w0);
+    hipLaunchKernelGGL(tridiag_invit_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, n, diag, off, w0, V, scratch);
+    (void)hipMemcpyAsync(w, w0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, diag, off, w0, w, V,
+                       scratch);
+    hipLaunchKernelGGL(tridiag_back_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, work, tau, V);
 }
 
 // ---------------------------------------------------------------------------

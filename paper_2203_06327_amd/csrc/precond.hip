@@ -165,25 +165,39 @@ __global__ void coarse_coef_kernel(int nH, int s, const double* __restrict__ YT,
     }
 }
 
-__global__ void coarse_back_kernel(int nH, int s, const double* __restrict__ Y, const double* __restrict__ Cw,
-                                   double* __restrict__ Zhat) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nH * s) return;
-    const int b = t / s, i = t % s;
+// Zhat[b][i] = sum_{j >= s} Y[b][j] Cw[j][i]: one wavefront per coarse row b reads the
+// row contiguously, keeps s (<= 16) partial sums per lane and reduces them across lanes.
+__global__ __launch_bounds__(64) void coarse_back_kernel(int nH, int s, const double* __restrict__ Y,
+                                                         const double* __restrict__ Cw, double* __restrict__ Zhat) {
+    const int b = blockIdx.x, lane = threadIdx.x;
     const double* yrow = Y + (long long)b * nH;
-    double acc = 0.0;
-    for (int j = s; j < nH; ++j) acc = fma(yrow[j], Cw[j * s + i], acc);
-    Zhat[t] = acc;
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int j = s + lane; j < nH; j += 64) {
+        const double y = yrow[j];
+        const double* c = Cw + j * s;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < s) acc[i] = fma(y, c[i], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i >= s) break;
+        double v = acc[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) Zhat[b * s + i] = v;
+    }
 }
 
 void launch_coarse_apply(hipStream_t st, int n, int nH, int s, const int* PTptr, const int* PTcol,
                          const double* PTval, const double* F, int ldf, const double* Y, const double* YT,
                          const double* lamH, const double* lam, double* G, double* Cw, double* Zhat) {
     (void)n;
-    const int work = nH * s;
     hipLaunchKernelGGL(restrict_kernel, dim3(nH), dim3(256), 0, st, nH, s, PTptr, PTcol, PTval, F, ldf, G);
     hipLaunchKernelGGL(coarse_coef_kernel, dim3(nH), dim3(64), 0, st, nH, s, YT, G, lamH, lam, Cw);
-    hipLaunchKernelGGL(coarse_back_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, nH, s, Y, Cw, Zhat);
+    hipLaunchKernelGGL(coarse_back_kernel, dim3(nH), dim3(64), 0, st, nH, s, Y, Cw, Zhat);
 }
 
 // ---------------------------------------------------------------------------
