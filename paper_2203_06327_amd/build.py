@@ -60,7 +60,8 @@ def build(verbose: bool = False) -> str:
     if errors:
         raise RuntimeError("HIP compilation failed:\n" + "\n".join(errors))
     tmp = lib_path() + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    # --no-undefined: a launcher declared but not defined fails the build, not the load
+    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,--no-undefined", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
