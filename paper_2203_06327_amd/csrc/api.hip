@@ -385,6 +385,9 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     p->Mmap = U.Mmap;
     p->n_init = opts->n_init;
     p->nnzKH = (int)khcol.size();
+    p->bwH = 0;                                    // lower bandwidth of the coarse matrices
+    for (int a = 0; a < nH; ++a)
+        for (int q = khptr[a]; q < khptr[a + 1]; ++q) p->bwH = std::max(p->bwH, a - khcol[q]);
     p->trace = std::getenv("BPJD_TRACE") != nullptr;
     p->h_bw = bw;
     p->h_nl.resize(nsub);
@@ -431,11 +434,10 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     const size_t nH2 = (size_t)nH * nH;
     chk(alloc_dev(p, &p->KH, nH2));
     chk(alloc_dev(p, &p->MH, nH2));
-    chk(alloc_dev(p, &p->Ccoarse, nH2));
     chk(alloc_dev(p, &p->Y, nH2));
     chk(alloc_dev(p, &p->jwork, nH2));
     chk(alloc_dev(p, &p->lamH, nH));
-    chk(alloc_dev(p, &p->esmall, 4 * (size_t)nH));
+    chk(alloc_dev(p, &p->esmall, 6 * (size_t)nH));
     chk(alloc_dev(p, &p->YT, nH2));
     chk(alloc_dev(p, &p->escratch, 8 * nH2));
     const size_t blk = (size_t)n * 3 * s;
@@ -552,17 +554,21 @@ static void coarse_setup(bpjd_problem* p) {
     if (p->slotE) launch_extract_local(st, p->sumN, p->slotE, p->lptr, p->ldd, p->lpos, p->km, p->sd, p->sv);
     launch_galerkin(st, p->n, nH, p->rowptr, p->col, p->km, p->Pptr, p->Pcol, p->Pval, p->PTptr, p->PTcol, p->PTval,
                     p->kpptr, p->kpcol, p->kpval, p->khptr, p->khcol, p->nnzKH, p->KH, p->MH);
-    // K_H y = lambda M_H y  ->  C z = lambda z with C = L^{-1} K_H L^{-T}, y = L^{-T} z
+    // K_H y = lambda M_H y  ->  C z = lambda z with C = L^{-1} K_H L^{-T}, y = L^{-T} z;
+    // L keeps the band of M_H, so the reductions are banded triangular solves
     const size_t nH2 = (size_t)nH * nH;
     double* E0 = p->escratch;                  // L^{-1} K_H, then the eigenvectors z
     double* E1 = p->escratch + nH2;            // Householder reflectors
     double* E2 = p->escratch + 2 * nH2;        // inverse-iteration scratch (6 nH^2)
-    launch_cholesky(st, nH, p->MH, p->status, STATUS_COARSE_NOT_SPD);              // MH <- L
-    launch_trinv(st, nH, p->MH, p->Ccoarse);                                        // L^{-1}
-    launch_gemm_sq(st, nH, p->Ccoarse, false, p->KH, false, E0);                   // L^{-1} K_H
-    launch_gemm_sq(st, nH, E0, false, p->Ccoarse, true, p->jwork);                 // L^{-1} K_H L^{-T}
+    const int bw = p->bwH;
+    launch_cholesky(st, nH, bw, p->MH, p->status, STATUS_COARSE_NOT_SPD);          // MH <- L
+    launch_copy_cols(st, nH, nH, p->KH, nH, E0, nH);
+    launch_trsm_band(st, nH, bw, nH, p->MH, E0, nH, false);                       // L^{-1} K_H
+    launch_transpose(st, nH, E0, p->jwork);                                       // K_H L^{-T}
+    launch_trsm_band(st, nH, bw, nH, p->MH, p->jwork, nH, false);                 // L^{-1} K_H L^{-T}
     launch_sym_eig(st, nH, p->jwork, p->lamH, E0, E1, p->esmall, E2, p->status);   // z
-    launch_gemm_sq(st, nH, p->Ccoarse, true, E0, false, p->Y);                     // Y = L^{-T} Z
+    launch_copy_cols(st, nH, nH, E0, nH, p->Y, nH);
+    launch_trsm_band(st, nH, bw, nH, p->MH, p->Y, nH, true);                      // Y = L^{-T} Z
     launch_transpose(st, nH, p->Y, p->YT);
 }
 

@@ -112,10 +112,9 @@ void launch_scatter_f32(hipStream_t st, int n, int s, int sumN, const int* Pptr,
 
 // ---- launchers: small dense kernels (dense.hip) -----------------------------
 // Lower Cholesky of an n x n SPD matrix (row-major, in place, lower part); status bit on failure.
-void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_bit);
+void launch_cholesky(hipStream_t st, int n, int bw, double* A, int* status, int status_bit);
 // Solve L X = B for X (L lower n x n, B n x nrhs row-major with ldb), in place in B.
-void launch_trinv(hipStream_t st, int n, const double* L, double* X);
-void launch_gemm_sq(hipStream_t st, int n, const double* A, bool ta, const double* B, bool tb, double* C);
+void launch_trsm_band(hipStream_t st, int n, int bw, int nrhs, const double* L, double* X, int ldx, bool backward);
 // Symmetric eigensolver (cyclic Jacobi, one workgroup): A n x n (destroyed), eigenvalues
 // ascending in w, eigenvectors as columns of V (n x n row-major). work: 2 n^2 doubles.
 // Symmetric eigensolver for n <= 1024 (Householder tridiagonalisation, bisection,
@@ -172,7 +171,7 @@ struct bpjd_problem {
     double2* sv = nullptr;
 
     // device numeric workspace
-    double *KH = nullptr, *MH = nullptr, *Ccoarse = nullptr, *Y = nullptr, *lamH = nullptr, *jwork = nullptr;
+    double *KH = nullptr, *MH = nullptr, *Y = nullptr, *lamH = nullptr, *jwork = nullptr;
     double* esmall = nullptr;
     double* YT = nullptr;              // coarse eigenvectors, transposed
     double* escratch = nullptr;
@@ -185,6 +184,7 @@ struct bpjd_problem {
     double* hbuf = nullptr;            // pinned host mirror for per-iteration scalars
     int npart = 0;
     int nnzKH = 0;
+    int bwH = 0;                       // lower bandwidth of K_H, M_H (and of L)
     bool trace = false;
     std::vector<int> h_nl, h_bw;     // host copies of subdomain sizes / half-bandwidths
     bool setup_done = false;

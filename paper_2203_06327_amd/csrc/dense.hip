@@ -8,6 +8,9 @@
 namespace bpjd {
 
 static constexpr int JACOBI_MAX_SWEEPS = 60;
+// up to this order the reduction to tridiagonal form runs in one workgroup; above it,
+// two launches per column spread the trailing update over all compute units
+constexpr int TRIDIAG_ONE_WG_MAX = 320;
 
 // ---------------------------------------------------------------------------
 // Right-looking Cholesky, lower, row-major, in place; upper part zeroed.
@@ -24,12 +27,14 @@ __device__ inline double block_sum_fast(double v, double* red) {
     return r;
 }
 
-// Right-looking Cholesky M = L L^T in place (one workgroup): the current column is
-// staged in LDS, the trailing lower triangle is updated with a fixed (row, column)
-// map per thread, and the threads owning the next column write it to LDS as well,
-// so that no step waits on a global load.  The strict upper triangle is zeroed.
-__global__ __launch_bounds__(1024) void cholesky_kernel(int n, double* __restrict__ A, int* __restrict__ status,
-                                                        int status_bit) {
+// Right-looking Cholesky M = L L^T in place (one workgroup) of a matrix with lower
+// bandwidth bw (entries with i - j > bw are zero; bw = n - 1 for a dense matrix): L
+// keeps that band, so step k only updates rows and columns k+1 .. k+bw.  The current
+// column is staged in LDS, the trailing window is updated with a fixed (row, column)
+// map per thread, and the threads owning the next column write it to LDS as well, so
+// that no step waits on a global load.  The strict upper triangle is zeroed.
+__global__ __launch_bounds__(1024) void cholesky_kernel(int n, int bw, double* __restrict__ A,
+                                                        int* __restrict__ status, int status_bit) {
     __shared__ double col[1024];     // column k of the trailing matrix (rows k..n-1)
     __shared__ double lk[1024];      // column k of L
     const int t = threadIdx.x, bd = blockDim.x;
@@ -37,20 +42,23 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int n, double* __restric
     for (int i = t; i < n; i += bd) col[i] = A[i * n];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
+        // rows k+1+bw.. of column k+1 enter the window only now: read them from A
+        if (k > 0 && t == 0 && k + bw < n) col[k + bw] = A[(k + bw) * n + k];
+        __syncthreads();
         double d = col[k];
         if (!(d > 0.0) || !isfinite(d)) {
             bad = 1;
             d = 1.0;
         }
         const double piv = sqrt(d), inv = 1.0 / piv;
-        for (int i = k + 1 + t; i < n; i += bd) {
+        const int m = min(n - k - 1, bw);       // rows below the diagonal inside the band
+        for (int i = k + 1 + t; i <= k + m; i += bd) {
             const double l = col[i] * inv;
             lk[i] = l;
             A[i * n + k] = l;
         }
         if (t == 0) A[k * n + k] = piv;
         __syncthreads();
-        const int m = n - k - 1;
         if (m > 0) {
             const int rs = bd / m, jj = t % m, r0 = t / m;
             if (r0 < rs) {
@@ -86,93 +94,104 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int n, double* __restric
     if (bad && t == 0) atomicOr(status, status_bit);
 }
 
-void launch_cholesky(hipStream_t st, int n, double* A, int* status, int status_bit) {
-    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, n, A, status, status_bit);
+void launch_cholesky(hipStream_t st, int n, int bw, double* A, int* status, int status_bit) {
+    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, n, bw, A, status, status_bit);
 }
 
-// X = L^{-1} for lower triangular L (n x n): a workgroup owns 32 columns c0.. of X and
-// runs the forward substitution from row c0 (rows above are zero), right-looking.
-__global__ __launch_bounds__(256) void trinv_kernel(int n, const double* __restrict__ L, double* __restrict__ X) {
-    __shared__ double xr[32];
-    const int c0 = blockIdx.x * 32;
-    const int t = threadIdx.x;
-    const int c = t & 31, g = t >> 5;          // 8 row groups x 32 columns
-    const int nc = min(32, n - c0);
-    for (int i = g; i < n; i += 8)
-        if (c < nc) X[i * n + c0 + c] = (i == c0 + c) ? 1.0 : 0.0;
-    __syncthreads();
-    for (int r = c0; r < n; ++r) {
-        if (t < nc) {
-            const double v = X[r * n + c0 + t] / L[r * n + r];
-            X[r * n + c0 + t] = v;
-            xr[t] = v;
-        }
-        __syncthreads();
-        if (c < nc) {
-            const double x = xr[c];
-#pragma unroll 4
-            for (int q = r + 1 + g; q < n; q += 8) X[q * n + c0 + c] -= L[q * n + r] * x;
-        }
-        __syncthreads();
-    }
-}
-
-void launch_trinv(hipStream_t st, int n, const double* L, double* X) {
-    hipLaunchKernelGGL(trinv_kernel, dim3(grid_for(n, 32)), dim3(256), 0, st, n, L, X);
-}
-
-// C = op(A) op(B) for n x n row-major matrices (op = transpose when ta / tb is set):
-// 64 x 64 output tiles, 16-deep panels staged in LDS, 4 x 4 outputs per thread.
-__global__ __launch_bounds__(256) void gemm_sq_kernel(int n, const double* __restrict__ A, int ta,
-                                                      const double* __restrict__ B, int tb, double* __restrict__ C) {
-    __shared__ double As[16][64 + 1];     // As[kk][i] = op(A)[i0 + i][k0 + kk]
-    __shared__ double Bs[16][64 + 1];     // Bs[kk][j] = op(B)[k0 + kk][j0 + j]
-    const int t = threadIdx.x;
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    const int ti = t >> 4, tj = t & 15;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        for (int e = t; e < 16 * 64; e += 256) {
-            // op(A)[i][k] = ta ? A[k][i] : A[i][k]; loads run along the contiguous index
-            int i, kk;
-            if (ta) { kk = e >> 6; i = e & 63; } else { i = e >> 4; kk = e & 15; }
-            const int gi = i0 + i, gk = k0 + kk;
-            As[kk][i] = (gi < n && gk < n) ? (ta ? A[gk * n + gi] : A[gi * n + gk]) : 0.0;
-            int j, kb;
-            if (tb) { j = e >> 4; kb = e & 15; } else { kb = e >> 6; j = e & 63; }
-            const int gj = j0 + j, gkb = k0 + kb;
-            Bs[kb][j] = (gj < n && gkb < n) ? (tb ? B[gj * n + gkb] : B[gkb * n + gj]) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = As[kk][ti + 16 * u];
-                b[u] = Bs[kk][tj + 16 * u];
+// Triangular solves with a banded lower triangular L (n x n, lower bandwidth bw) and
+// n_rhs right-hand sides, in place on X (row stride ldx): forward X <- L^{-1} X, or
+// backward X <- L^{-T} X.  One wavefront per 64 right-hand sides, one lane per column.
+// Narrow bands (bw < 64): per row, lane e reads band entry e of L (row r left of the
+// diagonal, or column r below it) and lane bw' the diagonal, a row ahead, together with
+// the next right-hand side; the entries are shared through LDS and the last results of
+// each lane stay in an LDS ring, so the recurrence never waits on global memory.
+// Wider bands read L and earlier results from global memory.
+template <bool NARROW>
+__global__ __launch_bounds__(64) void trsm_band_kernel(int n, int bw, int nrhs, const double* __restrict__ L,
+                                                       double* __restrict__ X, int ldx, int backward) {
+    __shared__ double lw[65];
+    __shared__ double ring[NARROW ? 64 : 1][64];
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x * 64 + lane;
+    const bool live = c < nrhs;
+    auto row_of = [&](int step) -> int { return backward ? n - 1 - step : step; };
+    auto rowcount = [&](int r) -> int { return backward ? min(bw, n - 1 - r) : min(bw, r); };
+    // global index of band entry e (0-based, away from the diagonal) of row r
+    auto lidx = [&](int r, int e) -> long long {
+        return backward ? (long long)(r + 1 + e) * n + r : (long long)r * n + (r - 1 - e);
+    };
+    if (NARROW) {
+        // the raw loads are kept and the selection is made a row later, so the loads stay
+        // in flight for a whole row
+        auto load_row = [&](int r, double& lval, bool& lok, double& bval) {
+            const int cnt = rowcount(r);
+            // one unconditional vector load per lane (index clamped onto the diagonal)
+            const long long idx = (lane < cnt) ? lidx(r, lane) : (long long)r * n + r;
+            lval = L[idx];
+            lok = lane <= cnt;
+            bval = X[(long long)r * ldx + (live ? c : 0)];
+        };
+        double pre_l = 0.0, pre_b = 0.0;
+        bool pre_ok = false;
+        if (n > 0) load_row(row_of(0), pre_l, pre_ok, pre_b);
+        for (int step = 0; step < n; ++step) {
+            const int r = row_of(step);
+            const int cnt = rowcount(r);
+            const double cur_l = pre_ok ? pre_l : 0.0, cur_b = pre_b;
+            if (step + 1 < n) load_row(row_of(step + 1), pre_l, pre_ok, pre_b);
+            lw[lane] = cur_l;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            double acc0 = cur_b, acc1 = 0.0;
+            int e = 0;
+            for (; e + 1 < cnt; e += 2) {
+                const int ja = backward ? r + 1 + e : r - 1 - e;
+                const int jb = backward ? ja + 1 : ja - 1;
+                acc0 = fma(-lw[e], ring[ja & 63][lane], acc0);
+                acc1 = fma(-lw[e + 1], ring[jb & 63][lane], acc1);
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+            if (e < cnt) {
+                const int ja = backward ? r + 1 + e : r - 1 - e;
+                acc0 = fma(-lw[e], ring[ja & 63][lane], acc0);
+            }
+            const double x = (acc0 + acc1) / lw[cnt];
+            if (live) X[(long long)r * ldx + c] = x;
+            ring[r & 63][lane] = x;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
-        __syncthreads();
+    } else {
+        if (!live) return;
+        for (int step = 0; step < n; ++step) {
+            const int r = row_of(step);
+            const int cnt = rowcount(r);
+            double acc0 = X[(long long)r * ldx + c], acc1 = 0.0;
+            int e = 0;
+            for (; e + 1 < cnt; e += 2) {
+                const int ja = backward ? r + 1 + e : r - 1 - e;
+                const int jb = backward ? ja + 1 : ja - 1;
+                acc0 = fma(-L[lidx(r, e)], X[(long long)ja * ldx + c], acc0);
+                acc1 = fma(-L[lidx(r, e + 1)], X[(long long)jb * ldx + c], acc1);
+            }
+            if (e < cnt) {
+                const int ja = backward ? r + 1 + e : r - 1 - e;
+                acc0 = fma(-L[lidx(r, e)], X[(long long)ja * ldx + c], acc0);
+            }
+            X[(long long)r * ldx + c] = (acc0 + acc1) / L[(long long)r * n + r];
+        }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int gi = i0 + ti + 16 * u, gj = j0 + tj + 16 * v;
-            if (gi < n && gj < n) C[gi * n + gj] = acc[u][v];
-        }
 }
 
-void launch_gemm_sq(hipStream_t st, int n, const double* A, bool ta, const double* B, bool tb, double* C) {
-    hipLaunchKernelGGL(gemm_sq_kernel, dim3(grid_for(n, 64), grid_for(n, 64)), dim3(256), 0, st, n, A, ta ? 1 : 0, B,
-                       tb ? 1 : 0, C);
+void launch_trsm_band(hipStream_t st, int n, int bw, int nrhs, const double* L, double* X, int ldx, bool backward) {
+    if (bw < 64)
+        hipLaunchKernelGGL(trsm_band_kernel<true>, dim3(grid_for(nrhs, 64)), dim3(64), 0, st, n, bw, nrhs, L, X, ldx,
+                           backward ? 1 : 0);
+    else
+        hipLaunchKernelGGL(trsm_band_kernel<false>, dim3(grid_for(nrhs, 64)), dim3(64), 0, st, n, bw, nrhs, L, X, ldx,
+                           backward ? 1 : 0);
 }
-
 
 __global__ void transpose_kernel(int n, const double* __restrict__ A, double* __restrict__ AT) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -419,6 +438,104 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(int n, double* __restrict
     }
 }
 
+// Householder reduction of the symmetric A (n x n) to tridiagonal form T = Q^T A Q,
+// one reflector H_k = I - tau_k v v^T (v_0 = 1) per column, with the trailing update
+// A22 <- A22 - v w^T - w v^T (p = tau A22 v, w = p - (tau/2)(p^T v) v) applied lazily:
+//   tridiag_head (one workgroup): finishes w_{k-1} from p, forms row k of the current
+//     matrix with the pending update of step k-1 applied on the fly, and builds v_k;
+//   tridiag_sweep (one wavefront per trailing row j, all compute units): applies the
+//     pending update of step k-1 to row j of A22 and forms (A22 v_k)_j.
+// A is symmetric, so rows stand for columns and every access is row-contiguous.
+// Outputs: diag, off (T), the reflectors Vh (row k = v_k, from column k+1), tau.
+// pbuf and wbuf (n each) carry A22 v_k and w_k between the two kernels.
+__global__ __launch_bounds__(1024) void tridiag_head_kernel(int n, int k, const double* __restrict__ A,
+                                                            double* __restrict__ Vh, double* __restrict__ tau,
+                                                            const double* __restrict__ pbuf,
+                                                            double* __restrict__ wbuf, double* __restrict__ diag,
+                                                            double* __restrict__ off) {
+    __shared__ double r[1024];            // row k of the current matrix, r[i] for i >= k
+    __shared__ double wred[16];
+    const int t = threadIdx.x, bd = blockDim.x;
+    if (k >= 1) {
+        // w_{k-1} = tau p - (tau/2)(tau p^T v) v over rows k..n-1
+        const int kp = k - 1;
+        const double tp = tau[kp];
+        const double* vp = Vh + (long long)kp * n;
+        double acc = 0.0;
+        for (int i = k + t; i < n; i += bd) acc = fma(tp * pbuf[i], vp[i], acc);
+        const double half_tpv = 0.5 * tp * block_sum_fast(acc, wred);
+        for (int i = k + t; i < n; i += bd) wbuf[i] = tp * pbuf[i] - half_tpv * vp[i];
+        __syncthreads();
+        for (int i = k + t; i < n; i += bd) r[i] = A[(long long)k * n + i] - (vp[k] * wbuf[i] + wbuf[k] * vp[i]);
+    } else {
+        for (int i = t; i < n; i += bd) r[i] = A[i];
+    }
+    __syncthreads();
+    if (k + 2 >= n) {                      // last 2 x 2 block (k = n - 2) or n = 1
+        if (t == 0) {
+            diag[k] = r[k];
+            if (k + 1 < n) {
+                off[k] = r[k + 1];
+                double d1 = A[(long long)(n - 1) * n + n - 1];
+                if (k >= 1) {
+                    const double* vp = Vh + (long long)(k - 1) * n;
+                    d1 -= 2.0 * vp[n - 1] * wbuf[n - 1];
+                }
+                diag[n - 1] = d1;
+            }
+            off[n - 1] = 0.0;
+        }
+        return;
+    }
+    double acc = 0.0;
+    for (int i = k + 2 + t; i < n; i += bd) acc = fma(r[i], r[i], acc);
+    const double xn2 = block_sum_fast(acc, wred);
+    const double alpha = r[k + 1];
+    double tk, scale, beta;
+    if (xn2 == 0.0) {
+        tk = 0.0;
+        scale = 0.0;
+        beta = alpha;
+    } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tk = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    if (t == 0) {
+        tau[k] = tk;
+        off[k] = beta;
+        diag[k] = r[k];
+    }
+    double* vk = Vh + (long long)k * n;
+    for (int i = k + 1 + t; i < n; i += bd) vk[i] = (i == k + 1) ? 1.0 : r[i] * scale;
+}
+
+__global__ __launch_bounds__(256) void tridiag_sweep_kernel(int n, int k, double* __restrict__ A,
+                                                            const double* __restrict__ Vh,
+                                                            const double* __restrict__ wbuf,
+                                                            double* __restrict__ pbuf) {
+    const int lane = threadIdx.x & 63;
+    const int j = k + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const double* vk = Vh + (long long)k * n;
+    double* row = A + (long long)j * n;
+    double acc = 0.0;
+    if (k >= 1) {
+        const double* vp = Vh + (long long)(k - 1) * n;
+        const double vj = vp[j], wj = wbuf[j];
+        for (int i = k + 1 + lane; i < n; i += 64) {
+            const double a = row[i] - (vj * wbuf[i] + wj * vp[i]);
+            row[i] = a;
+            acc = fma(a, vk[i], acc);
+        }
+    } else {
+        for (int i = k + 1 + lane; i < n; i += 64) acc = fma(row[i], vk[i], acc);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) pbuf[j] = acc;
+}
+
 // Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e,
 // e[i] coupling i and i+1) by bisection on Sturm counts: thread j finds the
 // j-th smallest eigenvalue.  count(x) = number of negative pivots of the
@@ -446,15 +563,17 @@ __device__ inline int sturm_count(int n, const double* d, const double* e2, doub
     return cnt;
 }
 
-// Bisection with G-way multisection: G threads per eigenvalue (G = 8, 4, 2 or 1, as
-// many as the block allows) evaluate Sturm counts at G interior points of the
-// current interval, which then shrinks by a factor G + 1 per round.  Eigenvalue j
-// (ascending) is the point where count(x) passes j.  d and e^2 live in LDS.
-__global__ __launch_bounds__(1024) void tridiag_bisect_kernel(int n, const double* __restrict__ dg,
-                                                              const double* __restrict__ eg, double* __restrict__ w) {
+// Bisection with 8-way multisection: 8 threads per eigenvalue (several workgroups)
+// evaluate Sturm counts at 8 interior points of the current interval, which then
+// shrinks by a factor 9 per round.  Eigenvalue j (ascending) is the point where
+// count(x) passes j.  Every workgroup stages d and e^2 in LDS and forms the same
+// Gershgorin interval.
+constexpr int BISECT_G = 8;
+__global__ __launch_bounds__(256) void tridiag_bisect_kernel(int n, const double* __restrict__ dg,
+                                                             const double* __restrict__ eg, double* __restrict__ w) {
     __shared__ double d[1024];
     __shared__ double e2[1024];
-    __shared__ double red[2][1024];
+    __shared__ double red[2][256];
     const int t = threadIdx.x, bd = blockDim.x;
     double lo = 1e300, hi = -1e300;
     for (int i = t; i < n; i += bd) {
@@ -479,42 +598,39 @@ __global__ __launch_bounds__(1024) void tridiag_bisect_kernel(int n, const doubl
     const double glo = red[0][0], ghi = red[1][0];
     const double tnorm = fmax(fabs(glo), fabs(ghi));
     const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
-    const int G = (bd >= 8 * n) ? 8 : (bd >= 4 * n) ? 4 : (bd >= 2 * n) ? 2 : 1;
-    const int lane = t & 63;
-    for (int base = 0; base < n * G; base += bd) {
-        const int tt = base + t;
-        const int j = tt / G, r = tt - (tt / G) * G;
-        const int gl = lane - r;                    // first lane of this thread's group
-        bool done = j >= n;
-        double a = glo - 1e-14 * tnorm - 1e-300, b = ghi + 1e-14 * tnorm + 1e-300;
-        for (int it = 0; it < 200 && __any(!done); ++it) {
-            if (!done && (!(0.5 * (a + b) > a && 0.5 * (a + b) < b) ||
-                          (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))))
-                done = true;
-            const double x = a + (b - a) * (double)(r + 1) / (double)(G + 1);
-            const int above = (!done && sturm_count(n, d, e2, x, pivmin) > j) ? 1 : 0;
-            // the first of the G points whose count exceeds j closes the interval
-            double na = a, nb = b;
-            bool found = false;
-            for (int q = 0; q < G; ++q) {
-                const int aq = __shfl(above, gl + q, 64);
-                const double xq = a + (b - a) * (double)(q + 1) / (double)(G + 1);
-                if (!found) {
-                    if (aq) {
-                        nb = xq;
-                        found = true;
-                    } else {
-                        na = xq;
-                    }
+    constexpr int G = BISECT_G;
+    const int tt = blockIdx.x * bd + t;
+    const int j = tt / G, r = tt % G;
+    const int gl = (t & 63) - r;                   // first lane of this thread's group
+    bool done = j >= n;
+    double a = glo - 1e-14 * tnorm - 1e-300, b = ghi + 1e-14 * tnorm + 1e-300;
+    for (int it = 0; it < 200 && __any(!done); ++it) {
+        if (!done && (!(0.5 * (a + b) > a && 0.5 * (a + b) < b) || (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))))
+            done = true;
+        const double x = a + (b - a) * (double)(r + 1) / (double)(G + 1);
+        const int above = (!done && sturm_count(n, d, e2, x, pivmin) > j) ? 1 : 0;
+        // the first of the G points whose count exceeds j closes the interval
+        double na = a, nb = b;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int aq = __shfl(above, gl + q, 64);
+            const double xq = a + (b - a) * (double)(q + 1) / (double)(G + 1);
+            if (!found) {
+                if (aq) {
+                    nb = xq;
+                    found = true;
+                } else {
+                    na = xq;
                 }
             }
-            if (!done) {
-                a = na;
-                b = nb;
-            }
         }
-        if (j < n && r == 0) w[j] = 0.5 * (a + b);
+        if (!done) {
+            a = na;
+            b = nb;
+        }
     }
+    if (j < n && r == 0) w[j] = 0.5 * (a + b);
 }
 
 // Inverse iteration for every eigenvalue (one thread each): three solves of
@@ -526,7 +642,9 @@ __global__ __launch_bounds__(1024) void tridiag_bisect_kernel(int n, const doubl
 __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* __restrict__ dg,
                                                            const double* __restrict__ eg,
                                                            const double* __restrict__ w, double* __restrict__ X,
-                                                           double* __restrict__ scratch) {
+                                                           double* __restrict__ u0, double* __restrict__ u1,
+                                                           double* __restrict__ u2, double* __restrict__ mu,
+                                                           double* __restrict__ pv, double* __restrict__ y) {
     __shared__ double d[1024];
     __shared__ double e[1024];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -536,12 +654,8 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
     __syncthreads();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    double* __restrict__ u0 = scratch;                        // 1 / U diagonal        [n][n]
-    double* __restrict__ u1 = scratch + (long long)n * n;     // U first superdiagonal
-    double* __restrict__ u2 = scratch + 2LL * n * n;          // U second superdiagonal
-    double* __restrict__ mu = scratch + 3LL * n * n;          // multipliers
-    double* __restrict__ pv = scratch + 4LL * n * n;          // 1.0 where rows were swapped
-    double* __restrict__ y = scratch + 5LL * n * n;           // forward-sweep result
+    // u0: 1 / U diagonal; u1, u2: U super-diagonals; mu: multipliers; pv: 1.0 where rows
+    // were swapped; y: forward-sweep result (all [n][n], interleaved over eigenvalues)
 #define IDX(i) ((long long)(i) * n + j)
     const double lam = w[j];
     double tn = 0.0;
@@ -790,16 +904,32 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(int n, const double* 
 
 void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
                     double* scratch, int* status) {
-    // work: n*n (reflectors); small: 4n (tau, diag, off, unrefined eigenvalues);
-    // scratch: 5 n*n (inverse iteration, then the cluster rotation)
+    // work: n*n (reflectors); small: 6n (tau, diag, off, unrefined eigenvalues, p, w);
+    // scratch: 6 n*n (inverse iteration, then the cluster rotation)
     (void)status;
     double* tau = small;
     double* diag = small + n;
     double* off = small + 2 * n;
     double* w0 = small + 3 * n;
-    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
-    hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(1), dim3(1024), 0, st, n, diag, off, w0);
-    hipLaunchKernelGGL(tridiag_invit_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, n, diag, off, w0, V, scratch);
+    double* pbuf = small + 4 * n;
+    double* wbuf = small + 5 * n;
+    if (n <= TRIDIAG_ONE_WG_MAX) {
+        // small matrices: one workgroup does every step (no per-column launches)
+        hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
+    } else {
+    for (int k = 0; k + 2 < n; ++k) {
+        hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, k, A, work, tau, pbuf, wbuf, diag, off);
+        hipLaunchKernelGGL(tridiag_sweep_kernel, dim3(grid_for(n - k - 1, 4)), dim3(256), 0, st, n, k, A, work, wbuf,
+                           pbuf);
+    }
+    hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, max(n - 2, 0), A, work, tau, pbuf, wbuf,
+                       diag, off);
+    }
+    hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(grid_for((long long)n * BISECT_G, 256)), dim3(256), 0, st, n, diag,
+                       off, w0);
+    const long long n2 = (long long)n * n;
+    hipLaunchKernelGGL(tridiag_invit_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, n, diag, off, w0, V, scratch,
+                       scratch + n2, scratch + 2 * n2, scratch + 3 * n2, scratch + 4 * n2, scratch + 5 * n2);
     (void)hipMemcpyAsync(w, w0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, diag, off, w0, w, V,
                        scratch);
