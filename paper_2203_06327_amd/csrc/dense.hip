@@ -1,19 +1,19 @@
-// Small dense FP64 kernels that run in a single workgroup: Cholesky,
-// triangular solves, the cyclic Jacobi symmetric eigensolver used for the
-// coarse generalized eigenproblem (Section 3, coarse spectral split) and the
-// Rayleigh-Ritz problem (Algorithm 3.1, Step 3), Cholesky-QR coefficients and
-// the coefficient-space step that keeps W^{k+1} = U^{k-1} + U^k + span{t}.
+// Small dense FP64 kernels: banded Cholesky and triangular solves, the symmetric
+// eigensolver (Householder tridiagonalisation, multisection on Sturm counts, inverse
+// iteration) used for the coarse generalized eigenproblem (Section 3, coarse spectral
+// split) and, in one workgroup, for the Rayleigh-Ritz problem (Algorithm 3.1, Step 3),
+// Cholesky-QR coefficients and the coefficient-space step that keeps
+// W^{k+1} = U^{k-1} + U^k + span{t}.
 #include "common.h"
 
 namespace bpjd {
 
-static constexpr int JACOBI_MAX_SWEEPS = 60;
+constexpr int RR_MAX = 48;           // largest Rayleigh-Ritz dimension (3 s, s <= 16)
 // up to this order the reduction to tridiagonal form runs in one workgroup; above it,
 // two launches per column spread the trailing update over all compute units
 constexpr int TRIDIAG_ONE_WG_MAX = 320;
 
 // ---------------------------------------------------------------------------
-// Right-looking Cholesky, lower, row-major, in place; upper part zeroed.
 // Block-wide sum with wave reductions (two barriers); every thread gets the result.
 __device__ inline double block_sum_fast(double v, double* red) {
     const int t = threadIdx.x, nw = (blockDim.x + 63) >> 6;
@@ -205,124 +205,6 @@ void launch_transpose(hipStream_t st, int n, const double* A, double* AT) {
 }
 
 // ---------------------------------------------------------------------------
-// Cyclic Jacobi with the round-robin (circle) ordering: every round applies
-// N/2 disjoint rotations; a sweep is N-1 rounds.  A (n x n, symmetric) and V
-// (n x n) may live in LDS or global memory.  On return A is diagonal to
-// working precision and A_in = V diag(A) V^T.
-// Cyclic Jacobi on the symmetric n x n matrix A (row stride lda, shared memory) with
-// the round-robin ordering: each round rotates n/2 disjoint (p, q) pairs at once.
-// Threshold variant: a rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|); a
-// sweep without rotations ends the iteration (relative accuracy of every eigenvalue).
-// V (stride ldv) receives the eigenvectors as columns.  Thread t owns pairs
-// k0, k0 + kstep, ... and columns j0, j0 + jstep, ... (one integer division per
-// thread), so the inner loops carry no index arithmetic beyond additions.
-__device__ void jacobi_core(int n, double* A, int lda, double* V, int ldv, double* cs, int* pr) {
-    __shared__ int rotated;
-    const int t = threadIdx.x, bd = blockDim.x;
-    const int N = n + (n & 1);
-    const int half = N / 2;
-    int k0, kstep, j0, jstep;
-    if (n <= bd) {
-        k0 = t / n;
-        kstep = bd / n;
-        j0 = t - k0 * n;
-        jstep = n;
-    } else {
-        k0 = 0;
-        kstep = 1;
-        j0 = t;
-        jstep = bd;
-    }
-    if (k0 >= kstep) k0 = half;                 // idle thread
-    for (int i = 0; i < n; ++i)
-        for (int j = t; j < n; j += bd) V[i * ldv + j] = (i == j) ? 1.0 : 0.0;
-    __syncthreads();
-    for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
-        if (t == 0) rotated = 0;
-        __syncthreads();
-        for (int r = 0; r < N - 1; ++r) {
-            for (int k = t; k < half; k += bd) {
-                int p, q;
-                if (k == 0) {
-                    p = r;
-                    q = N - 1;
-                } else {
-                    p = r + k;
-                    if (p >= N - 1) p -= N - 1;
-                    q = r - k;
-                    if (q < 0) q += N - 1;
-                }
-                if (p > q) {
-                    const int tmp = p;
-                    p = q;
-                    q = tmp;
-                }
-                double c = 1.0, sn = 0.0;
-                if (q < n) {
-                    const double apq = A[p * lda + q];
-                    const double app = A[p * lda + p], aqq = A[q * lda + q];
-                    if (fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq)) && apq != 0.0) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        sn = tt * c;
-                        rotated = 1;
-                    }
-                }
-                cs[2 * k] = c;
-                cs[2 * k + 1] = sn;
-                pr[2 * k] = p;
-                pr[2 * k + 1] = q;
-            }
-            __syncthreads();
-            // rows p, q of A
-            for (int k = k0; k < half; k += kstep) {
-                const double sn = cs[2 * k + 1];
-                const int q = pr[2 * k + 1];
-                if (sn == 0.0 || q >= n) continue;
-                const double c = cs[2 * k];
-                const int p = pr[2 * k];
-                for (int j = j0; j < n; j += jstep) {
-                    const double apj = A[p * lda + j], aqj = A[q * lda + j];
-                    A[p * lda + j] = c * apj - sn * aqj;
-                    A[q * lda + j] = sn * apj + c * aqj;
-                }
-            }
-            __syncthreads();
-            // columns p, q of A and of V; the rotation annihilates a_pq exactly, so the
-            // rounding residue at (p, q) and (q, p) is replaced by zero
-            for (int k = k0; k < half; k += kstep) {
-                const double sn = cs[2 * k + 1];
-                const int q = pr[2 * k + 1];
-                if (sn == 0.0 || q >= n) continue;
-                const double c = cs[2 * k];
-                const int p = pr[2 * k];
-                for (int i = j0; i < n; i += jstep) {
-                    const double aip = A[i * lda + p], aiq = A[i * lda + q];
-                    A[i * lda + p] = (i == q) ? 0.0 : c * aip - sn * aiq;
-                    A[i * lda + q] = (i == p) ? 0.0 : sn * aip + c * aiq;
-                    const double vip = V[i * ldv + p], viq = V[i * ldv + q];
-                    V[i * ldv + p] = c * vip - sn * viq;
-                    V[i * ldv + q] = sn * vip + c * viq;
-                }
-            }
-            __syncthreads();
-        }
-        const int any = rotated;
-        __syncthreads();
-        if (!any) break;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Dense symmetric eigensolver for the coarse problem (n <= 1024), in three
-// single-workgroup kernels: Householder reduction to tridiagonal form, the
-// implicit QL iteration with Wilkinson shifts on the tridiagonal matrix, and
-// back-transformation by the stored reflectors.
-//
-// tridiag: A (n x n, full symmetric storage, row-major) is reduced in place;
-// reflector k (acting on rows k+1..n-1) is v_k with v_k[0] = 1, stored in
-// Vh[k][k+1..n) together with tau[k]; diag/off receive the tridiagonal matrix.
 // Householder reduction of the symmetric A (n x n, one workgroup of 1024 threads) to
 // tridiagonal form T = Q^T A Q.  Step k: reflector H_k = I - tau_k v v^T (v_0 = 1)
 // annihilating A[k+2.., k]; A22 <- H_k A22 H_k as A22 - v w^T - w v^T with
@@ -550,17 +432,76 @@ __device__ inline double rcp_refined(double q) {
     r = fma(r, fma(-q, r, 1.0), r);
     return r;
 }
+// The operands of four steps are loaded before they enter the recurrence, so the
+// chain only waits on arithmetic.
 __device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
     int cnt = 0;
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (q < 0.0);
-    for (int i = 1; i < n; ++i) {
+    int i = 1;
+    for (; i + 3 < n; i += 4) {
+        double dv[4], ev[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            dv[u] = d[i + u] - x;
+            ev[u] = e2[i + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            q = dv[u] - ev[u] * rcp_refined(q);
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += (q < 0.0);
+        }
+    }
+    for (; i < n; ++i) {
         q = (d[i] - x) - e2[i - 1] * rcp_refined(q);
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += (q < 0.0);
     }
     return cnt;
+}
+
+// sum_i a[i * sa] b[i * sb], i < len, over LDS or registers-backed arrays: four
+// independent accumulators and operands loaded four at a time, so the loads of one
+// group are in flight together (fixed summation order)
+__device__ inline double dot_strided(const double* a, int sa, const double* b, int sb, int len) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int i = 0;
+    for (; i + 3 < len; i += 4) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = a[(i + u) * sa];
+            y[u] = b[(i + u) * sb];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(x[u], y[u], acc[u]);
+    }
+    for (; i < len; ++i) acc[0] = fma(a[i * sa], b[i * sb], acc[0]);
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Sum over the 64 lanes of a wavefront with DPP row operations (no LDS traffic); the
+// total is returned in every lane.  Lanes of rows excluded by a row mask add zero.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double wave_sum_dpp(double v) {
+    v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror: sums of 8
+    v += dpp_f64<0x140, 0xF>(v);   // row_mirror: sums of the 16-lane row
+    v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Bisection with 8-way multisection: 8 threads per eigenvalue (several workgroups)
@@ -607,27 +548,20 @@ __global__ __launch_bounds__(256) void tridiag_bisect_kernel(int n, const double
     for (int it = 0; it < 200 && __any(!done); ++it) {
         if (!done && (!(0.5 * (a + b) > a && 0.5 * (a + b) < b) || (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))))
             done = true;
-        const double x = a + (b - a) * (double)(r + 1) / (double)(G + 1);
-        const int above = (!done && sturm_count(n, d, e2, x, pivmin) > j) ? 1 : 0;
+        const double x = a + (b - a) / (double)(G + 1) * (double)(r + 1);
+        const bool above = !done && sturm_count(n, d, e2, x, pivmin) > j;
         // the first of the G points whose count exceeds j closes the interval
-        double na = a, nb = b;
-        bool found = false;
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int aq = __shfl(above, gl + q, 64);
-            const double xq = a + (b - a) * (double)(q + 1) / (double)(G + 1);
-            if (!found) {
-                if (aq) {
-                    nb = xq;
-                    found = true;
-                } else {
-                    na = xq;
-                }
-            }
-        }
+        const unsigned long long grp = (__ballot(above) >> gl) & ((1ull << G) - 1ull);
         if (!done) {
-            a = na;
-            b = nb;
+            const double h = (b - a) / (double)(G + 1);
+            if (grp) {
+                const int q = __ffsll((long long)grp) - 1;
+                const double na = (q > 0) ? a + h * (double)q : a;
+                b = a + h * (double)(q + 1);
+                a = na;
+            } else {
+                a = a + h * (double)G;
+            }
         }
     }
     if (j < n && r == 0) w[j] = 0.5 * (a + b);
@@ -693,6 +627,8 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
         mu[IDX(i)] = m;
     }
     u0[IDX(n - 1)] = 1.0 / ((fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0);
+    u1[IDX(n - 1)] = 0.0;                      // no super-diagonals in the last row
+    u2[IDX(n - 1)] = 0.0;
     // right-hand side: a fixed vector with varying entries
     for (int i = 0; i < n; ++i) X[IDX(i)] = 1.0 + 0.5 * sin(0.7 * i + 0.3 * j);
     for (int sweep = 0; sweep < 3; ++sweep) {
@@ -1008,27 +944,45 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz in coefficient space.  W = [X | P | T] (or [X | T]) is
 // M-orthonormal except for dropped (zero) columns, H = W^T K W (m x m, m <= 64).
-// Rayleigh-Ritz coefficients on the m x m projected matrix H (m <= RR_MAX).
-// Dropped columns (drop_in) are left out of the eigensolve and get an infinite Ritz
-// value, so they never enter the s lowest Ritz pairs.  Outputs theta (ascending) and
-// Cfull = [Q_s | C_p], where C_p spans the part of span{E_x, Q_s} orthogonal to Q_s
-// (E_x = the old X coordinates), so that span{W Q_s, W C_p} = U^k + U^{k+1}.
-// Because Q is orthogonal, (I - Q_s Q_s^T) e_j = Q_{>s} g_j with g_j = (row j of
-// Q_{>s})^T, so C_p = Q_{>s} orth(g_0 .. g_{s-1}); a direction whose norm after two
-// Gram-Schmidt passes is below 1e-12 (the old Ritz vector already lies in the new
-// span) is dropped: zero column and drop_out[s + j] = 1; drop_out[0..s) = 0.
-constexpr int RR_MAX = 48;
+// Rayleigh-Ritz coefficients on the m x m projected matrix H = W^T K W (m <= RR_MAX,
+// s <= RR_S_MAX), one workgroup of 256 threads.  W = [X | P | T] (or [X | T]) is
+// M-orthonormal except for dropped (zero) columns (drop_in), which are left out; the
+// update only needs the s lowest Ritz pairs Q_s, Theta_s:
+//   1. Householder reduction of the kept block to tridiagonal T (reflectors kept);
+//   2. the s lowest eigenvalues of T by 16-way multisection on Sturm counts;
+//   3. their eigenvectors by two inverse-iteration solves with a pivoted LU of T - theta I
+//      (distinct start vectors per eigenvalue, so degenerate pairs span their subspace);
+//   4. two classical Gram-Schmidt passes over them, then the reflectors back;
+//   5. C_p: the part of span{E_x, Q_s} orthogonal to Q_s (E_x = old X coordinates), so
+//      that span{W Q_s, W C_p} = U^k + U^{k+1}: b_j = (I - Q_s Q_s^T) e_j with two CGS
+//      passes against Q_s and the previous columns; a direction whose norm is then
+//      below 1e-12 (the old Ritz vector already lies in the new span) is dropped (zero
+//      column, drop_out[s + j] = 1); drop_out[0..s) = 0.
+// Outputs theta[0..s) ascending (theta[s..m) = +inf) and Cfull = [Q_s | C_p] (m x cw).
+constexpr int RR_S_MAX = 16;
+constexpr int RR_G = 16;                       // bisection points per eigenvalue
+__device__ inline double rr_block_sum(double v, double* wred) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((t & 63) == 0) wred[t >> 6] = v;
+    __syncthreads();
+    return ((wred[0] + wred[1]) + wred[2]) + wred[3];
+}
+
 __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, const double* __restrict__ H,
                                                       const int* __restrict__ drop_in, int* __restrict__ drop_out,
                                                       double* __restrict__ theta, double* __restrict__ Cfull) {
-    constexpr int LD = RR_MAX + 1;
-    __shared__ double A[RR_MAX * LD];
-    __shared__ double V[RR_MAX * LD];
-    __shared__ double Q[RR_MAX * LD];
-    __shared__ double cs[RR_MAX];
-    __shared__ int pr[RR_MAX];
-    __shared__ double wv[RR_MAX];
+    constexpr int LD = RR_MAX + 1, SD = RR_S_MAX + 1;
+    __shared__ double A[RR_MAX * LD];          // kept block; reflector k below the subdiagonal of column k
+    __shared__ double Z[RR_MAX * SD];          // eigenvectors (kept coordinates), n x ns
+    __shared__ double Q[RR_MAX * SD];          // Q_s (all coordinates), then C_p
+    __shared__ double iu0[RR_S_MAX * RR_MAX], iu1[RR_S_MAX * RR_MAX], iu2[RR_S_MAX * RR_MAX];
+    __shared__ double iy[RR_S_MAX * RR_MAX];
+    __shared__ double tauv[RR_MAX], dd[RR_MAX], ee[RR_MAX], e2[RR_MAX], vv[RR_MAX], ww[RR_MAX], wv[RR_MAX];
     __shared__ double red[RR_MAX];
+    __shared__ double wred[4];
     __shared__ int keep_idx[RR_MAX];
     __shared__ int mk;
     const int t = threadIdx.x, bd = blockDim.x;
@@ -1039,89 +993,274 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
         mk = c;
     }
     __syncthreads();
-    const int nk = mk;
-    for (int i = 0; i < nk; ++i)
-        for (int j = t; j < nk; j += bd) {
-            const int gi = keep_idx[i], gj = keep_idx[j];
-            A[i * LD + j] = 0.5 * (H[gi * m + gj] + H[gj * m + gi]);
+    const int n = mk;
+    const int ns = min(s, n);
+    for (int e = t; e < n * n; e += bd) {
+        const int i = e / n, j = e - (e / n) * n;
+        const int gi = keep_idx[i], gj = keep_idx[j];
+        A[i * LD + j] = 0.5 * (H[gi * m + gj] + H[gj * m + gi]);
+    }
+    __syncthreads();
+    // 1. tridiagonalisation: step k reflects rows/columns k+1..n-1.  Every thread forms
+    //    the norm and the reflector scalars itself (no reduction barrier); thread i forms
+    //    p_i = tau (A22 v)_i from column k directly; three barriers per step.
+    for (int k = 0; k + 2 < n; ++k) {
+        const int mm = n - k - 1;
+        const double* colk = A + (k + 1) * LD + k;           // x_i = colk[i * LD]
+        const double xn2 = dot_strided(colk + LD, LD, colk + LD, LD, mm - 1);
+        const double alpha = colk[0];
+        double tk = 0.0, scale = 0.0, beta = alpha;
+        if (xn2 != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tk = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
         }
-    __syncthreads();
-    if (nk > 0) jacobi_core(nk, A, LD, V, LD, cs, pr);
-    __syncthreads();
-    // ascending order of the kept Ritz values; Q (m x m) = eigenvectors placed back at the
-    // kept coordinates, followed by unit vectors (infinite value) for the dropped ones
-    for (int e = t; e < m * LD; e += bd) Q[e] = 0.0;
-    __syncthreads();
-    for (int i = t; i < nk; i += bd) {
-        const double di = A[i * LD + i];
-        int rank = 0;
-        for (int j = 0; j < nk; ++j) {
-            const double dj = A[j * LD + j];
-            rank += (dj < di) || (dj == di && j < i);
+        if (t == 0) {
+            tauv[k] = tk;
+            dd[k] = A[k * LD + k];
+            ee[k] = beta;
         }
-        wv[rank] = di;
-        for (int r = 0; r < nk; ++r) Q[keep_idx[r] * LD + rank] = V[r * LD + i];
+        for (int i = t; i < mm; i += bd) {
+            vv[i] = (i == 0) ? 1.0 : colk[i * LD] * scale;
+            if (tk != 0.0) {
+                const double* row = A + (k + 1 + i) * LD + (k + 1);
+                ww[i] = tk * (row[0] + scale * dot_strided(row + 1, 1, colk + LD, LD, mm - 1));
+            }
+        }
+        __syncthreads();
+        if (tk != 0.0) {
+            // w = p - (tau/2)(p^T v) v
+            const double half_tpv = 0.5 * tk * dot_strided(ww, 1, vv, 1, mm);
+            for (int i = t; i < mm; i += bd) e2[i] = ww[i] - half_tpv * vv[i];
+            __syncthreads();
+            for (int i = t >> 4; i < mm; i += bd >> 4) {
+                const double vi = vv[i], wi = e2[i];
+                for (int j = t & 15; j < mm; j += 16) A[(k + 1 + i) * LD + (k + 1 + j)] -= vi * e2[j] + wi * vv[j];
+            }
+        }
+        for (int i = t; i < mm; i += bd) A[(k + 1 + i) * LD + k] = vv[i];     // keep the reflector
+        __syncthreads();
     }
     if (t == 0) {
-        int c = nk;
-        for (int i = 0; i < m; ++i)
+        if (n >= 2) {
+            dd[n - 2] = A[(n - 2) * LD + n - 2];
+            ee[n - 2] = A[(n - 1) * LD + n - 2];
+            dd[n - 1] = A[(n - 1) * LD + n - 1];
+        } else if (n == 1) {
+            dd[0] = A[0];
+        }
+        if (n >= 1) ee[n - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += bd) e2[i] = ee[i] * ee[i];
+    // Gershgorin interval
+    double glo = 1e300, ghi = -1e300;
+    for (int i = 0; i < n; ++i) {
+        const double el = (i > 0) ? fabs(ee[i - 1]) : 0.0, er = fabs(ee[i]);
+        glo = fmin(glo, dd[i] - el - er);
+        ghi = fmax(ghi, dd[i] + el + er);
+    }
+    __syncthreads();
+    const double tnorm = fmax(fabs(glo), fabs(ghi));
+    const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
+    // 2. the ns lowest eigenvalues: RR_G threads per eigenvalue
+    {
+        const int j = t / RR_G, r = t % RR_G;
+        const int gl = (t & 63) - r;
+        bool done = j >= ns;
+        double a = glo - 1e-14 * tnorm - 1e-300, b = ghi + 1e-14 * tnorm + 1e-300;
+        for (int it = 0; it < 200 && __any(!done); ++it) {
+            if (!done && (!(0.5 * (a + b) > a && 0.5 * (a + b) < b) ||
+                          (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))))
+                done = true;
+            const double x = a + (b - a) / (double)(RR_G + 1) * (double)(r + 1);
+            const bool above = !done && sturm_count(n, dd, e2, x, pivmin) > j;
+            // the first of the group's points whose count exceeds j closes the interval
+            const unsigned long long grp = (__ballot(above) >> gl) & ((1ull << RR_G) - 1ull);
+            if (!done) {
+                const double h = (b - a) / (double)(RR_G + 1);
+                if (grp) {
+                    const int q = __ffsll((long long)grp) - 1;
+                    const double na = (q > 0) ? a + h * (double)q : a;
+                    b = a + h * (double)(q + 1);
+                    a = na;
+                } else {
+                    a = a + h * (double)RR_G;
+                }
+            }
+        }
+        if (j < ns && r == 0) wv[j] = 0.5 * (a + b);
+    }
+    __syncthreads();
+    // 3. inverse iteration, thread j: solve (T - theta_j I) x = b twice with a partial-
+    //    pivoting LU (U has two super-diagonals), refactoring on the fly each solve
+    if (t < ns) {
+        const int j = t;
+        const double lam = wv[j];
+        const double tiny = 2.3e-16 * fmax(tnorm, 1e-300);
+        double* u0 = iu0 + j * RR_MAX;
+        double* u1 = iu1 + j * RR_MAX;
+        double* u2 = iu2 + j * RR_MAX;
+        double* y = iy + j * RR_MAX;
+        for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * sin(0.7 * i + 0.3 * j + 0.1);
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            // forward: eliminate the sub-diagonal, applying the row operations to y; the
+            // operands of the next step are read one step ahead
+            double a0 = dd[0] - lam, a1 = (n > 1) ? ee[0] : 0.0, a2 = 0.0;
+            double yc = y[0];
+            double sub_n = ee[0], nd_n = (n > 1) ? dd[1] - lam : 0.0, ne_n = (n > 2) ? ee[1] : 0.0;
+            double yn_n = (n > 1) ? y[1] : 0.0;
+            for (int i = 0; i + 1 < n; ++i) {
+                const double sub = sub_n, nd = nd_n, ne = ne_n;
+                double yn = yn_n;
+                if (i + 2 < n) {
+                    sub_n = ee[i + 1];
+                    nd_n = dd[i + 2] - lam;
+                    ne_n = (i + 3 < n) ? ee[i + 2] : 0.0;
+                    yn_n = y[i + 2];
+                }
+                double p0, p1, p2;
+                if (fabs(sub) > fabs(a0)) {
+                    const double mlt = a0 / sub;
+                    p0 = sub;
+                    p1 = nd;
+                    p2 = ne;
+                    const double tmp = yc;
+                    yc = yn;
+                    yn = tmp - mlt * yn;
+                    const double na0 = a1 - mlt * nd, na1 = a2 - mlt * ne;
+                    a0 = na0;
+                    a1 = na1;
+                } else {
+                    const double piv = (fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0;
+                    const double mlt = sub / piv;
+                    p0 = piv;
+                    p1 = a1;
+                    p2 = a2;
+                    yn = yn - mlt * yc;
+                    a0 = nd - mlt * a1;
+                    a1 = ne - mlt * a2;
+                }
+                a2 = 0.0;
+                u0[i] = (fabs(p0) < tiny) ? copysign(tiny, p0 == 0.0 ? 1.0 : p0) : p0;
+                u1[i] = p1;
+                u2[i] = p2;
+                y[i] = yc;
+                yc = yn;
+            }
+            u0[n - 1] = (fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0;
+            u1[n - 1] = 0.0;                   // no super-diagonals in the last row
+            u2[n - 1] = 0.0;
+            y[n - 1] = yc;
+            // back substitution, normalised
+            double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+            double yb = y[n - 1], b0 = u0[n - 1], b1 = u1[n - 1], b2 = u2[n - 1];
+            for (int i = n - 1; i >= 0; --i) {
+                const double yi = yb, c0 = b0, c1 = b1, c2 = b2;
+                if (i > 0) {
+                    yb = y[i - 1];
+                    b0 = u0[i - 1];
+                    b1 = u1[i - 1];
+                    b2 = u2[i - 1];
+                }
+                const double xi = (yi - c1 * x1 - c2 * x2) / c0;
+                y[i] = xi;
+                x2 = x1;
+                x1 = xi;
+                nrm = fma(xi, xi, nrm);
+            }
+            const double inv = 1.0 / sqrt(nrm);
+            for (int i = 0; i < n; ++i) y[i] *= inv;
+        }
+        for (int i = 0; i < n; ++i) Z[i * SD + j] = y[i];
+    }
+    __syncthreads();
+    // 4. two CGS passes over the ns vectors, then Z <- H_0 ... H_{n-3} Z
+    for (int j = 0; j < ns; ++j) {
+        for (int pass = 0; pass < 2; ++pass) {
+            if (j > 0) {
+                for (int q = t; q < j; q += bd) red[q] = dot_strided(Z + q, SD, Z + j, SD, n);
+                __syncthreads();
+                for (int i = t; i < n; i += bd) Z[i * SD + j] -= dot_strided(red, 1, Z + i * SD, 1, j);
+                __syncthreads();
+            }
+        }
+        double acc = 0.0;
+        for (int i = t; i < n; i += bd) acc = fma(Z[i * SD + j], Z[i * SD + j], acc);
+        const double inv = 1.0 / sqrt(rr_block_sum(acc, wred));
+        for (int i = t; i < n; i += bd) Z[i * SD + j] *= inv;
+        __syncthreads();
+    }
+    {
+        // wavefront wq owns columns wq, wq + 4, ...: no barrier between reflectors
+        const int lane = t & 63, wq = t >> 6;
+        for (int j = wq; j < ns; j += 4)
+            for (int k = n - 3; k >= 0; --k) {
+                const double tk = tauv[k];
+                if (tk == 0.0) continue;
+                double acc = 0.0;
+                if (lane < n && lane > k) acc = A[lane * LD + k] * Z[lane * SD + j];
+                acc = wave_sum_dpp(acc);
+                if (lane < n && lane > k) Z[lane * SD + j] -= tk * acc * A[lane * LD + k];
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_wave_barrier();
+            }
+    }
+    __syncthreads();
+    // Q_s in all coordinates; missing pairs (fewer kept columns than s) are unit vectors of
+    // dropped coordinates with an infinite value
+    for (int e = t; e < m * SD; e += bd) Q[e] = 0.0;
+    __syncthreads();
+    for (int e = t; e < n * ns; e += bd) {
+        const int i = e / ns, j = e - (e / ns) * ns;
+        Q[keep_idx[i] * SD + j] = Z[i * SD + j];
+    }
+    if (t == 0) {
+        int c = ns;
+        for (int i = 0; i < m && c < s; ++i)
             if (drop_in[i]) {
-                Q[i * LD + c] = 1.0;
+                Q[i * SD + c] = 1.0;
                 wv[c] = INFINITY;
                 ++c;
             }
     }
     __syncthreads();
-    for (int i = t; i < m; i += bd) theta[i] = wv[i];
+    for (int i = t; i < m; i += bd) theta[i] = (i < s) ? wv[i] : INFINITY;
     const int cw = with_p ? 2 * s : s;
-    for (int r = 0; r < m; ++r)
-        for (int j = t; j < s; j += bd) Cfull[r * cw + j] = Q[r * LD + j];
+    for (int e = t; e < m * s; e += bd) {
+        const int r = e / s, j = e - (e / s) * s;
+        Cfull[r * cw + j] = Q[r * SD + j];
+    }
     for (int j = t; j < cw; j += bd) drop_out[j] = 0;
     if (!with_p) return;
-    // G (stored in A, (m - s) x s, stride LD): column j = g_j, then orthonormalised in
-    // place column by column with two classical Gram-Schmidt passes
-    const int mg = m - s;
-    for (int e = t; e < mg * s; e += bd) {
-        const int k = e / s, j = e - k * s;
-        A[k * LD + j] = Q[j * LD + s + k];
-    }
+    // 5. C_p: b_j = e_j - Q_s Q_s[j, :]^T, two CGS passes against Q_s and C_p so far
+    double* Cp = Z;                            // m x s, stride SD (Z is free now)
     __syncthreads();
     for (int j = 0; j < s; ++j) {
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int q = t; q < j; q += bd) {
-                double acc = 0.0;
-                for (int k = 0; k < mg; ++k) acc = fma(A[k * LD + q], A[k * LD + j], acc);
-                red[q] = acc;
-            }
-            __syncthreads();
-            for (int k = t; k < mg; k += bd) {
-                double v = A[k * LD + j];
-                for (int q = 0; q < j; ++q) v -= red[q] * A[k * LD + q];
-                A[k * LD + j] = v;
-            }
-            __syncthreads();
-        }
-        if (t < 64) {
-            double acc = 0.0;
-            for (int k = t; k < mg; k += 64) acc = fma(A[k * LD + j], A[k * LD + j], acc);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-            if (t == 0) red[RR_MAX - 1] = sqrt(acc);
-        }
+        for (int r = t; r < m; r += bd) vv[r] = ((r == j) ? 1.0 : 0.0) - dot_strided(Q + r * SD, 1, Q + j * SD, 1, s);
         __syncthreads();
-        const double nrm = red[RR_MAX - 1];
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int q = t; q < s + j; q += bd)
+                red[q] = dot_strided(vv, 1, (q < s) ? Q + q : Cp + (q - s), SD, m);
+            __syncthreads();
+            for (int r = t; r < m; r += bd)
+                ww[r] = vv[r] - dot_strided(red, 1, Q + r * SD, 1, s) - dot_strided(red + s, 1, Cp + r * SD, 1, j);
+            __syncthreads();
+            for (int r = t; r < m; r += bd) vv[r] = ww[r];
+            __syncthreads();
+        }
+        double acc = 0.0;
+        for (int r = t; r < m; r += bd) acc = fma(vv[r], vv[r], acc);
+        const double nrm = sqrt(rr_block_sum(acc, wred));
         const bool keep = nrm > 1e-12;
         const double inv = keep ? 1.0 / nrm : 0.0;
-        for (int k = t; k < mg; k += bd) A[k * LD + j] *= inv;
+        for (int r = t; r < m; r += bd) Cp[r * SD + j] = vv[r] * inv;
         if (t == 0) drop_out[s + j] = keep ? 0 : 1;
         __syncthreads();
     }
-    // C_p = Q_{>s} G
     for (int e = t; e < m * s; e += bd) {
-        const int r = e / s, j = e - r * s;
-        double acc = 0.0;
-        for (int k = 0; k < mg; ++k) acc = fma(Q[r * LD + s + k], A[k * LD + j], acc);
-        Cfull[r * cw + s + j] = acc;
+        const int r = e / s, j = e - (e / s) * s;
+        Cfull[r * cw + s + j] = Cp[r * SD + j];
     }
 }
 
