@@ -456,7 +456,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(upload(p, &p->Lwork, nullptr, elt * Ltot));
     p->npart = num_partials(n);
     chk(alloc_dev(p, &p->partial, (size_t)p->npart * 4096));
-    chk(alloc_dev(p, &p->colsq, 128));
+    chk(alloc_dev(p, &p->colsq, 256));     // [0, 2s) column norms, [128, 128+s) shifts, [192] status
     chk(alloc_dev(p, &p->lam, 64));
     chk(alloc_dev(p, &p->gsmall, 64 * 64));
     chk(alloc_dev(p, &p->csmall, 64 * 64));
@@ -572,8 +572,8 @@ static void coarse_setup(bpjd_problem* p) {
     launch_transpose(st, nH, p->Y, p->YT);
 }
 
-// Apply the two-level preconditioner to F (n x s, ld s) with shifts p->lam; Z (ld s).
-static void apply_precond(bpjd_problem* p, const double* F, double* Z, PhaseTimer* T) {
+// Apply the two-level preconditioner to F (n x s, ld s) with shifts p->lam; Z (ld ldz).
+static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, PhaseTimer* T) {
     hipStream_t st = p->ctx->stream;
     const int s = p->s;
     PH_BEGIN(T, BPJD_PHASE_COARSE);
@@ -597,10 +597,10 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, PhaseTime
     PH_BEGIN(T, BPJD_PHASE_GATHER);
     if (mixed)
         launch_scatter_f32(st, p->n, s, (int)p->sumN, p->Pptr, p->Pcol, p->Pval, p->Zhat, p->rptr, p->ridx,
-                           (const float*)p->zloc, Z, s);
+                           (const float*)p->zloc, Z, ldz);
     else
         launch_scatter_f64(st, p->n, s, (int)p->sumN, p->Pptr, p->Pcol, p->Pval, p->Zhat, p->rptr, p->ridx,
-                           (const double*)p->zloc, Z, s);
+                           (const double*)p->zloc, Z, ldz);
     PH_END(T);
 }
 
@@ -722,16 +722,16 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
     int iters = 0;
     double stop_value = NAN;
     double* h = p->hbuf;
-    int* hstatus = reinterpret_cast<int*>(h + 3 * 64);
+    int* hstatus = reinterpret_cast<int*>(h + 192);
     for (int it = 0; it <= p->opts.max_iter; ++it) {
         const int a = S.cur;
         // residual block F = M X Lambda - K X and its column norms
         PH_BEGIN(T, BPJD_PHASE_RESIDUAL);
-        launch_residual(st, n, s, p->KW[a], ld, p->MW[a], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq);
+        launch_residual(st, n, s, p->KW[a], ld, p->MW[a], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq,
+                        p->colsq + 128, p->status);
         PH_END(T);
-        BPJD_HIP(hipMemcpyAsync(h, p->colsq, sizeof(double) * 2 * s, hipMemcpyDeviceToHost, st));
-        BPJD_HIP(hipMemcpyAsync(h + 2 * 64, p->lam, sizeof(double) * s, hipMemcpyDeviceToHost, st));
-        BPJD_HIP(hipMemcpyAsync(hstatus, p->status, sizeof(int), hipMemcpyDeviceToHost, st));
+        // one read-back: column norms, shifts and status word
+        BPJD_HIP(hipMemcpyAsync(h, p->colsq, sizeof(double) * 193, hipMemcpyDeviceToHost, st));
         BPJD_HIP(hipStreamSynchronize(st));
         if (T) T->collect();
         if (*hstatus & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
@@ -766,14 +766,11 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
         if (it == p->opts.max_iter) break;
         lam_prev = lam_now;
 
-        // Step 2: t_i = (I - X X^T M) (B_i)^{-1} r_i
-        apply_precond(p, p->F, p->Z, T);
+        // Step 2: t_i = (I - X X^T M) (B_i)^{-1} r_i, written straight into the T slot of W.
         // The projection (I - X X^T M) of Step 2 is the first Gram-Schmidt pass of
         // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
         const int ct = s + S.np;
-        PH_BEGIN(T, BPJD_PHASE_ORTHO);
-        launch_copy_cols(st, n, s, p->Z, s, p->W[a] + ct, ld);
-        PH_END(T);
+        apply_precond(p, p->F, p->W[a] + ct, ld, T);
         // Step 3: Rayleigh-Ritz on W = [X | P | T]
         orthonormalize_T(p, a, ct, T);
         rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, T);
@@ -1013,8 +1010,9 @@ int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* la
     launch_copy_cols(st, n, s, p->Z, s, p->W[1], ld);
     launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[1], ld, s, p->KW[1], ld, p->MW[1], ld);
     BPJD_HIP(hipMemsetAsync(p->status, 0, sizeof(int), st));
-    launch_residual(st, n, s, p->KW[1], ld, p->MW[1], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq);
-    apply_precond(p, p->F, p->Z, nullptr);
+    launch_residual(st, n, s, p->KW[1], ld, p->MW[1], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq, nullptr,
+                    p->status);
+    apply_precond(p, p->F, p->Z, p->s, nullptr);
     const hipMemcpyKind kout = mem == BPJD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     BPJD_HIP(hipMemcpyAsync(Z, p->Z, sizeof(double) * n * s, kout, st));
     BPJD_HIP(hipStreamSynchronize(st));

@@ -103,9 +103,15 @@ static void launch_reduce(hipStream_t st, int npart, int len, const double* part
 // reduction over the row slots gives one partial per column and block.
 __global__ void residual_kernel(int n, int s, const double* __restrict__ KX, int ldk,
                                 const double* __restrict__ MX, int ldm, const double* __restrict__ lam,
-                                double* __restrict__ F, int ldf, int chunk, double* __restrict__ partial) {
+                                double* __restrict__ F, int ldf, int chunk, double* __restrict__ partial,
+                                double* __restrict__ aux, const int* __restrict__ status) {
     __shared__ double red[2][256];
     const int t = threadIdx.x;
+    // the shifts and the status word travel to the host with the column norms
+    if (aux != nullptr && blockIdx.x == 0) {
+        if (t < s) aux[t] = lam[t];
+        if (t == 0) *reinterpret_cast<int*>(aux + 64) = *status;
+    }
     const int slots = blockDim.x / s;
     const int c = t % s;
     const int rs = t / s;
@@ -137,10 +143,11 @@ __global__ void residual_kernel(int n, int s, const double* __restrict__ KX, int
 }
 
 void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, const double* MX, int ldm,
-                     const double* lam, double* F, int ldf, double* partial, int npart, double* colsq) {
+                     const double* lam, double* F, int ldf, double* partial, int npart, double* colsq, double* aux,
+                     const int* status) {
     const int chunk = (n + npart - 1) / npart;
     hipLaunchKernelGGL(residual_kernel, dim3(npart), dim3(256), 0, st, n, s, KX, ldk, MX, ldm, lam, F, ldf, chunk,
-                       partial);
+                       partial, aux, status);
     launch_reduce(st, npart, 2 * s, partial, colsq);
 }
 

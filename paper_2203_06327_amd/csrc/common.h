@@ -55,7 +55,8 @@ void launch_csr_dense(hipStream_t st, int rows, const int* ptr, const int* col, 
                       const double* B, int ldb, int ncols, double* Y, int ldy, bool accumulate);
 // F = MX diag(lam) - KX; colsq[0..s) = ||F_i||^2, colsq[s..2s) = ||MX_i||^2 (two-pass, deterministic).
 void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, const double* MX, int ldm,
-                     const double* lam, double* F, int ldf, double* partial, int npart, double* colsq);
+                     const double* lam, double* F, int ldf, double* partial, int npart, double* colsq, double* aux,
+                     const int* status);
 // C (a x b, row-major) = A^T B with A: n x a (lda), B: n x b (ldb); deterministic two-pass.
 void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, const double* B, int ldb,
                  double* partial, int npart, double* C);

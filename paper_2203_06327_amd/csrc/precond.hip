@@ -545,8 +545,6 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         for (int c = 0; c < 16; ++c) {
             const T u = a[c];
             const T dc = MT::bcast(u, c);
-            // a zero, tiny or non-finite pivot marks the factorisation as failed
-            bad |= !(fabs(dc) > T(1e-30) && fabs(dc) < T(1e30));
             const T lt = u * MT::recip(dc);
 #pragma unroll
             for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * MT::bcast(u, c2);
@@ -563,7 +561,13 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
 #pragma unroll
         for (int c = 0; c < 16; ++c) pan[lane][c] = a[c];
         wave_sync();
-        if (lane < 16 && base + lane < nl) z[base + lane] = y * MT::recip(pan[lane][lane]);
+        if (lane < 16 && base + lane < nl) {
+            // the pivots of the panel, one per lane: a zero, tiny or non-finite pivot marks
+            // the factorisation as failed (checked once per panel, off the elimination chain)
+            const T dl = pan[lane][lane];
+            bad |= !(fabs(dl) > T(1e-30) && fabs(dl) < T(1e30));
+            z[base + lane] = y * MT::recip(dl);
+        }
         // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T; k-step k of a lane
         // group lg covers panel column 4 lg + k, so each lane reads 4 adjacent columns
         T dcol[4];
@@ -659,7 +663,7 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         back_step(P, bufA, zA);
         if (P >= 1) back_step(P - 1, bufB, zB);
     }
-    if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
+    if (__any(bad) && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);   // pivots were checked per lane
 }
 
 // Local extraction (numeric setup): the lower entries of every local row of
