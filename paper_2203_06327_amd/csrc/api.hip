@@ -437,7 +437,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(alloc_dev(p, &p->Y, nH2));
     chk(alloc_dev(p, &p->jwork, nH2));
     chk(alloc_dev(p, &p->lamH, nH));
-    chk(alloc_dev(p, &p->esmall, 6 * (size_t)nH));
+    chk(alloc_dev(p, &p->esmall, 6 * (size_t)nH + 1));
     chk(alloc_dev(p, &p->YT, nH2));
     chk(alloc_dev(p, &p->escratch, 8 * nH2));
     const size_t blk = (size_t)n * 3 * s;

@@ -330,13 +330,11 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(int n, double* __restrict
 // A is symmetric, so rows stand for columns and every access is row-contiguous.
 // Outputs: diag, off (T), the reflectors Vh (row k = v_k, from column k+1), tau.
 // pbuf and wbuf (n each) carry A22 v_k and w_k between the two kernels.
-__global__ __launch_bounds__(1024) void tridiag_head_kernel(int n, int k, const double* __restrict__ A,
-                                                            double* __restrict__ Vh, double* __restrict__ tau,
-                                                            const double* __restrict__ pbuf,
-                                                            double* __restrict__ wbuf, double* __restrict__ diag,
-                                                            double* __restrict__ off) {
-    __shared__ double r[1024];            // row k of the current matrix, r[i] for i >= k
-    __shared__ double wred[16];
+// Head of step k (any block size): finishes w_{k-1} from p, forms row k of the current
+// matrix with the pending update of step k-1 applied on the fly, and builds v_k.
+__device__ void tridiag_head(int n, int k, const double* __restrict__ A, double* __restrict__ Vh,
+                             double* __restrict__ tau, const double* __restrict__ pbuf, double* __restrict__ wbuf,
+                             double* __restrict__ diag, double* __restrict__ off, double* r, double* wred) {
     const int t = threadIdx.x, bd = blockDim.x;
     if (k >= 1) {
         // w_{k-1} = tau p - (tau/2)(tau p^T v) v over rows k..n-1
@@ -392,30 +390,61 @@ __global__ __launch_bounds__(1024) void tridiag_head_kernel(int n, int k, const 
     for (int i = k + 1 + t; i < n; i += bd) vk[i] = (i == k + 1) ? 1.0 : r[i] * scale;
 }
 
-__global__ __launch_bounds__(256) void tridiag_sweep_kernel(int n, int k, double* __restrict__ A,
-                                                            const double* __restrict__ Vh,
-                                                            const double* __restrict__ wbuf,
-                                                            double* __restrict__ pbuf) {
+__global__ __launch_bounds__(1024) void tridiag_head_kernel(int n, int k, const double* __restrict__ A,
+                                                            double* __restrict__ Vh, double* __restrict__ tau,
+                                                            const double* __restrict__ pbuf,
+                                                            double* __restrict__ wbuf, double* __restrict__ diag,
+                                                            double* __restrict__ off, unsigned int* counter) {
+    __shared__ double r[1024];            // row k of the current matrix, r[i] for i >= k
+    __shared__ double wred[16];
+    if (threadIdx.x == 0) *counter = 0u;
+    tridiag_head(n, k, A, Vh, tau, pbuf, wbuf, diag, off, r, wred);
+}
+
+// Step k: one wavefront per trailing row j applies the pending update of step k-1 to
+// row j of A22 and forms (A22 v_k)_j; the last workgroup to finish (atomic counter,
+// with fences on both sides) then runs the head of step k+1, so each column costs
+// one launch.
+__global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double* __restrict__ A,
+                                                           double* __restrict__ Vh, double* __restrict__ tau,
+                                                           double* __restrict__ pbuf, double* __restrict__ wbuf,
+                                                           double* __restrict__ diag, double* __restrict__ off,
+                                                           unsigned int* counter) {
+    __shared__ double r[1024];
+    __shared__ double wred[16];
+    __shared__ int last;
     const int lane = threadIdx.x & 63;
     const int j = k + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= n) return;
-    const double* vk = Vh + (long long)k * n;
-    double* row = A + (long long)j * n;
-    double acc = 0.0;
-    if (k >= 1) {
-        const double* vp = Vh + (long long)(k - 1) * n;
-        const double vj = vp[j], wj = wbuf[j];
-        for (int i = k + 1 + lane; i < n; i += 64) {
-            const double a = row[i] - (vj * wbuf[i] + wj * vp[i]);
-            row[i] = a;
-            acc = fma(a, vk[i], acc);
+    if (j < n) {
+        const double* vk = Vh + (long long)k * n;
+        double* row = A + (long long)j * n;
+        double acc = 0.0;
+        if (k >= 1) {
+            const double* vp = Vh + (long long)(k - 1) * n;
+            const double vj = vp[j], wj = wbuf[j];
+            for (int i = k + 1 + lane; i < n; i += 64) {
+                const double a = row[i] - (vj * wbuf[i] + wj * vp[i]);
+                row[i] = a;
+                acc = fma(a, vk[i], acc);
+            }
+        } else {
+            for (int i = k + 1 + lane; i < n; i += 64) acc = fma(row[i], vk[i], acc);
         }
-    } else {
-        for (int i = k + 1 + lane; i < n; i += 64) acc = fma(row[i], vk[i], acc);
-    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) pbuf[j] = acc;
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) pbuf[j] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0u;
+    tridiag_head(n, k + 1, A, Vh, tau, pbuf, wbuf, diag, off, r, wred);
 }
 
 // Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e,
@@ -840,7 +869,8 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(int n, const double* 
 
 void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
                     double* scratch, int* status) {
-    // work: n*n (reflectors); small: 6n (tau, diag, off, unrefined eigenvalues, p, w);
+    // work: n*n (reflectors); small: 6n + 1 (tau, diag, off, unrefined eigenvalues, p, w, a
+    // completion counter);
     // scratch: 6 n*n (inverse iteration, then the cluster rotation)
     (void)status;
     double* tau = small;
@@ -853,13 +883,12 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
         // small matrices: one workgroup does every step (no per-column launches)
         hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
     } else {
-    for (int k = 0; k + 2 < n; ++k) {
-        hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, k, A, work, tau, pbuf, wbuf, diag, off);
-        hipLaunchKernelGGL(tridiag_sweep_kernel, dim3(grid_for(n - k - 1, 4)), dim3(256), 0, st, n, k, A, work, wbuf,
-                           pbuf);
-    }
-    hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, max(n - 2, 0), A, work, tau, pbuf, wbuf,
-                       diag, off);
+    unsigned int* counter = reinterpret_cast<unsigned int*>(small + 6 * n);
+    hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, 0, A, work, tau, pbuf, wbuf, diag, off,
+                       counter);
+    for (int k = 0; k + 2 < n; ++k)
+        hipLaunchKernelGGL(tridiag_step_kernel, dim3(grid_for(n - k - 1, 4)), dim3(256), 0, st, n, k, A, work, tau,
+                           pbuf, wbuf, diag, off, counter);
     }
     hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(grid_for((long long)n * BISECT_G, 256)), dim3(256), 0, st, n, diag,
                        off, w0);
