@@ -642,12 +642,11 @@ static void rayleigh_ritz(bpjd_problem* p, int a, int b, int m, int with_p, Phas
     const int n = p->n, s = p->s, ld = 3 * s;
     PH_BEGIN(T, BPJD_PHASE_RR);
     launch_gram(st, n, m, m, p->W[a], ld, p->KW[a], ld, p->partial, p->npart, p->Hm);
-    launch_rr_coef(st, m, s, with_p, p->Hm, p->dropped[a], p->dropped[b], p->theta, p->Cfull);
+    launch_rr_coef(st, m, s, with_p, p->Hm, p->dropped[a], p->dropped[b], p->theta, p->lam, p->Cfull);
     const int cw = with_p ? 2 * s : s;
     const double* src3[3] = {p->W[a], p->KW[a], p->MW[a]};
     double* dst3[3] = {p->W[b], p->KW[b], p->MW[b]};
     launch_gemm_rows(st, n, m, cw, 1.0, src3, dst3, 3, ld, p->Cfull, 0.0, ld);
-    launch_copy_cols(st, 1, s, p->theta, s, p->lam, s);
     PH_END(T);
 }
 
@@ -701,10 +700,19 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
     hipStream_t st = p->ctx->stream;
     const int n = p->n, s = p->s, k = p->k, ld = 3 * s;
     const bool uu = p->opts.subspace == BPJD_SUBSPACE_UU;
-    hipEvent_t e0, e1, e2;
-    BPJD_HIP(hipEventCreate(&e0));
-    BPJD_HIP(hipEventCreate(&e1));
-    BPJD_HIP(hipEventCreate(&e2));
+    // events are released on every exit path
+    struct Events {
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    BPJD_HIP(hipEventCreate(&ev.e[0]));
+    BPJD_HIP(hipEventCreate(&ev.e[1]));
+    BPJD_HIP(hipEventCreate(&ev.e[2]));
+    BPJD_HIP(hipEventCreateWithFlags(&ev.e[3], hipEventDisableTiming));
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1], e2 = ev.e[2], erb = ev.e[3];
     PhaseTimer timer;
     timer.st = st;
     if (p->opts.profile == 2) timer.mask = 1u << BPJD_PHASE_LOCAL;
@@ -730,9 +738,16 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
         launch_residual(st, n, s, p->KW[a], ld, p->MW[a], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq,
                         p->colsq + 128, p->status);
         PH_END(T);
-        // one read-back: column norms, shifts and status word
+        // one read-back: column norms, shifts and status word; the host polls its event
+        // (no yield), so the next launches follow the copy as closely as possible
         BPJD_HIP(hipMemcpyAsync(h, p->colsq, sizeof(double) * 193, hipMemcpyDeviceToHost, st));
-        BPJD_HIP(hipStreamSynchronize(st));
+        BPJD_HIP(hipEventRecord(erb, st));
+        {
+            hipError_t q;
+            while ((q = hipEventQuery(erb)) == hipErrorNotReady) {
+            }
+            BPJD_HIP(q);
+        }
         if (T) T->collect();
         if (*hstatus & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
         for (int i = 0; i < s; ++i) {
@@ -799,9 +814,6 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
     float ms_setup = 0.f, ms_iter = 0.f;
     BPJD_HIP(hipEventElapsedTime(&ms_setup, e0, e1));
     BPJD_HIP(hipEventElapsedTime(&ms_iter, e1, e2));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
 
     const int a = S.cur;
     if (eigvals) {

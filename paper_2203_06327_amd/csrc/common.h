@@ -133,7 +133,7 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 // of W, returns theta (m), Cfull (m x 2s) = [Q_s | orthonormal basis of span{E_x, Q_s}
 // minus Q_s] and the dropped flags of the new basis' first 2s (or s) columns.
 void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
-                    double* theta, double* Cfull);
+                    double* theta, double* lam, double* Cfull);
 
 }  // namespace bpjd
 

@@ -971,8 +971,6 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 }
 
 // ---------------------------------------------------------------------------
-// Rayleigh-Ritz in coefficient space.  W = [X | P | T] (or [X | T]) is
-// M-orthonormal except for dropped (zero) columns, H = W^T K W (m x m, m <= 64).
 // Rayleigh-Ritz coefficients on the m x m projected matrix H = W^T K W (m <= RR_MAX,
 // s <= RR_S_MAX), one workgroup of 256 threads.  W = [X | P | T] (or [X | T]) is
 // M-orthonormal except for dropped (zero) columns (drop_in), which are left out; the
@@ -1002,7 +1000,8 @@ __device__ inline double rr_block_sum(double v, double* wred) {
 
 __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, const double* __restrict__ H,
                                                       const int* __restrict__ drop_in, int* __restrict__ drop_out,
-                                                      double* __restrict__ theta, double* __restrict__ Cfull) {
+                                                      double* __restrict__ theta, double* __restrict__ lam,
+                                                      double* __restrict__ Cfull) {
     constexpr int LD = RR_MAX + 1, SD = RR_S_MAX + 1;
     __shared__ double A[RR_MAX * LD];          // kept block; reflector k below the subdiagonal of column k
     __shared__ double Z[RR_MAX * SD];          // eigenvectors (kept coordinates), n x ns
@@ -1255,6 +1254,7 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     }
     __syncthreads();
     for (int i = t; i < m; i += bd) theta[i] = (i < s) ? wv[i] : INFINITY;
+    for (int i = t; i < s; i += bd) lam[i] = wv[i];     // the new shifts
     const int cw = with_p ? 2 * s : s;
     for (int e = t; e < m * s; e += bd) {
         const int r = e / s, j = e - (e / s) * s;
@@ -1294,8 +1294,9 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
 }
 
 void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
-                    double* theta, double* Cfull) {
-    hipLaunchKernelGGL(rr_coef_kernel, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta, Cfull);
+                    double* theta, double* lam, double* Cfull) {
+    hipLaunchKernelGGL(rr_coef_kernel, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta, lam,
+                       Cfull);
 }
 
 }  // namespace bpjd
