@@ -307,17 +307,22 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
         std::vector<int> fillp(rptr.begin(), rptr.end() - 1);
         for (long long q = 0; q < sumN; ++q) ridx[fillp[sidx[q]]++] = (int)q;
     }
-    // factor storage per (subdomain, shift): the blocked solver keeps 64 x 16 panels,
-    // the windowed solver one band column per row
+    // factor storage per (subdomain, shift): the blocked solver keeps, per 16-column
+    // panel, the band part of each column (bws rows from the diagonal down), the windowed
+    // solver one band column per row
     int maxE = 0;
     for (long long q = 0; q < sumN; ++q) maxE = std::max(maxE, lptr[q + 1] - lptr[q]);
     const bool blocked = maxBW <= kBlockedMaxBand && maxE <= kBlockedMaxSlots;
+    // FP64 factors keep only the band of each column (halves the factor traffic that
+    // bounds the backward sweep); FP32 factors keep full 64-row columns, whose stores
+    // and loads need no per-lane masks
+    const int bws = opts->precision == BPJD_PREC_MIXED ? 64 : ((std::min(64, maxBW + 1) + 3) / 4) * 4;
     std::vector<long long> Loff(nsub, 0);
     long long Ltot = 0;
     for (int l = 0; l < nsub; ++l) {
         Loff[l] = Ltot;
         const long long nl = sptr[l + 1] - sptr[l];
-        Ltot += blocked ? (long long)s * ((nl + 15) / 16) * 64 * 16 : (long long)s * nl * (bw[l] + 1);
+        Ltot += blocked ? (long long)s * ((nl + 15) / 16) * 16 * bws : (long long)s * nl * (bw[l] + 1);
     }
 
     // P^T and Galerkin patterns
@@ -428,6 +433,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     chk(upload_vec(p, &p->Loff, Loff));
     if (blocked) {
         p->slotE = maxE;
+        p->bws = bws;
         chk(alloc_dev(p, &p->sd, (size_t)sumN * maxE));
         chk(alloc_dev(p, &p->sv, (size_t)sumN * maxE));
     }
@@ -588,10 +594,12 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
     PH_BEGIN(T, BPJD_PHASE_LOCAL);
     if (mixed)
         launch_local_solve_f32(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
-                               p->slotE, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc, (float*)p->Lwork, p->Loff, p->status);
+                               p->slotE, p->bws, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
+                               (float*)p->Lwork, p->Loff, p->status);
     else
         launch_local_solve_f64(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
-                               p->slotE, p->sd, p->sv, p->lam, (const double*)p->Floc, (double*)p->zloc, (double*)p->Lwork, p->Loff,
+                               p->slotE, p->bws, p->sd, p->sv, p->lam, (const double*)p->Floc, (double*)p->zloc,
+                               (double*)p->Lwork, p->Loff,
                                p->status);
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_GATHER);

@@ -94,12 +94,12 @@ void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const
 // solver (Lwork: n_l (bw_l + 1) per (l, i)).
 void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, const int* sd, const double2* sv,
+                            int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status);
 void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, const int* sd, const double2* sv,
+                            int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status);
 // Numeric local extraction: fixed-slot lower entries (offset, (K, M)) of every local row.
@@ -168,6 +168,7 @@ struct bpjd_problem {
     int *rptr = nullptr, *ridx = nullptr;
     long long* Loff = nullptr;
     int slotE = 0;                     // fixed slots per local row (blocked solver), 0 = windowed solver
+    int bws = 64;                      // stored rows per factor column (blocked solver)
     int* sd = nullptr;
     double2* sv = nullptr;
 

@@ -426,7 +426,7 @@ constexpr int MFMA_WIN = 64;       // window rows
 
 template <typename T>
 __global__ __launch_bounds__(64) void local_band_mfma_kernel(
-    int s, int E, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
+    int s, int E, int BWS, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
     const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
     T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
     using MT = MfmaTile<T>;
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     const double lamd = lam[i];
     const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
     const int q = lane >> 2, slot0 = lane & 3;
-    T* Lp = Lwork + Loff[l] + (long long)i * npan * (R * 16);
+    T* Lp = Lwork + Loff[l] + (long long)i * npan * (16 * BWS);
     const T* f = Floc + (long long)i * ldF + off;
     T* z = zloc + (long long)i * ldF + off;
 
@@ -552,11 +552,17 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
             if (lane > c) y -= lt * yc;
             a[c] = (lane == c) ? dc : lt;
         }
-        // store the factored panel (row per lane) and D^{-1} L^{-1} f of its 16 rows
-        // column-major panel storage: lanes write 64 consecutive values per column
-        T* Lpan = Lp + (long long)P * (R * 16) + lane;
+        // store the factored panel and D^{-1} L^{-1} f of its 16 rows: column c keeps its
+        // band part, window rows c .. c + BWS - 1 (lanes write consecutive values)
+        T* Lpan = Lp + (long long)P * (16 * BWS) + lane;
+        if (BWS >= R) {                       // full 64-row columns: unconditional stores
 #pragma unroll
-        for (int c = 0; c < 16; ++c) Lpan[c * R] = a[c];
+            for (int c = 0; c < 16; ++c) Lpan[c * R] = a[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (lane >= c && lane - c < BWS) Lpan[c * BWS - c] = a[c];
+        }
         wave_sync();
 #pragma unroll
         for (int c = 0; c < 16; ++c) pan[lane][c] = a[c];
@@ -612,9 +618,14 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     T zA, zB;
     auto load_panel = [&](const int P, T (&dst)[16], T& zdst) {
         const int Pc = max(P, 0);
-        const T* Lpan = Lp + (long long)Pc * (R * 16) + lane;
+        const T* Lpan = Lp + (long long)Pc * (16 * BWS) + lane;
+        if (BWS >= R) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) dst[c] = Lpan[c * R];
+            for (int c = 0; c < 16; ++c) dst[c] = Lpan[c * R];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) dst[c] = (lane >= c && lane - c < BWS) ? Lpan[c * BWS - c] : T(0);
+        }
         zdst = z[min(16 * Pc + lr, nl - 1)];
     };
     auto back_step = [&](const int P, T (&a)[16], T& zb) {
@@ -688,11 +699,11 @@ void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr
 }
 
 template <typename T>
-static void launch_local_mfma(hipStream_t st, int nsub, int s, int E, long long sumN, const int* subptr,
+static void launch_local_mfma(hipStream_t st, int nsub, int s, int E, int bws, long long sumN, const int* subptr,
                               const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
                               T* Lwork, const long long* Loff, int* status) {
-    hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, E, subptr, sd, sv, lam, Floc,
-                       sumN, zloc, Lwork, Loff, status);
+    hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv, lam,
+                       Floc, sumN, zloc, Lwork, Loff, status);
 }
 
 template <typename T>
@@ -706,11 +717,11 @@ static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long su
 
 void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, const int* sd, const double2* sv,
+                            int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status) {
     if (sd) {
-        launch_local_mfma<double>(st, nsub, s, E, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+        launch_local_mfma<double>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
         return;
     }
     launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
@@ -719,11 +730,11 @@ void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long
 
 void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
                             const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, const int* sd, const double2* sv,
+                            int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status) {
     if (sd) {
-        launch_local_mfma<float>(st, nsub, s, E, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+        launch_local_mfma<float>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
         return;
     }
     launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
