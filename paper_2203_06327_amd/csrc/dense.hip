@@ -27,12 +27,22 @@ __device__ inline double block_sum_fast(double v, double* red) {
     return r;
 }
 
+// Reciprocal from the hardware estimate refined by two Newton steps (within a few ulps
+// of the rounded quotient).
+__device__ inline double rcp_refined(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return r;
+}
+
 // Right-looking Cholesky M = L L^T in place (one workgroup) of a matrix with lower
 // bandwidth bw (entries with i - j > bw are zero; bw = n - 1 for a dense matrix): L
 // keeps that band, so step k only updates rows and columns k+1 .. k+bw.  The current
 // column is staged in LDS, the trailing window is updated with a fixed (row, column)
 // map per thread, and the threads owning the next column write it to LDS as well, so
-// that no step waits on a global load.  The strict upper triangle is zeroed.
+// that no step waits on a global load.  The strict upper triangle receives L^T, so that
+// rows of L^T are contiguous for the backward solve.
 __global__ __launch_bounds__(1024) void cholesky_kernel(int n, int bw, double* __restrict__ A,
                                                         int* __restrict__ status, int status_bit) {
     __shared__ double col[1024];     // column k of the trailing matrix (rows k..n-1)
@@ -90,12 +100,73 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int n, int bw, double* _
         __syncthreads();
     }
     for (int i = 0; i < n; ++i)
-        for (int j = i + 1 + t; j < n; j += bd) A[i * n + j] = 0.0;
+        for (int j = i + 1 + t; j < n; j += bd) A[i * n + j] = A[j * n + i];
     if (bad && t == 0) atomicOr(status, status_bit);
 }
 
+// The same factorisation for bands narrower than NB with the band held in registers:
+// one workgroup of ceil(n / 64) wavefronts, thread j owning column j (entries j..j+NB-1,
+// zero beyond the band).  The elimination runs in the square-root-free form: step k
+// publishes the unscaled column k and 1 / d_k in LDS (two buffers, alternating with k);
+// after one barrier the owner of column j = k + dd (dd = 1..bw) subtracts
+// a_k[dd + e] a_k[dd] / d_k from its entry e.  Nothing in the loop touches global
+// memory and the only division is the refined reciprocal of the pivot.  At the end
+// thread j scales its column by 1 / sqrt(d_j) (L = L~ D^{1/2}) and writes it below the
+// diagonal and, as row j of L^T, above it.
+template <int NB>
+__global__ __launch_bounds__(1024) void cholesky_reg_kernel(int n, int bw, double* __restrict__ A,
+                                                            int* __restrict__ status, int status_bit) {
+    __shared__ double lk[2][2 * NB];       // published column; entry 0 holds 1 / d_k, entries >= NB stay zero
+    const int j = threadIdx.x;
+    double a[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) a[e] = (j < n && e <= bw && j + e < n) ? A[(long long)(j + e) * n + j] : 0.0;
+    for (int i = threadIdx.x; i < 4 * NB; i += blockDim.x) (&lk[0][0])[i] = 0.0;
+    __syncthreads();
+    int bad = 0;
+    for (int k = 0; k < n; ++k) {
+        double* buf = lk[k & 1];
+        if (j == k) {
+            if (!(a[0] > 0.0) || !isfinite(a[0])) {
+                bad = 1;
+                a[0] = 1.0;
+            }
+            buf[0] = rcp_refined(a[0]);
+#pragma unroll
+            for (int e = 1; e < NB; ++e) buf[e] = a[e];
+        }
+        __syncthreads();
+        const int dd = j - k;
+        if (dd >= 1 && dd <= bw) {
+            double lv[NB];
+#pragma unroll
+            for (int e = 0; e < NB; ++e) lv[e] = buf[dd + e];
+            const double c = lv[0] * buf[0];
+#pragma unroll
+            for (int e = 0; e < NB; ++e) a[e] = fma(-lv[e], c, a[e]);
+        }
+    }
+    if (j < n) {
+        const double piv = sqrt(a[0]), inv = 1.0 / piv;
+#pragma unroll
+        for (int e = 0; e < NB; ++e)
+            if (e <= bw && j + e < n) {
+                const double l = (e == 0) ? piv : a[e] * inv;
+                A[(long long)(j + e) * n + j] = l;
+                A[(long long)j * n + j + e] = l;
+            }
+    }
+    if (bad) atomicOr(status, status_bit);
+}
+
 void launch_cholesky(hipStream_t st, int n, int bw, double* A, int* status, int status_bit) {
-    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, n, bw, A, status, status_bit);
+    const int threads = ((n + 63) / 64) * 64;
+    if (n <= 1024 && bw < 20)
+        hipLaunchKernelGGL(cholesky_reg_kernel<20>, dim3(1), dim3(threads), 0, st, n, bw, A, status, status_bit);
+    else if (n <= 1024 && bw < 36)
+        hipLaunchKernelGGL(cholesky_reg_kernel<36>, dim3(1), dim3(threads), 0, st, n, bw, A, status, status_bit);
+    else
+        hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, n, bw, A, status, status_bit);
 }
 
 // Triangular solves with a banded lower triangular L (n x n, lower bandwidth bw) and
@@ -184,8 +255,89 @@ __global__ __launch_bounds__(64) void trsm_band_kernel(int n, int bw, int nrhs, 
     }
 }
 
+// Narrow bands (bw < NB) with the recent results in registers: the row loop is unrolled
+// by NB, so result t sits in register t mod NB and every band term has a fixed
+// register.  Steps t (row t forward, row n-1-t backward) go in blocks of NB; the band
+// entries of a block (row r of L left of the diagonal forward, row r of L^T right of
+// it backward, both contiguous) and its right-hand sides are loaded one block ahead
+// into registers and moved to LDS at the block's start, where every lane reads the
+// band entries as broadcasts.  Entry e = 0 holds the reciprocal of the diagonal.
+// Terms beyond the band or the matrix are zero, so every step sums the same NB - 1
+// terms: even and odd distances in two partial sums (farthest first), then the
+// nearest result, so only one multiply-add per step waits on the previous step.
+template <int NB>
+__global__ __launch_bounds__(64) void trsm_reg_kernel(int n, int bw, int nrhs, const double* __restrict__ L,
+                                                      double* __restrict__ X, int ldx, int backward) {
+    constexpr int SPL = (NB * NB + 63) / 64;        // band values staged per lane
+    __shared__ double lb[NB * NB];                  // lb[u * NB + e]: block step u, band entry e
+    __shared__ double bx[NB][64];                   // right-hand sides of the block
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x * 64 + lane;
+    const bool live = c < nrhs;
+    const int cc = live ? c : 0;
+    const int sg = backward ? 1 : -1;
+    double stg[SPL], bnx[NB], xr[NB];
+    auto load_block = [&](int t0) {
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const int f = lane + 64 * q, u = f / NB, e = f - u * NB, t = t0 + u;
+            const int r = backward ? n - 1 - t : t, col = r + sg * e;
+            stg[q] = (f < NB * NB && t < n && e <= bw && col >= 0 && col < n) ? L[(long long)r * n + col] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int t = t0 + u;
+            bnx[u] = (t < n) ? X[(long long)(backward ? n - 1 - t : t) * ldx + cc] : 0.0;
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < NB; ++u) xr[u] = 0.0;
+    load_block(0);
+    for (int t0 = 0; t0 < n; t0 += NB) {
+        __syncthreads();                            // the previous block's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const int f = lane + 64 * q;
+            const double v = stg[q], rv = rcp_refined(v);
+            if (f < NB * NB) lb[f] = (f % NB != 0) ? v : (v != 0.0 ? rv : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) bx[u][lane] = bnx[u];
+        __syncthreads();
+        if (t0 + NB < n) load_block(t0 + NB);
+        // software pipeline: the band entries of step u + 1 are read from LDS while step u
+        // computes
+        double lv[2][NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) lv[0][e] = lb[e];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            if (u + 1 < NB) {
+#pragma unroll
+                for (int e = 0; e < NB; ++e) lv[(u + 1) & 1][e] = lb[(u + 1) * NB + e];
+            }
+            const double* l = lv[u & 1];
+            double se = bx[u][lane], so = 0.0;
+#pragma unroll
+            for (int e = NB - 1; e >= 2; --e) {
+                if (e & 1) so = fma(l[e], xr[(u - e + NB) % NB], so);
+                else se = fma(-l[e], xr[(u - e + NB) % NB], se);
+            }
+            xr[u] = fma(-l[1], xr[(u - 1 + NB) % NB], se - so) * l[0];
+            const int t = t0 + u;
+            if (live && t < n) X[(long long)(backward ? n - 1 - t : t) * ldx + c] = xr[u];
+        }
+    }
+}
+
 void launch_trsm_band(hipStream_t st, int n, int bw, int nrhs, const double* L, double* X, int ldx, bool backward) {
-    if (bw < 64)
+    if (bw < 20)
+        hipLaunchKernelGGL(trsm_reg_kernel<20>, dim3(grid_for(nrhs, 64)), dim3(64), 0, st, n, bw, nrhs, L, X, ldx,
+                           backward ? 1 : 0);
+    else if (bw < 36)
+        hipLaunchKernelGGL(trsm_reg_kernel<36>, dim3(grid_for(nrhs, 64)), dim3(64), 0, st, n, bw, nrhs, L, X, ldx,
+                           backward ? 1 : 0);
+    else if (bw < 64)
         hipLaunchKernelGGL(trsm_band_kernel<true>, dim3(grid_for(nrhs, 64)), dim3(64), 0, st, n, bw, nrhs, L, X, ldx,
                            backward ? 1 : 0);
     else
@@ -208,115 +360,139 @@ void launch_transpose(hipStream_t st, int n, const double* A, double* AT) {
 // Householder reduction of the symmetric A (n x n, one workgroup of 1024 threads) to
 // tridiagonal form T = Q^T A Q.  Step k: reflector H_k = I - tau_k v v^T (v_0 = 1)
 // annihilating A[k+2.., k]; A22 <- H_k A22 H_k as A22 - v w^T - w v^T with
-// p = tau A22 v, w = p - (tau/2)(p^T v) v.  The column that the next step reduces is
-// kept in LDS by the threads that update it, the rank-2 update uses a fixed
-// (row, column) map per thread, and block sums take two barriers.
+// p = tau A22 v, w = p - (tau/2)(p^T v) v.  One pass over the matrix per step: the
+// updated column k+1 is formed first (in LDS) and gives the next reflector v', and the
+// pass that applies the rank-2 update to rows and columns k+2.. also accumulates
+// A22' v' (column sums, A being symmetric) for the next step.  Column and row k+1 are
+// not written back; they are only needed as the next column, which stays in LDS.
 // Outputs: diag, off (T), the reflectors Vh (row k = v of step k, from column k+1)
 // and tau.
+__device__ inline double tridiag_reflector(int n, int k, const double* col, double* vk, double* Vh, double* tau,
+                                           double* diag, double* off, double* wred) {
+    // col[i] = current A[k + i][k], i = 0 .. n-k-1; writes vk[i] (rows k+1+i) and returns tau_k
+    const int t = threadIdx.x, bd = blockDim.x, m = n - k - 1;
+    double acc = 0.0;
+    for (int i = 2 + t; i <= m; i += bd) acc = fma(col[i], col[i], acc);
+    const double xn2 = block_sum_fast(acc, wred);
+    const double alpha = col[1];
+    double tk, scale, beta;
+    if (xn2 == 0.0) {
+        tk = 0.0;
+        scale = 0.0;
+        beta = alpha;
+    } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tk = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    if (t == 0) {
+        tau[k] = tk;
+        off[k] = beta;
+        diag[k] = col[0];
+    }
+    for (int i = t; i < m; i += bd) {
+        const double vi = (i == 0) ? 1.0 : col[1 + i] * scale;
+        vk[i] = vi;
+        Vh[(long long)k * n + k + 1 + i] = vi;
+    }
+    __syncthreads();
+    return tk;
+}
+
 __global__ __launch_bounds__(1024) void tridiag_kernel(int n, double* __restrict__ A, double* __restrict__ Vh,
                                                        double* __restrict__ tau, double* __restrict__ diag,
                                                        double* __restrict__ off) {
-    __shared__ double v[1024];
+    __shared__ double vbuf[2][1024];  // current and next reflector
     __shared__ double w[1024];
-    __shared__ double col[1024];     // column k of the current matrix, rows k..n-1 (col[i] = A[k + i][k])
+    __shared__ double col[1024];      // the column being reduced, col[i] = A[k + i][k]
+    __shared__ double pp[1024];       // A22 v (unscaled) for the current step
     __shared__ double red[1024];
     __shared__ double wred[16];
     const int t = threadIdx.x, bd = blockDim.x;
-    for (int i = t; i < n; i += bd) col[i] = A[i * n];
-    __syncthreads();
-    for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;                 // size of A22 (rows/cols k+1..n-1)
-        double acc = 0.0;
-        for (int i = 2 + t; i <= m; i += bd) acc = fma(col[i], col[i], acc);   // x_i = col[1 + i], i >= 1
-        const double xn2 = block_sum_fast(acc, wred);
-        const double alpha = col[1];
-        double tk, scale, beta;
-        if (xn2 == 0.0) {
-            tk = 0.0;
-            scale = 0.0;
-            beta = alpha;
-        } else {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tk = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
+    if (n <= 2) {
         if (t == 0) {
-            tau[k] = tk;
-            off[k] = beta;
-            diag[k] = col[0];
-        }
-        for (int i = t; i < m; i += bd) {
-            const double vi = (i == 0) ? 1.0 : col[1 + i] * scale;
-            v[i] = vi;
-            Vh[k * n + k + 1 + i] = vi;
-        }
-        __syncthreads();
-        const int rs = bd / m, jj = t % m, r0 = t / m;
-        const bool owner = r0 < rs;              // thread owns column jj, rows r0, r0 + rs, ...
-        if (tk == 0.0) {
-            // no reflection: the next column is read back as is
-            if (owner && jj == 0)
-                for (int ii = r0; ii < m; ii += rs) col[ii] = A[(k + 1 + ii) * n + k + 1];
-            __syncthreads();
-            continue;
-        }
-        // p = tau A22 v: column j read by 4 threads (row quarters), coalesced across j
-        {
-            const int qtr = t >> 8, jt = t & 255;
-            for (int j0 = 0; j0 < m; j0 += 256) {
-                const int j = j0 + jt;
-                double pj = 0.0;
-                if (j < m) {
-                    const double* colj = A + (k + 1) * n + (k + 1) + j;
-#pragma unroll 8
-                    for (int i = qtr; i < m; i += 4) pj = fma(colj[i * n], v[i], pj);
-                }
-                red[t] = pj;
-                __syncthreads();
-                if (qtr == 0 && j < m) w[j] = tk * (((red[jt] + red[256 + jt]) + red[512 + jt]) + red[768 + jt]);
-                __syncthreads();
+            diag[0] = A[0];
+            if (n == 2) {
+                off[0] = A[n];
+                diag[1] = A[n + 1];
             }
+            off[n - 1] = 0.0;
         }
-        double pv = 0.0;
-        for (int i = t; i < m; i += bd) pv = fma(w[i], v[i], pv);
-        const double half_tpv = 0.5 * tk * block_sum_fast(pv, wred);
-        for (int i = t; i < m; i += bd) w[i] -= half_tpv * v[i];
-        __syncthreads();
-        // A22 -= v w^T + w v^T; the owners of column 0 of A22 keep it for the next step
-        if (owner) {
-            const int j = k + 1 + jj;
-            const double vj = v[jj], wj = w[jj];
-            // batches of 8 rows: all loads are issued before the first store
-            for (int ii = r0; ii < m; ii += 8 * rs) {
+        return;
+    }
+    // Sweep over the square block of rows and columns r0..n-1 (mr = n - r0): thread
+    // (jj, rg) owns column jj and rows rg, rg + rs, ...; with upd, entries first take
+    // a -= v[i+1] w[j+1] + w[i+1] v[j+1] (v, w indexed from row r0 - 1) and are written
+    // back; then pp[j] = sum_i a[i][j] x[i] with a fixed summation order.
+    auto sweep = [&](int r0, bool upd, const double* vv, const double* x) {
+        const int mr = n - r0;
+        const int rs = bd / mr, jj = t % mr, rg = t / mr;
+        if (rg < rs) {
+            const int j = r0 + jj;
+            const double vj = upd ? vv[jj + 1] : 0.0, wj = upd ? w[jj + 1] : 0.0;
+            double acc = 0.0;
+            for (int ii = rg; ii < mr; ii += 8 * rs) {
                 double a[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int iu = ii + u * rs;
-                    a[u] = (iu < m) ? A[(k + 1 + iu) * n + j] : 0.0;
+                    a[u] = (iu < mr) ? A[(long long)(r0 + iu) * n + j] : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int iu = ii + u * rs;
-                    if (iu < m) {
-                        const double val = a[u] - (v[iu] * wj + w[iu] * vj);
-                        A[(k + 1 + iu) * n + j] = val;
-                        if (jj == 0) col[iu] = val;
+                    if (iu < mr) {
+                        double val = a[u];
+                        if (upd) {
+                            val -= vv[iu + 1] * wj + w[iu + 1] * vj;
+                            A[(long long)(r0 + iu) * n + j] = val;
+                        }
+                        acc = fma(val, x[iu], acc);
                     }
                 }
             }
+            red[rg * mr + jj] = acc;
         }
         __syncthreads();
-    }
-    // the last 2 x 2 block
-    if (t == 0) {
-        if (n >= 2) {
-            diag[n - 2] = col[0];
-            off[n - 2] = col[1];
-            diag[n - 1] = A[(n - 1) * n + n - 1];
-        } else {
-            diag[0] = A[0];
+        for (int j = t; j < mr; j += bd) {
+            double s = 0.0;
+            for (int g = 0; g < rs; ++g) s += red[g * mr + j];
+            pp[j] = s;
         }
-        off[n - 1] = 0.0;
+        __syncthreads();
+    };
+    for (int i = t; i < n; i += bd) col[i] = A[(long long)i * n];
+    __syncthreads();
+    int cur = 0;
+    double tk = tridiag_reflector(n, 0, col, vbuf[0], Vh, tau, diag, off, wred);
+    sweep(1, false, nullptr, vbuf[0]);                 // pp = A22 v_0
+    for (int k = 0;; ++k) {
+        const int m = n - k - 1;                       // A22: rows and columns k+1 .. n-1
+        const double* v = vbuf[cur];
+        // w = tau p - (tau / 2)(tau p^T v) v, with p = A22 v in pp
+        double acc = 0.0;
+        for (int i = t; i < m; i += bd) acc = fma(pp[i], v[i], acc);
+        const double pv = block_sum_fast(acc, wred);
+        for (int i = t; i < m; i += bd) w[i] = (tk == 0.0) ? 0.0 : tk * pp[i] - 0.5 * tk * tk * pv * v[i];
+        __syncthreads();
+        if (k + 3 >= n) {                              // A22 is the last 2 x 2 block
+            if (t == 0) {
+                const int r = k + 1;
+                diag[r] = A[(long long)r * n + r] - 2.0 * v[0] * w[0];
+                off[r] = A[(long long)(r + 1) * n + r] - (v[1] * w[0] + w[1] * v[0]);
+                diag[r + 1] = A[(long long)(r + 1) * n + r + 1] - 2.0 * v[1] * w[1];
+                off[r + 1] = 0.0;
+            }
+            break;
+        }
+        // column k+1 after the update, then its reflector
+        for (int i = t; i < m; i += bd) col[i] = A[(long long)(k + 1 + i) * n + k + 1] - (v[i] * w[0] + w[i] * v[0]);
+        __syncthreads();
+        const double tn = tridiag_reflector(n, k + 1, col, vbuf[cur ^ 1], Vh, tau, diag, off, wred);
+        // rank-2 update of rows/columns k+2.. and pp = A22' v'
+        sweep(k + 2, true, v, vbuf[cur ^ 1]);
+        cur ^= 1;
+        tk = tn;
     }
 }
 
@@ -455,12 +631,6 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double*
 // (within a few ulps of the rounded quotient): the count is that of a T whose
 // off-diagonal entries are perturbed by a few ulps, well inside the backward error
 // the recurrence has anyway; |q| >= pivmin keeps the reciprocal finite.
-__device__ inline double rcp_refined(double q) {
-    double r = __builtin_amdgcn_rcp(q);
-    r = fma(r, fma(-q, r, 1.0), r);
-    r = fma(r, fma(-q, r, 1.0), r);
-    return r;
-}
 // The operands of four steps are loaded before they enter the recurrence, so the
 // chain only waits on arithmetic.
 __device__ inline int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
@@ -533,12 +703,12 @@ __device__ inline double wave_sum_dpp(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Bisection with 8-way multisection: 8 threads per eigenvalue (several workgroups)
-// evaluate Sturm counts at 8 interior points of the current interval, which then
-// shrinks by a factor 9 per round.  Eigenvalue j (ascending) is the point where
+// Bisection with 32-way multisection: 32 threads per eigenvalue (several workgroups)
+// evaluate Sturm counts at 32 interior points of the current interval, which then
+// shrinks by a factor 33 per round.  Eigenvalue j (ascending) is the point where
 // count(x) passes j.  Every workgroup stages d and e^2 in LDS and forms the same
 // Gershgorin interval.
-constexpr int BISECT_G = 8;
+constexpr int BISECT_G = 32;
 __global__ __launch_bounds__(256) void tridiag_bisect_kernel(int n, const double* __restrict__ dg,
                                                              const double* __restrict__ eg, double* __restrict__ w) {
     __shared__ double d[1024];
@@ -599,9 +769,12 @@ __global__ __launch_bounds__(256) void tridiag_bisect_kernel(int n, const double
 // Inverse iteration for every eigenvalue (one thread each): three solves of
 // (T - lambda_j I) x = b with a partial-pivoting LU of the tridiagonal matrix
 // (U has two superdiagonals), starting from a fixed vector.  Scratch and result
-// vectors are interleaved ([i][j]) so accesses coalesce across threads; every sweep
-// reads one array and writes another, so loads can run ahead of the stores.
+// vectors are interleaved ([i][j]) so accesses coalesce across threads.  The sweeps
+// run in batches of IB steps whose operands are loaded one batch ahead, so the
+// recurrences wait on arithmetic, not on memory.  Each solve's right-hand side is the
+// previous solution scaled to unit norm.
 // Output: X[i][j] = component i of eigenvector j (unit 2-norm).
+constexpr int INVIT_B = 8;
 __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* __restrict__ dg,
                                                            const double* __restrict__ eg,
                                                            const double* __restrict__ w, double* __restrict__ X,
@@ -617,6 +790,7 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
     __syncthreads();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    constexpr int B = INVIT_B;
     // u0: 1 / U diagonal; u1, u2: U super-diagonals; mu: multipliers; pv: 1.0 where rows
     // were swapped; y: forward-sweep result (all [n][n], interleaved over eigenvalues)
 #define IDX(i) ((long long)(i) * n + j)
@@ -658,35 +832,98 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
     u0[IDX(n - 1)] = 1.0 / ((fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0);
     u1[IDX(n - 1)] = 0.0;                      // no super-diagonals in the last row
     u2[IDX(n - 1)] = 0.0;
-    // right-hand side: a fixed vector with varying entries
+    // first right-hand side: a fixed vector with varying entries
     for (int i = 0; i < n; ++i) X[IDX(i)] = 1.0 + 0.5 * sin(0.7 * i + 0.3 * j);
+    double scale = 1.0;                        // 1 / norm of the previous solution
     for (int sweep = 0; sweep < 3; ++sweep) {
-        // apply the row operations: X -> y
-        double cur = X[IDX(0)];
-        for (int i = 0; i + 1 < n; ++i) {
-            double nxt = X[IDX(i + 1)];
-            const double m = mu[IDX(i)];
-            if (pv[IDX(i)] != 0.0) {
-                const double tmp = cur;
-                cur = nxt;
-                nxt = tmp;
+        // apply the row operations to the right-hand side: b -> y (steps i = 0 .. n-2)
+        double cX[B] = {}, cM[B] = {}, cP[B] = {}, nX[B] = {}, nM[B] = {}, nP[B] = {};
+        auto fload = [&](int i0, double* bx, double* bm, double* bp) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = i0 + u;
+                if (i + 1 < n) {
+                    bx[u] = X[IDX(i + 1)];
+                    bm[u] = mu[IDX(i)];
+                    bp[u] = pv[IDX(i)];
+                }
             }
-            y[IDX(i)] = cur;
-            cur = nxt - m * cur;
+        };
+        double cur = X[IDX(0)] * scale;
+        fload(0, cX, cM, cP);
+        for (int i0 = 0; i0 + 1 < n; i0 += B) {
+            if (i0 + B + 1 < n) fload(i0 + B, nX, nM, nP);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = i0 + u;
+                if (i + 1 < n) {
+                    double nxt = cX[u] * scale;
+                    if (cP[u] != 0.0) {
+                        const double tmp = cur;
+                        cur = nxt;
+                        nxt = tmp;
+                    }
+                    y[IDX(i)] = cur;
+                    cur = nxt - cM[u] * cur;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                cX[u] = nX[u];
+                cM[u] = nM[u];
+                cP[u] = nP[u];
+            }
         }
         y[IDX(n - 1)] = cur;
-        // back substitution with U: y -> X
+        // back substitution with U: y -> X (steps i = n-1 .. 0)
+        double cY[B] = {}, c1[B] = {}, c2[B] = {}, c0[B] = {}, nY[B] = {}, n1[B] = {}, n2[B] = {}, n0[B] = {};
+        auto bload = [&](int i0, double* by, double* b1, double* b2, double* b0) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = i0 - u;
+                if (i >= 0) {
+                    by[u] = y[IDX(i)];
+                    b1[u] = u1[IDX(i)];
+                    b2[u] = u2[IDX(i)];
+                    b0[u] = u0[IDX(i)];
+                }
+            }
+        };
         double x1 = 0.0, x2 = 0.0;
         double nrm = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-            const double xi = (y[IDX(i)] - u1[IDX(i)] * x1 - u2[IDX(i)] * x2) * u0[IDX(i)];
-            X[IDX(i)] = xi;
-            x2 = x1;
-            x1 = xi;
-            nrm = fma(xi, xi, nrm);
+        bload(n - 1, cY, c1, c2, c0);
+        for (int i0 = n - 1; i0 >= 0; i0 -= B) {
+            if (i0 - B >= 0) bload(i0 - B, nY, n1, n2, n0);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = i0 - u;
+                if (i >= 0) {
+                    const double xi = (cY[u] - c1[u] * x1 - c2[u] * x2) * c0[u];
+                    X[IDX(i)] = xi;
+                    x2 = x1;
+                    x1 = xi;
+                    nrm = fma(xi, xi, nrm);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                cY[u] = nY[u];
+                c1[u] = n1[u];
+                c2[u] = n2[u];
+                c0[u] = n0[u];
+            }
         }
-        const double inv = 1.0 / sqrt(nrm);
-        for (int i = 0; i < n; ++i) X[IDX(i)] *= inv;
+        scale = 1.0 / sqrt(nrm);
+    }
+    // unit norm: read in batches, then write back
+    for (int i0 = 0; i0 < n; i0 += B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (i0 + u < n) v[u] = X[IDX(i0 + u)];
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (i0 + u < n) X[IDX(i0 + u)] = v[u] * scale;
     }
 #undef IDX
 }
@@ -823,42 +1060,51 @@ __global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const doubl
 }
 
 // Z <- H_0 H_1 ... H_{n-3} Z (eigenvectors of the reduced matrix back to the original
-// basis).  One wavefront per column: the column (n <= 1024) stays in registers, lane l
-// holding rows l, l + 64, ...; each reflector costs one coalesced read of v, a wave
-// reduction and an update.  The next reflector is read while the current one is applied.
+// basis).  One wavefront per column: the column stays in registers, lane l holding rows
+// l, l + 64, ... (RPL rows per lane, n <= 64 RPL); each reflector costs a coalesced read
+// of v, a DPP wave reduction and an update.  Reflectors are read D steps ahead into a
+// register ring (fixed slots: the loop is unrolled by D), tau from an LDS copy.
+template <int RPL, int D>
 __global__ __launch_bounds__(256) void tridiag_back_kernel(int n, const double* __restrict__ Vh,
                                                            const double* __restrict__ tau, double* __restrict__ Z) {
+    __shared__ double ts[1024];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ts[i] = tau[i];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= n) return;
-    constexpr int RPL = 16;                      // rows per lane (n <= 1024)
-    double z[RPL], vc[RPL], vn[RPL];
+    double z[RPL], vb[D][RPL], tb[D];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = lane + 64 * r;
         z[r] = (i < n) ? Z[i * n + j] : 0.0;
     }
-    auto load_v = [&](int k, double* dst) {
-        const int kc = max(k, 0);
+    auto load_v = [&](int k, double* dst, double& t) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int i = lane + 64 * r;
-            dst[r] = (i > kc && i < n) ? Vh[kc * n + i] : 0.0;
+            dst[r] = (i > k && i < n) ? Vh[k * n + i] : 0.0;
         }
+        t = ts[k];
     };
-    int k = n - 3;
-    if (k >= 0) load_v(k, vn);
-    for (; k >= 0; --k) {
+    // reflector k = n - 3 - step is applied at step 0, 1, ..., n - 3
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) vc[r] = vn[r];
-        if (k > 0) load_v(k - 1, vn);
-        const double tk = tau[k];
-        double acc = 0.0;
+    for (int u = 0; u < D; ++u)
+        if (n - 3 - u >= 0) load_v(n - 3 - u, vb[u], tb[u]);
+    for (int s0 = 0; s0 + 2 < n; s0 += D) {
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) acc = fma(vc[r], z[r], acc);
-        const double dk = tk * wave_sum_d(acc);
+        for (int u = 0; u < D; ++u) {
+            const int k = n - 3 - (s0 + u);
+            if (k >= 0) {
+                double acc = 0.0;
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) z[r] = fma(-dk, vc[r], z[r]);
+                for (int r = 0; r < RPL; ++r) acc = fma(vb[u][r], z[r], acc);
+                const double dk = tb[u] * wave_sum_dpp(acc);
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) z[r] = fma(-dk, vb[u][r], z[r]);
+                if (k - D >= 0) load_v(k - D, vb[u], tb[u]);
+            }
+        }
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -898,7 +1144,12 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
     (void)hipMemcpyAsync(w, w0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, diag, off, w0, w, V,
                        scratch);
-    hipLaunchKernelGGL(tridiag_back_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, work, tau, V);
+    if (n <= 256)
+        hipLaunchKernelGGL((tridiag_back_kernel<4, 8>), dim3(grid_for(n, 4)), dim3(256), 0, st, n, work, tau, V);
+    else if (n <= 512)
+        hipLaunchKernelGGL((tridiag_back_kernel<8, 6>), dim3(grid_for(n, 4)), dim3(256), 0, st, n, work, tau, V);
+    else
+        hipLaunchKernelGGL((tridiag_back_kernel<16, 4>), dim3(grid_for(n, 4)), dim3(256), 0, st, n, work, tau, V);
 }
 
 // ---------------------------------------------------------------------------
