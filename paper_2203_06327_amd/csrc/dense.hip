@@ -290,6 +290,15 @@ __global__ __launch_bounds__(64) void trsm_reg_kernel(int n, int bw, int nrhs, c
             bnx[u] = (t < n) ? X[(long long)(backward ? n - 1 - t : t) * ldx + cc] : 0.0;
         }
     };
+    // results of block t0 are stored at the start of the next block, before its loads
+    // are issued, so the wait for those loads never waits on fresh stores
+    auto store_block = [&](int t0) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int t = t0 + u;
+            if (live && t < n) X[(long long)(backward ? n - 1 - t : t) * ldx + c] = xr[u];
+        }
+    };
 #pragma unroll
     for (int u = 0; u < NB; ++u) xr[u] = 0.0;
     load_block(0);
@@ -304,6 +313,7 @@ __global__ __launch_bounds__(64) void trsm_reg_kernel(int n, int bw, int nrhs, c
 #pragma unroll
         for (int u = 0; u < NB; ++u) bx[u][lane] = bnx[u];
         __syncthreads();
+        if (t0 > 0) store_block(t0 - NB);
         if (t0 + NB < n) load_block(t0 + NB);
         // software pipeline: the band entries of step u + 1 are read from LDS while step u
         // computes
@@ -324,10 +334,9 @@ __global__ __launch_bounds__(64) void trsm_reg_kernel(int n, int bw, int nrhs, c
                 else se = fma(-l[e], xr[(u - e + NB) % NB], se);
             }
             xr[u] = fma(-l[1], xr[(u - 1 + NB) % NB], se - so) * l[0];
-            const int t = t0 + u;
-            if (live && t < n) X[(long long)(backward ? n - 1 - t : t) * ldx + c] = xr[u];
         }
     }
+    store_block(((n - 1) / NB) * NB);
 }
 
 void launch_trsm_band(hipStream_t st, int n, int bw, int nrhs, const double* L, double* X, int ldx, bool backward) {
@@ -357,7 +366,7 @@ void launch_transpose(hipStream_t st, int n, const double* A, double* AT) {
 }
 
 // ---------------------------------------------------------------------------
-// Householder reduction of the symmetric A (n x n, one workgroup of 1024 threads) to
+// Householder reduction of the symmetric A (n x n, one workgroup of 512 threads) to
 // tridiagonal form T = Q^T A Q.  Step k: reflector H_k = I - tau_k v v^T (v_0 = 1)
 // annihilating A[k+2.., k]; A22 <- H_k A22 H_k as A22 - v w^T - w v^T with
 // p = tau A22 v, w = p - (tau/2)(p^T v) v.  One pass over the matrix per step: the
@@ -399,7 +408,7 @@ __device__ inline double tridiag_reflector(int n, int k, const double* col, doub
     return tk;
 }
 
-__global__ __launch_bounds__(1024) void tridiag_kernel(int n, double* __restrict__ A, double* __restrict__ Vh,
+__global__ __launch_bounds__(512) void tridiag_kernel(int n, double* __restrict__ A, double* __restrict__ Vh,
                                                        double* __restrict__ tau, double* __restrict__ diag,
                                                        double* __restrict__ off) {
     __shared__ double vbuf[2][1024];  // current and next reflector
@@ -431,25 +440,38 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(int n, double* __restrict
             const int j = r0 + jj;
             const double vj = upd ? vv[jj + 1] : 0.0, wj = upd ? w[jj + 1] : 0.0;
             double acc = 0.0;
-            for (int ii = rg; ii < mr; ii += 8 * rs) {
-                double a[8];
+            // the thread's rows are rg + rs q, q < nq; full batches of 8 rows go through two
+            // alternating buffers, each loaded one batch ahead of its update and store.  The
+            // loads are unconditional (the batch index is clamped), so the wait before a
+            // batch's use covers that batch only; the last nq % 8 rows follow one by one.
+            const int nq = (mr - rg + rs - 1) / rs, nb = nq / 8;
+            double a0[8], a1[8];
+            auto load8 = [&](int b, double* dst) {
+                const int q0 = 8 * min(b, nb - 1);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int iu = ii + u * rs;
-                    a[u] = (iu < mr) ? A[(long long)(r0 + iu) * n + j] : 0.0;
+                for (int u = 0; u < 8; ++u) dst[u] = A[(long long)(r0 + rg + (q0 + u) * rs) * n + j];
+            };
+            auto row = [&](int iu, double val) {
+                if (upd) {
+                    val -= vv[iu + 1] * wj + w[iu + 1] * vj;
+                    A[(long long)(r0 + iu) * n + j] = val;
                 }
+                acc = fma(val, x[iu], acc);
+            };
+            auto work8 = [&](int b, const double* src) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int iu = ii + u * rs;
-                    if (iu < mr) {
-                        double val = a[u];
-                        if (upd) {
-                            val -= vv[iu + 1] * wj + w[iu + 1] * vj;
-                            A[(long long)(r0 + iu) * n + j] = val;
-                        }
-                        acc = fma(val, x[iu], acc);
-                    }
-                }
+                for (int u = 0; u < 8; ++u) row(rg + (8 * b + u) * rs, src[u]);
+            };
+            if (nb > 0) load8(0, a0);
+            for (int b = 0; b < nb; b += 2) {
+                load8(b + 1, a1);
+                work8(b, a0);
+                load8(b + 2, a0);
+                if (b + 1 < nb) work8(b + 1, a1);
+            }
+            for (int q = 8 * nb; q < nq; ++q) {
+                const int iu = rg + q * rs;
+                row(iu, A[(long long)(r0 + iu) * n + j]);
             }
             red[rg * mr + jj] = acc;
         }
@@ -770,8 +792,8 @@ __global__ __launch_bounds__(256) void tridiag_bisect_kernel(int n, const double
 // (T - lambda_j I) x = b with a partial-pivoting LU of the tridiagonal matrix
 // (U has two superdiagonals), starting from a fixed vector.  Scratch and result
 // vectors are interleaved ([i][j]) so accesses coalesce across threads.  The sweeps
-// run in batches of IB steps whose operands are loaded one batch ahead, so the
-// recurrences wait on arithmetic, not on memory.  Each solve's right-hand side is the
+// run in batches of INVIT_B steps whose operands are loaded one batch ahead into two
+// alternating buffers, so the recurrences wait on arithmetic, not on memory.  Each solve's right-hand side is the
 // previous solution scaled to unit norm.
 // Output: X[i][j] = component i of eigenvector j (unit 2-norm).
 constexpr int INVIT_B = 8;
@@ -838,41 +860,41 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
     for (int sweep = 0; sweep < 3; ++sweep) {
         // apply the row operations to the right-hand side: b -> y (steps i = 0 .. n-2)
         double cX[B] = {}, cM[B] = {}, cP[B] = {}, nX[B] = {}, nM[B] = {}, nP[B] = {};
+        // loads are unconditional with clamped indices (n >= 2), so every wait covers
+        // exactly the batch about to be used
         auto fload = [&](int i0, double* bx, double* bm, double* bp) {
 #pragma unroll
             for (int u = 0; u < B; ++u) {
-                const int i = i0 + u;
-                if (i + 1 < n) {
-                    bx[u] = X[IDX(i + 1)];
-                    bm[u] = mu[IDX(i)];
-                    bp[u] = pv[IDX(i)];
-                }
+                const int i = min(i0 + u, n - 2);
+                bx[u] = X[IDX(i + 1)];
+                bm[u] = mu[IDX(i)];
+                bp[u] = pv[IDX(i)];
             }
         };
         double cur = X[IDX(0)] * scale;
-        fload(0, cX, cM, cP);
-        for (int i0 = 0; i0 + 1 < n; i0 += B) {
-            if (i0 + B + 1 < n) fload(i0 + B, nX, nM, nP);
+        auto fwork = [&](int i0, const double* bx, const double* bm, const double* bp) {
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 const int i = i0 + u;
                 if (i + 1 < n) {
-                    double nxt = cX[u] * scale;
-                    if (cP[u] != 0.0) {
+                    double nxt = bx[u] * scale;
+                    if (bp[u] != 0.0) {
                         const double tmp = cur;
                         cur = nxt;
                         nxt = tmp;
                     }
                     y[IDX(i)] = cur;
-                    cur = nxt - cM[u] * cur;
+                    cur = nxt - bm[u] * cur;
                 }
             }
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                cX[u] = nX[u];
-                cM[u] = nM[u];
-                cP[u] = nP[u];
-            }
+        };
+        // two alternating batch buffers, each loaded one batch ahead of its use
+        if (n >= 2) fload(0, cX, cM, cP);
+        for (int i0 = 0; i0 + 1 < n; i0 += 2 * B) {
+            fload(i0 + B, nX, nM, nP);
+            fwork(i0, cX, cM, cP);
+            fload(i0 + 2 * B, cX, cM, cP);
+            if (i0 + B + 1 < n) fwork(i0 + B, nX, nM, nP);
         }
         y[IDX(n - 1)] = cur;
         // back substitution with U: y -> X (steps i = n-1 .. 0)
@@ -880,38 +902,34 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
         auto bload = [&](int i0, double* by, double* b1, double* b2, double* b0) {
 #pragma unroll
             for (int u = 0; u < B; ++u) {
-                const int i = i0 - u;
-                if (i >= 0) {
-                    by[u] = y[IDX(i)];
-                    b1[u] = u1[IDX(i)];
-                    b2[u] = u2[IDX(i)];
-                    b0[u] = u0[IDX(i)];
-                }
+                const int i = max(i0 - u, 0);
+                by[u] = y[IDX(i)];
+                b1[u] = u1[IDX(i)];
+                b2[u] = u2[IDX(i)];
+                b0[u] = u0[IDX(i)];
             }
         };
         double x1 = 0.0, x2 = 0.0;
         double nrm = 0.0;
-        bload(n - 1, cY, c1, c2, c0);
-        for (int i0 = n - 1; i0 >= 0; i0 -= B) {
-            if (i0 - B >= 0) bload(i0 - B, nY, n1, n2, n0);
+        auto bwork = [&](int i0, const double* by, const double* b1, const double* b2, const double* b0) {
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 const int i = i0 - u;
                 if (i >= 0) {
-                    const double xi = (cY[u] - c1[u] * x1 - c2[u] * x2) * c0[u];
+                    const double xi = (by[u] - b1[u] * x1 - b2[u] * x2) * b0[u];
                     X[IDX(i)] = xi;
                     x2 = x1;
                     x1 = xi;
                     nrm = fma(xi, xi, nrm);
                 }
             }
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                cY[u] = nY[u];
-                c1[u] = n1[u];
-                c2[u] = n2[u];
-                c0[u] = n0[u];
-            }
+        };
+        bload(n - 1, cY, c1, c2, c0);
+        for (int i0 = n - 1; i0 >= 0; i0 -= 2 * B) {
+            bload(i0 - B, nY, n1, n2, n0);
+            bwork(i0, cY, c1, c2, c0);
+            bload(i0 - 2 * B, cY, c1, c2, c0);
+            if (i0 - B >= 0) bwork(i0 - B, nY, n1, n2, n0);
         }
         scale = 1.0 / sqrt(nrm);
     }
@@ -1079,31 +1097,37 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(int n, const double* 
         const int i = lane + 64 * r;
         z[r] = (i < n) ? Z[i * n + j] : 0.0;
     }
+    // raw row k of Vh (indices clamped into the matrix); entries i <= k are masked
+    // to zero when the reflector is applied
     auto load_v = [&](int k, double* dst, double& t) {
+        const int kc = max(k, 0);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int i = lane + 64 * r;
-            dst[r] = (i > k && i < n) ? Vh[k * n + i] : 0.0;
-        }
-        t = ts[k];
+        for (int r = 0; r < RPL; ++r) dst[r] = Vh[kc * n + min(lane + 64 * r, n - 1)];
+        t = ts[kc];
     };
     // reflector k = n - 3 - step is applied at step 0, 1, ..., n - 3
 #pragma unroll
-    for (int u = 0; u < D; ++u)
-        if (n - 3 - u >= 0) load_v(n - 3 - u, vb[u], tb[u]);
+    for (int u = 0; u < D; ++u) load_v(n - 3 - u, vb[u], tb[u]);
     for (int s0 = 0; s0 + 2 < n; s0 += D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
+            // steps past the last reflector (k < 0) have v = 0 and leave z unchanged, so
+            // the unrolled body has no branches and every load is counted exactly
             const int k = n - 3 - (s0 + u);
-            if (k >= 0) {
-                double acc = 0.0;
+            double v[RPL];
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) acc = fma(vb[u][r], z[r], acc);
-                const double dk = tb[u] * wave_sum_dpp(acc);
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) z[r] = fma(-dk, vb[u][r], z[r]);
-                if (k - D >= 0) load_v(k - D, vb[u], tb[u]);
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                v[r] = (k >= 0 && i > k && i < n) ? vb[u][r] : 0.0;
             }
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc = fma(v[r], z[r], acc);
+            const double dk = tb[u] * wave_sum_dpp(acc);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) z[r] = fma(-dk, v[r], z[r]);
+            load_v(k - D, vb[u], tb[u]);
+            __builtin_amdgcn_sched_barrier(0);     // keep the prefetch D steps ahead of its use
         }
     }
 #pragma unroll
@@ -1127,7 +1151,7 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
     double* wbuf = small + 5 * n;
     if (n <= TRIDIAG_ONE_WG_MAX) {
         // small matrices: one workgroup does every step (no per-column launches)
-        hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, st, n, A, work, tau, diag, off);
+        hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(512), 0, st, n, A, work, tau, diag, off);
     } else {
     unsigned int* counter = reinterpret_cast<unsigned int*>(small + 6 * n);
     hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, 0, A, work, tau, pbuf, wbuf, diag, off,
@@ -1227,7 +1251,7 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 // M-orthonormal except for dropped (zero) columns (drop_in), which are left out; the
 // update only needs the s lowest Ritz pairs Q_s, Theta_s:
 //   1. Householder reduction of the kept block to tridiagonal T (reflectors kept);
-//   2. the s lowest eigenvalues of T by 16-way multisection on Sturm counts;
+//   2. the s lowest eigenvalues of T by multisection on Sturm counts;
 //   3. their eigenvectors by two inverse-iteration solves with a pivoted LU of T - theta I
 //      (distinct start vectors per eigenvalue, so degenerate pairs span their subspace);
 //   4. two classical Gram-Schmidt passes over them, then the reflectors back;
@@ -1236,103 +1260,122 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 //      passes against Q_s and the previous columns; a direction whose norm is then
 //      below 1e-12 (the old Ritz vector already lies in the new span) is dropped (zero
 //      column, drop_out[s + j] = 1); drop_out[0..s) = 0.
+// Wavefront 0 keeps row i of the kept block (and of every vector in steps 4 and 5) in
+// lane i, in registers indexed by compile-time columns (loops unrolled up to NM >= m),
+// so the reduction, the Gram-Schmidt passes, the back-transformation and C_p run on
+// DPP reductions and lane broadcasts without workgroup barriers; the multisection uses
+// all four wavefronts.
 // Outputs theta[0..s) ascending (theta[s..m) = +inf) and Cfull = [Q_s | C_p] (m x cw).
 constexpr int RR_S_MAX = 16;
-constexpr int RR_G = 16;                       // bisection points per eigenvalue
-__device__ inline double rr_block_sum(double v, double* wred) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    __syncthreads();
-    if ((t & 63) == 0) wred[t >> 6] = v;
-    __syncthreads();
-    return ((wred[0] + wred[1]) + wred[2]) + wred[3];
+
+__device__ inline double lane_bcast(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline void wave_lds_sync() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+template <int NM>
 __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, const double* __restrict__ H,
                                                       const int* __restrict__ drop_in, int* __restrict__ drop_out,
                                                       double* __restrict__ theta, double* __restrict__ lam,
                                                       double* __restrict__ Cfull) {
-    constexpr int LD = RR_MAX + 1, SD = RR_S_MAX + 1;
-    __shared__ double A[RR_MAX * LD];          // kept block; reflector k below the subdiagonal of column k
-    __shared__ double Z[RR_MAX * SD];          // eigenvectors (kept coordinates), n x ns
-    __shared__ double Q[RR_MAX * SD];          // Q_s (all coordinates), then C_p
-    __shared__ double iu0[RR_S_MAX * RR_MAX], iu1[RR_S_MAX * RR_MAX], iu2[RR_S_MAX * RR_MAX];
-    __shared__ double iy[RR_S_MAX * RR_MAX];
-    __shared__ double tauv[RR_MAX], dd[RR_MAX], ee[RR_MAX], e2[RR_MAX], vv[RR_MAX], ww[RR_MAX], wv[RR_MAX];
-    __shared__ double red[RR_MAX];
-    __shared__ double wred[4];
-    __shared__ int keep_idx[RR_MAX];
+    constexpr int SD = RR_S_MAX + 1;
+    __shared__ double vL[64], wL[64];
+    __shared__ double dd[NM], ee[NM], e2[NM], tauv[NM], wv[RR_S_MAX];
+    __shared__ double Zs[NM * SD];                  // eigenvectors of T, then of the kept block (n x ns)
+    __shared__ double Qs[NM * SD];                  // Q_s in all coordinates (m x s)
+    __shared__ double Vk[NM][64];                   // reflector k (row = lane), then C_p columns
+    __shared__ double bL[64], cL[2 * RR_S_MAX + 1];
+    __shared__ double iu0[RR_S_MAX * NM], iu1[RR_S_MAX * NM], iu2[RR_S_MAX * NM], iy[RR_S_MAX * NM];
+    __shared__ int keep_idx[NM];
     __shared__ int mk;
-    const int t = threadIdx.x, bd = blockDim.x;
+    const int t = threadIdx.x, lane = t & 63;
+    const bool w0 = t < 64;
     if (t == 0) {
         int c = 0;
         for (int i = 0; i < m; ++i)
             if (!drop_in[i]) keep_idx[c++] = i;
         mk = c;
+        for (int i = c; i < NM; ++i) keep_idx[i] = 0;
     }
     __syncthreads();
     const int n = mk;
     const int ns = min(s, n);
-    for (int e = t; e < n * n; e += bd) {
-        const int i = e / n, j = e - (e / n) * n;
-        const int gi = keep_idx[i], gj = keep_idx[j];
-        A[i * LD + j] = 0.5 * (H[gi * m + gj] + H[gj * m + gi]);
-    }
-    __syncthreads();
-    // 1. tridiagonalisation: step k reflects rows/columns k+1..n-1.  Every thread forms
-    //    the norm and the reflector scalars itself (no reduction barrier); thread i forms
-    //    p_i = tau (A22 v)_i from column k directly; three barriers per step.
-    for (int k = 0; k + 2 < n; ++k) {
-        const int mm = n - k - 1;
-        const double* colk = A + (k + 1) * LD + k;           // x_i = colk[i * LD]
-        const double xn2 = dot_strided(colk + LD, LD, colk + LD, LD, mm - 1);
-        const double alpha = colk[0];
-        double tk = 0.0, scale = 0.0, beta = alpha;
-        if (xn2 != 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tk = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
+    // 1. reduction to tridiagonal form (wavefront 0, lane i = row i)
+    if (w0) {
+        double a[NM];
+        const int gi = keep_idx[lane < n ? lane : 0];
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            const int gj = keep_idx[j];
+            a[j] = (lane < n && j < n) ? 0.5 * (H[gi * m + gj] + H[gj * m + gi]) : 0.0;
         }
-        if (t == 0) {
-            tauv[k] = tk;
-            dd[k] = A[k * LD + k];
-            ee[k] = beta;
-        }
-        for (int i = t; i < mm; i += bd) {
-            vv[i] = (i == 0) ? 1.0 : colk[i * LD] * scale;
-            if (tk != 0.0) {
-                const double* row = A + (k + 1 + i) * LD + (k + 1);
-                ww[i] = tk * (row[0] + scale * dot_strided(row + 1, 1, colk + LD, LD, mm - 1));
+#pragma unroll
+        for (int k = 0; k + 2 < NM; ++k) {
+            if (k + 2 < n) {
+                const double xk = a[k];
+                const double xn2 = wave_sum_dpp(lane >= k + 2 ? xk * xk : 0.0);
+                const double alpha = lane_bcast(xk, k + 1);
+                const double dk = lane_bcast(xk, k);
+                double tk = 0.0, scale = 0.0, beta = alpha;
+                if (xn2 != 0.0) {
+                    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                    tk = (beta - alpha) * rcp_refined(beta);
+                    scale = rcp_refined(alpha - beta);
+                }
+                const double vi = (lane == k + 1) ? 1.0 : ((lane >= k + 2 && lane < n) ? xk * scale : 0.0);
+                Vk[k][lane] = vi;
+                if (lane == 0) {
+                    tauv[k] = tk;
+                    dd[k] = dk;
+                    ee[k] = beta;
+                }
+                if (tk != 0.0) {
+                    // p = tau A22 v (rows k+1..), w = p - (tau/2)(p^T v) v, A22 -= v w^T + w v^T
+                    vL[lane] = vi;
+                    wave_lds_sync();
+                    double pp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = 0; j < NM; ++j)
+                        if (j > k) pp[j & 3] = fma(a[j], vL[j], pp[j & 3]);
+                    const double p = (lane > k) ? tk * ((pp[0] + pp[1]) + (pp[2] + pp[3])) : 0.0;
+                    const double pv = wave_sum_dpp(p * vi);
+                    const double wi = p - 0.5 * tk * pv * vi;
+                    wL[lane] = wi;
+                    wave_lds_sync();
+#pragma unroll
+                    for (int j = 0; j < NM; ++j)
+                        if (j > k) a[j] -= vi * wL[j] + wi * vL[j];
+                    wave_lds_sync();
+                }
             }
         }
-        __syncthreads();
-        if (tk != 0.0) {
-            // w = p - (tau/2)(p^T v) v
-            const double half_tpv = 0.5 * tk * dot_strided(ww, 1, vv, 1, mm);
-            for (int i = t; i < mm; i += bd) e2[i] = ww[i] - half_tpv * vv[i];
-            __syncthreads();
-            for (int i = t >> 4; i < mm; i += bd >> 4) {
-                const double vi = vv[i], wi = e2[i];
-                for (int j = t & 15; j < mm; j += 16) A[(k + 1 + i) * LD + (k + 1 + j)] -= vi * e2[j] + wi * vv[j];
-            }
+        // the last 2 x 2 block
+        double di = 0.0, si = 0.0;                  // a[lane], a[lane - 1]
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            if (j == lane) di = a[j];
+            if (j + 1 == lane) si = a[j];
         }
-        for (int i = t; i < mm; i += bd) A[(k + 1 + i) * LD + k] = vv[i];     // keep the reflector
-        __syncthreads();
-    }
-    if (t == 0) {
         if (n >= 2) {
-            dd[n - 2] = A[(n - 2) * LD + n - 2];
-            ee[n - 2] = A[(n - 1) * LD + n - 2];
-            dd[n - 1] = A[(n - 1) * LD + n - 1];
-        } else if (n == 1) {
-            dd[0] = A[0];
+            if (lane == n - 2) dd[n - 2] = di;
+            if (lane == n - 1) {
+                ee[n - 2] = si;
+                dd[n - 1] = di;
+            }
+        } else if (n == 1 && lane == 0) {
+            dd[0] = di;
         }
-        if (n >= 1) ee[n - 1] = 0.0;
+        if (lane == 0 && n >= 1) ee[n - 1] = 0.0;
     }
     __syncthreads();
-    for (int i = t; i < n; i += bd) e2[i] = ee[i] * ee[i];
-    // Gershgorin interval
+    for (int i = t; i < n; i += blockDim.x) e2[i] = ee[i] * ee[i];
     double glo = 1e300, ghi = -1e300;
     for (int i = 0; i < n; ++i) {
         const double el = (i > 0) ? fabs(ee[i - 1]) : 0.0, er = fabs(ee[i]);
@@ -1342,9 +1385,10 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     __syncthreads();
     const double tnorm = fmax(fabs(glo), fabs(ghi));
     const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
-    // 2. the ns lowest eigenvalues: RR_G threads per eigenvalue
+    // 2. the ns lowest eigenvalues: G threads per eigenvalue (G divides 64)
     {
-        const int j = t / RR_G, r = t % RR_G;
+        const int G = (ns <= 8) ? 32 : 16;
+        const int j = t / G, r = t % G;
         const int gl = (t & 63) - r;
         bool done = j >= ns;
         double a = glo - 1e-14 * tnorm - 1e-300, b = ghi + 1e-14 * tnorm + 1e-300;
@@ -1352,19 +1396,19 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
             if (!done && (!(0.5 * (a + b) > a && 0.5 * (a + b) < b) ||
                           (b - a) <= 2.3e-16 * fmax(fabs(a), fabs(b))))
                 done = true;
-            const double x = a + (b - a) / (double)(RR_G + 1) * (double)(r + 1);
+            const double x = a + (b - a) / (double)(G + 1) * (double)(r + 1);
             const bool above = !done && sturm_count(n, dd, e2, x, pivmin) > j;
             // the first of the group's points whose count exceeds j closes the interval
-            const unsigned long long grp = (__ballot(above) >> gl) & ((1ull << RR_G) - 1ull);
+            const unsigned long long grp = (__ballot(above) >> gl) & ((1ull << G) - 1ull);
             if (!done) {
-                const double h = (b - a) / (double)(RR_G + 1);
+                const double h = (b - a) / (double)(G + 1);
                 if (grp) {
                     const int q = __ffsll((long long)grp) - 1;
                     const double na = (q > 0) ? a + h * (double)q : a;
                     b = a + h * (double)(q + 1);
                     a = na;
                 } else {
-                    a = a + h * (double)RR_G;
+                    a = a + h * (double)G;
                 }
             }
         }
@@ -1372,35 +1416,28 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     }
     __syncthreads();
     // 3. inverse iteration, thread j: solve (T - theta_j I) x = b twice with a partial-
-    //    pivoting LU (U has two super-diagonals), refactoring on the fly each solve
+    //    pivoting LU (U has two super-diagonals), refactoring on the fly each solve; the
+    //    start vector is a fixed integer hash of (i, j)
     if (t < ns) {
         const int j = t;
-        const double lam = wv[j];
+        const double lmb = wv[j];
         const double tiny = 2.3e-16 * fmax(tnorm, 1e-300);
-        double* u0 = iu0 + j * RR_MAX;
-        double* u1 = iu1 + j * RR_MAX;
-        double* u2 = iu2 + j * RR_MAX;
-        double* y = iy + j * RR_MAX;
-        for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * sin(0.7 * i + 0.3 * j + 0.1);
+        double* u0 = iu0 + j * NM;                 // reciprocal pivots
+        double* u1 = iu1 + j * NM;
+        double* u2 = iu2 + j * NM;
+        double* y = iy + j * NM;
+        for (int i = 0; i < n; ++i)
+            y[i] = 0.5 + (double)((((unsigned int)i + 1u) * 2654435761u + ((unsigned int)j + 1u) * 40503u) >> 22) / 1024.0;
+        auto guard = [&](double p) { return (fabs(p) < tiny) ? copysign(tiny, p == 0.0 ? 1.0 : p) : p; };
         for (int sweep = 0; sweep < 2; ++sweep) {
-            // forward: eliminate the sub-diagonal, applying the row operations to y; the
-            // operands of the next step are read one step ahead
-            double a0 = dd[0] - lam, a1 = (n > 1) ? ee[0] : 0.0, a2 = 0.0;
+            double a0 = dd[0] - lmb, a1 = (n > 1) ? ee[0] : 0.0, a2 = 0.0;
             double yc = y[0];
-            double sub_n = ee[0], nd_n = (n > 1) ? dd[1] - lam : 0.0, ne_n = (n > 2) ? ee[1] : 0.0;
-            double yn_n = (n > 1) ? y[1] : 0.0;
             for (int i = 0; i + 1 < n; ++i) {
-                const double sub = sub_n, nd = nd_n, ne = ne_n;
-                double yn = yn_n;
-                if (i + 2 < n) {
-                    sub_n = ee[i + 1];
-                    nd_n = dd[i + 2] - lam;
-                    ne_n = (i + 3 < n) ? ee[i + 2] : 0.0;
-                    yn_n = y[i + 2];
-                }
+                const double sub = ee[i], nd = dd[i + 1] - lmb, ne = (i + 2 < n) ? ee[i + 1] : 0.0;
+                double yn = y[i + 1];
                 double p0, p1, p2;
                 if (fabs(sub) > fabs(a0)) {
-                    const double mlt = a0 / sub;
+                    const double mlt = a0 * rcp_refined(sub);
                     p0 = sub;
                     p1 = nd;
                     p2 = ne;
@@ -1411,8 +1448,8 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
                     a0 = na0;
                     a1 = na1;
                 } else {
-                    const double piv = (fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0;
-                    const double mlt = sub / piv;
+                    const double piv = guard(a0);
+                    const double mlt = sub * rcp_refined(piv);
                     p0 = piv;
                     p1 = a1;
                     p2 = a2;
@@ -1421,28 +1458,19 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
                     a1 = ne - mlt * a2;
                 }
                 a2 = 0.0;
-                u0[i] = (fabs(p0) < tiny) ? copysign(tiny, p0 == 0.0 ? 1.0 : p0) : p0;
+                u0[i] = rcp_refined(guard(p0));
                 u1[i] = p1;
                 u2[i] = p2;
                 y[i] = yc;
                 yc = yn;
             }
-            u0[n - 1] = (fabs(a0) < tiny) ? copysign(tiny, a0 == 0.0 ? 1.0 : a0) : a0;
-            u1[n - 1] = 0.0;                   // no super-diagonals in the last row
+            u0[n - 1] = rcp_refined(guard(a0));
+            u1[n - 1] = 0.0;                       // no super-diagonals in the last row
             u2[n - 1] = 0.0;
             y[n - 1] = yc;
-            // back substitution, normalised
             double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-            double yb = y[n - 1], b0 = u0[n - 1], b1 = u1[n - 1], b2 = u2[n - 1];
             for (int i = n - 1; i >= 0; --i) {
-                const double yi = yb, c0 = b0, c1 = b1, c2 = b2;
-                if (i > 0) {
-                    yb = y[i - 1];
-                    b0 = u0[i - 1];
-                    b1 = u1[i - 1];
-                    b2 = u2[i - 1];
-                }
-                const double xi = (yi - c1 * x1 - c2 * x2) / c0;
+                const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) * u0[i];
                 y[i] = xi;
                 x2 = x1;
                 x1 = xi;
@@ -1451,103 +1479,96 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
             const double inv = 1.0 / sqrt(nrm);
             for (int i = 0; i < n; ++i) y[i] *= inv;
         }
-        for (int i = 0; i < n; ++i) Z[i * SD + j] = y[i];
+        for (int i = 0; i < n; ++i) Zs[i * SD + j] = y[i];
     }
     __syncthreads();
-    // 4. two CGS passes over the ns vectors, then Z <- H_0 ... H_{n-3} Z
+    if (!w0) return;
+    // Steps 4 to 6 run in wavefront 0 on LDS-resident vectors.  The inner products of a
+    // step are taken one per lane (a serial sum over the rows), so a step costs one LDS
+    // round trip instead of one cross-lane reduction per product.
+    // 4. two CGS passes over the ns vectors (columns of Zs), then Z <- H_0 ... H_{n-3} Z
     for (int j = 0; j < ns; ++j) {
         for (int pass = 0; pass < 2; ++pass) {
             if (j > 0) {
-                for (int q = t; q < j; q += bd) red[q] = dot_strided(Z + q, SD, Z + j, SD, n);
-                __syncthreads();
-                for (int i = t; i < n; i += bd) Z[i * SD + j] -= dot_strided(red, 1, Z + i * SD, 1, j);
-                __syncthreads();
+                if (lane < j) cL[lane] = dot_strided(Zs + lane, SD, Zs + j, SD, n);
+                wave_lds_sync();
+                if (lane < n) Zs[lane * SD + j] -= dot_strided(cL, 1, Zs + lane * SD, 1, j);
+                wave_lds_sync();
             }
         }
-        double acc = 0.0;
-        for (int i = t; i < n; i += bd) acc = fma(Z[i * SD + j], Z[i * SD + j], acc);
-        const double inv = 1.0 / sqrt(rr_block_sum(acc, wred));
-        for (int i = t; i < n; i += bd) Z[i * SD + j] *= inv;
-        __syncthreads();
+        if (lane == 0) cL[0] = 1.0 / sqrt(dot_strided(Zs + j, SD, Zs + j, SD, n));
+        wave_lds_sync();
+        if (lane < n) Zs[lane * SD + j] *= cL[0];
+        wave_lds_sync();
     }
-    {
-        // wavefront wq owns columns wq, wq + 4, ...: no barrier between reflectors
-        const int lane = t & 63, wq = t >> 6;
-        for (int j = wq; j < ns; j += 4)
-            for (int k = n - 3; k >= 0; --k) {
-                const double tk = tauv[k];
-                if (tk == 0.0) continue;
-                double acc = 0.0;
-                if (lane < n && lane > k) acc = A[lane * LD + k] * Z[lane * SD + j];
-                acc = wave_sum_dpp(acc);
-                if (lane < n && lane > k) Z[lane * SD + j] -= tk * acc * A[lane * LD + k];
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                __builtin_amdgcn_wave_barrier();
-            }
+    for (int k = n - 3; k >= 0; --k) {
+        const double tk = tauv[k];
+        if (tk == 0.0) continue;
+        // d_c = tau_k v_k^T Z[:, c] (v_k is zero above row k + 1)
+        if (lane < ns) cL[lane] = tk * dot_strided(&Vk[k][k + 1], 1, Zs + (k + 1) * SD + lane, SD, n - k - 1);
+        wave_lds_sync();
+        if (lane < n && lane > k) {
+            const double vi = Vk[k][lane];
+            for (int c = 0; c < ns; ++c) Zs[lane * SD + c] -= cL[c] * vi;
+        }
+        wave_lds_sync();
     }
-    __syncthreads();
-    // Q_s in all coordinates; missing pairs (fewer kept columns than s) are unit vectors of
-    // dropped coordinates with an infinite value
-    for (int e = t; e < m * SD; e += bd) Q[e] = 0.0;
-    __syncthreads();
-    for (int e = t; e < n * ns; e += bd) {
-        const int i = e / ns, j = e - (e / ns) * ns;
-        Q[keep_idx[i] * SD + j] = Z[i * SD + j];
-    }
-    if (t == 0) {
+    // 5. Q_s in all coordinates (row r in lane r); missing pairs (fewer kept columns
+    //    than s) are unit vectors of dropped coordinates with an infinite value
+    for (int e = lane; e < m * SD; e += 64) Qs[e] = 0.0;
+    wave_lds_sync();
+    if (lane < n)
+        for (int c = 0; c < ns; ++c) Qs[keep_idx[lane] * SD + c] = Zs[lane * SD + c];
+    if (lane == 0) {
         int c = ns;
         for (int i = 0; i < m && c < s; ++i)
             if (drop_in[i]) {
-                Q[i * SD + c] = 1.0;
+                Qs[i * SD + c] = 1.0;
                 wv[c] = INFINITY;
                 ++c;
             }
     }
-    __syncthreads();
-    for (int i = t; i < m; i += bd) theta[i] = (i < s) ? wv[i] : INFINITY;
-    for (int i = t; i < s; i += bd) lam[i] = wv[i];     // the new shifts
+    wave_lds_sync();
     const int cw = with_p ? 2 * s : s;
-    for (int e = t; e < m * s; e += bd) {
-        const int r = e / s, j = e - (e / s) * s;
-        Cfull[r * cw + j] = Q[r * SD + j];
-    }
-    for (int j = t; j < cw; j += bd) drop_out[j] = 0;
+    for (int i = lane; i < m; i += 64) theta[i] = (i < s) ? wv[i] : INFINITY;
+    if (lane < s) lam[lane] = wv[lane];             // the new shifts
+    if (lane < m)
+        for (int c = 0; c < s; ++c) Cfull[lane * cw + c] = Qs[lane * SD + c];
+    if (lane < cw) drop_out[lane] = 0;
     if (!with_p) return;
-    // 5. C_p: b_j = e_j - Q_s Q_s[j, :]^T, two CGS passes against Q_s and C_p so far
-    double* Cp = Z;                            // m x s, stride SD (Z is free now)
-    __syncthreads();
+    // 6. C_p: b_j = e_j - Q_s Q_s[j, :]^T, two CGS passes against Q_s and C_p so far
+    //    (C_p column c in Vk[c])
     for (int j = 0; j < s; ++j) {
-        for (int r = t; r < m; r += bd) vv[r] = ((r == j) ? 1.0 : 0.0) - dot_strided(Q + r * SD, 1, Q + j * SD, 1, s);
-        __syncthreads();
+        if (lane < m) bL[lane] = ((lane == j) ? 1.0 : 0.0) - dot_strided(Qs + lane * SD, 1, Qs + j * SD, 1, s);
+        wave_lds_sync();
         for (int pass = 0; pass < 2; ++pass) {
-            for (int q = t; q < s + j; q += bd)
-                red[q] = dot_strided(vv, 1, (q < s) ? Q + q : Cp + (q - s), SD, m);
-            __syncthreads();
-            for (int r = t; r < m; r += bd)
-                ww[r] = vv[r] - dot_strided(red, 1, Q + r * SD, 1, s) - dot_strided(red + s, 1, Cp + r * SD, 1, j);
-            __syncthreads();
-            for (int r = t; r < m; r += bd) vv[r] = ww[r];
-            __syncthreads();
+            if (lane < s) cL[lane] = dot_strided(bL, 1, Qs + lane, SD, m);
+            else if (lane < s + j) cL[lane] = dot_strided(bL, 1, Vk[lane - s], 1, m);
+            wave_lds_sync();
+            if (lane < m)
+                bL[lane] -= dot_strided(cL, 1, Qs + lane * SD, 1, s) + dot_strided(cL + s, 1, &Vk[0][lane], 64, j);
+            wave_lds_sync();
         }
-        double acc = 0.0;
-        for (int r = t; r < m; r += bd) acc = fma(vv[r], vv[r], acc);
-        const double nrm = sqrt(rr_block_sum(acc, wred));
+        if (lane == 0) cL[2 * RR_S_MAX] = sqrt(dot_strided(bL, 1, bL, 1, m));
+        wave_lds_sync();
+        const double nrm = cL[2 * RR_S_MAX];
         const bool keep = nrm > 1e-12;
-        const double inv = keep ? 1.0 / nrm : 0.0;
-        for (int r = t; r < m; r += bd) Cp[r * SD + j] = vv[r] * inv;
-        if (t == 0) drop_out[s + j] = keep ? 0 : 1;
-        __syncthreads();
-    }
-    for (int e = t; e < m * s; e += bd) {
-        const int r = e / s, j = e - (e / s) * s;
-        Cfull[r * cw + s + j] = Cp[r * SD + j];
+        const double cpj = (lane < m && keep) ? bL[lane] * (1.0 / nrm) : 0.0;
+        Vk[j][lane] = cpj;
+        if (lane == 0) drop_out[s + j] = keep ? 0 : 1;
+        if (lane < m) Cfull[lane * cw + s + j] = cpj;
+        wave_lds_sync();
     }
 }
 
 void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
                     double* theta, double* lam, double* Cfull) {
-    hipLaunchKernelGGL(rr_coef_kernel, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta, lam,
-                       Cfull);
+    if (m <= 24)
+        hipLaunchKernelGGL(rr_coef_kernel<24>, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta,
+                           lam, Cfull);
+    else
+        hipLaunchKernelGGL(rr_coef_kernel<RR_MAX>, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out,
+                           theta, lam, Cfull);
 }
 
 }  // namespace bpjd
