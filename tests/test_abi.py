@@ -40,3 +40,55 @@ def test_error_strings_without_gpu():
     L = binding.lib()
     assert L.bpjd_strerror(-2) == b"malformed CSR matrix"
     assert L.bpjd_strerror(0) == b"ok"
+
+
+def _lib_or_skip():
+    from paper_2203_06327_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("library not built")
+    return binding, binding.lib()
+
+
+def test_null_arguments_are_rejected_without_touching_a_device():
+    binding, L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    assert L.bpjd_ctx_create(0, None, None) == binding.ERR_ARG
+    assert b"NULL" in L.bpjd_last_error()
+    assert L.bpjd_problem_create(None, None, None, None, None, ctypes.byref(h)) == binding.ERR_ARG
+    assert L.bpjd_problem_create_geom(None, None, None, None, None, ctypes.byref(h)) == binding.ERR_ARG
+    for call in (lambda: L.bpjd_solve(None, None, None, binding.MEM_HOST, None),
+                 lambda: L.bpjd_setup(None),
+                 lambda: L.bpjd_spmm(None, None, 1, None, None, binding.MEM_HOST),
+                 lambda: L.bpjd_coarse_eigenvalues(None, None, binding.MEM_HOST),
+                 lambda: L.bpjd_apply_preconditioner(None, None, None, None, binding.MEM_HOST),
+                 lambda: L.bpjd_problem_set_values(None, None, None, binding.MEM_HOST)):
+        assert call() == binding.ERR_ARG
+    L.bpjd_problem_destroy(None)             # no-ops on NULL
+    L.bpjd_ctx_destroy(None)
+
+
+def test_bad_device_ordinal_is_an_error():
+    binding, L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    code = L.bpjd_ctx_create(-1, None, ctypes.byref(h))
+    # no device at all (CPU host) or an ordinal out of range
+    assert code in (binding.ERR_HIP, binding.ERR_ARG)
+    assert L.bpjd_last_error() != b""
+    assert not h.value
+
+
+def test_every_error_code_has_a_message():
+    binding, L = _lib_or_skip()
+    codes = [binding.OK, binding.ERR_ARG, binding.ERR_CSR, binding.ERR_DD, binding.ERR_NOT_SPD, binding.ERR_NOCONV,
+             binding.ERR_OOM, binding.ERR_HIP, binding.ERR_OVER_BUDGET, binding.ERR_STATE]
+    msgs = [L.bpjd_strerror(c) for c in codes]
+    assert all(msgs) and len(set(msgs)) == len(msgs)
+    assert L.bpjd_strerror(-999) != b""
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    from paper_2203_06327_amd import binding
+    monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libbpjd.so")
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(binding.LibraryNotBuilt):
+        binding.lib()
