@@ -20,8 +20,6 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 VALU instructions stay off (plain float code only)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # fully unrolled register-resident loops (the Rayleigh-Ritz reduction for m <= 48)
-    "-mllvm", "-pragma-unroll-threshold=65536",
     "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 

@@ -1260,11 +1260,11 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 //      passes against Q_s and the previous columns; a direction whose norm is then
 //      below 1e-12 (the old Ritz vector already lies in the new span) is dropped (zero
 //      column, drop_out[s + j] = 1); drop_out[0..s) = 0.
-// Wavefront 0 keeps row i of the kept block (and of every vector in steps 4 and 5) in
-// lane i, in registers indexed by compile-time columns (loops unrolled up to NM >= m),
-// so the reduction, the Gram-Schmidt passes, the back-transformation and C_p run on
-// DPP reductions and lane broadcasts without workgroup barriers; the multisection uses
-// all four wavefronts.
+// Wavefront 0 works on row i of the kept block (and of every vector in steps 4 to 6)
+// in lane i, with the data in LDS, so the reduction, the Gram-Schmidt passes, the
+// back-transformation and C_p need no workgroup barriers; the multisection uses all
+// four wavefronts.  The loops stay compact: the kernel runs once per iteration, so
+// fully unrolled code would be fetched from L2 instruction by instruction.
 // Outputs theta[0..s) ascending (theta[s..m) = +inf) and Cfull = [Q_s | C_p] (m x cw).
 constexpr int RR_S_MAX = 16;
 
@@ -1286,6 +1286,7 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
                                                       double* __restrict__ theta, double* __restrict__ lam,
                                                       double* __restrict__ Cfull) {
     constexpr int SD = RR_S_MAX + 1;
+    __shared__ double Al[NM][NM + 1];               // the kept block, reduced in place
     __shared__ double vL[64], wL[64];
     __shared__ double dd[NM], ee[NM], e2[NM], tauv[NM], wv[RR_S_MAX];
     __shared__ double Zs[NM * SD];                  // eigenvectors of T, then of the kept block (n x ns)
@@ -1307,72 +1308,60 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     __syncthreads();
     const int n = mk;
     const int ns = min(s, n);
-    // 1. reduction to tridiagonal form (wavefront 0, lane i = row i)
+    // 1. reduction to tridiagonal form (wavefront 0, lane i = row i of the kept block in
+    //    LDS); a compact loop, so the code stays in the instruction cache
     if (w0) {
-        double a[NM];
-        const int gi = keep_idx[lane < n ? lane : 0];
-#pragma unroll
-        for (int j = 0; j < NM; ++j) {
-            const int gj = keep_idx[j];
-            a[j] = (lane < n && j < n) ? 0.5 * (H[gi * m + gj] + H[gj * m + gi]) : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k + 2 < NM; ++k) {
-            if (k + 2 < n) {
-                const double xk = a[k];
-                const double xn2 = wave_sum_dpp(lane >= k + 2 ? xk * xk : 0.0);
-                const double alpha = lane_bcast(xk, k + 1);
-                const double dk = lane_bcast(xk, k);
-                double tk = 0.0, scale = 0.0, beta = alpha;
-                if (xn2 != 0.0) {
-                    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                    tk = (beta - alpha) * rcp_refined(beta);
-                    scale = rcp_refined(alpha - beta);
-                }
-                const double vi = (lane == k + 1) ? 1.0 : ((lane >= k + 2 && lane < n) ? xk * scale : 0.0);
-                Vk[k][lane] = vi;
-                if (lane == 0) {
-                    tauv[k] = tk;
-                    dd[k] = dk;
-                    ee[k] = beta;
-                }
-                if (tk != 0.0) {
-                    // p = tau A22 v (rows k+1..), w = p - (tau/2)(p^T v) v, A22 -= v w^T + w v^T
-                    vL[lane] = vi;
-                    wave_lds_sync();
-                    double pp[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int j = 0; j < NM; ++j)
-                        if (j > k) pp[j & 3] = fma(a[j], vL[j], pp[j & 3]);
-                    const double p = (lane > k) ? tk * ((pp[0] + pp[1]) + (pp[2] + pp[3])) : 0.0;
-                    const double pv = wave_sum_dpp(p * vi);
-                    const double wi = p - 0.5 * tk * pv * vi;
-                    wL[lane] = wi;
-                    wave_lds_sync();
-#pragma unroll
-                    for (int j = 0; j < NM; ++j)
-                        if (j > k) a[j] -= vi * wL[j] + wi * vL[j];
-                    wave_lds_sync();
-                }
+        if (lane < n) {
+            const int gi = keep_idx[lane];
+            for (int j = 0; j < n; ++j) {
+                const int gj = keep_idx[j];
+                Al[lane][j] = 0.5 * (H[gi * m + gj] + H[gj * m + gi]);
             }
         }
-        // the last 2 x 2 block
-        double di = 0.0, si = 0.0;                  // a[lane], a[lane - 1]
-#pragma unroll
-        for (int j = 0; j < NM; ++j) {
-            if (j == lane) di = a[j];
-            if (j + 1 == lane) si = a[j];
-        }
-        if (n >= 2) {
-            if (lane == n - 2) dd[n - 2] = di;
-            if (lane == n - 1) {
-                ee[n - 2] = si;
-                dd[n - 1] = di;
+        wave_lds_sync();
+        for (int k = 0; k + 2 < n; ++k) {
+            const double xk = (lane < n) ? Al[lane][k] : 0.0;
+            const double xn2 = wave_sum_dpp(lane >= k + 2 ? xk * xk : 0.0);
+            const double alpha = lane_bcast(xk, k + 1);
+            const double dk = lane_bcast(xk, k);
+            double tk = 0.0, scale = 0.0, beta = alpha;
+            if (xn2 != 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tk = (beta - alpha) * rcp_refined(beta);
+                scale = rcp_refined(alpha - beta);
             }
-        } else if (n == 1 && lane == 0) {
-            dd[0] = di;
+            const double vi = (lane == k + 1) ? 1.0 : ((lane >= k + 2 && lane < n) ? xk * scale : 0.0);
+            Vk[k][lane] = vi;
+            if (lane == 0) {
+                tauv[k] = tk;
+                dd[k] = dk;
+                ee[k] = beta;
+            }
+            if (tk != 0.0) {
+                // p = tau A22 v (rows k+1..), w = p - (tau/2)(p^T v) v, A22 -= v w^T + w v^T
+                vL[lane] = vi;
+                wave_lds_sync();
+                double p = 0.0;
+                if (lane > k && lane < n) p = tk * dot_strided(&Al[lane][k + 1], 1, &vL[k + 1], 1, n - k - 1);
+                const double pv = wave_sum_dpp(p * vi);
+                const double wi = p - 0.5 * tk * pv * vi;
+                wL[lane] = wi;
+                wave_lds_sync();
+                if (lane > k && lane < n)
+                    for (int j = k + 1; j < n; ++j) Al[lane][j] -= vi * wL[j] + wi * vL[j];
+                wave_lds_sync();
+            }
         }
-        if (lane == 0 && n >= 1) ee[n - 1] = 0.0;
+        if (lane == 0) {
+            if (n >= 2) {
+                dd[n - 2] = Al[n - 2][n - 2];
+                ee[n - 2] = Al[n - 1][n - 2];
+                dd[n - 1] = Al[n - 1][n - 1];
+            } else if (n == 1) {
+                dd[0] = Al[0][0];
+            }
+            if (n >= 1) ee[n - 1] = 0.0;
+        }
     }
     __syncthreads();
     for (int i = t; i < n; i += blockDim.x) e2[i] = ee[i] * ee[i];
