@@ -153,17 +153,20 @@ void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, co
 
 // ---------------------------------------------------------------------------
 // Gram product C = A^T B (a, b <= 64) with FP64 16x16x4 MFMAs: the rows are the
-// contraction index.  One wave per chunk of rows; for a k-step of 4 rows, lane l
-// supplies A[r + l/16][16 tp + l%16] and B[r + l/16][16 tq + l%16] straight
-// from the row-major blocks.  Partials ([a*b][npart]) are reduced in a second
-// pass in a fixed order.
+// contraction index.  A workgroup of four wavefronts per chunk of rows: wavefront w
+// takes the k-steps of 4 rows numbered w, w + 4, ... and keeps U of them in flight; for
+// a k-step, lane l supplies A[r + l/16][16 tp + l%16] and B[r + l/16][16 tq + l%16]
+// straight from the row-major blocks.  The four accumulators are added in LDS in a
+// fixed order, one partial per workgroup ([a*b][npart]), and the partials are reduced
+// in a second pass in a fixed order.
 typedef double dx4_t __attribute__((ext_vector_type(4)));
 
 template <int TA, int TB>
-__global__ __launch_bounds__(64) void gram_mfma_kernel(int n, int a, int b, const double* __restrict__ A, int lda,
-                                                       const double* __restrict__ B, int ldb, int chunk,
-                                                       double* __restrict__ partial) {
-    const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
+__global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, const double* __restrict__ A, int lda,
+                                                        const double* __restrict__ B, int ldb, int chunk,
+                                                        double* __restrict__ partial) {
+    __shared__ double red[3][TA * TB * 4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int r0 = blockIdx.x * chunk;
     const int r1 = min(n, r0 + chunk);
     dx4_t acc[TA][TB];
@@ -172,11 +175,11 @@ __global__ __launch_bounds__(64) void gram_mfma_kernel(int n, int a, int b, cons
 #pragma unroll
         for (int q = 0; q < TB; ++q) acc[p][q] = dx4_t{0.0, 0.0, 0.0, 0.0};
     constexpr int U = 4;                        // k-steps whose loads are in flight together
-    for (int r = r0; r < r1; r += 4 * U) {
+    for (int r = r0 + 4 * w; r < r1; r += 16 * U) {
         double av[U][TA], bv[U][TB];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int rr = r + 4 * u + lk;
+            const int rr = r + 16 * u + lk;
             const bool rok = rr < r1;
 #pragma unroll
             for (int p = 0; p < TA; ++p) {
@@ -197,6 +200,16 @@ __global__ __launch_bounds__(64) void gram_mfma_kernel(int n, int a, int b, cons
                 for (int q = 0; q < TB; ++q)
                     acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][p], bv[u][q], acc[p][q], 0, 0, 0);
     }
+    if (w > 0) {
+#pragma unroll
+        for (int p = 0; p < TA; ++p)
+#pragma unroll
+            for (int q = 0; q < TB; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[w - 1][(p * TB + q) * 4 + i][lane] = acc[p][q][i];
+    }
+    __syncthreads();
+    if (w != 0) return;
     // FP64 accumulator element i of lane l: row l/16 + 4 i, column l%16 of the 16x16 tile
 #pragma unroll
     for (int p = 0; p < TA; ++p)
@@ -204,8 +217,10 @@ __global__ __launch_bounds__(64) void gram_mfma_kernel(int n, int a, int b, cons
         for (int q = 0; q < TB; ++q)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+                const int e = (p * TB + q) * 4 + i;
+                const double v = ((acc[p][q][i] + red[0][e][lane]) + red[1][e][lane]) + red[2][e][lane];
                 const int row = 16 * p + lk + 4 * i, col = 16 * q + lr;
-                if (row < a && col < b) partial[(long long)(row * b + col) * gridDim.x + blockIdx.x] = acc[p][q][i];
+                if (row < a && col < b) partial[(long long)(row * b + col) * gridDim.x + blockIdx.x] = v;
             }
 }
 
@@ -213,16 +228,17 @@ template <int TA>
 static void gram_dispatch_b(hipStream_t st, int TB, int grid, int n, int a, int b, const double* A, int lda,
                             const double* B, int ldb, int chunk, double* partial) {
     switch (TB) {
-        case 1: hipLaunchKernelGGL((gram_mfma_kernel<TA, 1>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        case 2: hipLaunchKernelGGL((gram_mfma_kernel<TA, 2>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        case 3: hipLaunchKernelGGL((gram_mfma_kernel<TA, 3>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        default: hipLaunchKernelGGL((gram_mfma_kernel<TA, 4>), dim3(grid), dim3(64), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 1: hipLaunchKernelGGL((gram_mfma_kernel<TA, 1>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 2: hipLaunchKernelGGL((gram_mfma_kernel<TA, 2>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 3: hipLaunchKernelGGL((gram_mfma_kernel<TA, 3>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        default: hipLaunchKernelGGL((gram_mfma_kernel<TA, 4>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
     }
 }
 
 void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, const double* B, int ldb,
                  double* partial, int npart, double* C) {
-    // 64 rows per wave (4 unrolled k-steps of 4 rows), at most npart waves
+    // at least 64 rows per workgroup (one k-step per wavefront and in-flight slot), at
+    // most npart workgroups
     int chunk = 64;
     while ((n + chunk - 1) / chunk > npart) chunk *= 2;
     const int grid = (n + chunk - 1) / chunk;
