@@ -490,7 +490,13 @@ static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR&
 }
 
 // ---- numeric pieces ------------------------------------------------------------
-static inline double* colp(double* base, int c) { return base + c; }
+// The blocks W = [X | P | T], K W and M W are stored as consecutive row-major n x s
+// blocks (column c of W lies in block c / s), so a kernel that touches one block reads
+// and writes whole rows of it.
+static inline double* blkp(const bpjd_problem* p, double* base, int c) {
+    return base + (size_t)(c / p->s) * p->n * p->s;
+}
+static inline BlockGeom wgeom(const bpjd_problem* p) { return BlockGeom{p->s, p->s, (long long)p->n * p->s}; }
 
 // HIP-event timing of solve phases (bpjd_opts.profile).  Events come from a
 // pool; elapsed times are collected at the host synchronisation point of
@@ -621,25 +627,27 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
 // passes applied to T, K T and M T alike.
 static void orthonormalize_T(bpjd_problem* p, int b, int ct, PhaseTimer* T) {
     hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, ld = 3 * s;
+    const int n = p->n, s = p->s;
+    const BlockGeom g = wgeom(p);
     double *W = p->W[b], *KW = p->KW[b], *MW = p->MW[b];
+    double* T0 = blkp(p, W, ct);
     const double* src1[1] = {W};
-    double* dst1[1] = {colp(W, ct)};
-    double* dst3[3] = {colp(W, ct), colp(KW, ct), colp(MW, ct)};
+    double* dst1[1] = {T0};
+    double* dst3[3] = {T0, blkp(p, KW, ct), blkp(p, MW, ct)};
     PH_BEGIN(T, BPJD_PHASE_ORTHO);
     for (int pass = 0; pass < 2 && ct > 0; ++pass) {
-        launch_gram(st, n, ct, s, MW, ld, colp(W, ct), ld, p->partial, p->npart, p->csmall);
-        launch_gemm_rows(st, n, ct, s, -1.0, src1, dst1, 1, ld, p->csmall, 1.0, ld);
+        launch_gram(st, n, ct, s, MW, T0, g, p->partial, p->npart, p->csmall);
+        launch_gemm_rows(st, n, ct, s, -1.0, src1, dst1, 1, g, p->csmall, 1.0);
     }
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_SPMM);
-    launch_spmm_km(st, n, p->rowptr, p->col, p->km, colp(W, ct), ld, s, colp(KW, ct), ld, colp(MW, ct), ld);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, T0, s, s, dst3[1], s, dst3[2], s);
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_ORTHO);
     for (int pass = 0; pass < 2; ++pass) {
-        launch_gram(st, n, s, s, colp(W, ct), ld, colp(MW, ct), ld, p->partial, p->npart, p->gsmall);
+        launch_gram(st, n, s, s, T0, dst3[2], g, p->partial, p->npart, p->gsmall);
         launch_cholqr_coef(st, s, p->gsmall, p->csmall, p->dropped[b] + ct, p->status);
-        launch_rightmul_rows(st, n, s, dst3, 3, ld, p->csmall);
+        launch_rightmul_rows(st, n, s, dst3, 3, g, p->csmall);
     }
     PH_END(T);
 }
@@ -647,14 +655,15 @@ static void orthonormalize_T(bpjd_problem* p, int b, int ct, PhaseTimer* T) {
 // Rayleigh-Ritz on W = buffer a (m columns), new X (and P when with_p) into buffer b.
 static void rayleigh_ritz(bpjd_problem* p, int a, int b, int m, int with_p, PhaseTimer* T) {
     hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, ld = 3 * s;
+    const int n = p->n, s = p->s;
+    const BlockGeom g = wgeom(p);
     PH_BEGIN(T, BPJD_PHASE_RR);
-    launch_gram(st, n, m, m, p->W[a], ld, p->KW[a], ld, p->partial, p->npart, p->Hm);
+    launch_gram(st, n, m, m, p->W[a], p->KW[a], g, p->partial, p->npart, p->Hm);
     launch_rr_coef(st, m, s, with_p, p->Hm, p->dropped[a], p->dropped[b], p->theta, p->lam, p->Cfull);
     const int cw = with_p ? 2 * s : s;
     const double* src3[3] = {p->W[a], p->KW[a], p->MW[a]};
     double* dst3[3] = {p->W[b], p->KW[b], p->MW[b]};
-    launch_gemm_rows(st, n, m, cw, 1.0, src3, dst3, 3, ld, p->Cfull, 0.0, ld);
+    launch_gemm_rows(st, n, m, cw, 1.0, src3, dst3, 3, g, p->Cfull, 0.0);
     PH_END(T);
 }
 
@@ -679,15 +688,15 @@ static int run_setup(bpjd_problem* p) {
 // caller block X_init, W^0 = span{P Y_s, X_init} and a Rayleigh-Ritz step.
 static int start_block(bpjd_problem* p) {
     hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, ld = 3 * s;
+    const int n = p->n, s = p->s, ld = s;
     BPJD_HIP(hipMemsetAsync(p->dropped[0], 0, 64 * sizeof(int), st));
     BPJD_HIP(hipMemsetAsync(p->dropped[1], 0, 64 * sizeof(int), st));
     launch_csr_dense(st, n, p->Pptr, p->Pcol, p->Pval, p->Y, p->nH, s, p->W[0], ld, false);
     launch_copy_cols(st, 1, s, p->lamH, s, p->lam, s);
     launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0], ld, s, p->KW[0], ld, p->MW[0], ld);
     if (p->n_init) {
-        BPJD_HIP(hipMemcpyAsync(p->Z, p->X_init.data(), sizeof(double) * n * s, hipMemcpyHostToDevice, st));
-        launch_copy_cols(st, n, s, p->Z, s, p->W[0] + s, ld);
+        BPJD_HIP(hipMemcpyAsync(blkp(p, p->W[0], s), p->X_init.data(), sizeof(double) * n * s,
+                                hipMemcpyHostToDevice, st));
         orthonormalize_T(p, 0, s, nullptr);
         rayleigh_ritz(p, 0, 1, 2 * s, 0, nullptr);
         // result in buffer 1: move it back to buffer 0 (the iteration starts from buffer 0)
@@ -706,7 +715,7 @@ struct IterState {
 
 static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem, bpjd_stats* stats) {
     hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, k = p->k, ld = 3 * s;
+    const int n = p->n, s = p->s, k = p->k, ld = s;   // X: block 0 of W, K W, M W
     const bool uu = p->opts.subspace == BPJD_SUBSPACE_UU;
     // events are released on every exit path
     struct Events {
@@ -793,7 +802,7 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
         // The projection (I - X X^T M) of Step 2 is the first Gram-Schmidt pass of
         // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
         const int ct = s + S.np;
-        apply_precond(p, p->F, p->W[a] + ct, ld, T);
+        apply_precond(p, p->F, blkp(p, p->W[a], ct), s, T);
         // Step 3: Rayleigh-Ritz on W = [X | P | T]
         orthonormalize_T(p, a, ct, T);
         rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, T);
@@ -1023,7 +1032,7 @@ int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* la
     if (!p || !X || !lambda || !Z) return fail(BPJD_ERR_ARG, "NULL argument");
     if (!p->setup_done) return fail(BPJD_ERR_STATE, "call bpjd_setup first");
     hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, ld = 3 * s;
+    const int n = p->n, s = p->s, ld = s;
     const hipMemcpyKind kin = mem == BPJD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     BPJD_HIP(hipMemcpyAsync(p->Z, X, sizeof(double) * n * s, kin, st));
     BPJD_HIP(hipMemcpyAsync(p->lam, lambda, sizeof(double) * s, kin, st));

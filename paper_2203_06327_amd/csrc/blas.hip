@@ -162,11 +162,16 @@ void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, co
 typedef double dx4_t __attribute__((ext_vector_type(4)));
 
 template <int TA, int TB>
-__global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, const double* __restrict__ A, int lda,
-                                                        const double* __restrict__ B, int ldb, int chunk,
+__global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, const double* __restrict__ A,
+                                                        const double* __restrict__ B, BlockGeom g, int chunk,
                                                         double* __restrict__ partial) {
     __shared__ double red[3][TA * TB * 4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    long long oa[TA], ob[TB];                   // column offsets of this lane's elements
+#pragma unroll
+    for (int p = 0; p < TA; ++p) oa[p] = g.col_offset(16 * p + lr);
+#pragma unroll
+    for (int q = 0; q < TB; ++q) ob[q] = g.col_offset(16 * q + lr);
     const int r0 = blockIdx.x * chunk;
     const int r1 = min(n, r0 + chunk);
     dx4_t acc[TA][TB];
@@ -184,12 +189,12 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, con
 #pragma unroll
             for (int p = 0; p < TA; ++p) {
                 const int c = 16 * p + lr;
-                av[u][p] = (rok && c < a) ? A[(long long)rr * lda + c] : 0.0;
+                av[u][p] = (rok && c < a) ? A[oa[p] + (long long)rr * g.ld] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < TB; ++q) {
                 const int c = 16 * q + lr;
-                bv[u][q] = (rok && c < b) ? B[(long long)rr * ldb + c] : 0.0;
+                bv[u][q] = (rok && c < b) ? B[ob[q] + (long long)rr * g.ld] : 0.0;
             }
         }
 #pragma unroll
@@ -225,17 +230,17 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, con
 }
 
 template <int TA>
-static void gram_dispatch_b(hipStream_t st, int TB, int grid, int n, int a, int b, const double* A, int lda,
-                            const double* B, int ldb, int chunk, double* partial) {
+static void gram_dispatch_b(hipStream_t st, int TB, int grid, int n, int a, int b, const double* A,
+                            const double* B, BlockGeom g, int chunk, double* partial) {
     switch (TB) {
-        case 1: hipLaunchKernelGGL((gram_mfma_kernel<TA, 1>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        case 2: hipLaunchKernelGGL((gram_mfma_kernel<TA, 2>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        case 3: hipLaunchKernelGGL((gram_mfma_kernel<TA, 3>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        default: hipLaunchKernelGGL((gram_mfma_kernel<TA, 4>), dim3(grid), dim3(256), 0, st, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 1: hipLaunchKernelGGL((gram_mfma_kernel<TA, 1>), dim3(grid), dim3(256), 0, st, n, a, b, A, B, g, chunk, partial); break;
+        case 2: hipLaunchKernelGGL((gram_mfma_kernel<TA, 2>), dim3(grid), dim3(256), 0, st, n, a, b, A, B, g, chunk, partial); break;
+        case 3: hipLaunchKernelGGL((gram_mfma_kernel<TA, 3>), dim3(grid), dim3(256), 0, st, n, a, b, A, B, g, chunk, partial); break;
+        default: hipLaunchKernelGGL((gram_mfma_kernel<TA, 4>), dim3(grid), dim3(256), 0, st, n, a, b, A, B, g, chunk, partial); break;
     }
 }
 
-void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, const double* B, int ldb,
+void launch_gram(hipStream_t st, int n, int a, int b, const double* A, const double* B, BlockGeom g,
                  double* partial, int npart, double* C) {
     // at least 64 rows per workgroup (one k-step per wavefront and in-flight slot), at
     // most npart workgroups
@@ -244,10 +249,10 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, 
     const int grid = (n + chunk - 1) / chunk;
     const int TA = (a + 15) / 16, TB = (b + 15) / 16;
     switch (TA) {
-        case 1: gram_dispatch_b<1>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        case 2: gram_dispatch_b<2>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        case 3: gram_dispatch_b<3>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
-        default: gram_dispatch_b<4>(st, TB, grid, n, a, b, A, lda, B, ldb, chunk, partial); break;
+        case 1: gram_dispatch_b<1>(st, TB, grid, n, a, b, A, B, g, chunk, partial); break;
+        case 2: gram_dispatch_b<2>(st, TB, grid, n, a, b, A, B, g, chunk, partial); break;
+        case 3: gram_dispatch_b<3>(st, TB, grid, n, a, b, A, B, g, chunk, partial); break;
+        default: gram_dispatch_b<4>(st, TB, grid, n, a, b, A, B, g, chunk, partial); break;
     }
     launch_reduce(st, grid, a * b, partial, C);
 }
@@ -270,8 +275,8 @@ constexpr int GR_MAXC = 48;
 // and C (a x b).  Thread t owns the output column t % b of rows t / b, t / b + 256 / b,
 // ... (one integer division per thread), so the result is written straight from
 // registers with row-contiguous stores and no second LDS buffer is needed.
-__global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, double alpha, Triple T, int lda,
-                                                        const double* __restrict__ C, double beta, int ldy) {
+__global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, double alpha, Triple T, BlockGeom g,
+                                                        const double* __restrict__ C, double beta) {
     extern __shared__ double gr_smem[];
     double* sA = gr_smem;                      // [GR_ROWS][a + 1]
     double* sC = gr_smem + GR_ROWS * (a + 1);  // [a][b]
@@ -284,10 +289,11 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
     {
         const int rpp = 256 / a;               // rows per pass of the load
         const int p = t % a, rr0 = t / a;
+        const long long op = g.col_offset(p);
         if (rr0 < rpp) {
             for (int rr = rr0; rr < GR_ROWS; rr += rpp) {
                 const int r = r0 + rr;
-                sA[rr * ap + p] = (r < n) ? A[(long long)r * lda + p] : 0.0;
+                sA[rr * ap + p] = (r < n) ? A[op + (long long)r * g.ld] : 0.0;
             }
         }
     }
@@ -295,13 +301,14 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
     const int rpp = 256 / b;
     const int q = t % b, rr0 = t / b;
     if (rr0 >= rpp) return;
+    const long long oq = g.col_offset(q);
     for (int rr = rr0; rr < GR_ROWS; rr += rpp) {
         const int r = r0 + rr;
         if (r >= n) break;
         const double* arow = sA + rr * ap;
         double acc = 0.0;
         for (int k = 0; k < a; ++k) acc = fma(arow[k], sC[k * b + q], acc);
-        double* y = Y + (long long)r * ldy + q;
+        double* y = Y + oq + (long long)r * g.ld;
         *y = (beta == 0.0) ? alpha * acc : fma(beta, *y, alpha * acc);
     }
 }
@@ -309,80 +316,24 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
 static size_t gemm_rows_smem(int a, int b) { return sizeof(double) * ((size_t)GR_ROWS * (a + 1) + (size_t)a * b); }
 
 void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
-                      int count, int lda, const double* C, double beta, int ldy) {
+                      int count, BlockGeom g, const double* C, double beta) {
     Triple T{};
     for (int k = 0; k < count; ++k) {
         T.A[k] = A[k];
         T.Y[k] = Y[k];
     }
     hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(a, b), st, n, a,
-                       b, alpha, T, lda, C, beta, ldy);
+                       b, alpha, T, g, C, beta);
 }
 
-void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, int ldy, const double* C) {
+void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, BlockGeom g, const double* C) {
     Triple T{};
     for (int k = 0; k < count; ++k) {
         T.A[k] = Y[k];
         T.Y[k] = Y[k];
     }
     hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(b, b), st, n, b,
-                       b, 1.0, T, ldy, C, 0.0, ldy);
-}
-
-// ---------------------------------------------------------------------------
-__global__ void gemm_small_kernel(int n, int a, int b, int cshift, double alpha, const double* __restrict__ A,
-                                  int lda, const double* __restrict__ C, double beta, double* __restrict__ Y,
-                                  int ldy) {
-    __shared__ double sC[64 * 64];
-    for (int idx = threadIdx.x; idx < a * b; idx += blockDim.x) sC[idx] = C[idx];
-    __syncthreads();
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = t >> cshift;
-    const int q = t & ((1 << cshift) - 1);
-    if (r >= n || q >= b) return;
-    const double* arow = A + (long long)r * lda;
-    double acc = 0.0;
-    for (int p = 0; p < a; ++p) acc = fma(arow[p], sC[p * b + q], acc);
-    double* y = Y + (long long)r * ldy + q;
-    *y = (beta == 0.0) ? alpha * acc : fma(beta, *y, alpha * acc);
-}
-
-void launch_gemm_small(hipStream_t st, int n, int a, int b, double alpha, const double* A, int lda,
-                       const double* C, double beta, double* Y, int ldy) {
-    const int cp = pow2_at_least(b);
-    int sh = 0;
-    while ((1 << sh) < cp) ++sh;
-    const long long work = (long long)n << sh;
-    hipLaunchKernelGGL(gemm_small_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, n, a, b, sh, alpha, A, lda, C,
-                       beta, Y, ldy);
-}
-
-// In-place Y = Y * C (C b x b): a block stages 256/bpad rows of Y in LDS.
-__global__ void rightmul_kernel(int n, int b, int cshift, double* __restrict__ Y, int ldy,
-                                const double* __restrict__ C) {
-    __shared__ double sC[64 * 64];
-    __shared__ double sY[256];
-    for (int idx = threadIdx.x; idx < b * b; idx += blockDim.x) sC[idx] = C[idx];
-    const int rows = blockDim.x >> cshift;
-    const int rr = threadIdx.x >> cshift;
-    const int q = threadIdx.x & ((1 << cshift) - 1);
-    const int r = blockIdx.x * rows + rr;
-    double* yrow = Y + (long long)r * ldy;
-    sY[threadIdx.x] = (r < n && q < b) ? yrow[q] : 0.0;
-    __syncthreads();
-    if (r >= n || q >= b) return;
-    double acc = 0.0;
-    const double* srow = sY + (rr << cshift);
-    for (int p = 0; p < b; ++p) acc = fma(srow[p], sC[p * b + q], acc);
-    yrow[q] = acc;
-}
-
-void launch_rightmul_inplace(hipStream_t st, int n, int b, double* Y, int ldy, const double* C) {
-    const int cp = pow2_at_least(b);
-    int sh = 0;
-    while ((1 << sh) < cp) ++sh;
-    const int rows = 256 >> sh;
-    hipLaunchKernelGGL(rightmul_kernel, dim3(grid_for(n, rows)), dim3(256), 0, st, n, b, sh, Y, ldy, C);
+                       b, 1.0, T, g, C, 0.0);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,6 +45,16 @@ inline int grid_for(long long work, int block) {
     return (int)g;
 }
 
+// Column-blocked n x (blocks * bw) matrices: element (r, c) lies at
+// (c / bw) * bs + r * ld + c % bw, i.e. consecutive row-major n x bw blocks (ld = bw,
+// bs = n * bw).  A plain row-major matrix is bw >= its column count, bs unused.
+struct BlockGeom {
+    int ld;
+    int bw;
+    long long bs;
+    __host__ __device__ long long col_offset(int c) const { return (long long)(c / bw) * bs + c % bw; }
+};
+
 // ---- launchers: block linear algebra (blas.hip) -------------------------------
 // KX = K X, MX = M X on the union pattern (km holds (K, M) value pairs).
 void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, const double2* km,
@@ -57,19 +67,17 @@ void launch_csr_dense(hipStream_t st, int rows, const int* ptr, const int* col, 
 void launch_residual(hipStream_t st, int n, int s, const double* KX, int ldk, const double* MX, int ldm,
                      const double* lam, double* F, int ldf, double* partial, int npart, double* colsq, double* aux,
                      const int* status);
-// C (a x b, row-major) = A^T B with A: n x a (lda), B: n x b (ldb); deterministic two-pass.
-void launch_gram(hipStream_t st, int n, int a, int b, const double* A, int lda, const double* B, int ldb,
+// C (a x b, row-major) = A^T B with A: n x a, B: n x b, both laid out as g; deterministic
+// two-pass.
+void launch_gram(hipStream_t st, int n, int a, int b, const double* A, const double* B, BlockGeom g,
                  double* partial, int npart, double* C);
-// Y(:, 0..b) = beta*Y + alpha * A(:, 0..a) * C, C a x b row-major (ldc = b).
-void launch_gemm_small(hipStream_t st, int n, int a, int b, double alpha, const double* A, int lda,
-                       const double* C, double beta, double* Y, int ldy);
-// Batched over up to three (A, Y) pairs sharing C: Y_k = beta Y_k + alpha A_k C (b <= 48).
+// Y(:, 0..b) = beta*Y + alpha * A(:, 0..a) * C, C a x b row-major (ldc = b), A and Y laid
+// out as g.  Batched over up to three (A, Y) pairs sharing C: Y_k = beta Y_k + alpha A_k C
+// (a, b <= 48).
 void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
-                      int count, int lda, const double* C, double beta, int ldy);
-// Batched in place Y_k = Y_k C (b <= 24).
-void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, int ldy, const double* C);
-// In place: Y(:, 0..b) = Y(:, 0..b) * C, C b x b row-major.
-void launch_rightmul_inplace(hipStream_t st, int n, int b, double* Y, int ldy, const double* C);
+                      int count, BlockGeom g, const double* C, double beta);
+// Batched in place Y_k = Y_k C (b <= 48), Y laid out as g.
+void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, BlockGeom g, const double* C);
 // Copy/convert helpers.
 void launch_copy_cols(hipStream_t st, int n, int ncols, const double* src, int lds, double* dst, int ldd);
 void launch_fill(hipStream_t st, long long count, double* dst, double value);
