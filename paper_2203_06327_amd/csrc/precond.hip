@@ -753,9 +753,38 @@ __global__ void scatter_kernel(int n, int s, long long sumN, const int* __restri
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)n * s) return;
     const int d = (int)(t / s), i = (int)(t % s);
+    const int p0 = Pptr[d], p1 = Pptr[d + 1], e0 = rptr[d], e1 = rptr[d + 1];
     double acc = 0.0;
-    for (int q = Pptr[d]; q < Pptr[d + 1]; ++q) acc = fma(Pval[q], Zhat[Pcol[q] * s + i], acc);
-    for (int e = rptr[d]; e < rptr[d + 1]; ++e) acc += (double)zloc[(long long)i * sumN + ridx[e]];
+    // groups of 4 entries: indices clamped into the row, every load of a group issued
+    // before the first product, sums in entry order
+    for (int qb = p0; qb < p1; qb += 4) {
+        const int cnt = min(4, p1 - qb);
+        int pc[4];
+        double pv[4], zh[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = qb + min(u, cnt - 1);
+            pc[u] = Pcol[q];
+            pv[u] = Pval[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) zh[u] = Zhat[pc[u] * s + i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < cnt) acc = fma(pv[u], zh[u], acc);
+    }
+    for (int eb = e0; eb < e1; eb += 4) {
+        const int cnt = min(4, e1 - eb);
+        int ri[4];
+        T zv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ri[u] = ridx[eb + min(u, cnt - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) zv[u] = zloc[(long long)i * sumN + ri[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < cnt) acc += (double)zv[u];
+    }
     Z[(long long)d * ldz + i] = acc;
 }
 
