@@ -70,6 +70,9 @@ extern "C" {
 #define BPJD_PREC_FP64   0      /* everything in FP64 */
 #define BPJD_PREC_MIXED  1      /* local factor/solve in FP32; residual, projection, coarse solve, RR in FP64 */
 
+/* largest block size s = k + guard (the Rayleigh-Ritz problem has dimension <= 3 s) */
+#define BPJD_MAX_BLOCK   18
+
 typedef struct bpjd_ctx bpjd_ctx;
 typedef struct bpjd_problem bpjd_problem;
 typedef struct bpjd_server bpjd_server;
@@ -111,7 +114,8 @@ typedef struct {
 
 typedef struct {
     int32_t k;                  /* eigenpairs wanted (>= 1) */
-    int32_t guard;              /* extra block columns: block size s = k + guard (Assumption 1 remark) */
+    int32_t guard;              /* extra block columns: block size s = k + guard <= BPJD_MAX_BLOCK
+                                   (Assumption 1 remark) */
     int32_t max_iter;           /* outer iterations before BPJD_ERR_NOCONV */
     double  tol;                /* tolerance of the stop rule */
     int32_t stop_rule;          /* BPJD_STOP_* */

@@ -240,7 +240,8 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     const int nsub = (int)sptr.size() - 1;
     if (nsub < 1) return fail(BPJD_ERR_DD, "no subdomains");
     const int s = opts->k + opts->guard;
-    if (opts->k < 1 || opts->guard < 0 || s > 16) return fail(BPJD_ERR_ARG, "need 1 <= k and k + guard <= 16");
+    if (opts->k < 1 || opts->guard < 0 || s > BPJD_MAX_BLOCK)
+        return fail(BPJD_ERR_ARG, "need 1 <= k and k + guard <= " + std::to_string(BPJD_MAX_BLOCK));
     if (s >= nH) return fail(BPJD_ERR_DD, "block size s must be smaller than dim V^H");
     if (nH > 1024) return fail(BPJD_ERR_DD, "coarse space larger than 1024 is not supported");
     if (opts->n_init != 0 && opts->n_init != s) return fail(BPJD_ERR_ARG, "n_init must be 0 or k + guard");

@@ -258,7 +258,7 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Tall-times-small products Y = beta Y + alpha A C (a <= 48, b <= 48): a block
+// Tall-times-small products Y = beta Y + alpha A C (a, b <= 64): a block
 // stages 64 rows of A and the coefficients in LDS with coalesced loads, forms
 // the 64 x b result in LDS and writes it back row-contiguously.  Up to three
 // (A, Y) pairs share one launch (blockIdx.y); with A == Y (in-place Y = Y C)
@@ -269,7 +269,7 @@ struct Triple {
 };
 
 constexpr int GR_ROWS = 64;
-constexpr int GR_MAXC = 48;
+constexpr int GR_MAXC = 64;
 
 // Dynamic LDS: the block's A rows (GR_ROWS x (a + 1), padded against bank conflicts)
 // and C (a x b).  Thread t owns the output column t % b of rows t / b, t / b + 256 / b,

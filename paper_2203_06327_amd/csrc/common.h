@@ -73,10 +73,10 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, const dou
                  double* partial, int npart, double* C);
 // Y(:, 0..b) = beta*Y + alpha * A(:, 0..a) * C, C a x b row-major (ldc = b), A and Y laid
 // out as g.  Batched over up to three (A, Y) pairs sharing C: Y_k = beta Y_k + alpha A_k C
-// (a, b <= 48).
+// (a, b <= 64).
 void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
                       int count, BlockGeom g, const double* C, double beta);
-// Batched in place Y_k = Y_k C (b <= 48), Y laid out as g.
+// Batched in place Y_k = Y_k C (b <= 64), Y laid out as g.
 void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, BlockGeom g, const double* C);
 // Copy/convert helpers.
 void launch_copy_cols(hipStream_t st, int n, int ncols, const double* src, int lds, double* dst, int ldd);

@@ -8,7 +8,7 @@
 
 namespace bpjd {
 
-constexpr int RR_MAX = 48;           // largest Rayleigh-Ritz dimension (3 s, s <= 16)
+constexpr int RR_MAX = 3 * BPJD_MAX_BLOCK;   // largest Rayleigh-Ritz dimension (3 s)
 // up to this order the reduction to tridiagonal form runs in one workgroup; above it,
 // two launches per column spread the trailing update over all compute units
 constexpr int TRIDIAG_ONE_WG_MAX = 320;
@@ -1266,7 +1266,7 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 // four wavefronts.  The loops stay compact: the kernel runs once per iteration, so
 // fully unrolled code would be fetched from L2 instruction by instruction.
 // Outputs theta[0..s) ascending (theta[s..m) = +inf) and Cfull = [Q_s | C_p] (m x cw).
-constexpr int RR_S_MAX = 16;
+constexpr int RR_S_MAX = BPJD_MAX_BLOCK;
 
 __device__ inline double lane_bcast(double v, int l) {
     const long long b = __double_as_longlong(v);
@@ -1376,7 +1376,7 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
     // 2. the ns lowest eigenvalues: G threads per eigenvalue (G divides 64)
     {
-        const int G = (ns <= 8) ? 32 : 16;
+        const int G = (ns <= 8) ? 32 : ((ns <= 16) ? 16 : 8);
         const int j = t / G, r = t % G;
         const int gl = (t & 63) - r;
         bool done = j >= ns;
@@ -1555,9 +1555,12 @@ void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, c
     if (m <= 24)
         hipLaunchKernelGGL(rr_coef_kernel<24>, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta,
                            lam, Cfull);
+    else if (m <= 48)
+        hipLaunchKernelGGL(rr_coef_kernel<48>, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta,
+                           lam, Cfull);
     else
-        hipLaunchKernelGGL(rr_coef_kernel<RR_MAX>, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out,
-                           theta, lam, Cfull);
+        hipLaunchKernelGGL(rr_coef_kernel<64>, dim3(1), dim3(256), 0, st, m, s, with_p, H, drop_in, drop_out, theta,
+                           lam, Cfull);
 }
 
 }  // namespace bpjd

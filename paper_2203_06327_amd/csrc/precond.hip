@@ -166,23 +166,24 @@ __global__ void coarse_coef_kernel(int nH, int s, const double* __restrict__ YT,
 }
 
 // Zhat[b][i] = sum_{j >= s} Y[b][j] Cw[j][i]: one wavefront per coarse row b reads the
-// row contiguously, keeps s (<= 16) partial sums per lane and reduces them across lanes.
+// row contiguously, keeps s (<= BPJD_MAX_BLOCK) partial sums per lane and reduces them
+// across lanes.
 __global__ __launch_bounds__(64) void coarse_back_kernel(int nH, int s, const double* __restrict__ Y,
                                                          const double* __restrict__ Cw, double* __restrict__ Zhat) {
     const int b = blockIdx.x, lane = threadIdx.x;
     const double* yrow = Y + (long long)b * nH;
-    double acc[16];
+    double acc[BPJD_MAX_BLOCK];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int i = 0; i < BPJD_MAX_BLOCK; ++i) acc[i] = 0.0;
     for (int j = s + lane; j < nH; j += 64) {
         const double y = yrow[j];
         const double* c = Cw + j * s;
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
             if (i < s) acc[i] = fma(y, c[i], acc[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < BPJD_MAX_BLOCK; ++i) {
         if (i >= s) break;
         double v = acc[i];
 #pragma unroll

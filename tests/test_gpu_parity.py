@@ -172,3 +172,21 @@ def test_coarse_eigenvalues_large(B, ctx, name):
     print(f"  n_H={lamH.size} max rel err {err:.3e}", flush=True)
     assert err < 1e-11
     prob.close()
+
+
+def test_solve_largest_block(B, ctx):
+    """k = 16 with guard 2 (s = 18, Rayleigh-Ritz dimension 54) on a rectangle of the
+    served family (h = 1/64, H = 1/8, two overlap layers): eigenvalues against the
+    reference eigensolver."""
+    req = dict(Lx=1.0, Ly=1.5, Nx=64, Ny=96, coarse=8, L=2, k=16, guard=2)
+    mesh = w.p1_mesh(req["Lx"], req["Ly"], req["Nx"], req["Ny"], req["coarse"])
+    _case(f"largest block: n={mesh.K.shape[0]} k=16 guard=2")
+    prob = B.problem_from_mesh(ctx, mesh, req["L"], k=req["k"], guard=req["guard"], precision=B.PREC_MIXED)
+    assert prob.s == 18
+    lam, X, st = prob.solve()
+    prob.close()
+    ref = o.reference_eigs(mesh.K, mesh.M, req["k"])[0]
+    assert st["max_residual"] <= 1e-8
+    assert np.max(np.abs(lam - ref) / ref) < 1e-9
+    G = X.T @ (mesh.M @ X)
+    assert np.max(np.abs(G - np.eye(req["k"]))) < 1e-10
