@@ -139,6 +139,140 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
 
 
+def _request_mesh(req):
+    from paper_2203_06327_amd import workloads as w
+    return w.request_mesh(req)
+
+
+def build_served_meshes(count: int, workers: int = 8):
+    """Meshes of the served mix (assembled on the host in worker processes started
+    before the GPU is touched)."""
+    import multiprocessing as mp
+    from paper_2203_06327_amd import workloads as w
+    reqs = w.serving_requests(count)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        meshes = pool.map(_request_mesh, reqs, chunksize=1)
+    return reqs, meshes
+
+
+def _wait(srv, ids, done_at=None):
+    out = {}
+    pending = list(ids)
+    while pending:
+        left = []
+        for i in pending:
+            r = srv.poll(i, raise_noconv=False)
+            if r is None:
+                left.append(i)
+            else:
+                out[i] = r
+                if done_at is not None:
+                    done_at[i] = time.perf_counter()
+        pending = left
+        if pending:
+            time.sleep(0.0005)
+    return out
+
+
+def serving_bench(B, ctx, reqs, meshes, budget: int, slots: int, rate_frac: float = 0.7):
+    """The served mix three ways: plain FP64 solves one request at a time (host CSR in,
+    eigenpairs in host memory), the mixed-precision server with every request
+    submitted at once (saturated throughput mu), and the server under Poisson
+    arrivals at rate_frac * mu (latency percentiles)."""
+    ks = np.array([r["k"] for r in reqs])
+    total_k = int(ks.sum())
+    # (i) plain FP64, one request at a time
+    t0 = time.perf_counter()
+    plain = []
+    log = open(os.path.join(ROOT, "gpurun_out", "served_plain_fp64.tsv"), "w") if os.path.isdir(
+        os.path.join(ROOT, "gpurun_out")) else None
+    for j, (r, mesh) in enumerate(zip(reqs, meshes)):
+        ts = time.perf_counter()
+        prob = B.problem_from_mesh(ctx, mesh, r["L"], k=r["k"], guard=r["guard"], precision=B.PREC_FP64)
+        tc = time.perf_counter()
+        lam, _, st = prob.solve(raise_noconv=False)
+        plain.append((lam, st))
+        prob.close()
+        if log:
+            log.write(f"{j}\t{r['Nx']}\t{mesh.n}\t{r['k']}\t{st['iterations']}\t{st['converged']}\t"
+                      f"{1e3 * (tc - ts):.1f}\t{1e3 * (time.perf_counter() - tc):.1f}\t{st['max_band']}\n")
+            log.flush()
+        if (j + 1) % 16 == 0:
+            print(f"[bench] plain FP64: {j + 1} requests, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
+    t_plain = time.perf_counter() - t0
+    print(f"[bench] served mix, plain FP64 one at a time: {t_plain:.2f} s", file=sys.stderr, flush=True)
+
+    # (ii) server, burst: all requests at t = 0
+    srv = B.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    ids = [srv.submit_mesh(mesh, r["L"], k=r["k"], guard=r["guard"], precision=B.PREC_MIXED)
+           for r, mesh in zip(reqs, meshes)]
+    res = _wait(srv, ids)
+    t_burst = time.perf_counter() - t0
+    info_burst = srv.info()
+    srv.close()
+    mu = len(reqs) / t_burst
+    print(f"[bench] served mix, server burst: {t_burst:.2f} s", file=sys.stderr, flush=True)
+    rel = max(float(np.max(np.abs(res[i][0] - p[0]) / np.abs(p[0]))) for i, p in zip(ids, plain))
+    rmax = max(res[i][2]["max_residual"] for i in ids)
+    unconverged = sum(1 for i in ids if not res[i][2]["converged"]) + sum(1 for p in plain if not p[1]["converged"])
+
+    # (iii) server, Poisson arrivals at rate_frac * mu
+    rate = rate_frac * mu
+    gaps = np.random.default_rng(2203).exponential(1.0 / rate, size=len(reqs))
+    arrive = np.cumsum(gaps) - gaps[0]
+    srv = B.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    ids2 = []
+    done_at, out2 = {}, {}
+    for j, (r, mesh) in enumerate(zip(reqs, meshes)):
+        while time.perf_counter() - t0 < arrive[j]:
+            ready = _poll_some(srv, ids2, out2, done_at)
+            if not ready:
+                time.sleep(0.0002)
+        ids2.append(srv.submit_mesh(mesh, r["L"], k=r["k"], guard=r["guard"], precision=B.PREC_MIXED))
+    out2.update(_wait(srv, [i for i in ids2 if i not in out2], done_at))
+    t_poisson = time.perf_counter() - t0
+    info_p = srv.info()
+    srv.close()
+    lat = np.array([out2[i][2]["latency_ms"] for i in ids2])
+    qms = np.array([out2[i][2]["queue_ms"] for i in ids2])
+    print(f"[bench] served mix, Poisson arrivals: {t_poisson:.2f} s", file=sys.stderr, flush=True)
+    return {
+        "workload": (f"{len(reqs)} requests: -div(a grad u) = lambda u on [0,1]x[0,r], r~U[1,2], a piecewise "
+                     f"constant on 4x4 blocks, log-uniform in [0.1,10], P1, h in 1/64..1/512, k in 4..16 "
+                     f"(guard 2), H=1/8, delta=2h"),
+        "requests": len(reqs), "eigenpairs": total_k, "dofs_total": int(sum(m.n for m in meshes)),
+        "hbm_budget_bytes": budget, "slots": slots,
+        "plain_fp64_one_at_a_time": {"value": total_k / t_plain, "unit": "eigenpairs/s", "wall_s": t_plain},
+        "served_mixed_burst": {"value": total_k / t_burst, "unit": "eigenpairs/s", "wall_s": t_burst,
+                               "requests_per_s": mu, "peak_running": info_burst["peak_running"],
+                               "peak_bytes": info_burst["peak_bytes"]},
+        "speedup_vs_plain_fp64": t_plain / t_burst,
+        "served_mixed_poisson": {"arrival_rate_per_s": rate, "value": total_k / t_poisson, "unit": "eigenpairs/s",
+                                 "wall_s": t_poisson, "p50_ms": float(np.percentile(lat, 50)),
+                                 "p99_ms": float(np.percentile(lat, 99)),
+                                 "queue_p50_ms": float(np.percentile(qms, 50)),
+                                 "queue_p99_ms": float(np.percentile(qms, 99)),
+                                 "peak_running": info_p["peak_running"], "peak_bytes": info_p["peak_bytes"]},
+        "max_rel_eig_diff_served_vs_plain_fp64": rel, "max_residual_served": rmax,
+        "unconverged": unconverged,
+    }
+
+
+def _poll_some(srv, ids, out, done_at):
+    got = False
+    for i in ids:
+        if i not in out:
+            r = srv.poll(i, raise_noconv=False)
+            if r is not None:
+                out[i] = r
+                done_at[i] = time.perf_counter()
+                got = True
+    return got
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +283,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the untimed per-phase profile solve")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests of the served mix (0: skip the serving measurement)")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of the server")
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling memory counters)")
     args = ap.parse_args()
@@ -156,6 +294,14 @@ def main():
         print("bench.py measures one GPU: multi-GPU runs are not part of this build (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    served = None
+    if args.serve_requests > 0 and not args.copy_calibration:
+        # host assembly of the served meshes, before anything touches the GPU
+        t0 = time.perf_counter()
+        served = build_served_meshes(args.serve_requests)
+        print(f"[bench] served mix: {len(served[0])} meshes assembled in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
 
     import torch
     if not torch.cuda.is_available():
@@ -240,6 +386,11 @@ def main():
         t1 = load_table1()[:k, 2]
         check["max_abs_err_vs_table1"] = float(np.max(np.abs(lam / np.pi ** 2 - t1)))
 
+    serving = None
+    if served is not None:
+        serving = serving_bench(B, ctx, served[0], served[1], int(args.serve_budget_gb * (1 << 30)),
+                                args.serve_slots)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(mesh, cfg, gpu_iters, args.cpu_sample_iters)
@@ -254,7 +405,7 @@ def main():
         "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "iterations": st["iterations"], "max_residual": st["max_residual"],
         "fp64": fp64, "phase_ms_per_solve": ph, "phase_launches": cnt,
-        "roofline": roofline, "roofline_spmm": roof_spmm, "cpu_baseline": cpu, **check,
+        "roofline": roofline, "roofline_spmm": roof_spmm, "cpu_baseline": cpu, "serving": serving, **check,
     }
     print(json.dumps(out), flush=True)
     prob.close()

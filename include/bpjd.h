@@ -152,6 +152,8 @@ typedef struct {
     double  residuals[64];      /* rho_i of the returned pairs, i < min(k, 64) */
     double  phase_ms[8];        /* device time per phase (profile = 1), summed over the solve */
     int32_t phase_count[8];     /* launches timed per phase */
+    double  queue_ms;           /* served requests: submission to admission (0 for bpjd_solve) */
+    double  latency_ms;         /* served requests: submission to result in host memory */
 } bpjd_stats;
 
 /* Default options: k as given, guard 0, max_iter 500, tol 1e-8, residual
@@ -183,6 +185,9 @@ int bpjd_problem_set_values(bpjd_problem* p, const double* Kval, const double* M
 /* Size queries: n (dofs), n_H, number of subdomains, block size s. */
 int bpjd_problem_dims(const bpjd_problem* p, int32_t* n, int32_t* n_coarse, int32_t* n_sub, int32_t* s);
 
+/* Device bytes the problem holds (what a server's HBM budget counts for it). */
+int bpjd_problem_footprint(const bpjd_problem* p, uint64_t* bytes);
+
 /* Subdomain sizes n_l and local half-bandwidths w_l (arrays of n_sub, host). */
 int bpjd_problem_local_sizes(const bpjd_problem* p, int32_t* n_l, int32_t* bw);
 
@@ -207,6 +212,50 @@ int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* la
 int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, double* MX, int32_t mem);
 /* Coarse eigenvalues (ascending, n_H values) from the last setup. */
 int bpjd_coarse_eigenvalues(bpjd_problem* p, double* lamH, int32_t mem);
+
+/* ---- serving: continuous batching of independent solves ------------------
+ * A server solves many problems of the form above (a stream of requests,
+ * each its own K, M, decomposition and options) on the context's GPU.
+ * Requests are admitted in submission order as soon as a solve slot is free
+ * and the request's device footprint fits the HBM budget; every admitted
+ * request runs Algorithm 3.1 on a slot of its own (its own stream), and the
+ * outer iterations of all admitted requests advance together, so their
+ * kernels overlap on the device.  A request's result does not depend on what
+ * else runs.  Served matrices and decompositions are host arrays; they are
+ * copied at submission.  Submit and poll may be called from any thread. */
+typedef struct {
+    uint64_t submitted;         /* requests accepted by bpjd_server_submit */
+    uint64_t completed;         /* requests with a final status (success or error) */
+    uint64_t failed;            /* completed with an error other than BPJD_ERR_NOCONV */
+    uint32_t queued;            /* waiting for admission */
+    uint32_t running;           /* admitted, on the device */
+    uint32_t peak_running;      /* most requests on the device at once */
+    uint32_t max_slots;
+    uint64_t budget_bytes;      /* HBM budget of admitted requests */
+    uint64_t bytes_in_use;      /* device bytes of the admitted requests */
+    uint64_t peak_bytes;        /* largest bytes_in_use seen */
+} bpjd_server_info;
+
+/* hbm_budget_bytes: device bytes all admitted requests may hold together (0:
+ * 90 % of the device memory free at creation).  max_slots: requests on the
+ * device at once, 1..64.  Errors: BPJD_ERR_ARG, _HIP. */
+int  bpjd_server_create(bpjd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots, bpjd_server** out);
+/* Queue one request; exactly one of dd / geom is given (as for
+ * bpjd_problem_create / _create_geom).  The problem is validated when it is
+ * planned for admission: errors found then (BPJD_ERR_CSR, _DD, _ARG, and
+ * BPJD_ERR_OVER_BUDGET when it can never fit the budget) are returned by
+ * bpjd_server_poll.  Errors here: BPJD_ERR_ARG, _DD, _STATE (shutting down). */
+int  bpjd_server_submit(bpjd_server* s, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
+                        const bpjd_dd_geom* geom, const bpjd_opts* opts, uint64_t* req_id);
+/* BPJD_PENDING while the request is queued or running.  Otherwise its final
+ * status (as bpjd_solve's), with eigvals (k) and eigvecs (n x k row-major)
+ * copied to the host buffers given (either may be NULL) and the request
+ * released: a later poll of the same id is BPJD_ERR_ARG. */
+int  bpjd_server_poll(bpjd_server* s, uint64_t req_id, double* eigvals, double* eigvecs, bpjd_stats* st);
+int  bpjd_server_get_info(bpjd_server* s, bpjd_server_info* out);
+/* Stops admission, waits for the solves on the device, frees everything;
+ * requests not yet polled are dropped. */
+void bpjd_server_destroy(bpjd_server* s);
 
 /* ---- errors ------------------------------------------------------------ */
 const char* bpjd_strerror(int code);

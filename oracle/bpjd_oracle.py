@@ -191,12 +191,42 @@ def coarse_term_direct(F: np.ndarray, lam: np.ndarray, cs: CoarseSetup, s: int) 
     return cs.P @ out
 
 
+def positive_definite(A) -> bool:
+    """Whether the symmetric sparse matrix A is positive definite: its Cholesky
+    factorisation (dense up to 400 rows, banded above) runs to the end."""
+    n = A.shape[0]
+    try:
+        if n <= 400:
+            np.linalg.cholesky(A.toarray())
+            return True
+        C = A.tocoo()
+        low = C.row >= C.col
+        d = C.row[low] - C.col[low]
+        ab = np.zeros((int(d.max()) + 1, n))
+        ab[d, C.col[low]] = C.data[low]
+        sla.cholesky_banded(ab, lower=True)
+        return True
+    except np.linalg.LinAlgError:
+        return False
+
+
+def local_shift(Kl, Ml, lam_i: float) -> float:
+    """Shift of one local solve: lambda_i where K_l - lambda_i M_l is positive
+    definite, as the paper's analysis has it (lambda_min(B_l,i) of order H^{-2m},
+    far above lambda_i); 0 where a subdomain breaks that premise (a strong
+    coefficient contrast puts a local Dirichlet eigenvalue below lambda_i), so that
+    the local problem stays a positive definite Schwarz solve."""
+    return lam_i if positive_definite((Kl - lam_i * Ml).tocsc()) else 0.0
+
+
 def local_term(F: np.ndarray, lam: np.ndarray, ls: LocalSetup) -> np.ndarray:
-    """sum_l R_l^T (K_l - lambda_i M_l)^{-1} R_l F_i  (unweighted sum, one shift per column)."""
+    """sum_l R_l^T (K_l - sigma_{l,i} M_l)^{-1} R_l F_i (unweighted sum), with
+    sigma_{l,i} = local_shift(K_l, M_l, lambda_i): lambda_i on every subdomain
+    where the paper's premise holds."""
     Z = np.zeros_like(F)
     for S, Kl, Ml in zip(ls.subs, ls.K_loc, ls.M_loc):
         for i in range(F.shape[1]):
-            A = (Kl - lam[i] * Ml).tocsc()
+            A = (Kl - local_shift(Kl, Ml, lam[i]) * Ml).tocsc()
             if A.shape[0] <= 400:
                 z = np.linalg.solve(A.toarray(), F[S, i])
             else:

@@ -62,7 +62,8 @@ class Stats(C.Structure):
                 ("max_residual", C.c_double), ("setup_ms", C.c_double), ("iterate_ms", C.c_double),
                 ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("max_local", C.c_int32),
                 ("max_band", C.c_int32), ("residuals", C.c_double * 64),
-                ("phase_ms", C.c_double * 8), ("phase_count", C.c_int32 * 8)]
+                ("phase_ms", C.c_double * 8), ("phase_count", C.c_int32 * 8),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
 
     def to_dict(self) -> dict:
         arrays = ("residuals", "phase_ms", "phase_count")
@@ -70,6 +71,16 @@ class Stats(C.Structure):
         for a in arrays:
             d[a] = list(getattr(self, a))
         return d
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("queued", C.c_uint32), ("running", C.c_uint32), ("peak_running", C.c_uint32),
+                ("max_slots", C.c_uint32), ("budget_bytes", C.c_uint64), ("bytes_in_use", C.c_uint64),
+                ("peak_bytes", C.c_uint64)]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 PHASES = ["local", "spmm", "coarse", "gather_scatter", "ortho", "rr", "residual", "setup"]
@@ -90,11 +101,18 @@ EXPORTS = {
     "bpjd_problem_dims": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "bpjd_problem_local_sizes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bpjd_problem_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "bpjd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Stats)]),
     "bpjd_setup": (C.c_int, [C.c_void_p]),
     "bpjd_apply_preconditioner": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "bpjd_spmm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "bpjd_coarse_eigenvalues": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "bpjd_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
+    "bpjd_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.POINTER(Csr), C.POINTER(DD), C.POINTER(DDGeom),
+                                     C.POINTER(Opts), C.POINTER(C.c_uint64)]),
+    "bpjd_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.POINTER(Stats)]),
+    "bpjd_server_get_info": (C.c_int, [C.c_void_p, C.POINTER(ServerInfo)]),
+    "bpjd_server_destroy": (None, [C.c_void_p]),
     "bpjd_strerror": (C.c_char_p, [C.c_int]),
     "bpjd_last_error": (C.c_char_p, []),
 }
@@ -241,6 +259,11 @@ class Problem:
             _check(code)
         return eigvals, eigvecs, st.to_dict()
 
+    def footprint(self) -> int:
+        b = C.c_uint64()
+        _check(lib().bpjd_problem_footprint(self.handle, C.byref(b)))
+        return b.value
+
     def local_sizes(self):
         nl = np.empty(self.n_sub, dtype=np.int32)
         bw = np.empty(self.n_sub, dtype=np.int32)
@@ -273,3 +296,82 @@ class Problem:
 def problem_from_mesh(ctx: Context, mesh, layers: int, **kw) -> Problem:
     """Problem on a structured P1 mesh (coarse grid lines and coordinates from the mesh)."""
     return Problem(ctx, mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers), **kw)
+
+
+class Server:
+    """Continuous-batching eigensolver server on one GPU (wraps bpjd_server).
+
+    ``submit`` queues a problem and returns its id; ``poll`` returns None while it is
+    queued or running, else (eigvals, eigvecs, stats dict) (raises on an error status).
+    """
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 8):
+        h = C.c_void_p()
+        _check(lib().bpjd_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self.ctx = ctx
+        self.handle = h
+        self._shape = {}
+
+    def submit(self, K, M, *, geom=None, dd=None, k: int, guard: int = 0, tol: float = 1e-8, max_iter: int = 500,
+               stop_rule: int = STOP_RESIDUAL, subspace: int = SUBSPACE_UU, precision: int = PREC_MIXED,
+               X_init: Optional[np.ndarray] = None) -> int:
+        keep: list = []
+        Kc, Mc = _csr(K, keep), _csr(M, keep)
+        opts = make_opts(k, guard, tol, max_iter, stop_rule, subspace, precision, X_init, keep, 0)
+        rid = C.c_uint64()
+        if geom is not None:
+            coords, cx, cy, layers = geom
+            coords = np.ascontiguousarray(coords, dtype=np.float64)
+            cx = np.ascontiguousarray(cx, dtype=np.float64)
+            cy = np.ascontiguousarray(cy, dtype=np.float64)
+            keep += [coords, cx, cy]
+            g = DDGeom(coords.ctypes.data, len(cx), len(cy), cx.ctypes.data, cy.ctypes.data, int(layers))
+            _check(lib().bpjd_server_submit(self.handle, C.byref(Kc), C.byref(Mc), None, C.byref(g),
+                                            C.byref(opts), C.byref(rid)))
+        elif dd is not None:
+            P, subs = dd
+            Pc = _csr(P, keep)
+            sub_ptr = np.zeros(len(subs) + 1, dtype=np.int32)
+            sub_ptr[1:] = np.cumsum([len(S) for S in subs])
+            sub_idx = np.ascontiguousarray(np.concatenate([np.asarray(S) for S in subs]), dtype=np.int32)
+            keep += [sub_ptr, sub_idx]
+            d = DD(Pc, len(subs), sub_ptr.ctypes.data, sub_idx.ctypes.data)
+            _check(lib().bpjd_server_submit(self.handle, C.byref(Kc), C.byref(Mc), C.byref(d), None,
+                                            C.byref(opts), C.byref(rid)))
+        else:
+            raise ValueError("give dd=(P, subdomains) or geom=(coords, cx, cy, layers)")
+        self._shape[rid.value] = (K.shape[0], k)
+        return rid.value
+
+    def submit_mesh(self, mesh, layers: int, **kw) -> int:
+        return self.submit(mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers), **kw)
+
+    def poll(self, req_id: int, raise_noconv: bool = True):
+        n, k = self._shape.get(req_id, (0, 0))      # an unknown id is the library's error
+        lam = np.empty(k)
+        X = np.empty((n, k))
+        st = Stats()
+        code = lib().bpjd_server_poll(self.handle, req_id, lam.ctypes.data if k else None,
+                                      X.ctypes.data if k else None, C.byref(st))
+        if code == PENDING:
+            return None
+        self._shape.pop(req_id, None)
+        if code != ERR_NOCONV or raise_noconv:
+            _check(code)
+        return lam, X, st.to_dict()
+
+    def info(self) -> dict:
+        inf = ServerInfo()
+        _check(lib().bpjd_server_get_info(self.handle, C.byref(inf)))
+        return inf.to_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bpjd_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <numeric>
 
 #include "common.h"
@@ -231,8 +232,111 @@ static int alloc_dev(bpjd_problem* p, T** dst, size_t count) {
     return upload(p, (void**)dst, nullptr, count * sizeof(T));
 }
 
+// Host-side result of planning a problem: every array the device copy needs.
+struct HostPlan {
+    std::vector<int> rowptr, col;
+    std::vector<double2> km;
+    std::vector<int> Pptr, Pcol;
+    std::vector<double> Pval;
+    std::vector<int> PTptr, PTcol;
+    std::vector<double> PTval;
+    std::vector<int> kpptr, kpcol, khptr, khcol;
+    std::vector<int> sptr, sidx, bw, lptr, ldd, lpos, rptr, ridx;
+    std::vector<long long> Loff;
+    bool blocked = false;
+    int maxE = 0, bws = 64;
+    long long Ltot = 0;
+    size_t elt = 8;
+};
+
+// The one list of device arrays of a problem.  `op(dst, src, bytes)` either allocates
+// (and uploads src when non-NULL) or only counts bytes, so the footprint used for
+// admission and the real allocation cannot drift apart.
+template <class Op>
+static int device_layout(bpjd_problem* p, const HostPlan& h, Op&& op) {
+    int rc = BPJD_OK;
+    auto put = [&](auto** dst, const auto& v) {
+        using E = typename std::decay_t<decltype(v)>::value_type;
+        int r = op((void**)dst, v.empty() ? nullptr : (const void*)v.data(), v.size() * sizeof(E));
+        if (r < 0 && rc == BPJD_OK) rc = r;
+    };
+    auto zero = [&](auto** dst, size_t count) {
+        using E = std::remove_pointer_t<std::remove_pointer_t<decltype(dst)>>;
+        int r = op((void**)dst, nullptr, count * sizeof(E));
+        if (r < 0 && rc == BPJD_OK) rc = r;
+    };
+    const int n = p->n, nH = p->nH, s = p->s;
+    put(&p->rowptr, h.rowptr);
+    put(&p->col, h.col);
+    put(&p->km, h.km);
+    put(&p->Pptr, h.Pptr);
+    put(&p->Pcol, h.Pcol);
+    put(&p->Pval, h.Pval);
+    put(&p->PTptr, h.PTptr);
+    put(&p->PTcol, h.PTcol);
+    put(&p->PTval, h.PTval);
+    put(&p->kpptr, h.kpptr);
+    put(&p->kpcol, h.kpcol);
+    zero(&p->kpval, h.kpcol.size());
+    put(&p->khptr, h.khptr);
+    put(&p->khcol, h.khcol);
+    put(&p->subptr, h.sptr);
+    put(&p->subidx, h.sidx);
+    put(&p->bw, h.bw);
+    put(&p->lptr, h.lptr);
+    put(&p->ldd, h.ldd);
+    put(&p->lpos, h.lpos);
+    put(&p->rptr, h.rptr);
+    put(&p->ridx, h.ridx);
+    put(&p->Loff, h.Loff);
+    zero(&p->sd, (size_t)p->sumN * h.maxE);
+    zero(&p->sv, (size_t)p->sumN * h.maxE);
+    const size_t nH2 = (size_t)nH * nH;
+    zero(&p->KH, nH2);
+    zero(&p->MH, nH2);
+    zero(&p->Y, nH2);
+    zero(&p->jwork, nH2);
+    zero(&p->lamH, nH);
+    zero(&p->esmall, 6 * (size_t)nH + 1);
+    zero(&p->YT, nH2);
+    zero(&p->escratch, 8 * nH2);
+    const size_t blk = (size_t)n * 3 * s;
+    for (int b = 0; b < 2; ++b) {
+        zero(&p->W[b], blk);
+        zero(&p->KW[b], blk);
+        zero(&p->MW[b], blk);
+    }
+    zero(&p->F, (size_t)n * s);
+    zero(&p->Z, (size_t)n * s);
+    zero(&p->Zhat, (size_t)nH * s);
+    zero(&p->G, (size_t)nH * s);
+    zero(&p->Cw, (size_t)nH * s);
+    {
+        int r = op(&p->Floc, nullptr, h.elt * s * p->sumN);
+        if (r < 0 && rc == BPJD_OK) rc = r;
+        r = op(&p->zloc, nullptr, h.elt * s * p->sumN);
+        if (r < 0 && rc == BPJD_OK) rc = r;
+        r = op(&p->Lwork, nullptr, h.elt * h.Ltot);
+        if (r < 0 && rc == BPJD_OK) rc = r;
+    }
+    zero(&p->partial, (size_t)p->npart * 4096);
+    zero(&p->colsq, 256);     // [0, 2s) column norms, [128, 128+s) shifts, [192] status
+    zero(&p->lam, 64);
+    zero(&p->gsmall, 64 * 64);
+    zero(&p->csmall, 64 * 64);
+    zero(&p->Hm, 64 * 64);
+    zero(&p->theta, 64);
+    zero(&p->Cfull, 64 * 128);
+    zero(&p->dropped[0], 64);
+    zero(&p->dropped[1], 64);
+    zero(&p->status, 4);
+    zero(&p->negflag, (size_t)p->nsub * s);
+    return rc;
+}
+
 // Everything after the decomposition is known: local band layout, reverse
-// map, Galerkin patterns, device allocations.
+// map, Galerkin patterns.  Builds the problem's host plan and its device
+// footprint; materialize_problem allocates and uploads.
 static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, const Pattern& U, const HostCSR& P,
                          int nH, std::vector<int>& sptr, std::vector<int>& sidx, const bpjd_opts* opts,
                          bpjd_problem** out) {
@@ -314,6 +418,10 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     int maxE = 0;
     for (long long q = 0; q < sumN; ++q) maxE = std::max(maxE, lptr[q + 1] - lptr[q]);
     const bool blocked = maxBW <= kBlockedMaxBand && maxE <= kBlockedMaxSlots;
+    // the windowed solver gives each lane at most two entries of a window row and loads
+    // the slots of a block of rows one slot per lane
+    if (!blocked && (maxBW > 127 || maxE > 64))
+        return fail(BPJD_ERR_DD, "local half-bandwidth above 127 or more than 64 lower entries in a local row");
     // FP64 factors keep only the band of each column (halves the factor traffic that
     // bounds the backward sweep); FP32 factors keep full 64-row columns, whose stores
     // and loads need no per-lane masks
@@ -400,87 +508,65 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     for (int l = 0; l < nsub; ++l) p->h_nl[l] = sptr[l + 1] - sptr[l];
     if (opts->n_init) p->X_init.assign(opts->X_init, opts->X_init + (size_t)n * s);
 
-    std::vector<double2> km(p->nnz, make_double2(0.0, 0.0));
-    for (size_t q = 0; q < K.col.size(); ++q) km[U.Kmap[q]].x = K.val[q];
-    for (size_t q = 0; q < M.col.size(); ++q) km[U.Mmap[q]].y = M.val[q];
-
-    int rc = BPJD_OK;
-    auto chk = [&](int r) {
-        if (r < 0 && rc == BPJD_OK) rc = r;
-    };
-    BPJD_HIP(hipSetDevice(ctx->device));
-    chk(upload_vec(p, &p->rowptr, U.ptr));
-    chk(upload_vec(p, &p->col, U.col));
-    chk(upload_vec(p, &p->km, km));
-    chk(upload_vec(p, &p->Pptr, P.ptr));
-    chk(upload_vec(p, &p->Pcol, P.col));
-    chk(upload_vec(p, &p->Pval, P.val));
-    chk(upload_vec(p, &p->PTptr, PTptr));
-    chk(upload_vec(p, &p->PTcol, PTcol));
-    chk(upload_vec(p, &p->PTval, PTval));
-    chk(upload_vec(p, &p->kpptr, kpptr));
-    chk(upload_vec(p, &p->kpcol, kpcol));
-    chk(alloc_dev(p, &p->kpval, kpcol.size()));
-    chk(upload_vec(p, &p->khptr, khptr));
-    chk(upload_vec(p, &p->khcol, khcol));
-    chk(upload_vec(p, &p->subptr, sptr));
-    chk(upload_vec(p, &p->subidx, sidx));
-    chk(upload_vec(p, &p->bw, bw));
-    chk(upload_vec(p, &p->lptr, lptr));
-    chk(upload_vec(p, &p->ldd, ldd));
-    chk(upload_vec(p, &p->lpos, lpos));
-    chk(upload_vec(p, &p->rptr, rptr));
-    chk(upload_vec(p, &p->ridx, ridx));
-    chk(upload_vec(p, &p->Loff, Loff));
-    if (blocked) {
-        p->slotE = maxE;
-        p->bws = bws;
-        chk(alloc_dev(p, &p->sd, (size_t)sumN * maxE));
-        chk(alloc_dev(p, &p->sv, (size_t)sumN * maxE));
-    }
-    const size_t nH2 = (size_t)nH * nH;
-    chk(alloc_dev(p, &p->KH, nH2));
-    chk(alloc_dev(p, &p->MH, nH2));
-    chk(alloc_dev(p, &p->Y, nH2));
-    chk(alloc_dev(p, &p->jwork, nH2));
-    chk(alloc_dev(p, &p->lamH, nH));
-    chk(alloc_dev(p, &p->esmall, 6 * (size_t)nH + 1));
-    chk(alloc_dev(p, &p->YT, nH2));
-    chk(alloc_dev(p, &p->escratch, 8 * nH2));
-    const size_t blk = (size_t)n * 3 * s;
-    for (int b = 0; b < 2; ++b) {
-        chk(alloc_dev(p, &p->W[b], blk));
-        chk(alloc_dev(p, &p->KW[b], blk));
-        chk(alloc_dev(p, &p->MW[b], blk));
-    }
-    chk(alloc_dev(p, &p->F, (size_t)n * s));
-    chk(alloc_dev(p, &p->Z, (size_t)n * s));
-    chk(alloc_dev(p, &p->Zhat, (size_t)nH * s));
-    chk(alloc_dev(p, &p->G, (size_t)nH * s));
-    chk(alloc_dev(p, &p->Cw, (size_t)nH * s));
-    chk(upload(p, &p->Floc, nullptr, elt * s * sumN));
-    chk(upload(p, &p->zloc, nullptr, elt * s * sumN));
-    chk(upload(p, &p->Lwork, nullptr, elt * Ltot));
+    auto* h = new HostPlan();
+    p->plan = h;
+    h->km.assign(p->nnz, make_double2(0.0, 0.0));
+    for (size_t q = 0; q < K.col.size(); ++q) h->km[U.Kmap[q]].x = K.val[q];
+    for (size_t q = 0; q < M.col.size(); ++q) h->km[U.Mmap[q]].y = M.val[q];
+    h->rowptr = U.ptr;
+    h->col = U.col;
+    h->Pptr = P.ptr;
+    h->Pcol = P.col;
+    h->Pval = P.val;
+    h->PTptr = std::move(PTptr);
+    h->PTcol = std::move(PTcol);
+    h->PTval = std::move(PTval);
+    h->kpptr = std::move(kpptr);
+    h->kpcol = std::move(kpcol);
+    h->khptr = std::move(khptr);
+    h->khcol = std::move(khcol);
+    h->sptr = std::move(sptr);
+    h->sidx = std::move(sidx);
+    h->bw = std::move(bw);
+    h->lptr = std::move(lptr);
+    h->ldd = std::move(ldd);
+    h->lpos = std::move(lpos);
+    h->rptr = std::move(rptr);
+    h->ridx = std::move(ridx);
+    h->Loff = std::move(Loff);
+    h->blocked = blocked;
+    h->maxE = maxE;
+    h->bws = bws;
+    h->Ltot = Ltot;
+    h->elt = elt;
+    p->slotE = maxE;
+    p->blocked = blocked;
+    if (blocked) p->bws = bws;
     p->npart = num_partials(n);
-    chk(alloc_dev(p, &p->partial, (size_t)p->npart * 4096));
-    chk(alloc_dev(p, &p->colsq, 256));     // [0, 2s) column norms, [128, 128+s) shifts, [192] status
-    chk(alloc_dev(p, &p->lam, 64));
-    chk(alloc_dev(p, &p->gsmall, 64 * 64));
-    chk(alloc_dev(p, &p->csmall, 64 * 64));
-    chk(alloc_dev(p, &p->Hm, 64 * 64));
-    chk(alloc_dev(p, &p->theta, 64));
-    chk(alloc_dev(p, &p->Cfull, 64 * 128));
-    chk(alloc_dev(p, &p->dropped[0], 64));
-    chk(alloc_dev(p, &p->dropped[1], 64));
-    chk(alloc_dev(p, &p->status, 4));
-    if (rc == BPJD_OK && hipHostMalloc((void**)&p->hbuf, 4096 * sizeof(double)) != hipSuccess)
-        rc = fail(BPJD_ERR_OOM, "pinned host allocation failed");
-    if (rc != BPJD_OK) {
-        bpjd_problem_destroy(p);
-        return rc;
-    }
+    size_t bytes = 0;
+    device_layout(p, *h, [&](void**, const void*, size_t b) {
+        bytes += (std::max<size_t>(b, 8) + 4095) & ~size_t(4095);   // allocation granularity
+        return BPJD_OK;
+    });
+    p->footprint = bytes;
     *out = p;
     return BPJD_OK;
+}
+
+// Allocate the device memory of a planned problem and upload its structural data
+// (synchronous copies); releases the host plan.  On failure the problem keeps what
+// was allocated, for bpjd_problem_destroy.
+int materialize_problem(bpjd_problem* p) {
+    if (!p->plan) return fail(BPJD_ERR_STATE, "problem already materialised");
+    BPJD_HIP(hipSetDevice(p->ctx->device));
+    int rc = device_layout(p, *p->plan, [&](void** dst, const void* src, size_t b) {
+        return upload(p, dst, src, b);
+    });
+    if (rc == BPJD_OK && hipHostMalloc((void**)&p->hbuf, 4096 * sizeof(double)) != hipSuccess)
+        rc = fail(BPJD_ERR_OOM, "pinned host allocation failed");
+    delete p->plan;
+    p->plan = nullptr;
+    return rc;
 }
 
 static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR& hM, Pattern& U) {
@@ -564,7 +650,7 @@ static int check_status(bpjd_problem* p) {
 static void coarse_setup(bpjd_problem* p) {
     hipStream_t st = p->ctx->stream;
     const int nH = p->nH;
-    if (p->slotE) launch_extract_local(st, p->sumN, p->slotE, p->lptr, p->ldd, p->lpos, p->km, p->sd, p->sv);
+    launch_extract_local(st, p->sumN, p->slotE, p->lptr, p->ldd, p->lpos, p->km, p->sd, p->sv);
     launch_galerkin(st, p->n, nH, p->rowptr, p->col, p->km, p->Pptr, p->Pcol, p->Pval, p->PTptr, p->PTcol, p->PTval,
                     p->kpptr, p->kpcol, p->kpval, p->khptr, p->khcol, p->nnzKH, p->KH, p->MH);
     // K_H y = lambda M_H y  ->  C z = lambda z with C = L^{-1} K_H L^{-T}, y = L^{-T} z;
@@ -600,14 +686,13 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_LOCAL);
     if (mixed)
-        launch_local_solve_f32(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
+        launch_local_solve_f32(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->blocked ? 1 : 0,
                                p->slotE, p->bws, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
-                               (float*)p->Lwork, p->Loff, p->status);
+                               (float*)p->Lwork, p->Loff, p->status, p->negflag);
     else
-        launch_local_solve_f64(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->lptr, p->ldd, p->lpos, p->km,
+        launch_local_solve_f64(st, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->blocked ? 1 : 0,
                                p->slotE, p->bws, p->sd, p->sv, p->lam, (const double*)p->Floc, (double*)p->zloc,
-                               (double*)p->Lwork, p->Loff,
-                               p->status);
+                               (double*)p->Lwork, p->Loff, p->status, p->negflag);
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_GATHER);
     if (mixed)
@@ -709,156 +794,233 @@ static int start_block(bpjd_problem* p) {
     return BPJD_OK;
 }
 
-struct IterState {
+// One solve as a state machine, so that several solves can share the device: every
+// stage ends with an asynchronous read-back of a few scalars and an event; the next
+// stage is enqueued once that event has completed (run_poll / run_advance).  A plain
+// bpjd_solve drives one machine to the end; the server interleaves many.
+struct SolveRun {
+    bpjd_problem* p = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, erb = nullptr;
+    PhaseTimer timer;
+    PhaseTimer* T = nullptr;
+    enum Stage { IDLE, SETUP, ITER, DONE, FAILED } stage = IDLE;
     int cur = 0;        // buffer holding X (and P)
     int np = 0;         // columns of P in use (0 or s)
+    int it = 0;         // outer iteration whose residual is being read back
+    int iters = 0;
+    bool converged = false;
+    double stop_value = NAN;
+    std::vector<double> lam_prev, lam_now, rho;
+    ~SolveRun() {
+        for (hipEvent_t x : {e0, e1, e2, erb})
+            if (x) (void)hipEventDestroy(x);
+    }
 };
 
-static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem, bpjd_stats* stats) {
-    hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, k = p->k, ld = s;   // X: block 0 of W, K W, M W
-    const bool uu = p->opts.subspace == BPJD_SUBSPACE_UU;
-    // events are released on every exit path
-    struct Events {
-        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
-        ~Events() {
-            for (hipEvent_t x : e)
-                if (x) (void)hipEventDestroy(x);
-        }
-    } ev;
-    BPJD_HIP(hipEventCreate(&ev.e[0]));
-    BPJD_HIP(hipEventCreate(&ev.e[1]));
-    BPJD_HIP(hipEventCreate(&ev.e[2]));
-    BPJD_HIP(hipEventCreateWithFlags(&ev.e[3], hipEventDisableTiming));
-    hipEvent_t e0 = ev.e[0], e1 = ev.e[1], e2 = ev.e[2], erb = ev.e[3];
-    PhaseTimer timer;
-    timer.st = st;
-    if (p->opts.profile == 2) timer.mask = 1u << BPJD_PHASE_LOCAL;
-    PhaseTimer* T = p->opts.profile ? &timer : nullptr;
-    BPJD_HIP(hipEventRecord(e0, st));
-    PH_BEGIN(T, BPJD_PHASE_SETUP);
-    BPJD_TRY(run_setup(p));
-    BPJD_TRY(start_block(p));
-    PH_END(T);
-    BPJD_HIP(hipEventRecord(e1, st));
-
-    IterState S;
-    std::vector<double> lam_prev(s, 0.0), lam_now(s, 0.0), rho(s, 0.0);
-    bool converged = false;
-    int iters = 0;
-    double stop_value = NAN;
-    double* h = p->hbuf;
-    int* hstatus = reinterpret_cast<int*>(h + 192);
-    for (int it = 0; it <= p->opts.max_iter; ++it) {
-        const int a = S.cur;
-        // residual block F = M X Lambda - K X and its column norms
-        PH_BEGIN(T, BPJD_PHASE_RESIDUAL);
-        launch_residual(st, n, s, p->KW[a], ld, p->MW[a], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq,
-                        p->colsq + 128, p->status);
-        PH_END(T);
-        // one read-back: column norms, shifts and status word; the host polls its event
-        // (no yield), so the next launches follow the copy as closely as possible
-        BPJD_HIP(hipMemcpyAsync(h, p->colsq, sizeof(double) * 193, hipMemcpyDeviceToHost, st));
-        BPJD_HIP(hipEventRecord(erb, st));
-        {
-            hipError_t q;
-            while ((q = hipEventQuery(erb)) == hipErrorNotReady) {
-            }
-            BPJD_HIP(q);
-        }
-        if (T) T->collect();
-        if (*hstatus & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
-        for (int i = 0; i < s; ++i) {
-            lam_now[i] = h[128 + i];
-            rho[i] = std::sqrt(h[i]) / (std::fabs(lam_now[i]) * std::sqrt(h[s + i]));
-        }
-        double rmax = 0.0;
-        bool finite = true;
-        for (int i = 0; i < k; ++i) {
-            rmax = std::max(rmax, rho[i]);
-            finite = finite && std::isfinite(rho[i]);
-        }
-        if (p->trace) {
-            std::fprintf(stderr, "[bpjd] it %d rho_max %.3e lam:", it, rmax);
-            for (int i = 0; i < s; ++i) std::fprintf(stderr, " %.12g", lam_now[i]);
-            std::fprintf(stderr, "\n");
-        }
-        if (!finite) return fail(BPJD_ERR_NOT_SPD, "non-finite residual (breakdown)");
-        if (it > 0) {
-            stop_value = 0.0;
-            for (int i = 0; i < s; ++i) stop_value += std::fabs(lam_now[i] - lam_prev[i]);
-        }
-        if (p->opts.stop_rule == BPJD_STOP_RESIDUAL && rmax <= p->opts.tol) {
-            converged = true;
-            break;
-        }
-        if (p->opts.stop_rule == BPJD_STOP_PAPER && it > 0 && stop_value < p->opts.tol) {
-            converged = true;
-            break;
-        }
-        if (it == p->opts.max_iter) break;
-        lam_prev = lam_now;
-
-        // Step 2: t_i = (I - X X^T M) (B_i)^{-1} r_i, written straight into the T slot of W.
-        // The projection (I - X X^T M) of Step 2 is the first Gram-Schmidt pass of
-        // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
-        const int ct = s + S.np;
-        apply_precond(p, p->F, blkp(p, p->W[a], ct), s, T);
-        // Step 3: Rayleigh-Ritz on W = [X | P | T]
-        orthonormalize_T(p, a, ct, T);
-        rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, T);
-        if (p->trace) {
-            int fl[128];
-            BPJD_HIP(hipMemcpyAsync(fl, p->dropped[a], sizeof(int) * (ct + s), hipMemcpyDeviceToHost, st));
-            BPJD_HIP(hipMemcpyAsync(fl + 64, p->dropped[1 - a], sizeof(int) * 2 * s, hipMemcpyDeviceToHost, st));
-            double th[64];
-            BPJD_HIP(hipMemcpyAsync(th, p->theta, sizeof(double) * (ct + s), hipMemcpyDeviceToHost, st));
-            BPJD_HIP(hipStreamSynchronize(st));
-            std::fprintf(stderr, "[bpjd]   m=%d drop_in:", ct + s);
-            for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, "%d", fl[q]);
-            std::fprintf(stderr, " drop_out:");
-            for (int q = 0; q < 2 * s; ++q) std::fprintf(stderr, "%d", fl[64 + q]);
-            std::fprintf(stderr, " theta:");
-            for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, " %.6g", th[q]);
-            std::fprintf(stderr, "\n");
-        }
-        S.cur = 1 - a;
-        S.np = uu ? s : 0;
-        iters = it + 1;
+int run_create(bpjd_problem* p, SolveRun** out) {
+    auto* r = new SolveRun();
+    r->p = p;
+    const int s = p->s;
+    r->lam_prev.assign(s, 0.0);
+    r->lam_now.assign(s, 0.0);
+    r->rho.assign(s, 0.0);
+    r->timer.st = p->ctx->stream;
+    if (p->opts.profile == 2) r->timer.mask = 1u << BPJD_PHASE_LOCAL;
+    r->T = p->opts.profile ? &r->timer : nullptr;
+    if (hipEventCreate(&r->e0) != hipSuccess || hipEventCreate(&r->e1) != hipSuccess ||
+        hipEventCreate(&r->e2) != hipSuccess ||
+        hipEventCreateWithFlags(&r->erb, hipEventDisableTiming) != hipSuccess) {
+        delete r;
+        return fail(BPJD_ERR_HIP, "hipEventCreate failed");
     }
-    BPJD_HIP(hipEventRecord(e2, st));
-    BPJD_HIP(hipEventSynchronize(e2));
-    if (T) T->collect();
-    float ms_setup = 0.f, ms_iter = 0.f;
-    BPJD_HIP(hipEventElapsedTime(&ms_setup, e0, e1));
-    BPJD_HIP(hipEventElapsedTime(&ms_iter, e1, e2));
+    *out = r;
+    return BPJD_OK;
+}
 
-    const int a = S.cur;
+void run_destroy(SolveRun* r) { delete r; }
+
+// residual block F = M X Lambda - K X and its column norms, then one read-back of the
+// column norms, shifts and status word into the pinned mirror, then the event
+static int enqueue_residual(SolveRun* r) {
+    bpjd_problem* p = r->p;
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, a = r->cur;
+    PH_BEGIN(r->T, BPJD_PHASE_RESIDUAL);
+    launch_residual(st, n, s, p->KW[a], s, p->MW[a], s, p->lam, p->F, s, p->partial, p->npart, p->colsq,
+                    p->colsq + 128, p->status);
+    PH_END(r->T);
+    BPJD_HIP(hipMemcpyAsync(p->hbuf, p->colsq, sizeof(double) * 193, hipMemcpyDeviceToHost, st));
+    BPJD_HIP(hipEventRecord(r->erb, st));
+    return BPJD_OK;
+}
+
+int run_begin(SolveRun* r) {
+    bpjd_problem* p = r->p;
+    hipStream_t st = p->ctx->stream;
+    BPJD_HIP(hipSetDevice(p->ctx->device));
+    BPJD_HIP(hipEventRecord(r->e0, st));
+    PH_BEGIN(r->T, BPJD_PHASE_SETUP);
+    BPJD_HIP(hipMemsetAsync(p->status, 0, sizeof(int), st));
+    coarse_setup(p);
+    BPJD_HIP(hipMemcpyAsync(p->hbuf + 256, p->status, sizeof(int), hipMemcpyDeviceToHost, st));
+    BPJD_HIP(hipEventRecord(r->erb, st));
+    r->stage = SolveRun::SETUP;
+    return BPJD_OK;
+}
+
+// 1: the pending read-back has arrived; 0: not yet; < 0: HIP error
+int run_poll(SolveRun* r) {
+    const hipError_t q = hipEventQuery(r->erb);
+    if (q == hipSuccess) return 1;
+    if (q == hipErrorNotReady) return 0;
+    return fail(BPJD_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+}
+
+int run_wait(SolveRun* r) {
+    // spin (no yield): the next launches follow the read-back as closely as possible
+    int q;
+    while ((q = run_poll(r)) == 0) {
+    }
+    return q < 0 ? q : BPJD_OK;
+}
+
+static int advance_setup(SolveRun* r) {
+    bpjd_problem* p = r->p;
+    const int st_word = *reinterpret_cast<const int*>(p->hbuf + 256);
+    if (st_word & STATUS_COARSE_NOT_SPD) return fail(BPJD_ERR_NOT_SPD, "coarse mass matrix M_H is not positive definite");
+    if (st_word & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
+    p->setup_done = true;
+    BPJD_TRY(start_block(p));
+    PH_END(r->T);
+    BPJD_HIP(hipEventRecord(r->e1, p->ctx->stream));
+    BPJD_TRY(enqueue_residual(r));
+    r->stage = SolveRun::ITER;
+    return 0;
+}
+
+static int advance_iter(SolveRun* r) {
+    bpjd_problem* p = r->p;
+    hipStream_t st = p->ctx->stream;
+    const int s = p->s, k = p->k;
+    const bool uu = p->opts.subspace == BPJD_SUBSPACE_UU;
+    const double* h = p->hbuf;
+    const int hstatus = *reinterpret_cast<const int*>(h + 192);
+    if (r->T) r->T->collect();
+    if (hstatus & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
+    for (int i = 0; i < s; ++i) {
+        r->lam_now[i] = h[128 + i];
+        r->rho[i] = std::sqrt(h[i]) / (std::fabs(r->lam_now[i]) * std::sqrt(h[s + i]));
+    }
+    double rmax = 0.0;
+    bool finite = true;
+    for (int i = 0; i < k; ++i) {
+        rmax = std::max(rmax, r->rho[i]);
+        finite = finite && std::isfinite(r->rho[i]);
+    }
+    if (p->trace) {
+        std::fprintf(stderr, "[bpjd] it %d rho_max %.3e lam:", r->it, rmax);
+        for (int i = 0; i < s; ++i) std::fprintf(stderr, " %.12g", r->lam_now[i]);
+        std::fprintf(stderr, "\n");
+    }
+    if (!finite) return fail(BPJD_ERR_NOT_SPD, "non-finite residual (breakdown)");
+    if (r->it > 0) {
+        r->stop_value = 0.0;
+        for (int i = 0; i < s; ++i) r->stop_value += std::fabs(r->lam_now[i] - r->lam_prev[i]);
+    }
+    bool stop = false;
+    if (p->opts.stop_rule == BPJD_STOP_RESIDUAL && rmax <= p->opts.tol) stop = r->converged = true;
+    if (p->opts.stop_rule == BPJD_STOP_PAPER && r->it > 0 && r->stop_value < p->opts.tol) stop = r->converged = true;
+    if (r->it == p->opts.max_iter) stop = true;
+    if (stop) {
+        BPJD_HIP(hipEventRecord(r->e2, st));
+        r->stage = SolveRun::DONE;
+        return 1;
+    }
+    r->lam_prev = r->lam_now;
+
+    // Step 2: t_i = (I - X X^T M) (B_i)^{-1} r_i, written straight into the T slot of W.
+    // The projection (I - X X^T M) of Step 2 is the first Gram-Schmidt pass of
+    // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
+    const int a = r->cur;
+    const int ct = s + r->np;
+    apply_precond(p, p->F, blkp(p, p->W[a], ct), s, r->T);
+    // Step 3: Rayleigh-Ritz on W = [X | P | T]
+    orthonormalize_T(p, a, ct, r->T);
+    rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, r->T);
+    if (p->trace) {
+        int fl[128];
+        BPJD_HIP(hipMemcpyAsync(fl, p->dropped[a], sizeof(int) * (ct + s), hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipMemcpyAsync(fl + 64, p->dropped[1 - a], sizeof(int) * 2 * s, hipMemcpyDeviceToHost, st));
+        double th[64];
+        BPJD_HIP(hipMemcpyAsync(th, p->theta, sizeof(double) * (ct + s), hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipStreamSynchronize(st));
+        std::fprintf(stderr, "[bpjd]   m=%d drop_in:", ct + s);
+        for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, "%d", fl[q]);
+        std::fprintf(stderr, " drop_out:");
+        for (int q = 0; q < 2 * s; ++q) std::fprintf(stderr, "%d", fl[64 + q]);
+        std::fprintf(stderr, " theta:");
+        for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, " %.6g", th[q]);
+        std::fprintf(stderr, "\n");
+    }
+    r->cur = 1 - a;
+    r->np = uu ? s : 0;
+    r->iters = ++r->it;
+    BPJD_TRY(enqueue_residual(r));
+    return 0;
+}
+
+// Consume the arrived read-back and enqueue the next stage: 1 = the stop rule (or the
+// iteration cap) was reached, 0 = more work was enqueued, < 0 = error.
+int run_advance(SolveRun* r) {
+    int rc;
+    switch (r->stage) {
+        case SolveRun::SETUP: rc = advance_setup(r); break;
+        case SolveRun::ITER: rc = advance_iter(r); break;
+        case SolveRun::DONE: return 1;
+        default: return fail(BPJD_ERR_STATE, "solve not started");
+    }
+    if (rc < 0) r->stage = SolveRun::FAILED;
+    return rc;
+}
+
+// Copy the result out (eigvals: k values; eigvecs: n x k row-major; both in `mem`) and
+// fill the statistics.  Synchronises the problem's stream.
+int run_finish(SolveRun* r, double* eigvals, double* eigvecs, int mem, bpjd_stats* stats) {
+    bpjd_problem* p = r->p;
+    if (r->stage != SolveRun::DONE) return fail(BPJD_ERR_STATE, "solve has not finished");
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s, k = p->k;
+    BPJD_HIP(hipEventSynchronize(r->e2));
+    if (r->T) r->T->collect();
+    float ms_setup = 0.f, ms_iter = 0.f;
+    BPJD_HIP(hipEventElapsedTime(&ms_setup, r->e0, r->e1));
+    BPJD_HIP(hipEventElapsedTime(&ms_iter, r->e1, r->e2));
+    const int a = r->cur;
     if (eigvals) {
         if (mem == BPJD_MEM_DEVICE) {
             BPJD_HIP(hipMemcpyAsync(eigvals, p->lam, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
         } else {
-            std::memcpy(eigvals, lam_now.data(), sizeof(double) * k);
+            std::memcpy(eigvals, r->lam_now.data(), sizeof(double) * k);
         }
     }
     if (eigvecs) {
         if (mem == BPJD_MEM_DEVICE) {
-            launch_copy_cols(st, n, k, p->W[a], ld, eigvecs, k);
+            launch_copy_cols(st, n, k, p->W[a], s, eigvecs, k);
         } else {
-            launch_copy_cols(st, n, k, p->W[a], ld, p->Z, k);
+            launch_copy_cols(st, n, k, p->W[a], s, p->Z, k);
             BPJD_HIP(hipMemcpyAsync(eigvecs, p->Z, sizeof(double) * n * k, hipMemcpyDeviceToHost, st));
         }
     }
     BPJD_HIP(hipStreamSynchronize(st));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->iterations = iters;
-        stats->converged = converged ? 1 : 0;
-        stats->stop_value = stop_value;
+        stats->iterations = r->iters;
+        stats->converged = r->converged ? 1 : 0;
+        stats->stop_value = r->stop_value;
         double rmax = 0.0;
-        for (int i = 0; i < k; ++i) rmax = std::max(rmax, rho[i]);
+        for (int i = 0; i < k; ++i) rmax = std::max(rmax, r->rho[i]);
         stats->max_residual = rmax;
-        for (int i = 0; i < k && i < 64; ++i) stats->residuals[i] = rho[i];
+        for (int i = 0; i < k && i < 64; ++i) stats->residuals[i] = r->rho[i];
         stats->setup_ms = ms_setup;
         stats->iterate_ms = ms_iter;
         stats->n_sub = p->nsub;
@@ -866,12 +1028,26 @@ static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem,
         stats->max_local = p->maxN;
         stats->max_band = p->maxBW;
         for (int q = 0; q < BPJD_NUM_PHASES; ++q) {
-            stats->phase_ms[q] = timer.ms[q];
-            stats->phase_count[q] = timer.count[q];
+            stats->phase_ms[q] = r->timer.ms[q];
+            stats->phase_count[q] = r->timer.count[q];
         }
     }
-    if (!converged) return fail(BPJD_ERR_NOCONV, "maximum number of iterations reached");
+    if (!r->converged) return fail(BPJD_ERR_NOCONV, "maximum number of iterations reached");
     return BPJD_OK;
+}
+
+static int run_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int mem, bpjd_stats* stats) {
+    SolveRun* raw = nullptr;
+    BPJD_TRY(run_create(p, &raw));
+    std::unique_ptr<SolveRun> r(raw);
+    BPJD_TRY(run_begin(r.get()));
+    for (;;) {
+        BPJD_TRY(run_wait(r.get()));
+        const int q = run_advance(r.get());
+        if (q < 0) return q;
+        if (q == 1) break;
+    }
+    return run_finish(r.get(), eigvals, eigvecs, mem, stats);
 }
 
 }  // namespace bpjd
@@ -925,9 +1101,12 @@ void bpjd_ctx_destroy(bpjd_ctx* ctx) {
     delete ctx;
 }
 
-int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
-                        const bpjd_opts* opts, bpjd_problem** out) {
-    if (!ctx || !K || !M || !dd || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+}  // extern "C"
+
+namespace bpjd {
+
+static int plan_dd(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
+                   const bpjd_opts* opts, bpjd_problem** out) {
     HostCSR hK, hM, P;
     Pattern U;
     BPJD_TRY(read_pair(K, M, hK, hM, U));
@@ -955,9 +1134,8 @@ int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, con
     }
 }
 
-int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd_geom* g,
-                             const bpjd_opts* opts, bpjd_problem** out) {
-    if (!ctx || !K || !M || !g || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+static int plan_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd_geom* g,
+                     const bpjd_opts* opts, bpjd_problem** out) {
     if (!g->coords || !g->cx || !g->cy || g->n_cx < 2 || g->n_cy < 2) return fail(BPJD_ERR_ARG, "bad coarse grid");
     HostCSR hK, hM, P;
     Pattern U;
@@ -975,8 +1153,46 @@ int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M
     return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out);
 }
 
+// Host planning of a problem (validation, structure, footprint) without device memory;
+// exactly one of dd / geom is used.
+int plan_problem(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd, const bpjd_dd_geom* geom,
+                 const bpjd_opts* opts, bpjd_problem** out) {
+    if (!ctx || !K || !M || (!dd && !geom) || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+    return dd ? plan_dd(ctx, K, M, dd, opts, out) : plan_geom(ctx, K, M, geom, opts, out);
+}
+
+static int create_now(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
+                      const bpjd_dd_geom* geom, const bpjd_opts* opts, bpjd_problem** out) {
+    bpjd_problem* p = nullptr;
+    BPJD_TRY(plan_problem(ctx, K, M, dd, geom, opts, &p));
+    const int rc = materialize_problem(p);
+    if (rc < 0) {
+        bpjd_problem_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return BPJD_OK;
+}
+
+}  // namespace bpjd
+
+extern "C" {
+
+int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
+                        const bpjd_opts* opts, bpjd_problem** out) {
+    if (!ctx || !K || !M || !dd || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+    return create_now(ctx, K, M, dd, nullptr, opts, out);
+}
+
+int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd_geom* g,
+                             const bpjd_opts* opts, bpjd_problem** out) {
+    if (!ctx || !K || !M || !g || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
+    return create_now(ctx, K, M, nullptr, g, opts, out);
+}
+
 void bpjd_problem_destroy(bpjd_problem* p) {
     if (!p) return;
+    delete p->plan;
     for (void* d : p->allocations) (void)hipFree(d);
     if (p->hbuf) (void)hipHostFree(p->hbuf);
     delete p;
@@ -1006,6 +1222,12 @@ int bpjd_problem_dims(const bpjd_problem* p, int32_t* n, int32_t* n_coarse, int3
     if (n_coarse) *n_coarse = p->nH;
     if (n_sub) *n_sub = p->nsub;
     if (s) *s = p->s;
+    return BPJD_OK;
+}
+
+int bpjd_problem_footprint(const bpjd_problem* p, uint64_t* bytes) {
+    if (!p || !bytes) return fail(BPJD_ERR_ARG, "NULL argument");
+    *bytes = p->footprint;
     return BPJD_OK;
 }
 

@@ -96,20 +96,20 @@ void launch_coarse_apply(hipStream_t st, int n, int nH, int s,
                          const double* lam, double* G, double* Cw, double* Zhat);
 void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, double* Floc);
 void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc);
-// Batched local LDL^T factor + solve, one wavefront per (subdomain, shift).
-// Floc/zloc: [s][sumN].  With fixed-slot local rows (sd != NULL, E slots per row) the
-// blocked MFMA solver runs (Lwork: 64 x 16 panels per (l, i)); otherwise the windowed
-// solver (Lwork: n_l (bw_l + 1) per (l, i)).
+// Batched local LDL^T factor + solve, one wavefront per (subdomain, shift).  Shift
+// lambda_i, or 0 for a system whose factorisation meets a negative pivot (the local
+// matrix is indefinite); negflag: nsub * s ints of scratch.
+// Floc/zloc: [s][sumN].  Local rows come as E fixed slots (band offset sd, (K, M)
+// pair sv).  blocked: the MFMA solver (band <= 48, E <= 8; Lwork: 64 x 16 panels per
+// (l, i)); otherwise the windowed solver (Lwork: n_l (bw_l + 1) per (l, i)).
 void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, int bws, const int* sd, const double2* sv,
+                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
-                            const long long* Loff, int* status);
+                            const long long* Loff, int* status, int* negflag);
 void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, int bws, const int* sd, const double2* sv,
+                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
-                            const long long* Loff, int* status);
+                            const long long* Loff, int* status, int* negflag);
 // Numeric local extraction: fixed-slot lower entries (offset, (K, M)) of every local row.
 void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr, const int* ldd, const int* lpos,
                           const double2* km, int* sd, double2* sv);
@@ -143,6 +143,23 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
                     double* theta, double* lam, double* Cfull);
 
+// ---- problem creation in two steps and the stepwise solve (api.hip) ----------
+struct HostPlan;
+// Validate and plan a problem on the host (no device memory); fills footprint.
+int plan_problem(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd, const bpjd_dd_geom* geom,
+                 const bpjd_opts* opts, bpjd_problem** out);
+// Allocate and upload a planned problem (on p->ctx's device).
+int materialize_problem(bpjd_problem* p);
+// One solve as a sequence of stages, each ending in a read-back event.
+struct SolveRun;
+int  run_create(bpjd_problem* p, SolveRun** out);
+void run_destroy(SolveRun* r);
+int  run_begin(SolveRun* r);       // enqueue the numeric setup
+int  run_poll(SolveRun* r);        // 1: pending read-back arrived, 0: not yet, < 0: error
+int  run_wait(SolveRun* r);        // spin until run_poll != 0
+int  run_advance(SolveRun* r);     // 1: finished, 0: next stage enqueued, < 0: error
+int  run_finish(SolveRun* r, double* eigvals, double* eigvecs, int mem, bpjd_stats* st);
+
 }  // namespace bpjd
 
 // ---- the opaque objects ---------------------------------------------------------
@@ -175,7 +192,8 @@ struct bpjd_problem {
     int *lptr = nullptr, *ldd = nullptr, *lpos = nullptr;
     int *rptr = nullptr, *ridx = nullptr;
     long long* Loff = nullptr;
-    int slotE = 0;                     // fixed slots per local row (blocked solver), 0 = windowed solver
+    int slotE = 0;                     // fixed slots per local row (lower entries incl. the diagonal)
+    bool blocked = false;              // local solver: blocked MFMA (true) or windowed
     int bws = 64;                      // stored rows per factor column (blocked solver)
     int* sd = nullptr;
     double2* sv = nullptr;
@@ -191,6 +209,7 @@ struct bpjd_problem {
     double *partial = nullptr, *colsq = nullptr, *lam = nullptr;
     double *gsmall = nullptr, *csmall = nullptr, *Hm = nullptr, *theta = nullptr, *Cfull = nullptr, *rrwork = nullptr;
     int *dropped[2] = {nullptr, nullptr}, *status = nullptr;   // per-buffer flags of W's columns
+    int* negflag = nullptr;            // per (subdomain, shift): indefinite local matrix
     double* hbuf = nullptr;            // pinned host mirror for per-iteration scalars
     int npart = 0;
     int nnzKH = 0;
@@ -199,4 +218,6 @@ struct bpjd_problem {
     std::vector<int> h_nl, h_bw;     // host copies of subdomain sizes / half-bandwidths
     bool setup_done = false;
     std::vector<void*> allocations;
+    bpjd::HostPlan* plan = nullptr;    // host arrays between planning and materialisation
+    size_t footprint = 0;              // device bytes of the problem (allocation granularity included)
 };

@@ -239,12 +239,18 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Local LDL^T factor + solve for bands too wide for the blocked solver: one wavefront
+// per (subdomain, shift), the band window of C = w + 1 rows in LDS as a circular
+// buffer.  Step j scales column j and updates the window (lane a owns row j + a), then
+// row j + C enters the window.  The entering rows come from the fixed-slot arrays
+// (band offset, (K, M) pair) and are loaded a block of RB rows at a time, one block
+// ahead, one slot per lane, so no step waits on global memory; the backward sweep
+// reads the stored factor columns D steps ahead in a register ring.
 template <typename T>
 __global__ __launch_bounds__(64) void local_ldlt_kernel(
-    int s, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ lptr,
-    const int* __restrict__ ldd, const int* __restrict__ lpos, const double2* __restrict__ km,
-    const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
-    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
+    int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
+    const double2* __restrict__ sv, const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF,
+    T* __restrict__ zloc, T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
     extern __shared__ unsigned char smem_raw[];
     T* win = reinterpret_cast<T*>(smem_raw);
     const int sys = blockIdx.x;
@@ -256,80 +262,156 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
     const int C = w + 1;
     T* ywin = win + C * C;
     T* zwin = ywin + C;
-    const double lamd = lam[i];
+    double shift = lam[i];      // 0 when K_l - lambda_i M_l is not positive definite
     T* Lc = Lwork + Loff[l] + (long long)i * nl * C;
     const T* f = Floc + (long long)i * ldF + off;
     T* z = zloc + (long long)i * ldF + off;
     const int lane = threadIdx.x;
-
-    for (int e = lane; e < C * C + 2 * C; e += 64) win[e] = T(0);
-    __syncthreads();
-    const int r0max = min(C, nl);
-    for (int r = lane; r < r0max; r += 64) {
-        T* row = win + r * C;
-        for (int e = lptr[off + r]; e < lptr[off + r + 1]; ++e) {
-            const double2 v = km[lpos[e]];
-            row[ldd[e]] = (T)(v.x - lamd * v.y);
-        }
-        ywin[r] = f[r];
-    }
-    __syncthreads();
+    // entering rows in blocks of RB rows, lane = (row d of the block, slot e); EP = slots
+    // per row rounded up to a power of two (E <= 64)
+    int EP = 1;
+    while (EP < E) EP <<= 1;
+    const int RB = 64 / EP;
+    const int ld = lane / EP, le = lane - ld * EP;
+    int bsd = -1, nsd = -1;            // slot of this lane in the current / next block
+    double2 bsv = make_double2(0.0, 0.0), nsv = bsv;
+    T bf = T(0), nf = T(0);            // right-hand side of row d of the block
+    auto load_block = [&](const int r0, int& dsd, double2& dsv, T& df) {
+        const int r = r0 + ld;
+        const bool ok = r < nl && le < E;
+        const long long k = ok ? (long long)(off + r) * E + le : 0LL;
+        dsd = sd[k];
+        dsv = sv[k];
+        if (!ok) dsd = -1;
+        df = f[min(r, nl - 1)];
+    };
 
     int bad = 0;
-    for (int j = 0; j < nl; ++j) {
-        const int sj = j % C;
-        T dj = win[sj * C];
-        if (!(dj == dj) || dj == T(0) || !isfinite((double)dj)) {
-            bad = 1;
-            dj = T(1);
-        }
-        const T inv = T(1) / dj;
-        const T yj = ywin[sj];
-        for (int a = lane + 1; a <= w && j + a < nl; a += 64) {
-            const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
-            T* rowa = win + ra * C;
-            const T lsc = rowa[a] * inv;
-            int rb = sj + 1 - (sj + 1 >= C ? C : 0);           // slot of row j + b, b = 1
-            for (int b = 1; b <= a; ++b) {
-                rowa[a - b] -= lsc * win[rb * C + b];
-                rb = (rb + 1 == C) ? 0 : rb + 1;
+    // forward phase; a negative pivot (indefinite local matrix) runs it again with shift 0
+    for (int attempt = 0;; ++attempt) {
+        for (int e = lane; e < C * C + 2 * C; e += 64) win[e] = T(0);
+        __syncthreads();
+        // rows 0 .. C-1 start the window
+        for (int r0 = 0; r0 < min(C, nl); r0 += RB) {
+            int dsd;
+            double2 dsv;
+            T df;
+            load_block(r0, dsd, dsv, df);
+            const int r = r0 + ld;
+            if (r < min(C, nl)) {
+                if (dsd >= 0) win[r * C + dsd] = (T)(dsv.x - shift * dsv.y);
+                if (le == 0) ywin[r] = df;
             }
-            ywin[ra] -= lsc * yj;
-            Lc[(long long)j * C + a] = lsc;
         }
-        if (lane == 0) {
-            Lc[(long long)j * C] = dj;
-            z[j] = yj * inv;
-        }
+        // blocks of the rows entering from step 0 on (row C + j at step j)
+        int bstart = C;
+        load_block(bstart, bsd, bsv, bf);
+        load_block(bstart + RB, nsd, nsv, nf);
         __syncthreads();
-        T* row = win + sj * C;
-        for (int e = lane; e < C; e += 64) row[e] = T(0);
-        __syncthreads();
-        const int rn = j + C;
-        if (rn < nl) {
-            for (int e = lptr[off + rn] + lane; e < lptr[off + rn + 1]; e += 64) {
-                const double2 v = km[lpos[e]];
-                row[ldd[e]] = (T)(v.x - lamd * v.y);
+
+        bad = 0;
+        int neg = 0;
+        for (int j = 0; j < nl; ++j) {
+            const int sj = j % C;
+            T dj = win[sj * C];
+            if (!(dj == dj) || dj == T(0) || !isfinite((double)dj)) {
+                bad = 1;
+                dj = T(1);
             }
-            if (lane == 0) ywin[sj] = f[rn];
+            neg |= dj < T(0);
+            const T inv = T(1) / dj;
+            const T yj = ywin[sj];
+            for (int a = lane + 1; a <= w && j + a < nl; a += 64) {
+                const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
+                T* rowa = win + ra * C;
+                const T lsc = rowa[a] * inv;
+                int rb = sj + 1 - (sj + 1 >= C ? C : 0);           // slot of row j + b, b = 1
+                // row j + a (offsets a - b) -= l_{j+a} * column j (row j + b, offset b),
+                // 8 entries at a time: the column entries are never written in this step,
+                // so all 16 loads of a group are issued before its first update
+                int b = 1;
+                for (; b + 7 <= a; b += 8) {
+                    T cv[8], rv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        cv[u] = win[rb * C + b + u];
+                        rv[u] = rowa[a - b - u];
+                        rb = (rb + 1 == C) ? 0 : rb + 1;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) rowa[a - b - u] = rv[u] - lsc * cv[u];
+                }
+                for (; b <= a; ++b) {
+                    rowa[a - b] -= lsc * win[rb * C + b];
+                    rb = (rb + 1 == C) ? 0 : rb + 1;
+                }
+                ywin[ra] -= lsc * yj;
+                Lc[(long long)j * C + a] = lsc;
+            }
+            if (lane == 0) {
+                Lc[(long long)j * C] = dj;
+                z[j] = yj * inv;
+            }
+            __syncthreads();
+            T* row = win + sj * C;
+            for (int e = lane; e < C; e += 64) row[e] = T(0);
+            __syncthreads();
+            const int rn = j + C;
+            if (rn < nl) {
+                if (rn == bstart + RB) {       // next block becomes current; fetch the one after
+                    bstart += RB;
+                    bsd = nsd;
+                    bsv = nsv;
+                    bf = nf;
+                    load_block(bstart + RB, nsd, nsv, nf);
+                }
+                if (ld == rn - bstart) {
+                    if (bsd >= 0) row[bsd] = (T)(bsv.x - shift * bsv.y);
+                    if (le == 0) ywin[sj] = bf;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        if (attempt > 0 || !neg) break;    // every lane reads the same pivots
+        shift = 0.0;
     }
-    // backward sweep with the unit upper factor L^T
-    for (int j = nl - 1; j >= 0; --j) {
-        const int sj = j % C;
-        T part = T(0);
-        for (int a = lane + 1; a <= w && j + a < nl; a += 64) {
-            const int ra = sj + a - (sj + a >= C ? C : 0);
-            part += Lc[(long long)j * C + a] * zwin[ra];
+    // backward sweep with the unit upper factor L^T; the columns of steps j - 1 .. j - D
+    // are in flight while step j is summed (lane a owns entries a = lane + 1, lane + 65)
+    constexpr int D = 4;
+    T la[D], lb[D], zq[D];
+    auto fetch_col = [&](const int j, T& va, T& vb, T& vz) {
+        const int jc = max(j, 0);
+        const int a1 = lane + 1, a2 = lane + 65;
+        va = (a1 <= w && jc + a1 < nl) ? Lc[(long long)jc * C + a1] : T(0);
+        vb = (a2 <= w && jc + a2 < nl) ? Lc[(long long)jc * C + a2] : T(0);
+        vz = z[jc];
+    };
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch_col(nl - 1 - u, la[u], lb[u], zq[u]);
+    for (int jj = nl - 1; jj >= 0; jj -= D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int j = jj - u;
+            if (j >= 0) {
+                const int sj = j % C;
+                const int a1 = lane + 1, a2 = lane + 65;
+                const int r1 = sj + a1 - (sj + a1 >= C ? C : 0);
+                T part = la[u] * zwin[(a1 <= w) ? r1 : 0];
+                if (a2 <= w) {
+                    const int r2 = sj + a2 - (sj + a2 >= C ? C : 0);
+                    part += lb[u] * zwin[r2];
+                }
+                const T zj0 = zq[u];
+                fetch_col(j - D, la[u], lb[u], zq[u]);
+                part = wave_sum(part);
+                if (lane == 0) {
+                    const T zj = zj0 - part;
+                    zwin[sj] = zj;
+                    z[j] = zj;
+                }
+                __syncthreads();
+            }
         }
-        part = wave_sum(part);
-        if (lane == 0) {
-            const T zj = z[j] - part;
-            zwin[sj] = zj;
-            z[j] = zj;
-        }
-        __syncthreads();
     }
     if (bad && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
 }
@@ -429,7 +511,8 @@ template <typename T>
 __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     int s, int E, int BWS, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
     const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
-    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
+    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status, int mode,
+    int* __restrict__ negflag) {
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
     constexpr int NT = 4, R = MFMA_WIN;
@@ -448,12 +531,15 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     __shared__ T vec[R];
     __shared__ T colsum[16];
     const int sys = blockIdx.x;
+    // mode 0: shift lambda_i, and negflag[sys] records a negative pivot (K_l - lambda_i M_l
+    // indefinite); mode 1: only the recorded systems, again with shift 0
+    if (mode && !negflag[sys]) return;
     const int l = sys / s;
     const int i = sys - l * s;
     const int off = subptr[l];
     const int nl = subptr[l + 1] - off;
     const int npan = (nl + 15) >> 4;
-    const double lamd = lam[i];
+    const double lamd = mode ? 0.0 : lam[i];
     const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
     const int q = lane >> 2, slot0 = lane & 3;
     T* Lp = Lwork + Loff[l] + (long long)i * npan * (16 * BWS);
@@ -525,7 +611,7 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         place(I, 16 * I, 0);
     }
     T y = (lane < nl) ? f[lane] : T(0);
-    int bad = 0;
+    int bad = 0, neg = 0;
 
     for (int P = 0; P < npan; ++P) {
         const int base = 16 * P;
@@ -573,6 +659,7 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
             // the factorisation as failed (checked once per panel, off the elimination chain)
             const T dl = pan[lane][lane];
             bad |= !(fabs(dl) > T(1e-30) && fabs(dl) < T(1e30));
+            neg |= dl < T(0);
             z[base + lane] = y * MT::recip(dl);
         }
         // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T; k-step k of a lane
@@ -676,6 +763,8 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         if (P >= 1) back_step(P - 1, bufB, zB);
     }
     if (__any(bad) && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);   // pivots were checked per lane
+    const bool indefinite = __any(neg);
+    if (mode == 0 && lane == 0) negflag[sys] = indefinite ? 1 : 0;
 }
 
 // Local extraction (numeric setup): the lower entries of every local row of
@@ -702,44 +791,45 @@ void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr
 template <typename T>
 static void launch_local_mfma(hipStream_t st, int nsub, int s, int E, int bws, long long sumN, const int* subptr,
                               const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
-                              T* Lwork, const long long* Loff, int* status) {
-    hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv, lam,
-                       Floc, sumN, zloc, Lwork, Loff, status);
+                              T* Lwork, const long long* Loff, int* status, int* negflag) {
+    // every system with shift lambda_i, then the indefinite ones again with shift 0 (the
+    // second launch's waves return at once when no system was flagged)
+    for (int mode = 0; mode < 2; ++mode)
+        hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv,
+                           lam, Floc, sumN, zloc, Lwork, Loff, status, mode, negflag);
 }
 
 template <typename T>
 static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr, const int* bw,
-                         const int* lptr, const int* ldd, const int* lpos, const double2* km, const double* lam,
-                         const T* Floc, T* zloc, T* Lwork, const long long* Loff, int* status) {
+                         int E, const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
+                         T* Lwork, const long long* Loff, int* status) {
     const size_t shmem = (size_t)(maxC * maxC + 2 * maxC) * sizeof(T);
-    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(64), shmem, st, s, subptr, bw, lptr, ldd, lpos, km,
-                       lam, Floc, sumN, zloc, Lwork, Loff, status);
+    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(64), shmem, st, s, E, subptr, bw, sd, sv, lam, Floc,
+                       sumN, zloc, Lwork, Loff, status);
 }
 
 void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, int bws, const int* sd, const double2* sv,
+                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
-                            const long long* Loff, int* status) {
-    if (sd) {
-        launch_local_mfma<double>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+                            const long long* Loff, int* status, int* negflag) {
+    if (blocked) {
+        launch_local_mfma<double>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
+                               negflag);
         return;
     }
-    launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
-                         status);
+    launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
 }
 
 void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, const int* lptr, const int* ldd, const int* lpos, const double2* km,
-                            int E, int bws, const int* sd, const double2* sv,
+                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
-                            const long long* Loff, int* status) {
-    if (sd) {
-        launch_local_mfma<float>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+                            const long long* Loff, int* status, int* negflag) {
+    if (blocked) {
+        launch_local_mfma<float>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
+                               negflag);
         return;
     }
-    launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, lptr, ldd, lpos, km, lam, Floc, zloc, Lwork, Loff,
-                        status);
+    launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
 }
 
 // ---------------------------------------------------------------------------

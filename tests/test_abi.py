@@ -61,10 +61,16 @@ def test_null_arguments_are_rejected_without_touching_a_device():
                  lambda: L.bpjd_spmm(None, None, 1, None, None, binding.MEM_HOST),
                  lambda: L.bpjd_coarse_eigenvalues(None, None, binding.MEM_HOST),
                  lambda: L.bpjd_apply_preconditioner(None, None, None, None, binding.MEM_HOST),
-                 lambda: L.bpjd_problem_set_values(None, None, None, binding.MEM_HOST)):
+                 lambda: L.bpjd_problem_set_values(None, None, None, binding.MEM_HOST),
+                 lambda: L.bpjd_problem_footprint(None, None),
+                 lambda: L.bpjd_server_create(None, 0, 4, ctypes.byref(h)),
+                 lambda: L.bpjd_server_submit(None, None, None, None, None, None, None),
+                 lambda: L.bpjd_server_poll(None, 1, None, None, None),
+                 lambda: L.bpjd_server_get_info(None, None)):
         assert call() == binding.ERR_ARG
     L.bpjd_problem_destroy(None)             # no-ops on NULL
     L.bpjd_ctx_destroy(None)
+    L.bpjd_server_destroy(None)
 
 
 def test_bad_device_ordinal_is_an_error():

@@ -83,6 +83,64 @@ def test_preconditioner_parity(B, ctx, name, prec):
     prob.close()
 
 
+def _local_minima(mesh, dd):
+    """Lowest Dirichlet eigenvalue of every subdomain's (K_l, M_l)."""
+    import scipy.linalg as sla
+    import scipy.sparse.linalg as spla
+    ls = o.local_setup(mesh.K, mesh.M, dd.subs)
+    mus = []
+    for Kl, Ml in zip(ls.K_loc, ls.M_loc):
+        if Kl.shape[0] <= 600:
+            mus.append(sla.eigh(Kl.toarray(), Ml.toarray(), eigvals_only=True, subset_by_index=[0, 0])[0])
+        else:
+            mus.append(float(np.min(spla.eigsh(Kl, k=1, M=Ml, sigma=0.0, which="LM",
+                                               return_eigenvectors=False))))
+    return np.array(mus), ls
+
+
+@pytest.mark.parametrize("name", ["c1", "w56", "served0"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_preconditioner_indefinite_local(B, ctx, name, prec):
+    """Shifts above some subdomains' lowest Dirichlet eigenvalue: there the local matrix
+    K_l - lambda_i M_l is indefinite and the local solve takes shift 0 (the oracle's
+    reading of the paper's positive-definiteness premise); both the blocked MFMA solver
+    (c1, served0) and the windowed solver (w56) take that path."""
+    _case(f"preconditioner indefinite {name} {prec}")
+    if name == "served0":
+        r = w.serving_requests(count=1, h_choices=(64,))[0]
+        mesh, L, k, guard = w.request_mesh(r), r["L"], r["k"], r["guard"]
+    else:
+        mesh, cfg = w.config_mesh(name)
+        L, k, guard = cfg["L"], cfg["k"], cfg["guard"]
+    s = k + guard
+    precision = B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED
+    prob = B.problem_from_mesh(ctx, mesh, L, k=k, guard=guard, precision=precision)
+    prob.setup()
+    dd = o.build_dd(mesh, L)
+    cs = o.coarse_setup(mesh.K, mesh.M, dd.P)
+    mus, ls = _local_minima(mesh, dd)
+    # shifts spread over [0.5, 2.5] x the smallest local minimum, each at least 5 % away
+    # from every subdomain's lowest eigenvalue (the definiteness decision is then the
+    # same in FP32, FP64 and exact arithmetic, and no local system is worse conditioned
+    # than the FP32 tolerance allows) and from the coarse eigenvalues (the coarse
+    # denominators lambda^H_j - lambda_i stay well away from 0)
+    lam = np.linspace(0.5, 2.5, s) * mus.min()
+    avoid = np.concatenate([mus, cs.lamH])
+    for q in range(s):
+        while np.min(np.abs(lam[q] / avoid - 1.0)) < 0.05:
+            lam[q] *= 1.013
+    n_indef = sum(int(np.sum(lam[q] > mus)) for q in range(s))
+    assert n_indef > 0
+    X = np.random.default_rng(4).standard_normal((mesh.n, s))
+    Zg = prob.apply_preconditioner(X, lam)
+    F = (mesh.M @ X) * lam - mesh.K @ X
+    Zo = o.precondition(F, lam, cs, ls, s)
+    err = np.abs(Zg - Zo).max() / np.abs(Zo).max()
+    print(f"  indefinite local systems {n_indef}, max rel err {err:.3e}", flush=True)
+    assert err < (1e-12 if prec == "fp64" else 2e-5)
+    prob.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("subspace", ["UU", "U"])
 def test_solve_c1(B, ctx, prec, subspace):

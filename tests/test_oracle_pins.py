@@ -184,14 +184,15 @@ def test_preconditioner_symmetric():
 
 
 def test_single_subdomain_degeneracy():
-    """One subdomain holding every dof and no coarse term: z_i = -x_i, so t_i = 0."""
+    """One subdomain holding every dof and no coarse term: z_i = -x_i, so t_i = 0
+    (shifts below lambda_1 ~ 2 pi^2, where K - lambda_i M is positive definite)."""
     mesh, cfg = w.config_mesh("t16")
     dd = o.build_dd(mesh, cfg["L"])
     s = 3
     cs = o.coarse_setup(mesh.K, mesh.M, dd.P)
     ls = o.local_setup(mesh.K, mesh.M, [np.arange(mesh.n)])
     X = o.m_orthonormalize(np.random.default_rng(5).standard_normal((mesh.n, s)), mesh.M)
-    lam = np.array([30.0, 60.0, 90.0])
+    lam = np.array([5.0, 10.0, 15.0])
     MX = mesh.M @ X
     F = MX * lam - mesh.K @ X
     Z = o.precondition(F, lam, cs, ls, s, use_coarse=False)
@@ -254,3 +255,32 @@ def test_iterations_stable_in_h():
         assert res.converged
         its.append(res.iterations)
     assert max(its) - min(its) <= 2, its
+
+
+def test_positive_definite_test_against_eigenvalues():
+    """The Cholesky-based definiteness test agrees with the sign of the smallest
+    eigenvalue, on dense (n <= 400) and banded (n > 400) local matrices."""
+    for name in ("t16", "c1", "t64"):
+        mesh, cfg = w.config_mesh(name)
+        dd = o.build_dd(mesh, cfg["L"])
+        ls = o.local_setup(mesh.K, mesh.M, dd.subs[:2])
+        for Kl, Ml in zip(ls.K_loc, ls.M_loc):
+            mu = sla.eigh(Kl.toarray(), Ml.toarray(), eigvals_only=True, subset_by_index=[0, 0])[0]
+            for shift in (0.0, 0.5 * mu, 0.99 * mu, 1.01 * mu, 2.0 * mu):
+                assert o.positive_definite((Kl - shift * Ml).tocsc()) == (shift < mu), (name, shift, mu)
+
+
+def test_local_shift_falls_back_to_zero_when_indefinite():
+    """Above the subdomain's lowest Dirichlet eigenvalue the local solve is K_l^{-1}
+    (shift 0); below it, (K_l - lambda_i M_l)^{-1}."""
+    mesh, cfg = w.config_mesh("c1")
+    dd = o.build_dd(mesh, cfg["L"])
+    S = dd.subs[5]
+    ls = o.local_setup(mesh.K, mesh.M, [S])
+    Kl, Ml = ls.K_loc[0].toarray(), ls.M_loc[0].toarray()
+    mu = sla.eigh(Kl, Ml, eigvals_only=True, subset_by_index=[0, 0])[0]
+    F = np.random.default_rng(7).standard_normal((mesh.n, 2))
+    lam = np.array([0.9 * mu, 1.1 * mu])
+    Z = o.local_term(F, lam, ls)
+    np.testing.assert_allclose(Z[S, 0], np.linalg.solve(Kl - lam[0] * Ml, F[S, 0]), rtol=1e-10)
+    np.testing.assert_allclose(Z[S, 1], np.linalg.solve(Kl, F[S, 1]), rtol=1e-10)
