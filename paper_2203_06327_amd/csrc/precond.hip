@@ -321,7 +321,9 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
             neg |= dj < T(0);
             const T inv = T(1) / dj;
             const T yj = ywin[sj];
-            for (int a = lane + 1; a <= w && j + a < nl; a += 64) {
+            // rows j + a, a = 1..w, in pairs (a, w + 1 - a): lane q < ceil(w/2) updates rows
+            // q + 1 and w - q, so every lane does at most w + 1 entries
+            auto update_row = [&](const int a) {
                 const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
                 T* rowa = win + ra * C;
                 const T lsc = rowa[a] * inv;
@@ -347,6 +349,11 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
                 }
                 ywin[ra] -= lsc * yj;
                 Lc[(long long)j * C + a] = lsc;
+            };
+            if (lane < (w + 1) / 2) {
+                const int a1 = lane + 1, a2 = w - lane;
+                if (j + a1 < nl) update_row(a1);
+                if (a2 != a1 && j + a2 < nl) update_row(a2);
             }
             if (lane == 0) {
                 Lc[(long long)j * C] = dj;

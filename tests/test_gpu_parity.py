@@ -248,3 +248,26 @@ def test_solve_largest_block(B, ctx):
     assert np.max(np.abs(lam - ref) / ref) < 1e-9
     G = X.T @ (mesh.M @ X)
     assert np.max(np.abs(G - np.eye(req["k"]))) < 1e-10
+
+
+def test_solve_c3_full_size(B, ctx):
+    """The 1,056,759-dof rectangle (32 x 32 subdomains, uneven last row, k = 12 with one
+    guard vector) with FP32 local solves: eigenvalues against the stored oracle
+    reference, residuals recomputed on the host, M-orthonormality."""
+    import os
+    _case("solve c3 full size mixed")
+    mesh, cfg = w.config_mesh("c3")
+    k = cfg["k"]
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8, precision=B.PREC_MIXED)
+    lam, X, st = prob.solve()
+    prob.close()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_reference.txt")
+    ref = np.array([float(line.split()[1]) for line in open(path) if not line.startswith("#")])[:k]
+    rel = np.abs(lam - ref) / ref
+    KX, MX = mesh.K @ X, mesh.M @ X
+    rho = np.linalg.norm(KX - MX * lam, axis=0) / (lam * np.linalg.norm(MX, axis=0))
+    print(f"  iterations {st['iterations']}  max rel err {rel.max():.3e}  host max rho {rho.max():.3e}", flush=True)
+    assert st["converged"]
+    assert rel.max() < 1e-10
+    assert rho.max() <= 1.5e-8
+    np.testing.assert_allclose(X.T @ MX, np.eye(k), atol=1e-10)

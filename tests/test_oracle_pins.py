@@ -284,3 +284,14 @@ def test_local_shift_falls_back_to_zero_when_indefinite():
     Z = o.local_term(F, lam, ls)
     np.testing.assert_allclose(Z[S, 0], np.linalg.solve(Kl - lam[0] * Ml, F[S, 0]), rtol=1e-10)
     np.testing.assert_allclose(Z[S, 1], np.linalg.solve(Kl, F[S, 1]), rtol=1e-10)
+
+
+def test_c3_reference_file_against_continuous_limit():
+    """The stored reference eigenvalues of the 1,056,759-dof rectangle lie just above
+    pi^2 (i^2 + j^2 / 1.01^2) (conforming P1, error O(h^2) at h = 1/1024)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_reference.txt")
+    lam = np.array([float(line.split()[1]) for line in open(path) if not line.startswith("#")])
+    modes = sorted(i * i + j * j / 1.01 ** 2 for i in range(1, 8) for j in range(1, 8))[:13]
+    rel = lam / (PI2 * np.array(modes)) - 1.0
+    assert np.all(rel > 0) and np.all(rel < 3e-5), rel
