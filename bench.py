@@ -202,6 +202,15 @@ def serving_bench(B, ctx, reqs, meshes, budget: int, slots: int, rate_frac: floa
                   flush=True)
     t_plain = time.perf_counter() - t0
     print(f"[bench] served mix, plain FP64 one at a time: {t_plain:.2f} s", file=sys.stderr, flush=True)
+    # (i') the same one at a time with FP32 local solves: separates the precision gain
+    # from the batching gain
+    t0 = time.perf_counter()
+    for r, mesh in zip(reqs, meshes):
+        prob = B.problem_from_mesh(ctx, mesh, r["L"], k=r["k"], guard=r["guard"], precision=B.PREC_MIXED)
+        prob.solve(raise_noconv=False)
+        prob.close()
+    t_mixed1 = time.perf_counter() - t0
+    print(f"[bench] served mix, mixed one at a time: {t_mixed1:.2f} s", file=sys.stderr, flush=True)
 
     # (ii) server, burst: all requests at t = 0
     srv = B.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
@@ -246,10 +255,12 @@ def serving_bench(B, ctx, reqs, meshes, budget: int, slots: int, rate_frac: floa
         "requests": len(reqs), "eigenpairs": total_k, "dofs_total": int(sum(m.n for m in meshes)),
         "hbm_budget_bytes": budget, "slots": slots,
         "plain_fp64_one_at_a_time": {"value": total_k / t_plain, "unit": "eigenpairs/s", "wall_s": t_plain},
+        "mixed_one_at_a_time": {"value": total_k / t_mixed1, "unit": "eigenpairs/s", "wall_s": t_mixed1},
         "served_mixed_burst": {"value": total_k / t_burst, "unit": "eigenpairs/s", "wall_s": t_burst,
                                "requests_per_s": mu, "peak_running": info_burst["peak_running"],
                                "peak_bytes": info_burst["peak_bytes"]},
         "speedup_vs_plain_fp64": t_plain / t_burst,
+        "speedup_batching_vs_mixed_one_at_a_time": t_mixed1 / t_burst,
         "served_mixed_poisson": {"arrival_rate_per_s": rate, "value": total_k / t_poisson, "unit": "eigenpairs/s",
                                  "wall_s": t_poisson, "p50_ms": float(np.percentile(lat, 50)),
                                  "p99_ms": float(np.percentile(lat, 99)),
@@ -283,8 +294,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the untimed per-phase profile solve")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
-    ap.add_argument("--serve-requests", type=int, default=256,
-                    help="requests of the served mix (0: skip the serving measurement)")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests of the served mix: the first N of the 256-request workload "
+                         "(0: skip the serving measurement)")
+    ap.add_argument("--serve-only", action="store_true", help="only the served-mix measurement")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of the server")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -312,6 +325,17 @@ def main():
         return
     from paper_2203_06327_amd import binding as B
     from paper_2203_06327_amd import workloads as w
+
+    if args.serve_only:
+        if served is None:
+            print("--serve-only needs --serve-requests > 0", file=sys.stderr)
+            sys.exit(2)
+        ctx = B.Context(0)
+        serving = serving_bench(B, ctx, served[0], served[1], int(args.serve_budget_gb * (1 << 30)),
+                                args.serve_slots)
+        print(json.dumps({"metric": METRIC, "n_gpus": 1, "data": "synthetic", "serving": serving}), flush=True)
+        ctx.close()
+        return
 
     mesh, cfg = w.config_mesh(args.config)
     k, s = cfg["k"], cfg["k"] + cfg["guard"]
@@ -365,7 +389,7 @@ def main():
     local_flops = local_solve_flops(nl, bw, s)
     roofline = {"bound": "alu", "achieved": local_flops / (local_avg_ms * 1e-3) / 1e12,
                 "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s", "traffic": None,
-                "kernel": "local_band_mfma_kernel<float>", "avg_launch_ms": local_avg_ms,
+                "kernel": "local_band_mfma_kernel<float, 0>", "avg_launch_ms": local_avg_ms,
                 "launches_timed": local_n, "algorithmic_per_launch": local_flops}
     roofline["frac"] = roofline["achieved"] / roofline["peak"]
     roofline["traffic"] = counter_traffic(args.config)

@@ -98,16 +98,20 @@ void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const
 void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc);
 // Batched local LDL^T factor + solve, one wavefront per (subdomain, shift).  Shift
 // lambda_i, or 0 for a system whose factorisation meets a negative pivot (the local
-// matrix is indefinite); negflag: nsub * s ints of scratch.
+// matrix is indefinite).  mode 0 solves every system (the windowed solver redoes an
+// indefinite one in place); mode 1 redoes the blocked solver's indefinite systems
+// with shift 0 (no-op for the windowed solver).  negflag: nsub * s ints of scratch.
 // Floc/zloc: [s][sumN].  Local rows come as E fixed slots (band offset sd, (K, M)
 // pair sv).  blocked: the MFMA solver (band <= 48, E <= 8; Lwork: 64 x 16 panels per
 // (l, i)); otherwise the windowed solver (Lwork: n_l (bw_l + 1) per (l, i)).
-void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
+void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
+                            const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
+                            const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status, int* negflag);
-void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
+void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
+                            const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
+                            const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status, int* negflag);
 // Numeric local extraction: fixed-slot lower entries (offset, (K, M)) of every local row.

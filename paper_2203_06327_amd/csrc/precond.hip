@@ -514,12 +514,13 @@ struct MfmaTile<double> {
 
 constexpr int MFMA_WIN = 64;       // window rows
 
-template <typename T>
+template <typename T, int MODE>
 __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     int s, int E, int BWS, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
     const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
-    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status, int mode,
+    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
     int* __restrict__ negflag) {
+    constexpr int mode = MODE;
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
     constexpr int NT = 4, R = MFMA_WIN;
@@ -796,14 +797,17 @@ void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr
 }
 
 template <typename T>
-static void launch_local_mfma(hipStream_t st, int nsub, int s, int E, int bws, long long sumN, const int* subptr,
-                              const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
-                              T* Lwork, const long long* Loff, int* status, int* negflag) {
-    // every system with shift lambda_i, then the indefinite ones again with shift 0 (the
-    // second launch's waves return at once when no system was flagged)
-    for (int mode = 0; mode < 2; ++mode)
-        hipLaunchKernelGGL(local_band_mfma_kernel<T>, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv,
-                           lam, Floc, sumN, zloc, Lwork, Loff, status, mode, negflag);
+static void launch_local_mfma(hipStream_t st, int mode, int nsub, int s, int E, int bws, long long sumN,
+                              const int* subptr, const int* sd, const double2* sv, const double* lam, const T* Floc,
+                              T* zloc, T* Lwork, const long long* Loff, int* status, int* negflag) {
+    // mode 0: every system with shift lambda_i; mode 1: the systems found indefinite,
+    // again with shift 0 (its waves return at once when no system was flagged)
+    if (mode == 0)
+        hipLaunchKernelGGL((local_band_mfma_kernel<T, 0>), dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv,
+                           lam, Floc, sumN, zloc, Lwork, Loff, status, negflag);
+    else
+        hipLaunchKernelGGL((local_band_mfma_kernel<T, 1>), dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv,
+                           lam, Floc, sumN, zloc, Lwork, Loff, status, negflag);
 }
 
 template <typename T>
@@ -815,28 +819,30 @@ static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long su
                        sumN, zloc, Lwork, Loff, status);
 }
 
-void launch_local_solve_f64(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
-                            const double* lam, const double* Floc, double* zloc, double* Lwork,
+void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
+                            const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
+                            const double2* sv, const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status, int* negflag) {
     if (blocked) {
-        launch_local_mfma<double>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
+        launch_local_mfma<double>(st, mode, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
                                negflag);
         return;
     }
-    launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+    if (mode == 0)   // the windowed solver takes its second pass inside the kernel
+        launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
 }
 
-void launch_local_solve_f32(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr,
-                            const int* bw, int blocked, int E, int bws, const int* sd, const double2* sv,
-                            const double* lam, const float* Floc, float* zloc, float* Lwork,
+void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
+                            const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
+                            const double2* sv, const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status, int* negflag) {
     if (blocked) {
-        launch_local_mfma<float>(st, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
+        launch_local_mfma<float>(st, mode, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
                                negflag);
         return;
     }
-    launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+    if (mode == 0)   // the windowed solver takes its second pass inside the kernel
+        launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
 }
 
 // ---------------------------------------------------------------------------
