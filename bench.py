@@ -389,7 +389,7 @@ def main():
     local_flops = local_solve_flops(nl, bw, s)
     roofline = {"bound": "alu", "achieved": local_flops / (local_avg_ms * 1e-3) / 1e12,
                 "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s", "traffic": None,
-                "kernel": "local_band_mfma_kernel<float, 0>", "avg_launch_ms": local_avg_ms,
+                "kernel": "local_band_mfma_kernel<float, 0, 4>", "avg_launch_ms": local_avg_ms,
                 "launches_timed": local_n, "algorithmic_per_launch": local_flops}
     roofline["frac"] = roofline["achieved"] / roofline["peak"]
     roofline["traffic"] = counter_traffic(args.config)

@@ -22,7 +22,8 @@ namespace bpjd {
 static thread_local std::string g_last_error;
 
 // largest half-bandwidth and lower entries per row handled by the blocked (MFMA) local solver
-static constexpr int kBlockedMaxBand = 48;
+static constexpr int kBlockedMaxBand = 48;       // 64-row window (4 tile-rows)
+static constexpr int kBlockedWideMaxBand = 80;   // 96-row window (6 tile-rows)
 static constexpr int kBlockedMaxSlots = 8;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -417,7 +418,8 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     // solver one band column per row
     int maxE = 0;
     for (long long q = 0; q < sumN; ++q) maxE = std::max(maxE, lptr[q + 1] - lptr[q]);
-    const bool blocked = maxBW <= kBlockedMaxBand && maxE <= kBlockedMaxSlots;
+    const bool blocked = maxBW <= kBlockedWideMaxBand && maxE <= kBlockedMaxSlots;
+    const int nt = !blocked ? 0 : (maxBW <= kBlockedMaxBand ? 4 : 6);   // window tile-rows
     // the windowed solver gives each lane at most two entries of a window row and loads
     // the slots of a block of rows one slot per lane
     if (!blocked && (maxBW > 127 || maxE > 64))
@@ -425,7 +427,8 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     // FP64 factors keep only the band of each column (halves the factor traffic that
     // bounds the backward sweep); FP32 factors keep full 64-row columns, whose stores
     // and loads need no per-lane masks
-    const int bws = opts->precision == BPJD_PREC_MIXED ? 64 : ((std::min(64, maxBW + 1) + 3) / 4) * 4;
+    const int win = 16 * std::max(nt, 4);
+    const int bws = opts->precision == BPJD_PREC_MIXED ? win : ((std::min(win, maxBW + 1) + 3) / 4) * 4;
     std::vector<long long> Loff(nsub, 0);
     long long Ltot = 0;
     for (int l = 0; l < nsub; ++l) {
@@ -541,6 +544,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     h->elt = elt;
     p->slotE = maxE;
     p->blocked = blocked;
+    p->mfma_nt = nt;
     if (blocked) p->bws = bws;
     p->npart = num_partials(n);
     size_t bytes = 0;
@@ -689,11 +693,11 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
     for (int mode = 0; mode < 2; ++mode) {
         if (mode == 0) PH_BEGIN(T, BPJD_PHASE_LOCAL);
         if (mixed)
-            launch_local_solve_f32(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->blocked ? 1 : 0,
+            launch_local_solve_f32(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->mfma_nt,
                                    p->slotE, p->bws, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
                                    (float*)p->Lwork, p->Loff, p->status, p->negflag);
         else
-            launch_local_solve_f64(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->blocked ? 1 : 0,
+            launch_local_solve_f64(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->mfma_nt,
                                    p->slotE, p->bws, p->sd, p->sv, p->lam, (const double*)p->Floc,
                                    (double*)p->zloc, (double*)p->Lwork, p->Loff, p->status, p->negflag);
         if (mode == 0) PH_END(T);

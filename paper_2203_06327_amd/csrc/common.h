@@ -102,8 +102,9 @@ void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const
 // indefinite one in place); mode 1 redoes the blocked solver's indefinite systems
 // with shift 0 (no-op for the windowed solver).  negflag: nsub * s ints of scratch.
 // Floc/zloc: [s][sumN].  Local rows come as E fixed slots (band offset sd, (K, M)
-// pair sv).  blocked: the MFMA solver (band <= 48, E <= 8; Lwork: 64 x 16 panels per
-// (l, i)); otherwise the windowed solver (Lwork: n_l (bw_l + 1) per (l, i)).
+// pair sv).  blocked = 4 or 6: the MFMA solver with a window of 16 * blocked rows
+// (band <= 48 or <= 80, E <= 8; Lwork: bws x 16 panels per (l, i)); blocked = 0: the
+// windowed solver (Lwork: n_l (bw_l + 1) per (l, i)).
 void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv,
@@ -198,6 +199,7 @@ struct bpjd_problem {
     long long* Loff = nullptr;
     int slotE = 0;                     // fixed slots per local row (lower entries incl. the diagonal)
     bool blocked = false;              // local solver: blocked MFMA (true) or windowed
+    int mfma_nt = 0;                   // blocked solver's window tile-rows (4 or 6), 0 = windowed
     int bws = 64;                      // stored rows per factor column (blocked solver)
     int* sd = nullptr;
     double2* sv = nullptr;

@@ -512,9 +512,10 @@ struct MfmaTile<double> {
     }
 };
 
-constexpr int MFMA_WIN = 64;       // window rows
-
-template <typename T, int MODE>
+// Window of NT tile-rows (R = 16 NT rows): NT = 4 for half-bandwidths up to 48, NT = 6
+// for up to 80.  Rows 0..63 of the window are one per lane ("set 1"); with NT = 6,
+// rows 64..95 are held by lanes 0..31 as a second set of registers ("set 2").
+template <typename T, int MODE, int NT>
 __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     int s, int E, int BWS, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
     const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
@@ -523,7 +524,9 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     constexpr int mode = MODE;
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
-    constexpr int NT = 4, R = MFMA_WIN;
+    constexpr int R = 16 * NT;
+    constexpr bool TWO = R > 64;            // a second set of window rows (64 .. R-1)
+    static_assert(R <= 128 && (NT == 4 || NT == 6), "window of 64 or 96 rows");
     constexpr int EPL = 2;                  // slot entries a lane carries (E <= 4 * EPL)
     // LDS: panT (column-major panel, accumulator -> row-per-lane), pan (row-major factored
     // panel, -> MFMA operands; reused column-major by the backward sweep), nrowT (the
@@ -531,7 +534,8 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     // accumulator rows of a lane are adjacent), vec (shift of the right-hand side)
     // (strides keep 16-byte alignment and spread lanes over banks; the FP64 sizes keep a
     // workgroup under 20 KB so that eight fit in one compute unit's LDS)
-    constexpr int PS = sizeof(T) == 4 ? 84 : 82, QS = sizeof(T) == 4 ? 20 : 18;
+    constexpr int PS = TWO ? (sizeof(T) == 4 ? 124 : 114) : (sizeof(T) == 4 ? 84 : 82);
+    constexpr int QS = sizeof(T) == 4 ? 20 : 18;
     static_assert(16 * PS >= R * QS, "pan aliases panT");
     __shared__ __align__(16) T panT[16][PS];
     __shared__ __align__(16) T nrowT[R][QS];
@@ -619,6 +623,7 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         place(I, 16 * I, 0);
     }
     T y = (lane < nl) ? f[lane] : T(0);
+    T y2 = (TWO && lane < R - 64 && 64 + lane < nl) ? f[64 + lane] : T(0);
     int bad = 0, neg = 0;
 
     for (int P = 0; P < npan; ++P) {
@@ -627,40 +632,71 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         fetch(base + 16 * NT);
         const int rnew = base + 16 + lane;
         const T fraw = f[min(rnew, nl - 1)];
+        const int rnew2 = base + 80 + lane;            // set 2: window row 64 + lane after the slide
+        const T fraw2 = TWO ? f[min(rnew2, nl - 1)] : T(0);
         // panel (tile column 0) -> one row per lane, through the column-major panT
 #pragma unroll
         for (int I = 0; I < NT; ++I)
 #pragma unroll
             for (int ii = 0; ii < 4; ++ii) panT[lr][16 * I + MT::row(lane, ii)] = A[I][0][ii];
         wave_sync();
-        T a[16];
+        T a[16], a2[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[c] = panT[c][lane];
+        if constexpr (TWO) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a2[c] = panT[c][min(64 + lane, R - 1)];
+        }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const T u = a[c];
             const T dc = MT::bcast(u, c);
-            const T lt = u * MT::recip(dc);
+            const T rc = MT::recip(dc);
+            const T lt = u * rc;
 #pragma unroll
             for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * MT::bcast(u, c2);
             const T yc = MT::bcast(y, c);
             if (lane > c) y -= lt * yc;
             a[c] = (lane == c) ? dc : lt;
+            if constexpr (TWO) {       // rows 64.. lie below the panel: plain elimination
+                const T lt2 = a2[c] * rc;
+#pragma unroll
+                for (int c2 = c + 1; c2 < 16; ++c2) a2[c2] -= lt2 * MT::bcast(u, c2);
+                y2 -= lt2 * yc;
+                a2[c] = lt2;
+            }
         }
         // store the factored panel and D^{-1} L^{-1} f of its 16 rows: column c keeps its
         // band part, window rows c .. c + BWS - 1 (lanes write consecutive values)
         T* Lpan = Lp + (long long)P * (16 * BWS) + lane;
-        if (BWS >= R) {                       // full 64-row columns: unconditional stores
+        if (BWS >= R) {                       // full R-row columns: unconditional stores
 #pragma unroll
             for (int c = 0; c < 16; ++c) Lpan[c * R] = a[c];
+            if constexpr (TWO) {
+                if (lane < R - 64) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) Lpan[c * R + 64] = a2[c];
+                }
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 16; ++c)
                 if (lane >= c && lane - c < BWS) Lpan[c * BWS - c] = a[c];
+            if constexpr (TWO) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (lane < R - 64 && 64 + lane - c < BWS) Lpan[c * BWS - c + 64] = a2[c];
+            }
         }
         wave_sync();
 #pragma unroll
         for (int c = 0; c < 16; ++c) pan[lane][c] = a[c];
+        if constexpr (TWO) {
+            if (lane < R - 64) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) pan[64 + lane][c] = a2[c];
+            }
+        }
         wave_sync();
         if (lane < 16 && base + lane < nl) {
             // the pivots of the panel, one per lane: a zero, tiny or non-finite pivot marks
@@ -699,53 +735,79 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
 #pragma unroll
             for (int J = 1; J <= I; ++J) A[I - 1][J - 1] = A[I][J];
         if (P + 1 < npan) place(NT - 1, base + 16 * NT, base + 16);
+        // shift the right-hand side by 16 window rows; fresh rows enter at the bottom
         vec[lane] = y;
+        if constexpr (TWO) {
+            if (lane < R - 64) vec[64 + lane] = y2;
+        }
         wave_sync();
         y = (lane < R - 16) ? vec[lane + 16] : ((rnew < nl) ? fraw : T(0));
+        if constexpr (TWO) y2 = (lane < R - 80) ? vec[80 + lane] : ((lane < R - 64 && rnew2 < nl) ? fraw2 : T(0));
         wave_sync();
     }
 
     // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows.
     // Two register buffers alternate: a panel is read two steps before it is used, so
     // the loads overlap two panel steps; indices are clamped so every load is in bounds.
-    T zw = T(0);
+    T zw = T(0), zw2 = T(0);                // z of window rows lane (and 64 + lane)
     T (*bt)[PS] = panT;                     // column-major panel copy
-    T bufA[16], bufB[16];
+    T bufA[16], bufB[16], bufA2[16], bufB2[16];
     T zA, zB;
-    auto load_panel = [&](const int P, T (&dst)[16], T& zdst) {
+    auto load_panel = [&](const int P, T (&dst)[16], T (&dst2)[16], T& zdst) {
         const int Pc = max(P, 0);
         const T* Lpan = Lp + (long long)Pc * (16 * BWS) + lane;
         if (BWS >= R) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) dst[c] = Lpan[c * R];
+            if constexpr (TWO) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) dst2[c] = (lane < R - 64) ? Lpan[c * R + 64] : T(0);
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 16; ++c) dst[c] = (lane >= c && lane - c < BWS) ? Lpan[c * BWS - c] : T(0);
+            if constexpr (TWO) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    dst2[c] = (lane < R - 64 && 64 + lane - c < BWS) ? Lpan[c * BWS - c + 64] : T(0);
+            }
         }
         zdst = z[min(16 * Pc + lr, nl - 1)];
     };
-    auto back_step = [&](const int P, T (&a)[16], T& zb) {
+    auto back_step = [&](const int P, T (&a)[16], T (&a2)[16], T& zb) {
         const int base = 16 * P;
         const T zc0 = (lane < 16 && base + lane < nl) ? zb : T(0);
         vec[lane] = zw;
+        if constexpr (TWO) {
+            if (lane < R - 64) vec[64 + lane] = zw2;
+        }
         wave_sync();
         zw = (lane >= 16) ? vec[lane - 16] : T(0);
+        if constexpr (TWO) zw2 = (lane < R - 64) ? vec[48 + lane] : T(0);
         wave_sync();
         // column-major copy of the panel in LDS (reusing the panel buffer): rows below
         // the panel hold L(r, c) z_r, the 16 panel rows hold L(r, c) itself
 #pragma unroll
         for (int c = 0; c < 16; ++c) bt[c][lane] = (lane >= 16) ? a[c] * zw : a[c];
+        if constexpr (TWO) {
+            if (lane < R - 64) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) bt[c][64 + lane] = a2[c] * zw2;
+            }
+        }
         wave_sync();
         // this buffer is free again: start reading the panel two steps further down
-        load_panel(P - 2, a, zb);
-        // contributions of the 48 rows below the panel: lane (c, quarter) sums 12 rows
-        // of column c, then the four quarters are added with quad permutations
+        load_panel(P - 2, a, a2, zb);
+        // contributions of the R - 16 rows below the panel: lane (c, quarter) sums
+        // (R - 16) / 4 rows of column c, then the four quarters are added with quad
+        // permutations
         {
+            constexpr int RQ = (R - 16) / 4;
             const int c = lane >> 2, qq = lane & 3;
-            const T* src = &bt[c][16 + 12 * qq];
+            const T* src = &bt[c][16 + RQ * qq];
             T acc = T(0);
 #pragma unroll
-            for (int j = 0; j < 12; ++j) acc += src[j];
+            for (int j = 0; j < RQ; ++j) acc += src[j];
             acc = quad_sum(acc);
             if (qq == 0) colsum[c] = acc;
         }
@@ -764,11 +826,11 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         if (lane < 16 && base + lane < nl) z[base + lane] = val;
         wave_sync();
     };
-    load_panel(npan - 1, bufA, zA);
-    load_panel(npan - 2, bufB, zB);
+    load_panel(npan - 1, bufA, bufA2, zA);
+    load_panel(npan - 2, bufB, bufB2, zB);
     for (int P = npan - 1; P >= 0; P -= 2) {
-        back_step(P, bufA, zA);
-        if (P >= 1) back_step(P - 1, bufB, zB);
+        back_step(P, bufA, bufA2, zA);
+        if (P >= 1) back_step(P - 1, bufB, bufB2, zB);
     }
     if (__any(bad) && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);   // pivots were checked per lane
     const bool indefinite = __any(neg);
@@ -797,17 +859,23 @@ void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr
 }
 
 template <typename T>
-static void launch_local_mfma(hipStream_t st, int mode, int nsub, int s, int E, int bws, long long sumN,
+static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s, int E, int bws, long long sumN,
                               const int* subptr, const int* sd, const double2* sv, const double* lam, const T* Floc,
                               T* zloc, T* Lwork, const long long* Loff, int* status, int* negflag) {
     // mode 0: every system with shift lambda_i; mode 1: the systems found indefinite,
-    // again with shift 0 (its waves return at once when no system was flagged)
-    if (mode == 0)
-        hipLaunchKernelGGL((local_band_mfma_kernel<T, 0>), dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv,
-                           lam, Floc, sumN, zloc, Lwork, Loff, status, negflag);
-    else
-        hipLaunchKernelGGL((local_band_mfma_kernel<T, 1>), dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv,
-                           lam, Floc, sumN, zloc, Lwork, Loff, status, negflag);
+    // again with shift 0 (its waves return at once when no system was flagged).
+    // nt: window tile-rows (4 or 6)
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv, lam, Floc, sumN, zloc,
+                           Lwork, Loff, status, negflag);
+    };
+    if (nt == 4) {
+        if (mode == 0) go(local_band_mfma_kernel<T, 0, 4>);
+        else go(local_band_mfma_kernel<T, 1, 4>);
+    } else {
+        if (mode == 0) go(local_band_mfma_kernel<T, 0, 6>);
+        else go(local_band_mfma_kernel<T, 1, 6>);
+    }
 }
 
 template <typename T>
@@ -824,8 +892,8 @@ void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC,
                             const double2* sv, const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status, int* negflag) {
     if (blocked) {
-        launch_local_mfma<double>(st, mode, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
-                               negflag);
+        launch_local_mfma<double>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff,
+                               status, negflag);
         return;
     }
     if (mode == 0)   // the windowed solver takes its second pass inside the kernel
@@ -837,8 +905,8 @@ void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC,
                             const double2* sv, const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status, int* negflag) {
     if (blocked) {
-        launch_local_mfma<float>(st, mode, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
-                               negflag);
+        launch_local_mfma<float>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff,
+                               status, negflag);
         return;
     }
     if (mode == 0)   // the windowed solver takes its second pass inside the kernel

@@ -172,7 +172,11 @@ CONFIGS = {
     "t128": dict(Lx=1.0, Ly=1.0, Nx=128, Ny=128, coarse=16, L=2, k=8, guard=0, seed_block=None,
                  desc="h=1/128 (the 16129-dof mesh of the first Table 1 column), 8x8 subdomains"),
     "w56": dict(Lx=1.0, Ly=1.0, Nx=144, Ny=144, coarse=48, L=4, k=2, guard=0, seed_block=None,
-                desc="3x3 wide subdomains: local half-bandwidth above the blocked solver's limit"),
+                desc="3x3 wide subdomains: local half-bandwidths 52-56"),
+    "w78": dict(Lx=1.0, Ly=1.0, Nx=216, Ny=216, coarse=72, L=3, k=2, guard=0, seed_block=None,
+                desc="3x3 wide subdomains: local half-bandwidths 75-78"),
+    "w84": dict(Lx=1.0, Ly=1.0, Nx=240, Ny=240, coarse=80, L=2, k=2, guard=0, seed_block=None,
+                desc="3x3 wide subdomains: local half-bandwidths 82-84"),
     "r96": dict(Lx=1.0, Ly=1.01, Nx=96, Ny=97, coarse=12, L=2, k=6, guard=1, seed_block=None,
                 desc="rectangle [0,1]x[0,1.01], uneven last coarse row"),
 }

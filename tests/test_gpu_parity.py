@@ -59,7 +59,7 @@ def test_coarse_eigenvalues(B, ctx, name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96", "w56"])
+@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96", "w56", "w78", "w84"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_preconditioner_parity(B, ctx, name, prec):
     _case(f"preconditioner {name} {prec}")
@@ -79,8 +79,16 @@ def test_preconditioner_parity(B, ctx, name, prec):
     Zo = o.precondition(F, lam, cs, ls, s)
     err = np.abs(Zg - Zo).max() / np.abs(Zo).max()
     print(f"  max rel err {err:.3e}", flush=True)
-    assert err < (1e-12 if prec == "fp64" else 2e-5)
+    assert err < (1e-12 if prec == "fp64" else _fp32_tolerance(prob))
     prob.close()
+
+
+def _fp32_tolerance(prob):
+    """Relative tolerance of the preconditioner with FP32 local solves: 2e-5 up to local
+    half-bandwidth 48, growing as the square of the bandwidth beyond (the condition
+    number of K_l - lambda M_l on a subdomain w cells wide grows as w^2)."""
+    _, bw = prob.local_sizes()
+    return 2e-5 * max(1.0, (int(bw.max()) / 48.0) ** 2)
 
 
 def _local_minima(mesh, dd):
@@ -98,13 +106,14 @@ def _local_minima(mesh, dd):
     return np.array(mus), ls
 
 
-@pytest.mark.parametrize("name", ["c1", "w56", "served0"])
+@pytest.mark.parametrize("name", ["c1", "w56", "w84", "served0"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_preconditioner_indefinite_local(B, ctx, name, prec):
     """Shifts above some subdomains' lowest Dirichlet eigenvalue: there the local matrix
     K_l - lambda_i M_l is indefinite and the local solve takes shift 0 (the oracle's
-    reading of the paper's positive-definiteness premise); both the blocked MFMA solver
-    (c1, served0) and the windowed solver (w56) take that path."""
+    reading of the paper's positive-definiteness premise); the blocked MFMA solver with
+    its 64-row (c1, served0) and 96-row (w56) windows and the windowed solver (w84)
+    take that path."""
     _case(f"preconditioner indefinite {name} {prec}")
     if name == "served0":
         r = w.serving_requests(count=1, h_choices=(64,))[0]
@@ -137,7 +146,7 @@ def test_preconditioner_indefinite_local(B, ctx, name, prec):
     Zo = o.precondition(F, lam, cs, ls, s)
     err = np.abs(Zg - Zo).max() / np.abs(Zo).max()
     print(f"  indefinite local systems {n_indef}, max rel err {err:.3e}", flush=True)
-    assert err < (1e-12 if prec == "fp64" else 2e-5)
+    assert err < (1e-12 if prec == "fp64" else _fp32_tolerance(prob))
     prob.close()
 
 
