@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true", help="skip the untimed per-phase profile solve")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the served mix: the first N of the 256-request workload "
                          "(0: skip the serving measurement)")
     ap.add_argument("--serve-only", action="store_true", help="only the served-mix measurement")
