@@ -1,6 +1,8 @@
 // Block linear algebra on n x c row-major FP64 blocks: fused SpMM with K and M,
 // residual block, Gram products, tall-times-small products.  All reductions are
 // two-pass with a fixed summation order, so results do not depend on timing.
+#include <cstdint>
+
 #include "common.h"
 
 namespace bpjd {
@@ -18,29 +20,131 @@ __global__ void spmm_km_kernel(int n, const int* __restrict__ rowptr, const int*
                                const double2* __restrict__ km, const double* __restrict__ X, int ldx,
                                int ncols, int cshift, double* __restrict__ KX, int ldk,
                                double* __restrict__ MX, int ldm) {
+    // a row is handled by a group of G = 2^cshift lanes (one per column of X).  Its
+    // entries are taken 8 at a time (G at a time when G < 8): lane g of the group loads
+    // entry g, the group shares them by lane shuffles, and then every lane loads the 8
+    // X entries of its column, so each entry's index and value pair is fetched once per
+    // row and not once per column.  Sums keep the entry order.
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = t >> cshift;
-    const int c = t & ((1 << cshift) - 1);
-    if (r >= n || c >= ncols) return;
-    double ak = 0.0, am = 0.0;
-    for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
-        const double2 v = km[p];
-        const double x = X[(long long)col[p] * ldx + c];
-        ak = fma(v.x, x, ak);
-        am = fma(v.y, x, am);
+    const int G = 1 << cshift;
+    const int c = t & (G - 1);
+    const int gbase = (threadIdx.x & 63) & ~(G - 1);   // first lane of the row's group (G <= 64)
+    const int CH = G < 8 ? G : 8;
+    const int cc = min(c, ncols - 1);                  // lanes past the last column load in bounds
+    int p0 = 0, p1 = 0;
+    if (r < n) {
+        p0 = rowptr[r];
+        p1 = rowptr[r + 1];
     }
-    KX[(long long)r * ldk + c] = ak;
-    MX[(long long)r * ldm + c] = am;
+    double ak = 0.0, am = 0.0;
+    for (int pb = p0; pb < p1; pb += CH) {             // same trip count for the whole group
+        const int pg = min(pb + min(c, CH - 1), p1 - 1);
+        const int cg = col[pg];
+        const double2 vg = km[pg];
+        int cj[8];
+        double vk[8], vm[8], xj[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int src = gbase + (j < CH ? j : 0);
+            cj[j] = __shfl(cg, src, 64);
+            vk[j] = __shfl(vg.x, src, 64);
+            vm[j] = __shfl(vg.y, src, 64);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xj[j] = X[(long long)cj[j] * ldx + cc];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j < CH && pb + j < p1) {
+                ak = fma(vk[j], xj[j], ak);
+                am = fma(vm[j], xj[j], am);
+            }
+        }
+    }
+    if (r < n && c < ncols) {
+        KX[(long long)r * ldk + c] = ak;
+        MX[(long long)r * ldm + c] = am;
+    }
+}
+
+// The same product for an even number of columns: a lane owns two adjacent columns
+// (16-byte loads and stores), a row a group of G = 2^cshift lanes.  The row's entries
+// are taken 8 at a time (2G when 2G < 8); lane g of the group loads entries g and g + G,
+// the group shares them by lane shuffles.
+__global__ void spmm_km_pair_kernel(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                    const double2* __restrict__ km, const double* __restrict__ X, int ldx,
+                                    int ncols, int cshift, double* __restrict__ KX, int ldk,
+                                    double* __restrict__ MX, int ldm) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = t >> cshift;
+    const int G = 1 << cshift;
+    const int c = t & (G - 1);                         // columns 2c, 2c + 1
+    const int gbase = (threadIdx.x & 63) & ~(G - 1);
+    const int CH = 2 * G < 8 ? 2 * G : 8;
+    const int cc = min(2 * c, ncols - 2);              // lanes past the last pair load in bounds
+    int p0 = 0, p1 = 0;
+    if (r < n) {
+        p0 = rowptr[r];
+        p1 = rowptr[r + 1];
+    }
+    double ak0 = 0.0, ak1 = 0.0, am0 = 0.0, am1 = 0.0;
+    for (int pb = p0; pb < p1; pb += CH) {             // same trip count for the whole group
+        const int pa = min(pb + min(c, CH - 1), p1 - 1);
+        const int pc = min(pb + min(c + G, CH - 1), p1 - 1);
+        const int ca = col[pa], cb = col[pc];
+        const double2 va = km[pa], vb = km[pc];
+        int cj[8];
+        double vk[8], vm[8];
+        double2 xj[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int jj = j < CH ? j : 0;
+            if (jj < G) {                              // uniform: G is the same for every lane
+                cj[j] = __shfl(ca, gbase + jj, 64);
+                vk[j] = __shfl(va.x, gbase + jj, 64);
+                vm[j] = __shfl(va.y, gbase + jj, 64);
+            } else {
+                cj[j] = __shfl(cb, gbase + jj - G, 64);
+                vk[j] = __shfl(vb.x, gbase + jj - G, 64);
+                vm[j] = __shfl(vb.y, gbase + jj - G, 64);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xj[j] = *reinterpret_cast<const double2*>(X + (long long)cj[j] * ldx + cc);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j < CH && pb + j < p1) {
+                ak0 = fma(vk[j], xj[j].x, ak0);
+                ak1 = fma(vk[j], xj[j].y, ak1);
+                am0 = fma(vm[j], xj[j].x, am0);
+                am1 = fma(vm[j], xj[j].y, am1);
+            }
+        }
+    }
+    if (r < n && 2 * c < ncols) {
+        *reinterpret_cast<double2*>(KX + (long long)r * ldk + 2 * c) = make_double2(ak0, ak1);
+        *reinterpret_cast<double2*>(MX + (long long)r * ldm + 2 * c) = make_double2(am0, am1);
+    }
 }
 
 void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, const double2* km,
                     const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm) {
-    const int cp = pow2_at_least(ncols);
+    // column pairs need even column counts and leading dimensions and 16-byte aligned
+    // blocks (every block of the library is a hipMalloc base plus multiples of 16 bytes)
+    const bool pair = (ncols % 2 == 0) && (ldx % 2 == 0) && (ldk % 2 == 0) && (ldm % 2 == 0) &&
+                      ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(KX) |
+                        reinterpret_cast<uintptr_t>(MX)) % 16 == 0);
+    const int lanes = pair ? ncols / 2 : ncols;
+    const int cp = pow2_at_least(lanes);
     int sh = 0;
     while ((1 << sh) < cp) ++sh;
     const long long work = (long long)n << sh;
-    hipLaunchKernelGGL(spmm_km_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, n, rowptr, col, km, X, ldx,
-                       ncols, sh, KX, ldk, MX, ldm);
+    if (pair)
+        hipLaunchKernelGGL(spmm_km_pair_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, n, rowptr, col, km, X,
+                           ldx, ncols, sh, KX, ldk, MX, ldm);
+    else
+        hipLaunchKernelGGL(spmm_km_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, n, rowptr, col, km, X, ldx,
+                           ncols, sh, KX, ldk, MX, ldm);
 }
 
 // ---------------------------------------------------------------------------
