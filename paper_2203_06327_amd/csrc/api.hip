@@ -502,6 +502,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     p->Mmap = U.Mmap;
     p->n_init = opts->n_init;
     p->nnzKH = (int)khcol.size();
+    for (int a2 = 0; a2 < nH; ++a2) p->maxPT = std::max(p->maxPT, PTptr[a2 + 1] - PTptr[a2]);
     p->bwH = 0;                                    // lower bandwidth of the coarse matrices
     for (int a = 0; a < nH; ++a)
         for (int q = khptr[a]; q < khptr[a + 1]; ++q) p->bwH = std::max(p->bwH, a - khcol[q]);
@@ -681,7 +682,7 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
     const int s = p->s;
     PH_BEGIN(T, BPJD_PHASE_COARSE);
     launch_coarse_apply(st, p->n, p->nH, s, p->PTptr, p->PTcol, p->PTval, F, s, p->Y, p->YT, p->lamH, p->lam, p->G,
-                        p->Cw, p->Zhat);
+                        p->Cw, p->Zhat, p->maxPT, p->partial, (long long)p->npart * 4096);
     PH_END(T);
     const bool mixed = p->opts.precision == BPJD_PREC_MIXED;
     PH_BEGIN(T, BPJD_PHASE_GATHER);

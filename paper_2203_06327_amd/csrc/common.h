@@ -93,7 +93,8 @@ void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int
 void launch_coarse_apply(hipStream_t st, int n, int nH, int s,
                          const int* PTptr, const int* PTcol, const double* PTval,
                          const double* F, int ldf, const double* Y, const double* YT, const double* lamH,
-                         const double* lam, double* G, double* Cw, double* Zhat);
+                         const double* lam, double* G, double* Cw, double* Zhat, int maxPT, double* part,
+                         long long part_cap);
 void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, double* Floc);
 void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc);
 // Batched local LDL^T factor + solve, one wavefront per (subdomain, shift).  Shift
@@ -219,6 +220,7 @@ struct bpjd_problem {
     double* hbuf = nullptr;            // pinned host mirror for per-iteration scalars
     int npart = 0;
     int nnzKH = 0;
+    int maxPT = 0;                     // largest coarse basis support (entries of a row of P^T)
     int bwH = 0;                       // lower bandwidth of K_H, M_H (and of L)
     bool trace = false;
     std::vector<int> h_nl, h_bw;     // host copies of subdomain sizes / half-bandwidths

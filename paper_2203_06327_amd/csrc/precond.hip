@@ -192,11 +192,75 @@ __global__ __launch_bounds__(64) void coarse_back_kernel(int nH, int s, const do
     }
 }
 
+// G = P^T F in two deterministic stages for wide coarse supports: workgroup (k, a) sums
+// the k-th chunk of `chunk` support entries of coarse dof a for every column (wave sums,
+// then the four waves in order) into part[a][k][i]; then each G[a][i] adds its chunks
+// in order.  Chunks past the end of a support contribute zeros.
+__global__ __launch_bounds__(256) void restrict_partial_kernel(int s, int nchunk, int chunk,
+                                                               const int* __restrict__ PTptr,
+                                                               const int* __restrict__ PTcol,
+                                                               const double* __restrict__ PTval,
+                                                               const double* __restrict__ F, int ldf,
+                                                               double* __restrict__ part) {
+    __shared__ double red[4][BPJD_MAX_BLOCK];
+    const int k = blockIdx.x, a = blockIdx.y;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int q0 = PTptr[a] + k * chunk;
+    const int q1 = min(q0 + chunk, PTptr[a + 1]);
+    double acc[BPJD_MAX_BLOCK];
+#pragma unroll
+    for (int i = 0; i < BPJD_MAX_BLOCK; ++i) acc[i] = 0.0;
+    for (int q = q0 + t; q < q1; q += 256) {
+        const double w = PTval[q];
+        const double* frow = F + (long long)PTcol[q] * ldf;
+#pragma unroll
+        for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+            if (i < s) acc[i] = fma(w, frow[i], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < BPJD_MAX_BLOCK; ++i) {
+        if (i >= s) break;
+        double v = acc[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wv][i] = v;
+    }
+    __syncthreads();
+    if (t < s) part[((long long)a * nchunk + k) * s + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+__global__ void restrict_sum_kernel(int nH, int s, int nchunk, const double* __restrict__ part,
+                                    double* __restrict__ G) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nH * s) return;
+    const int a = t / s, i = t - a * s;
+    double acc = 0.0;
+    for (int k = 0; k < nchunk; ++k) acc += part[((long long)a * nchunk + k) * s + i];
+    G[t] = acc;
+}
+
 void launch_coarse_apply(hipStream_t st, int n, int nH, int s, const int* PTptr, const int* PTcol,
                          const double* PTval, const double* F, int ldf, const double* Y, const double* YT,
-                         const double* lamH, const double* lam, double* G, double* Cw, double* Zhat) {
+                         const double* lamH, const double* lam, double* G, double* Cw, double* Zhat,
+                         int maxPT, double* part, long long part_cap) {
     (void)n;
-    hipLaunchKernelGGL(restrict_kernel, dim3(nH), dim3(256), 0, st, nH, s, PTptr, PTcol, PTval, F, ldf, G);
+    // coarse supports of more than 4096 entries: chunked two-stage restriction (enough
+    // workgroups to fill the device); otherwise one workgroup per coarse dof
+    bool two_stage = false;
+    if (maxPT > 4096 && s <= BPJD_MAX_BLOCK) {
+        long long chunk = 1024;
+        while (chunk < maxPT && (long long)nH * s * ((maxPT + chunk - 1) / chunk) > part_cap) chunk *= 2;
+        const long long nchunk = (maxPT + chunk - 1) / chunk;
+        if ((long long)nH * s * nchunk <= part_cap) {
+            two_stage = true;
+            hipLaunchKernelGGL(restrict_partial_kernel, dim3((int)nchunk, nH), dim3(256), 0, st, s, (int)nchunk,
+                               (int)chunk, PTptr, PTcol, PTval, F, ldf, part);
+            hipLaunchKernelGGL(restrict_sum_kernel, dim3((nH * s + 255) / 256), dim3(256), 0, st, nH, s, (int)nchunk,
+                               part, G);
+        }
+    }
+    if (!two_stage)
+        hipLaunchKernelGGL(restrict_kernel, dim3(nH), dim3(256), 0, st, nH, s, PTptr, PTcol, PTval, F, ldf, G);
     hipLaunchKernelGGL(coarse_coef_kernel, dim3(nH), dim3(64), 0, st, nH, s, YT, G, lamH, lam, Cw);
     hipLaunchKernelGGL(coarse_back_kernel, dim3(nH), dim3(64), 0, st, nH, s, Y, Cw, Zhat);
 }

@@ -177,6 +177,8 @@ CONFIGS = {
                 desc="3x3 wide subdomains: local half-bandwidths 75-78"),
     "w84": dict(Lx=1.0, Ly=1.0, Nx=240, Ny=240, coarse=80, L=2, k=2, guard=0, seed_block=None,
                 desc="3x3 wide subdomains: local half-bandwidths 82-84"),
+    "h64": dict(Lx=1.0, Ly=1.0, Nx=192, Ny=192, coarse=64, L=1, k=3, guard=0, seed_block=None,
+                desc="3x3 coarse cells of 64x64 fine cells: coarse supports above 4096 dofs"),
     "r96": dict(Lx=1.0, Ly=1.01, Nx=96, Ny=97, coarse=12, L=2, k=6, guard=1, seed_block=None,
                 desc="rectangle [0,1]x[0,1.01], uneven last coarse row"),
 }

@@ -59,7 +59,7 @@ def test_coarse_eigenvalues(B, ctx, name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96", "w56", "w78", "w84"])
+@pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96", "w56", "w78", "w84", "h64"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_preconditioner_parity(B, ctx, name, prec):
     _case(f"preconditioner {name} {prec}")
