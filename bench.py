@@ -97,10 +97,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "local_band_mfma_c2_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_06327_amd", "csrc", "precond.hip")
 
 
+KERNEL_REGION = ("// Local solves, blocked:", "// Local extraction (numeric setup)")
+
+
 def source_hash(path: str) -> str:
+    """First 16 hex digits of the sha256 of the blocked local solver's source: the text
+    of precond.hip from the comment that opens the blocked solver (its helpers, tile
+    traits and kernel) up to the next section."""
     import hashlib
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    text = open(path, encoding="utf-8").read()
+    a = text.index(KERNEL_REGION[0])
+    b = text.index(KERNEL_REGION[1], a)
+    return hashlib.sha256(text[a:b].encode("utf-8")).hexdigest()[:16]
 
 
 def counter_traffic(config: str):

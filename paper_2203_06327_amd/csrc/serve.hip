@@ -8,10 +8,13 @@
 // kernels of different requests overlap on the device and the host-side stop test
 // of one request never stalls another.
 //
-// Three host threads:
-//   admit  - plans the oldest queued request on the host (validation, subdomains,
-//            band layout, footprint), waits until a slot is free and the footprint
-//            fits the budget, then allocates, uploads and enqueues its setup;
+// Host threads:
+//   plan   - (kPlanners of them) plan queued requests on the host, in submission
+//            order, a few ahead of admission: validation, subdomains, band layout,
+//            device footprint;
+//   admit  - takes the oldest queued request once it is planned, waits until a slot
+//            is free and its footprint fits the budget, then allocates, uploads and
+//            enqueues its setup;
 //   step   - polls the read-back event of every running solve and enqueues its
 //            next stage as soon as that event has completed;
 //   reap   - copies finished results to host memory, frees the device memory and
@@ -53,6 +56,10 @@ struct Request {
     enum State { QUEUED, RUNNING, DONE } state = QUEUED;
     int rc = BPJD_OK;
     std::string err;
+    bool planned = false;                    // set by a planner
+    int plan_rc = BPJD_OK;
+    std::string plan_err;
+    bpjd_problem* planned_p = nullptr;       // planned, not yet materialised
     bpjd_problem* p = nullptr;
     bpjd::SolveRun* run = nullptr;
     int slot = -1;
@@ -78,6 +85,9 @@ void copy_csr(const bpjd_csr& in, std::vector<int32_t>& ptr, std::vector<int32_t
 
 }  // namespace
 
+constexpr int kPlanners = 3;                 // host planning threads
+constexpr int kPlanAhead = 4;                // planned requests waiting for admission, at most
+
 struct bpjd_server {
     bpjd_ctx* ctx = nullptr;                 // caller's context: device
     size_t budget = 0;
@@ -86,10 +96,12 @@ struct bpjd_server {
     std::vector<char> slot_busy;
 
     std::mutex mu;
-    std::condition_variable cv_admit, cv_step, cv_reap;
+    std::condition_variable cv_admit, cv_step, cv_reap, cv_plan;
     bool stopping = false;
     uint64_t next_id = 1;
     std::deque<Request*> queued;
+    std::deque<Request*> to_plan;            // submitted, not yet taken by a planner
+    int plan_pending = 0;                    // being planned, or planned and not admitted
     std::vector<Request*> running;           // owned by the step thread while RUNNING
     std::deque<Request*> finished;           // handed from step to reap
     std::unordered_map<uint64_t, Request*> all;
@@ -97,6 +109,7 @@ struct bpjd_server {
     bpjd_server_info info{};
 
     std::thread admit_thr, step_thr, reap_thr;
+    std::vector<std::thread> plan_thr;
 };
 
 namespace {
@@ -112,17 +125,20 @@ void finish_request(bpjd_server* s, Request* r, int rc, const std::string& err) 
     if (rc < 0 && rc != BPJD_ERR_NOCONV) s->info.failed++;
 }
 
-void admit_loop(bpjd_server* s) {
+void plan_loop(bpjd_server* s) {
     (void)hipSetDevice(s->ctx->device);
     for (;;) {
         Request* r = nullptr;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_admit.wait(lk, [&] { return s->stopping || !s->queued.empty(); });
+            s->cv_plan.wait(lk, [&] {
+                return s->stopping || (!s->to_plan.empty() && s->plan_pending < kPlanAhead);
+            });
             if (s->stopping) return;
-            r = s->queued.front();
+            r = s->to_plan.front();
+            s->to_plan.pop_front();
+            s->plan_pending++;
         }
-        // host planning of the oldest request, outside the lock
         bpjd_problem* p = nullptr;
         int rc = bpjd::plan_problem(s->ctx, &r->K, &r->M, r->use_geom ? nullptr : &r->dd,
                                     r->use_geom ? &r->geom : nullptr, &r->opts, &p);
@@ -132,13 +148,46 @@ void admit_loop(bpjd_server* s) {
             err = "request needs " + std::to_string(p->footprint) + " device bytes, budget is " +
                   std::to_string(s->budget);
         }
+        if (rc < 0 && p) {
+            bpjd_problem_destroy(p);
+            p = nullptr;
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            r->planned_p = p;
+            r->plan_rc = rc;
+            r->plan_err = err;
+            r->planned = true;
+        }
+        s->cv_admit.notify_all();
+    }
+}
+
+void admit_loop(bpjd_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    for (;;) {
+        Request* r = nullptr;
+        bpjd_problem* p = nullptr;
+        int rc = BPJD_OK;
+        std::string err;
+        {
+            // the oldest queued request, once a planner has finished with it
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_admit.wait(lk, [&] { return s->stopping || (!s->queued.empty() && s->queued.front()->planned); });
+            if (s->stopping) return;
+            r = s->queued.front();
+            p = r->planned_p;
+            rc = r->plan_rc;
+            err = r->plan_err;
+        }
         if (rc < 0) {
-            if (p) bpjd_problem_destroy(p);
             std::lock_guard<std::mutex> lk(s->mu);
             s->queued.pop_front();
+            s->plan_pending--;
             finish_request(s, r, rc, err);
             r->stats.queue_ms = ms_between(r->t_submit, r->t_admit);
             r->stats.latency_ms = ms_between(r->t_submit, r->t_done);
+            s->cv_plan.notify_one();
             continue;
         }
         // wait for a free slot and room in the budget
@@ -152,16 +201,16 @@ void admit_loop(bpjd_server* s) {
                     if (!s->slot_busy[q]) return true;
                 return false;
             });
-            if (s->stopping) {
-                bpjd_problem_destroy(p);
-                return;
-            }
+            if (s->stopping) return;        // the request (and its plan) is freed by destroy
             for (int q = 0; q < s->max_slots && slot < 0; ++q)
                 if (!s->slot_busy[q]) slot = q;
             s->slot_busy[slot] = 1;
             s->in_use += p->footprint;
             s->info.peak_bytes = std::max<uint64_t>(s->info.peak_bytes, s->in_use);
             s->queued.pop_front();
+            s->plan_pending--;
+            r->planned_p = nullptr;
+            s->cv_plan.notify_one();
             r->state = Request::RUNNING;
             r->t_admit = Clock::now();
         }
@@ -283,6 +332,7 @@ int bpjd_server_create(bpjd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots
     }
     s->info.budget_bytes = s->budget;
     s->info.max_slots = max_slots;
+    for (int q = 0; q < kPlanners; ++q) s->plan_thr.emplace_back(plan_loop, s);
     s->admit_thr = std::thread(admit_loop, s);
     s->step_thr = std::thread(step_loop, s);
     s->reap_thr = std::thread(reap_loop, s);
@@ -344,9 +394,10 @@ int bpjd_server_submit(bpjd_server* s, const bpjd_csr* K, const bpjd_csr* M, con
     r->id = s->next_id++;
     s->all[r->id] = r;
     s->queued.push_back(r);
+    s->to_plan.push_back(r);
     s->info.submitted++;
     *req_id = r->id;
-    s->cv_admit.notify_one();
+    s->cv_plan.notify_one();
     return BPJD_OK;
 }
 
@@ -389,6 +440,8 @@ void bpjd_server_destroy(bpjd_server* s) {
     s->cv_admit.notify_all();
     s->cv_step.notify_all();
     s->cv_reap.notify_all();
+    s->cv_plan.notify_all();
+    for (auto& t : s->plan_thr) t.join();
     s->admit_thr.join();
     s->step_thr.join();
     s->reap_thr.join();
@@ -398,6 +451,7 @@ void bpjd_server_destroy(bpjd_server* s) {
         Request* r = kv.second;
         if (r->run) bpjd::run_destroy(r->run);
         if (r->p) bpjd_problem_destroy(r->p);
+        if (r->planned_p) bpjd_problem_destroy(r->planned_p);
         delete r;
     }
     for (auto& c : s->slot_ctx) (void)hipStreamDestroy(c.stream);
