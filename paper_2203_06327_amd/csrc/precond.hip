@@ -687,7 +687,11 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         place(I, 16 * I, 0);
     }
     T y = (lane < nl) ? f[lane] : T(0);
-    T y2 = (TWO && lane < R - 64 && 64 + lane < nl) ? f[64 + lane] : T(0);
+    T y2 = T(0);
+    if constexpr (TWO) {   // an unconditional, clamped load and a select
+        const T fv = f[min(64 + (lane & 31), nl - 1)];
+        y2 = (lane < R - 64 && 64 + lane < nl) ? fv : T(0);
+    }
     int bad = 0, neg = 0;
 
     for (int P = 0; P < npan; ++P) {
@@ -733,11 +737,17 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         // store the factored panel and D^{-1} L^{-1} f of its 16 rows: column c keeps its
         // band part, window rows c .. c + BWS - 1 (lanes write consecutive values)
         T* Lpan = Lp + (long long)P * (16 * BWS) + lane;
-        if (BWS >= R) {                       // full R-row columns: unconditional stores
+        // full R-row columns (FP32 always, BWS == R): unconditional stores; FP32 takes this
+        // path at compile time, which keeps its loop free of a second, branchy store path
+        if (sizeof(T) == 4 || BWS >= R) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) Lpan[c * R] = a[c];
             if constexpr (TWO) {
-                if (lane < R - 64) {
+                if constexpr (sizeof(T) == 4) {
+                    // rows 64.. by every lane: lanes 32.. repeat the values of lanes 0..31
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) Lpan[c * R + 64 + (lane & 31) - lane] = __shfl(a2[c], lane & 31, 64);
+                } else if (lane < R - 64) {
 #pragma unroll
                     for (int c = 0; c < 16; ++c) Lpan[c * R + 64] = a2[c];
                 }
@@ -762,13 +772,30 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
             }
         }
         wave_sync();
-        if (lane < 16 && base + lane < nl) {
+        if constexpr (sizeof(T) == 4) {
             // the pivots of the panel, one per lane: a zero, tiny or non-finite pivot marks
             // the factorisation as failed (checked once per panel, off the elimination chain)
-            const T dl = pan[lane][lane];
-            bad |= !(fabs(dl) > T(1e-30) && fabs(dl) < T(1e30));
-            neg |= dl < T(0);
-            z[base + lane] = y * MT::recip(dl);
+            const T dl = pan[lane & 15][lane & 15];
+            if (lane < 16 && base + lane < nl) {
+                bad |= !(fabs(dl) > T(1e-30) && fabs(dl) < T(1e30));
+                neg |= dl < T(0);
+            }
+            // D^{-1} L^{-1} f of the panel rows, stored by every lane (each group of 16 lanes
+            // writes the same 16 values; rows past the end repeat the last row's value), so
+            // no store sits under a branch and the compiler's memory counters stay exact
+            // across the loop (the prefetched loads then stay in flight)
+            const int zr = min(lane & 15, nl - 1 - base);
+            const T zv = __shfl(y * MT::recip(dl), zr, 64);
+            z[base + zr] = zv;
+        } else {
+            // FP64: the masked form (the shuffles of the form above cost this instance more
+            // registers than they save)
+            if (lane < 16 && base + lane < nl) {
+                const T dl = pan[lane][lane];
+                bad |= !(fabs(dl) > T(1e-30) && fabs(dl) < T(1e30));
+                neg |= dl < T(0);
+                z[base + lane] = y * MT::recip(dl);
+            }
         }
         // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T; k-step k of a lane
         // group lg covers panel column 4 lg + k, so each lane reads 4 adjacent columns
@@ -820,12 +847,15 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     auto load_panel = [&](const int P, T (&dst)[16], T (&dst2)[16], T& zdst) {
         const int Pc = max(P, 0);
         const T* Lpan = Lp + (long long)Pc * (16 * BWS) + lane;
-        if (BWS >= R) {
+        if (sizeof(T) == 4 || BWS >= R) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) dst[c] = Lpan[c * R];
             if constexpr (TWO) {
 #pragma unroll
-                for (int c = 0; c < 16; ++c) dst2[c] = (lane < R - 64) ? Lpan[c * R + 64] : T(0);
+                for (int c = 0; c < 16; ++c) {
+                    const T v = Lpan[c * R + 64 + (lane & 31) - lane];   // in bounds for every lane
+                    dst2[c] = (lane < R - 64) ? v : T(0);
+                }
             }
         } else {
 #pragma unroll
@@ -887,7 +917,13 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
             if (lane < r) val -= lt[r] * zr;
         }
         if (lane < 16) zw = val;
-        if (lane < 16 && base + lane < nl) z[base + lane] = val;
+        if constexpr (sizeof(T) == 4) {
+            const int zr = min(lane & 15, nl - 1 - base);
+            const T zv = __shfl(val, zr, 64);
+            z[base + zr] = zv;            // every lane (duplicates write equal values)
+        } else {
+            if (lane < 16 && base + lane < nl) z[base + lane] = val;
+        }
         wave_sync();
     };
     load_panel(npan - 1, bufA, bufA2, zA);
