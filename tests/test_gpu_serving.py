@@ -136,3 +136,34 @@ def test_server_errors_are_per_request(B, ctx):
         _wait_all(tiny, [rid])
     assert e.value.code == B.ERR_OVER_BUDGET
     tiny.close()
+
+
+def test_served_wide_band_request_equals_alone(B, ctx):
+    """A served h = 1/512 request (local half-bandwidth 68: the 96-row blocked window)
+    next to small ones: the same result alone and in the mix, residuals recomputed on
+    the host, M-orthonormal eigenvectors."""
+    reqs = w.serving_requests(count=8)
+    big = next(r for r in reqs if r["Nx"] == 512)
+    small = [r for r in reqs if r["Nx"] == 64][:3]
+    mix = [big] + small
+    meshes = [w.request_mesh(r) for r in mix]
+    alone = []
+    for r, mesh in zip(mix, meshes):
+        _case(f"serving alone request {r['j']} n={mesh.n} k={r['k']}")
+        prob = B.problem_from_mesh(ctx, mesh, r["L"], k=r["k"], guard=r["guard"])
+        alone.append(prob.solve())
+        prob.close()
+    _case("serving mix with a wide-band request")
+    srv = B.Server(ctx, hbm_budget_bytes=0, max_slots=4)
+    ids = [srv.submit_mesh(mesh, r["L"], k=r["k"], guard=r["guard"]) for r, mesh in zip(mix, meshes)]
+    res = _wait_all(srv, ids)
+    info = srv.info()
+    srv.close()
+    assert info["completed"] == len(mix) and info["failed"] == 0
+    for r, mesh, rid, (lam_a, X_a, st_a) in zip(mix, meshes, ids, alone):
+        lam_s, X_s, st_s = res[rid]
+        np.testing.assert_allclose(lam_s, lam_a, rtol=1e-12, atol=0)
+        assert np.abs(X_s - X_a).max() <= 1e-10 * np.abs(X_a).max()
+        assert st_s["converged"] and st_s["iterations"] == st_a["iterations"]
+        assert _host_residuals(mesh, lam_s, X_s).max() <= 1.5e-8
+        np.testing.assert_allclose(X_s.T @ (mesh.M @ X_s), np.eye(r["k"]), atol=1e-10)
