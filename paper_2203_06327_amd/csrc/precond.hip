@@ -737,9 +737,19 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
         // store the factored panel and D^{-1} L^{-1} f of its 16 rows: column c keeps its
         // band part, window rows c .. c + BWS - 1 (lanes write consecutive values)
         T* Lpan = Lp + (long long)P * (16 * BWS) + lane;
-        // full R-row columns (FP32 always, BWS == R): unconditional stores; FP32 takes this
-        // path at compile time, which keeps its loop free of a second, branchy store path
-        if (sizeof(T) == 4 || BWS >= R) {
+        // three forms, chosen at compile time for FP32 so that its loop holds one of them:
+        // FP32, 64-row window: the band part of each column (rows c .. c + BWS - 1), stored
+        // by every lane (a lane outside the band repeats, by a lane shuffle, the value of
+        // the nearest band row, at that row's address); FP32, 96-row window: full columns
+        // (BWS == R); FP64: full columns or the masked band part
+        if constexpr (sizeof(T) == 4 && !TWO) {
+            T* Lb = Lp + (long long)P * (16 * BWS);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int lc = min(max(lane, c), c + BWS - 1);
+                Lb[c * BWS + (lc - c)] = __shfl(a[c], lc, 64);
+            }
+        } else if (sizeof(T) == 4 || BWS >= R) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) Lpan[c * R] = a[c];
             if constexpr (TWO) {
@@ -847,7 +857,17 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     auto load_panel = [&](const int P, T (&dst)[16], T (&dst2)[16], T& zdst) {
         const int Pc = max(P, 0);
         const T* Lpan = Lp + (long long)Pc * (16 * BWS) + lane;
-        if (sizeof(T) == 4 || BWS >= R) {
+        if constexpr (sizeof(T) == 4 && !TWO) {
+            // band part: every lane loads the nearest band row of its column (in bounds)
+            // and keeps it only where its own row lies in the band
+            const T* Lb = Lp + (long long)Pc * (16 * BWS);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int lc = min(max(lane, c), c + BWS - 1);
+                const T v = Lb[c * BWS + (lc - c)];
+                dst[c] = (lc == lane) ? v : T(0);
+            }
+        } else if (sizeof(T) == 4 || BWS >= R) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) dst[c] = Lpan[c * R];
             if constexpr (TWO) {
