@@ -125,6 +125,12 @@ typedef struct {
     const double* X_init;       /* host, n x n_init row-major, or NULL */
     int32_t profile;            /* 0: off; 1: time every phase with HIP events (bpjd_stats.phase_ms);
                                    2: time only the local-solve phase (two events per iteration) */
+    int32_t graphs;             /* 1 (default): each outer iteration is captured once per problem as a
+                                   HIP graph and replayed; 0: kernels are launched one by one.
+                                   Graphs are not used while phases are timed, nor for served
+                                   requests.  A capture needs the context's stream to be a
+                                   created (non-null) stream with no device-wide synchronisation
+                                   (another thread's hipFree, hipDeviceSynchronize) meanwhile. */
 } bpjd_opts;
 
 /* phases timed when bpjd_opts.profile = 1 (profile = 2: BPJD_PHASE_LOCAL only) */

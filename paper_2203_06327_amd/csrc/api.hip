@@ -852,17 +852,63 @@ void run_destroy(SolveRun* r) { delete r; }
 
 // residual block F = M X Lambda - K X and its column norms, then one read-back of the
 // column norms, shifts and status word into the pinned mirror, then the event
-static int enqueue_residual(SolveRun* r) {
+static int enqueue_residual_work(SolveRun* r, int a) {
     bpjd_problem* p = r->p;
     hipStream_t st = p->ctx->stream;
-    const int n = p->n, s = p->s, a = r->cur;
+    const int n = p->n, s = p->s;
     PH_BEGIN(r->T, BPJD_PHASE_RESIDUAL);
     launch_residual(st, n, s, p->KW[a], s, p->MW[a], s, p->lam, p->F, s, p->partial, p->npart, p->colsq,
                     p->colsq + 128, p->status);
     PH_END(r->T);
     BPJD_HIP(hipMemcpyAsync(p->hbuf, p->colsq, sizeof(double) * 193, hipMemcpyDeviceToHost, st));
-    BPJD_HIP(hipEventRecord(r->erb, st));
     return BPJD_OK;
+}
+
+static int enqueue_residual(SolveRun* r) {
+    BPJD_TRY(enqueue_residual_work(r, r->cur));
+    BPJD_HIP(hipEventRecord(r->erb, r->p->ctx->stream));
+    return BPJD_OK;
+}
+
+// One outer iteration after the stop test (Steps 2 and 3, then the next residual and
+// its read-back) on buffers a -> 1 - a with np columns of P in W.
+static void enqueue_iteration(SolveRun* r, int a, int np) {
+    bpjd_problem* p = r->p;
+    const int s = p->s;
+    const bool uu = p->opts.subspace == BPJD_SUBSPACE_UU;
+    const int ct = s + np;
+    apply_precond(p, p->F, blkp(p, p->W[a], ct), s, r->T);
+    orthonormalize_T(p, a, ct, r->T);
+    rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, r->T);
+}
+
+// The same iteration as a HIP graph: captured from the problem's stream the first time
+// a (buffer, P columns) combination occurs, then replayed; its kernel arguments are the
+// problem's fixed buffers and sizes.  Returns false when capture is not available (the
+// caller then launches the kernels directly and stops trying for this problem).
+static bool launch_iteration_graph(SolveRun* r, int a, int np) {
+    bpjd_problem* p = r->p;
+    hipStream_t st = p->ctx->stream;
+    hipGraphExec_t& ge = p->graph_exec[a][np > 0 ? 1 : 0];
+    if (!ge) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+        enqueue_iteration(r, a, np);
+        const int rc = enqueue_residual_work(r, 1 - a);
+        if (hipStreamEndCapture(st, &g) != hipSuccess || rc < 0 || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return false;   // nothing was enqueued: the caller launches the iteration directly
+        }
+        const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            ge = nullptr;
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    return hipGraphLaunch(ge, st) == hipSuccess;
 }
 
 int run_begin(SolveRun* r) {
@@ -954,10 +1000,25 @@ static int advance_iter(SolveRun* r) {
     // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
     const int a = r->cur;
     const int ct = s + r->np;
-    apply_precond(p, p->F, blkp(p, p->W[a], ct), s, r->T);
-    // Step 3: Rayleigh-Ritz on W = [X | P | T]
-    orthonormalize_T(p, a, ct, r->T);
-    rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, r->T);
+    // Step 3: Rayleigh-Ritz on W = [X | P | T]; then the next residual and its read-back.
+    // Replayed as a HIP graph unless phases are timed, the iteration is traced, or the
+    // caller turned graphs off.
+    const bool graph = p->opts.graphs && !r->T && !p->trace && !p->graph_failed;
+    if (graph && launch_iteration_graph(r, a, r->np)) {
+        r->cur = 1 - a;
+        r->np = uu ? s : 0;
+        r->iters = ++r->it;
+        BPJD_HIP(hipEventRecord(r->erb, st));
+        return 0;
+    }
+    if (graph) {
+        p->graph_failed = true;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return fail(BPJD_ERR_HIP, "stream left in capture mode by a failed graph capture");
+        (void)hipGetLastError();
+    }
+    enqueue_iteration(r, a, r->np);
     if (p->trace) {
         int fl[128];
         BPJD_HIP(hipMemcpyAsync(fl, p->dropped[a], sizeof(int) * (ct + s), hipMemcpyDeviceToHost, st));
@@ -1082,6 +1143,7 @@ void bpjd_opts_default(bpjd_opts* o, int32_t k) {
     o->precision = BPJD_PREC_MIXED;
     o->n_init = 0;
     o->X_init = nullptr;
+    o->graphs = 1;
 }
 
 int bpjd_ctx_create(int device, void* hip_stream, bpjd_ctx** out) {
@@ -1204,6 +1266,9 @@ int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M
 void bpjd_problem_destroy(bpjd_problem* p) {
     if (!p) return;
     delete p->plan;
+    for (auto& row : p->graph_exec)
+        for (hipGraphExec_t ge : row)
+            if (ge) (void)hipGraphExecDestroy(ge);
     for (void* d : p->allocations) (void)hipFree(d);
     if (p->hbuf) (void)hipHostFree(p->hbuf);
     delete p;

@@ -227,5 +227,7 @@ struct bpjd_problem {
     bool setup_done = false;
     std::vector<void*> allocations;
     bpjd::HostPlan* plan = nullptr;    // host arrays between planning and materialisation
+    hipGraphExec_t graph_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [buffer][P in W]
+    bool graph_failed = false;         // capture unavailable: launch directly
     size_t footprint = 0;              // device bytes of the problem (allocation granularity included)
 };

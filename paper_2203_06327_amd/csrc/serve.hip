@@ -355,6 +355,10 @@ int bpjd_server_submit(bpjd_server* s, const bpjd_csr* K, const bpjd_csr* M, con
     copy_csr(*K, r->Kptr, r->Kcol, r->Kval, r->K);
     copy_csr(*M, r->Mptr, r->Mcol, r->Mval, r->M);
     r->opts = *opts;
+    // served solves launch their kernels one by one: the admit and reap threads allocate,
+    // upload and free device memory while solves run, and a stream capture must not
+    // overlap such device-wide synchronisation
+    r->opts.graphs = 0;
     if (opts->n_init > 0 && opts->X_init) {
         r->X_init.assign(opts->X_init, opts->X_init + (size_t)r->n * opts->n_init);
         r->opts.X_init = r->X_init.data();

@@ -280,3 +280,27 @@ def test_solve_c3_full_size(B, ctx):
     assert rel.max() < 1e-10
     assert rho.max() <= 1.5e-8
     np.testing.assert_allclose(X.T @ MX, np.eye(k), atol=1e-10)
+
+
+@pytest.mark.parametrize("name,prec", [("c1", "mixed"), ("t64", "fp64"), ("r96", "mixed")])
+def test_graph_replay_equals_direct_launches(B, ctx, name, prec):
+    """Outer iterations replayed as captured HIP graphs give the same iterates as the
+    same kernels launched one by one: three solves with graphs on one problem (capture,
+    then replays across solves, with host synchronisation between iterations) against
+    one solve without, compared bit for bit."""
+    _case(f"graph replay {name} {prec}")
+    mesh, cfg = w.config_mesh(name)
+    s = cfg["k"] + cfg["guard"]
+    X0 = None if cfg["seed_block"] is None else w.seeded_block(mesh.n, s, cfg["seed_block"])
+    precision = B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED
+    kw = dict(k=cfg["k"], guard=cfg["guard"], precision=precision, X_init=X0)
+    direct = B.problem_from_mesh(ctx, mesh, cfg["L"], graphs=False, **kw)
+    lam0, X0d, st0 = direct.solve()
+    direct.close()
+    graphed = B.problem_from_mesh(ctx, mesh, cfg["L"], graphs=True, **kw)
+    for rep in range(3):
+        lam, X, st = graphed.solve()
+        assert st["iterations"] == st0["iterations"]
+        assert np.array_equal(lam, lam0), (rep, np.abs(lam - lam0).max())
+        assert np.array_equal(X, X0d), (rep, np.abs(X - X0d).max())
+    graphed.close()
