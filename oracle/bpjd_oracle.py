@@ -40,7 +40,7 @@ import scipy.sparse.linalg as spla
 __all__ = [
     "DD", "build_dd", "coarse_prolongation", "subdomain_sets", "CoarseSetup", "coarse_setup",
     "LocalSetup", "local_setup", "precondition", "coarse_term", "coarse_term_direct",
-    "local_term", "m_orthonormalize", "rayleigh_ritz", "bpjd", "BPJDResult",
+    "local_term", "spd_solve", "m_orthonormalize", "rayleigh_ritz", "bpjd", "BPJDResult",
     "reference_eigs", "residual_norms", "subspace_gap_b",
 ]
 
@@ -191,23 +191,32 @@ def coarse_term_direct(F: np.ndarray, lam: np.ndarray, cs: CoarseSetup, s: int) 
     return cs.P @ out
 
 
-def positive_definite(A) -> bool:
-    """Whether the symmetric sparse matrix A is positive definite: its Cholesky
-    factorisation (dense up to 400 rows, banded above) runs to the end."""
+def _cholesky(A):
+    """Cholesky factor of the symmetric sparse matrix A (dense up to 400 rows,
+    banded above), or None when A is not positive definite."""
     n = A.shape[0]
     try:
         if n <= 400:
-            np.linalg.cholesky(A.toarray())
-            return True
+            return ("dense", sla.cho_factor(A.toarray(), lower=True))
         C = A.tocoo()
         low = C.row >= C.col
         d = C.row[low] - C.col[low]
         ab = np.zeros((int(d.max()) + 1, n))
         ab[d, C.col[low]] = C.data[low]
-        sla.cholesky_banded(ab, lower=True)
-        return True
+        return ("band", sla.cholesky_banded(ab, lower=True))
     except np.linalg.LinAlgError:
-        return False
+        return None
+
+
+def _cholesky_solve(fac, b: np.ndarray) -> np.ndarray:
+    kind, f = fac
+    return sla.cho_solve(f, b) if kind == "dense" else sla.cho_solve_banded((f, True), b)
+
+
+def positive_definite(A) -> bool:
+    """Whether the symmetric sparse matrix A is positive definite: its Cholesky
+    factorisation (dense up to 400 rows, banded above) runs to the end."""
+    return _cholesky(A) is not None
 
 
 def local_shift(Kl, Ml, lam_i: float) -> float:
@@ -219,19 +228,29 @@ def local_shift(Kl, Ml, lam_i: float) -> float:
     return lam_i if positive_definite((Kl - lam_i * Ml).tocsc()) else 0.0
 
 
+def spd_solve(A, b: np.ndarray) -> np.ndarray:
+    """Solve A z = b for a symmetric positive definite sparse A by Cholesky.  Its
+    rounding error depends only on the diagonally scaled matrix, so dofs of very
+    different sizes (the derivative dofs of the fourth-order elements carry powers
+    of h) keep full accuracy."""
+    fac = _cholesky(A)
+    if fac is None:
+        raise np.linalg.LinAlgError("matrix is not positive definite")
+    return _cholesky_solve(fac, b)
+
+
 def local_term(F: np.ndarray, lam: np.ndarray, ls: LocalSetup) -> np.ndarray:
     """sum_l R_l^T (K_l - sigma_{l,i} M_l)^{-1} R_l F_i (unweighted sum), with
     sigma_{l,i} = local_shift(K_l, M_l, lambda_i): lambda_i on every subdomain
-    where the paper's premise holds."""
+    where the paper's premise holds.  The Cholesky factorisation that decides the
+    shift is the one that solves (K_l alone is positive definite)."""
     Z = np.zeros_like(F)
     for S, Kl, Ml in zip(ls.subs, ls.K_loc, ls.M_loc):
         for i in range(F.shape[1]):
-            A = (Kl - local_shift(Kl, Ml, lam[i]) * Ml).tocsc()
-            if A.shape[0] <= 400:
-                z = np.linalg.solve(A.toarray(), F[S, i])
-            else:
-                z = spla.splu(A).solve(F[S, i])
-            Z[S, i] += z
+            fac = _cholesky((Kl - lam[i] * Ml).tocsc())
+            if fac is None:                       # local_shift gives 0 here
+                fac = _cholesky(Kl.tocsc())
+            Z[S, i] += _cholesky_solve(fac, F[S, i])
     return Z
 
 

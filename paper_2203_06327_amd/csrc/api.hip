@@ -424,11 +424,9 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     // the slots of a block of rows one slot per lane
     if (!blocked && (maxBW > 127 || maxE > 64))
         return fail(BPJD_ERR_DD, "local half-bandwidth above 127 or more than 64 lower entries in a local row");
-    // FP64 factors keep only the band of each column (halves the factor traffic that
-    // bounds the backward sweep); FP32 factors keep full 64-row columns, whose stores
-    // and loads need no per-lane masks
-    // stored rows per factor column: the band part (rounded up to 4), except FP32 with the
-    // 96-row window, which keeps full columns
+    // stored rows per factor column: the band part (rounded up to 4; the factor traffic
+    // bounds the backward sweep), except FP32 with the 96-row window, which keeps full
+    // columns
     const int win = 16 * std::max(nt, 4);
     const int bws = (opts->precision == BPJD_PREC_MIXED && nt == 6) ? win : ((std::min(win, maxBW + 1) + 3) / 4) * 4;
     std::vector<long long> Loff(nsub, 0);

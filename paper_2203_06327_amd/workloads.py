@@ -12,6 +12,18 @@ oracle each implement those on their own and both read what is made here.
 Matrices are returned as scipy CSR on the *union* pattern of K and M: the
 hypotenuse couplings of the right triangles are exact zeros in K but not in M,
 so K stores them as explicit zeros.
+
+For the fourth-order case (Section 2.2, the biharmonic problem with clamped
+edges, a(u,v) = int Lap u Lap v) the module also makes the Bogner-Fox-Schmit
+(bicubic Hermite) discretisation of the unit square, which the paper names for
+m = 2.  Its element is not tied to a triangle mesh, so the generic interface
+of the library takes it: the caller hands over the coarse space as a
+prolongation matrix P (the nested coarse BFS space written in fine dofs) and
+the local spaces as dof sets (all dofs of the fine vertices strictly inside
+each enlarged coarse cell, i.e. V^h intersected with H^2_0 of that cell).
+These are the caller's description of V^H and V^(l); the eigensolver's own
+steps (Galerkin products, coarse eigenbasis, local factorisations) are not
+here.
 """
 from __future__ import annotations
 
@@ -24,6 +36,7 @@ import scipy.sparse as sp
 __all__ = [
     "Mesh", "p1_mesh", "coarse_lines", "config_mesh", "CONFIGS",
     "block_coefficient", "seeded_block", "serving_requests",
+    "Plate", "hermite_1d", "bfs_plate", "PLATE_CONFIGS", "config_plate",
 ]
 
 
@@ -217,3 +230,174 @@ def serving_requests(count: int = 256, base_seed: int = 2203, h_choices=(64, 128
 def request_mesh(req: dict) -> Mesh:
     coef = block_coefficient(req["Lx"], req["Ly"], req["coef_values"])
     return p1_mesh(req["Lx"], req["Ly"], req["Nx"], req["Ny"], req["coarse"], coef=coef)
+
+
+# ----------------------------------------------------------------------------
+# Fourth order: Bogner-Fox-Schmit elements on the unit square (m = 2)
+@dataclass
+class Plate:
+    """BFS discretisation of Lap^2 u = lambda u on the unit square (N x N cells).
+
+    Dofs sit on the fine vertices, four per vertex in the order u, u_x, u_y,
+    u_xy; vertices are numbered row by row (x fastest), so a vertex's dofs are
+    consecutive and the dofs of a subdomain keep the row-by-row order.
+    """
+    N: int
+    bc: str                     # "clamped" (u = du/dn = 0) or "simply" (u = 0)
+    K: sp.csr_matrix            # int Lap u Lap v, union pattern with M
+    M: sp.csr_matrix            # int u v
+    vert: np.ndarray            # (n, 2) int: fine vertex (ix, iy) of each dof
+    kind: np.ndarray            # (n,) int: 0 u, 1 u_x, 2 u_y, 3 u_xy
+    P: Optional[sp.csr_matrix] = None       # n x n_H nested coarse space
+    subs: Optional[list] = None             # local dof sets (sorted int32 arrays)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.K.shape[0]
+
+
+def _hermite_shapes(t: np.ndarray, h: float):
+    """Cubic Hermite shape functions on [0, h] at t in [0, 1] (dof order: f(0),
+    f'(0), f(h), f'(h)) with their first and second x-derivatives."""
+    f = np.stack([1 - 3 * t**2 + 2 * t**3, h * (t - 2 * t**2 + t**3), 3 * t**2 - 2 * t**3, h * (t**3 - t**2)])
+    d1 = np.stack([(-6 * t + 6 * t**2) / h, 1 - 4 * t + 3 * t**2, (6 * t - 6 * t**2) / h, 3 * t**2 - 2 * t])
+    d2 = np.stack([(-6 + 12 * t) / h**2, (-4 + 6 * t) / h, (6 - 12 * t) / h**2, (6 * t - 2) / h])
+    return f, d1, d2
+
+
+def _free_1d(N: int, bc: str) -> np.ndarray:
+    """Kept 1-D dofs (2 i: value at node i, 2 i + 1: slope) under the boundary condition."""
+    drop = {0, 2 * N} if bc == "simply" else {0, 1, 2 * N, 2 * N + 1}
+    if bc not in ("simply", "clamped"):
+        raise ValueError("bc must be 'clamped' or 'simply'")
+    return np.array([d for d in range(2 * N + 2) if d not in drop], dtype=np.int64)
+
+
+def hermite_1d(N: int, bc: str = "clamped"):
+    """1-D cubic Hermite matrices on [0, 1] with N cells: (mass, int f'g', int f''g'')
+    restricted to the dofs kept by ``bc``, in node order (value, slope).  Element
+    integrals by 5-point Gauss-Legendre quadrature (exact for these degree-6 products)."""
+    h = 1.0 / N
+    xg, wg = np.polynomial.legendre.leggauss(5)
+    t = 0.5 * (xg + 1.0)
+    w = 0.5 * wg * h
+    f, d1, d2 = _hermite_shapes(t, h)
+    Me = (f * w) @ f.T
+    Ke = (d1 * w) @ d1.T
+    Be = (d2 * w) @ d2.T
+    nd = 2 * N + 2
+    rows, cols, vm, vk, vb = [], [], [], [], []
+    for e in range(N):
+        dofs = np.arange(2 * e, 2 * e + 4)
+        rows.append(np.repeat(dofs, 4))
+        cols.append(np.tile(dofs, 4))
+        vm.append(Me.ravel())
+        vk.append(Ke.ravel())
+        vb.append(Be.ravel())
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    free = _free_1d(N, bc)
+    out = []
+    for v in (vm, vk, vb):
+        A = sp.coo_matrix((np.concatenate(v), (r, c)), shape=(nd, nd)).tocsr()
+        out.append(A[free][:, free].tocsr())
+    return tuple(out)
+
+
+def _vertex_major(N: int, bc: str):
+    """Permutation from the Kronecker order (y dof major, x dof minor) of the kept
+    1-D dofs to vertex-major order; returns (perm, vert, kind)."""
+    free = _free_1d(N, bc)
+    node, slope = free // 2, free % 2
+    ny, nx = np.meshgrid(np.arange(len(free)), np.arange(len(free)), indexing="ij")
+    ny, nx = ny.ravel(), nx.ravel()
+    iy, ix = node[ny], node[nx]
+    kind = slope[nx] + 2 * slope[ny]
+    perm = np.lexsort((kind, ix, iy))
+    return perm, np.stack([ix[perm], iy[perm]], 1), kind[perm]
+
+
+def _hermite_prolongation_1d(N: int, Nc: int, bc: str) -> sp.csr_matrix:
+    """Fine 1-D dofs of the coarse Hermite basis functions (values and slopes of the
+    coarse cubic pieces at the fine nodes): the inclusion of the coarse space."""
+    r = N // Nc
+    Hc = 1.0 / Nc
+    rows, cols, vals = [], [], []
+    for i in range(N + 1):
+        e = min(i // r, Nc - 1)
+        t = np.array([(i - e * r) / r])
+        f, d1, _ = _hermite_shapes(t, Hc)
+        for a in range(4):
+            cdof = 2 * e + a
+            for fd, v in ((2 * i, f[a, 0]), (2 * i + 1, d1[a, 0])):
+                if v != 0.0:
+                    rows.append(fd)
+                    cols.append(cdof)
+                    vals.append(v)
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(2 * N + 2, 2 * Nc + 2)).tocsr()
+    A.sum_duplicates()
+    return A[_free_1d(N, bc)][:, _free_1d(Nc, bc)].tocsr()
+
+
+def bfs_plate(N: int, bc: str = "clamped", coarse: Optional[int] = None, L: int = 0) -> Plate:
+    """BFS stiffness and mass of the unit square with N x N cells.
+
+    Tensor-product Hermite functions f(x) g(y) give int Lap u Lap v =
+    B (x) M + M (x) B + 2 K (x) K with the 1-D mass M, int f'g' = K and
+    int f''g'' = B (int f''g = -int f'g' because g vanishes at both ends).
+    With ``coarse`` (fine cells per coarse cell) the nested coarse space P and
+    the local dof sets with ``L`` element layers of overlap are added.
+    """
+    M1, K1, B1 = hermite_1d(N, bc)
+    K = (sp.kron(M1, B1) + sp.kron(B1, M1) + 2.0 * sp.kron(K1, K1)).tocsr()
+    M = sp.kron(M1, M1).tocsr()
+    perm, vert, kind = _vertex_major(N, bc)
+    K = K[perm][:, perm]
+    M = M[perm][:, perm]
+    # one (union) pattern for both matrices, explicit zeros kept
+    Kp = (K + 0.0 * M).tocsr()
+    Mp = (M + 0.0 * K).tocsr()
+    for A in (Kp, Mp):
+        A.sort_indices()
+    assert np.array_equal(Kp.indptr, Mp.indptr) and np.array_equal(Kp.indices, Mp.indices)
+    plate = Plate(N, bc, Kp, Mp, vert, kind, meta={"h": 1.0 / N})
+    if coarse is not None:
+        if N % coarse or bc != "clamped":
+            raise ValueError("coarse cells must tile the mesh; local spaces need clamped edges")
+        Nc = N // coarse
+        P1 = _hermite_prolongation_1d(N, Nc, bc)
+        pc, _, _ = _vertex_major(Nc, bc)
+        P = sp.kron(P1, P1).tocsr()[perm][:, pc].tocsr()
+        P.eliminate_zeros()
+        P.sort_indices()
+        plate.P = P
+        subs = []
+        ix, iy = vert[:, 0], vert[:, 1]
+        for b in range(Nc):
+            for a in range(Nc):
+                inside = ((ix > a * coarse - L) & (ix < (a + 1) * coarse + L)
+                          & (iy > b * coarse - L) & (iy < (b + 1) * coarse + L))
+                subs.append(np.flatnonzero(inside).astype(np.int32))
+        plate.subs = subs
+        plate.meta.update(coarse=coarse, L=L, H=1.0 / Nc)
+    return plate
+
+
+# Named fourth-order workloads (clamped unit square, BFS): N fine cells per side,
+# `coarse` fine cells per coarse cell, L overlap layers (delta = L h).
+PLATE_CONFIGS = {
+    "b16": dict(N=16, coarse=4, L=1, k=4, guard=1,
+                desc="BFS plate h=1/16, 4x4 subdomains, delta=h, k=4"),
+    "b32": dict(N=32, coarse=8, L=2, k=6, guard=2,
+                desc="BFS plate h=1/32, 4x4 subdomains, delta=2h, k=6"),
+    "b64": dict(N=64, coarse=8, L=2, k=6, guard=2,
+                desc="BFS plate h=1/64, 8x8 subdomains, delta=2h, k=6"),
+    "c4": dict(N=128, coarse=16, L=4, k=6, guard=2,
+               desc="clamped plate (biharmonic, BFS) h=1/128, 8x8 subdomains, delta=4h, k=6"),
+}
+
+
+def config_plate(name: str) -> tuple[Plate, dict]:
+    """Build a named fourth-order workload; returns (plate, config dict)."""
+    cfg = dict(PLATE_CONFIGS[name])
+    return bfs_plate(cfg["N"], "clamped", cfg["coarse"], cfg["L"]), cfg
