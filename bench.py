@@ -44,6 +44,17 @@ def local_solve_flops(nl: np.ndarray, bw: np.ndarray, s: int) -> float:
     return total * s
 
 
+def local_kernel_name(band: int, slots: int) -> str:
+    """The FP32 local solver the library picks: the blocked MFMA solver with a 64-row
+    window up to half-bandwidth 48 and a 96-row window up to 80 (at most 8 lower
+    entries per local row), the windowed LDS solver otherwise."""
+    if slots <= 8 and band <= 48:
+        return "local_band_mfma_kernel<float, 0, 4>"
+    if slots <= 8 and band <= 80:
+        return "local_band_mfma_kernel<float, 0, 6>"
+    return "local_ldlt_kernel<float>"
+
+
 def spmm_bytes(n: int, nnz: int, ncols: int) -> float:
     """Algorithmic HBM bytes of one fused [K;M] X launch: row pointers, column
     indices, (K, M) value pairs, the X block once, KX and MX written once."""
@@ -75,7 +86,12 @@ def cpu_baseline(mesh, cfg, gpu_iters: int, sample_iters: int):
     iteration count of the same algorithm (the GPU FP64 run's count)."""
     from oracle import bpjd_oracle as o
     t0 = time.perf_counter()
-    dd = o.build_dd(mesh, cfg["L"])
+    if getattr(mesh, "P", None) is not None:          # plate: the oracle's own BFS spaces
+        from oracle import bfs_space as bs
+        Nc = cfg["N"] // cfg["coarse"]
+        dd = o.DD(bs.coarse_space(cfg["N"], Nc, mesh.vert, mesh.kind), bs.local_spaces(cfg["N"], Nc, cfg["L"], mesh.vert))
+    else:
+        dd = o.build_dd(mesh, cfg["L"])
     cs = o.coarse_setup(mesh.K, mesh.M, dd.P)
     ls = o.local_setup(mesh.K, mesh.M, dd.subs)
     t1 = time.perf_counter()
@@ -345,13 +361,23 @@ def main():
         ctx.close()
         return
 
-    mesh, cfg = w.config_mesh(args.config)
+    plate = args.config in w.PLATE_CONFIGS
+    if plate:          # clamped plate, BFS elements: the caller's coarse space and local sets
+        mesh, cfg = w.config_plate(args.config)
+    else:
+        mesh, cfg = w.config_mesh(args.config)
     k, s = cfg["k"], cfg["k"] + cfg["guard"]
     print(f"[bench] {args.config}: n={mesh.n} nnz={mesh.K.nnz} k={k}", file=sys.stderr, flush=True)
     ctx = B.Context(0)
+
+    def make(**kw):
+        if plate:
+            return B.Problem(ctx, mesh.K, mesh.M, dd=(mesh.P, mesh.subs), k=k, guard=cfg["guard"],
+                             tol=cfg.get("tol", 1e-8), **kw)
+        return B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8, **kw)
+
     # timed solves: only the local-solve phase carries HIP events (two per iteration)
-    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8, precision=B.PREC_MIXED,
-                               profile=2)
+    prob = make(precision=B.PREC_MIXED, profile=2)
     secs, lat, stats, lam, X_d = time_solves(prob, args.steps, args.warmup, torch, k, mesh.n)
     print(f"[bench] mixed: {secs / args.steps * 1e3:.1f} ms/solve, iterations {stats[-1]['iterations']}",
           file=sys.stderr, flush=True)
@@ -365,8 +391,7 @@ def main():
     # per-phase breakdown from one extra, untimed solve with every phase timed
     ph = cnt = None
     if not args.no_breakdown:
-        probp = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
-                                    precision=B.PREC_MIXED, profile=1)
+        probp = make(precision=B.PREC_MIXED, profile=1)
         _, _, stp = probp.solve(torch.empty(k, dtype=torch.float64, device="cuda"),
                                 torch.empty((mesh.n, k), dtype=torch.float64, device="cuda"), mem=B.MEM_DEVICE)
         torch.cuda.synchronize()
@@ -375,9 +400,16 @@ def main():
         probp.close()
 
     fp64 = None
+    prob64 = None
     if not args.no_fp64:
-        prob64 = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
-                                     precision=B.PREC_FP64, profile=2)
+        try:
+            prob64 = make(precision=B.PREC_FP64, profile=2)
+        except B.BPJDError as e:       # e.g. an FP64 local window that does not fit in LDS
+            if e.code != B.ERR_DD:
+                raise
+            fp64 = {"skipped": str(e)}
+            print(f"[bench] fp64 comparison not available: {e}", file=sys.stderr, flush=True)
+    if prob64 is not None:
         secs64, lat64, stats64, lam64, _ = time_solves(prob64, max(1, args.steps // 2), 1, torch, k, mesh.n)
         fp64 = {"value": k * len(lat64) / secs64, "ms_per_solve": 1e3 * secs64 / len(lat64),
                 "iterations": stats64[-1]["iterations"], "max_residual": stats64[-1]["max_residual"],
@@ -395,9 +427,11 @@ def main():
     # HIP events on the library's stream inside the timed solves
     nl, bw = prob.local_sizes()
     local_flops = local_solve_flops(nl, bw, s)
+    # lower entries per local row, diagonal included: 4 for P1 on the "/" mesh, 20 for BFS
+    slots = 20 if plate else 4
     roofline = {"bound": "alu", "achieved": local_flops / (local_avg_ms * 1e-3) / 1e12,
                 "peak": PEAK["fp32_TFs"], "unit": "TFLOP/s", "traffic": None,
-                "kernel": "local_band_mfma_kernel<float, 0, 4>", "avg_launch_ms": local_avg_ms,
+                "kernel": local_kernel_name(int(bw.max()), slots), "avg_launch_ms": local_avg_ms,
                 "launches_timed": local_n, "algorithmic_per_launch": local_flops}
     roofline["frac"] = roofline["achieved"] / roofline["peak"]
     roofline["traffic"] = counter_traffic(args.config)
@@ -433,7 +467,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.config}: {cfg['desc']}", "n": mesh.n, "k": k, "s": s,
                    "n_sub": prob.n_sub, "n_coarse": prob.n_coarse, "precision": "mixed (FP32 local solves)",
-                   "subspace": "UU", "stop": "max relative residual <= 1e-8"},
+                   "subspace": "UU", "stop": f"max relative residual <= {cfg.get('tol', 1e-8):g}"},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "iterations": st["iterations"], "max_residual": st["max_residual"],
         "fp64": fp64, "phase_ms_per_solve": ph, "phase_launches": cnt,

@@ -420,10 +420,10 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     for (long long q = 0; q < sumN; ++q) maxE = std::max(maxE, lptr[q + 1] - lptr[q]);
     const bool blocked = maxBW <= kBlockedWideMaxBand && maxE <= kBlockedMaxSlots;
     const int nt = !blocked ? 0 : (maxBW <= kBlockedMaxBand ? 4 : 6);   // window tile-rows
-    // the windowed solver gives each lane at most two entries of a window row and loads
+    // the windowed solver gives each lane at most three entries of a window row and loads
     // the slots of a block of rows one slot per lane
-    if (!blocked && (maxBW > 127 || maxE > 64))
-        return fail(BPJD_ERR_DD, "local half-bandwidth above 127 or more than 64 lower entries in a local row");
+    if (!blocked && (maxBW > 191 || maxE > 64))
+        return fail(BPJD_ERR_DD, "local half-bandwidth above 191 or more than 64 lower entries in a local row");
     // stored rows per factor column: the band part (rounded up to 4; the factor traffic
     // bounds the backward sweep), except FP32 with the 96-row window, which keeps full
     // columns
@@ -818,6 +818,7 @@ struct SolveRun {
     int it = 0;         // outer iteration whose residual is being read back
     int iters = 0;
     bool converged = false;
+    bool fresh = false; // the residual being read back comes from K X, M X formed from X itself
     double stop_value = NAN;
     std::vector<double> lam_prev, lam_now, rho;
     ~SolveRun() {
@@ -983,7 +984,23 @@ static int advance_iter(SolveRun* r) {
         for (int i = 0; i < s; ++i) r->stop_value += std::fabs(r->lam_now[i] - r->lam_prev[i]);
     }
     bool stop = false;
-    if (p->opts.stop_rule == BPJD_STOP_RESIDUAL && rmax <= p->opts.tol) stop = r->converged = true;
+    if (p->opts.stop_rule == BPJD_STOP_RESIDUAL && rmax <= p->opts.tol) {
+        if (!r->fresh) {
+            // K X and M X are carried through the Rayleigh-Ritz updates (X <- W Q with
+            // K X <- (K W) Q), and rounding lets them drift from the products of X itself
+            // by about u |K| |X| per update: far above the residual for a fourth-order
+            // operator on a fine mesh.  The stop is decided on products formed afresh.
+            PH_BEGIN(r->T, BPJD_PHASE_SPMM);
+            launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, p->W[r->cur], s, s, p->KW[r->cur], s,
+                           p->MW[r->cur], s);
+            PH_END(r->T);
+            r->fresh = true;
+            if (p->trace) std::fprintf(stderr, "[bpjd]   products of X formed afresh\n");
+            BPJD_TRY(enqueue_residual(r));
+            return 0;
+        }
+        stop = r->converged = true;
+    }
     if (p->opts.stop_rule == BPJD_STOP_PAPER && r->it > 0 && r->stop_value < p->opts.tol) stop = r->converged = true;
     if (r->it == p->opts.max_iter) stop = true;
     if (stop) {
@@ -1002,6 +1019,7 @@ static int advance_iter(SolveRun* r) {
     // Replayed as a HIP graph unless phases are timed, the iteration is traced, or the
     // caller turned graphs off.
     const bool graph = p->opts.graphs && !r->T && !p->trace && !p->graph_failed;
+    r->fresh = false;
     if (graph && launch_iteration_graph(r, a, r->np)) {
         r->cur = 1 - a;
         r->np = uu ? s : 0;

@@ -303,6 +303,11 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// The windowed solver, like the blocked one below, runs one wavefront per workgroup
+// and exchanges LDS data within the step loops through wave_sync (defined with the
+// blocked solver): a wave barrier without the memory fence of __syncthreads.
+__device__ inline void wave_sync();
+
 // Local LDL^T factor + solve for bands too wide for the blocked solver: one wavefront
 // per (subdomain, shift), the band window of C = w + 1 rows in LDS as a circular
 // buffer.  Step j scales column j and updates the window (lane a owns row j + a), then
@@ -385,8 +390,8 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
             neg |= dj < T(0);
             const T inv = T(1) / dj;
             const T yj = ywin[sj];
-            // rows j + a, a = 1..w, in pairs (a, w + 1 - a): lane q < ceil(w/2) updates rows
-            // q + 1 and w - q, so every lane does at most w + 1 entries
+            // rows j + a, a = 1..w, in pairs (a, w + 1 - a): pair q < ceil(w/2) updates rows
+            // q + 1 and w - q (w + 1 entries) and belongs to lane q mod 64
             auto update_row = [&](const int a) {
                 const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
                 T* rowa = win + ra * C;
@@ -414,8 +419,8 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
                 ywin[ra] -= lsc * yj;
                 Lc[(long long)j * C + a] = lsc;
             };
-            if (lane < (w + 1) / 2) {
-                const int a1 = lane + 1, a2 = w - lane;
+            for (int q = lane; q < (w + 1) / 2; q += 64) {   // a second pair on lanes 0..31 for w > 127
+                const int a1 = q + 1, a2 = w - q;
                 if (j + a1 < nl) update_row(a1);
                 if (a2 != a1 && j + a2 < nl) update_row(a2);
             }
@@ -423,10 +428,10 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
                 Lc[(long long)j * C] = dj;
                 z[j] = yj * inv;
             }
-            __syncthreads();
+            wave_sync();
             T* row = win + sj * C;
             for (int e = lane; e < C; e += 64) row[e] = T(0);
-            __syncthreads();
+            wave_sync();
             const int rn = j + C;
             if (rn < nl) {
                 if (rn == bstart + RB) {       // next block becomes current; fetch the one after
@@ -441,24 +446,27 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
                     if (le == 0) ywin[sj] = bf;
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
         if (attempt > 0 || !neg) break;    // every lane reads the same pivots
         shift = 0.0;
     }
+    __syncthreads();    // the stored factor and forward values are complete before they are read back
     // backward sweep with the unit upper factor L^T; the columns of steps j - 1 .. j - D
-    // are in flight while step j is summed (lane a owns entries a = lane + 1, lane + 65)
+    // are in flight while step j is summed (lane owns entries a = lane + 1, lane + 65,
+    // lane + 129)
     constexpr int D = 4;
-    T la[D], lb[D], zq[D];
-    auto fetch_col = [&](const int j, T& va, T& vb, T& vz) {
+    T la[D], lb[D], lc3[D], zq[D];
+    auto fetch_col = [&](const int j, T& va, T& vb, T& vc, T& vz) {
         const int jc = max(j, 0);
-        const int a1 = lane + 1, a2 = lane + 65;
+        const int a1 = lane + 1, a2 = lane + 65, a3 = lane + 129;
         va = (a1 <= w && jc + a1 < nl) ? Lc[(long long)jc * C + a1] : T(0);
         vb = (a2 <= w && jc + a2 < nl) ? Lc[(long long)jc * C + a2] : T(0);
+        vc = (a3 <= w && jc + a3 < nl) ? Lc[(long long)jc * C + a3] : T(0);
         vz = z[jc];
     };
 #pragma unroll
-    for (int u = 0; u < D; ++u) fetch_col(nl - 1 - u, la[u], lb[u], zq[u]);
+    for (int u = 0; u < D; ++u) fetch_col(nl - 1 - u, la[u], lb[u], lc3[u], zq[u]);
     for (int jj = nl - 1; jj >= 0; jj -= D) {
 #pragma unroll
         for (int u = 0; u < D; ++u) {
@@ -472,15 +480,20 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
                     const int r2 = sj + a2 - (sj + a2 >= C ? C : 0);
                     part += lb[u] * zwin[r2];
                 }
+                const int a3 = lane + 129;
+                if (a3 <= w) {
+                    const int r3 = sj + a3 - (sj + a3 >= C ? C : 0);
+                    part += lc3[u] * zwin[r3];
+                }
                 const T zj0 = zq[u];
-                fetch_col(j - D, la[u], lb[u], zq[u]);
+                fetch_col(j - D, la[u], lb[u], lc3[u], zq[u]);
                 part = wave_sum(part);
                 if (lane == 0) {
                     const T zj = zj0 - part;
                     zwin[sj] = zj;
                     z[j] = zj;
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
     }

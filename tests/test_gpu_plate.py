@@ -3,7 +3,7 @@
 The clamped plate Lap^2 u = lambda u on the unit square with Bogner-Fox-Schmit
 elements goes through the generic interface: the caller's coarse space P and
 local dof sets (bpjd_problem_create).  Four dofs per vertex give local rows with
-up to 20 lower entries and half-bandwidths 27-99, so every local system takes
+up to 20 lower entries and half-bandwidths 27-163, so every local system takes
 the windowed LDL^T solver.  The oracle builds its own coarse and local spaces.
 """
 import os
@@ -18,7 +18,7 @@ from paper_2203_06327_amd import workloads as w
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c4_reference.txt")
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -138,26 +138,79 @@ def test_plate_solve(B, ctx, name, prec):
         assert abs(st["iterations"] - r.iterations) <= 1
 
 
-def _golden():
-    vals = [float(line.split()[1]) for line in open(GOLDEN) if line.strip() and not line.startswith("#")]
-    return np.array(vals)
+def _golden(name):
+    """Rows of a stored reference: eigenvalue, and (where given) the relative accuracy
+    the FP64 data allow."""
+    rows = [line.split() for line in open(os.path.join(GOLDEN_DIR, f"{name}_reference.txt"))
+            if line.strip() and not line.startswith("#")]
+    lam = np.array([float(r[1]) for r in rows])
+    floor = np.array([float(r[2]) if len(r) > 2 else 0.0 for r in rows])
+    return lam, floor
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_plate_c4_full_size(B, ctx, prec):
+def test_plate_p128(B, ctx, prec):
     """The clamped plate at h = 1/128 (64,516 dofs, 8 x 8 subdomains, delta = 4h, local
     half-bandwidth 99): the six smallest eigenvalues against the oracle's stored
     reference, host residuals, M-orthonormal eigenvectors."""
-    _case(f"plate c4 {prec}")
-    pl, cfg = w.config_plate("c4")
+    _case(f"plate p128 {prec}")
+    pl, cfg = w.config_plate("p128")
     k = cfg["k"]
     precision = B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED
     prob = _problem(B, ctx, pl, cfg, precision)
     lam, X, st = prob.solve()
     prob.close()
     print(f"  iterations {st['iterations']}, max residual {st['max_residual']:.2e}", flush=True)
-    np.testing.assert_allclose(lam, _golden()[:k], rtol=1e-10)
+    np.testing.assert_allclose(lam, _golden("p128")[0][:k], rtol=1e-10)
     assert _host_residuals(pl.K, pl.M, lam, X).max() <= 1.5e-8
     np.testing.assert_allclose(X.T @ (pl.M @ X), np.eye(k), atol=1e-10)
     # the double eigenvalue (x <-> y symmetry) comes out double
     assert abs(lam[1] - lam[2]) <= 1e-10 * lam[2]
+
+
+def _residual_floor(name):
+    for line in open(os.path.join(GOLDEN_DIR, f"{name}_reference.txt")):
+        if line.startswith("# residual_floor"):
+            return float(line.split("=")[1].split()[0])
+    raise KeyError(name)
+
+
+def test_plate_c4_full_size(B, ctx):
+    """The clamped plate at h = 1/256 (260,100 dofs, 8 x 8 subdomains, delta = 4h, local
+    half-bandwidth 163, 6084 dofs per interior subdomain), FP32 local solves.  Here a
+    relative residual of 1e-8 lies below what FP64 vectors attain: entries with relative
+    errors of order u reach up to u lambda_max / lambda_1 = 3e-6 (lambda_max = 3.7e13),
+    and the iterates level off near 1e-6.  The solve stops at that floor; its
+    eigenvalues must match the oracle's stored reference within the accuracy the FP64
+    data allow (at least 1e-10), the host residuals must meet the floor, and the
+    eigenvectors must be M-orthonormal."""
+    _case("plate c4 mixed")
+    pl, cfg = w.config_plate("c4")
+    k = cfg["k"]
+    tol = _residual_floor("c4")
+    prob = _problem(B, ctx, pl, cfg, B.PREC_MIXED, tol=tol, max_iter=150)
+    nl, bw = prob.local_sizes()
+    print(f"  local sizes {nl.min()}-{nl.max()}, half-bandwidths {bw.min()}-{bw.max()}, tol {tol:.2e}", flush=True)
+    lam, X, st = prob.solve(raise_noconv=False)
+    prob.close()
+    print(f"  iterations {st['iterations']}, max residual {st['max_residual']:.2e}", flush=True)
+    ref, floor = _golden("c4")
+    etol = np.maximum(1e-10, floor[:k])
+    err = np.abs(lam / ref[:k] - 1.0)
+    print("  eigenvalue errors " + " ".join(f"{e:.1e}/{t:.1e}" for e, t in zip(err, etol)), flush=True)
+    res = _host_residuals(pl.K, pl.M, lam, X)
+    print("  host residuals " + " ".join(f"{r:.1e}" for r in res), flush=True)
+    assert st["converged"]
+    assert np.all(err <= etol)
+    assert res.max() <= tol
+    np.testing.assert_allclose(X.T @ (pl.M @ X), np.eye(k), atol=1e-10)
+
+
+def test_plate_c4_fp64_window_does_not_fit(B, ctx):
+    """With FP64 local solves the band-163 window (164^2 doubles) exceeds the LDS of a
+    workgroup: the library says so when the problem is created, before any launch."""
+    _case("plate c4 fp64 rejected")
+    pl, cfg = w.config_plate("c4")
+    with pytest.raises(B.BPJDError) as e:
+        _problem(B, ctx, pl, cfg, B.PREC_FP64)
+    assert e.value.code == B.ERR_DD
