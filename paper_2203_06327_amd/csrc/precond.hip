@@ -331,6 +331,10 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
     const int C = w + 1;
     T* ywin = win + C * C;
     T* zwin = ywin + C;
+    // column j of the window, contiguous (cwin[b] = A(j + b, j)), during the forward phase
+    // only: it shares the storage of the backward sweep's z (the LDS footprint decides
+    // how many systems share a compute unit)
+    T* cwin = zwin;
     double shift = lam[i];      // 0 when K_l - lambda_i M_l is not positive definite
     T* Lc = Lwork + Loff[l] + (long long)i * nl * C;
     const T* f = Floc + (long long)i * ldF + off;
@@ -390,32 +394,34 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
             neg |= dj < T(0);
             const T inv = T(1) / dj;
             const T yj = ywin[sj];
+            // column j out of the ring of rows into a contiguous vector, so that the update
+            // loops index it directly (no per-entry ring arithmetic)
+            for (int b = lane; b < C; b += 64) {
+                const int rb = sj + b - (sj + b >= C ? C : 0);
+                cwin[b] = win[rb * C + b];
+            }
+            wave_sync();
             // rows j + a, a = 1..w, in pairs (a, w + 1 - a): pair q < ceil(w/2) updates rows
             // q + 1 and w - q (w + 1 entries) and belongs to lane q mod 64
             auto update_row = [&](const int a) {
                 const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
                 T* rowa = win + ra * C;
-                const T lsc = rowa[a] * inv;
-                int rb = sj + 1 - (sj + 1 >= C ? C : 0);           // slot of row j + b, b = 1
-                // row j + a (offsets a - b) -= l_{j+a} * column j (row j + b, offset b),
-                // 8 entries at a time: the column entries are never written in this step,
-                // so all 16 loads of a group are issued before its first update
+                const T lsc = cwin[a] * inv;
+                // row j + a (offsets a - b) -= l_{j+a} * column j (entry b), 8 entries at a
+                // time: the column entries are never written in this step, so all 16 loads
+                // of a group are issued before its first update
                 int b = 1;
                 for (; b + 7 <= a; b += 8) {
                     T cv[8], rv[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        cv[u] = win[rb * C + b + u];
+                        cv[u] = cwin[b + u];
                         rv[u] = rowa[a - b - u];
-                        rb = (rb + 1 == C) ? 0 : rb + 1;
                     }
 #pragma unroll
                     for (int u = 0; u < 8; ++u) rowa[a - b - u] = rv[u] - lsc * cv[u];
                 }
-                for (; b <= a; ++b) {
-                    rowa[a - b] -= lsc * win[rb * C + b];
-                    rb = (rb + 1 == C) ? 0 : rb + 1;
-                }
+                for (; b <= a; ++b) rowa[a - b] -= lsc * cwin[b];
                 ywin[ra] -= lsc * yj;
                 Lc[(long long)j * C + a] = lsc;
             };
@@ -451,6 +457,7 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
         if (attempt > 0 || !neg) break;    // every lane reads the same pivots
         shift = 0.0;
     }
+    for (int e = lane; e < C; e += 64) zwin[e] = T(0);     // it held column values
     __syncthreads();    // the stored factor and forward values are complete before they are read back
     // backward sweep with the unit upper factor L^T; the columns of steps j - 1 .. j - D
     // are in flight while step j is summed (lane owns entries a = lane + 1, lane + 65,
