@@ -308,15 +308,23 @@ __device__ inline T wave_sum(T v) {
 // blocked solver): a wave barrier without the memory fence of __syncthreads.
 __device__ inline void wave_sync();
 
-// Local LDL^T factor + solve for bands too wide for the blocked solver: one wavefront
-// per (subdomain, shift), the band window of C = w + 1 rows in LDS as a circular
-// buffer.  Step j scales column j and updates the window (lane a owns row j + a), then
-// row j + C enters the window.  The entering rows come from the fixed-slot arrays
-// (band offset, (K, M) pair) and are loaded a block of RB rows at a time, one block
-// ahead, one slot per lane, so no step waits on global memory; the backward sweep
-// reads the stored factor columns D steps ahead in a register ring.
+// Workgroup barrier for data exchanged through LDS only: waits for this wave's LDS
+// accesses, not for its outstanding global loads and stores.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+constexpr int kLdltThreads = 256;   // four waves per system in the forward phase
+
+// Local LDL^T factor + solve for bands too wide for the blocked solver (or rows with more
+// than 8 lower entries): one workgroup of four waves per (subdomain, shift), the band
+// window of C = w + 1 rows in LDS as a circular buffer.  Step j scales column j and
+// updates the window: every thread takes a fixed chunk of the rows below the pivot, so
+// the step's work is spread over all four waves.  Wave 0 then puts row j + C into the
+// freed slot and copies column j + 1 out for the next step.  The entering rows come from
+// the fixed-slot arrays (band offset, (K, M) pair) and are loaded a block of RB rows at a
+// time, one block ahead, one slot per lane.  The backward sweep (wave 0) reads the stored
+// factor columns D steps ahead in a register ring.
 template <typename T>
-__global__ __launch_bounds__(64) void local_ldlt_kernel(
+__global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
     int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
     const double2* __restrict__ sv, const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF,
     T* __restrict__ zloc, T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
@@ -339,7 +347,9 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
     T* Lc = Lwork + Loff[l] + (long long)i * nl * C;
     const T* f = Floc + (long long)i * ldF + off;
     T* z = zloc + (long long)i * ldF + off;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const bool wave0 = tid < 64;    // entering rows, column copies and the backward sweep
     // entering rows in blocks of RB rows, lane = (row d of the block, slot e); EP = slots
     // per row rounded up to a power of two (E <= 64)
     int EP = 1;
@@ -358,35 +368,54 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
         if (!ok) dsd = -1;
         df = f[min(r, nl - 1)];
     };
+    // this thread's share of each step's window update: the rows j + a, a = 1..w, go in
+    // pairs (q + 1, w - q), q < ceil(w/2), of w + 1 entries together, and each pair is cut
+    // into S chunks of Lch consecutive entries; thread (q, h) updates chunk h of pair q
+    const int npair = (w + 1) / 2;
+    const int S = max(1, kLdltThreads / npair);
+    const int Lch = (w + S) / S;
+    const int pq = tid / S, ph = tid - pq * S;
+    const int a1 = pq + 1, a2 = w - pq;
+    auto copy_column = [&](const int jn) {   // column jn of the window into cwin (wave 0)
+        const int sn = jn % C;
+        for (int b = lane; b < C; b += 64) {
+            const int rb = sn + b - (sn + b >= C ? C : 0);
+            cwin[b] = win[rb * C + b];
+        }
+    };
 
     int bad = 0;
     // forward phase; a negative pivot (indefinite local matrix) runs it again with shift 0
     for (int attempt = 0;; ++attempt) {
-        for (int e = lane; e < C * C + 2 * C; e += 64) win[e] = T(0);
+        for (int e = tid; e < C * C + 2 * C; e += kLdltThreads) win[e] = T(0);
         __syncthreads();
-        // rows 0 .. C-1 start the window
-        for (int r0 = 0; r0 < min(C, nl); r0 += RB) {
-            int dsd;
-            double2 dsv;
-            T df;
-            load_block(r0, dsd, dsv, df);
-            const int r = r0 + ld;
-            if (r < min(C, nl)) {
-                if (dsd >= 0) win[r * C + dsd] = (T)(dsv.x - shift * dsv.y);
-                if (le == 0) ywin[r] = df;
-            }
-        }
-        // blocks of the rows entering from step 0 on (row C + j at step j)
         int bstart = C;
-        load_block(bstart, bsd, bsv, bf);
-        load_block(bstart + RB, nsd, nsv, nf);
+        if (wave0) {
+            // rows 0 .. C-1 start the window
+            for (int r0 = 0; r0 < min(C, nl); r0 += RB) {
+                int dsd;
+                double2 dsv;
+                T df;
+                load_block(r0, dsd, dsv, df);
+                const int r = r0 + ld;
+                if (r < min(C, nl)) {
+                    if (dsd >= 0) win[r * C + dsd] = (T)(dsv.x - shift * dsv.y);
+                    if (le == 0) ywin[r] = df;
+                }
+            }
+            // blocks of the rows entering from step 0 on (row C + j at step j)
+            load_block(bstart, bsd, bsv, bf);
+            load_block(bstart + RB, nsd, nsv, nf);
+            wave_sync();
+            copy_column(0);
+        }
         __syncthreads();
 
         bad = 0;
         int neg = 0;
         for (int j = 0; j < nl; ++j) {
             const int sj = j % C;
-            T dj = win[sj * C];
+            T dj = cwin[0];
             if (!(dj == dj) || dj == T(0) || !isfinite((double)dj)) {
                 bad = 1;
                 dj = T(1);
@@ -394,24 +423,15 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
             neg |= dj < T(0);
             const T inv = T(1) / dj;
             const T yj = ywin[sj];
-            // column j out of the ring of rows into a contiguous vector, so that the update
-            // loops index it directly (no per-entry ring arithmetic)
-            for (int b = lane; b < C; b += 64) {
-                const int rb = sj + b - (sj + b >= C ? C : 0);
-                cwin[b] = win[rb * C + b];
-            }
-            wave_sync();
-            // rows j + a, a = 1..w, in pairs (a, w + 1 - a): pair q < ceil(w/2) updates rows
-            // q + 1 and w - q (w + 1 entries) and belongs to lane q mod 64
-            auto update_row = [&](const int a) {
+            // entries b = b0..b1 of row j + a: -= l_{j+a} * column j (entry b), 8 at a time
+            // (the column is never written in this step, so all 16 loads of a group are
+            // issued before its first update)
+            auto update_range = [&](const int a, const int b0, const int b1) {
                 const int ra = sj + a - (sj + a >= C ? C : 0);     // slot of row j + a
                 T* rowa = win + ra * C;
                 const T lsc = cwin[a] * inv;
-                // row j + a (offsets a - b) -= l_{j+a} * column j (entry b), 8 entries at a
-                // time: the column entries are never written in this step, so all 16 loads
-                // of a group are issued before its first update
-                int b = 1;
-                for (; b + 7 <= a; b += 8) {
+                int b = b0;
+                for (; b + 7 <= b1; b += 8) {
                     T cv[8], rv[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
@@ -421,44 +441,60 @@ __global__ __launch_bounds__(64) void local_ldlt_kernel(
 #pragma unroll
                     for (int u = 0; u < 8; ++u) rowa[a - b - u] = rv[u] - lsc * cv[u];
                 }
-                for (; b <= a; ++b) rowa[a - b] -= lsc * cwin[b];
+                for (; b <= b1; ++b) rowa[a - b] -= lsc * cwin[b];
+            };
+            auto finish_row = [&](const int a) {   // multiplier stored, forward substitution
+                const int ra = sj + a - (sj + a >= C ? C : 0);
+                const T lsc = cwin[a] * inv;
                 ywin[ra] -= lsc * yj;
                 Lc[(long long)j * C + a] = lsc;
             };
-            for (int q = lane; q < (w + 1) / 2; q += 64) {   // a second pair on lanes 0..31 for w > 127
-                const int a1 = q + 1, a2 = w - q;
-                if (j + a1 < nl) update_row(a1);
-                if (a2 != a1 && j + a2 < nl) update_row(a2);
+            if (pq < npair) {
+                const int n1 = (j + a1 < nl) ? a1 : 0;                     // entries of row j + a1
+                const int n2 = (a2 != a1 && j + a2 < nl) ? a2 : 0;         // and of row j + a2
+                const int lo = ph * Lch, hi = min(lo + Lch, n1 + n2);      // this chunk: [lo, hi)
+                if (lo < min(hi, n1)) update_range(a1, lo + 1, min(hi, n1));
+                if (hi > max(lo, n1)) update_range(a2, max(lo, n1) - n1 + 1, hi - n1);
+                if (ph == 0) {
+                    if (n1) finish_row(a1);
+                    if (n2) finish_row(a2);
+                }
             }
-            if (lane == 0) {
+            if (tid == 0) {
                 Lc[(long long)j * C] = dj;
                 z[j] = yj * inv;
             }
-            wave_sync();
-            T* row = win + sj * C;
-            for (int e = lane; e < C; e += 64) row[e] = T(0);
-            wave_sync();
-            const int rn = j + C;
-            if (rn < nl) {
-                if (rn == bstart + RB) {       // next block becomes current; fetch the one after
-                    bstart += RB;
-                    bsd = nsd;
-                    bsv = nsv;
-                    bf = nf;
-                    load_block(bstart + RB, nsd, nsv, nf);
+            lds_barrier();
+            if (wave0) {
+                // the pivot row's slot takes row j + C; then column j + 1 is copied out
+                T* row = win + sj * C;
+                for (int e = lane; e < C; e += 64) row[e] = T(0);
+                wave_sync();
+                const int rn = j + C;
+                if (rn < nl) {
+                    if (rn == bstart + RB) {       // next block becomes current; fetch the one after
+                        bstart += RB;
+                        bsd = nsd;
+                        bsv = nsv;
+                        bf = nf;
+                        load_block(bstart + RB, nsd, nsv, nf);
+                    }
+                    if (ld == rn - bstart) {
+                        if (bsd >= 0) row[bsd] = (T)(bsv.x - shift * bsv.y);
+                        if (le == 0) ywin[sj] = bf;
+                    }
                 }
-                if (ld == rn - bstart) {
-                    if (bsd >= 0) row[bsd] = (T)(bsv.x - shift * bsv.y);
-                    if (le == 0) ywin[sj] = bf;
-                }
+                wave_sync();
+                if (j + 1 < nl) copy_column(j + 1);
             }
-            wave_sync();
+            lds_barrier();
         }
-        if (attempt > 0 || !neg) break;    // every lane reads the same pivots
+        if (attempt > 0 || !neg) break;    // every thread reads the same pivots
         shift = 0.0;
     }
-    for (int e = lane; e < C; e += 64) zwin[e] = T(0);     // it held column values
+    for (int e = tid; e < C; e += kLdltThreads) zwin[e] = T(0);     // it held column values
     __syncthreads();    // the stored factor and forward values are complete before they are read back
+    if (!wave0) return;
     // backward sweep with the unit upper factor L^T; the columns of steps j - 1 .. j - D
     // are in flight while step j is summed (lane owns entries a = lane + 1, lane + 65,
     // lane + 129)
@@ -1023,7 +1059,7 @@ static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long su
                          int E, const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
                          T* Lwork, const long long* Loff, int* status) {
     const size_t shmem = (size_t)(maxC * maxC + 2 * maxC) * sizeof(T);
-    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(64), shmem, st, s, E, subptr, bw, sd, sv, lam, Floc,
+    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(kLdltThreads), shmem, st, s, E, subptr, bw, sd, sv, lam, Floc,
                        sumN, zloc, Lwork, Loff, status);
 }
 
