@@ -131,6 +131,14 @@ typedef struct {
                                    requests.  A capture needs the context's stream to be a
                                    created (non-null) stream with no device-wide synchronisation
                                    (another thread's hipFree, hipDeviceSynchronize) meanwhile. */
+    int32_t autotune;           /* 1 (default): when a problem is first set up, the launch shapes that
+                                   leave the arithmetic unchanged (threads per system of the windowed
+                                   local solver: 64, 128 or 256; one or two SpMM columns per lane) are
+                                   timed on its own data and the fastest is kept, per process and keyed
+                                   by the problem's shape (and appended to the file named by the
+                                   environment variable BPJD_TUNE_CACHE, read at the first tuning, when
+                                   it is set).  Results are the same bit for bit either way.
+                                   0: fixed choices (256 threads, two columns per lane). */
 } bpjd_opts;
 
 /* phases timed when bpjd_opts.profile = 1 (profile = 2: BPJD_PHASE_LOCAL only) */

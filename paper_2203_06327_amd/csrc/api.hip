@@ -7,6 +7,9 @@
 // operators, the coarse eigenproblem, SpMM, residuals, the preconditioner,
 // orthonormalisation, Rayleigh-Ritz) runs in the HIP kernels of this library.
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -696,11 +699,12 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
         if (mixed)
             launch_local_solve_f32(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->mfma_nt,
                                    p->slotE, p->bws, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
-                                   (float*)p->Lwork, p->Loff, p->status, p->negflag);
+                                   (float*)p->Lwork, p->Loff, p->status, p->negflag, p->ldlt_threads);
         else
             launch_local_solve_f64(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->mfma_nt,
                                    p->slotE, p->bws, p->sd, p->sv, p->lam, (const double*)p->Floc,
-                                   (double*)p->zloc, (double*)p->Lwork, p->Loff, p->status, p->negflag);
+                                   (double*)p->zloc, (double*)p->Lwork, p->Loff, p->status, p->negflag,
+                                   p->ldlt_threads);
         if (mode == 0) PH_END(T);
     }
     PH_BEGIN(T, BPJD_PHASE_GATHER);
@@ -736,7 +740,7 @@ static void orthonormalize_T(bpjd_problem* p, int b, int ct, PhaseTimer* T) {
     }
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_SPMM);
-    launch_spmm_km(st, n, p->rowptr, p->col, p->km, T0, s, s, dst3[1], s, dst3[2], s);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, T0, s, s, dst3[1], s, dst3[2], s, p->spmm_variant);
     PH_END(T);
     PH_BEGIN(T, BPJD_PHASE_ORTHO);
     for (int pass = 0; pass < 2; ++pass) {
@@ -940,6 +944,125 @@ int run_wait(SolveRun* r) {
     return q < 0 ? q : BPJD_OK;
 }
 
+// ---- autotuner ----------------------------------------------------------------------
+// Launch shapes that leave the data layout and the arithmetic unchanged (results are the
+// same bit for bit) are timed on the problem's own data when it is first set up: the
+// threads per system of the windowed local solver (64, 128 or 256) and the SpMM form (two
+// columns per lane or one).  The fastest is kept per process, keyed by the problem's shape,
+// and appended to the file named by BPJD_TUNE_CACHE when that is set (read at the first
+// tuning of the process).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("BPJD_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream in(path);
+    std::string key, rest;
+    while (std::getline(in, rest)) {
+        const size_t sp = rest.rfind(' ');
+        if (sp == std::string::npos) continue;
+        key = rest.substr(0, sp);
+        try {
+            g_tune[key] = std::stoi(rest.substr(sp + 1));
+        } catch (...) {
+        }
+    }
+}
+}  // namespace
+
+// milliseconds per call of `launch` on st: one warm-up call, then `reps` timed calls
+template <class Launch>
+static int time_launch(hipStream_t st, Launch&& launch, int reps, float* ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return fail(BPJD_ERR_HIP, "autotune: hipEventCreate failed");
+    }
+    launch();
+    hipError_t e = hipEventRecord(a, st);
+    for (int q = 0; q < reps; ++q) launch();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail(BPJD_ERR_HIP, std::string("autotune timing: ") + hipGetErrorString(e));
+    *ms = t / reps;
+    return BPJD_OK;
+}
+
+// the cached choice for `key`, else the fastest of `cands` timed with run(candidate)
+template <class Run>
+static int tune_choice(const std::string& key, const std::vector<int>& cands, hipStream_t st, Run&& run, int* out) {
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end()) {
+            *out = it->second;
+            return BPJD_OK;
+        }
+    }
+    int best = cands[0];
+    float tbest = 0.f;
+    for (size_t q = 0; q < cands.size(); ++q) {
+        float t = 0.f;
+        BPJD_TRY(time_launch(st, [&] { run(cands[q]); }, 2, &t));
+        if (q == 0 || t < tbest) {
+            tbest = t;
+            best = cands[q];
+        }
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto ins = g_tune.emplace(key, best);     // another thread may have tuned the same shape first
+    *out = ins.first->second;
+    if (ins.second) {
+        if (const char* path = std::getenv("BPJD_TUNE_CACHE")) {
+            std::ofstream o(path, std::ios::app);
+            o << key << ' ' << best << '\n';
+        }
+    }
+    return BPJD_OK;
+}
+
+// Runs after the first numeric setup of a problem, outside any stream capture.  The SpMM
+// candidates write buffer 1's products (not yet in use); the local-solve candidates solve
+// zero right-hand sides with the current shifts (the factorisations are the real ones).
+static int autotune(bpjd_problem* p) {
+    hipStream_t st = p->ctx->stream;
+    const int s = p->s;
+    const bool mixed = p->opts.precision == BPJD_PREC_MIXED;
+    char key[192];
+    if (s % 2 == 0) {
+        std::snprintf(key, sizeof key, "spmm n%d nnz%lld c%d", p->n, p->nnz, s);
+        BPJD_TRY(tune_choice(key, {0, 1}, st, [&](int v) {
+            launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, p->W[0], s, s, p->KW[1], s, p->MW[1], s, v);
+        }, &p->spmm_variant));
+    }
+    if (!p->blocked) {
+        BPJD_HIP(hipMemsetAsync(p->Floc, 0, (size_t)p->sumN * s * (mixed ? sizeof(float) : sizeof(double)), st));
+        std::snprintf(key, sizeof key, "ldlt %s s%d sub%d n%d w%d e%d", mixed ? "f32" : "f64", s, p->nsub, p->maxN,
+                      p->maxBW, p->slotE);
+        BPJD_TRY(tune_choice(key, {64, 128, 256}, st, [&](int th) {
+            if (mixed)
+                launch_local_solve_f32(st, 0, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, 0, p->slotE, p->bws,
+                                       p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
+                                       (float*)p->Lwork, p->Loff, p->status, p->negflag, th);
+            else
+                launch_local_solve_f64(st, 0, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, 0, p->slotE, p->bws,
+                                       p->sd, p->sv, p->lam, (const double*)p->Floc, (double*)p->zloc,
+                                       (double*)p->Lwork, p->Loff, p->status, p->negflag, th);
+        }, &p->ldlt_threads));
+    }
+    return BPJD_OK;
+}
+
 static int advance_setup(SolveRun* r) {
     bpjd_problem* p = r->p;
     const int st_word = *reinterpret_cast<const int*>(p->hbuf + 256);
@@ -947,6 +1070,10 @@ static int advance_setup(SolveRun* r) {
     if (st_word & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
     p->setup_done = true;
     BPJD_TRY(start_block(p));
+    if (!p->tuned) {
+        if (p->opts.autotune) BPJD_TRY(autotune(p));
+        p->tuned = true;
+    }
     PH_END(r->T);
     BPJD_HIP(hipEventRecord(r->e1, p->ctx->stream));
     BPJD_TRY(enqueue_residual(r));
@@ -992,7 +1119,7 @@ static int advance_iter(SolveRun* r) {
             // operator on a fine mesh.  The stop is decided on products formed afresh.
             PH_BEGIN(r->T, BPJD_PHASE_SPMM);
             launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, p->W[r->cur], s, s, p->KW[r->cur], s,
-                           p->MW[r->cur], s);
+                           p->MW[r->cur], s, p->spmm_variant);
             PH_END(r->T);
             r->fresh = true;
             if (p->trace) std::fprintf(stderr, "[bpjd]   products of X formed afresh\n");
@@ -1160,6 +1287,7 @@ void bpjd_opts_default(bpjd_opts* o, int32_t k) {
     o->n_init = 0;
     o->X_init = nullptr;
     o->graphs = 1;
+    o->autotune = 1;
 }
 
 int bpjd_ctx_create(int device, void* hip_stream, bpjd_ctx** out) {

@@ -128,10 +128,11 @@ __global__ void spmm_km_pair_kernel(int n, const int* __restrict__ rowptr, const
 }
 
 void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, const double2* km,
-                    const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm) {
+                    const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm, int variant) {
     // column pairs need even column counts and leading dimensions and 16-byte aligned
-    // blocks (every block of the library is a hipMalloc base plus multiples of 16 bytes)
-    const bool pair = (ncols % 2 == 0) && (ldx % 2 == 0) && (ldk % 2 == 0) && (ldm % 2 == 0) &&
+    // blocks (every block of the library is a hipMalloc base plus multiples of 16 bytes);
+    // variant 1 keeps one column per lane.  Both forms add a row's entries in the same order.
+    const bool pair = variant == 0 && (ncols % 2 == 0) && (ldx % 2 == 0) && (ldk % 2 == 0) && (ldm % 2 == 0) &&
                       ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(KX) |
                         reinterpret_cast<uintptr_t>(MX)) % 16 == 0);
     const int lanes = pair ? ncols / 2 : ncols;

@@ -58,7 +58,7 @@ struct BlockGeom {
 // ---- launchers: block linear algebra (blas.hip) -------------------------------
 // KX = K X, MX = M X on the union pattern (km holds (K, M) value pairs).
 void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, const double2* km,
-                    const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm);
+                    const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm, int variant = 0);
 // Y = A * B with A CSR (rows x ?) and B dense (row-major, ldb), ncols columns; Y(ldy).
 // accumulate: Y += instead of Y =.
 void launch_csr_dense(hipStream_t st, int rows, const int* ptr, const int* col, const double* val,
@@ -110,12 +110,12 @@ void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
-                            const long long* Loff, int* status, int* negflag);
+                            const long long* Loff, int* status, int* negflag, int threads = 256);
 void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
-                            const long long* Loff, int* status, int* negflag);
+                            const long long* Loff, int* status, int* negflag, int threads = 256);
 // Numeric local extraction: fixed-slot lower entries (offset, (K, M)) of every local row.
 void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr, const int* ldd, const int* lpos,
                           const double2* km, int* sd, double2* sv);
@@ -229,5 +229,8 @@ struct bpjd_problem {
     bpjd::HostPlan* plan = nullptr;    // host arrays between planning and materialisation
     hipGraphExec_t graph_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [buffer][P in W]
     bool graph_failed = false;         // capture unavailable: launch directly
+    bool tuned = false;                // launch shapes chosen (autotuner or fixed)
+    int ldlt_threads = 256;            // threads per system of the windowed local solver
+    int spmm_variant = 0;              // 0: two SpMM columns per lane where allowed, 1: one
     size_t footprint = 0;              // device bytes of the problem (allocation granularity included)
 };

@@ -312,19 +312,19 @@ __device__ inline void wave_sync();
 // accesses, not for its outstanding global loads and stores.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-constexpr int kLdltThreads = 256;   // four waves per system in the forward phase
+constexpr int kLdltMaxThreads = 256;   // up to four waves per system in the forward phase
 
 // Local LDL^T factor + solve for bands too wide for the blocked solver (or rows with more
-// than 8 lower entries): one workgroup of four waves per (subdomain, shift), the band
-// window of C = w + 1 rows in LDS as a circular buffer.  Step j scales column j and
-// updates the window: every thread takes a fixed chunk of the rows below the pivot, so
-// the step's work is spread over all four waves.  Wave 0 then puts row j + C into the
+// than 8 lower entries): one workgroup of one to four waves (the launch picks it) per
+// (subdomain, shift), the band window of C = w + 1 rows in LDS as a circular buffer.
+// Step j scales column j and updates the window: every thread takes fixed chunks of the
+// rows below the pivot, so the step's work is spread over all waves.  Wave 0 then puts row j + C into the
 // freed slot and copies column j + 1 out for the next step.  The entering rows come from
 // the fixed-slot arrays (band offset, (K, M) pair) and are loaded a block of RB rows at a
 // time, one block ahead, one slot per lane.  The backward sweep (wave 0) reads the stored
 // factor columns D steps ahead in a register ring.
 template <typename T>
-__global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
+__global__ __launch_bounds__(kLdltMaxThreads) void local_ldlt_kernel(
     int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
     const double2* __restrict__ sv, const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF,
     T* __restrict__ zloc, T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status) {
@@ -348,6 +348,7 @@ __global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
     const T* f = Floc + (long long)i * ldF + off;
     T* z = zloc + (long long)i * ldF + off;
     const int tid = threadIdx.x;
+    const int nthr = blockDim.x;    // 64, 128 or 256
     const int lane = tid & 63;
     const bool wave0 = tid < 64;    // entering rows, column copies and the backward sweep
     // entering rows in blocks of RB rows, lane = (row d of the block, slot e); EP = slots
@@ -369,13 +370,17 @@ __global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
         df = f[min(r, nl - 1)];
     };
     // this thread's share of each step's window update: the rows j + a, a = 1..w, go in
-    // pairs (q + 1, w - q), q < ceil(w/2), of w + 1 entries together, and each pair is cut
-    // into S chunks of Lch consecutive entries; thread (q, h) updates chunk h of pair q
+    // pairs (q + 1, w - q), q < ceil(w/2) <= 96, of w + 1 entries together, and each pair
+    // is cut into S chunks of Lch consecutive entries.  Item (q, h) = chunk h of pair q;
+    // there are npair * S <= max(nthr, npair) < 2 nthr items, so a thread has at most two:
+    // tid and tid + nthr.
     const int npair = (w + 1) / 2;
-    const int S = max(1, kLdltThreads / npair);
+    const int S = max(1, nthr / npair);
     const int Lch = (w + S) / S;
-    const int pq = tid / S, ph = tid - pq * S;
-    const int a1 = pq + 1, a2 = w - pq;
+    const int nitem = npair * S;
+    const int pq0 = tid / S, ph0 = tid - pq0 * S;
+    const int it1 = tid + nthr;
+    const int pq1 = it1 / S, ph1 = it1 - pq1 * S;
     auto copy_column = [&](const int jn) {   // column jn of the window into cwin (wave 0)
         const int sn = jn % C;
         for (int b = lane; b < C; b += 64) {
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
     int bad = 0;
     // forward phase; a negative pivot (indefinite local matrix) runs it again with shift 0
     for (int attempt = 0;; ++attempt) {
-        for (int e = tid; e < C * C + 2 * C; e += kLdltThreads) win[e] = T(0);
+        for (int e = tid; e < C * C + 2 * C; e += nthr) win[e] = T(0);
         __syncthreads();
         int bstart = C;
         if (wave0) {
@@ -449,17 +454,20 @@ __global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
                 ywin[ra] -= lsc * yj;
                 Lc[(long long)j * C + a] = lsc;
             };
-            if (pq < npair) {
+            auto update_item = [&](const int q, const int h) {
+                const int a1 = q + 1, a2 = w - q;
                 const int n1 = (j + a1 < nl) ? a1 : 0;                     // entries of row j + a1
                 const int n2 = (a2 != a1 && j + a2 < nl) ? a2 : 0;         // and of row j + a2
-                const int lo = ph * Lch, hi = min(lo + Lch, n1 + n2);      // this chunk: [lo, hi)
+                const int lo = h * Lch, hi = min(lo + Lch, n1 + n2);       // this chunk: [lo, hi)
                 if (lo < min(hi, n1)) update_range(a1, lo + 1, min(hi, n1));
                 if (hi > max(lo, n1)) update_range(a2, max(lo, n1) - n1 + 1, hi - n1);
-                if (ph == 0) {
+                if (h == 0) {
                     if (n1) finish_row(a1);
                     if (n2) finish_row(a2);
                 }
-            }
+            };
+            if (tid < nitem) update_item(pq0, ph0);
+            if (it1 < nitem) update_item(pq1, ph1);
             if (tid == 0) {
                 Lc[(long long)j * C] = dj;
                 z[j] = yj * inv;
@@ -492,7 +500,7 @@ __global__ __launch_bounds__(kLdltThreads) void local_ldlt_kernel(
         if (attempt > 0 || !neg) break;    // every thread reads the same pivots
         shift = 0.0;
     }
-    for (int e = tid; e < C; e += kLdltThreads) zwin[e] = T(0);     // it held column values
+    for (int e = tid; e < C; e += nthr) zwin[e] = T(0);     // it held column values
     __syncthreads();    // the stored factor and forward values are complete before they are read back
     if (!wave0) return;
     // backward sweep with the unit upper factor L^T; the columns of steps j - 1 .. j - D
@@ -1057,36 +1065,38 @@ static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s,
 template <typename T>
 static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long sumN, const int* subptr, const int* bw,
                          int E, const int* sd, const double2* sv, const double* lam, const T* Floc, T* zloc,
-                         T* Lwork, const long long* Loff, int* status) {
+                         T* Lwork, const long long* Loff, int* status, int threads) {
     const size_t shmem = (size_t)(maxC * maxC + 2 * maxC) * sizeof(T);
-    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(kLdltThreads), shmem, st, s, E, subptr, bw, sd, sv, lam, Floc,
+    hipLaunchKernelGGL(local_ldlt_kernel<T>, dim3(nsub * s), dim3(threads), shmem, st, s, E, subptr, bw, sd, sv, lam, Floc,
                        sumN, zloc, Lwork, Loff, status);
 }
 
 void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv, const double* lam, const double* Floc, double* zloc, double* Lwork,
-                            const long long* Loff, int* status, int* negflag) {
+                            const long long* Loff, int* status, int* negflag, int threads) {
     if (blocked) {
         launch_local_mfma<double>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff,
                                status, negflag);
         return;
     }
     if (mode == 0)   // the windowed solver takes its second pass inside the kernel
-        launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+        launch_local<double>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
+                             threads);
 }
 
 void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv, const double* lam, const float* Floc, float* zloc, float* Lwork,
-                            const long long* Loff, int* status, int* negflag) {
+                            const long long* Loff, int* status, int* negflag, int threads) {
     if (blocked) {
         launch_local_mfma<float>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff,
                                status, negflag);
         return;
     }
     if (mode == 0)   // the windowed solver takes its second pass inside the kernel
-        launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status);
+        launch_local<float>(st, nsub, s, maxC, sumN, subptr, bw, E, sd, sv, lam, Floc, zloc, Lwork, Loff, status,
+                            threads);
 }
 
 // ---------------------------------------------------------------------------

@@ -214,3 +214,29 @@ def test_plate_c4_fp64_window_does_not_fit(B, ctx):
     with pytest.raises(B.BPJDError) as e:
         _problem(B, ctx, pl, cfg, B.PREC_FP64)
     assert e.value.code == B.ERR_DD
+
+
+def test_autotune_keeps_results_and_records_choices(B, ctx, tmp_path, monkeypatch):
+    """The autotuner only picks launch shapes that leave the arithmetic unchanged (threads
+    per system of the windowed local solver, one or two SpMM columns per lane): a solve
+    with tuning equals, bit for bit, one with the fixed choices; the chosen shapes are
+    appended to the cache file, keyed by the problem's shape."""
+    _case("autotune b32 s=10")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("BPJD_TUNE_CACHE", str(cache))
+    pl, cfg = w.config_plate("b32")
+    kw = dict(k=cfg["k"], guard=4, precision=B.PREC_MIXED)    # s = 10: a shape no other test tunes
+    tuned = B.Problem(ctx, pl.K, pl.M, dd=(pl.P, pl.subs), autotune=True, **kw)
+    lam1, X1, st1 = tuned.solve()
+    tuned.close()
+    fixed = B.Problem(ctx, pl.K, pl.M, dd=(pl.P, pl.subs), autotune=False, **kw)
+    lam0, X0, st0 = fixed.solve()
+    fixed.close()
+    assert st1["iterations"] == st0["iterations"]
+    assert np.array_equal(lam1, lam0) and np.array_equal(X1, X0)
+    rows = [line.rsplit(" ", 1) for line in cache.read_text().splitlines() if line.strip()]
+    print("  " + "; ".join(f"{k} -> {v}" for k, v in rows), flush=True)
+    ldlt = [int(v) for k, v in rows if k.startswith("ldlt f32 s10 ")]
+    spmm = [int(v) for k, v in rows if k.startswith(f"spmm n{pl.n} ") and k.endswith(" c10")]
+    assert len(ldlt) == 1 and ldlt[0] in (64, 128, 256)
+    assert len(spmm) == 1 and spmm[0] in (0, 1)
