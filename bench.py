@@ -198,7 +198,7 @@ def _wait(srv, ids, done_at=None):
     return out
 
 
-def serving_bench(B, ctx, reqs, meshes, budget: int, slots: int, rate_frac: float = 0.7):
+def serving_bench(B, ctx, reqs, meshes, budget: int, slots: int, rate_frac: float = 0.7, log_path=None):
     """The served mix three ways: plain FP64 solves one request at a time (host CSR in,
     eigenpairs in host memory), the mixed-precision server with every request
     submitted at once (saturated throughput mu), and the server under Poisson
@@ -208,8 +208,7 @@ def serving_bench(B, ctx, reqs, meshes, budget: int, slots: int, rate_frac: floa
     # (i) plain FP64, one request at a time
     t0 = time.perf_counter()
     plain = []
-    log = open(os.path.join(ROOT, "gpurun_out", "served_plain_fp64.tsv"), "w") if os.path.isdir(
-        os.path.join(ROOT, "gpurun_out")) else None
+    log = open(log_path, "w") if log_path else None     # per-request times of this leg
     for j, (r, mesh) in enumerate(zip(reqs, meshes)):
         ts = time.perf_counter()
         prob = B.problem_from_mesh(ctx, mesh, r["L"], k=r["k"], guard=r["guard"], precision=B.PREC_FP64)
@@ -324,11 +323,12 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="only the served-mix measurement")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of the server")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-log", default=None, help="file for per-request times of the plain FP64 serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: multi-GPU runs are not part of this build (use --gpus 1)",
+        print("bench.py measures one GPU: multi-GPU execution is not implemented (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -356,7 +356,7 @@ def main():
             sys.exit(2)
         ctx = B.Context(0)
         serving = serving_bench(B, ctx, served[0], served[1], int(args.serve_budget_gb * (1 << 30)),
-                                args.serve_slots)
+                                args.serve_slots, log_path=args.serve_log)
         print(json.dumps({"metric": METRIC, "n_gpus": 1, "data": "synthetic", "serving": serving}), flush=True)
         ctx.close()
         return
@@ -470,7 +470,7 @@ def main():
     serving = None
     if served is not None:
         serving = serving_bench(B, ctx, served[0], served[1], int(args.serve_budget_gb * (1 << 30)),
-                                args.serve_slots)
+                                args.serve_slots, log_path=args.serve_log)
 
     cpu = None
     if not args.no_cpu_baseline:
