@@ -240,3 +240,47 @@ def test_autotune_keeps_results_and_records_choices(B, ctx, tmp_path, monkeypatc
     spmm = [int(v) for k, v in rows if k.startswith(f"spmm n{pl.n} ") and k.endswith(" c10")]
     assert len(ldlt) == 1 and ldlt[0] in (64, 128, 256)
     assert len(spmm) == 1 and spmm[0] in (0, 1)
+
+
+def _wait_all(srv, ids, timeout_s=120.0):
+    import time
+    out = {}
+    t0 = time.perf_counter()
+    while len(out) < len(ids):
+        for i in ids:
+            if i not in out:
+                r = srv.poll(i)
+                if r is not None:
+                    out[i] = r
+        if time.perf_counter() - t0 > timeout_s:
+            raise TimeoutError(f"{len(ids) - len(out)} requests still pending")
+        time.sleep(0.001)
+    return out
+
+
+def test_served_plate_requests_equal_alone(B, ctx):
+    """Fourth-order requests through the server (the caller's coarse space and local sets)
+    beside a second-order one: each served result equals the same request solved alone."""
+    _case("serving plates beside a P1 request")
+    plates = [w.config_plate(name) for name in ("b16", "b32", "b64")]
+    mesh, cfg1 = w.config_mesh("t64")
+    alone = []
+    for pl, cfg in plates:
+        prob = _problem(B, ctx, pl, cfg, B.PREC_MIXED)
+        alone.append(prob.solve())
+        prob.close()
+    prob = B.problem_from_mesh(ctx, mesh, cfg1["L"], k=cfg1["k"], guard=cfg1["guard"])
+    alone.append(prob.solve())
+    prob.close()
+    srv = B.Server(ctx, hbm_budget_bytes=0, max_slots=4)
+    ids = [srv.submit(pl.K, pl.M, dd=(pl.P, pl.subs), k=cfg["k"], guard=cfg["guard"]) for pl, cfg in plates]
+    ids.append(srv.submit_mesh(mesh, cfg1["L"], k=cfg1["k"], guard=cfg1["guard"]))
+    res = _wait_all(srv, ids)
+    info = srv.info()
+    srv.close()
+    assert info["completed"] == len(ids) and info["failed"] == 0
+    for (lam_a, X_a, st_a), rid in zip(alone, ids):
+        lam_s, X_s, st_s = res[rid]
+        np.testing.assert_allclose(lam_s, lam_a, rtol=1e-12, atol=0)
+        assert np.abs(X_s - X_a).max() <= 1e-10 * np.abs(X_a).max()
+        assert st_s["converged"] and st_s["iterations"] == st_a["iterations"]
