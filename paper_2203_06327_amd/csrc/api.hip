@@ -461,26 +461,41 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
         if (PTptr[a + 1] == PTptr[a]) return fail(BPJD_ERR_DD, "coarse basis function with empty support");
     std::vector<int> kpptr(n + 1, 0), kpcol;
     std::vector<int> tmp;
+    // distinct columns are collected with a last-seen marker per coarse dof, then sorted
+    // (a row of K P has a few dozen; gathering and sorting all the repeats was the bulk of
+    // the host planning for elements with many dofs per vertex)
+    std::vector<int> mark(nH, -1);
     for (int i = 0; i < n; ++i) {
         tmp.clear();
         for (int q = U.ptr[i]; q < U.ptr[i + 1]; ++q) {
             const int j = U.col[q];
-            for (int r = P.ptr[j]; r < P.ptr[j + 1]; ++r) tmp.push_back(P.col[r]);
+            for (int r = P.ptr[j]; r < P.ptr[j + 1]; ++r) {
+                const int c = P.col[r];
+                if (mark[c] != i) {
+                    mark[c] = i;
+                    tmp.push_back(c);
+                }
+            }
         }
         std::sort(tmp.begin(), tmp.end());
-        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
         kpcol.insert(kpcol.end(), tmp.begin(), tmp.end());
         kpptr[i + 1] = (int)kpcol.size();
     }
+    std::fill(mark.begin(), mark.end(), -1);
     std::vector<int> khptr(nH + 1, 0), khcol;
     for (int a = 0; a < nH; ++a) {
         tmp.clear();
         for (int q = PTptr[a]; q < PTptr[a + 1]; ++q) {
             const int i = PTcol[q];
-            tmp.insert(tmp.end(), kpcol.begin() + kpptr[i], kpcol.begin() + kpptr[i + 1]);
+            for (int t = kpptr[i]; t < kpptr[i + 1]; ++t) {
+                const int c = kpcol[t];
+                if (mark[c] != a) {
+                    mark[c] = a;
+                    tmp.push_back(c);
+                }
+            }
         }
         std::sort(tmp.begin(), tmp.end());
-        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
         khcol.insert(khcol.end(), tmp.begin(), tmp.end());
         khptr[a + 1] = (int)khcol.size();
     }
