@@ -185,6 +185,11 @@ void bpjd_ctx_destroy(bpjd_ctx* ctx);
  * pattern, subdomain maps, local band layout, coarse pattern) on the host
  * and uploads it together with the matrix values.  Device memory for the
  * whole solve is allocated here; bpjd_solve allocates nothing.
+ * Local solver limits (half-bandwidth w in the subdomain's ascending dof order):
+ * w <= 191 and at most 64 lower entries per local row; the windowed solver used
+ * above w = 80 (or above 8 lower entries) keeps (w+1)^2 + 2(w+1) entries of the
+ * solve precision in one workgroup's LDS (160 KB on MI355X: FP64 up to w = 141,
+ * FP32 up to 191).  Beyond these the call returns BPJD_ERR_DD before any launch.
  * Errors: BPJD_ERR_ARG, _CSR, _DD, _OOM, _HIP. */
 int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M,
                         const bpjd_dd* dd, const bpjd_opts* opts, bpjd_problem** out);
