@@ -163,19 +163,15 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
 
 
-def _request_mesh(req):
-    from paper_2203_06327_amd import workloads as w
-    return w.request_mesh(req)
-
-
 def build_served_meshes(count: int, workers: int = 8):
-    """Meshes of the served mix (assembled on the host in worker processes started
-    before the GPU is touched)."""
-    import multiprocessing as mp
+    """Meshes of the served mix, assembled on the host by a pool of threads of this
+    process (no child process is ever started, so a profiler's preloaded library
+    never sees a fork)."""
+    from concurrent.futures import ThreadPoolExecutor
     from paper_2203_06327_amd import workloads as w
     reqs = w.serving_requests(count)
-    with mp.get_context("spawn").Pool(workers) as pool:
-        meshes = pool.map(_request_mesh, reqs, chunksize=1)
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        meshes = list(pool.map(w.request_mesh, reqs))
     return reqs, meshes
 
 

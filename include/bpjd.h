@@ -71,7 +71,7 @@ extern "C" {
 #define BPJD_PREC_MIXED  1      /* local factor/solve in FP32; residual, projection, coarse solve, RR in FP64 */
 
 /* largest block size s = k + guard (the Rayleigh-Ritz problem has dimension <= 3 s) */
-#define BPJD_MAX_BLOCK   18
+#define BPJD_MAX_BLOCK   20
 
 typedef struct bpjd_ctx bpjd_ctx;
 typedef struct bpjd_problem bpjd_problem;
@@ -97,19 +97,26 @@ typedef struct {
     const int32_t* sub_idx;
 } bpjd_dd;
 
-/* Structured decomposition for P1 on a rectangle whose fine mesh refines a
- * coarse grid of lines cx[0..n_cx) x cy[0..n_cy) (each coarse cell cut by its
- * "/" diagonal, like the fine cells).  The library builds P (nodal
- * interpolation of the coarse P1 hat functions at the dof coordinates) and
- * the subdomains: closed coarse cell + (overlap_layers - 1) graph layers of
- * the union pattern of K and M, i.e. overlap delta = overlap_layers * h.
- * All arrays: host. */
+/* Structured decomposition for P1 on a domain made of cells of a coarse grid
+ * of lines cx[0..n_cx) x cy[0..n_cy) (each coarse cell cut by its "/"
+ * diagonal, like the fine cells), whose fine mesh refines that grid: a
+ * rectangle, or a union of coarse cells such as the L-shaped domain of
+ * Section 6.  The library builds P (nodal interpolation of the coarse P1 hat
+ * functions at the dof coordinates; a coarse vertex has a hat function when a
+ * dof sits on it) and the subdomains Omega_l of Section 2.3: each closed coarse
+ * cell, or each closed coarse triangle (cell_shape), grown by
+ * (overlap_layers - 1) graph layers of the union pattern of K and M, i.e.
+ * overlap delta = overlap_layers * h; cells or triangles holding no dof are
+ * skipped.  All arrays: host. */
+#define BPJD_CELL_SQUARE    0   /* Omega_l = a coarse cell (two coarse triangles) */
+#define BPJD_CELL_TRIANGLE  1   /* Omega_l = a coarse triangle (the coarse elements, as in Section 6) */
 typedef struct {
     const double* coords;       /* n x 2, row-major (x, y) of each dof */
     int32_t n_cx, n_cy;
     const double* cx;
     const double* cy;
     int32_t overlap_layers;     /* >= 1 */
+    int32_t cell_shape;         /* BPJD_CELL_SQUARE or BPJD_CELL_TRIANGLE */
 } bpjd_dd_geom;
 
 typedef struct {
@@ -221,8 +228,14 @@ int bpjd_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int32_t mem, b
 /* ---- stage entry points (one piece of an outer iteration each) ---------- */
 /* Two-level preconditioner (eq. Preconditioner) applied to the residual
  * block of (X, lambda): with F = M X diag(lambda) - K X,
- *   Z_i = P (B_0,i)^{-1} Q^H_{s+1} Q^H r_i + sum_l R_l^T (K_l - lambda_i M_l)^{-1} R_l F_i.
- * Needs the coarse eigenbasis: call bpjd_setup first (bpjd_solve does).
+ *   Z_i = P (B_0,i)^{-1} Q^H_{s+1} Q^H r_i + sum_l R_l^T (K_l - sigma_{l,i} M_l)^{-1} R_l F_i,
+ * where sigma_{l,i} = lambda_i whenever K_l - lambda_i M_l is positive definite
+ * (the local solvability the analysis of Section 3 rests on: the lowest local
+ * eigenvalue is of order H^{-2m}, far above lambda_i), and sigma_{l,i} = 0 on a
+ * subdomain where it is not (the LDL^T factorisation met a negative pivot:
+ * a strong coefficient contrast put a local Dirichlet eigenvalue below
+ * lambda_i); there the local solve is K_l^{-1}, a positive definite Schwarz
+ * solve.  Needs the coarse eigenbasis: call bpjd_setup first (bpjd_solve does).
  * X, Z: n x s row-major; lambda: s values.  All three in `mem`. */
 int bpjd_setup(bpjd_problem* p);
 int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* lambda,

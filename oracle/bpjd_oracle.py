@@ -60,12 +60,22 @@ def coarse_prolongation(coords: np.ndarray, cx: np.ndarray, cy: np.ndarray) -> s
     The coarse mesh is the grid of lines cx x cy with every coarse cell cut
     by its "/" diagonal (the same triangulation rule as the fine mesh, so
     V^H is a subspace of V^h when coarse cells are unions of fine cells
-    along the diagonal).  Column (B-1)(ncx-1)+(A-1) is the hat function of
-    interior coarse vertex (A, B).
+    along the diagonal).  A coarse vertex carries a basis function of V^H when
+    a fine dof sits on it (the free vertices of the coarse mesh: on a
+    rectangle every interior one, on the L-shaped domain those off the
+    re-entrant edges and the removed quadrant).  Columns follow the coarse
+    vertices row by row (x fastest).
     """
     n = coords.shape[0]
     ncx, ncy = len(cx) - 1, len(cy) - 1
     x, y = coords[:, 0], coords[:, 1]
+    tol = 1e-9 * min(np.min(np.diff(cx)), np.min(np.diff(cy)))
+    # free coarse vertices: coincide with a fine dof
+    col_of = {}
+    for B in range(1, ncy):
+        for A in range(1, ncx):
+            if np.any((np.abs(x - cx[A]) <= tol) & (np.abs(y - cy[B]) <= tol)):
+                col_of[(A, B)] = len(col_of)
     a = np.clip(np.searchsorted(cx, x, side="right") - 1, 0, ncx - 1)
     b = np.clip(np.searchsorted(cy, y, side="right") - 1, 0, ncy - 1)
     xi = (x - cx[a]) / (cx[a + 1] - cx[a])
@@ -77,26 +87,32 @@ def coarse_prolongation(coords: np.ndarray, cx: np.ndarray, cy: np.ndarray) -> s
             verts = [(A, B, 1.0 - xi[d]), (A + 1, B, xi[d] - eta[d]), (A + 1, B + 1, eta[d])]
         else:                    # upper-left triangle (A,B),(A+1,B+1),(A,B+1)
             verts = [(A, B, 1.0 - eta[d]), (A + 1, B + 1, xi[d]), (A, B + 1, eta[d] - xi[d])]
-        for (VA, VB, w) in verts:
-            if 1 <= VA <= ncx - 1 and 1 <= VB <= ncy - 1 and w != 0.0:
+        for (VA, VB, wv) in verts:
+            c = col_of.get((VA, VB))
+            if c is not None and wv != 0.0:
                 rows.append(d)
-                cols.append((VB - 1) * (ncx - 1) + (VA - 1))
-                vals.append(w)
-    nH = (ncx - 1) * (ncy - 1)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(n, nH))
+                cols.append(c)
+                vals.append(wv)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, len(col_of)))
 
 
-def subdomain_sets(coords, cx, cy, K, M, layers: int) -> list:
+def subdomain_sets(coords, cx, cy, K, M, layers: int, shape: str = "square") -> list:
     """Local dof sets of the overlapping subdomains Omega'_l.
 
-    Omega_l is a closed coarse cell; it is enlarged by ``layers`` layers of
-    fine elements (every element touching the current region is added).  The
-    dofs of V^(l) are those interior to the enlarged region: the dofs of the
-    closed cell plus those within graph distance layers-1 of them in the
-    element adjacency graph (the union pattern of K and M).
+    Omega_l is a closed coarse cell (shape "square"), or one of the two closed
+    coarse triangles a coarse cell is cut into by its "/" diagonal (shape
+    "triangle": the coarse elements themselves, as in the experiments of
+    Section 6); it is enlarged by ``layers`` layers of fine elements (every
+    element touching the current region is added).  The dofs of V^(l) are those
+    interior to the enlarged region: the dofs of the closed cell plus those
+    within graph distance layers-1 of them in the element adjacency graph (the
+    union pattern of K and M).  Triangles are listed cell by cell, the lower-right
+    one (below the diagonal) first.
     """
     if layers < 1:
         raise ValueError("overlap must be at least one element layer")
+    if shape not in ("square", "triangle"):
+        raise ValueError(shape)
     adj = (abs(K) + abs(M)).tocsr()
     adj = (adj != 0).astype(np.int8)
     x, y = coords[:, 0], coords[:, 1]
@@ -105,18 +121,25 @@ def subdomain_sets(coords, cx, cy, K, M, layers: int) -> list:
     for B in range(len(cy) - 1):
         for A in range(len(cx) - 1):
             inside = (x >= cx[A] - tol) & (x <= cx[A + 1] + tol) & (y >= cy[B] - tol) & (y <= cy[B + 1] + tol)
-            mask = inside.astype(np.int8)
-            for _ in range(layers - 1):
-                mask = ((adj @ mask) > 0).astype(np.int8) | mask
-            idx = np.flatnonzero(mask)
-            if idx.size:
-                subs.append(idx.astype(np.int64))
+            if shape == "square":
+                parts = [inside]
+            else:
+                # position along the cell's diagonal: xi - eta >= 0 below it, <= 0 above
+                d = (x - cx[A]) / (cx[A + 1] - cx[A]) - (y - cy[B]) / (cy[B + 1] - cy[B])
+                parts = [inside & (d >= -1e-9), inside & (d <= 1e-9)]
+            for part in parts:
+                mask = part.astype(np.int8)
+                for _ in range(layers - 1):
+                    mask = ((adj @ mask) > 0).astype(np.int8) | mask
+                idx = np.flatnonzero(mask)
+                if idx.size:
+                    subs.append(idx.astype(np.int64))
     return subs
 
 
-def build_dd(mesh, layers: int) -> DD:
+def build_dd(mesh, layers: int, shape: str = "square") -> DD:
     P = coarse_prolongation(mesh.coords, mesh.cx, mesh.cy)
-    subs = subdomain_sets(mesh.coords, mesh.cx, mesh.cy, mesh.K, mesh.M, layers)
+    subs = subdomain_sets(mesh.coords, mesh.cx, mesh.cy, mesh.K, mesh.M, layers, shape)
     return DD(P=P, subs=subs)
 
 

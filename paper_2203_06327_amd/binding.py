@@ -23,6 +23,7 @@ ERR_ARG, ERR_CSR, ERR_DD, ERR_NOT_SPD, ERR_NOCONV, ERR_OOM, ERR_HIP, ERR_OVER_BU
     -1, -2, -3, -4, -5, -6, -7, -8, -9
 MEM_HOST, MEM_DEVICE = 0, 1
 STOP_RESIDUAL, STOP_PAPER = 0, 1
+CELL_SQUARE, CELL_TRIANGLE = 0, 1
 SUBSPACE_UU, SUBSPACE_U = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 
@@ -48,7 +49,8 @@ class DD(C.Structure):
 
 class DDGeom(C.Structure):
     _fields_ = [("coords", C.c_void_p), ("n_cx", C.c_int32), ("n_cy", C.c_int32),
-                ("cx", C.c_void_p), ("cy", C.c_void_p), ("overlap_layers", C.c_int32)]
+                ("cx", C.c_void_p), ("cy", C.c_void_p), ("overlap_layers", C.c_int32),
+                ("cell_shape", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -149,6 +151,17 @@ def _ptr(a) -> int:
     return a.ctypes.data
 
 
+def _geom(geom, keep: list) -> DDGeom:
+    """(coords, cx, cy, layers[, cell_shape]) -> bpjd_dd_geom (host arrays kept alive in keep)."""
+    coords, cx, cy, layers = geom[:4]
+    shape = geom[4] if len(geom) > 4 else CELL_SQUARE
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cx = np.ascontiguousarray(cx, dtype=np.float64)
+    cy = np.ascontiguousarray(cy, dtype=np.float64)
+    keep += [coords, cx, cy]
+    return DDGeom(coords.ctypes.data, len(cx), len(cy), cx.ctypes.data, cy.ctypes.data, int(layers), int(shape))
+
+
 @dataclass
 class _Keep:
     arrays: list
@@ -212,12 +225,7 @@ class Problem:
                          autotune)
         h = C.c_void_p()
         if geom is not None:
-            coords, cx, cy, layers = geom
-            coords = np.ascontiguousarray(coords, dtype=np.float64)
-            cx = np.ascontiguousarray(cx, dtype=np.float64)
-            cy = np.ascontiguousarray(cy, dtype=np.float64)
-            keep += [coords, cx, cy]
-            g = DDGeom(coords.ctypes.data, len(cx), len(cy), cx.ctypes.data, cy.ctypes.data, int(layers))
+            g = _geom(geom, keep)
             _check(lib().bpjd_problem_create_geom(ctx.handle, C.byref(Kc), C.byref(Mc), C.byref(g), C.byref(opts),
                                                   C.byref(h)))
         elif dd is not None:
@@ -298,9 +306,10 @@ class Problem:
         return out
 
 
-def problem_from_mesh(ctx: Context, mesh, layers: int, **kw) -> Problem:
-    """Problem on a structured P1 mesh (coarse grid lines and coordinates from the mesh)."""
-    return Problem(ctx, mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers), **kw)
+def problem_from_mesh(ctx: Context, mesh, layers: int, shape: int = CELL_SQUARE, **kw) -> Problem:
+    """Problem on a structured P1 mesh (coarse grid lines and coordinates from the mesh);
+    shape: subdomains are coarse cells (CELL_SQUARE) or coarse triangles (CELL_TRIANGLE)."""
+    return Problem(ctx, mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers, shape), **kw)
 
 
 class Server:
@@ -325,12 +334,7 @@ class Server:
         opts = make_opts(k, guard, tol, max_iter, stop_rule, subspace, precision, X_init, keep, 0)
         rid = C.c_uint64()
         if geom is not None:
-            coords, cx, cy, layers = geom
-            coords = np.ascontiguousarray(coords, dtype=np.float64)
-            cx = np.ascontiguousarray(cx, dtype=np.float64)
-            cy = np.ascontiguousarray(cy, dtype=np.float64)
-            keep += [coords, cx, cy]
-            g = DDGeom(coords.ctypes.data, len(cx), len(cy), cx.ctypes.data, cy.ctypes.data, int(layers))
+            g = _geom(geom, keep)
             _check(lib().bpjd_server_submit(self.handle, C.byref(Kc), C.byref(Mc), None, C.byref(g),
                                             C.byref(opts), C.byref(rid)))
         elif dd is not None:
@@ -348,8 +352,8 @@ class Server:
         self._shape[rid.value] = (K.shape[0], k)
         return rid.value
 
-    def submit_mesh(self, mesh, layers: int, **kw) -> int:
-        return self.submit(mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers), **kw)
+    def submit_mesh(self, mesh, layers: int, shape: int = CELL_SQUARE, **kw) -> int:
+        return self.submit(mesh.K, mesh.M, geom=(mesh.coords, mesh.cx, mesh.cy, layers, shape), **kw)
 
     def poll(self, req_id: int, raise_noconv: bool = True):
         n, k = self._shape.get(req_id, (0, 0))      # an unknown id is the library's error

@@ -120,11 +120,32 @@ static int build_union(const HostCSR& K, const HostCSR& M, Pattern& U) {
 
 // ---- structured P1 decomposition ----------------------------------------------
 // Coarse P1 on the grid cx x cy, each coarse cell cut by its "/" diagonal;
-// nodal interpolation at the dof coordinates (same rule as the fine mesh).
+// nodal interpolation at the dof coordinates (same rule as the fine mesh).  A
+// coarse vertex carries a coarse basis function when a fine dof sits on it (on a
+// rectangle every interior coarse vertex; on a domain with fixed inner edges, such
+// as the L-shape, only the free ones), numbered row by row, x fastest.
 static void build_p1_prolongation(int n, const double* xy, const std::vector<double>& cx,
                                   const std::vector<double>& cy, HostCSR& P, int& nH) {
     const int ncx = (int)cx.size() - 1, ncy = (int)cy.size() - 1;
-    nH = (ncx - 1) * (ncy - 1);
+    double hmin = 1e300;
+    for (int i = 0; i < ncx; ++i) hmin = std::min(hmin, cx[i + 1] - cx[i]);
+    for (int i = 0; i < ncy; ++i) hmin = std::min(hmin, cy[i + 1] - cy[i]);
+    const double tol = 1e-9 * hmin;
+    // free coarse vertices: a fine dof lies on the vertex
+    std::vector<int> vnum((size_t)(ncx + 1) * (ncy + 1), -1);
+    std::vector<char> hit((size_t)(ncx + 1) * (ncy + 1), 0);
+    for (int d = 0; d < n; ++d) {
+        const double x = xy[2 * d], y = xy[2 * d + 1];
+        const int a = (int)(std::lower_bound(cx.begin(), cx.end(), x - tol) - cx.begin());
+        const int b = (int)(std::lower_bound(cy.begin(), cy.end(), y - tol) - cy.begin());
+        if (a >= 1 && a <= ncx - 1 && b >= 1 && b <= ncy - 1 && std::fabs(cx[a] - x) <= tol &&
+            std::fabs(cy[b] - y) <= tol)
+            hit[(size_t)b * (ncx + 1) + a] = 1;
+    }
+    nH = 0;
+    for (int b = 1; b < ncy; ++b)
+        for (int a = 1; a < ncx; ++a)
+            if (hit[(size_t)b * (ncx + 1) + a]) vnum[(size_t)b * (ncx + 1) + a] = nH++;
     P.n = n;
     P.ptr.assign(n + 1, 0);
     P.col.clear();
@@ -150,8 +171,8 @@ static void build_p1_prolongation(int n, const double* xy, const std::vector<dou
         }
         std::vector<std::pair<int, double>> ent;
         for (int k = 0; k < 3; ++k) {
-            if (va[k] >= 1 && va[k] <= ncx - 1 && vb[k] >= 1 && vb[k] <= ncy - 1 && w[k] != 0.0)
-                ent.push_back({(vb[k] - 1) * (ncx - 1) + (va[k] - 1), w[k]});
+            const int c = vnum[(size_t)vb[k] * (ncx + 1) + va[k]];
+            if (c >= 0 && w[k] != 0.0) ent.push_back({c, w[k]});
         }
         std::sort(ent.begin(), ent.end());
         for (auto& e : ent) {
@@ -162,19 +183,24 @@ static void build_p1_prolongation(int n, const double* xy, const std::vector<dou
     }
 }
 
-// Closed coarse cell plus (layers - 1) graph layers of the union pattern.
+// Subdomains: each closed coarse cell (cell_shape BPJD_CELL_SQUARE), or each of the
+// two closed coarse triangles a cell is cut into by its "/" diagonal
+// (BPJD_CELL_TRIANGLE, the lower-right one first), plus (layers - 1) graph layers of
+// the union pattern.  Cells or triangles that hold no dof are skipped.
 static int build_geom_subdomains(const Pattern& U, const double* xy, const std::vector<double>& cx,
-                                 const std::vector<double>& cy, int layers, std::vector<int>& sptr,
+                                 const std::vector<double>& cy, int layers, int shape, std::vector<int>& sptr,
                                  std::vector<int>& sidx) {
     if (layers < 1) return fail(BPJD_ERR_ARG, "overlap_layers must be >= 1");
+    if (shape != BPJD_CELL_SQUARE && shape != BPJD_CELL_TRIANGLE) return fail(BPJD_ERR_ARG, "unknown cell_shape");
     const int n = U.n;
     const int ncx = (int)cx.size() - 1, ncy = (int)cy.size() - 1;
+    const int parts = shape == BPJD_CELL_TRIANGLE ? 2 : 1;
     double hmin = 1e300;
     for (int i = 0; i < ncx; ++i) hmin = std::min(hmin, cx[i + 1] - cx[i]);
     for (int i = 0; i < ncy; ++i) hmin = std::min(hmin, cy[i + 1] - cy[i]);
     const double tol = 1e-9 * hmin;
     // closed-cell membership: each dof lies in at most two closed cells per axis
-    std::vector<std::vector<int>> cell(ncx * ncy);
+    std::vector<std::vector<int>> cell((size_t)ncx * ncy * parts);
     for (int d = 0; d < n; ++d) {
         const double x = xy[2 * d], y = xy[2 * d + 1];
         int a0 = (int)(std::upper_bound(cx.begin(), cx.end(), x) - cx.begin()) - 1;
@@ -183,24 +209,32 @@ static int build_geom_subdomains(const Pattern& U, const double* xy, const std::
             if (!(y >= cy[B] - tol && y <= cy[B + 1] + tol)) continue;
             for (int A = std::max(0, a0 - 1); A <= std::min(ncx - 1, a0 + 1); ++A) {
                 if (!(x >= cx[A] - tol && x <= cx[A + 1] + tol)) continue;
-                cell[B * ncx + A].push_back(d);
+                const size_t c = (size_t)B * ncx + A;
+                if (parts == 1) {
+                    cell[c].push_back(d);
+                } else {
+                    // side of the cell's diagonal: xi - eta >= 0 below it, <= 0 above it
+                    const double dg = (x - cx[A]) / (cx[A + 1] - cx[A]) - (y - cy[B]) / (cy[B + 1] - cy[B]);
+                    if (dg >= -1e-9) cell[2 * c].push_back(d);
+                    if (dg <= 1e-9) cell[2 * c + 1].push_back(d);
+                }
             }
         }
     }
     std::vector<int> mark(n, -1), frontier, next;
     sptr.assign(1, 0);
     sidx.clear();
-    for (int c = 0; c < ncx * ncy; ++c) {
+    for (size_t c = 0; c < cell.size(); ++c) {
         std::vector<int> members = cell[c];
-        for (int d : members) mark[d] = c;
+        for (int d : members) mark[d] = (int)c;
         frontier = members;
         for (int layer = 1; layer < layers; ++layer) {
             next.clear();
             for (int d : frontier) {
                 for (int q = U.ptr[d]; q < U.ptr[d + 1]; ++q) {
                     const int e = U.col[q];
-                    if (mark[e] != c) {
-                        mark[e] = c;
+                    if (mark[e] != (int)c) {
+                        mark[e] = (int)c;
                         members.push_back(e);
                         next.push_back(e);
                     }
@@ -1381,7 +1415,7 @@ static int plan_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const 
     build_p1_prolongation(U.n, g->coords, cx, cy, P, nH);
     if (nH < 1) return fail(BPJD_ERR_DD, "coarse grid has no interior vertex");
     std::vector<int> sptr, sidx;
-    BPJD_TRY(build_geom_subdomains(U, g->coords, cx, cy, g->overlap_layers, sptr, sidx));
+    BPJD_TRY(build_geom_subdomains(U, g->coords, cx, cy, g->overlap_layers, g->cell_shape, sptr, sidx));
     return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out);
 }
 

@@ -34,7 +34,7 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = [
-    "Mesh", "p1_mesh", "coarse_lines", "config_mesh", "CONFIGS",
+    "Mesh", "p1_mesh", "p1_lshape", "coarse_lines", "config_mesh", "CONFIGS",
     "block_coefficient", "seeded_block", "serving_requests",
     "Plate", "hermite_1d", "bfs_plate", "PLATE_CONFIGS", "config_plate",
 ]
@@ -87,6 +87,55 @@ def coarse_lines(L: float, N: int, cells_per_coarse: int) -> np.ndarray:
     return idx * (L / N)
 
 
+def _p1_assemble(x0: float, y0: float, hx: float, hy: float, Nx: int, Ny: int,
+                 node_is_dof: np.ndarray, cell_kept: np.ndarray,
+                 coef: Optional[Callable[[np.ndarray, np.ndarray], np.ndarray]] = None):
+    """P1 stiffness/mass of the kept cells of a uniform "/" grid.
+
+    Grid node (i, j), 0 <= i <= Nx, 0 <= j <= Ny, sits at (x0 + i hx, y0 + j hy);
+    ``node_is_dof[j, i]`` marks the free nodes (dofs numbered row by row, x
+    fastest), ``cell_kept[j, i]`` the cells of the domain.  Cell (i, j) is split
+    into T1 = {(i,j),(i+1,j),(i+1,j+1)} and T2 = {(i,j),(i+1,j+1),(i,j+1)}.
+    Returns (K, M, coords) with K, M on one (union) pattern.
+    """
+    dofnum = -np.ones((Ny + 1, Nx + 1), dtype=np.int64)
+    jj, ii = np.nonzero(node_is_dof)
+    dofnum[jj, ii] = np.arange(jj.size)
+    n = int(jj.size)
+    cj, ci = np.nonzero(cell_kept)
+    tri_i = np.concatenate([np.stack([ci, ci + 1, ci + 1], 1), np.stack([ci, ci + 1, ci], 1)])
+    tri_j = np.concatenate([np.stack([cj, cj, cj + 1], 1), np.stack([cj, cj + 1, cj + 1], 1)])
+    x = x0 + tri_i * hx
+    y = y0 + tri_j * hy
+    # gradients of the barycentric functions: grad phi_a = (y_b - y_c, x_c - x_b) / (2 area)
+    xa, xb, xc = x[:, 0], x[:, 1], x[:, 2]
+    ya, yb, yc = y[:, 0], y[:, 1], y[:, 2]
+    area2 = (xb - xa) * (yc - ya) - (xc - xa) * (yb - ya)
+    gx = np.stack([yb - yc, yc - ya, ya - yb], 1) / area2[:, None]
+    gy = np.stack([xc - xb, xa - xc, xb - xa], 1) / area2[:, None]
+    area = 0.5 * area2
+    if coef is None:
+        a = np.ones_like(area)
+    else:
+        a = np.asarray(coef(x.mean(1), y.mean(1)), dtype=np.float64)
+    Ke = a[:, None, None] * area[:, None, None] * (gx[:, :, None] * gx[:, None, :] + gy[:, :, None] * gy[:, None, :])
+    Me = (area / 12.0)[:, None, None] * (np.ones((3, 3)) + np.eye(3))[None]
+    d = dofnum[tri_j, tri_i]
+    rows = np.repeat(d, 3, axis=1).ravel()
+    cols = np.tile(d, (1, 3)).ravel()
+    keep = (rows >= 0) & (cols >= 0)
+    r, c = rows[keep], cols[keep]
+    # K and M come from the same (row, col) list, so coo->csr gives both the
+    # same (union) pattern; K's hypotenuse couplings stay as explicit zeros.
+    K = sp.coo_matrix((Ke.reshape(-1)[keep], (r, c)), shape=(n, n)).tocsr()
+    M = sp.coo_matrix((Me.reshape(-1)[keep], (r, c)), shape=(n, n)).tocsr()
+    K.sort_indices()
+    M.sort_indices()
+    assert np.array_equal(K.indptr, M.indptr) and np.array_equal(K.indices, M.indices)
+    coords = np.stack([x0 + ii * hx, y0 + jj * hy], 1).astype(np.float64)
+    return K, M, coords
+
+
 def p1_mesh(Lx: float, Ly: float, Nx: int, Ny: int, cells_per_coarse_x: int,
             cells_per_coarse_y: Optional[int] = None,
             coef: Optional[Callable[[np.ndarray, np.ndarray], np.ndarray]] = None) -> Mesh:
@@ -101,51 +150,35 @@ def p1_mesh(Lx: float, Ly: float, Nx: int, Ny: int, cells_per_coarse_x: int,
     if cells_per_coarse_y is None:
         cells_per_coarse_y = cells_per_coarse_x
     hx, hy = Lx / Nx, Ly / Ny
-    nxi, nyi = Nx - 1, Ny - 1
-    n = nxi * nyi
-
-    def dof(i, j):
-        inside = (i >= 1) & (i <= Nx - 1) & (j >= 1) & (j <= Ny - 1)
-        return np.where(inside, (j - 1) * nxi + (i - 1), -1)
-
-    ci, cj = np.meshgrid(np.arange(Nx), np.arange(Ny), indexing="xy")
-    ci = ci.ravel()
-    cj = cj.ravel()
-    # vertex index triples (i,j) for both triangle families
-    tri_i = np.concatenate([np.stack([ci, ci + 1, ci + 1], 1), np.stack([ci, ci + 1, ci], 1)])
-    tri_j = np.concatenate([np.stack([cj, cj, cj + 1], 1), np.stack([cj, cj + 1, cj + 1], 1)])
-    x = tri_i * hx
-    y = tri_j * hy
-    # gradients of the barycentric functions: grad phi_a = (y_b - y_c, x_c - x_b) / (2 area)
-    x0, x1, x2 = x[:, 0], x[:, 1], x[:, 2]
-    y0, y1, y2 = y[:, 0], y[:, 1], y[:, 2]
-    area2 = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)
-    gx = np.stack([y1 - y2, y2 - y0, y0 - y1], 1) / area2[:, None]
-    gy = np.stack([x2 - x1, x0 - x2, x1 - x0], 1) / area2[:, None]
-    area = 0.5 * area2
-    if coef is None:
-        a = np.ones_like(area)
-    else:
-        a = np.asarray(coef(x.mean(1), y.mean(1)), dtype=np.float64)
-    Ke = a[:, None, None] * area[:, None, None] * (gx[:, :, None] * gx[:, None, :] + gy[:, :, None] * gy[:, None, :])
-    Me = (area / 12.0)[:, None, None] * (np.ones((3, 3)) + np.eye(3))[None]
-    d = dof(tri_i, tri_j)
-    rows = np.repeat(d, 3, axis=1).ravel()
-    cols = np.tile(d, (1, 3)).ravel()
-    keep = (rows >= 0) & (cols >= 0)
-    r, c = rows[keep], cols[keep]
-    # K and M come from the same (row, col) list, so coo->csr gives both the
-    # same (union) pattern; K's hypotenuse couplings stay as explicit zeros.
-    K = sp.coo_matrix((Ke.reshape(-1)[keep], (r, c)), shape=(n, n)).tocsr()
-    M = sp.coo_matrix((Me.reshape(-1)[keep], (r, c)), shape=(n, n)).tocsr()
-    K.sort_indices()
-    M.sort_indices()
-    assert np.array_equal(K.indptr, M.indptr) and np.array_equal(K.indices, M.indices)
-    ii, jj = np.meshgrid(np.arange(1, Nx), np.arange(1, Ny), indexing="xy")
-    coords = np.stack([ii.ravel() * hx, jj.ravel() * hy], 1)
+    node = np.zeros((Ny + 1, Nx + 1), dtype=bool)
+    node[1:Ny, 1:Nx] = True
+    cells = np.ones((Ny, Nx), dtype=bool)
+    K, M, coords = _p1_assemble(0.0, 0.0, hx, hy, Nx, Ny, node, cells, coef)
     return Mesh(Lx, Ly, Nx, Ny, K, M, coords,
                 coarse_lines(Lx, Nx, cells_per_coarse_x),
                 coarse_lines(Ly, Ny, cells_per_coarse_y))
+
+
+def p1_lshape(N: int, cells_per_coarse: int) -> Mesh:
+    """P1 on the L-shaped domain (-pi,pi)^2 minus [0,pi) x (-pi,0] (Section 6,
+    Example 6.2), from the uniform "/" mesh of the square with N x N cells (N
+    even): the cells of the removed quadrant are dropped and every node on the
+    boundary of the L (outer edges and the two re-entrant edges) is fixed.  The
+    coarse grid lines split the square into coarse cells of ``cells_per_coarse``
+    fine cells; coarse cells of the removed quadrant hold no dof."""
+    if N % 2:
+        raise ValueError("N must be even")
+    h = 2.0 * np.pi / N
+    half = N // 2
+    node = np.zeros((N + 1, N + 1), dtype=bool)
+    node[1:N, 1:N] = True
+    node[0:half + 1, half:] = False          # x >= 0 and y <= 0: the removed quadrant, closed
+    cells = np.ones((N, N), dtype=bool)
+    cells[:half, half:] = False              # cells with x > 0, y < 0
+    K, M, coords = _p1_assemble(-np.pi, -np.pi, h, h, N, N, node, cells)
+    lines = coarse_lines(2.0 * np.pi, N, cells_per_coarse) - np.pi
+    return Mesh(2.0 * np.pi, 2.0 * np.pi, N, N, K, M, coords, lines, lines.copy(),
+                meta={"domain": "lshape"})
 
 
 def block_coefficient(Lx: float, Ly: float, values: np.ndarray):
@@ -196,11 +229,32 @@ CONFIGS = {
                 desc="rectangle [0,1]x[0,1.01], uneven last coarse row"),
 }
 
+# The experiments of Section 6 in 2-D (Examples 6.1 and 6.2): coarse triangles as
+# subdomains (shape "triangle"), delta/H = 1/4 in element layers, the paper's stop rule
+# sum_i |lambda_i^{k+1} - lambda_i^k| < 1e-10 on the eigenvalues of the stated domain.
+#   e1_*: (0,pi)^2, 16 x 16 coarse cells = 512 coarse triangles, s = 19 (Table 1)
+#   e2_*: L-shape (-pi,pi)^2 minus [0,pi) x (-pi,0], 384 coarse triangles, s = 20 (Table 3)
+for _N, _dofs in ((128, "16129"), (256, "65025"), (512, "261121"), (1024, "1046529")):
+    CONFIGS[f"e1_{_N}"] = dict(Lx=np.pi, Ly=np.pi, Nx=_N, Ny=_N, coarse=_N // 16, L=_N // 64, k=19, guard=0,
+                               seed_block=None, shape="triangle", stop="paper", tol=1e-10,
+                               table1_col=(128, 256, 512, 1024).index(_N),
+                               desc=(f"Example 6.1: Laplacian P1 (0,pi)^2, {_dofs} dofs, 512 coarse triangles, "
+                                     f"delta/H=1/4, s=19, stop sum|dlambda|<1e-10"))
+for _N, _dofs in ((128, "12033"), (256, "48641"), (512, "195585"), (1024, "784385")):
+    CONFIGS[f"e2_{_N}"] = dict(domain="lshape", Lx=2 * np.pi, Ly=2 * np.pi, Nx=_N, Ny=_N, coarse=_N // 16,
+                               L=_N // 64, k=20, guard=0, seed_block=None, shape="triangle", stop="paper",
+                               tol=1e-10, table3_col=(128, 256, 512, 1024).index(_N),
+                               desc=(f"Example 6.2: Laplacian P1 on the L-shape, {_dofs} dofs, 384 coarse "
+                                     f"triangles, delta/H=1/4, s=20, stop sum|dlambda|<1e-10"))
+
 
 def config_mesh(name: str) -> tuple[Mesh, dict]:
     """Build the mesh of a named workload; returns (mesh, config dict)."""
     cfg = dict(CONFIGS[name])
-    mesh = p1_mesh(cfg["Lx"], cfg["Ly"], cfg["Nx"], cfg["Ny"], cfg["coarse"])
+    if cfg.get("domain") == "lshape":
+        mesh = p1_lshape(cfg["Nx"], cfg["coarse"])
+    else:
+        mesh = p1_mesh(cfg["Lx"], cfg["Ly"], cfg["Nx"], cfg["Ny"], cfg["coarse"])
     return mesh, cfg
 
 

@@ -14,7 +14,11 @@ def pytest_configure(config):
 
 
 def load_table1():
-    path = os.path.join(ROOT, "tests", "golden", "table1.txt")
+    return load_golden_table("table1.txt")
+
+
+def load_golden_table(name):
+    path = os.path.join(ROOT, "tests", "golden", name)
     rows = []
     with open(path) as f:
         for line in f:
@@ -29,3 +33,8 @@ def load_table1():
 @pytest.fixture(scope="session")
 def table1():
     return load_table1()
+
+
+@pytest.fixture(scope="session")
+def table3():
+    return load_golden_table("table3.txt")
