@@ -88,7 +88,7 @@ def test_invalid_decomposition_and_options(B, ctx, t16):
     _case("DD: block size not below dim V^H")
     _expect(B, B.ERR_DD, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=dd.P.shape[1]))
     _case("options: k + guard above the largest block, bad tolerance, unknown precision")
-    _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=4, guard=15))
+    _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=4, guard=17))
     _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=2, tol=0.0))
     _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=2, precision=7))
 
