@@ -17,7 +17,8 @@
  * Conventions
  *   - every function returns an int status: BPJD_OK (0), BPJD_PENDING (>0)
  *     or a negative BPJD_ERR_* code; nothing throws across the ABI;
- *     bpjd_last_error() gives a human-readable detail for the calling thread.
+ *     bpjd_last_error(ctx) gives a human-readable detail of the last failed
+ *     call on a context, bpjd_last_error(NULL) that of the calling thread.
  *   - CSR matrices are 0-based, square, with sorted column indices and no
  *     duplicates; K and M store the full symmetric pattern.  K and M may have
  *     different patterns: the library works on their union.
@@ -30,6 +31,11 @@
  *     Handles are freed only by their *_destroy call.
  *   - all device work of a context is ordered on its HIP stream; a call
  *     that returns results in host memory synchronises that stream.
+ *   - device memory: every device byte the library holds comes from the
+ *     context's allocator (bpjd_allocator; the default is hipMalloc/hipFree),
+ *     obtained when a problem is created (or, for served requests, from the
+ *     server's block, obtained when the server is created); solving allocates
+ *     nothing.
  *   - one thread per problem; a context may be shared by several problems.
  */
 #ifndef BPJD_H
@@ -63,8 +69,10 @@ extern "C" {
 #define BPJD_STOP_PAPER     1   /* sum_{i<s} |lambda_i^{k+1} - lambda_i^k| < tol */
 
 /* subspace W^{k+1} (remark after Algorithm 3.1) */
-#define BPJD_SUBSPACE_UU  0     /* W^{k+1} = U^{k-1} + U^k + span{t_i}  (fixed dimension 3s) */
-#define BPJD_SUBSPACE_U   1     /* W^{k+1} = U^k + span{t_i}            (fixed dimension 2s) */
+#define BPJD_SUBSPACE_UU   0    /* W^{k+1} = U^{k-1} + U^k + span{t_i}  (fixed dimension 3s) */
+#define BPJD_SUBSPACE_U    1    /* W^{k+1} = U^k + span{t_i}            (fixed dimension 2s) */
+#define BPJD_SUBSPACE_GROW 2    /* W^{k+1} = W^k + span{t_i} (Algorithm 3.1, Step 3 as written:
+                                   dimension s (k+1) after k steps) */
 
 /* precision of the local subdomain factorisations and solves */
 #define BPJD_PREC_FP64   0      /* everything in FP64 */
@@ -175,6 +183,7 @@ typedef struct {
     int32_t phase_count[8];     /* launches timed per phase */
     double  queue_ms;           /* served requests: submission to admission (0 for bpjd_solve) */
     double  latency_ms;         /* served requests: submission to result in host memory */
+    int32_t graph_iterations;   /* outer iterations replayed from a captured HIP graph */
 } bpjd_stats;
 
 /* Default options: k as given, guard 0, max_iter 500, tol 1e-8, residual
@@ -182,9 +191,24 @@ typedef struct {
 void bpjd_opts_default(bpjd_opts* o, int32_t k);
 
 /* ---- context ----------------------------------------------------------- */
-/* device: HIP device ordinal.  hip_stream: a hipStream_t to order all work
- * on, or NULL for a stream the context creates (default priority). */
-int  bpjd_ctx_create(int device, void* hip_stream, bpjd_ctx** out);
+/* Device memory provider of a context (for instance a framework's caching
+ * allocator).  alloc(bytes, user) returns device memory of the context's GPU,
+ * at least 256-byte aligned, or NULL when it cannot; free(ptr, user) gives it
+ * back.  The library calls them from the thread that creates or destroys a
+ * problem or a server; it synchronises the context's stream before it frees,
+ * so no kernel still uses a block handed back. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void  (*free)(void* ptr, void* user);
+    void* user;
+} bpjd_allocator;
+
+/* device: HIP device ordinal.  allocator: NULL for hipMalloc/hipFree, else
+ * copied (its callbacks and user pointer must stay valid until
+ * bpjd_ctx_destroy).  hip_stream: a hipStream_t to order all work on, or NULL
+ * for a stream the context creates (default priority).
+ * Errors: BPJD_ERR_ARG (bad ordinal, an allocator with one callback), _HIP. */
+int  bpjd_ctx_create(int device, const bpjd_allocator* allocator, void* hip_stream, bpjd_ctx** out);
 void bpjd_ctx_destroy(bpjd_ctx* ctx);
 
 /* ---- problems ---------------------------------------------------------- */
@@ -291,7 +315,11 @@ void bpjd_server_destroy(bpjd_server* s);
 
 /* ---- errors ------------------------------------------------------------ */
 const char* bpjd_strerror(int code);
-const char* bpjd_last_error(void);
+/* ctx != NULL: the message of the last failed call made on that context (on
+ * its problems or its server) from any thread; NULL: the last failure of the
+ * calling thread.  The text is copied into storage of the calling thread and
+ * stays valid until that thread's next call of bpjd_last_error. */
+const char* bpjd_last_error(const bpjd_ctx* ctx);
 
 #ifdef __cplusplus
 }

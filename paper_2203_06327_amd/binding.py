@@ -24,7 +24,7 @@ ERR_ARG, ERR_CSR, ERR_DD, ERR_NOT_SPD, ERR_NOCONV, ERR_OOM, ERR_HIP, ERR_OVER_BU
 MEM_HOST, MEM_DEVICE = 0, 1
 STOP_RESIDUAL, STOP_PAPER = 0, 1
 CELL_SQUARE, CELL_TRIANGLE = 0, 1
-SUBSPACE_UU, SUBSPACE_U = 0, 1
+SUBSPACE_UU, SUBSPACE_U, SUBSPACE_GROW = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -66,7 +66,7 @@ class Stats(C.Structure):
                 ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("max_local", C.c_int32),
                 ("max_band", C.c_int32), ("residuals", C.c_double * 64),
                 ("phase_ms", C.c_double * 8), ("phase_count", C.c_int32 * 8),
-                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("graph_iterations", C.c_int32)]
 
     def to_dict(self) -> dict:
         arrays = ("residuals", "phase_ms", "phase_count")
@@ -93,7 +93,7 @@ _lib = None
 
 EXPORTS = {
     "bpjd_opts_default": (None, [C.POINTER(Opts), C.c_int32]),
-    "bpjd_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "bpjd_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "bpjd_ctx_destroy": (None, [C.c_void_p]),
     "bpjd_problem_create": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.POINTER(Csr), C.POINTER(DD), C.POINTER(Opts),
                                       C.POINTER(C.c_void_p)]),
@@ -117,7 +117,7 @@ EXPORTS = {
     "bpjd_server_get_info": (C.c_int, [C.c_void_p, C.POINTER(ServerInfo)]),
     "bpjd_server_destroy": (None, [C.c_void_p]),
     "bpjd_strerror": (C.c_char_p, [C.c_int]),
-    "bpjd_last_error": (C.c_char_p, []),
+    "bpjd_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
 
@@ -139,7 +139,7 @@ def lib():
 def _check(code: int):
     if code < 0:
         L = lib()
-        raise BPJDError(code, f"{L.bpjd_strerror(code).decode()}: {L.bpjd_last_error().decode()}")
+        raise BPJDError(code, f"{L.bpjd_strerror(code).decode()}: {L.bpjd_last_error(None).decode()}")
     return code
 
 
@@ -167,11 +167,71 @@ class _Keep:
     arrays: list
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory of a context from PyTorch's caching allocator, on the context's
+    stream (a torch stream made for it).  Counts calls and bytes, so a test can see
+    every device byte the library holds."""
+
+    def __init__(self, device: int):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+        self.live = {}                  # ptr -> bytes
+        self.allocs = self.frees = 0
+        self.bytes_allocated = 0
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._free = FREE_FN(self._on_free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+    def _on_alloc(self, nbytes, user):
+        try:
+            ptr = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:
+            return None
+        self.live[ptr] = int(nbytes)
+        self.allocs += 1
+        self.bytes_allocated += int(nbytes)
+        return ptr
+
+    def _on_free(self, ptr, user):
+        self.live.pop(ptr, None)
+        self.frees += 1
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+
 class Context:
-    def __init__(self, device: int = 0, stream: Optional[int] = None):
+    """A device, a stream and a device-memory provider (bpjd_ctx).  allocator: None
+    (hipMalloc) or "torch" (PyTorch's caching allocator on a torch stream)."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None, allocator: Optional[str] = None):
         h = C.c_void_p()
-        _check(lib().bpjd_ctx_create(device, stream, C.byref(h)))
+        self.allocator = None
+        al = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator(device)
+            al = C.byref(self.allocator.struct)
+            if stream is None:
+                stream = self.allocator.stream.cuda_stream
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
+        _check(lib().bpjd_ctx_create(device, al, stream, C.byref(h)))
         self.handle = h
+
+    def last_error(self) -> str:
+        return lib().bpjd_last_error(self.handle).decode()
 
     def close(self):
         if self.handle:

@@ -23,17 +23,110 @@
 namespace bpjd {
 
 static thread_local std::string g_last_error;
+static thread_local bpjd_ctx* g_scope_ctx = nullptr;   // context of the ABI call in progress
+static thread_local std::string g_error_copy;          // bpjd_last_error(ctx) storage
 
 // largest half-bandwidth and lower entries per row handled by the blocked (MFMA) local solver
 static constexpr int kBlockedMaxBand = 48;       // 64-row window (4 tile-rows)
 static constexpr int kBlockedWideMaxBand = 80;   // 96-row window (6 tile-rows)
 static constexpr int kBlockedMaxSlots = 8;
 
-void set_error(const std::string& msg) { g_last_error = msg; }
+void set_error(const std::string& msg) {
+    g_last_error = msg;
+    if (bpjd_ctx* c = g_scope_ctx) {
+        std::lock_guard<std::mutex> g(c->err_mu);
+        c->last_error = msg;
+    }
+}
 
 int fail(int code, const std::string& msg) {
-    g_last_error = msg;
+    set_error(msg);
     return code;
+}
+
+CtxScope::CtxScope(bpjd_ctx* c) : prev(g_scope_ctx) { g_scope_ctx = c; }
+CtxScope::~CtxScope() { g_scope_ctx = prev; }
+
+// ---- device memory ----------------------------------------------------------------
+void* DevArena::alloc(size_t bytes) {
+    const size_t b = round(bytes);
+    std::lock_guard<std::mutex> g(mu);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < b) continue;
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > b) free_[off + b] = len - b;
+        return base + off;
+    }
+    return nullptr;
+}
+
+void DevArena::release(void* ptr, size_t bytes) {
+    const size_t b = round(bytes);
+    size_t off = (size_t)((char*)ptr - base), len = b;
+    std::lock_guard<std::mutex> g(mu);
+    auto next = free_.lower_bound(off);
+    if (next != free_.begin()) {                      // merge with the free block before
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+            off = prev->first;
+            len += prev->second;
+            free_.erase(prev);
+        }
+    }
+    if (next != free_.end() && off + len == next->first) {   // and the one after
+        len += next->second;
+        free_.erase(next);
+    }
+    free_[off] = len;
+}
+
+bool DevArena::alloc_all(const std::vector<size_t>& sizes, std::vector<void*>& out) {
+    std::lock_guard<std::mutex> g(mu);
+    std::map<size_t, size_t> f = free_;
+    std::vector<void*> got;
+    got.reserve(sizes.size());
+    for (size_t bytes : sizes) {
+        const size_t b = round(bytes);
+        bool placed = false;
+        for (auto it = f.begin(); it != f.end(); ++it) {
+            if (it->second < b) continue;
+            const size_t off = it->first, len = it->second;
+            f.erase(it);
+            if (len > b) f[off + b] = len - b;
+            got.push_back(base + off);
+            placed = true;
+            break;
+        }
+        if (!placed) return false;
+    }
+    free_.swap(f);
+    out.swap(got);
+    return true;
+}
+
+// A device block for problem p: from the server's block (a served problem), the
+// context's allocator, or hipMalloc.
+static void* dev_alloc(bpjd_problem* p, size_t bytes, int* route) {
+    bpjd_ctx* c = p->ctx;
+    if (c->arena) {          // blocks reserved at admission, handed out in allocation order
+        *route = 2;
+        return p->reserved_next < p->reserved.size() ? p->reserved[p->reserved_next++] : nullptr;
+    }
+    if (c->alloc.alloc) {
+        *route = 1;
+        return c->alloc.alloc(bytes, c->alloc.user);
+    }
+    *route = 0;
+    void* d = nullptr;
+    return hipMalloc(&d, bytes) == hipSuccess ? d : nullptr;
+}
+
+static void dev_free(bpjd_problem* p, const DevBlock& b) {
+    bpjd_ctx* c = p->ctx;
+    if (b.route == 2) c->arena->release(b.ptr, b.bytes);
+    else if (b.route == 1) c->alloc.free(b.ptr, c->alloc.user);
+    else (void)hipFree(b.ptr);
 }
 
 struct HostCSR {
@@ -42,14 +135,15 @@ struct HostCSR {
     std::vector<double> val;
 };
 
-static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out) {
+static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out, hipStream_t st) {
     if (!A || !A->rowptr || !A->col || !A->val) return fail(BPJD_ERR_ARG, std::string(name) + ": NULL array");
     if (A->n_rows <= 0 || A->n_rows != A->n_cols) return fail(BPJD_ERR_CSR, std::string(name) + ": not square");
     const int n = A->n_rows;
     out.n = n;
     out.ptr.resize(n + 1);
     if (A->mem == BPJD_MEM_DEVICE) {
-        BPJD_HIP(hipMemcpy(out.ptr.data(), A->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+        BPJD_HIP(hipMemcpyAsync(out.ptr.data(), A->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipStreamSynchronize(st));
     } else {
         std::memcpy(out.ptr.data(), A->rowptr, sizeof(int) * (n + 1));
     }
@@ -60,8 +154,9 @@ static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out) {
     out.col.resize(A->nnz);
     out.val.resize(A->nnz);
     if (A->mem == BPJD_MEM_DEVICE) {
-        BPJD_HIP(hipMemcpy(out.col.data(), A->col, sizeof(int) * A->nnz, hipMemcpyDeviceToHost));
-        BPJD_HIP(hipMemcpy(out.val.data(), A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost));
+        BPJD_HIP(hipMemcpyAsync(out.col.data(), A->col, sizeof(int) * A->nnz, hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipMemcpyAsync(out.val.data(), A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, st));
+        BPJD_HIP(hipStreamSynchronize(st));
     } else {
         std::memcpy(out.col.data(), A->col, sizeof(int) * A->nnz);
         std::memcpy(out.val.data(), A->val, sizeof(double) * A->nnz);
@@ -251,11 +346,17 @@ static int build_geom_subdomains(const Pattern& U, const double* xy, const std::
 }
 
 static int upload(bpjd_problem* p, void** dst, const void* src, size_t bytes) {
-    void* d = nullptr;
     if (bytes == 0) bytes = 8;
-    if (hipMalloc(&d, bytes) != hipSuccess) return fail(BPJD_ERR_OOM, "device allocation failed");
-    p->allocations.push_back(d);
-    if (src) BPJD_HIP(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+    int route = 0;
+    void* d = dev_alloc(p, bytes, &route);
+    if (!d) {
+        (void)hipGetLastError();
+        return fail(BPJD_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    p->allocations.push_back(DevBlock{d, bytes, route});
+    // on the problem's own stream (never the legacy stream, which would wait for, or be
+    // refused by, another stream's capture); materialize_problem synchronises it
+    if (src) BPJD_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, p->ctx->stream));
     *dst = d;
     return BPJD_OK;
 }
@@ -619,16 +720,38 @@ int materialize_problem(bpjd_problem* p) {
     int rc = device_layout(p, *p->plan, [&](void** dst, const void* src, size_t b) {
         return upload(p, dst, src, b);
     });
-    if (rc == BPJD_OK && hipHostMalloc((void**)&p->hbuf, 4096 * sizeof(double)) != hipSuccess)
-        rc = fail(BPJD_ERR_OOM, "pinned host allocation failed");
+    // the plan's host arrays are the sources of the copies just enqueued
+    if (hipStreamSynchronize(p->ctx->stream) != hipSuccess && rc == BPJD_OK)
+        rc = fail(BPJD_ERR_HIP, "upload of the problem's structure failed");
+    if (rc == BPJD_OK) {
+        if (p->ctx->hbuf) {
+            p->hbuf = p->ctx->hbuf;           // a server slot's read-back buffer
+        } else if (hipHostMalloc((void**)&p->hbuf, 4096 * sizeof(double)) != hipSuccess) {
+            p->hbuf = nullptr;
+            rc = fail(BPJD_ERR_OOM, "pinned host allocation failed");
+        } else {
+            p->own_hbuf = true;
+        }
+    }
     delete p->plan;
     p->plan = nullptr;
     return rc;
 }
 
-static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR& hM, Pattern& U) {
-    BPJD_TRY(read_csr(K, "K", hK));
-    BPJD_TRY(read_csr(M, "M", hM));
+// Sizes of the device blocks a planned problem will allocate, in allocation order.
+std::vector<size_t> planned_blocks(bpjd_problem* p) {
+    std::vector<size_t> out;
+    if (!p->plan) return out;
+    device_layout(p, *p->plan, [&](void**, const void*, size_t b) {
+        out.push_back(b ? b : 8);
+        return BPJD_OK;
+    });
+    return out;
+}
+
+static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR& hM, Pattern& U, hipStream_t st) {
+    BPJD_TRY(read_csr(K, "K", hK, st));
+    BPJD_TRY(read_csr(M, "M", hM, st));
     if (hK.n != hM.n) return fail(BPJD_ERR_CSR, "K and M differ in size");
     return build_union(hK, hM, U);
 }
@@ -870,6 +993,7 @@ struct SolveRun {
     int np = 0;         // columns of P in use (0 or s)
     int it = 0;         // outer iteration whose residual is being read back
     int iters = 0;
+    int graph_iters = 0;    // iterations launched as a graph replay
     bool converged = false;
     bool fresh = false; // the residual being read back comes from K X, M X formed from X itself
     double stop_value = NAN;
@@ -1197,6 +1321,7 @@ static int advance_iter(SolveRun* r) {
     const bool graph = p->opts.graphs && !r->T && !p->trace && !p->graph_failed;
     r->fresh = false;
     if (graph && launch_iteration_graph(r, a, r->np)) {
+        r->graph_iters++;
         r->cur = 1 - a;
         r->np = uu ? s : 0;
         r->iters = ++r->it;
@@ -1279,6 +1404,7 @@ int run_finish(SolveRun* r, double* eigvals, double* eigvecs, int mem, bpjd_stat
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = r->iters;
+        stats->graph_iterations = r->graph_iters;
         stats->converged = r->converged ? 1 : 0;
         stats->stop_value = r->stop_value;
         double rmax = 0.0;
@@ -1339,14 +1465,17 @@ void bpjd_opts_default(bpjd_opts* o, int32_t k) {
     o->autotune = 1;
 }
 
-int bpjd_ctx_create(int device, void* hip_stream, bpjd_ctx** out) {
+int bpjd_ctx_create(int device, const bpjd_allocator* allocator, void* hip_stream, bpjd_ctx** out) {
     if (!out) return fail(BPJD_ERR_ARG, "out is NULL");
+    if (allocator && (!allocator->alloc) != (!allocator->free))
+        return fail(BPJD_ERR_ARG, "allocator needs both alloc and free (or neither)");
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(BPJD_ERR_HIP, "no HIP device");
     if (device < 0 || device >= count) return fail(BPJD_ERR_ARG, "device ordinal out of range");
     BPJD_HIP(hipSetDevice(device));
     bpjd_ctx* c = new bpjd_ctx();
     c->device = device;
+    if (allocator) c->alloc = *allocator;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
         c->own_stream = false;
@@ -1375,7 +1504,7 @@ static int plan_dd(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bp
                    const bpjd_opts* opts, bpjd_problem** out) {
     HostCSR hK, hM, P;
     Pattern U;
-    BPJD_TRY(read_pair(K, M, hK, hM, U));
+    BPJD_TRY(read_pair(K, M, hK, hM, U, ctx->stream));
     if (dd->P.n_rows != U.n || dd->P.n_cols < 1) return fail(BPJD_ERR_DD, "P must be n x n_H");
     {
         // P is rectangular: read it without the square check
@@ -1384,7 +1513,7 @@ static int plan_dd(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bp
         Pc.n_cols = Pc.n_rows;
         HostCSR tmp;
         // reuse the reader for bounds/order checks against n_rows, then re-check columns against n_H
-        int rc = read_csr(&Pc, "P", tmp);
+        int rc = read_csr(&Pc, "P", tmp, ctx->stream);
         if (rc < 0 && rc != BPJD_ERR_CSR) return rc;
         if (rc == BPJD_ERR_CSR) return fail(BPJD_ERR_DD, "P: " + std::string(g_last_error));
         for (int c : tmp.col)
@@ -1405,7 +1534,7 @@ static int plan_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const 
     if (!g->coords || !g->cx || !g->cy || g->n_cx < 2 || g->n_cy < 2) return fail(BPJD_ERR_ARG, "bad coarse grid");
     HostCSR hK, hM, P;
     Pattern U;
-    BPJD_TRY(read_pair(K, M, hK, hM, U));
+    BPJD_TRY(read_pair(K, M, hK, hM, U, ctx->stream));
     std::vector<double> cx(g->cx, g->cx + g->n_cx), cy(g->cy, g->cy + g->n_cy);
     for (size_t i = 0; i + 1 < cx.size(); ++i)
         if (!(cx[i + 1] > cx[i])) return fail(BPJD_ERR_ARG, "cx not increasing");
@@ -1446,12 +1575,14 @@ extern "C" {
 
 int bpjd_problem_create(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
                         const bpjd_opts* opts, bpjd_problem** out) {
+    CtxScope cs_(ctx);
     if (!ctx || !K || !M || !dd || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
     return create_now(ctx, K, M, dd, nullptr, opts, out);
 }
 
 int bpjd_problem_create_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd_geom* g,
                              const bpjd_opts* opts, bpjd_problem** out) {
+    CtxScope cs_(ctx);
     if (!ctx || !K || !M || !g || !opts || !out) return fail(BPJD_ERR_ARG, "NULL argument");
     return create_now(ctx, K, M, nullptr, g, opts, out);
 }
@@ -1462,17 +1593,25 @@ void bpjd_problem_destroy(bpjd_problem* p) {
     for (auto& row : p->graph_exec)
         for (hipGraphExec_t ge : row)
             if (ge) (void)hipGraphExecDestroy(ge);
-    for (void* d : p->allocations) (void)hipFree(d);
-    if (p->hbuf) (void)hipHostFree(p->hbuf);
+    // no kernel of this problem may still use a block handed back (an allocator or the
+    // server's block may give it out again at once)
+    if (!p->allocations.empty()) (void)hipStreamSynchronize(p->ctx->stream);
+    for (const DevBlock& b : p->allocations) dev_free(p, b);
+    if (p->ctx && p->ctx->arena)            // reserved blocks never handed out
+        for (size_t q = p->reserved_next; q < p->reserved.size(); ++q)
+            p->ctx->arena->release(p->reserved[q], p->reserved_bytes[q]);
+    if (p->hbuf && p->own_hbuf) (void)hipHostFree(p->hbuf);
     delete p;
 }
 
 int bpjd_problem_set_values(bpjd_problem* p, const double* Kval, const double* Mval, int32_t mem) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p || !Kval || !Mval) return fail(BPJD_ERR_ARG, "NULL argument");
     std::vector<double> kv(p->nnzK), mv(p->nnzM);
     if (mem == BPJD_MEM_DEVICE) {
-        BPJD_HIP(hipMemcpy(kv.data(), Kval, sizeof(double) * p->nnzK, hipMemcpyDeviceToHost));
-        BPJD_HIP(hipMemcpy(mv.data(), Mval, sizeof(double) * p->nnzM, hipMemcpyDeviceToHost));
+        BPJD_HIP(hipMemcpyAsync(kv.data(), Kval, sizeof(double) * p->nnzK, hipMemcpyDeviceToHost, p->ctx->stream));
+        BPJD_HIP(hipMemcpyAsync(mv.data(), Mval, sizeof(double) * p->nnzM, hipMemcpyDeviceToHost, p->ctx->stream));
+        BPJD_HIP(hipStreamSynchronize(p->ctx->stream));
     } else {
         std::memcpy(kv.data(), Kval, sizeof(double) * p->nnzK);
         std::memcpy(mv.data(), Mval, sizeof(double) * p->nnzM);
@@ -1480,12 +1619,14 @@ int bpjd_problem_set_values(bpjd_problem* p, const double* Kval, const double* M
     std::vector<double2> km(p->nnz, make_double2(0.0, 0.0));
     for (long long q = 0; q < p->nnzK; ++q) km[p->Kmap[q]].x = kv[q];
     for (long long q = 0; q < p->nnzM; ++q) km[p->Mmap[q]].y = mv[q];
-    BPJD_HIP(hipMemcpy(p->km, km.data(), sizeof(double2) * p->nnz, hipMemcpyHostToDevice));
+    BPJD_HIP(hipMemcpyAsync(p->km, km.data(), sizeof(double2) * p->nnz, hipMemcpyHostToDevice, p->ctx->stream));
+    BPJD_HIP(hipStreamSynchronize(p->ctx->stream));
     p->setup_done = false;
     return BPJD_OK;
 }
 
 int bpjd_problem_dims(const bpjd_problem* p, int32_t* n, int32_t* n_coarse, int32_t* n_sub, int32_t* s) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p) return fail(BPJD_ERR_ARG, "NULL problem");
     if (n) *n = p->n;
     if (n_coarse) *n_coarse = p->nH;
@@ -1495,12 +1636,14 @@ int bpjd_problem_dims(const bpjd_problem* p, int32_t* n, int32_t* n_coarse, int3
 }
 
 int bpjd_problem_footprint(const bpjd_problem* p, uint64_t* bytes) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p || !bytes) return fail(BPJD_ERR_ARG, "NULL argument");
     *bytes = p->footprint;
     return BPJD_OK;
 }
 
 int bpjd_problem_local_sizes(const bpjd_problem* p, int32_t* n_l, int32_t* bw) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p || !n_l || !bw) return fail(BPJD_ERR_ARG, "NULL argument");
     for (int l = 0; l < p->nsub; ++l) {
         n_l[l] = p->h_nl[l];
@@ -1510,17 +1653,20 @@ int bpjd_problem_local_sizes(const bpjd_problem* p, int32_t* n_l, int32_t* bw) {
 }
 
 int bpjd_solve(bpjd_problem* p, double* eigvals, double* eigvecs, int32_t mem, bpjd_stats* st) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p) return fail(BPJD_ERR_ARG, "NULL problem");
     if (mem != BPJD_MEM_HOST && mem != BPJD_MEM_DEVICE) return fail(BPJD_ERR_ARG, "bad mem");
     return run_solve(p, eigvals, eigvecs, mem, st);
 }
 
 int bpjd_setup(bpjd_problem* p) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p) return fail(BPJD_ERR_ARG, "NULL problem");
     return run_setup(p);
 }
 
 int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* lambda, double* Z, int32_t mem) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p || !X || !lambda || !Z) return fail(BPJD_ERR_ARG, "NULL argument");
     if (!p->setup_done) return fail(BPJD_ERR_STATE, "call bpjd_setup first");
     hipStream_t st = p->ctx->stream;
@@ -1541,6 +1687,7 @@ int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* la
 }
 
 int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, double* MX, int32_t mem) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p || !X || !KX || !MX) return fail(BPJD_ERR_ARG, "NULL argument");
     if (ncols < 1 || ncols > 3 * p->s) return fail(BPJD_ERR_ARG, "ncols must be in [1, 3s]");
     hipStream_t st = p->ctx->stream;
@@ -1562,6 +1709,7 @@ int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, doubl
 }
 
 int bpjd_coarse_eigenvalues(bpjd_problem* p, double* lamH, int32_t mem) {
+    CtxScope cs_(p ? p->ctx : nullptr);
     if (!p || !lamH) return fail(BPJD_ERR_ARG, "NULL argument");
     if (!p->setup_done) return fail(BPJD_ERR_STATE, "call bpjd_setup first");
     const hipMemcpyKind k = mem == BPJD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1587,6 +1735,12 @@ const char* bpjd_strerror(int code) {
     }
 }
 
-const char* bpjd_last_error(void) { return g_last_error.c_str(); }
+const char* bpjd_last_error(const bpjd_ctx* ctx) {
+    if (!ctx) return g_last_error.c_str();
+    bpjd_ctx* c = const_cast<bpjd_ctx*>(ctx);
+    std::lock_guard<std::mutex> g(c->err_mu);
+    g_error_copy = c->last_error;
+    return g_error_copy.c_str();
+}
 
 }  // extern "C"

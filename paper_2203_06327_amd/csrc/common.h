@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,8 +16,36 @@
 namespace bpjd {
 
 // ---- error plumbing ---------------------------------------------------------
+// fail()/set_error() record the message for the calling thread and, while an ABI call
+// on a context is in progress on this thread (CtxScope), for that context as well.
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
+struct CtxScope {
+    explicit CtxScope(bpjd_ctx* c);
+    ~CtxScope();
+    bpjd_ctx* prev;
+};
+
+// ---- device memory -----------------------------------------------------------
+// Sub-allocator over one device block (a server's HBM budget): first fit over an
+// address-ordered free list with coalescing, 4096-byte granularity.  Thread-safe.
+struct DevArena {
+    std::mutex mu;
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;    // offset -> length
+    static size_t round(size_t b) { return (std::max<size_t>(b, 8) + 4095) & ~size_t(4095); }
+    void* alloc(size_t bytes);
+    void release(void* p, size_t bytes);
+    // places blocks of all these sizes at once (first fit, in order), or none of them
+    bool alloc_all(const std::vector<size_t>& sizes, std::vector<void*>& out);
+};
+// one device block of a problem and how it was obtained
+struct DevBlock {
+    void* ptr;
+    size_t bytes;
+    int route;                          // 0 hipMalloc, 1 the context's allocator, 2 the arena
+};
 
 #define BPJD_HIP(call)                                                                 \
     do {                                                                               \
@@ -156,6 +186,8 @@ int plan_problem(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd
                  const bpjd_opts* opts, bpjd_problem** out);
 // Allocate and upload a planned problem (on p->ctx's device).
 int materialize_problem(bpjd_problem* p);
+// Sizes of the device blocks materialize_problem will allocate for a planned problem.
+std::vector<size_t> planned_blocks(bpjd_problem* p);
 // One solve as a sequence of stages, each ending in a read-back event.
 struct SolveRun;
 int  run_create(bpjd_problem* p, SolveRun** out);
@@ -173,6 +205,11 @@ struct bpjd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bpjd_allocator alloc{};            // alloc.alloc == NULL: hipMalloc / hipFree
+    bpjd::DevArena* arena = nullptr;   // a server's slot: device memory comes from the server's block
+    double* hbuf = nullptr;            // a server's slot: its pinned read-back buffer (owned by the server)
+    std::mutex err_mu;
+    std::string last_error;            // message of the last failed ABI call on this context
 };
 
 struct bpjd_problem {
@@ -225,7 +262,11 @@ struct bpjd_problem {
     bool trace = false;
     std::vector<int> h_nl, h_bw;     // host copies of subdomain sizes / half-bandwidths
     bool setup_done = false;
-    std::vector<void*> allocations;
+    std::vector<bpjd::DevBlock> allocations;
+    std::vector<void*> reserved;       // served problem: its blocks, placed in the server's block at admission
+    std::vector<size_t> reserved_bytes;
+    size_t reserved_next = 0;          // next reserved block to hand out
+    bool own_hbuf = false;
     bpjd::HostPlan* plan = nullptr;    // host arrays between planning and materialisation
     hipGraphExec_t graph_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [buffer][P in W]
     bool graph_failed = false;         // capture unavailable: launch directly

@@ -29,6 +29,7 @@
 #include <deque>
 #include <mutex>
 #include <thread>
+#include <memory>
 #include <unordered_map>
 
 #include "common.h"
@@ -92,7 +93,9 @@ struct bpjd_server {
     bpjd_ctx* ctx = nullptr;                 // caller's context: device
     size_t budget = 0;
     int max_slots = 0;
-    std::vector<bpjd_ctx> slot_ctx;          // one non-blocking stream per slot
+    std::vector<std::unique_ptr<bpjd_ctx>> slot_ctx;   // one non-blocking stream per slot
+    bpjd::DevArena arena;                    // the whole budget, one device block, sub-allocated
+    int arena_route = 0;                     // how the block was obtained: 0 hipMalloc, 1 the allocator
     std::vector<char> slot_busy;
 
     std::mutex mu;
@@ -142,7 +145,7 @@ void plan_loop(bpjd_server* s) {
         bpjd_problem* p = nullptr;
         int rc = bpjd::plan_problem(s->ctx, &r->K, &r->M, r->use_geom ? nullptr : &r->dd,
                                     r->use_geom ? &r->geom : nullptr, &r->opts, &p);
-        std::string err = rc < 0 ? bpjd_last_error() : "";
+        std::string err = rc < 0 ? bpjd_last_error(nullptr) : "";
         if (rc == BPJD_OK && p->footprint > s->budget) {
             rc = BPJD_ERR_OVER_BUDGET;
             err = "request needs " + std::to_string(p->footprint) + " device bytes, budget is " +
@@ -190,16 +193,20 @@ void admit_loop(bpjd_server* s) {
             s->cv_plan.notify_one();
             continue;
         }
-        // wait for a free slot and room in the budget
+        // wait for a free slot and room in the budget: the footprint fits the bytes left, and
+        // the blocks fit the server's block as it is now (first fit, so fragmentation can
+        // delay a request; with nothing running the whole block is free and it fits)
         int slot = -1;
+        const std::vector<size_t> blocks = bpjd::planned_blocks(p);
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_admit.wait(lk, [&] {
                 if (s->stopping) return true;
                 if (s->in_use + p->footprint > s->budget) return false;
-                for (int q = 0; q < s->max_slots; ++q)
-                    if (!s->slot_busy[q]) return true;
-                return false;
+                bool slot_free = false;
+                for (int q = 0; q < s->max_slots; ++q) slot_free = slot_free || !s->slot_busy[q];
+                // last: reserves the blocks when everything else allows admission
+                return slot_free && s->arena.alloc_all(blocks, p->reserved);
             });
             if (s->stopping) return;        // the request (and its plan) is freed by destroy
             for (int q = 0; q < s->max_slots && slot < 0; ++q)
@@ -214,16 +221,17 @@ void admit_loop(bpjd_server* s) {
             r->state = Request::RUNNING;
             r->t_admit = Clock::now();
         }
+        p->reserved_bytes = blocks;
         r->slot = slot;
         r->footprint = p->footprint;
         r->p = p;
-        p->ctx = &s->slot_ctx[slot];
+        p->ctx = s->slot_ctx[slot].get();
         rc = bpjd::materialize_problem(p);
         if (rc == BPJD_OK) rc = bpjd::run_create(p, &r->run);
         if (rc == BPJD_OK) rc = bpjd::run_begin(r->run);
         std::lock_guard<std::mutex> lk(s->mu);
         if (rc < 0) {
-            r->err = bpjd_last_error();
+            r->err = bpjd_last_error(nullptr);
             r->rc = rc;
             s->finished.push_back(r);   // the reaper frees what was allocated
             s->cv_reap.notify_one();
@@ -253,7 +261,7 @@ void step_loop(bpjd_server* s) {
             if (q == 0) continue;
             if (q < 0) {
                 r->rc = q;
-                r->err = bpjd_last_error();
+                r->err = bpjd_last_error(nullptr);
             }
             done.push_back(r);
         }
@@ -288,7 +296,7 @@ void reap_loop(bpjd_server* s) {
             r->eigvals.assign(r->k, 0.0);
             r->eigvecs.assign((size_t)r->n * r->k, 0.0);
             rc = bpjd::run_finish(r->run, r->eigvals.data(), r->eigvecs.data(), BPJD_MEM_HOST, &r->stats);
-            if (rc < 0) err = bpjd_last_error();
+            if (rc < 0) err = bpjd_last_error(nullptr);
         }
         if (r->p) (void)hipStreamSynchronize(r->p->ctx->stream);
         bpjd::run_destroy(r->run);
@@ -310,6 +318,7 @@ void reap_loop(bpjd_server* s) {
 extern "C" {
 
 int bpjd_server_create(bpjd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots, bpjd_server** out) {
+    bpjd::CtxScope cs_(ctx);
     if (!ctx || !out) return bpjd::fail(BPJD_ERR_ARG, "NULL argument");
     if (max_slots < 1 || max_slots > 64) return bpjd::fail(BPJD_ERR_ARG, "max_slots must be in [1, 64]");
     BPJD_HIP(hipSetDevice(ctx->device));
@@ -317,18 +326,48 @@ int bpjd_server_create(bpjd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots
     BPJD_HIP(hipMemGetInfo(&free_b, &total_b));
     auto* s = new bpjd_server();
     s->ctx = ctx;
-    s->budget = hbm_budget_bytes ? hbm_budget_bytes : free_b / 10 * 9;
+    s->budget = bpjd::DevArena::round(hbm_budget_bytes ? hbm_budget_bytes : free_b / 10 * 9);
     s->max_slots = max_slots;
-    s->slot_ctx.resize(max_slots);
+    // the whole budget as one device block, from the context's allocator or hipMalloc:
+    // admitting and reaping requests then sub-allocate and release without any device
+    // allocation call (which would synchronise the device under running solves)
+    void* block = nullptr;
+    if (ctx->alloc.alloc) {
+        block = ctx->alloc.alloc(s->budget, ctx->alloc.user);
+        s->arena_route = 1;
+    } else if (hipMalloc(&block, s->budget) != hipSuccess) {
+        block = nullptr;
+    }
+    if (!block) {
+        (void)hipGetLastError();
+        delete s;
+        return bpjd::fail(BPJD_ERR_OOM, "server block of " + std::to_string(hbm_budget_bytes) + " bytes");
+    }
+    s->arena.base = (char*)block;
+    s->arena.size = s->budget;
+    s->arena.free_[0] = s->budget;
     s->slot_busy.assign(max_slots, 0);
+    int made = 0;
     for (int q = 0; q < max_slots; ++q) {
-        s->slot_ctx[q].device = ctx->device;
-        s->slot_ctx[q].own_stream = true;
-        if (hipStreamCreateWithFlags(&s->slot_ctx[q].stream, hipStreamNonBlocking) != hipSuccess) {
-            for (int r = 0; r < q; ++r) (void)hipStreamDestroy(s->slot_ctx[r].stream);
-            delete s;
-            return bpjd::fail(BPJD_ERR_HIP, "hipStreamCreateWithFlags failed");
+        auto c = std::make_unique<bpjd_ctx>();
+        c->device = ctx->device;
+        c->own_stream = true;
+        c->arena = &s->arena;
+        const bool ok = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
+                        hipHostMalloc((void**)&c->hbuf, 4096 * sizeof(double)) == hipSuccess;
+        s->slot_ctx.push_back(std::move(c));
+        if (!ok) break;
+        ++made;
+    }
+    if (made < max_slots) {
+        for (auto& c : s->slot_ctx) {
+            if (c->stream) (void)hipStreamDestroy(c->stream);
+            if (c->hbuf) (void)hipHostFree(c->hbuf);
         }
+        if (s->arena_route == 1) ctx->alloc.free(block, ctx->alloc.user);
+        else (void)hipFree(block);
+        delete s;
+        return bpjd::fail(BPJD_ERR_HIP, "slot stream or pinned buffer creation failed");
     }
     s->info.budget_bytes = s->budget;
     s->info.max_slots = max_slots;
@@ -342,6 +381,7 @@ int bpjd_server_create(bpjd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots
 
 int bpjd_server_submit(bpjd_server* s, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
                        const bpjd_dd_geom* geom, const bpjd_opts* opts, uint64_t* req_id) {
+    bpjd::CtxScope cs_(s ? s->ctx : nullptr);
     if (!s || !K || !M || !opts || !req_id || (!dd && !geom) || (dd && geom))
         return bpjd::fail(BPJD_ERR_ARG, "need K, M, opts, req_id and exactly one of dd / geom");
     if (K->mem != BPJD_MEM_HOST || M->mem != BPJD_MEM_HOST || (dd && dd->P.mem != BPJD_MEM_HOST))
@@ -355,10 +395,8 @@ int bpjd_server_submit(bpjd_server* s, const bpjd_csr* K, const bpjd_csr* M, con
     copy_csr(*K, r->Kptr, r->Kcol, r->Kval, r->K);
     copy_csr(*M, r->Mptr, r->Mcol, r->Mval, r->M);
     r->opts = *opts;
-    // served solves launch their kernels one by one: the admit and reap threads allocate,
-    // upload and free device memory while solves run, and a stream capture must not
-    // overlap such device-wide synchronisation
-    r->opts.graphs = 0;
+    // served solves keep the caller's graphs option: admission and reaping sub-allocate
+    // from the server's block, so no device-wide synchronisation overlaps a capture
     if (opts->n_init > 0 && opts->X_init) {
         r->X_init.assign(opts->X_init, opts->X_init + (size_t)r->n * opts->n_init);
         r->opts.X_init = r->X_init.data();
@@ -406,6 +444,7 @@ int bpjd_server_submit(bpjd_server* s, const bpjd_csr* K, const bpjd_csr* M, con
 }
 
 int bpjd_server_poll(bpjd_server* s, uint64_t req_id, double* eigvals, double* eigvecs, bpjd_stats* st) {
+    bpjd::CtxScope cs_(s ? s->ctx : nullptr);
     if (!s) return bpjd::fail(BPJD_ERR_ARG, "NULL server");
     Request* r = nullptr;
     {
@@ -426,6 +465,7 @@ int bpjd_server_poll(bpjd_server* s, uint64_t req_id, double* eigvals, double* e
 }
 
 int bpjd_server_get_info(bpjd_server* s, bpjd_server_info* out) {
+    bpjd::CtxScope cs_(s ? s->ctx : nullptr);
     if (!s || !out) return bpjd::fail(BPJD_ERR_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->info;
@@ -450,7 +490,7 @@ void bpjd_server_destroy(bpjd_server* s) {
     s->step_thr.join();
     s->reap_thr.join();
     // solves still on the device are drained before their memory is freed
-    for (auto& c : s->slot_ctx) (void)hipStreamSynchronize(c.stream);
+    for (auto& c : s->slot_ctx) (void)hipStreamSynchronize(c->stream);
     for (auto& kv : s->all) {
         Request* r = kv.second;
         if (r->run) bpjd::run_destroy(r->run);
@@ -458,7 +498,14 @@ void bpjd_server_destroy(bpjd_server* s) {
         if (r->planned_p) bpjd_problem_destroy(r->planned_p);
         delete r;
     }
-    for (auto& c : s->slot_ctx) (void)hipStreamDestroy(c.stream);
+    for (auto& c : s->slot_ctx) {
+        (void)hipStreamDestroy(c->stream);
+        if (c->hbuf) (void)hipHostFree(c->hbuf);
+    }
+    if (s->arena.base) {
+        if (s->arena_route == 1) s->ctx->alloc.free(s->arena.base, s->ctx->alloc.user);
+        else (void)hipFree(s->arena.base);
+    }
     delete s;
 }
 

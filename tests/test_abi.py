@@ -52,8 +52,13 @@ def _lib_or_skip():
 def test_null_arguments_are_rejected_without_touching_a_device():
     binding, L = _lib_or_skip()
     h = ctypes.c_void_p()
-    assert L.bpjd_ctx_create(0, None, None) == binding.ERR_ARG
-    assert b"NULL" in L.bpjd_last_error()
+    assert L.bpjd_ctx_create(0, None, None, None) == binding.ERR_ARG
+    assert b"NULL" in L.bpjd_last_error(None)
+    # an allocator with only one of its two callbacks
+    half = binding.Allocator()
+    half.alloc = binding.ALLOC_FN(lambda n, u: None)
+    assert L.bpjd_ctx_create(0, ctypes.byref(half), None, ctypes.byref(h)) == binding.ERR_ARG
+    assert b"allocator" in L.bpjd_last_error(None)
     assert L.bpjd_problem_create(None, None, None, None, None, ctypes.byref(h)) == binding.ERR_ARG
     assert L.bpjd_problem_create_geom(None, None, None, None, None, ctypes.byref(h)) == binding.ERR_ARG
     for call in (lambda: L.bpjd_solve(None, None, None, binding.MEM_HOST, None),
@@ -76,10 +81,10 @@ def test_null_arguments_are_rejected_without_touching_a_device():
 def test_bad_device_ordinal_is_an_error():
     binding, L = _lib_or_skip()
     h = ctypes.c_void_p()
-    code = L.bpjd_ctx_create(-1, None, ctypes.byref(h))
+    code = L.bpjd_ctx_create(-1, None, None, ctypes.byref(h))
     # no device at all (CPU host) or an ordinal out of range
     assert code in (binding.ERR_HIP, binding.ERR_ARG)
-    assert L.bpjd_last_error() != b""
+    assert L.bpjd_last_error(None) != b""
     assert not h.value
 
 

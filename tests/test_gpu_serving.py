@@ -92,6 +92,8 @@ def test_served_equals_alone(B, ctx, prec):
         assert np.abs(X_s - X_a).max() <= 1e-10 * np.abs(X_a).max()
         assert st_s["iterations"] == st_a["iterations"]
         assert st_s["latency_ms"] >= st_s["queue_ms"] >= 0.0
+        # served solves replay their captured iteration graphs like solves alone
+        assert st_s["graph_iterations"] >= st_s["iterations"] - 3 > 0, st_s
         # and both are the pencil's eigenpairs
         lam_ref, _ = o.reference_eigs(mesh.K, mesh.M, r["k"])
         np.testing.assert_allclose(lam_s, lam_ref, rtol=1e-10 if prec == "fp64" else 1e-9)
