@@ -269,6 +269,27 @@ int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, doubl
 /* Coarse eigenvalues (ascending, n_H values) from the last setup. */
 int bpjd_coarse_eigenvalues(bpjd_problem* p, double* lamH, int32_t mem);
 
+/* ---- allocation-free call -------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that forbid allocation): the coarse generalized eigenproblem of
+ * the numeric setup (the spectral split of V^H behind the coarse term, computed
+ * by bpjd_setup and read by bpjd_coarse_eigenvalues) on caller-given dense
+ * matrices, with no allocation of any kind and no host synchronisation.
+ *   K_H Y = M_H Y diag(lamH),  Y^T M_H Y = I,  lamH ascending.
+ * KH, MH: n_H x n_H row-major symmetric (M_H positive definite), lower bandwidth
+ * bw (entries farther than bw from the diagonal are zero; n_H - 1 if unknown),
+ * read only.  lamH: n_H values; Y: n_H x n_H row-major, eigenvector j in column
+ * j; info: one int32 set to 0, or to 2 when M_H is not positive definite.  All
+ * device pointers of the context's GPU.  The work is enqueued on the context's
+ * stream and the call returns at once (results and info are valid when that
+ * stream reaches this point).  Working arrays: a fixed device array of the
+ * library, about 8 MB per GPU, held until the process ends, shared by every
+ * call on that GPU: calls that overlap in time on one GPU race.  Errors (before
+ * anything is enqueued): BPJD_ERR_ARG (NULL, n_H outside 1..320, bw outside
+ * 0..n_H-1), BPJD_ERR_STATE, BPJD_ERR_HIP. */
+int bpjd_coarse_eigen_noalloc(bpjd_ctx* ctx, int32_t n_H, int32_t bw, const double* KH, const double* MH,
+                              double* lamH, double* Y, int32_t* info);
+
 /* ---- serving: continuous batching of independent solves ------------------
  * A server solves many problems of the form above (a stream of requests,
  * each its own K, M, decomposition and options) on the context's GPU.

@@ -110,6 +110,8 @@ EXPORTS = {
     "bpjd_apply_preconditioner": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "bpjd_spmm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "bpjd_coarse_eigenvalues": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "bpjd_coarse_eigen_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p]),
     "bpjd_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
     "bpjd_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.POINTER(Csr), C.POINTER(DD), C.POINTER(DDGeom),
                                      C.POINTER(Opts), C.POINTER(C.c_uint64)]),
@@ -444,3 +446,10 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def coarse_eigen_noalloc(ctx: Context, KH, MH, bw: int, lamH, Y, info) -> None:
+    """bpjd_coarse_eigen_noalloc on device tensors (KH, MH, lamH, Y: float64; info:
+    int32): enqueued on the context's stream, no allocation, no synchronisation."""
+    _check(lib().bpjd_coarse_eigen_noalloc(ctx.handle, int(KH.shape[0]), int(bw), _ptr(KH), _ptr(MH), _ptr(lamH),
+                                           _ptr(Y), _ptr(info)))

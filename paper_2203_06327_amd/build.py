@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "lib")
 LIB_NAME = "libbpjd.so"
-SOURCES = ["blas.hip", "precond.hip", "dense.hip", "api.hip", "serve.hip"]
+SOURCES = ["blas.hip", "precond.hip", "dense.hip", "api.hip", "serve.hip", "noalloc.hip"]
 ARCH = os.environ.get("BPJD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1473,6 +1473,7 @@ int bpjd_ctx_create(int device, const bpjd_allocator* allocator, void* hip_strea
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(BPJD_ERR_HIP, "no HIP device");
     if (device < 0 || device >= count) return fail(BPJD_ERR_ARG, "device ordinal out of range");
     BPJD_HIP(hipSetDevice(device));
+    BPJD_TRY(noalloc_init(device));
     bpjd_ctx* c = new bpjd_ctx();
     c->device = device;
     if (allocator) c->alloc = *allocator;

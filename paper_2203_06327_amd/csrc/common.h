@@ -179,6 +179,10 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
                     double* theta, double* lam, double* Cfull);
 
+// ---- allocation-free coarse eigenproblem (noalloc.hip) --------------------------
+// Looks up this device's scratch address; called once per device with it current.
+int noalloc_init(int device);
+
 // ---- problem creation in two steps and the stepwise solve (api.hip) ----------
 struct HostPlan;
 // Validate and plan a problem on the host (no device memory); fills footprint.
