@@ -154,6 +154,10 @@ typedef struct {
                                    environment variable BPJD_TUNE_CACHE, read at the first tuning, when
                                    it is set).  Results are the same bit for bit either way.
                                    0: fixed choices (256 threads, two columns per lane). */
+    int32_t local_threads;      /* threads per system of the windowed local solver (used for half-
+                                   bandwidths above 80 or more than 8 lower entries per local row):
+                                   0 (default) = the autotuner's choice (256 without autotune), or
+                                   exactly 64, 128 or 256.  The arithmetic is the same for all. */
 } bpjd_opts;
 
 /* phases timed when bpjd_opts.profile = 1 (profile = 2: BPJD_PHASE_LOCAL only) */

@@ -57,7 +57,7 @@ class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("guard", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("stop_rule", C.c_int32), ("subspace", C.c_int32), ("precision", C.c_int32),
                 ("n_init", C.c_int32), ("X_init", C.c_void_p), ("profile", C.c_int32), ("graphs", C.c_int32),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("local_threads", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -258,13 +258,15 @@ def _csr(A, keep: list) -> Csr:
 
 def make_opts(k: int, guard: int = 0, tol: float = 1e-8, max_iter: int = 500, stop_rule: int = STOP_RESIDUAL,
               subspace: int = SUBSPACE_UU, precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None,
-              keep: Optional[list] = None, profile: int = 0, graphs: bool = True, autotune: bool = True) -> Opts:
+              keep: Optional[list] = None, profile: int = 0, graphs: bool = True, autotune: bool = True,
+              local_threads: int = 0) -> Opts:
     o = Opts()
     lib().bpjd_opts_default(C.byref(o), k)
     o.guard, o.tol, o.max_iter, o.stop_rule, o.subspace, o.precision = guard, tol, max_iter, stop_rule, subspace, precision
     o.profile = int(profile)
     o.graphs = 1 if graphs else 0
     o.autotune = 1 if autotune else 0
+    o.local_threads = int(local_threads)
     if X_init is not None:
         Xi = np.ascontiguousarray(X_init, dtype=np.float64)
         if keep is not None:
@@ -280,11 +282,11 @@ class Problem:
     def __init__(self, ctx: Context, K, M, *, dd=None, geom=None, k: int, guard: int = 0, tol: float = 1e-8,
                  max_iter: int = 500, stop_rule: int = STOP_RESIDUAL, subspace: int = SUBSPACE_UU,
                  precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None, profile: int = 0,
-                 graphs: bool = True, autotune: bool = True):
+                 graphs: bool = True, autotune: bool = True, local_threads: int = 0):
         keep: list = []
         Kc, Mc = _csr(K, keep), _csr(M, keep)
         opts = make_opts(k, guard, tol, max_iter, stop_rule, subspace, precision, X_init, keep, profile, graphs,
-                         autotune)
+                         autotune, local_threads)
         h = C.c_void_p()
         if geom is not None:
             g = _geom(geom, keep)

@@ -496,6 +496,9 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     if (opts->precision != BPJD_PREC_FP64 && opts->precision != BPJD_PREC_MIXED)
         return fail(BPJD_ERR_ARG, "unknown precision");
     if (opts->profile < 0 || opts->profile > 2) return fail(BPJD_ERR_ARG, "profile must be 0, 1 or 2");
+    if (opts->local_threads != 0 && opts->local_threads != 64 && opts->local_threads != 128 &&
+        opts->local_threads != 256)
+        return fail(BPJD_ERR_ARG, "local_threads must be 0, 64, 128 or 256");
     if (!(opts->tol > 0.0) || opts->max_iter < 0) return fail(BPJD_ERR_ARG, "bad tol or max_iter");
 
     // coverage and local orderings (ascending global index)
@@ -660,6 +663,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     for (int a = 0; a < nH; ++a)
         for (int q = khptr[a]; q < khptr[a + 1]; ++q) p->bwH = std::max(p->bwH, a - khcol[q]);
     p->trace = std::getenv("BPJD_TRACE") != nullptr;
+    if (opts->local_threads) p->ldlt_threads = opts->local_threads;
     p->h_bw = bw;
     p->h_nl.resize(nsub);
     for (int l = 0; l < nsub; ++l) p->h_nl[l] = sptr[l + 1] - sptr[l];
@@ -1218,7 +1222,7 @@ static int autotune(bpjd_problem* p) {
             launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, p->W[0], s, s, p->KW[1], s, p->MW[1], s, v);
         }, &p->spmm_variant));
     }
-    if (!p->blocked) {
+    if (!p->blocked && p->opts.local_threads == 0) {
         BPJD_HIP(hipMemsetAsync(p->Floc, 0, (size_t)p->sumN * s * (mixed ? sizeof(float) : sizeof(double)), st));
         std::snprintf(key, sizeof key, "ldlt %s s%d sub%d n%d w%d e%d", mixed ? "f32" : "f64", s, p->nsub, p->maxN,
                       p->maxBW, p->slotE);

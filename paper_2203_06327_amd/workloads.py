@@ -408,9 +408,14 @@ def bfs_plate(N: int, bc: str = "clamped", coarse: Optional[int] = None, L: int 
     perm, vert, kind = _vertex_major(N, bc)
     K = K[perm][:, perm]
     M = M[perm][:, perm]
-    # one (union) pattern for both matrices, explicit zeros kept
-    Kp = (K + 0.0 * M).tocsr()
-    Mp = (M + 0.0 * K).tocsr()
+    # one (union) pattern for both matrices, explicit zeros kept: both come from the same
+    # (row, col) list (a sum that cancels to an exact zero keeps its entry)
+    Kc, Mc = K.tocoo(), M.tocoo()
+    r = np.concatenate([Kc.row, Mc.row])
+    c = np.concatenate([Kc.col, Mc.col])
+    zk, zm = np.zeros(Kc.nnz), np.zeros(Mc.nnz)
+    Kp = sp.coo_matrix((np.concatenate([Kc.data, zm]), (r, c)), shape=K.shape).tocsr()
+    Mp = sp.coo_matrix((np.concatenate([zk, Mc.data]), (r, c)), shape=M.shape).tocsr()
     for A in (Kp, Mp):
         A.sort_indices()
     assert np.array_equal(Kp.indptr, Mp.indptr) and np.array_equal(Kp.indices, Mp.indices)

@@ -284,3 +284,83 @@ def test_served_plate_requests_equal_alone(B, ctx):
         np.testing.assert_allclose(lam_s, lam_a, rtol=1e-12, atol=0)
         assert np.abs(X_s - X_a).max() <= 1e-10 * np.abs(X_a).max()
         assert st_s["converged"] and st_s["iterations"] == st_a["iterations"]
+
+
+# Wide local bands: the windowed solver's paths that only the finest plates reach
+# (a second row pair per thread in the update once (w+1)/2 exceeds the threads per
+# system, a second and third backward-sweep entry per lane, FP64 up to its LDS limit).
+WIDE = {
+    # 2 x 2 coarse cells (one free coarse vertex, four coarse dofs, so s <= 3) of 32 fine
+    # cells, two layers: half-bandwidth 139 (FP64 fits in LDS up to 141)
+    "wide139": dict(N=64, coarse=32, L=2, k=2, guard=1),
+    # 2 x 2 coarse cells of 31 fine cells, two layers: half-bandwidth 135
+    "wide135": dict(N=62, coarse=31, L=2, k=2, guard=1),
+}
+_WIDE_BOUND = {}
+
+
+def _fp32_bound_sparse(name, ls, lam_max):
+    """_fp32_bound with the extreme eigenvalues of each scaled local matrix from sparse
+    Lanczos runs (the local matrices have 4000+ rows); cached per configuration."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    if name not in _WIDE_BOUND:
+        kap = 0.0
+        for Kl, Ml in zip(ls.K_loc, ls.M_loc):
+            A = (Kl - lam_max * Ml).tocsc()
+            d = sp.diags(1.0 / np.sqrt(A.diagonal()))
+            S = (d @ A @ d).tocsc()
+            top = spla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+            bot = spla.eigsh(S, k=1, sigma=0.0, which="LM", return_eigenvectors=False, tol=1e-6)[0]
+            kap = max(kap, top / bot)
+        _WIDE_BOUND[name] = (4.0 * 2.0 ** -24 * kap, kap)
+    return _WIDE_BOUND[name]
+
+
+@pytest.mark.parametrize("threads", [64, 128, 256])
+@pytest.mark.parametrize("name,prec", [("wide139", "mixed"), ("wide139", "fp64"), ("wide135", "mixed")])
+def test_plate_preconditioner_wide_band(B, ctx, name, prec, threads):
+    _case(f"plate preconditioner {name} {prec} threads {threads}")
+    cfg = dict(WIDE[name])
+    pl = w.bfs_plate(cfg["N"], "clamped", cfg["coarse"], cfg["L"])
+    s = cfg["k"] + cfg["guard"]
+    precision = B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED
+    prob = _problem(B, ctx, pl, cfg, precision, local_threads=threads, autotune=False)
+    nl, bw = prob.local_sizes()
+    print(f"  local sizes {nl.min()}-{nl.max()}, half-bandwidths {bw.min()}-{bw.max()}", flush=True)
+    assert bw.min() >= 128                  # every system takes the wide-band paths
+    prob.setup()
+    dd = _oracle_dd(pl, cfg)
+    cs = o.coarse_setup(pl.K, pl.M, dd.P)
+    ls = o.local_setup(pl.K, pl.M, dd.subs)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((pl.n, s))
+    lam = cs.lamH[:s] * (1.0 - 0.05 * rng.random(s))
+    Zg = prob.apply_preconditioner(X, lam)
+    F = (pl.M @ X) * lam - pl.K @ X
+    Zo = o.precondition(F, lam, cs, ls, s)
+    err = _rel_err_by_kind(Zg, Zo, pl.kind)
+    if prec == "fp64":
+        tol = 1e-11
+    else:
+        tol, kap = _fp32_bound_sparse(name, ls, lam.max())
+        print(f"  scaled local condition {kap:.3e}", flush=True)
+    print(f"  max rel err per kind {err:.3e} (bound {tol:.1e})", flush=True)
+    assert err < tol
+    prob.close()
+
+
+def test_plate_p128_fp64_iteration_count(B, ctx):
+    """p128 (64,516 dofs, half-bandwidths 91-99) in FP64: the count equals the oracle's
+    within one (same subspace choice and stop rule)."""
+    _case("plate p128 fp64 iteration count vs oracle")
+    pl, cfg = w.config_plate("p128")
+    prob = _problem(B, ctx, pl, cfg, B.PREC_FP64, tol=1e-8)
+    lam, X, st = prob.solve()
+    prob.close()
+    dd = _oracle_dd(pl, cfg)
+    res = o.bpjd(pl.K, pl.M, dd, cfg["k"], cfg["guard"], tol=1e-8, subspace="UU", max_iter=200)
+    print(f"  iterations gpu {st['iterations']} oracle {res.iterations}", flush=True)
+    assert res.converged and st["converged"]
+    assert abs(int(st["iterations"]) - int(res.iterations)) <= 1
+    np.testing.assert_allclose(lam, res.lam, rtol=1e-10)
