@@ -247,8 +247,26 @@ class Context:
             pass
 
 
+class DeviceCSR:
+    """A CSR matrix resident in device memory (torch tensors on the GPU): int32 row
+    pointers and columns, float64 values; passed to the library as BPJD_MEM_DEVICE."""
+
+    def __init__(self, A, device: int = 0):
+        import torch
+        dev = torch.device("cuda", device)
+        self.shape = A.shape
+        self.nnz = A.nnz
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(A.indptr, dtype=np.int32)).to(dev)
+        self.col = torch.from_numpy(np.ascontiguousarray(A.indices, dtype=np.int32)).to(dev)
+        self.val = torch.from_numpy(np.ascontiguousarray(A.data, dtype=np.float64)).to(dev)
+
+
 def _csr(A, keep: list) -> Csr:
-    """scipy CSR (host) -> bpjd_csr with int32 indices and float64 values."""
+    """scipy CSR (host) or DeviceCSR -> bpjd_csr with int32 indices and float64 values."""
+    if isinstance(A, DeviceCSR):
+        keep.append(A)
+        return Csr(A.shape[0], A.shape[1], A.nnz, A.rowptr.data_ptr(), A.col.data_ptr(), A.val.data_ptr(),
+                   MEM_DEVICE)
     rowptr = np.ascontiguousarray(A.indptr, dtype=np.int32)
     col = np.ascontiguousarray(A.indices, dtype=np.int32)
     val = np.ascontiguousarray(A.data, dtype=np.float64)
