@@ -388,6 +388,10 @@ struct HostPlan {
     size_t elt = 8;
 };
 
+// Distance in doubles between consecutive n x s blocks of W, K W and M W: n s rounded
+// up to even, so that every block starts on a 16-byte boundary.
+static inline long long block_stride(int n, int s) { return ((long long)n * s + 1) & ~1LL; }
+
 // The one list of device arrays of a problem.  `op(dst, src, bytes)` either allocates
 // (and uploads src when non-NULL) or only counts bytes, so the footprint used for
 // admission and the real allocation cannot drift apart.
@@ -439,7 +443,7 @@ static int device_layout(bpjd_problem* p, const HostPlan& h, Op&& op) {
     zero(&p->esmall, 6 * (size_t)nH + 1);
     zero(&p->YT, nH2);
     zero(&p->escratch, 8 * nH2);
-    const size_t blk = (size_t)n * 3 * s;
+    const size_t blk = 3 * (size_t)block_stride(n, s);
     for (int b = 0; b < 2; ++b) {
         zero(&p->W[b], blk);
         zero(&p->KW[b], blk);
@@ -765,9 +769,9 @@ static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR&
 // blocks (column c of W lies in block c / s), so a kernel that touches one block reads
 // and writes whole rows of it.
 static inline double* blkp(const bpjd_problem* p, double* base, int c) {
-    return base + (size_t)(c / p->s) * p->n * p->s;
+    return base + (size_t)(c / p->s) * block_stride(p->n, p->s);
 }
-static inline BlockGeom wgeom(const bpjd_problem* p) { return BlockGeom{p->s, p->s, (long long)p->n * p->s}; }
+static inline BlockGeom wgeom(const bpjd_problem* p) { return BlockGeom{p->s, p->s, block_stride(p->n, p->s)}; }
 
 // HIP-event timing of solve phases (bpjd_opts.profile).  Events come from a
 // pool; elapsed times are collected at the host synchronisation point of

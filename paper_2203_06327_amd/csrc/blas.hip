@@ -377,48 +377,133 @@ constexpr int GR_ROWS = 64;
 constexpr int GR_MAXC = 64;
 
 // Dynamic LDS: the block's A rows (GR_ROWS x (a + 1), padded against bank conflicts)
-// and C (a x b).  Thread t owns the output column t % b of rows t / b, t / b + 256 / b,
-// ... (one integer division per thread), so the result is written straight from
-// registers with row-contiguous stores and no second LDS buffer is needed.
+// and C (a x b, zero-padded to whole k-steps and column tiles).  With the blocked
+// layout (row-major n x bw blocks, a and b multiples of bw: every use here), the
+// block's rows of each n x bw block form one contiguous run of GR_ROWS * bw values:
+// it is read and written as a flat array with 16-byte accesses (consecutive threads
+// on consecutive addresses) and placed in, or taken from, LDS by (row, column).
+// Otherwise each column is read by strided loads.  The product is formed with FP64
+// 16x16x4 MFMAs: wavefront w takes rows 16 w .. 16 w + 15 of the block and every
+// 16-column tile of the result; for a k-step, lane l supplies A[16 w + l % 16][k0 + l / 16]
+// and C[k0 + l / 16][16 q + l % 16] from LDS.  Each output is one fixed-order sum over k
+// (the k-steps in order, four products per step as the MFMA adds them), so the result
+// does not depend on the launch.  With A == Y (in place) every row of the block is read
+// before any is written.
 __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, double alpha, Triple T, BlockGeom g,
-                                                        const double* __restrict__ C, double beta) {
+                                                        const double* __restrict__ C, double beta, int flat) {
     extern __shared__ double gr_smem[];
-    double* sA = gr_smem;                      // [GR_ROWS][a + 1]
-    double* sC = gr_smem + GR_ROWS * (a + 1);  // [a][b]
+    const int ak = (a + 3) & ~3;               // k padded to whole k-steps
+    const int bq = (b + 15) & ~15;             // columns padded to whole tiles
+    const int ap = ak + 1;
+    double* sA = gr_smem;                      // [GR_ROWS][ak + 1]; later the result [GR_ROWS][bq + 1]
+    double* sC = gr_smem + GR_ROWS * (ap > bq + 1 ? ap : bq + 1);   // [ak][bq]
     const int t = threadIdx.x;
     const int r0 = blockIdx.x * GR_ROWS;
+    const int rows = min(GR_ROWS, n - r0);
     const double* A = T.A[blockIdx.y];
     double* Y = T.Y[blockIdx.y];
-    const int ap = a + 1;
-    for (int e = t; e < a * b; e += 256) sC[e] = C[e];
-    {
+    for (int e = t; e < ak * bq; e += 256) {
+        const int k = e / bq, q = e - k * bq;
+        sC[e] = (k < a && q < b) ? C[k * b + q] : 0.0;
+    }
+    for (int e = t; e < GR_ROWS * (ak - a); e += 256) sA[(e / (ak - a)) * ap + a + e % (ak - a)] = 0.0;
+    if (rows < GR_ROWS)
+        for (int e = t; e < (GR_ROWS - rows) * a; e += 256) sA[(rows + e / a) * ap + e % a] = 0.0;
+    if (flat) {
+        const int bw = g.bw;
+        const int cnt = rows * bw;             // values of one block's run (odd only in the last block)
+        for (int jb = 0; jb < a / bw; ++jb) {
+            const double* run = A + jb * g.bs + (long long)r0 * bw;
+            const double2* src = reinterpret_cast<const double2*>(run);
+            for (int e2 = t; 2 * e2 + 1 < cnt; e2 += 256) {
+                const double2 v = src[e2];
+                const int e = 2 * e2;
+                const int row = e / bw, col = e - row * bw;
+                sA[row * ap + jb * bw + col] = v.x;
+                if (col + 1 < bw) sA[row * ap + jb * bw + col + 1] = v.y;
+                else sA[(row + 1) * ap + jb * bw] = v.y;
+            }
+            if ((cnt & 1) && t == 0) sA[(rows - 1) * ap + jb * bw + bw - 1] = run[cnt - 1];
+        }
+    } else {
         const int rpp = 256 / a;               // rows per pass of the load
         const int p = t % a, rr0 = t / a;
         const long long op = g.col_offset(p);
         if (rr0 < rpp) {
-            for (int rr = rr0; rr < GR_ROWS; rr += rpp) {
-                const int r = r0 + rr;
-                sA[rr * ap + p] = (r < n) ? A[op + (long long)r * g.ld] : 0.0;
-            }
+            for (int rr = rr0; rr < rows; rr += rpp) sA[rr * ap + p] = A[op + (long long)(r0 + rr) * g.ld];
         }
     }
     __syncthreads();
-    const int rpp = 256 / b;
-    const int q = t % b, rr0 = t / b;
-    if (rr0 >= rpp) return;
-    const long long oq = g.col_offset(q);
-    for (int rr = rr0; rr < GR_ROWS; rr += rpp) {
-        const int r = r0 + rr;
-        if (r >= n) break;
-        const double* arow = sA + rr * ap;
-        double acc = 0.0;
-        for (int k = 0; k < a; ++k) acc = fma(arow[k], sC[k * b + q], acc);
-        double* y = Y + oq + (long long)r * g.ld;
-        *y = (beta == 0.0) ? alpha * acc : fma(beta, *y, alpha * acc);
+    const int w = t >> 6, lane = t & 63, lr = lane & 15, lk = lane >> 4;
+    const double* arow = sA + (16 * w + lr) * ap + lk;
+    dx4_t acc[GR_MAXC / 16];
+#pragma unroll
+    for (int qt = 0; qt < GR_MAXC / 16; ++qt) {
+        acc[qt] = dx4_t{0.0, 0.0, 0.0, 0.0};
+        if (16 * qt < bq) {
+            const double* ccol = sC + lk * bq + 16 * qt + lr;
+            for (int k0 = 0; k0 < ak; k0 += 4)
+                acc[qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[k0], ccol[k0 * bq], acc[qt], 0, 0, 0);
+        }
+    }
+    __syncthreads();                           // every MFMA operand has been read
+    // the result through LDS: element i of lane l is row l / 16 + 4 i, column l % 16 of
+    // a tile
+    const int yp = bq + 1;
+#pragma unroll
+    for (int qt = 0; qt < GR_MAXC / 16; ++qt)
+        if (16 * qt < bq)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sA[(16 * w + lk + 4 * i) * yp + 16 * qt + lr] = acc[qt][i];
+    __syncthreads();
+    if (flat) {
+        const int bw = g.bw;
+        const int cnt = rows * bw;
+        for (int jb = 0; jb < b / bw; ++jb) {
+            double* run = Y + jb * g.bs + (long long)r0 * bw;
+            double2* dst = reinterpret_cast<double2*>(run);
+            if ((cnt & 1) && t == 0) {
+                const double v = sA[(rows - 1) * yp + jb * bw + bw - 1];
+                run[cnt - 1] = (beta == 0.0) ? alpha * v : fma(beta, run[cnt - 1], alpha * v);
+            }
+            for (int e2 = t; 2 * e2 + 1 < cnt; e2 += 256) {
+                const int e = 2 * e2;
+                const int row = e / bw, col = e - row * bw;
+                const double v0 = sA[row * yp + jb * bw + col];
+                const double v1 = (col + 1 < bw) ? sA[row * yp + jb * bw + col + 1] : sA[(row + 1) * yp + jb * bw];
+                double2 o;
+                if (beta == 0.0) {
+                    o = make_double2(alpha * v0, alpha * v1);
+                } else {
+                    const double2 old = dst[e2];
+                    o = make_double2(fma(beta, old.x, alpha * v0), fma(beta, old.y, alpha * v1));
+                }
+                dst[e2] = o;
+            }
+        }
+    } else {
+        for (int e = t; e < rows * b; e += 256) {
+            const int row = e / b, q = e - row * b;
+            double* y = Y + g.col_offset(q) + (long long)(r0 + row) * g.ld;
+            const double v = sA[row * yp + q];
+            *y = (beta == 0.0) ? alpha * v : fma(beta, *y, alpha * v);
+        }
     }
 }
 
-static size_t gemm_rows_smem(int a, int b) { return sizeof(double) * ((size_t)GR_ROWS * (a + 1) + (size_t)a * b); }
+static size_t gemm_rows_smem(int a, int b) {
+    const size_t ak = (a + 3) & ~3, bq = (b + 15) & ~15;
+    const size_t rowsz = ak + 1 > bq + 1 ? ak + 1 : bq + 1;
+    return sizeof(double) * ((size_t)GR_ROWS * rowsz + ak * bq);
+}
+
+// blocked layout with whole blocks and 16-byte aligned block bases: flat row runs
+static int gemm_rows_flat(int a, int b, BlockGeom g, const double* const* A, const double* const* Y, int count) {
+    if (g.ld != g.bw || a % g.bw || b % g.bw || (g.bs % 2) || ((long long)GR_ROWS * g.bw) % 2) return 0;
+    for (int k = 0; k < count; ++k)
+        if ((reinterpret_cast<uintptr_t>(A[k]) | reinterpret_cast<uintptr_t>(Y[k])) % 16) return 0;
+    return 1;
+}
 
 void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const double* const* A, double* const* Y,
                       int count, BlockGeom g, const double* C, double beta) {
@@ -427,8 +512,9 @@ void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const d
         T.A[k] = A[k];
         T.Y[k] = Y[k];
     }
+    const int flat = gemm_rows_flat(a, b, g, A, Y, count);
     hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(a, b), st, n, a,
-                       b, alpha, T, g, C, beta);
+                       b, alpha, T, g, C, beta, flat);
 }
 
 void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int count, BlockGeom g, const double* C) {
@@ -437,8 +523,9 @@ void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int co
         T.A[k] = Y[k];
         T.Y[k] = Y[k];
     }
+    const int flat = gemm_rows_flat(b, b, g, Y, Y, count);
     hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(b, b), st, n, b,
-                       b, 1.0, T, g, C, 0.0);
+                       b, 1.0, T, g, C, 0.0, flat);
 }
 
 // ---------------------------------------------------------------------------

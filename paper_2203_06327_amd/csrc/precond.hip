@@ -101,39 +101,6 @@ void launch_galerkin(hipStream_t st, int n, int nH, const int* rowptr, const int
 
 // ---------------------------------------------------------------------------
 // Coarse term.
-// G = P^T F: one workgroup per coarse dof a; threads stride over the support of
-// the coarse basis function and reduce per column in a fixed tree order.
-__global__ void restrict_kernel(int nH, int s, const int* __restrict__ PTptr, const int* __restrict__ PTcol,
-                                const double* __restrict__ PTval, const double* __restrict__ F, int ldf,
-                                double* __restrict__ G) {
-    __shared__ double red[256 * 8];
-    const int a = blockIdx.x;
-    const int t = threadIdx.x;
-    for (int i0 = 0; i0 < s; i0 += 8) {
-        double acc[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-        for (int q = PTptr[a] + t; q < PTptr[a + 1]; q += blockDim.x) {
-            const double w = PTval[q];
-            const double* frow = F + (long long)PTcol[q] * ldf + i0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i0 + u < s) acc[u] = fma(w, frow[u], acc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) red[u * 256 + t] = acc[u];
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (t < o) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) red[u * 256 + t] += red[u * 256 + t + o];
-            }
-            __syncthreads();
-        }
-        if (t < 8 && i0 + t < s) G[a * s + i0 + t] = red[t * 256];
-        __syncthreads();
-    }
-}
 
 // Cw[j][i] = (y_j^T G_i) / (lambda^H_j - lambda_i) for j >= s; one workgroup per
 // coarse eigenvector j reads row j of Y^T (contiguous) and reduces per column i.
@@ -192,41 +159,37 @@ __global__ __launch_bounds__(64) void coarse_back_kernel(int nH, int s, const do
     }
 }
 
-// G = P^T F in two deterministic stages for wide coarse supports: workgroup (k, a) sums
-// the k-th chunk of `chunk` support entries of coarse dof a for every column (wave sums,
-// then the four waves in order) into part[a][k][i]; then each G[a][i] adds its chunks
-// in order.  Chunks past the end of a support contribute zeros.
-__global__ __launch_bounds__(256) void restrict_partial_kernel(int s, int nchunk, int chunk,
-                                                               const int* __restrict__ PTptr,
-                                                               const int* __restrict__ PTcol,
-                                                               const double* __restrict__ PTval,
-                                                               const double* __restrict__ F, int ldf,
-                                                               double* __restrict__ part) {
-    __shared__ double red[4][BPJD_MAX_BLOCK];
+
+// G = P^T F, chunked: workgroup (k, a) takes the k-th chunk of `chunk` support entries
+// of coarse dof a.  Thread t works on column t % s of the entries t / s, t / s + slots,
+// ... (slots = 256 / s), so the lanes of one entry read its row of F contiguously;
+// the per-entry-slot sums are then added in slot order for each column.  With one
+// chunk the sum is G itself, else it goes to part[a][k][i] and restrict_sum_kernel
+// adds the chunks in order (deterministic either way).
+__global__ __launch_bounds__(256) void restrict_cols_kernel(int s, int nchunk, int chunk,
+                                                            const int* __restrict__ PTptr,
+                                                            const int* __restrict__ PTcol,
+                                                            const double* __restrict__ PTval,
+                                                            const double* __restrict__ F, int ldf,
+                                                            double* __restrict__ out) {
+    __shared__ double red[256];
     const int k = blockIdx.x, a = blockIdx.y;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x;
+    const int slots = 256 / s;
+    const int c = t % s, e = t / s;
     const int q0 = PTptr[a] + k * chunk;
     const int q1 = min(q0 + chunk, PTptr[a + 1]);
-    double acc[BPJD_MAX_BLOCK];
-#pragma unroll
-    for (int i = 0; i < BPJD_MAX_BLOCK; ++i) acc[i] = 0.0;
-    for (int q = q0 + t; q < q1; q += 256) {
-        const double w = PTval[q];
-        const double* frow = F + (long long)PTcol[q] * ldf;
-#pragma unroll
-        for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
-            if (i < s) acc[i] = fma(w, frow[i], acc[i]);
+    double acc = 0.0;
+    if (e < slots) {
+        for (int q = q0 + e; q < q1; q += slots) acc = fma(PTval[q], F[(long long)PTcol[q] * ldf + c], acc);
     }
-#pragma unroll
-    for (int i = 0; i < BPJD_MAX_BLOCK; ++i) {
-        if (i >= s) break;
-        double v = acc[i];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wv][i] = v;
-    }
+    red[t] = acc;
     __syncthreads();
-    if (t < s) part[((long long)a * nchunk + k) * s + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    if (t < s) {
+        double v = 0.0;
+        for (int j = 0; j < slots; ++j) v += red[j * s + t];
+        out[((long long)a * nchunk + k) * s + t] = v;
+    }
 }
 
 __global__ void restrict_sum_kernel(int nH, int s, int nchunk, const double* __restrict__ part,
@@ -244,23 +207,21 @@ void launch_coarse_apply(hipStream_t st, int n, int nH, int s, const int* PTptr,
                          const double* lamH, const double* lam, double* G, double* Cw, double* Zhat,
                          int maxPT, double* part, long long part_cap) {
     (void)n;
-    // coarse supports of more than 4096 entries: chunked two-stage restriction (enough
-    // workgroups to fill the device); otherwise one workgroup per coarse dof
-    bool two_stage = false;
-    if (maxPT > 4096 && s <= BPJD_MAX_BLOCK) {
-        long long chunk = 1024;
-        while (chunk < maxPT && (long long)nH * s * ((maxPT + chunk - 1) / chunk) > part_cap) chunk *= 2;
-        const long long nchunk = (maxPT + chunk - 1) / chunk;
-        if ((long long)nH * s * nchunk <= part_cap) {
-            two_stage = true;
-            hipLaunchKernelGGL(restrict_partial_kernel, dim3((int)nchunk, nH), dim3(256), 0, st, s, (int)nchunk,
-                               (int)chunk, PTptr, PTcol, PTval, F, ldf, part);
-            hipLaunchKernelGGL(restrict_sum_kernel, dim3((nH * s + 255) / 256), dim3(256), 0, st, nH, s, (int)nchunk,
-                               part, G);
-        }
+    // chunks of at most 512 support entries, one workgroup per (chunk, coarse dof), so
+    // that even a few coarse dofs with wide supports fill the device; a single chunk
+    // writes G directly, several go through the ordered second pass
+    long long chunk = 512;
+    while (chunk < maxPT && (long long)nH * s * ((maxPT + chunk - 1) / chunk) > part_cap) chunk *= 2;
+    const long long nchunk = std::max<long long>(1, (maxPT + chunk - 1) / chunk);
+    if (nchunk == 1) {
+        hipLaunchKernelGGL(restrict_cols_kernel, dim3(1, nH), dim3(256), 0, st, s, 1, (int)chunk, PTptr, PTcol,
+                           PTval, F, ldf, G);
+    } else {
+        hipLaunchKernelGGL(restrict_cols_kernel, dim3((int)nchunk, nH), dim3(256), 0, st, s, (int)nchunk, (int)chunk,
+                           PTptr, PTcol, PTval, F, ldf, part);
+        hipLaunchKernelGGL(restrict_sum_kernel, dim3((nH * s + 255) / 256), dim3(256), 0, st, nH, s, (int)nchunk,
+                           part, G);
     }
-    if (!two_stage)
-        hipLaunchKernelGGL(restrict_kernel, dim3(nH), dim3(256), 0, st, nH, s, PTptr, PTcol, PTval, F, ldf, G);
     hipLaunchKernelGGL(coarse_coef_kernel, dim3(nH), dim3(64), 0, st, nH, s, YT, G, lamH, lam, Cw);
     hipLaunchKernelGGL(coarse_back_kernel, dim3(nH), dim3(64), 0, st, nH, s, Y, Cw, Zhat);
 }
@@ -268,22 +229,40 @@ void launch_coarse_apply(hipStream_t st, int n, int nH, int s, const int* PTptr,
 // ---------------------------------------------------------------------------
 // Gather R_l F into per-shift contiguous arrays Floc[i][pos] (pos runs over
 // all subdomains' dofs in subdomain order), converting to the solve precision.
+// Staged through LDS: a workgroup takes GT consecutive positions, reads their rows
+// of F with consecutive threads on consecutive columns of a row, and writes each
+// shift's GT values with consecutive threads on consecutive positions.
+constexpr int GT = 256;
+
 template <typename T>
-__global__ void gather_kernel(int sumN, int s, const int* __restrict__ subidx, const double* __restrict__ F, int ldf,
-                              T* __restrict__ Floc) {
-    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= sumN) return;
-    const double* frow = F + (long long)subidx[pos] * ldf;
-    for (int i = 0; i < s; ++i) Floc[(long long)i * sumN + pos] = (T)frow[i];
+__global__ __launch_bounds__(256) void gather_kernel(int sumN, int s, const int* __restrict__ subidx,
+                                                     const double* __restrict__ F, int ldf, T* __restrict__ Floc) {
+    extern __shared__ __align__(16) unsigned char gather_smem[];
+    T (*tile)[GT + 1] = reinterpret_cast<T (*)[GT + 1]>(gather_smem);   // [s][GT + 1]
+    __shared__ int rowi[GT];
+    const int pos0 = blockIdx.x * GT;
+    const int cnt = min(GT, sumN - pos0);
+    const int t = threadIdx.x;
+    if (t < cnt) rowi[t] = subidx[pos0 + t];
+    __syncthreads();
+    for (int e = t; e < cnt * s; e += 256) {
+        const int p = e / s, i = e - p * s;
+        tile[i][p] = (T)F[(long long)rowi[p] * ldf + i];
+    }
+    __syncthreads();
+    for (int e = t; e < GT * s; e += 256) {
+        const int i = e / GT, p = e - i * GT;
+        if (p < cnt) Floc[(long long)i * sumN + pos0 + p] = tile[i][p];
+    }
 }
 
 void launch_gather_f64(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, double* Floc) {
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(grid_for(sumN, 256)), dim3(256), 0, st, sumN, s, subidx, F, ldf,
-                       Floc);
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(grid_for(sumN, GT)), dim3(256), sizeof(double) * s * (GT + 1), st,
+                       sumN, s, subidx, F, ldf, Floc);
 }
 void launch_gather_f32(hipStream_t st, int sumN, int s, const int* subidx, const double* F, int ldf, float* Floc) {
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(grid_for(sumN, 256)), dim3(256), 0, st, sumN, s, subidx, F, ldf,
-                       Floc);
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(grid_for(sumN, GT)), dim3(256), sizeof(float) * s * (GT + 1), st,
+                       sumN, s, subidx, F, ldf, Floc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1103,58 +1082,58 @@ void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC,
 // Z(d, i) = sum_b P(d,b) Zhat(b,i) + sum over the (subdomain, local row) copies
 // of dof d of zloc_i, in the order of the reverse map (deterministic).
 template <typename T>
-__global__ void scatter_kernel(int n, int s, long long sumN, const int* __restrict__ Pptr,
-                               const int* __restrict__ Pcol, const double* __restrict__ Pval,
-                               const double* __restrict__ Zhat, const int* __restrict__ rptr,
-                               const int* __restrict__ ridx, const T* __restrict__ zloc, double* __restrict__ Z,
-                               int ldz) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)n * s) return;
-    const int d = (int)(t / s), i = (int)(t % s);
-    const int p0 = Pptr[d], p1 = Pptr[d + 1], e0 = rptr[d], e1 = rptr[d + 1];
-    double acc = 0.0;
-    // groups of 4 entries: indices clamped into the row, every load of a group issued
-    // before the first product, sums in entry order
-    for (int qb = p0; qb < p1; qb += 4) {
-        const int cnt = min(4, p1 - qb);
-        int pc[4];
-        double pv[4], zh[4];
+__global__ __launch_bounds__(256) void scatter_kernel(int n, int s, long long sumN, const int* __restrict__ Pptr,
+                                                      const int* __restrict__ Pcol, const double* __restrict__ Pval,
+                                                      const double* __restrict__ Zhat, const int* __restrict__ rptr,
+                                                      const int* __restrict__ ridx, const T* __restrict__ zloc,
+                                                      double* __restrict__ Z, int ldz) {
+    // one dof per thread, every shift in registers: for a shift, consecutive threads read
+    // consecutive local positions of zloc_i (the dofs of a subdomain keep their order);
+    // the sums go through LDS so that Z is written with consecutive threads on
+    // consecutive columns of a row
+    extern __shared__ double scatter_tile[];   // [s][257]: shift i of dof d0 + r at i * 257 + r
+    const int t = threadIdx.x;
+    const int d0 = blockIdx.x * 256;
+    const int d = d0 + t;
+    const int cnt = min(256, n - d0);
+    if (d < n) {
+        double acc[BPJD_MAX_BLOCK];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = qb + min(u, cnt - 1);
-            pc[u] = Pcol[q];
-            pv[u] = Pval[q];
+        for (int i = 0; i < BPJD_MAX_BLOCK; ++i) acc[i] = 0.0;
+        const int p0 = Pptr[d], p1 = Pptr[d + 1], e0 = rptr[d], e1 = rptr[d + 1];
+        for (int q = p0; q < p1; ++q) {
+            const int pc = Pcol[q];
+            const double pv = Pval[q];
+#pragma unroll
+            for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+                if (i < s) acc[i] = fma(pv, Zhat[pc * s + i], acc[i]);
+        }
+        for (int e = e0; e < e1; ++e) {
+            const int ri = ridx[e];
+#pragma unroll
+            for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+                if (i < s) acc[i] += (double)zloc[(long long)i * sumN + ri];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) zh[u] = Zhat[pc[u] * s + i];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (u < cnt) acc = fma(pv[u], zh[u], acc);
+        for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+            if (i < s) scatter_tile[i * 257 + t] = acc[i];
     }
-    for (int eb = e0; eb < e1; eb += 4) {
-        const int cnt = min(4, e1 - eb);
-        int ri[4];
-        T zv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) ri[u] = ridx[eb + min(u, cnt - 1)];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) zv[u] = zloc[(long long)i * sumN + ri[u]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (u < cnt) acc += (double)zv[u];
+    __syncthreads();
+    for (int e = t; e < cnt * s; e += 256) {
+        const int r = e / s, i = e - r * s;
+        Z[(long long)(d0 + r) * ldz + i] = scatter_tile[i * 257 + r];
     }
-    Z[(long long)d * ldz + i] = acc;
 }
 
 void launch_scatter_f64(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
                         const double* Zhat, const int* rptr, const int* ridx, const double* zloc, double* Z, int ldz) {
-    hipLaunchKernelGGL(scatter_kernel<double>, dim3(grid_for((long long)n * s, 256)), dim3(256), 0, st, n, s,
+    hipLaunchKernelGGL(scatter_kernel<double>, dim3(grid_for(n, 256)), dim3(256), sizeof(double) * s * 257, st, n, s,
                        (long long)sumN, Pptr, Pcol, Pval, Zhat, rptr, ridx, zloc, Z, ldz);
 }
 
 void launch_scatter_f32(hipStream_t st, int n, int s, int sumN, const int* Pptr, const int* Pcol, const double* Pval,
                         const double* Zhat, const int* rptr, const int* ridx, const float* zloc, double* Z, int ldz) {
-    hipLaunchKernelGGL(scatter_kernel<float>, dim3(grid_for((long long)n * s, 256)), dim3(256), 0, st, n, s,
+    hipLaunchKernelGGL(scatter_kernel<float>, dim3(grid_for(n, 256)), dim3(256), sizeof(double) * s * 257, st, n, s,
                        (long long)sumN, Pptr, Pcol, Pval, Zhat, rptr, ridx, zloc, Z, ldz);
 }
 
