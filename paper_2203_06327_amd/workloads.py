@@ -465,3 +465,102 @@ def config_plate(name: str) -> tuple[Plate, dict]:
     """Build a named fourth-order workload; returns (plate, config dict)."""
     cfg = dict(PLATE_CONFIGS[name])
     return bfs_plate(cfg["N"], "clamped", cfg["coarse"], cfg["L"]), cfg
+
+
+# ----------------------------------------------------------------------------
+# Three dimensions: trilinear (Q1) elements on the cube (0,pi)^3 (Section 6, Example 6.3)
+@dataclass
+class Cube:
+    """Q1 discretisation of -Lap u = lambda u on (0,pi)^3 with N^3 cells (Dirichlet).
+
+    Dofs are the interior nodes (i, j, k), 1 <= i, j, k <= N - 1, numbered with i
+    fastest.  K and M are tensor sums of the 1-D P1 stiffness K1 and mass M1 (the Q1
+    basis functions are products of 1-D hats):  K = K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1
+    + M1 (x) M1 (x) K1, M = M1 (x) M1 (x) M1.  With ``coarse`` (fine cells per coarse
+    cell) the caller's description of the two-level spaces is added: P, the coarse Q1
+    hats written in fine dofs, and the local dof sets (the nodes of each closed coarse
+    cube grown by L - 1 node layers: delta = L h).
+    """
+    N: int
+    K: sp.csr_matrix
+    M: sp.csr_matrix
+    node: np.ndarray            # (n, 3) int: fine node (i, j, k) of each dof
+    P: Optional[sp.csr_matrix] = None
+    subs: Optional[list] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.K.shape[0]
+
+
+def _p1_1d(N: int, h: float):
+    """1-D P1 stiffness and consistent mass on N cells of size h, interior nodes only."""
+    m = N - 1
+    K1 = sp.diags([-np.ones(m - 1), 2.0 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1]) / h
+    M1 = sp.diags([np.ones(m - 1), 4.0 * np.ones(m), np.ones(m - 1)], [-1, 0, 1]) * (h / 6.0)
+    return K1.tocsr(), M1.tocsr()
+
+
+def _hat_prolongation_1d(N: int, Nc: int) -> sp.csr_matrix:
+    """Coarse interior hats evaluated at the fine interior nodes ((N-1) x (Nc-1))."""
+    r = N // Nc
+    rows, cols, vals = [], [], []
+    for c in range(1, Nc):
+        for i in range(max(1, (c - 1) * r + 1), min(N, (c + 1) * r)):
+            rows.append(i - 1)
+            cols.append(c - 1)
+            vals.append(1.0 - abs(i - c * r) / r)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N - 1, Nc - 1))
+
+
+def q1_cube(N: int, coarse: Optional[int] = None, L: int = 1) -> Cube:
+    h = np.pi / N
+    K1, M1 = _p1_1d(N, h)
+    K = (sp.kron(sp.kron(M1, M1), K1) + sp.kron(sp.kron(M1, K1), M1) + sp.kron(sp.kron(K1, M1), M1)).tocoo()
+    M = sp.kron(sp.kron(M1, M1), M1).tocoo()
+    # one (union) pattern for both matrices, explicit zeros kept
+    r = np.concatenate([K.row, M.row])
+    c = np.concatenate([K.col, M.col])
+    Kp = sp.coo_matrix((np.concatenate([K.data, np.zeros(M.nnz)]), (r, c)), shape=K.shape).tocsr()
+    Mp = sp.coo_matrix((np.concatenate([np.zeros(K.nnz), M.data]), (r, c)), shape=M.shape).tocsr()
+    Kp.sort_indices()
+    Mp.sort_indices()
+    m = N - 1
+    kk, jj, ii = np.meshgrid(np.arange(1, N), np.arange(1, N), np.arange(1, N), indexing="ij")
+    node = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1)
+    cube = Cube(N, Kp, Mp, node, meta={"h": h})
+    if coarse is not None:
+        if N % coarse:
+            raise ValueError("coarse cells must tile the mesh")
+        Nc = N // coarse
+        P1 = _hat_prolongation_1d(N, Nc)
+        cube.P = sp.kron(sp.kron(P1, P1), P1).tocsr()
+        cube.P.sort_indices()
+        subs = []
+        for c3 in range(Nc):
+            for c2 in range(Nc):
+                for c1 in range(Nc):
+                    lo = np.array([c1, c2, c3]) * coarse - (L - 1)
+                    hi = (np.array([c1, c2, c3]) + 1) * coarse + (L - 1)
+                    inside = np.all((node >= lo[None, :]) & (node <= hi[None, :]), axis=1)
+                    subs.append(np.flatnonzero(inside).astype(np.int32))
+        cube.subs = subs
+        cube.meta.update(coarse=coarse, L=L, H=np.pi / Nc)
+    assert m ** 3 == Kp.shape[0]
+    return cube
+
+
+# Example 6.3: (0,pi)^3, 8 x 8 x 8 coarse cubes (N = 512, H = pi/8), delta/H = 1/2 in
+# node layers, s = 20, the paper's stop rule (Table 5).
+CUBE_CONFIGS = {
+    "e3_16": dict(N=16, coarse=2, L=1, k=20, guard=0, stop="paper", tol=1e-10, table5_col=0,
+                  desc="Example 6.3: Laplacian Q1 (0,pi)^3, 3375 dofs, 512 coarse cubes, delta/H=1/2, s=20"),
+    "e3_32": dict(N=32, coarse=4, L=2, k=20, guard=0, stop="paper", tol=1e-10, table5_col=1,
+                  desc="Example 6.3: Laplacian Q1 (0,pi)^3, 29791 dofs, 512 coarse cubes, delta/H=1/2, s=20"),
+}
+
+
+def config_cube(name: str) -> tuple[Cube, dict]:
+    cfg = dict(CUBE_CONFIGS[name])
+    return q1_cube(cfg["N"], cfg["coarse"], cfg["L"]), cfg

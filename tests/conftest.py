@@ -38,3 +38,8 @@ def table1():
 @pytest.fixture(scope="session")
 def table3():
     return load_golden_table("table3.txt")
+
+
+@pytest.fixture(scope="session")
+def table5():
+    return load_golden_table("table5.txt")
