@@ -26,6 +26,9 @@ static thread_local std::string g_last_error;
 static thread_local bpjd_ctx* g_scope_ctx = nullptr;   // context of the ABI call in progress
 static thread_local std::string g_error_copy;          // bpjd_last_error(ctx) storage
 
+// largest dimension of a growing subspace W (its projected eigenproblem is dense)
+static constexpr int kGrowMaxDim = 1024;
+
 // largest half-bandwidth and lower entries per row handled by the blocked (MFMA) local solver
 static constexpr int kBlockedMaxBand = 48;       // 64-row window (4 tile-rows)
 static constexpr int kBlockedWideMaxBand = 80;   // 96-row window (6 tile-rows)
@@ -474,6 +477,22 @@ static int device_layout(bpjd_problem* p, const HostPlan& h, Op&& op) {
     zero(&p->dropped[1], 64);
     zero(&p->status, 4);
     zero(&p->negflag, (size_t)p->nsub * s);
+    {
+        const size_t gc = (size_t)p->grow_cap;
+        const size_t gb = gc ? (size_t)(gc / s) * block_stride(n, s) : 0;
+        zero(&p->Wg, gb);
+        zero(&p->MWg, gb);
+        zero(&p->Hg, gc * gc);
+        zero(&p->Hw, gc * gc);
+        zero(&p->Vg, gc * gc);
+        zero(&p->thetag, gc);
+        zero(&p->Cg, gc * s);
+        zero(&p->Qg, gc * s);
+        zero(&p->gwork, gc * gc);
+        zero(&p->gsmall2, 6 * gc + 1);
+        zero(&p->gscratch, 6 * gc * gc);
+        zero(&p->dropg, gc);
+    }
     return rc;
 }
 
@@ -495,7 +514,8 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     if (opts->n_init && !opts->X_init) return fail(BPJD_ERR_ARG, "X_init is NULL");
     if (opts->stop_rule != BPJD_STOP_RESIDUAL && opts->stop_rule != BPJD_STOP_PAPER)
         return fail(BPJD_ERR_ARG, "unknown stop rule");
-    if (opts->subspace != BPJD_SUBSPACE_UU && opts->subspace != BPJD_SUBSPACE_U)
+    if (opts->subspace != BPJD_SUBSPACE_UU && opts->subspace != BPJD_SUBSPACE_U &&
+        opts->subspace != BPJD_SUBSPACE_GROW)
         return fail(BPJD_ERR_ARG, "unknown subspace choice");
     if (opts->precision != BPJD_PREC_FP64 && opts->precision != BPJD_PREC_MIXED)
         return fail(BPJD_ERR_ARG, "unknown precision");
@@ -709,6 +729,8 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     p->mfma_nt = nt;
     if (blocked) p->bws = bws;
     p->npart = num_partials(n);
+    if (opts->subspace == BPJD_SUBSPACE_GROW)   // dim W <= 1024 (the dense eigensolver's reach)
+        p->grow_cap = s * std::max(2, std::min(kGrowMaxDim / s, opts->max_iter + 1));
     size_t bytes = 0;
     device_layout(p, *h, [&](void**, const void*, size_t b) {
         bytes += (std::max<size_t>(b, 8) + 4095) & ~size_t(4095);   // allocation granularity
@@ -1002,6 +1024,7 @@ struct SolveRun {
     int it = 0;         // outer iteration whose residual is being read back
     int iters = 0;
     int graph_iters = 0;    // iterations launched as a graph replay
+    int grow_m = 0;         // GROW: columns of W in use
     bool converged = false;
     bool fresh = false; // the residual being read back comes from K X, M X formed from X itself
     double stop_value = NAN;
@@ -1064,6 +1087,97 @@ static void enqueue_iteration(SolveRun* r, int a, int np) {
     apply_precond(p, p->F, blkp(p, p->W[a], ct), s, r->T);
     orthonormalize_T(p, a, ct, r->T);
     rayleigh_ritz(p, a, 1 - a, ct + s, uu ? 1 : 0, r->T);
+}
+
+// Chunks of whole n x s blocks of a growing basis, at most 64 columns each (the limit of
+// the Gram and tall-times-small kernels): calls f(first column, columns).
+template <class F>
+static void for_chunks(int m, int s, F&& f) {
+    const int per = std::max(1, 64 / s) * s;
+    for (int c0 = 0; c0 < m; c0 += per) f(c0, std::min(per, m - c0));
+}
+
+// Start of W^0 = span{X} for the growing subspace: W and M W take X and M X (buffer 0,
+// block 0), the projected matrix H = X^T K X.
+static void grow_start(SolveRun* r) {
+    bpjd_problem* p = r->p;
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s;
+    const BlockGeom g = wgeom(p);
+    (void)hipMemsetAsync(p->dropg, 0, sizeof(int) * p->grow_cap, st);   // GROW is never graph-captured
+    launch_copy_cols(st, n, s, p->W[0], s, p->Wg, s);
+    launch_copy_cols(st, n, s, p->MW[0], s, p->MWg, s);
+    launch_gram(st, n, s, s, p->W[0], p->KW[0], g, p->partial, p->npart, p->Cg);
+    launch_grow_place(st, 0, s, p->Cg, p->dropg, p->Hg, p->grow_cap);
+    r->grow_m = s;
+}
+
+// One outer iteration with W^{k+1} = W^k + span{t_i} (Algorithm 3.1, Step 3 as written):
+// t_i into block 1 of buffer 0, two classical Gram-Schmidt passes against all of W (with
+// the stored M W), K T and M T by one SpMM, two Cholesky-QR passes; T and M T become
+// W's next block; the new column block of H = W^T K W from one Gram product with K T;
+// the lowest s eigenpairs of H (dense symmetric eigensolver); X = W Q_s and K X, M X by
+// one SpMM, then the next residual.  Shapes change every step, so it is not captured.
+static int enqueue_iteration_grow(SolveRun* r) {
+    bpjd_problem* p = r->p;
+    hipStream_t st = p->ctx->stream;
+    const int n = p->n, s = p->s;
+    const BlockGeom g = wgeom(p);
+    const long long bsp = block_stride(n, s);
+    const int m = r->grow_m;
+    if (m + s > p->grow_cap)
+        return fail(BPJD_ERR_NOCONV, "growing subspace reached its dimension limit (" + std::to_string(p->grow_cap) +
+                                         ")");
+    double* T = blkp(p, p->W[0], s);
+    double* KT = blkp(p, p->KW[0], s);
+    double* MT = blkp(p, p->MW[0], s);
+    apply_precond(p, p->F, T, s, r->T);
+    PH_BEGIN(r->T, BPJD_PHASE_ORTHO);
+    for (int pass = 0; pass < 2; ++pass) {
+        for_chunks(m, s, [&](int c0, int cc) {
+            launch_gram(st, n, cc, s, p->MWg + (c0 / s) * bsp, T, g, p->partial, p->npart, p->Cg + (size_t)c0 * s);
+        });
+        for_chunks(m, s, [&](int c0, int cc) {
+            const double* src[1] = {p->Wg + (c0 / s) * bsp};
+            double* dst[1] = {T};
+            launch_gemm_rows(st, n, cc, s, -1.0, src, dst, 1, g, p->Cg + (size_t)c0 * s, 1.0);
+        });
+    }
+    PH_END(r->T);
+    PH_BEGIN(r->T, BPJD_PHASE_SPMM);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, T, s, s, KT, s, MT, s, p->spmm_variant);
+    PH_END(r->T);
+    PH_BEGIN(r->T, BPJD_PHASE_ORTHO);
+    double* dst3[3] = {T, KT, MT};
+    for (int pass = 0; pass < 2; ++pass) {
+        launch_gram(st, n, s, s, T, MT, g, p->partial, p->npart, p->gsmall);
+        launch_cholqr_coef(st, s, p->gsmall, p->csmall, p->dropg + m, p->status);
+        launch_rightmul_rows(st, n, s, dst3, 3, g, p->csmall);
+    }
+    launch_copy_cols(st, n, s, T, s, p->Wg + (m / s) * bsp, s);
+    launch_copy_cols(st, n, s, MT, s, p->MWg + (m / s) * bsp, s);
+    PH_END(r->T);
+    PH_BEGIN(r->T, BPJD_PHASE_RR);
+    const int mn = m + s;
+    for_chunks(mn, s, [&](int c0, int cc) {
+        launch_gram(st, n, cc, s, p->Wg + (c0 / s) * bsp, KT, g, p->partial, p->npart, p->Cg + (size_t)c0 * s);
+    });
+    launch_grow_place(st, m, s, p->Cg, p->dropg, p->Hg, p->grow_cap);
+    launch_copy_cols(st, mn, mn, p->Hg, p->grow_cap, p->Hw, mn);
+    launch_sym_eig(st, mn, p->Hw, p->thetag, p->Vg, p->gwork, p->gsmall2, p->gscratch, p->status);
+    launch_copy_cols(st, mn, s, p->Vg, mn, p->Qg, s);
+    launch_copy_cols(st, 1, s, p->thetag, s, p->lam, s);
+    for_chunks(mn, s, [&](int c0, int cc) {
+        const double* src[1] = {p->Wg + (c0 / s) * bsp};
+        double* dst[1] = {p->W[0]};
+        launch_gemm_rows(st, n, cc, s, 1.0, src, dst, 1, g, p->Qg + (size_t)c0 * s, c0 == 0 ? 0.0 : 1.0);
+    });
+    PH_END(r->T);
+    PH_BEGIN(r->T, BPJD_PHASE_SPMM);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0], s, s, p->KW[0], s, p->MW[0], s, p->spmm_variant);
+    PH_END(r->T);
+    r->grow_m = mn;
+    return BPJD_OK;
 }
 
 // The same iteration as a HIP graph: captured from the problem's stream the first time
@@ -1251,6 +1365,7 @@ static int advance_setup(SolveRun* r) {
     if (st_word & STATUS_LOCAL_PIVOT) return fail(BPJD_ERR_NOT_SPD, "singular pivot in a local factorisation");
     p->setup_done = true;
     BPJD_TRY(start_block(p));
+    if (p->opts.subspace == BPJD_SUBSPACE_GROW) grow_start(r);
     if (!p->tuned) {
         if (p->opts.autotune) BPJD_TRY(autotune(p));
         p->tuned = true;
@@ -1323,6 +1438,13 @@ static int advance_iter(SolveRun* r) {
     // the M-orthonormalisation against [X | P] below (same subspace W^{k+1}).
     const int a = r->cur;
     const int ct = s + r->np;
+    if (p->opts.subspace == BPJD_SUBSPACE_GROW) {
+        BPJD_TRY(enqueue_iteration_grow(r));
+        r->fresh = true;        // K X and M X come from an SpMM of X itself
+        r->iters = ++r->it;
+        BPJD_TRY(enqueue_residual(r));
+        return 0;
+    }
     // Step 3: Rayleigh-Ritz on W = [X | P | T]; then the next residual and its read-back.
     // Replayed as a HIP graph unless phases are timed, the iteration is traced, or the
     // caller turned graphs off.

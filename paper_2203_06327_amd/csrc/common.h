@@ -173,6 +173,10 @@ void launch_transpose(hipStream_t st, int n, const double* A, double* AT);
 // CholQR coefficients: G (b x b) -> C = D^{-1/2} L^{-T} (G scaled by D = diag(G) = L L^T);
 // directions with a pivot below the drop tolerance get a zero column and dropped[j] = 1.
 void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* dropped, int* status);
+// Growing subspace: write the Gram block C ((m + s) x s: W^T K T for the m + s columns of
+// W, T included) into the symmetric H (ld ldh) as rows/columns m .. m + s - 1; a dropped
+// (zero) new column j gets the diagonal entry 4 trace(H) + 1, above every Ritz value.
+void launch_grow_place(hipStream_t st, int m, int s, const double* C, const int* dropped, double* H, int ldh);
 // Rayleigh-Ritz coefficient step: given H (m x m) and the dropped flags of all m columns
 // of W, returns theta (m), Cfull (m x 2s) = [Q_s | orthonormal basis of span{E_x, Q_s}
 // minus Q_s] and the dropped flags of the new basis' first 2s (or s) columns.
@@ -258,6 +262,12 @@ struct bpjd_problem {
     double *gsmall = nullptr, *csmall = nullptr, *Hm = nullptr, *theta = nullptr, *Cfull = nullptr, *rrwork = nullptr;
     int *dropped[2] = {nullptr, nullptr}, *status = nullptr;   // per-buffer flags of W's columns
     int* negflag = nullptr;            // per (subdomain, shift): indefinite local matrix
+    // W^{k+1} = W^k + span{t} (BPJD_SUBSPACE_GROW): the basis and M times it as n x s blocks
+    // (block stride as W), the projected K (grow_cap x grow_cap) and the eigensolver's arrays
+    int grow_cap = 0;                  // largest dimension of W (a multiple of s), 0 unless GROW
+    double *Wg = nullptr, *MWg = nullptr, *Hg = nullptr, *Hw = nullptr, *Vg = nullptr, *thetag = nullptr;
+    double *Cg = nullptr, *Qg = nullptr, *gwork = nullptr, *gsmall2 = nullptr, *gscratch = nullptr;
+    int* dropg = nullptr;              // dropped (zero) columns of W
     double* hbuf = nullptr;            // pinned host mirror for per-iteration scalars
     int npart = 0;
     int nnzKH = 0;

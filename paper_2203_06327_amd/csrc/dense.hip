@@ -1550,6 +1550,43 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     }
 }
 
+// Rows and columns m .. m + s - 1 of the projected matrix of a growing basis (one
+// workgroup): off-diagonal entries from the new Gram block, the new diagonal block
+// symmetrised, and dropped columns decoupled with a diagonal entry above every
+// eigenvalue (H is positive semidefinite, so 4 trace + 1 exceeds its spectrum).
+__global__ __launch_bounds__(256) void grow_place_kernel(int m, int s, const double* __restrict__ C,
+                                                         const int* __restrict__ dropped, double* __restrict__ H,
+                                                         int ldh) {
+    const int t = threadIdx.x;
+    const int mn = m + s;
+    for (int e = t; e < mn * s; e += blockDim.x) {
+        const int r = e / s, c = e - r * s;
+        const int j = m + c;
+        double v;
+        if (r < m) {
+            v = C[e];
+        } else {
+            const int c2 = r - m;
+            v = 0.5 * (C[e] + C[(m + c) * s + c2]);
+        }
+        if (dropped[j] || dropped[r]) v = 0.0;
+        H[(long long)r * ldh + j] = v;
+        H[(long long)j * ldh + r] = v;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double tr = 0.0;
+        for (int j = 0; j < mn; ++j)
+            if (!dropped[j]) tr += fabs(H[(long long)j * ldh + j]);
+        for (int j = 0; j < mn; ++j)
+            if (dropped[j]) H[(long long)j * ldh + j] = 4.0 * tr + 1.0;
+    }
+}
+
+void launch_grow_place(hipStream_t st, int m, int s, const double* C, const int* dropped, double* H, int ldh) {
+    hipLaunchKernelGGL(grow_place_kernel, dim3(1), dim3(256), 0, st, m, s, C, dropped, H, ldh);
+}
+
 void launch_rr_coef(hipStream_t st, int m, int s, int with_p, const double* H, const int* drop_in, int* drop_out,
                     double* theta, double* lam, double* Cfull) {
     if (m <= 24)

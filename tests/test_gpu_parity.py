@@ -151,7 +151,7 @@ def test_preconditioner_indefinite_local(B, ctx, name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("subspace", ["UU", "U"])
+@pytest.mark.parametrize("subspace", ["UU", "U", "GROW"])
 def test_solve_c1(B, ctx, prec, subspace):
     _case(f"solve c1 {prec} {subspace}")
     mesh, cfg = w.config_mesh("c1")
@@ -159,7 +159,8 @@ def test_solve_c1(B, ctx, prec, subspace):
     X0 = w.seeded_block(mesh.n, s, cfg["seed_block"])
     prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=k, guard=cfg["guard"], tol=1e-8,
                                precision=B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED,
-                               subspace=B.SUBSPACE_UU if subspace == "UU" else B.SUBSPACE_U, X_init=X0)
+                               subspace={"UU": B.SUBSPACE_UU, "U": B.SUBSPACE_U, "GROW": B.SUBSPACE_GROW}[subspace],
+                               X_init=X0)
     lam, X, st = prob.solve()
     ref, Xref = o.reference_eigs(mesh.K, mesh.M, k)
     rel = np.abs(lam - ref) / ref
@@ -177,7 +178,7 @@ def test_solve_c1(B, ctx, prec, subspace):
     dd = o.build_dd(mesh, cfg["L"])
     res = o.bpjd(mesh.K, mesh.M, dd, k, cfg["guard"], tol=1e-8, subspace=subspace, X_init=X0)
     it_o, it_g = int(res.iterations), int(st["iterations"])
-    slack = 0.03 if (prec == "fp64" and subspace == "UU") else 0.10
+    slack = 0.03 if (prec == "fp64" and subspace in ("UU", "GROW")) else 0.10
     assert abs(it_o - it_g) <= max(1, int(np.ceil(slack * it_o))), (it_o, it_g)
     prob.close()
 

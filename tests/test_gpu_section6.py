@@ -143,3 +143,31 @@ def test_section6_iterations_match_oracle(B, ctx, name):
     print(f"  iterations gpu {st['iterations']} oracle {res.iterations}", flush=True)
     assert res.converged and abs(int(st["iterations"]) - int(res.iterations)) <= 1
     np.testing.assert_allclose(lam, res.lam, rtol=1e-10)
+
+
+@pytest.mark.parametrize("name,paper_its", [("e1_128", 21), ("e2_128", 20), ("e1_256", 22)])
+def test_section6_growing_subspace(B, ctx, table1, table3, name, paper_its):
+    """Algorithm 3.1 as written (W^{k+1} = W^k + span{t_i}) in FP64: the printed
+    eigenvalues, and the count equal to the oracle's run of the same algorithm within
+    one (reported beside the paper's)."""
+    _case(f"section 6 GROW {name}")
+    mesh, cfg = w.config_mesh(name)
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], shape=B.CELL_TRIANGLE, k=cfg["k"], guard=cfg["guard"],
+                               tol=cfg["tol"], stop_rule=B.STOP_PAPER, precision=B.PREC_FP64,
+                               subspace=B.SUBSPACE_GROW)
+    lam, X, st = prob.solve()
+    prob.close()
+    ref = table1[:, cfg["table1_col"]] if "table1_col" in cfg else table3[:, cfg["table3_col"]]
+    err = np.max(np.abs(lam - ref))
+    msg = f"  n={mesh.n} iterations {st['iterations']} (paper {paper_its})  max |lambda - table| {err:.2e}"
+    assert st["converged"] and err <= 5.1e-9
+    np.testing.assert_allclose(X.T @ (mesh.M @ X), np.eye(cfg["k"]), atol=1e-10)
+    if name.endswith("_128"):
+        dd = o.build_dd(mesh, cfg["L"], "triangle")
+        res = o.bpjd(mesh.K, mesh.M, dd, cfg["k"], 0, tol=cfg["tol"], stop_rule="paper", subspace="GROW",
+                     max_iter=80)
+        msg += f"  oracle {res.iterations}"
+        print(msg, flush=True)
+        assert abs(int(st["iterations"]) - int(res.iterations)) <= 1
+    else:
+        print(msg, flush=True)
