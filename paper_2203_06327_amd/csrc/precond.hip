@@ -622,8 +622,15 @@ struct MfmaTile<double> {
 // Window of NT tile-rows (R = 16 NT rows): NT = 4 for half-bandwidths up to 48, NT = 6
 // for up to 80.  Rows 0..63 of the window are one per lane ("set 1"); with NT = 6,
 // rows 64..95 are held by lanes 0..31 as a second set of registers ("set 2").
+// Register budget: the FP32 64-row instance is held to 168 registers (three waves per
+// SIMD instead of two; it has no spills), the others keep the compiler's choice.
+template <typename T, int NT>
+struct BandWaves {
+    static constexpr int value = (sizeof(T) == 4 && NT == 4) ? 3 : 1;
+};
+
 template <typename T, int MODE, int NT>
-__global__ __launch_bounds__(64) void local_band_mfma_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T, NT>::value, 8))) void local_band_mfma_kernel(
     int s, int E, int BWS, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
     const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
     T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
@@ -641,14 +648,18 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     // accumulator rows of a lane are adjacent), vec (shift of the right-hand side)
     // (strides keep 16-byte alignment and spread lanes over banks; the FP64 sizes keep a
     // workgroup under 20 KB so that eight fit in one compute unit's LDS)
-    constexpr int PS = TWO ? (sizeof(T) == 4 ? 124 : 114) : (sizeof(T) == 4 ? 84 : 82);
+    // (the FP32 64-row instance fits in 10 KB, so that 16 systems share a compute unit)
+    constexpr int PS = TWO ? (sizeof(T) == 4 ? 124 : 114) : (sizeof(T) == 4 ? 80 : 82);
     constexpr int QS = sizeof(T) == 4 ? 20 : 18;
     static_assert(16 * PS >= R * QS, "pan aliases panT");
+    static_assert(QS >= 18, "vec and colsum live in the padding columns 16 and 17 of nrowT");
     __shared__ __align__(16) T panT[16][PS];
     __shared__ __align__(16) T nrowT[R][QS];
     T (*pan)[QS] = reinterpret_cast<T (*)[QS]>(&panT[0][0]);   // free once a[] is read
-    __shared__ T vec[R];
-    __shared__ T colsum[16];
+    // vec (R values) and colsum (16) use the padding columns of nrowT, which the tile-row
+    // placement never touches
+    auto VEC = [&](const int r) -> T& { return nrowT[r][16]; };
+    auto CSUM = [&](const int c) -> T& { return nrowT[c][17]; };
     const int sys = blockIdx.x;
     // mode 0: shift lambda_i, and negflag[sys] records a negative pivot (K_l - lambda_i M_l
     // indefinite); mode 1: only the recorded systems, again with shift 0
@@ -880,13 +891,13 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
             for (int J = 1; J <= I; ++J) A[I - 1][J - 1] = A[I][J];
         if (P + 1 < npan) place(NT - 1, base + 16 * NT, base + 16);
         // shift the right-hand side by 16 window rows; fresh rows enter at the bottom
-        vec[lane] = y;
+        VEC(lane) = y;
         if constexpr (TWO) {
-            if (lane < R - 64) vec[64 + lane] = y2;
+            if (lane < R - 64) VEC(64 + lane) = y2;
         }
         wave_sync();
-        y = (lane < R - 16) ? vec[lane + 16] : ((rnew < nl) ? fraw : T(0));
-        if constexpr (TWO) y2 = (lane < R - 80) ? vec[80 + lane] : ((lane < R - 64 && rnew2 < nl) ? fraw2 : T(0));
+        y = (lane < R - 16) ? VEC(min(lane + 16, R - 1)) : ((rnew < nl) ? fraw : T(0));
+        if constexpr (TWO) y2 = (lane < R - 80) ? VEC(min(80 + lane, R - 1)) : ((lane < R - 64 && rnew2 < nl) ? fraw2 : T(0));
         wave_sync();
     }
 
@@ -934,13 +945,13 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
     auto back_step = [&](const int P, T (&a)[16], T (&a2)[16], T& zb) {
         const int base = 16 * P;
         const T zc0 = (lane < 16 && base + lane < nl) ? zb : T(0);
-        vec[lane] = zw;
+        VEC(lane) = zw;
         if constexpr (TWO) {
-            if (lane < R - 64) vec[64 + lane] = zw2;
+            if (lane < R - 64) VEC(64 + lane) = zw2;
         }
         wave_sync();
-        zw = (lane >= 16) ? vec[lane - 16] : T(0);
-        if constexpr (TWO) zw2 = (lane < R - 64) ? vec[48 + lane] : T(0);
+        zw = (lane >= 16) ? VEC(max(lane - 16, 0)) : T(0);
+        if constexpr (TWO) zw2 = (lane < R - 64) ? VEC(min(48 + lane, R - 1)) : T(0);
         wave_sync();
         // column-major copy of the panel in LDS (reusing the panel buffer): rows below
         // the panel hold L(r, c) z_r, the 16 panel rows hold L(r, c) itself
@@ -966,14 +977,14 @@ __global__ __launch_bounds__(64) void local_band_mfma_kernel(
 #pragma unroll
             for (int j = 0; j < RQ; ++j) acc += src[j];
             acc = quad_sum(acc);
-            if (qq == 0) colsum[c] = acc;
+            if (qq == 0) CSUM(c) = acc;
         }
         T lt[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) lt[r] = bt[lr][r];
         wave_sync();
         // unit upper triangular solve with the panel's 16 x 16 block, one row per step
-        T val = zc0 - colsum[lr];
+        T val = zc0 - CSUM(lr);
 #pragma unroll
         for (int r = 15; r > 0; --r) {
             const T zr = MT::bcast(val, r);
