@@ -646,20 +646,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T,
     // panel, -> MFMA operands; reused column-major by the backward sweep), nrowT (the
     // tile-row entering the window, column-major with rows permuted so that the four
     // accumulator rows of a lane are adjacent), vec (shift of the right-hand side)
-    // (strides keep 16-byte alignment and spread lanes over banks; the FP64 sizes keep a
-    // workgroup under 20 KB so that eight fit in one compute unit's LDS)
-    // (the FP32 64-row instance fits in 10 KB, so that 16 systems share a compute unit)
-    constexpr int PS = TWO ? (sizeof(T) == 4 ? 124 : 114) : (sizeof(T) == 4 ? 80 : 82);
+    // (strides keep 16-byte alignment and spread lanes over banks: with PS = 84 and
+    // QS = 20 FP32 words, the 16-byte accesses of 16 consecutive rows (lr * PS, lr * QS)
+    // fall on distinct banks; the FP64 sizes keep a workgroup under 20 KB so that eight
+    // fit in one compute unit's LDS)
+    constexpr int PS = TWO ? (sizeof(T) == 4 ? 124 : 114) : (sizeof(T) == 4 ? 84 : 82);
     constexpr int QS = sizeof(T) == 4 ? 20 : 18;
     static_assert(16 * PS >= R * QS, "pan aliases panT");
-    static_assert(QS >= 18, "vec and colsum live in the padding columns 16 and 17 of nrowT");
     __shared__ __align__(16) T panT[16][PS];
     __shared__ __align__(16) T nrowT[R][QS];
     T (*pan)[QS] = reinterpret_cast<T (*)[QS]>(&panT[0][0]);   // free once a[] is read
-    // vec (R values) and colsum (16) use the padding columns of nrowT, which the tile-row
-    // placement never touches
-    auto VEC = [&](const int r) -> T& { return nrowT[r][16]; };
-    auto CSUM = [&](const int c) -> T& { return nrowT[c][17]; };
+    __shared__ T vec[R];
+    __shared__ T colsum[16];
+    auto VEC = [&](const int r) -> T& { return vec[r]; };
+    auto CSUM = [&](const int c) -> T& { return colsum[c]; };
     const int sys = blockIdx.x;
     // mode 0: shift lambda_i, and negflag[sys] records a negative pivot (K_l - lambda_i M_l
     // indefinite); mode 1: only the recorded systems, again with shift 0
