@@ -58,6 +58,10 @@ def local_kernel_name(band: int, slots: int) -> str:
     return "local_ldlt_kernel<float>"
 
 
+# kernel of each SpMM lane layout (bpjd_stats.spmm_form)
+SPMM_KERNELS = {1: "spmm_km_pair_kernel", 2: "spmm_km_kernel", 3: "spmm_km_flat_kernel"}
+
+
 def spmm_bytes(n: int, nnz: int, ncols: int) -> float:
     """Algorithmic HBM bytes of one fused [K;M] X launch: row pointers, column
     indices, (K, M) value pairs, the X block once, KX and MX written once."""
@@ -518,28 +522,35 @@ def main():
         lam_w = torch.empty(k, dtype=torch.float64, device="cuda")
         X_w = torch.empty((mesh.n, k), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
-        reps = 2
-        t0 = time.perf_counter()
+        reps = 3                     # median of the repetitions (a device allocation can stall once)
+        times = []
         for _ in range(reps):
+            t0 = time.perf_counter()
             pr = make(K=Kd, M=Md, precision=B.PREC_MIXED)
             pr.solve(lam_w, X_w, mem=B.MEM_DEVICE)
             pr.close()
-        torch.cuda.synchronize()
-        dev_ms = (time.perf_counter() - t0) / reps * 1e3
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        dev_ms = float(np.median(times))
         whole_dev = {"ms_per_solve": dev_ms, "value": k / (dev_ms * 1e-3), "unit": "eigenpairs/s",
+                     "runs_ms": [round(x, 1) for x in times],
                      "span": "bpjd_problem_create from device-resident CSR (host planning included) to eigenpairs "
-                             "in device memory, mixed"}
+                             "in device memory, mixed; median of the runs"}
         print(f"[bench] whole job, device-resident inputs: {dev_ms:.1f} ms/solve", file=sys.stderr, flush=True)
         del Kd, Md
         # from host CSR to eigenpairs in host memory (PCIe transfers included)
-        t0 = time.perf_counter()
+        times = []
         for _ in range(reps):
+            t0 = time.perf_counter()
             pr = make(precision=B.PREC_MIXED)
             pr.solve()
             pr.close()
-        host_ms = (time.perf_counter() - t0) / reps * 1e3
+            times.append((time.perf_counter() - t0) * 1e3)
+        host_ms = float(np.median(times))
         host_inclusive = {"ms_per_solve": host_ms, "value": k / (host_ms * 1e-3), "unit": "eigenpairs/s",
-                          "span": "bpjd_problem_create from host CSR to eigenpairs in host memory, mixed"}
+                          "runs_ms": [round(x, 1) for x in times],
+                          "span": "bpjd_problem_create from host CSR to eigenpairs in host memory, mixed; median of "
+                                  "the runs"}
         print(f"[bench] host-inclusive: {host_ms:.1f} ms/solve", file=sys.stderr, flush=True)
 
     # dominant kernel of the mixed solve (the batched local LDL^T factor + solve) and its
@@ -557,7 +568,7 @@ def main():
         spmm_avg_ms = ph["spmm"] / max(1, cnt["spmm"])
         sb = spmm_bytes(mesh.n, mesh.K.nnz, s)
         roof_spmm = {"bound": "hbm", "achieved": sb / (spmm_avg_ms * 1e-3) / 1e9, "peak": PEAK["hbm_GBs"],
-                     "unit": "GB/s", "kernel": "spmm_km_pair_kernel" if s % 2 == 0 else "spmm_km_kernel",
+                     "unit": "GB/s", "kernel": SPMM_KERNELS.get(stp.get("spmm_form"), "unknown"),
                      "avg_launch_ms": spmm_avg_ms, "algorithmic_per_launch": sb, "source": "untimed profiled solve"}
         roof_spmm["frac"] = roof_spmm["achieved"] / roof_spmm["peak"]
 

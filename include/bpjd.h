@@ -158,7 +158,16 @@ typedef struct {
                                    bandwidths above 80 or more than 8 lower entries per local row):
                                    0 (default) = the autotuner's choice (256 without autotune), or
                                    exactly 64, 128 or 256.  The arithmetic is the same for all. */
+    int32_t spmm_form;          /* lane layout of the fused K/M SpMM: 0 (default) = the autotuner's
+                                   choice (BPJD_SPMM_PAIRS without autotune); or exactly one of
+                                   BPJD_SPMM_*.  Every form adds a row's entries in the same order,
+                                   so the results are the same bit for bit. */
 } bpjd_opts;
+
+/* SpMM lane layouts (bpjd_opts.spmm_form) */
+#define BPJD_SPMM_PAIRS   1     /* two adjacent columns per lane (even block sizes; else as COLUMN) */
+#define BPJD_SPMM_COLUMN  2     /* one column per lane, a power-of-two group of lanes per row */
+#define BPJD_SPMM_FLAT    3     /* one lane per (row, column), lanes numbered row by row */
 
 /* phases timed when bpjd_opts.profile = 1 (profile = 2: BPJD_PHASE_LOCAL only) */
 #define BPJD_PHASE_LOCAL     0  /* batched local factor + solve kernel */
@@ -188,11 +197,25 @@ typedef struct {
     double  queue_ms;           /* served requests: submission to admission (0 for bpjd_solve) */
     double  latency_ms;         /* served requests: submission to result in host memory */
     int32_t graph_iterations;   /* outer iterations replayed from a captured HIP graph */
+    int32_t spmm_form;          /* SpMM lane layout the solve used (BPJD_SPMM_*) */
 } bpjd_stats;
 
 /* Default options: k as given, guard 0, max_iter 500, tol 1e-8, residual
  * stop rule, UU subspace, mixed precision, no initial block. */
 void bpjd_opts_default(bpjd_opts* o, int32_t k);
+
+/* Trace.  When the environment variable BPJD_TRACE is set as a problem is created
+ * ("1" or "stderr": standard error; any other value: a file the lines are appended
+ * to), the library writes one JSON object per line:
+ *   {"event": "create", "stage": ..., "ms": ...}        host planning stages;
+ *   {"event": "iteration", "problem", "it", "fresh", "rho_max", "stop_value",
+ *    "lambda": [s values], "rho": [k values]}          every residual read-back;
+ *   {"event": "rayleigh_ritz", "problem", "it", "m", "dropped_in", "dropped_out",
+ *    "theta": [m values]}                               every UU/U Rayleigh-Ritz step;
+ *   {"event": "solve", "problem", "iterations", "converged", "stop_value",
+ *    "setup_ms", "iterate_ms"}                          the end of each solve.
+ * A traced problem launches its iterations directly (no graph replay) and
+ * synchronises its stream once per Rayleigh-Ritz step. */
 
 /* ---- context ----------------------------------------------------------- */
 /* Device memory provider of a context (for instance a framework's caching

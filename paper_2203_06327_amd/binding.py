@@ -25,6 +25,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 STOP_RESIDUAL, STOP_PAPER = 0, 1
 CELL_SQUARE, CELL_TRIANGLE = 0, 1
 SUBSPACE_UU, SUBSPACE_U, SUBSPACE_GROW = 0, 1, 2
+SPMM_PAIRS, SPMM_COLUMN, SPMM_FLAT = 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -57,7 +58,8 @@ class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("guard", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("stop_rule", C.c_int32), ("subspace", C.c_int32), ("precision", C.c_int32),
                 ("n_init", C.c_int32), ("X_init", C.c_void_p), ("profile", C.c_int32), ("graphs", C.c_int32),
-                ("autotune", C.c_int32), ("local_threads", C.c_int32)]
+                ("autotune", C.c_int32), ("local_threads", C.c_int32),
+                ("spmm_form", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -66,7 +68,8 @@ class Stats(C.Structure):
                 ("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("max_local", C.c_int32),
                 ("max_band", C.c_int32), ("residuals", C.c_double * 64),
                 ("phase_ms", C.c_double * 8), ("phase_count", C.c_int32 * 8),
-                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("graph_iterations", C.c_int32)]
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("graph_iterations", C.c_int32),
+                ("spmm_form", C.c_int32)]
 
     def to_dict(self) -> dict:
         arrays = ("residuals", "phase_ms", "phase_count")
@@ -277,7 +280,7 @@ def _csr(A, keep: list) -> Csr:
 def make_opts(k: int, guard: int = 0, tol: float = 1e-8, max_iter: int = 500, stop_rule: int = STOP_RESIDUAL,
               subspace: int = SUBSPACE_UU, precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None,
               keep: Optional[list] = None, profile: int = 0, graphs: bool = True, autotune: bool = True,
-              local_threads: int = 0) -> Opts:
+              local_threads: int = 0, spmm_form: int = 0) -> Opts:
     o = Opts()
     lib().bpjd_opts_default(C.byref(o), k)
     o.guard, o.tol, o.max_iter, o.stop_rule, o.subspace, o.precision = guard, tol, max_iter, stop_rule, subspace, precision
@@ -285,6 +288,7 @@ def make_opts(k: int, guard: int = 0, tol: float = 1e-8, max_iter: int = 500, st
     o.graphs = 1 if graphs else 0
     o.autotune = 1 if autotune else 0
     o.local_threads = int(local_threads)
+    o.spmm_form = int(spmm_form)
     if X_init is not None:
         Xi = np.ascontiguousarray(X_init, dtype=np.float64)
         if keep is not None:
@@ -300,11 +304,11 @@ class Problem:
     def __init__(self, ctx: Context, K, M, *, dd=None, geom=None, k: int, guard: int = 0, tol: float = 1e-8,
                  max_iter: int = 500, stop_rule: int = STOP_RESIDUAL, subspace: int = SUBSPACE_UU,
                  precision: int = PREC_MIXED, X_init: Optional[np.ndarray] = None, profile: int = 0,
-                 graphs: bool = True, autotune: bool = True, local_threads: int = 0):
+                 graphs: bool = True, autotune: bool = True, local_threads: int = 0, spmm_form: int = 0):
         keep: list = []
         Kc, Mc = _csr(K, keep), _csr(M, keep)
         opts = make_opts(k, guard, tol, max_iter, stop_rule, subspace, precision, X_init, keep, profile, graphs,
-                         autotune, local_threads)
+                         autotune, local_threads, spmm_form)
         h = C.c_void_p()
         if geom is not None:
             g = _geom(geom, keep)

@@ -17,6 +17,8 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <climits>
+#include <thread>
 
 #include "common.h"
 
@@ -33,6 +35,42 @@ static constexpr int kGrowMaxDim = 1024;
 static constexpr int kBlockedMaxBand = 48;       // 64-row window (4 tile-rows)
 static constexpr int kBlockedWideMaxBand = 80;   // 96-row window (6 tile-rows)
 static constexpr int kBlockedMaxSlots = 8;
+
+// Host planning runs its per-row, per-dof and per-subdomain loops on up to 16 threads.
+// Every loop writes disjoint outputs, or per-item results merged in item order, so the
+// plan does not depend on the number of threads.
+static int planning_threads() {
+    static const int nt = [] {
+        const unsigned h = std::thread::hardware_concurrency();
+        return (int)std::min(16u, std::max(1u, h));
+    }();
+    return nt;
+}
+
+// f(lo, hi, t) over [0, n) in contiguous chunks, chunk t on its own thread; small ranges
+// stay on the calling thread.
+template <class F>
+static void parallel_chunks(long long n, F&& f, long long min_chunk = 8192) {
+    const int nt = (int)std::min<long long>(planning_threads(), std::max<long long>(1, n / min_chunk));
+    if (nt <= 1) {
+        f(0LL, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) th.emplace_back([&f, n, nt, t] { f(n * t / nt, n * (t + 1) / nt, t); });
+    f(0LL, n / nt, 0);
+    for (auto& x : th) x.join();
+}
+
+// The lowest failing item over the chunks of a parallel check (INT_MAX: none).
+struct FirstBad {
+    std::vector<std::pair<int, int>> at = std::vector<std::pair<int, int>>(planning_threads(), {INT_MAX, 0});
+    void set(int t, int item, int kind) {
+        if (item < at[t].first) at[t] = {item, kind};
+    }
+    std::pair<int, int> get() const { return *std::min_element(at.begin(), at.end()); }
+};
 
 void set_error(const std::string& msg) {
     g_last_error = msg;
@@ -51,6 +89,64 @@ CtxScope::CtxScope(bpjd_ctx* c) : prev(g_scope_ctx) { g_scope_ctx = c; }
 CtxScope::~CtxScope() { g_scope_ctx = prev; }
 
 // ---- device memory ----------------------------------------------------------------
+// ---- trace: JSON lines ------------------------------------------------------------
+// Enabled by the environment variable BPJD_TRACE, read when a problem is created (a
+// problem keeps the setting it was created with): "1" or "stderr" writes to stderr, any
+// other value names a file the lines are appended to.
+static std::mutex g_trace_mu;
+static FILE* g_trace_f = nullptr;
+static std::string g_trace_target;    // value of BPJD_TRACE the stream was opened for
+
+bool trace_on() {
+    std::lock_guard<std::mutex> g(g_trace_mu);
+    const char* v = std::getenv("BPJD_TRACE");
+    const std::string target = v ? v : "";
+    if (target != g_trace_target) {
+        if (g_trace_f && g_trace_f != stderr) std::fclose(g_trace_f);
+        g_trace_f = nullptr;
+        g_trace_target = target;
+        if (target == "1" || target == "stderr") g_trace_f = stderr;
+        else if (!target.empty()) g_trace_f = std::fopen(target.c_str(), "a");
+    }
+    return g_trace_f != nullptr;
+}
+
+// Writes one line to the stream of the last trace_on() that found tracing on (a problem
+// created while tracing keeps writing there, to stderr if the stream was closed since).
+void trace_line(const std::string& json) {
+    std::lock_guard<std::mutex> g(g_trace_mu);
+    FILE* f = g_trace_f ? g_trace_f : stderr;
+    std::fputs(json.c_str(), f);
+    std::fputc('\n', f);
+    std::fflush(f);
+}
+
+// Wall time of the host planning stages of one problem creation
+struct StageClock {
+    bool on = trace_on();
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char* stage) {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "{\"event\": \"create\", \"stage\": \"%s\", \"ms\": %.3f}", stage,
+                      std::chrono::duration<double, std::milli>(now - t).count());
+        trace_line(buf);
+        t = now;
+    }
+};
+
+static std::string json_doubles(const double* v, int count, const char* fmt = "%.15g") {
+    std::string o = "[";
+    char buf[40];
+    for (int q = 0; q < count; ++q) {
+        std::snprintf(buf, sizeof buf, fmt, v[q]);
+        if (q) o += ", ";
+        o += std::isfinite(v[q]) ? buf : "null";
+    }
+    return o + "]";
+}
+
 void* DevArena::alloc(size_t bytes) {
     const size_t b = round(bytes);
     std::lock_guard<std::mutex> g(mu);
@@ -164,15 +260,24 @@ static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out, hipStream
         std::memcpy(out.col.data(), A->col, sizeof(int) * A->nnz);
         std::memcpy(out.val.data(), A->val, sizeof(double) * A->nnz);
     }
-    for (int i = 0; i < n; ++i) {
-        for (int p = out.ptr[i]; p < out.ptr[i + 1]; ++p) {
-            const int c = out.col[p];
-            if (c < 0 || c >= n) return fail(BPJD_ERR_CSR, std::string(name) + ": column index out of range");
-            if (p > out.ptr[i] && c <= out.col[p - 1])
-                return fail(BPJD_ERR_CSR, std::string(name) + ": columns not strictly increasing in a row");
-            if (!std::isfinite(out.val[p])) return fail(BPJD_ERR_CSR, std::string(name) + ": non-finite value");
+    FirstBad bad;
+    parallel_chunks(n, [&](long long lo, long long hi, int t) {
+        for (int i = (int)lo; i < (int)hi; ++i) {
+            for (int p = out.ptr[i]; p < out.ptr[i + 1]; ++p) {
+                const int c = out.col[p];
+                const int kind = (c < 0 || c >= n) ? 1 : (p > out.ptr[i] && c <= out.col[p - 1]) ? 2
+                                                        : !std::isfinite(out.val[p]) ? 3 : 0;
+                if (kind) {
+                    bad.set(t, i, kind);
+                    return;
+                }
+            }
         }
-    }
+    });
+    const int kind = bad.get().second;
+    if (kind == 1) return fail(BPJD_ERR_CSR, std::string(name) + ": column index out of range");
+    if (kind == 2) return fail(BPJD_ERR_CSR, std::string(name) + ": columns not strictly increasing in a row");
+    if (kind == 3) return fail(BPJD_ERR_CSR, std::string(name) + ": non-finite value");
     return BPJD_OK;
 }
 
@@ -183,36 +288,56 @@ struct Pattern {
     std::vector<long long> Kmap, Mmap;
 };
 
+// Row i of the union pattern: merge of the sorted columns of K and M; with emit, the
+// columns go to out and the positions of K's and M's entries to Kmap / Mmap.
+template <bool emit>
+static int union_row(const HostCSR& K, const HostCSR& M, int i, int* out, long long pos, long long* Kmap,
+                     long long* Mmap) {
+    int a = K.ptr[i], b = M.ptr[i], cnt = 0;
+    const int ae = K.ptr[i + 1], be = M.ptr[i + 1];
+    while (a < ae || b < be) {
+        const int c = (b >= be || (a < ae && K.col[a] < M.col[b])) ? K.col[a] : M.col[b];
+        if (emit) {
+            if (a < ae && K.col[a] == c) Kmap[a] = pos + cnt;
+            if (b < be && M.col[b] == c) Mmap[b] = pos + cnt;
+            out[cnt] = c;
+        }
+        if (a < ae && K.col[a] == c) ++a;
+        if (b < be && M.col[b] == c) ++b;
+        ++cnt;
+    }
+    return cnt;
+}
+
 static int build_union(const HostCSR& K, const HostCSR& M, Pattern& U) {
     const int n = K.n;
     U.n = n;
     U.ptr.assign(n + 1, 0);
-    U.col.clear();
-    U.col.reserve(std::max(K.col.size(), M.col.size()));
+    parallel_chunks(n, [&](long long lo, long long hi, int) {
+        for (int i = (int)lo; i < (int)hi; ++i) U.ptr[i + 1] = union_row<false>(K, M, i, nullptr, 0, nullptr, nullptr);
+    });
+    for (int i = 0; i < n; ++i) U.ptr[i + 1] += U.ptr[i];
+    U.col.resize(U.ptr[n]);
     U.Kmap.resize(K.col.size());
     U.Mmap.resize(M.col.size());
-    for (int i = 0; i < n; ++i) {
-        int a = K.ptr[i], b = M.ptr[i];
-        const int ae = K.ptr[i + 1], be = M.ptr[i + 1];
-        while (a < ae || b < be) {
-            int c;
-            if (b >= be || (a < ae && K.col[a] < M.col[b])) c = K.col[a];
-            else c = M.col[b];
-            const long long pos = (long long)U.col.size();
-            if (a < ae && K.col[a] == c) U.Kmap[a++] = pos;
-            if (b < be && M.col[b] == c) U.Mmap[b++] = pos;
-            U.col.push_back(c);
-        }
-        U.ptr[i + 1] = (int)U.col.size();
-    }
+    parallel_chunks(n, [&](long long lo, long long hi, int) {
+        for (int i = (int)lo; i < (int)hi; ++i)
+            union_row<true>(K, M, i, U.col.data() + U.ptr[i], U.ptr[i], U.Kmap.data(), U.Mmap.data());
+    });
     // structural symmetry of the union pattern
-    for (int i = 0; i < n; ++i) {
-        for (int p = U.ptr[i]; p < U.ptr[i + 1]; ++p) {
-            const int j = U.col[p];
-            if (!std::binary_search(U.col.begin() + U.ptr[j], U.col.begin() + U.ptr[j + 1], i))
-                return fail(BPJD_ERR_CSR, "pattern of K + M is not symmetric");
+    FirstBad bad;
+    parallel_chunks(n, [&](long long lo, long long hi, int t) {
+        for (int i = (int)lo; i < (int)hi; ++i) {
+            for (int p = U.ptr[i]; p < U.ptr[i + 1]; ++p) {
+                const int j = U.col[p];
+                if (!std::binary_search(U.col.begin() + U.ptr[j], U.col.begin() + U.ptr[j + 1], i)) {
+                    bad.set(t, i, 1);
+                    return;
+                }
+            }
         }
-    }
+    });
+    if (bad.get().second) return fail(BPJD_ERR_CSR, "pattern of K + M is not symmetric");
     return BPJD_OK;
 }
 
@@ -232,53 +357,73 @@ static void build_p1_prolongation(int n, const double* xy, const std::vector<dou
     // free coarse vertices: a fine dof lies on the vertex
     std::vector<int> vnum((size_t)(ncx + 1) * (ncy + 1), -1);
     std::vector<char> hit((size_t)(ncx + 1) * (ncy + 1), 0);
-    for (int d = 0; d < n; ++d) {
-        const double x = xy[2 * d], y = xy[2 * d + 1];
-        const int a = (int)(std::lower_bound(cx.begin(), cx.end(), x - tol) - cx.begin());
-        const int b = (int)(std::lower_bound(cy.begin(), cy.end(), y - tol) - cy.begin());
-        if (a >= 1 && a <= ncx - 1 && b >= 1 && b <= ncy - 1 && std::fabs(cx[a] - x) <= tol &&
-            std::fabs(cy[b] - y) <= tol)
-            hit[(size_t)b * (ncx + 1) + a] = 1;
-    }
+    std::vector<int> onv(n, -1);      // interior coarse vertex a dof sits on, or -1
+    parallel_chunks(n, [&](long long lo, long long hi, int) {
+        for (int d = (int)lo; d < (int)hi; ++d) {
+            const double x = xy[2 * d], y = xy[2 * d + 1];
+            const int a = (int)(std::lower_bound(cx.begin(), cx.end(), x - tol) - cx.begin());
+            const int b = (int)(std::lower_bound(cy.begin(), cy.end(), y - tol) - cy.begin());
+            if (a >= 1 && a <= ncx - 1 && b >= 1 && b <= ncy - 1 && std::fabs(cx[a] - x) <= tol &&
+                std::fabs(cy[b] - y) <= tol)
+                onv[d] = b * (ncx + 1) + a;
+        }
+    });
+    for (int d = 0; d < n; ++d)
+        if (onv[d] >= 0) hit[onv[d]] = 1;
     nH = 0;
     for (int b = 1; b < ncy; ++b)
         for (int a = 1; a < ncx; ++a)
             if (hit[(size_t)b * (ncx + 1) + a]) vnum[(size_t)b * (ncx + 1) + a] = nH++;
+    // at most three entries per dof (the vertices of its coarse triangle), sorted by
+    // coarse index, then compacted
+    std::vector<int> ecol((size_t)3 * n);
+    std::vector<double> eval((size_t)3 * n);
     P.n = n;
     P.ptr.assign(n + 1, 0);
-    P.col.clear();
-    P.val.clear();
-    for (int d = 0; d < n; ++d) {
-        const double x = xy[2 * d], y = xy[2 * d + 1];
-        int a = (int)(std::upper_bound(cx.begin(), cx.end(), x) - cx.begin()) - 1;
-        int b = (int)(std::upper_bound(cy.begin(), cy.end(), y) - cy.begin()) - 1;
-        a = std::min(std::max(a, 0), ncx - 1);
-        b = std::min(std::max(b, 0), ncy - 1);
-        const double xi = (x - cx[a]) / (cx[a + 1] - cx[a]);
-        const double eta = (y - cy[b]) / (cy[b + 1] - cy[b]);
-        int va[3], vb[3];
-        double w[3];
-        if (xi >= eta) {
-            va[0] = a; vb[0] = b; w[0] = 1.0 - xi;
-            va[1] = a + 1; vb[1] = b; w[1] = xi - eta;
-            va[2] = a + 1; vb[2] = b + 1; w[2] = eta;
-        } else {
-            va[0] = a; vb[0] = b; w[0] = 1.0 - eta;
-            va[1] = a + 1; vb[1] = b + 1; w[1] = xi;
-            va[2] = a; vb[2] = b + 1; w[2] = eta - xi;
+    parallel_chunks(n, [&](long long lo, long long hi, int) {
+        for (int d = (int)lo; d < (int)hi; ++d) {
+            const double x = xy[2 * d], y = xy[2 * d + 1];
+            int a = (int)(std::upper_bound(cx.begin(), cx.end(), x) - cx.begin()) - 1;
+            int b = (int)(std::upper_bound(cy.begin(), cy.end(), y) - cy.begin()) - 1;
+            a = std::min(std::max(a, 0), ncx - 1);
+            b = std::min(std::max(b, 0), ncy - 1);
+            const double xi = (x - cx[a]) / (cx[a + 1] - cx[a]);
+            const double eta = (y - cy[b]) / (cy[b + 1] - cy[b]);
+            int va[3], vb[3];
+            double w[3];
+            if (xi >= eta) {
+                va[0] = a; vb[0] = b; w[0] = 1.0 - xi;
+                va[1] = a + 1; vb[1] = b; w[1] = xi - eta;
+                va[2] = a + 1; vb[2] = b + 1; w[2] = eta;
+            } else {
+                va[0] = a; vb[0] = b; w[0] = 1.0 - eta;
+                va[1] = a + 1; vb[1] = b + 1; w[1] = xi;
+                va[2] = a; vb[2] = b + 1; w[2] = eta - xi;
+            }
+            std::pair<int, double> ent[3];
+            int ne = 0;
+            for (int k = 0; k < 3; ++k) {
+                const int c = vnum[(size_t)vb[k] * (ncx + 1) + va[k]];
+                if (c >= 0 && w[k] != 0.0) ent[ne++] = {c, w[k]};
+            }
+            std::sort(ent, ent + ne);
+            for (int k = 0; k < ne; ++k) {
+                ecol[(size_t)3 * d + k] = ent[k].first;
+                eval[(size_t)3 * d + k] = ent[k].second;
+            }
+            P.ptr[d + 1] = ne;
         }
-        std::vector<std::pair<int, double>> ent;
-        for (int k = 0; k < 3; ++k) {
-            const int c = vnum[(size_t)vb[k] * (ncx + 1) + va[k]];
-            if (c >= 0 && w[k] != 0.0) ent.push_back({c, w[k]});
-        }
-        std::sort(ent.begin(), ent.end());
-        for (auto& e : ent) {
-            P.col.push_back(e.first);
-            P.val.push_back(e.second);
-        }
-        P.ptr[d + 1] = (int)P.col.size();
-    }
+    });
+    for (int d = 0; d < n; ++d) P.ptr[d + 1] += P.ptr[d];
+    P.col.resize(P.ptr[n]);
+    P.val.resize(P.ptr[n]);
+    parallel_chunks(n, [&](long long lo, long long hi, int) {
+        for (int d = (int)lo; d < (int)hi; ++d)
+            for (int k = 0; k < P.ptr[d + 1] - P.ptr[d]; ++k) {
+                P.col[P.ptr[d] + k] = ecol[(size_t)3 * d + k];
+                P.val[P.ptr[d] + k] = eval[(size_t)3 * d + k];
+            }
+    });
 }
 
 // Subdomains: each closed coarse cell (cell_shape BPJD_CELL_SQUARE), or each of the
@@ -319,30 +464,41 @@ static int build_geom_subdomains(const Pattern& U, const double* xy, const std::
             }
         }
     }
-    std::vector<int> mark(n, -1), frontier, next;
-    sptr.assign(1, 0);
-    sidx.clear();
-    for (size_t c = 0; c < cell.size(); ++c) {
-        std::vector<int> members = cell[c];
-        for (int d : members) mark[d] = (int)c;
-        frontier = members;
-        for (int layer = 1; layer < layers; ++layer) {
-            next.clear();
-            for (int d : frontier) {
-                for (int q = U.ptr[d]; q < U.ptr[d + 1]; ++q) {
-                    const int e = U.col[q];
-                    if (mark[e] != (int)c) {
-                        mark[e] = (int)c;
-                        members.push_back(e);
-                        next.push_back(e);
+    // each cell grows by (layers - 1) graph layers; cells in parallel, a mark array per thread
+    const long long ncell = (long long)cell.size();
+    std::vector<std::vector<int>> grown(ncell);
+    std::vector<std::vector<int>> marks(planning_threads());
+    parallel_chunks(ncell, [&](long long lo, long long hi, int t) {
+        std::vector<int>& mark = marks[t];
+        mark.assign(n, -1);
+        std::vector<int> frontier, next;
+        for (long long c = lo; c < hi; ++c) {
+            std::vector<int> members = cell[c];
+            for (int d : members) mark[d] = (int)c;
+            frontier = members;
+            for (int layer = 1; layer < layers; ++layer) {
+                next.clear();
+                for (int d : frontier) {
+                    for (int q = U.ptr[d]; q < U.ptr[d + 1]; ++q) {
+                        const int e = U.col[q];
+                        if (mark[e] != (int)c) {
+                            mark[e] = (int)c;
+                            members.push_back(e);
+                            next.push_back(e);
+                        }
                     }
                 }
+                frontier.swap(next);
             }
-            frontier.swap(next);
+            std::sort(members.begin(), members.end());
+            grown[c].swap(members);
         }
-        if (members.empty()) continue;
-        std::sort(members.begin(), members.end());
-        sidx.insert(sidx.end(), members.begin(), members.end());
+    }, 1);
+    sptr.assign(1, 0);
+    sidx.clear();
+    for (long long c = 0; c < ncell; ++c) {
+        if (grown[c].empty()) continue;
+        sidx.insert(sidx.end(), grown[c].begin(), grown[c].end());
         sptr.push_back((int)sidx.size());
     }
     return BPJD_OK;
@@ -499,9 +655,10 @@ static int device_layout(bpjd_problem* p, const HostPlan& h, Op&& op) {
 // Everything after the decomposition is known: local band layout, reverse
 // map, Galerkin patterns.  Builds the problem's host plan and its device
 // footprint; materialize_problem allocates and uploads.
-static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, const Pattern& U, const HostCSR& P,
+// K, M, U and P are consumed (their arrays move into the plan).
+static int finish_create(bpjd_ctx* ctx, HostCSR& K, HostCSR& M, Pattern& U, HostCSR& P,
                          int nH, std::vector<int>& sptr, std::vector<int>& sidx, const bpjd_opts* opts,
-                         bpjd_problem** out) {
+                         bpjd_problem** out, StageClock& clk) {
     const int n = U.n;
     const int nsub = (int)sptr.size() - 1;
     if (nsub < 1) return fail(BPJD_ERR_DD, "no subdomains");
@@ -523,45 +680,85 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     if (opts->local_threads != 0 && opts->local_threads != 64 && opts->local_threads != 128 &&
         opts->local_threads != 256)
         return fail(BPJD_ERR_ARG, "local_threads must be 0, 64, 128 or 256");
+    if (opts->spmm_form < 0 || opts->spmm_form > BPJD_SPMM_FLAT)
+        return fail(BPJD_ERR_ARG, "spmm_form must be 0 or one of BPJD_SPMM_*");
     if (!(opts->tol > 0.0) || opts->max_iter < 0) return fail(BPJD_ERR_ARG, "bad tol or max_iter");
 
-    // coverage and local orderings (ascending global index)
-    std::vector<int> cover(n, 0);
-    for (int l = 0; l < nsub; ++l) {
-        if (sptr[l + 1] <= sptr[l]) return fail(BPJD_ERR_DD, "empty subdomain");
-        std::sort(sidx.begin() + sptr[l], sidx.begin() + sptr[l + 1]);
-        for (int q = sptr[l]; q < sptr[l + 1]; ++q) {
-            if (sidx[q] < 0 || sidx[q] >= n) return fail(BPJD_ERR_DD, "subdomain index out of range");
-            if (q > sptr[l] && sidx[q] == sidx[q - 1]) return fail(BPJD_ERR_DD, "duplicate dof in a subdomain");
-            cover[sidx[q]]++;
-        }
-    }
-    for (int d = 0; d < n; ++d)
-        if (!cover[d]) return fail(BPJD_ERR_DD, "dof " + std::to_string(d) + " lies in no subdomain");
-
-    const long long sumN = sptr[nsub];
-    std::vector<int> lptr(sumN + 1, 0), ldd, lpos, bw(nsub, 0);
-    std::vector<int> gl(n, -1);
-    int maxN = 0, maxBW = 0;
-    for (int l = 0; l < nsub; ++l) {
-        const int off = sptr[l], nl = sptr[l + 1] - off;
-        maxN = std::max(maxN, nl);
-        for (int r = 0; r < nl; ++r) gl[sidx[off + r]] = r;
-        for (int r = 0; r < nl; ++r) {
-            const int g = sidx[off + r];
-            for (int p = U.ptr[g]; p < U.ptr[g + 1]; ++p) {
-                const int c = gl[U.col[p]];
-                if (c >= 0 && c <= r) {
-                    ldd.push_back(r - c);
-                    lpos.push_back(p);
-                    bw[l] = std::max(bw[l], r - c);
+    // coverage and local orderings (ascending global index); subdomains in parallel
+    {
+        FirstBad bad;
+        parallel_chunks(nsub, [&](long long lo, long long hi, int t) {
+            for (int l = (int)lo; l < (int)hi; ++l) {
+                if (sptr[l + 1] <= sptr[l]) {
+                    bad.set(t, l, 1);
+                    return;
+                }
+                std::sort(sidx.begin() + sptr[l], sidx.begin() + sptr[l + 1]);
+                for (int q = sptr[l]; q < sptr[l + 1]; ++q) {
+                    const int kind = (sidx[q] < 0 || sidx[q] >= n) ? 2 : (q > sptr[l] && sidx[q] == sidx[q - 1]) ? 3 : 0;
+                    if (kind) {
+                        bad.set(t, l, kind);
+                        return;
+                    }
                 }
             }
-            lptr[off + r + 1] = (int)ldd.size();
-        }
-        for (int r = 0; r < nl; ++r) gl[sidx[off + r]] = -1;
+        }, 16);
+        const int kind = bad.get().second;
+        if (kind == 1) return fail(BPJD_ERR_DD, "empty subdomain");
+        if (kind == 2) return fail(BPJD_ERR_DD, "subdomain index out of range");
+        if (kind == 3) return fail(BPJD_ERR_DD, "duplicate dof in a subdomain");
+    }
+    std::vector<int> cover(n, 0);
+    for (int q = 0; q < sptr[nsub]; ++q) cover[sidx[q]] = 1;
+    for (int d = 0; d < n; ++d)
+        if (!cover[d]) return fail(BPJD_ERR_DD, "dof " + std::to_string(d) + " lies in no subdomain");
+    clk.mark("cover");
+
+    // lower band entries of every local row (band offset and position in the union
+    // pattern): counted, then written, subdomains in parallel with a local-index map per
+    // thread
+    const long long sumN = sptr[nsub];
+    std::vector<int> lptr(sumN + 1, 0), ldd, lpos, bw(nsub, 0);
+    std::vector<std::vector<int>> gls(planning_threads());
+    auto band_pass = [&](const bool write) {
+        parallel_chunks(nsub, [&](long long lo, long long hi, int t) {
+            std::vector<int>& gl = gls[t];
+            if ((int)gl.size() != n) gl.assign(n, -1);
+            for (int l = (int)lo; l < (int)hi; ++l) {
+                const int off = sptr[l], nl = sptr[l + 1] - off;
+                for (int r = 0; r < nl; ++r) gl[sidx[off + r]] = r;
+                for (int r = 0; r < nl; ++r) {
+                    const int g = sidx[off + r];
+                    int cnt = 0;
+                    for (int p = U.ptr[g]; p < U.ptr[g + 1]; ++p) {
+                        const int c = gl[U.col[p]];
+                        if (c >= 0 && c <= r) {
+                            if (write) {
+                                ldd[lptr[off + r] + cnt] = r - c;
+                                lpos[lptr[off + r] + cnt] = p;
+                            } else {
+                                bw[l] = std::max(bw[l], r - c);
+                            }
+                            ++cnt;
+                        }
+                    }
+                    if (!write) lptr[off + r + 1] = cnt;
+                }
+                for (int r = 0; r < nl; ++r) gl[sidx[off + r]] = -1;
+            }
+        }, 16);
+    };
+    band_pass(false);
+    for (long long q = 0; q < sumN; ++q) lptr[q + 1] += lptr[q];
+    ldd.resize(lptr[sumN]);
+    lpos.resize(lptr[sumN]);
+    band_pass(true);
+    int maxN = 0, maxBW = 0;
+    for (int l = 0; l < nsub; ++l) {
+        maxN = std::max(maxN, sptr[l + 1] - sptr[l]);
         maxBW = std::max(maxBW, bw[l]);
     }
+    clk.mark("local_band");
     hipDeviceProp_t prop;
     BPJD_HIP(hipGetDeviceProperties(&prop, ctx->device));
     const size_t elt = opts->precision == BPJD_PREC_MIXED ? sizeof(float) : sizeof(double);
@@ -602,6 +799,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
         Ltot += blocked ? (long long)s * ((nl + 15) / 16) * 16 * bws : (long long)s * nl * (bw[l] + 1);
     }
 
+    clk.mark("reverse_map");
     // P^T and Galerkin patterns
     std::vector<int> PTptr(nH + 1, 0), PTcol(P.col.size());
     std::vector<double> PTval(P.col.size());
@@ -621,47 +819,56 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     }
     for (int a = 0; a < nH; ++a)
         if (PTptr[a + 1] == PTptr[a]) return fail(BPJD_ERR_DD, "coarse basis function with empty support");
-    std::vector<int> kpptr(n + 1, 0), kpcol;
-    std::vector<int> tmp;
-    // distinct columns are collected with a last-seen marker per coarse dof, then sorted
+    // patterns of K P (n x n_H) and of K_H = P^T K P: the distinct columns of each row
+    // are collected with a last-seen marker per coarse dof (a marker array per thread),
+    // counted in one pass and written sorted in a second
     // (a row of K P has a few dozen; gathering and sorting all the repeats was the bulk of
     // the host planning for elements with many dofs per vertex)
-    std::vector<int> mark(nH, -1);
-    for (int i = 0; i < n; ++i) {
-        tmp.clear();
+    std::vector<std::vector<int>> marks(planning_threads());
+    auto sparse_product_pattern = [&](const int rows, auto&& row_cols, std::vector<int>& ptr, std::vector<int>& cols) {
+        ptr.assign(rows + 1, 0);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                for (int i = 0; i < rows; ++i) ptr[i + 1] += ptr[i];
+                cols.resize(ptr[rows]);
+            }
+            parallel_chunks(rows, [&](long long lo, long long hi, int t) {
+                std::vector<int>& mark = marks[t];
+                mark.assign(nH, -1);
+                std::vector<int> tmp;
+                for (int i = (int)lo; i < (int)hi; ++i) {
+                    tmp.clear();
+                    row_cols(i, [&](const int c) {
+                        if (mark[c] != i) {
+                            mark[c] = i;
+                            tmp.push_back(c);
+                        }
+                    });
+                    if (pass == 0) {
+                        ptr[i + 1] = (int)tmp.size();
+                    } else {
+                        std::sort(tmp.begin(), tmp.end());
+                        std::copy(tmp.begin(), tmp.end(), cols.begin() + ptr[i]);
+                    }
+                }
+            }, 256);
+        }
+    };
+    std::vector<int> kpptr, kpcol, khptr, khcol;
+    sparse_product_pattern(n, [&](const int i, auto&& add) {
         for (int q = U.ptr[i]; q < U.ptr[i + 1]; ++q) {
             const int j = U.col[q];
-            for (int r = P.ptr[j]; r < P.ptr[j + 1]; ++r) {
-                const int c = P.col[r];
-                if (mark[c] != i) {
-                    mark[c] = i;
-                    tmp.push_back(c);
-                }
-            }
+            for (int r = P.ptr[j]; r < P.ptr[j + 1]; ++r) add(P.col[r]);
         }
-        std::sort(tmp.begin(), tmp.end());
-        kpcol.insert(kpcol.end(), tmp.begin(), tmp.end());
-        kpptr[i + 1] = (int)kpcol.size();
-    }
-    std::fill(mark.begin(), mark.end(), -1);
-    std::vector<int> khptr(nH + 1, 0), khcol;
-    for (int a = 0; a < nH; ++a) {
-        tmp.clear();
+    }, kpptr, kpcol);
+    sparse_product_pattern(nH, [&](const int a, auto&& add) {
         for (int q = PTptr[a]; q < PTptr[a + 1]; ++q) {
             const int i = PTcol[q];
-            for (int t = kpptr[i]; t < kpptr[i + 1]; ++t) {
-                const int c = kpcol[t];
-                if (mark[c] != a) {
-                    mark[c] = a;
-                    tmp.push_back(c);
-                }
-            }
+            for (int t = kpptr[i]; t < kpptr[i + 1]; ++t) add(kpcol[t]);
         }
-        std::sort(tmp.begin(), tmp.end());
-        khcol.insert(khcol.end(), tmp.begin(), tmp.end());
-        khptr[a + 1] = (int)khcol.size();
-    }
+    }, khptr, khcol);
 
+    clk.mark("galerkin_pattern");
     bpjd_problem* p = new bpjd_problem();
     p->ctx = ctx;
     p->opts = *opts;
@@ -678,16 +885,15 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
     p->maxC = maxC;
     p->nnzK = (long long)K.col.size();
     p->nnzM = (long long)M.col.size();
-    p->Kmap = U.Kmap;
-    p->Mmap = U.Mmap;
     p->n_init = opts->n_init;
     p->nnzKH = (int)khcol.size();
     for (int a2 = 0; a2 < nH; ++a2) p->maxPT = std::max(p->maxPT, PTptr[a2 + 1] - PTptr[a2]);
     p->bwH = 0;                                    // lower bandwidth of the coarse matrices
     for (int a = 0; a < nH; ++a)
         for (int q = khptr[a]; q < khptr[a + 1]; ++q) p->bwH = std::max(p->bwH, a - khcol[q]);
-    p->trace = std::getenv("BPJD_TRACE") != nullptr;
+    p->trace = trace_on();
     if (opts->local_threads) p->ldlt_threads = opts->local_threads;
+    if (opts->spmm_form) p->spmm_variant = opts->spmm_form - 1;
     p->h_bw = bw;
     p->h_nl.resize(nsub);
     for (int l = 0; l < nsub; ++l) p->h_nl[l] = sptr[l + 1] - sptr[l];
@@ -695,14 +901,19 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
 
     auto* h = new HostPlan();
     p->plan = h;
-    h->km.assign(p->nnz, make_double2(0.0, 0.0));
-    for (size_t q = 0; q < K.col.size(); ++q) h->km[U.Kmap[q]].x = K.val[q];
-    for (size_t q = 0; q < M.col.size(); ++q) h->km[U.Mmap[q]].y = M.val[q];
-    h->rowptr = U.ptr;
-    h->col = U.col;
-    h->Pptr = P.ptr;
-    h->Pcol = P.col;
-    h->Pval = P.val;
+    h->km.resize(p->nnz);
+    parallel_chunks(n, [&](long long lo, long long hi, int) {   // rows of the union pattern
+        for (long long q = U.ptr[lo]; q < U.ptr[hi]; ++q) h->km[q] = make_double2(0.0, 0.0);
+        for (long long q = K.ptr[lo]; q < K.ptr[hi]; ++q) h->km[U.Kmap[q]].x = K.val[q];
+        for (long long q = M.ptr[lo]; q < M.ptr[hi]; ++q) h->km[U.Mmap[q]].y = M.val[q];
+    });
+    p->Kmap = std::move(U.Kmap);
+    p->Mmap = std::move(U.Mmap);
+    h->rowptr = std::move(U.ptr);
+    h->col = std::move(U.col);
+    h->Pptr = std::move(P.ptr);
+    h->Pcol = std::move(P.col);
+    h->Pval = std::move(P.val);
     h->PTptr = std::move(PTptr);
     h->PTcol = std::move(PTcol);
     h->PTval = std::move(PTval);
@@ -737,6 +948,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
         return BPJD_OK;
     });
     p->footprint = bytes;
+    clk.mark("host_plan");
     *out = p;
     return BPJD_OK;
 }
@@ -746,6 +958,7 @@ static int finish_create(bpjd_ctx* ctx, const HostCSR& K, const HostCSR& M, cons
 // was allocated, for bpjd_problem_destroy.
 int materialize_problem(bpjd_problem* p) {
     if (!p->plan) return fail(BPJD_ERR_STATE, "problem already materialised");
+    StageClock clk;
     BPJD_HIP(hipSetDevice(p->ctx->device));
     int rc = device_layout(p, *p->plan, [&](void** dst, const void* src, size_t b) {
         return upload(p, dst, src, b);
@@ -765,6 +978,7 @@ int materialize_problem(bpjd_problem* p) {
     }
     delete p->plan;
     p->plan = nullptr;
+    clk.mark("allocate_upload");
     return rc;
 }
 
@@ -779,11 +993,15 @@ std::vector<size_t> planned_blocks(bpjd_problem* p) {
     return out;
 }
 
-static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR& hM, Pattern& U, hipStream_t st) {
+static int read_pair(const bpjd_csr* K, const bpjd_csr* M, HostCSR& hK, HostCSR& hM, Pattern& U, hipStream_t st,
+                     StageClock* clk) {
     BPJD_TRY(read_csr(K, "K", hK, st));
     BPJD_TRY(read_csr(M, "M", hM, st));
     if (hK.n != hM.n) return fail(BPJD_ERR_CSR, "K and M differ in size");
-    return build_union(hK, hM, U);
+    clk->mark("read_csr");
+    BPJD_TRY(build_union(hK, hM, U));
+    clk->mark("union_pattern");
+    return BPJD_OK;
 }
 
 // ---- numeric pieces ------------------------------------------------------------
@@ -994,7 +1212,7 @@ static int start_block(bpjd_problem* p) {
     BPJD_HIP(hipMemsetAsync(p->dropped[1], 0, 64 * sizeof(int), st));
     launch_csr_dense(st, n, p->Pptr, p->Pcol, p->Pval, p->Y, p->nH, s, p->W[0], ld, false);
     launch_copy_cols(st, 1, s, p->lamH, s, p->lam, s);
-    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0], ld, s, p->KW[0], ld, p->MW[0], ld);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[0], ld, s, p->KW[0], ld, p->MW[0], ld, p->spmm_variant);
     if (p->n_init) {
         BPJD_HIP(hipMemcpyAsync(blkp(p, p->W[0], s), p->X_init.data(), sizeof(double) * n * s,
                                 hipMemcpyHostToDevice, st));
@@ -1334,9 +1552,10 @@ static int autotune(bpjd_problem* p) {
     const int s = p->s;
     const bool mixed = p->opts.precision == BPJD_PREC_MIXED;
     char key[192];
-    if (s % 2 == 0) {
+    if (p->opts.spmm_form == 0) {
         std::snprintf(key, sizeof key, "spmm n%d nnz%lld c%d", p->n, p->nnz, s);
-        BPJD_TRY(tune_choice(key, {0, 1}, st, [&](int v) {
+        const std::vector<int> cands = s % 2 == 0 ? std::vector<int>{0, 1, 2} : std::vector<int>{1, 2};
+        BPJD_TRY(tune_choice(key, cands, st, [&](int v) {
             launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, p->W[0], s, s, p->KW[1], s, p->MW[1], s, v);
         }, &p->spmm_variant));
     }
@@ -1396,15 +1615,19 @@ static int advance_iter(SolveRun* r) {
         rmax = std::max(rmax, r->rho[i]);
         finite = finite && std::isfinite(r->rho[i]);
     }
-    if (p->trace) {
-        std::fprintf(stderr, "[bpjd] it %d rho_max %.3e lam:", r->it, rmax);
-        for (int i = 0; i < s; ++i) std::fprintf(stderr, " %.12g", r->lam_now[i]);
-        std::fprintf(stderr, "\n");
-    }
     if (!finite) return fail(BPJD_ERR_NOT_SPD, "non-finite residual (breakdown)");
     if (r->it > 0) {
         r->stop_value = 0.0;
         for (int i = 0; i < s; ++i) r->stop_value += std::fabs(r->lam_now[i] - r->lam_prev[i]);
+    }
+    if (p->trace) {
+        char head[200];
+        std::snprintf(head, sizeof head,
+                      "{\"event\": \"iteration\", \"problem\": \"%p\", \"it\": %d, \"fresh\": %s, "
+                      "\"rho_max\": %.6e, \"stop_value\": %.6e, ",
+                      (const void*)p, r->it, r->fresh ? "true" : "false", rmax, r->it > 0 ? r->stop_value : 0.0);
+        trace_line(std::string(head) + "\"lambda\": " + json_doubles(r->lam_now.data(), s) +
+                   ", \"rho\": " + json_doubles(r->rho.data(), k, "%.6e") + "}");
     }
     bool stop = false;
     if (p->opts.stop_rule == BPJD_STOP_RESIDUAL && rmax <= p->opts.tol) {
@@ -1418,7 +1641,6 @@ static int advance_iter(SolveRun* r) {
                            p->MW[r->cur], s, p->spmm_variant);
             PH_END(r->T);
             r->fresh = true;
-            if (p->trace) std::fprintf(stderr, "[bpjd]   products of X formed afresh\n");
             BPJD_TRY(enqueue_residual(r));
             return 0;
         }
@@ -1473,13 +1695,14 @@ static int advance_iter(SolveRun* r) {
         double th[64];
         BPJD_HIP(hipMemcpyAsync(th, p->theta, sizeof(double) * (ct + s), hipMemcpyDeviceToHost, st));
         BPJD_HIP(hipStreamSynchronize(st));
-        std::fprintf(stderr, "[bpjd]   m=%d drop_in:", ct + s);
-        for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, "%d", fl[q]);
-        std::fprintf(stderr, " drop_out:");
-        for (int q = 0; q < 2 * s; ++q) std::fprintf(stderr, "%d", fl[64 + q]);
-        std::fprintf(stderr, " theta:");
-        for (int q = 0; q < ct + s; ++q) std::fprintf(stderr, " %.6g", th[q]);
-        std::fprintf(stderr, "\n");
+        std::string din, dout;
+        for (int q = 0; q < ct + s; ++q) din += fl[q] ? '1' : '0';
+        for (int q = 0; q < 2 * s; ++q) dout += fl[64 + q] ? '1' : '0';
+        char head[160];
+        std::snprintf(head, sizeof head, "{\"event\": \"rayleigh_ritz\", \"problem\": \"%p\", \"it\": %d, \"m\": %d, ",
+                      (const void*)p, r->it, ct + s);
+        trace_line(std::string(head) + "\"dropped_in\": \"" + din + "\", \"dropped_out\": \"" + dout +
+                   "\", \"theta\": " + json_doubles(th, ct + s, "%.10g") + "}");
     }
     r->cur = 1 - a;
     r->np = uu ? s : 0;
@@ -1535,6 +1758,15 @@ int run_finish(SolveRun* r, double* eigvals, double* eigvecs, int mem, bpjd_stat
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = r->iters;
         stats->graph_iterations = r->graph_iters;
+        if (p->trace) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf,
+                          "{\"event\": \"solve\", \"problem\": \"%p\", \"iterations\": %d, \"converged\": %s, "
+                          "\"stop_value\": %.6e, \"setup_ms\": %.3f, \"iterate_ms\": %.3f}",
+                          (const void*)p, r->iters, r->converged ? "true" : "false", r->stop_value, ms_setup, ms_iter);
+            trace_line(buf);
+        }
+        stats->spmm_form = (p->spmm_variant == 0 && p->s % 2) ? BPJD_SPMM_COLUMN : p->spmm_variant + 1;
         stats->converged = r->converged ? 1 : 0;
         stats->stop_value = r->stop_value;
         double rmax = 0.0;
@@ -1633,9 +1865,10 @@ namespace bpjd {
 
 static int plan_dd(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd* dd,
                    const bpjd_opts* opts, bpjd_problem** out) {
+    StageClock clk;
     HostCSR hK, hM, P;
     Pattern U;
-    BPJD_TRY(read_pair(K, M, hK, hM, U, ctx->stream));
+    BPJD_TRY(read_pair(K, M, hK, hM, U, ctx->stream, &clk));
     if (dd->P.n_rows != U.n || dd->P.n_cols < 1) return fail(BPJD_ERR_DD, "P must be n x n_H");
     {
         // P is rectangular: read it without the square check
@@ -1649,23 +1882,25 @@ static int plan_dd(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bp
         if (rc == BPJD_ERR_CSR) return fail(BPJD_ERR_DD, "P: " + std::string(g_last_error));
         for (int c : tmp.col)
             if (c >= nH) return fail(BPJD_ERR_DD, "P column index out of range");
-        P = tmp;
+        P = std::move(tmp);
         if (dd->n_sub < 1 || !dd->sub_ptr || !dd->sub_idx) return fail(BPJD_ERR_DD, "no subdomains");
         std::vector<int> sptr(dd->sub_ptr, dd->sub_ptr + dd->n_sub + 1);
         if (sptr[0] != 0) return fail(BPJD_ERR_DD, "sub_ptr[0] must be 0");
         for (int l = 0; l < dd->n_sub; ++l)
             if (sptr[l + 1] < sptr[l]) return fail(BPJD_ERR_DD, "sub_ptr not monotone");
         std::vector<int> sidx(dd->sub_idx, dd->sub_idx + sptr[dd->n_sub]);
-        return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out);
+        clk.mark("prolongation");
+        return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out, clk);
     }
 }
 
 static int plan_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const bpjd_dd_geom* g,
                      const bpjd_opts* opts, bpjd_problem** out) {
     if (!g->coords || !g->cx || !g->cy || g->n_cx < 2 || g->n_cy < 2) return fail(BPJD_ERR_ARG, "bad coarse grid");
+    StageClock clk;
     HostCSR hK, hM, P;
     Pattern U;
-    BPJD_TRY(read_pair(K, M, hK, hM, U, ctx->stream));
+    BPJD_TRY(read_pair(K, M, hK, hM, U, ctx->stream, &clk));
     std::vector<double> cx(g->cx, g->cx + g->n_cx), cy(g->cy, g->cy + g->n_cy);
     for (size_t i = 0; i + 1 < cx.size(); ++i)
         if (!(cx[i + 1] > cx[i])) return fail(BPJD_ERR_ARG, "cx not increasing");
@@ -1673,10 +1908,12 @@ static int plan_geom(bpjd_ctx* ctx, const bpjd_csr* K, const bpjd_csr* M, const 
         if (!(cy[i + 1] > cy[i])) return fail(BPJD_ERR_ARG, "cy not increasing");
     int nH = 0;
     build_p1_prolongation(U.n, g->coords, cx, cy, P, nH);
+    clk.mark("prolongation");
     if (nH < 1) return fail(BPJD_ERR_DD, "coarse grid has no interior vertex");
     std::vector<int> sptr, sidx;
     BPJD_TRY(build_geom_subdomains(U, g->coords, cx, cy, g->overlap_layers, g->cell_shape, sptr, sidx));
-    return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out);
+    clk.mark("subdomains");
+    return finish_create(ctx, hK, hM, U, P, nH, sptr, sidx, opts, out, clk);
 }
 
 // Host planning of a problem (validation, structure, footprint) without device memory;
@@ -1806,7 +2043,7 @@ int bpjd_apply_preconditioner(bpjd_problem* p, const double* X, const double* la
     BPJD_HIP(hipMemcpyAsync(p->Z, X, sizeof(double) * n * s, kin, st));
     BPJD_HIP(hipMemcpyAsync(p->lam, lambda, sizeof(double) * s, kin, st));
     launch_copy_cols(st, n, s, p->Z, s, p->W[1], ld);
-    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[1], ld, s, p->KW[1], ld, p->MW[1], ld);
+    launch_spmm_km(st, n, p->rowptr, p->col, p->km, p->W[1], ld, s, p->KW[1], ld, p->MW[1], ld, p->spmm_variant);
     BPJD_HIP(hipMemsetAsync(p->status, 0, sizeof(int), st));
     launch_residual(st, n, s, p->KW[1], ld, p->MW[1], ld, p->lam, p->F, s, p->partial, p->npart, p->colsq, nullptr,
                     p->status);
@@ -1830,7 +2067,7 @@ int bpjd_spmm(bpjd_problem* p, const double* X, int32_t ncols, double* KX, doubl
     }
     double* dK = mem == BPJD_MEM_HOST ? p->KW[1] : KX;
     double* dM = mem == BPJD_MEM_HOST ? p->MW[1] : MX;
-    launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, dX, ncols, ncols, dK, ncols, dM, ncols);
+    launch_spmm_km(st, p->n, p->rowptr, p->col, p->km, dX, ncols, ncols, dK, ncols, dM, ncols, p->spmm_variant);
     if (mem == BPJD_MEM_HOST) {
         BPJD_HIP(hipMemcpyAsync(KX, dK, bytes, hipMemcpyDeviceToHost, st));
         BPJD_HIP(hipMemcpyAsync(MX, dM, bytes, hipMemcpyDeviceToHost, st));

@@ -127,11 +127,82 @@ __global__ void spmm_km_pair_kernel(int n, const int* __restrict__ rowptr, const
     }
 }
 
+// The same product with one lane per (row, column), lanes numbered row by row
+// (t = r * ncols + c), so no lane idles for a column count that is not a power of two and
+// the stores of a wave are one contiguous run when ldk = ldm = ncols.  A wavefront stages
+// the index and value pairs of its rows in LDS, 64 entries at a time with one coalesced
+// load per array, and every lane reads its row's entries from there (the lanes of a row
+// read the same address).  Sums keep the entry order.
+__global__ __launch_bounds__(256) void spmm_km_flat_kernel(int n, const int* __restrict__ rowptr,
+                                                           const int* __restrict__ col,
+                                                           const double2* __restrict__ km,
+                                                           const double* __restrict__ X, int ldx, int ncols,
+                                                           double* __restrict__ KX, int ldk,
+                                                           double* __restrict__ MX, int ldm) {
+    __shared__ int scol[4][64];
+    __shared__ double2 skm[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long t0 = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    const long long t = t0 + lane;
+    const int rfirst = (int)(t0 / ncols);
+    if (rfirst >= n) return;                           // the whole wavefront (t0 is shared)
+    const long long tl = (t0 + 63) / ncols;
+    const int rlast = (int)(tl < n - 1 ? tl : n - 1);
+    const int r = (int)(t / ncols);
+    const int c = (int)(t - (long long)r * ncols);
+    const bool active = r < n;
+    const int rr = active ? r : rlast;
+    const int p0 = rowptr[rr], p1 = active ? rowptr[rr + 1] : p0;
+    const int e0 = rowptr[rfirst], e1 = rowptr[rlast + 1];
+    double ak = 0.0, am = 0.0;
+    for (int cb = e0; cb < e1; cb += 64) {
+        const int e = min(cb + lane, e1 - 1);          // in bounds; entries past e1 are never read
+        scol[wv][lane] = col[e];
+        skm[wv][lane] = km[e];
+        __builtin_amdgcn_wave_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int q0 = max(p0, cb), q1 = min(p1, cb + 64);   // this lane's entries in the chunk
+        for (int qb = q0; qb < q1; qb += 8) {
+            int cj[8];
+            double2 v[8];
+            double xj[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int o = min(qb + j, q1 - 1) - cb;
+                cj[j] = scol[wv][o];
+                v[j] = skm[wv][o];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xj[j] = X[(long long)cj[j] * ldx + c];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (qb + j < q1) {
+                    ak = fma(v[j].x, xj[j], ak);
+                    am = fma(v[j].y, xj[j], am);
+                }
+            }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (active) {
+        KX[(long long)r * ldk + c] = ak;
+        MX[(long long)r * ldm + c] = am;
+    }
+}
+
 void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, const double2* km,
                     const double* X, int ldx, int ncols, double* KX, int ldk, double* MX, int ldm, int variant) {
     // column pairs need even column counts and leading dimensions and 16-byte aligned
     // blocks (every block of the library is a hipMalloc base plus multiples of 16 bytes);
-    // variant 1 keeps one column per lane.  Both forms add a row's entries in the same order.
+    // variant 1 keeps one column per lane in a power-of-two group per row, variant 2 one
+    // lane per (row, column).  All forms add a row's entries in the same order.
+    if (variant == 2) {
+        const long long work = (long long)n * ncols;
+        hipLaunchKernelGGL(spmm_km_flat_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, n, rowptr, col, km, X,
+                           ldx, ncols, KX, ldk, MX, ldm);
+        return;
+    }
     const bool pair = variant == 0 && (ncols % 2 == 0) && (ldx % 2 == 0) && (ldk % 2 == 0) && (ldm % 2 == 0) &&
                       ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(KX) |
                         reinterpret_cast<uintptr_t>(MX)) % 16 == 0);

@@ -20,6 +20,9 @@ namespace bpjd {
 // on a context is in progress on this thread (CtxScope), for that context as well.
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
+// JSON-lines trace (environment variable BPJD_TRACE: "1"/"stderr", or a file to append to)
+bool trace_on();
+void trace_line(const std::string& json);
 struct CtxScope {
     explicit CtxScope(bpjd_ctx* c);
     ~CtxScope();
@@ -286,6 +289,7 @@ struct bpjd_problem {
     bool graph_failed = false;         // capture unavailable: launch directly
     bool tuned = false;                // launch shapes chosen (autotuner or fixed)
     int ldlt_threads = 256;            // threads per system of the windowed local solver
-    int spmm_variant = 0;              // 0: two SpMM columns per lane where allowed, 1: one
+    int spmm_variant = 0;              // SpMM form: 0 two columns per lane where allowed, 1 one column
+                                       // per lane (power-of-two group per row), 2 one lane per (row, column)
     size_t footprint = 0;              // device bytes of the problem (allocation granularity included)
 };

@@ -91,6 +91,7 @@ def test_invalid_decomposition_and_options(B, ctx, t16):
     _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=4, guard=17))
     _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=2, tol=0.0))
     _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=2, precision=7))
+    _expect(B, B.ERR_ARG, lambda: B.Problem(ctx, mesh.K, mesh.M, dd=(dd.P, dd.subs), k=2, spmm_form=4))
 
 
 def test_state_and_breakdown(B, ctx, t16):

@@ -34,16 +34,38 @@ def _case(msg):
     print(f"\n[gpu case] {msg}", flush=True)
 
 
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", ["t8", "c1", "r96"])
-def test_spmm_parity(B, ctx, name):
-    _case(f"spmm {name}")
+def test_spmm_parity(B, ctx, name, form):
+    """K X and M X for every lane layout of the fused SpMM (0: the default), with an even
+    and an odd column count."""
+    _case(f"spmm {name} form {form}")
     mesh, cfg = w.config_mesh(name)
-    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=B.PREC_FP64)
-    X = np.random.default_rng(1).standard_normal((mesh.n, prob.s * 3))
-    KX, MX = prob.spmm(X)
-    np.testing.assert_allclose(KX, mesh.K @ X, rtol=0, atol=1e-13 * np.abs(mesh.K @ X).max())
-    np.testing.assert_allclose(MX, mesh.M @ X, rtol=0, atol=1e-13 * np.abs(mesh.M @ X).max())
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=B.PREC_FP64,
+                               spmm_form=form)
+    for ncols in (prob.s * 3, prob.s * 3 - 1):
+        X = np.random.default_rng(1).standard_normal((mesh.n, ncols))
+        KX, MX = prob.spmm(X)
+        np.testing.assert_allclose(KX, mesh.K @ X, rtol=0, atol=1e-13 * np.abs(mesh.K @ X).max())
+        np.testing.assert_allclose(MX, mesh.M @ X, rtol=0, atol=1e-13 * np.abs(mesh.M @ X).max())
     prob.close()
+
+
+@pytest.mark.parametrize("guard", [0, 1])
+def test_spmm_forms_give_identical_solves(B, ctx, guard):
+    """The SpMM lane layouts add every row's entries in the same order: whole solves
+    (block sizes 4 and 5, the second odd) agree bit for bit across them."""
+    _case(f"spmm forms c1 guard {guard}")
+    mesh, cfg = w.config_mesh("c1")
+    out = []
+    for form in (B.SPMM_PAIRS, B.SPMM_COLUMN, B.SPMM_FLAT):
+        prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=guard, precision=B.PREC_MIXED,
+                                   spmm_form=form, autotune=False)
+        out.append(prob.solve())
+        prob.close()
+    for lam, X, st in out[1:]:
+        assert st["iterations"] == out[0][2]["iterations"]
+        assert np.array_equal(lam, out[0][0]) and np.array_equal(X, out[0][1])
 
 
 @pytest.mark.parametrize("name", ["t8", "c1", "t64", "r96"])
