@@ -142,14 +142,17 @@ __global__ __launch_bounds__(256) void spmm_km_flat_kernel(int n, const int* __r
     __shared__ int scol[4][64];
     __shared__ double2 skm[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long t0 = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-    const long long t = t0 + lane;
-    const int rfirst = (int)(t0 / ncols);
+    // 32-bit lane numbers (n * ncols < 2^32 is checked at launch): a 64-bit division
+    // would be most of this kernel's instructions
+    const unsigned t0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    const unsigned t = t0 + lane;
+    const unsigned nc = (unsigned)ncols;
+    const int rfirst = (int)(t0 / nc);
     if (rfirst >= n) return;                           // the whole wavefront (t0 is shared)
-    const long long tl = (t0 + 63) / ncols;
-    const int rlast = (int)(tl < n - 1 ? tl : n - 1);
-    const int r = (int)(t / ncols);
-    const int c = (int)(t - (long long)r * ncols);
+    const unsigned tl = (t0 + 63) / nc;
+    const int rlast = (int)(tl < (unsigned)(n - 1) ? tl : (unsigned)(n - 1));
+    const int r = (int)(t / nc);
+    const int c = (int)(t - (unsigned)r * nc);
     const bool active = r < n;
     const int rr = active ? r : rlast;
     const int p0 = rowptr[rr], p1 = active ? rowptr[rr + 1] : p0;
@@ -197,7 +200,7 @@ void launch_spmm_km(hipStream_t st, int n, const int* rowptr, const int* col, co
     // blocks (every block of the library is a hipMalloc base plus multiples of 16 bytes);
     // variant 1 keeps one column per lane in a power-of-two group per row, variant 2 one
     // lane per (row, column).  All forms add a row's entries in the same order.
-    if (variant == 2) {
+    if (variant == 2 && (long long)n * ncols < (1LL << 32) - 256) {
         const long long work = (long long)n * ncols;
         hipLaunchKernelGGL(spmm_km_flat_kernel, dim3(grid_for(work, 256)), dim3(256), 0, st, n, rowptr, col, km, X,
                            ldx, ncols, KX, ldk, MX, ldm);
@@ -473,26 +476,49 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
     const int rows = min(GR_ROWS, n - r0);
     const double* A = T.A[blockIdx.y];
     double* Y = T.Y[blockIdx.y];
-    for (int e = t; e < ak * bq; e += 256) {
-        const int k = e / bq, q = e - k * bq;
-        sC[e] = (k < a && q < b) ? C[k * b + q] : 0.0;
+    // Index arithmetic: a thread's (row, column) positions advance by fixed strides, so
+    // each takes one division up front (a division per element was most of the
+    // instructions of this memory-bound kernel).
+    {
+        int k = t / bq, q = t - k * bq;                    // element t of C (ak x bq)
+        const int dk = 256 / bq, dq = 256 - dk * bq;
+        for (int e = t; e < ak * bq; e += 256) {
+            sC[e] = (k < a && q < b) ? C[k * b + q] : 0.0;
+            k += dk;
+            q += dq;
+            if (q >= bq) {
+                q -= bq;
+                ++k;
+            }
+        }
     }
-    for (int e = t; e < GR_ROWS * (ak - a); e += 256) sA[(e / (ak - a)) * ap + a + e % (ak - a)] = 0.0;
+    if (ak > a)                                            // k padding: at most three columns
+        for (int e = t; e < GR_ROWS * 4; e += 256)
+            if ((e & 3) < ak - a) sA[(e >> 2) * ap + a + (e & 3)] = 0.0;
     if (rows < GR_ROWS)
         for (int e = t; e < (GR_ROWS - rows) * a; e += 256) sA[(rows + e / a) * ap + e % a] = 0.0;
+    const int bw = g.bw;
+    // pair e2 = t + 256 i of a run starts at element 2 e2: row and column, and the stride
+    const int row_t = (2 * t) / bw, col_t = 2 * t - row_t * bw;
+    const int drow = 512 / bw, dcol = 512 - drow * bw;
     if (flat) {
-        const int bw = g.bw;
         const int cnt = rows * bw;             // values of one block's run (odd only in the last block)
-        for (int jb = 0; jb < a / bw; ++jb) {
+        const int nrun = a / bw;
+        for (int jb = 0; jb < nrun; ++jb) {
             const double* run = A + jb * g.bs + (long long)r0 * bw;
             const double2* src = reinterpret_cast<const double2*>(run);
+            int row = row_t, col = col_t;
             for (int e2 = t; 2 * e2 + 1 < cnt; e2 += 256) {
                 const double2 v = src[e2];
-                const int e = 2 * e2;
-                const int row = e / bw, col = e - row * bw;
                 sA[row * ap + jb * bw + col] = v.x;
                 if (col + 1 < bw) sA[row * ap + jb * bw + col + 1] = v.y;
                 else sA[(row + 1) * ap + jb * bw] = v.y;
+                row += drow;
+                col += dcol;
+                if (col >= bw) {
+                    col -= bw;
+                    ++row;
+                }
             }
             if ((cnt & 1) && t == 0) sA[(rows - 1) * ap + jb * bw + bw - 1] = run[cnt - 1];
         }
@@ -528,18 +554,17 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
             for (int i = 0; i < 4; ++i) sA[(16 * w + lk + 4 * i) * yp + 16 * qt + lr] = acc[qt][i];
     __syncthreads();
     if (flat) {
-        const int bw = g.bw;
         const int cnt = rows * bw;
-        for (int jb = 0; jb < b / bw; ++jb) {
+        const int nrun = b / bw;
+        for (int jb = 0; jb < nrun; ++jb) {
             double* run = Y + jb * g.bs + (long long)r0 * bw;
             double2* dst = reinterpret_cast<double2*>(run);
             if ((cnt & 1) && t == 0) {
                 const double v = sA[(rows - 1) * yp + jb * bw + bw - 1];
                 run[cnt - 1] = (beta == 0.0) ? alpha * v : fma(beta, run[cnt - 1], alpha * v);
             }
+            int row = row_t, col = col_t;
             for (int e2 = t; 2 * e2 + 1 < cnt; e2 += 256) {
-                const int e = 2 * e2;
-                const int row = e / bw, col = e - row * bw;
                 const double v0 = sA[row * yp + jb * bw + col];
                 const double v1 = (col + 1 < bw) ? sA[row * yp + jb * bw + col + 1] : sA[(row + 1) * yp + jb * bw];
                 double2 o;
@@ -550,6 +575,12 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
                     o = make_double2(fma(beta, old.x, alpha * v0), fma(beta, old.y, alpha * v1));
                 }
                 dst[e2] = o;
+                row += drow;
+                col += dcol;
+                if (col >= bw) {
+                    col -= bw;
+                    ++row;
+                }
             }
         }
     } else {

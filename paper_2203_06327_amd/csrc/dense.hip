@@ -946,6 +946,14 @@ __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* 
 #undef IDX
 }
 
+// orders the LDS accesses of one wavefront before and after (its LDS operations execute
+// in issue order; this keeps the compiler from reordering them)
+__device__ inline void wave_sync_fence() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -958,7 +966,9 @@ __device__ inline double wave_sum_d(double v) {
 // unrefined values w_in, split into chunks of at most 32): two Gram-Schmidt passes,
 // then a Rayleigh-Ritz step on the chunk (Jacobi on X_c^T T X_c) that rotates the
 // basis into eigenvectors and refines the eigenvalues (written to w).  Xn: n x n
-// scratch for the rotated columns.
+// scratch; rows start .. start + cs - 1 of it hold the chunk's columns of X
+// contiguously (one strided read and one strided write of X per chunk; every pass
+// in between reads contiguous vectors).
 __global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const double* __restrict__ dg,
                                                               const double* __restrict__ eg,
                                                               const double* __restrict__ w_in, double* __restrict__ w,
@@ -979,30 +989,43 @@ __global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const doubl
     for (int start = j; start < e; start += 32) {
         const int cs = min(32, e - start);
         if (cs < 2) break;
+        // the chunk's columns, contiguous: xc(q) = column start + q of X
+        double* xc0 = Xn + (long long)start * n;
+        auto xc = [&](const int q) { return xc0 + (long long)q * n; };
+        for (int i = lane; i < n; i += 64)
+            for (int q = 0; q < cs; ++q) xc(q)[i] = X[(long long)i * n + start + q];
+        __builtin_amdgcn_wave_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         // two Gram-Schmidt passes over the chunk's columns
-        for (int c = start; c < start + cs; ++c) {
+        for (int c = 0; c < cs; ++c) {
+            double* vc = xc(c);
             for (int pass = 0; pass < 2; ++pass)
-                for (int q = start; q < c; ++q) {
+                for (int q = 0; q < c; ++q) {
+                    const double* vq = xc(q);
                     double acc = 0.0;
-                    for (int i = lane; i < n; i += 64) acc = fma(X[i * n + q], X[i * n + c], acc);
+                    for (int i = lane; i < n; i += 64) acc = fma(vq[i], vc[i], acc);
                     const double cq = wave_sum_d(acc);
-                    for (int i = lane; i < n; i += 64) X[i * n + c] -= cq * X[i * n + q];
+                    for (int i = lane; i < n; i += 64) vc[i] -= cq * vq[i];
                 }
             double acc = 0.0;
-            for (int i = lane; i < n; i += 64) acc = fma(X[i * n + c], X[i * n + c], acc);
+            for (int i = lane; i < n; i += 64) acc = fma(vc[i], vc[i], acc);
             const double inv = 1.0 / sqrt(wave_sum_d(acc));
-            for (int i = lane; i < n; i += 64) X[i * n + c] *= inv;
+            for (int i = lane; i < n; i += 64) vc[i] *= inv;
         }
+        // the product with T reads neighbours that other lanes wrote: their stores complete first
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
         // Tc = X_c^T T X_c
         for (int pp = 0; pp < cs; ++pp)
             for (int qq = pp; qq < cs; ++qq) {
-                const int cp = start + pp, cq = start + qq;
+                const double* vp = xc(pp);
+                const double* vq = xc(qq);
                 double acc = 0.0;
                 for (int i = lane; i < n; i += 64) {
-                    double tx = dg[i] * X[i * n + cq];
-                    if (i > 0) tx = fma(eg[i - 1], X[(i - 1) * n + cq], tx);
-                    if (i + 1 < n) tx = fma(eg[i], X[(i + 1) * n + cq], tx);
-                    acc = fma(X[i * n + cp], tx, acc);
+                    double tx = dg[i] * vq[i];
+                    if (i > 0) tx = fma(eg[i - 1], vq[i - 1], tx);
+                    if (i + 1 < n) tx = fma(eg[i], vq[i + 1], tx);
+                    acc = fma(vp[i], tx, acc);
                 }
                 const double v = wave_sum_d(acc);
                 if (lane == 0) {
@@ -1011,41 +1034,47 @@ __global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const doubl
                 }
             }
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-            // cyclic Jacobi on the cs x cs matrix, then ascending sort of the pairs
+        // cyclic Jacobi on the cs x cs matrix: every lane computes the same rotation and
+        // lane k updates entry k of the two rows and columns (each rotation applies the
+        // column updates, then the row updates, as a serial sweep would)
+        for (int e2 = lane; e2 < cs * 33; e2 += 64) Qc[e2] = (e2 % 33 == e2 / 33) ? 1.0 : 0.0;
+        wave_sync_fence();
+        for (int sweep = 0; sweep < 50; ++sweep) {
+            bool rot = false;
             for (int pp = 0; pp < cs; ++pp)
-                for (int qq = 0; qq < cs; ++qq) Qc[pp * 33 + qq] = (pp == qq) ? 1.0 : 0.0;
-            for (int sweep = 0; sweep < 50; ++sweep) {
-                bool rot = false;
-                for (int pp = 0; pp < cs; ++pp)
-                    for (int qq = pp + 1; qq < cs; ++qq) {
-                        const double apq = Tc[pp * 33 + qq];
-                        const double app = Tc[pp * 33 + pp], aqq = Tc[qq * 33 + qq];
-                        if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
-                        rot = true;
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
-                        for (int k = 0; k < cs; ++k) {
-                            const double akp = Tc[k * 33 + pp], akq = Tc[k * 33 + qq];
-                            Tc[k * 33 + pp] = c * akp - sn * akq;
-                            Tc[k * 33 + qq] = sn * akp + c * akq;
-                        }
-                        for (int k = 0; k < cs; ++k) {
-                            const double apk = Tc[pp * 33 + k], aqk = Tc[qq * 33 + k];
-                            Tc[pp * 33 + k] = c * apk - sn * aqk;
-                            Tc[qq * 33 + k] = sn * apk + c * aqk;
-                        }
+                for (int qq = pp + 1; qq < cs; ++qq) {
+                    const double apq = Tc[pp * 33 + qq];
+                    const double app = Tc[pp * 33 + pp], aqq = Tc[qq * 33 + qq];
+                    if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
+                    rot = true;
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+                    const int k = lane;
+                    if (k < cs) {
+                        const double akp = Tc[k * 33 + pp], akq = Tc[k * 33 + qq];
+                        Tc[k * 33 + pp] = c * akp - sn * akq;
+                        Tc[k * 33 + qq] = sn * akp + c * akq;
+                    }
+                    wave_sync_fence();
+                    if (k < cs) {
+                        const double apk = Tc[pp * 33 + k], aqk = Tc[qq * 33 + k];
+                        const double vkp = Qc[k * 33 + pp], vkq = Qc[k * 33 + qq];
+                        Qc[k * 33 + pp] = c * vkp - sn * vkq;
+                        Qc[k * 33 + qq] = sn * vkp + c * vkq;
+                        Tc[pp * 33 + k] = c * apk - sn * aqk;
+                        Tc[qq * 33 + k] = sn * apk + c * aqk;
+                    }
+                    wave_sync_fence();
+                    if (lane == 0) {
                         Tc[pp * 33 + qq] = 0.0;
                         Tc[qq * 33 + pp] = 0.0;
-                        for (int k = 0; k < cs; ++k) {
-                            const double vkp = Qc[k * 33 + pp], vkq = Qc[k * 33 + qq];
-                            Qc[k * 33 + pp] = c * vkp - sn * vkq;
-                            Qc[k * 33 + qq] = sn * vkp + c * vkq;
-                        }
                     }
-                if (!rot) break;
-            }
+                    wave_sync_fence();
+                }
+            if (!rot) break;
+        }
+        if (lane == 0) {
             for (int pp = 0; pp < cs; ++pp) {          // selection sort of the pairs
                 int best = pp;
                 for (int qq = pp + 1; qq < cs; ++qq)
@@ -1065,15 +1094,13 @@ __global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const doubl
         }
         __builtin_amdgcn_wave_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // X_c <- X_c Q_c through the scratch Xn (same columns), then copied back
+        // X_c <- X_c Q_c, from the contiguous copy into the columns of X
         for (int i = lane; i < n; i += 64)
             for (int q = 0; q < cs; ++q) {
                 double v = 0.0;
-                for (int pp = 0; pp < cs; ++pp) v = fma(X[i * n + start + pp], Qc[pp * 33 + q], v);
-                Xn[i * n + start + q] = v;
+                for (int pp = 0; pp < cs; ++pp) v = fma(xc(pp)[i], Qc[pp * 33 + q], v);
+                X[(long long)i * n + start + q] = v;
             }
-        for (int i = lane; i < n; i += 64)
-            for (int q = 0; q < cs; ++q) X[i * n + start + q] = Xn[i * n + start + q];
     }
 }
 
@@ -1142,7 +1169,6 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
     // work: n*n (reflectors); small: 6n + 1 (tau, diag, off, unrefined eigenvalues, p, w, a
     // completion counter);
     // scratch: 6 n*n (inverse iteration, then the cluster rotation)
-    (void)status;
     double* tau = small;
     double* diag = small + n;
     double* off = small + 2 * n;
@@ -1153,12 +1179,12 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
         // small matrices: one workgroup does every step (no per-column launches)
         hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(512), 0, st, n, A, work, tau, diag, off);
     } else {
-    unsigned int* counter = reinterpret_cast<unsigned int*>(small + 6 * n);
-    hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, 0, A, work, tau, pbuf, wbuf, diag, off,
-                       counter);
-    for (int k = 0; k + 2 < n; ++k)
-        hipLaunchKernelGGL(tridiag_step_kernel, dim3(grid_for(n - k - 1, 4)), dim3(256), 0, st, n, k, A, work, tau,
-                           pbuf, wbuf, diag, off, counter);
+        unsigned int* counter = reinterpret_cast<unsigned int*>(small + 6 * n);
+        hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, 0, A, work, tau, pbuf, wbuf, diag, off,
+                           counter);
+        for (int k = 0; k + 2 < n; ++k)
+            hipLaunchKernelGGL(tridiag_step_kernel, dim3(grid_for(n - k - 1, 4)), dim3(256), 0, st, n, k, A, work,
+                               tau, pbuf, wbuf, diag, off, counter);
     }
     hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(grid_for((long long)n * BISECT_G, 256)), dim3(256), 0, st, n, diag,
                        off, w0);

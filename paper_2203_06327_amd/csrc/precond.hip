@@ -245,9 +245,19 @@ __global__ __launch_bounds__(256) void gather_kernel(int sumN, int s, const int*
     const int t = threadIdx.x;
     if (t < cnt) rowi[t] = subidx[pos0 + t];
     __syncthreads();
-    for (int e = t; e < cnt * s; e += 256) {
-        const int p = e / s, i = e - p * s;
-        tile[i][p] = (T)F[(long long)rowi[p] * ldf + i];
+    {
+        // element e = t + 256 k is (row p, shift i) = (e / s, e % s): one division, then strides
+        int p = t / s, i = t - p * s;
+        const int dp = 256 / s, di = 256 - dp * s;
+        for (int e = t; e < cnt * s; e += 256) {
+            tile[i][p] = (T)F[(long long)rowi[p] * ldf + i];
+            p += dp;
+            i += di;
+            if (i >= s) {
+                i -= s;
+                ++p;
+            }
+        }
     }
     __syncthreads();
     for (int e = t; e < GT * s; e += 256) {
@@ -1130,9 +1140,16 @@ __global__ __launch_bounds__(256) void scatter_kernel(int n, int s, long long su
             if (i < s) scatter_tile[i * 257 + t] = acc[i];
     }
     __syncthreads();
+    int r = t / s, i = t - r * s;                      // element e = t + 256 k: (e / s, e % s)
+    const int dr = 256 / s, di = 256 - dr * s;
     for (int e = t; e < cnt * s; e += 256) {
-        const int r = e / s, i = e - r * s;
         Z[(long long)(d0 + r) * ldz + i] = scatter_tile[i * 257 + r];
+        r += dr;
+        i += di;
+        if (i >= s) {
+            i -= s;
+            ++r;
+        }
     }
 }
 
