@@ -50,11 +50,14 @@ def local_solve_flops(nl: np.ndarray, bw: np.ndarray, s: int) -> float:
 def local_kernel_name(band: int, slots: int) -> str:
     """The FP32 local solver the library picks: the blocked MFMA solver with a 64-row
     window up to half-bandwidth 48 and a 96-row window up to 80 (at most 8 lower
-    entries per local row), the windowed LDS solver otherwise."""
+    entries per local row), the wide blocked solver (192-row window) for bands 49..176
+    with up to 20 lower entries, the windowed LDS solver otherwise."""
     if slots <= 8 and band <= 48:
         return "local_band_mfma_kernel<float, 0, 4>"
     if slots <= 8 and band <= 80:
         return "local_band_mfma_kernel<float, 0, 6>"
+    if 49 <= band <= 176 and slots <= 20:
+        return "local_band_wide_kernel<0>"
     return "local_ldlt_kernel<float>"
 
 

@@ -154,10 +154,16 @@ typedef struct {
                                    environment variable BPJD_TUNE_CACHE, read at the first tuning, when
                                    it is set).  Results are the same bit for bit either way.
                                    0: fixed choices (256 threads, two columns per lane). */
-    int32_t local_threads;      /* threads per system of the windowed local solver (used for half-
-                                   bandwidths above 80 or more than 8 lower entries per local row):
-                                   0 (default) = the autotuner's choice (256 without autotune), or
-                                   exactly 64, 128 or 256.  The arithmetic is the same for all. */
+    int32_t local_threads;      /* threads per system of the windowed local solver: 0 (default) =
+                                   the autotuner's choice (256 without autotune), or exactly 64,
+                                   128 or 256, which also selects the windowed solver where the
+                                   wide blocked one would run.  The local solver is chosen by the
+                                   largest half-bandwidth w and lower entries per local row E:
+                                   blocked MFMA with a 64-row window (w <= 48, E <= 8) or a 96-row
+                                   window (w <= 80, E <= 8); in mixed precision the wide blocked
+                                   solver with a 192-row window (49 <= w <= 176, E <= 20); the
+                                   windowed LDS solver otherwise (w <= 191).  The windowed
+                                   solver's arithmetic is the same for all thread counts. */
     int32_t spmm_form;          /* lane layout of the fused K/M SpMM: 0 (default) = the autotuner's
                                    choice (BPJD_SPMM_PAIRS without autotune); or exactly one of
                                    BPJD_SPMM_*.  Every form adds a row's entries in the same order,

@@ -35,6 +35,11 @@ static constexpr int kGrowMaxDim = 1024;
 static constexpr int kBlockedMaxBand = 48;       // 64-row window (4 tile-rows)
 static constexpr int kBlockedWideMaxBand = 80;   // 96-row window (6 tile-rows)
 static constexpr int kBlockedMaxSlots = 8;
+// the wide blocked solver (FP32, 192-row window): half-bandwidths 49..176, up to 20 lower
+// entries per row (elements with several dofs per vertex, three dimensions)
+static constexpr int kWideMinBand = 49;
+static constexpr int kWideMaxBand = 176;
+static constexpr int kWideMaxSlots = 20;
 
 // Host planning runs its per-row, per-dof and per-subdomain loops on up to 16 threads.
 // Every loop writes disjoint outputs, or per-item results merged in item order, so the
@@ -780,17 +785,24 @@ static int finish_create(bpjd_ctx* ctx, HostCSR& K, HostCSR& M, Pattern& U, Host
     // solver one band column per row
     int maxE = 0;
     for (long long q = 0; q < sumN; ++q) maxE = std::max(maxE, lptr[q + 1] - lptr[q]);
-    const bool blocked = maxBW <= kBlockedWideMaxBand && maxE <= kBlockedMaxSlots;
-    const int nt = !blocked ? 0 : (maxBW <= kBlockedMaxBand ? 4 : 6);   // window tile-rows
+    const bool narrow = maxBW <= kBlockedWideMaxBand && maxE <= kBlockedMaxSlots;
+    // the wide solver where the windowed one would run (mixed precision only: the
+    // window's tiles are FP32), unless the caller fixed the windowed solver's threads
+    const bool wide = !narrow && opts->precision == BPJD_PREC_MIXED && opts->local_threads == 0 &&
+                      maxBW >= kWideMinBand && maxBW <= kWideMaxBand && maxE <= kWideMaxSlots;
+    const bool blocked = narrow || wide;
+    const int nt = wide ? 12 : !blocked ? 0 : (maxBW <= kBlockedMaxBand ? 4 : 6);   // window tile-rows
     // the windowed solver gives each lane at most three entries of a window row and loads
     // the slots of a block of rows one slot per lane
     if (!blocked && (maxBW > 191 || maxE > 64))
         return fail(BPJD_ERR_DD, "local half-bandwidth above 191 or more than 64 lower entries in a local row");
     // stored rows per factor column: the band part (rounded up to 4; the factor traffic
-    // bounds the backward sweep), except FP32 with the 96-row window, which keeps full
-    // columns
+    // bounds the backward sweep), except FP32 with the 96- and 192-row windows, which keep
+    // full columns
     const int win = 16 * std::max(nt, 4);
-    const int bws = (opts->precision == BPJD_PREC_MIXED && nt == 6) ? win : ((std::min(win, maxBW + 1) + 3) / 4) * 4;
+    const int bws = (opts->precision == BPJD_PREC_MIXED && (nt == 6 || nt == 12))
+                        ? win
+                        : ((std::min(win, maxBW + 1) + 3) / 4) * 4;
     std::vector<long long> Loff(nsub, 0);
     long long Ltot = 0;
     for (int l = 0; l < nsub; ++l) {

@@ -1042,13 +1042,334 @@ void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr
                        km, sd, sv);
 }
 
+// Local solves, blocked, wide bands (FP32): the blocked LDL^T above with a window of
+// 192 rows (12 tile-rows, half-bandwidths up to 176) and up to 20 lower entries per row
+// (fourth-order and three-dimensional elements).  One wavefront per (subdomain, shift).
+// The 78 lower tiles of the window live in LDS (16 x 16 FP32 in accumulator order:
+// element (r, c) at 4 (16 (r / 4) + c) + r % 4, so that lane l's four accumulator values,
+// rows 4 (l / 16) + 0..3 of column l % 16, are the 16 bytes at 16 l), one ring per tile
+// diagonal d = I - J: the tiles of diagonal d
+// belong to absolute tile-rows TR = P + d .. P + 11 and take slot TR mod (12 - d) of the
+// ring, so when the window slides the retiring panel tile of each ring frees exactly the
+// slot its entering tile needs (TR = P + 12 = P + d mod 12 - d) and nothing moves.  Per
+// panel: the panel tiles are read to one row per lane (three row sets: rows lane,
+// 64 + lane, 128 + lane) and factored with lane broadcasts (one pivot row serves the
+// three sets); the next tile-row is scattered into the freed slots; the factored panel
+// goes to HBM (full 192-row columns) and, row-major, to LDS as MFMA operands; each of
+// the 66 trailing tiles is read, takes -L_I D L_J^T with four 16x16x4 MFMAs and is
+// written back.  The right-hand side shifts through LDS; the backward sweep sums the
+// contributions of the 176 rows below each panel through a column-major LDS copy.
+constexpr int WIDE_NT = 12;                 // tile-rows of the window
+constexpr int WIDE_R = 16 * WIDE_NT;        // window rows (192)
+constexpr int WIDE_EPL = 5;                 // fixed slots a lane carries (E <= 20)
+constexpr int WIDE_TILES = WIDE_NT * (WIDE_NT + 1) / 2;   // 78 ring slots
+
+// first ring slot of diagonal d and its ring size
+__host__ __device__ constexpr int wide_ring_base(int d) { return WIDE_NT * d - d * (d - 1) / 2; }
+__host__ __device__ constexpr int wide_ring_size(int d) { return WIDE_NT - d; }
+
+template <int MODE>
+__global__ __launch_bounds__(64) void local_band_wide_kernel(
+    int s, int E, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
+    const double* __restrict__ lam, const float* __restrict__ Floc, long long ldF, float* __restrict__ zloc,
+    float* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
+    int* __restrict__ negflag) {
+    using T = float;
+    using MT = MfmaTile<T>;
+    using acc_t = typename MT::acc;
+    constexpr int NT = WIDE_NT, R = WIDE_R, NS = 3, EPL = WIDE_EPL;
+    constexpr int QS = 20;                     // row stride of the factored panel (16-byte rows, spread banks)
+    constexpr int PS = 196;                    // backward sweep: column stride of its panel copy
+    static_assert(WIDE_TILES * 256 >= 16 * PS, "the backward sweep's copy aliases the tile rings");
+    __shared__ __align__(16) T tiles[WIDE_TILES * 256];
+    __shared__ __align__(16) T pan[R][QS];
+    __shared__ T vec[R];
+    __shared__ T colsum[16];
+    __shared__ T ucol[16][17];                 // column c of the panel at elimination step c
+    __shared__ T urc[16], uyc[16];             // pivot reciprocal and y_c of step c
+    const int sys = blockIdx.x;
+    if (MODE && !negflag[sys]) return;
+    const int l = sys / s;
+    const int i = sys - l * s;
+    const int off = subptr[l];
+    const int nl = subptr[l + 1] - off;
+    const int npan = (nl + 15) >> 4;
+    const double lamd = MODE ? 0.0 : lam[i];
+    const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+    const int q = lane >> 2, slot0 = lane & 3;
+    T* Lp = Lwork + Loff[l] + (long long)i * npan * (16 * R);
+    const float* f = Floc + (long long)i * ldF + off;
+    float* z = zloc + (long long)i * ldF + off;
+    // tile (I, J) of the window of panel P: ring d = I - J, absolute tile-row P + I
+    auto tile = [&](const int P, const int I, const int J) -> T* {
+        const int d = I - J;
+        return tiles + (wide_ring_base(d) + (P + I) % wide_ring_size(d)) * 256;
+    };
+
+    int pdr[EPL];
+    double2 pvr[EPL];
+    bool pok[EPL];
+    auto fetch = [&](const int rb) {           // slots of row rb + q for this lane
+        const int r = rb + q;
+#pragma unroll
+        for (int u = 0; u < EPL; ++u) {
+            const int e = slot0 + 4 * u;
+            pok[u] = (r < nl && e < E);
+            const long long k = pok[u] ? (long long)(off + r) * E + e : 0LL;
+            pdr[u] = sd[k];
+            pvr[u] = sv[k];
+        }
+    };
+    // the fetched rows rb..rb+15 as tile-row I of panel P's window (its tiles zeroed
+    // before): entry (row, column) of the window goes to tile (I, column / 16)
+    auto place = [&](const int P, const int I, const int rb) {
+        const int r = rb + q;
+        const int cb = 16 * P;                 // first column of the window
+#pragma unroll
+        for (int u = 0; u < EPL; ++u) {
+            int cw = -1;
+            T v = T(1);
+            if (r < nl) {
+                if (pok[u] && pdr[u] >= 0) {
+                    cw = r - pdr[u] - cb;
+                    v = (T)(pvr[u].x - lamd * pvr[u].y);
+                }
+            } else if (u == 0 && slot0 == 0) {
+                cw = r - cb;                   // identity row past the end
+            }
+            if (cw >= 0) {
+                const int J = cw >> 4, d = I - J;
+                T* t = tiles + (wide_ring_base(d) + (P + I) % wide_ring_size(d)) * 256;
+                t[4 * (16 * (q >> 2) + (cw & 15)) + (q & 3)] = v;
+            }
+        }
+    };
+    auto zero_row_tiles = [&](const int P, const int I) {   // the tiles (I, 0..I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J)
+            reinterpret_cast<floatx4_t*>(tile(P, I, J))[lane] = floatx4_t{T(0), T(0), T(0), T(0)};
+    };
+
+#pragma unroll
+    for (int I = 0; I < NT; ++I) zero_row_tiles(0, I);
+    wave_sync();
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+        fetch(16 * I);
+        place(0, I, 16 * I);
+    }
+    T y[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const T fv = f[min(64 * k + lane, nl - 1)];         // unconditional, clamped, then selected
+        y[k] = (64 * k + lane < nl) ? fv : T(0);
+    }
+    int bad = 0, neg = 0;
+
+    for (int P = 0; P < npan; ++P) {
+        const int base = 16 * P;
+        fetch(base + R);                                   // the tile-row entering after this panel
+        const int rnew = base + 16 + 128 + lane;           // set 3 row after the slide (lanes 48..63)
+        const T fraw = f[min(rnew, nl - 1)];
+        wave_sync();
+        // panel rows: row 64 k + lane is row lr of tile (4 k + lg, 0)
+        T a[NS][16];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int I = 4 * k + lg;
+            const T* t = tiles + (wide_ring_base(I) + (P + I) % wide_ring_size(I)) * 256 + 64 * (lr >> 2) + (lr & 3);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[k][c] = t[4 * c];
+        }
+        wave_sync();
+        // the panel tiles are free: the next tile-row takes their slots
+        if (P + 1 < npan) {
+            zero_row_tiles(P + 1, NT - 1);
+            wave_sync();
+            place(P + 1, NT - 1, base + R);
+        }
+        // rows 0..63: elimination with lane broadcasts; step c's column (rows c..15), the
+        // pivot reciprocal and y_c are recorded for the rows below
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const T u = a[0][c];
+            const T dc = MT::bcast(u, c);
+            const T rc = MT::recip(dc);
+            const T yc = MT::bcast(y[0], c);
+            if (lane < 16) ucol[c][lane] = u;
+            if (lane == 0) {
+                urc[c] = rc;
+                uyc[c] = yc;
+            }
+            T urow[16];
+#pragma unroll
+            for (int c2 = c + 1; c2 < 16; ++c2) urow[c2] = MT::bcast(u, c2);
+            const T lt = u * rc;
+#pragma unroll
+            for (int c2 = c + 1; c2 < 16; ++c2) a[0][c2] -= lt * urow[c2];
+            if (lane > c) y[0] -= lt * yc;
+            a[0][c] = (lane == c) ? dc : lt;
+        }
+        wave_sync();
+        // rows 64..191 lie below the panel: the same steps with the recorded values
+        // (constant trip counts, so that every loop unrolls and the rows stay in registers)
+#pragma clang loop unroll(full)
+        for (int c = 0; c < 16; ++c) {
+            const T rc = urc[c], yc = uyc[c];
+            T urow[16];
+#pragma clang loop unroll(full)
+            for (int c2 = 0; c2 < 16; ++c2) urow[c2] = ucol[c][c2];
+            const T lt1 = a[1][c] * rc, lt2 = a[2][c] * rc;
+#pragma clang loop unroll(full)
+            for (int c2 = 0; c2 < 16; ++c2) {
+                if (c2 > c) {
+                    a[1][c2] -= lt1 * urow[c2];
+                    a[2][c2] -= lt2 * urow[c2];
+                }
+            }
+            y[1] -= lt1 * yc;
+            y[2] -= lt2 * yc;
+            a[1][c] = lt1;
+            a[2][c] = lt2;
+        }
+        // the factored panel's full columns (window rows 0..191) for the backward sweep
+        T* Lb = Lp + (long long)P * (16 * R) + lane;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Lb[c * R + 64 * k] = a[k][c];
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) pan[64 * k + lane][c] = a[k][c];
+        wave_sync();
+        {
+            // pivots of the panel (checked once per panel) and D^{-1} L^{-1} f of its rows,
+            // stored by every lane (rows past the end repeat the last row's value)
+            const T dl = pan[lane & 15][lane & 15];
+            if (lane < 16 && base + lane < nl) {
+                bad |= !(fabs(dl) > T(1e-30) && fabs(dl) < T(1e30));
+                neg |= dl < T(0);
+            }
+            const int zr = min(lane & 15, nl - 1 - base);
+            const T zv = __shfl(y[0] * MT::recip(dl), zr, 64);
+            z[base + zr] = zv;
+        }
+        // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T, read from and
+        // written back to their ring slots (the next panel's tile (I - 1, J - 1))
+        T dcol[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dcol[k] = pan[4 * lg + k][4 * lg + k];
+        T bop[NT][4];
+#pragma unroll
+        for (int J = 1; J < NT; ++J) {
+            const T* src = &pan[16 * J + lr][4 * lg];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bop[J][k] = src[k];
+        }
+#pragma unroll
+        for (int I = 1; I < NT; ++I) {
+            T aop[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) aop[k] = -bop[I][k] * dcol[k];
+#pragma unroll
+            for (int J = 1; J <= I; ++J) {
+                floatx4_t* tp = reinterpret_cast<floatx4_t*>(tile(P, I, J)) + lane;
+                acc_t acc = *tp;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc = MT::mma(aop[k], bop[J][k], acc);
+                *tp = acc;
+            }
+        }
+        // shift the right-hand side by 16 window rows; fresh rows enter at the bottom
+#pragma unroll
+        for (int k = 0; k < NS; ++k) vec[64 * k + lane] = y[k];
+        wave_sync();
+        y[0] = vec[lane + 16];
+        y[1] = vec[80 + lane];
+        y[2] = (lane < 48) ? vec[min(144 + lane, R - 1)] : ((rnew < nl) ? fraw : T(0));
+        wave_sync();
+    }
+
+    // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows
+    T zw[NS] = {T(0), T(0), T(0)};
+    T (*bt)[PS] = reinterpret_cast<T (*)[PS]>(tiles);
+    T bufA[NS][16], bufB[NS][16];
+    T zA, zB;
+    auto load_panel = [&](const int P, T (&dst)[NS][16], T& zdst) {
+        const int Pc = max(P, 0);
+        const T* Lpan = Lp + (long long)Pc * (16 * R) + lane;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+#pragma unroll
+            for (int k = 0; k < NS; ++k) dst[k][c] = Lpan[c * R + 64 * k];
+        zdst = z[min(16 * Pc + lr, nl - 1)];
+    };
+    auto back_step = [&](const int P, T (&a)[NS][16], T& zb) {
+        const int base = 16 * P;
+        const T zc0 = (lane < 16 && base + lane < nl) ? zb : T(0);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) vec[64 * k + lane] = zw[k];
+        wave_sync();
+        zw[0] = (lane >= 16) ? vec[max(lane - 16, 0)] : T(0);
+        zw[1] = vec[48 + lane];
+        zw[2] = vec[112 + lane];
+        wave_sync();
+        // column-major copy of the panel: rows below the panel hold L(r, c) z_r, the 16
+        // panel rows hold L(r, c) itself
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            bt[c][lane] = (lane >= 16) ? a[0][c] * zw[0] : a[0][c];
+            bt[c][64 + lane] = a[1][c] * zw[1];
+            bt[c][128 + lane] = a[2][c] * zw[2];
+        }
+        wave_sync();
+        load_panel(P - 2, a, zb);                          // this buffer is free again
+        {
+            // contributions of the 176 rows below the panel: lane (c, quarter) sums 44 rows
+            constexpr int RQ = (R - 16) / 4;
+            const int c = lane >> 2, qq = lane & 3;
+            const T* src = &bt[c][16 + RQ * qq];
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < RQ; ++j) acc += src[j];
+            acc = quad_sum(acc);
+            if (qq == 0) colsum[c] = acc;
+        }
+        T lt[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lt[r] = bt[lr][r];
+        wave_sync();
+        T val = zc0 - colsum[lr];
+#pragma unroll
+        for (int r = 15; r > 0; --r) {
+            const T zr = MT::bcast(val, r);
+            if (lane < r) val -= lt[r] * zr;
+        }
+        if (lane < 16) zw[0] = val;
+        const int zr = min(lane & 15, nl - 1 - base);
+        const T zv = __shfl(val, zr, 64);
+        z[base + zr] = zv;
+        wave_sync();
+    };
+    load_panel(npan - 1, bufA, zA);
+    load_panel(npan - 2, bufB, zB);
+    for (int P = npan - 1; P >= 0; P -= 2) {
+        back_step(P, bufA, zA);
+        if (P >= 1) back_step(P - 1, bufB, zB);
+    }
+    if (__any(bad) && lane == 0) atomicOr(status, STATUS_LOCAL_PIVOT);
+    const bool indefinite = __any(neg);
+    if (MODE == 0 && lane == 0) negflag[sys] = indefinite ? 1 : 0;
+}
+
 template <typename T>
 static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s, int E, int bws, long long sumN,
                               const int* subptr, const int* sd, const double2* sv, const double* lam, const T* Floc,
                               T* zloc, T* Lwork, const long long* Loff, int* status, int* negflag) {
     // mode 0: every system with shift lambda_i; mode 1: the systems found indefinite,
     // again with shift 0 (its waves return at once when no system was flagged).
-    // nt: window tile-rows (4 or 6)
+    // nt: window tile-rows (4 or 6; 12: the wide FP32 kernel, whose stored columns are full)
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv, lam, Floc, sumN, zloc,
                            Lwork, Loff, status, negflag);
@@ -1056,6 +1377,15 @@ static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s,
     if (nt == 4) {
         if (mode == 0) go(local_band_mfma_kernel<T, 0, 4>);
         else go(local_band_mfma_kernel<T, 1, 4>);
+    } else if (nt == WIDE_NT) {
+        if constexpr (sizeof(T) == 4) {
+            auto wide = [&](auto kernel) {
+                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, subptr, sd, sv, lam, Floc, sumN,
+                                   zloc, Lwork, Loff, status, negflag);
+            };
+            if (mode == 0) wide(local_band_wide_kernel<0>);
+            else wide(local_band_wide_kernel<1>);
+        }
     } else {
         if (mode == 0) go(local_band_mfma_kernel<T, 0, 6>);
         else go(local_band_mfma_kernel<T, 1, 6>);

@@ -221,11 +221,12 @@ def test_autotune_keeps_results_and_records_choices(B, ctx, tmp_path, monkeypatc
     per system of the windowed local solver, one or two SpMM columns per lane): a solve
     with tuning equals, bit for bit, one with the fixed choices; the chosen shapes are
     appended to the cache file, keyed by the problem's shape."""
-    _case("autotune b32 s=10")
+    _case("autotune b16 s=10")
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("BPJD_TUNE_CACHE", str(cache))
-    pl, cfg = w.config_plate("b32")
-    kw = dict(k=cfg["k"], guard=4, precision=B.PREC_MIXED)    # s = 10: a shape no other test tunes
+    # b16 (half-bandwidths 23-27, 20 lower entries per row): the windowed local solver
+    pl, cfg = w.config_plate("b16")
+    kw = dict(k=cfg["k"], guard=10 - cfg["k"], precision=B.PREC_MIXED)    # s = 10: a shape no other test tunes
     tuned = B.Problem(ctx, pl.K, pl.M, dd=(pl.P, pl.subs), autotune=True, **kw)
     lam1, X1, st1 = tuned.solve()
     tuned.close()
@@ -239,7 +240,7 @@ def test_autotune_keeps_results_and_records_choices(B, ctx, tmp_path, monkeypatc
     ldlt = [int(v) for k, v in rows if k.startswith("ldlt f32 s10 ")]
     spmm = [int(v) for k, v in rows if k.startswith(f"spmm n{pl.n} ") and k.endswith(" c10")]
     assert len(ldlt) == 1 and ldlt[0] in (64, 128, 256)
-    assert len(spmm) == 1 and spmm[0] in (0, 1)
+    assert len(spmm) == 1 and spmm[0] in (0, 1, 2)
 
 
 def _wait_all(srv, ids, timeout_s=120.0):
