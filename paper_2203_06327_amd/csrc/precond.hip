@@ -1070,7 +1070,8 @@ __host__ __device__ constexpr int wide_ring_size(int d) { return WIDE_NT - d; }
 
 template <int MODE>
 __global__ __launch_bounds__(64) void local_band_wide_kernel(
-    int s, int E, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
+    int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
+    const double2* __restrict__ sv,
     const double* __restrict__ lam, const float* __restrict__ Floc, long long ldF, float* __restrict__ zloc,
     float* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
     int* __restrict__ negflag) {
@@ -1094,6 +1095,9 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
     const int off = subptr[l];
     const int nl = subptr[l + 1] - off;
     const int npan = (nl + 15) >> 4;
+    // tile-rows of the panel that can hold a nonzero (rows r - c <= w below the panel's
+    // columns): the trailing update of the others adds zero and is skipped
+    const int imax = min(NT - 1, (bwv[l] + 15) >> 4);
     const double lamd = MODE ? 0.0 : lam[i];
     const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
     const int q = lane >> 2, slot0 = lane & 3;
@@ -1267,18 +1271,23 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
 #pragma unroll
             for (int k = 0; k < 4; ++k) bop[J][k] = src[k];
         }
-#pragma unroll
+        // per tile-row: its tiles are read together, their MFMAs interleaved (no
+        // dependent pair back to back), then written back
+#pragma clang loop unroll(full)
         for (int I = 1; I < NT; ++I) {
-            T aop[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) aop[k] = -bop[I][k] * dcol[k];
-#pragma unroll
-            for (int J = 1; J <= I; ++J) {
-                floatx4_t* tp = reinterpret_cast<floatx4_t*>(tile(P, I, J)) + lane;
-                acc_t acc = *tp;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc = MT::mma(aop[k], bop[J][k], acc);
-                *tp = acc;
+            if (I <= imax) {                               // uniform
+                T aop[4];
+#pragma clang loop unroll(full)
+                for (int k = 0; k < 4; ++k) aop[k] = -bop[I][k] * dcol[k];
+                acc_t acc[NT];
+#pragma clang loop unroll(full)
+                for (int J = 1; J <= I; ++J) acc[J] = reinterpret_cast<const floatx4_t*>(tile(P, I, J))[lane];
+#pragma clang loop unroll(full)
+                for (int k = 0; k < 4; ++k)
+#pragma clang loop unroll(full)
+                    for (int J = 1; J <= I; ++J) acc[J] = MT::mma(aop[k], bop[J][k], acc[J]);
+#pragma clang loop unroll(full)
+                for (int J = 1; J <= I; ++J) reinterpret_cast<floatx4_t*>(tile(P, I, J))[lane] = acc[J];
             }
         }
         // shift the right-hand side by 16 window rows; fresh rows enter at the bottom
@@ -1365,7 +1374,7 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
 
 template <typename T>
 static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s, int E, int bws, long long sumN,
-                              const int* subptr, const int* sd, const double2* sv, const double* lam, const T* Floc,
+                              const int* subptr, const int* bw, const int* sd, const double2* sv, const double* lam, const T* Floc,
                               T* zloc, T* Lwork, const long long* Loff, int* status, int* negflag) {
     // mode 0: every system with shift lambda_i; mode 1: the systems found indefinite,
     // again with shift 0 (its waves return at once when no system was flagged).
@@ -1380,8 +1389,8 @@ static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s,
     } else if (nt == WIDE_NT) {
         if constexpr (sizeof(T) == 4) {
             auto wide = [&](auto kernel) {
-                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, subptr, sd, sv, lam, Floc, sumN,
-                                   zloc, Lwork, Loff, status, negflag);
+                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, subptr, bw, sd, sv, lam, Floc,
+                                   sumN, zloc, Lwork, Loff, status, negflag);
             };
             if (mode == 0) wide(local_band_wide_kernel<0>);
             else wide(local_band_wide_kernel<1>);
@@ -1406,7 +1415,7 @@ void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC,
                             const double2* sv, const double* lam, const double* Floc, double* zloc, double* Lwork,
                             const long long* Loff, int* status, int* negflag, int threads) {
     if (blocked) {
-        launch_local_mfma<double>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff,
+        launch_local_mfma<double>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, bw, sd, sv, lam, Floc, zloc, Lwork, Loff,
                                status, negflag);
         return;
     }
@@ -1420,7 +1429,7 @@ void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC,
                             const double2* sv, const double* lam, const float* Floc, float* zloc, float* Lwork,
                             const long long* Loff, int* status, int* negflag, int threads) {
     if (blocked) {
-        launch_local_mfma<float>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, sd, sv, lam, Floc, zloc, Lwork, Loff,
+        launch_local_mfma<float>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, bw, sd, sv, lam, Floc, zloc, Lwork, Loff,
                                status, negflag);
         return;
     }
