@@ -1069,16 +1069,22 @@ __host__ __device__ constexpr int wide_ring_base(int d) { return WIDE_NT * d - d
 __host__ __device__ constexpr int wide_ring_size(int d) { return WIDE_NT - d; }
 
 template <int MODE>
-__global__ __launch_bounds__(64) void local_band_wide_kernel(
+__global__ __launch_bounds__(128) void local_band_wide_kernel(
     int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
     const double2* __restrict__ sv,
     const double* __restrict__ lam, const float* __restrict__ Floc, long long ldF, float* __restrict__ zloc,
     float* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
     int* __restrict__ negflag) {
+    // Two wavefronts per system.  Wave 0 holds window rows 0..127 (row sets 0 and 1),
+    // wave 1 rows 128..191 (set 2) and brings in the entering tile-rows while wave 0
+    // eliminates rows 0..63; the trailing tile-rows are split between the waves
+    // (33 tiles each); the backward sweep runs on wave 0.  Barriers are LDS-only
+    // except one full barrier after the forward sweep (the factor columns wave 1 stored
+    // are read back by wave 0).
     using T = float;
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
-    constexpr int NT = WIDE_NT, R = WIDE_R, NS = 3, EPL = WIDE_EPL;
+    constexpr int NT = WIDE_NT, R = WIDE_R, EPL = WIDE_EPL;
     constexpr int QS = 20;                     // row stride of the factored panel (16-byte rows, spread banks)
     constexpr int PS = 196;                    // backward sweep: column stride of its panel copy
     static_assert(WIDE_TILES * 256 >= 16 * PS, "the backward sweep's copy aliases the tile rings");
@@ -1089,7 +1095,7 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
     __shared__ T ucol[16][17];                 // column c of the panel at elimination step c
     __shared__ T urc[16], uyc[16];             // pivot reciprocal and y_c of step c
     const int sys = blockIdx.x;
-    if (MODE && !negflag[sys]) return;
+    if (MODE && !negflag[sys]) return;         // uniform over the workgroup
     const int l = sys / s;
     const int i = sys - l * s;
     const int off = subptr[l];
@@ -1099,7 +1105,8 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
     // columns): the trailing update of the others adds zero and is skipped
     const int imax = min(NT - 1, (bwv[l] + 15) >> 4);
     const double lamd = MODE ? 0.0 : lam[i];
-    const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int q = lane >> 2, slot0 = lane & 3;
     T* Lp = Lwork + Loff[l] + (long long)i * npan * (16 * R);
     const float* f = Floc + (long long)i * ldF + off;
@@ -1153,101 +1160,125 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
         for (int J = 0; J <= I; ++J)
             reinterpret_cast<floatx4_t*>(tile(P, I, J))[lane] = floatx4_t{T(0), T(0), T(0), T(0)};
     };
-
+    // panel row lr of tile (I, 0): its 16 columns
+    auto read_row = [&](const int P, const int I, T (&dst)[16]) {
+        const T* t = tiles + (wide_ring_base(I) + (P + I) % wide_ring_size(I)) * 256 + 64 * (lr >> 2) + (lr & 3);
 #pragma unroll
-    for (int I = 0; I < NT; ++I) zero_row_tiles(0, I);
-    wave_sync();
-#pragma unroll
-    for (int I = 0; I < NT; ++I) {
-        fetch(16 * I);
-        place(0, I, 16 * I);
-    }
-    T y[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const T fv = f[min(64 * k + lane, nl - 1)];         // unconditional, clamped, then selected
-        y[k] = (64 * k + lane < nl) ? fv : T(0);
-    }
-    int bad = 0, neg = 0;
-
-    for (int P = 0; P < npan; ++P) {
-        const int base = 16 * P;
-        fetch(base + R);                                   // the tile-row entering after this panel
-        const int rnew = base + 16 + 128 + lane;           // set 3 row after the slide (lanes 48..63)
-        const T fraw = f[min(rnew, nl - 1)];
-        wave_sync();
-        // panel rows: row 64 k + lane is row lr of tile (4 k + lg, 0)
-        T a[NS][16];
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            const int I = 4 * k + lg;
-            const T* t = tiles + (wide_ring_base(I) + (P + I) % wide_ring_size(I)) * 256 + 64 * (lr >> 2) + (lr & 3);
-#pragma unroll
-            for (int c = 0; c < 16; ++c) a[k][c] = t[4 * c];
-        }
-        wave_sync();
-        // the panel tiles are free: the next tile-row takes their slots
-        if (P + 1 < npan) {
-            zero_row_tiles(P + 1, NT - 1);
-            wave_sync();
-            place(P + 1, NT - 1, base + R);
-        }
-        // rows 0..63: elimination with lane broadcasts; step c's column (rows c..15), the
-        // pivot reciprocal and y_c are recorded for the rows below
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const T u = a[0][c];
-            const T dc = MT::bcast(u, c);
-            const T rc = MT::recip(dc);
-            const T yc = MT::bcast(y[0], c);
-            if (lane < 16) ucol[c][lane] = u;
-            if (lane == 0) {
-                urc[c] = rc;
-                uyc[c] = yc;
-            }
-            T urow[16];
-#pragma unroll
-            for (int c2 = c + 1; c2 < 16; ++c2) urow[c2] = MT::bcast(u, c2);
-            const T lt = u * rc;
-#pragma unroll
-            for (int c2 = c + 1; c2 < 16; ++c2) a[0][c2] -= lt * urow[c2];
-            if (lane > c) y[0] -= lt * yc;
-            a[0][c] = (lane == c) ? dc : lt;
-        }
-        wave_sync();
-        // rows 64..191 lie below the panel: the same steps with the recorded values
-        // (constant trip counts, so that every loop unrolls and the rows stay in registers)
+        for (int c = 0; c < 16; ++c) dst[c] = t[4 * c];
+    };
+    // rows below the pivot block: the elimination steps with the values recorded by wave 0
+    // (constant trip counts, so that every loop unrolls and the rows stay in registers)
+    auto eliminate_below = [&](T (&ar)[16], T& yr) {
 #pragma clang loop unroll(full)
         for (int c = 0; c < 16; ++c) {
             const T rc = urc[c], yc = uyc[c];
             T urow[16];
 #pragma clang loop unroll(full)
             for (int c2 = 0; c2 < 16; ++c2) urow[c2] = ucol[c][c2];
-            const T lt1 = a[1][c] * rc, lt2 = a[2][c] * rc;
+            const T lt = ar[c] * rc;
 #pragma clang loop unroll(full)
-            for (int c2 = 0; c2 < 16; ++c2) {
-                if (c2 > c) {
-                    a[1][c2] -= lt1 * urow[c2];
-                    a[2][c2] -= lt2 * urow[c2];
-                }
-            }
-            y[1] -= lt1 * yc;
-            y[2] -= lt2 * yc;
-            a[1][c] = lt1;
-            a[2][c] = lt2;
+            for (int c2 = 0; c2 < 16; ++c2)
+                if (c2 > c) ar[c2] -= lt * urow[c2];
+            yr -= lt * yc;
+            ar[c] = lt;
         }
-        // the factored panel's full columns (window rows 0..191) for the backward sweep
-        T* Lb = Lp + (long long)P * (16 * R) + lane;
+    };
+
+    // the first window: wave 0 clears the tiles, wave 1 brings in rows 0..191
+    if (wv == 0) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
+        for (int I = 0; I < NT; ++I) zero_row_tiles(0, I);
+    }
+    lds_barrier();
+    if (wv == 1) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) Lb[c * R + 64 * k] = a[k][c];
+        for (int I = 0; I < NT; ++I) {
+            fetch(16 * I);
+            place(0, I, 16 * I);
+        }
+    }
+    // right-hand sides: wave 0 rows 0..127 (ya, yb), wave 1 rows 128..191 (ya)
+    T ya, yb = T(0);
+    {
+        const int r0 = wv == 0 ? lane : 128 + lane;
+        const T fa = f[min(r0, nl - 1)];                    // unconditional, clamped, then selected
+        ya = (r0 < nl) ? fa : T(0);
+        if (wv == 0) {
+            const T fb = f[min(64 + lane, nl - 1)];
+            yb = (64 + lane < nl) ? fb : T(0);
+        }
+    }
+    lds_barrier();
+    int bad = 0, neg = 0;
+
+    for (int P = 0; P < npan; ++P) {
+        const int base = 16 * P;
+        const int rnew = base + 16 + 128 + lane;           // set 2 row after the slide (lanes 48..63)
+        T fraw = T(0);
+        if (wv == 1) {
+            fetch(base + R);                               // the tile-row entering after this panel
+            fraw = f[min(rnew, nl - 1)];
+        }
+        // panel rows: row 64 k + lane is row lr of tile (4 k + lg, 0)
+        T a0[16], a1[16];
+        if (wv == 0) {
+            read_row(P, lg, a0);
+            read_row(P, 4 + lg, a1);
+        } else {
+            read_row(P, 8 + lg, a0);
+        }
+        lds_barrier();                                     // the panel tiles are free
+        if (wv == 0) {
+            // rows 0..63: elimination with lane broadcasts; step c's column (rows c..15),
+            // the pivot reciprocal and y_c are recorded for the rows below
 #pragma unroll
-        for (int k = 0; k < NS; ++k)
+            for (int c = 0; c < 16; ++c) {
+                const T u = a0[c];
+                const T dc = MT::bcast(u, c);
+                const T rc = MT::recip(dc);
+                const T yc = MT::bcast(ya, c);
+                if (lane < 16) ucol[c][lane] = u;
+                if (lane == 0) {
+                    urc[c] = rc;
+                    uyc[c] = yc;
+                }
+                T urow[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) pan[64 * k + lane][c] = a[k][c];
-        wave_sync();
+                for (int c2 = c + 1; c2 < 16; ++c2) urow[c2] = MT::bcast(u, c2);
+                const T lt = u * rc;
+#pragma unroll
+                for (int c2 = c + 1; c2 < 16; ++c2) a0[c2] -= lt * urow[c2];
+                if (lane > c) ya -= lt * yc;
+                a0[c] = (lane == c) ? dc : lt;
+            }
+        } else if (P + 1 < npan) {
+            // the next tile-row takes the panel tiles' slots
+            zero_row_tiles(P + 1, NT - 1);
+            wave_sync();
+            place(P + 1, NT - 1, base + R);
+        }
+        lds_barrier();
+        // rows 64..127 (wave 0) and 128..191 (wave 1) lie below the panel
+        if (wv == 0) eliminate_below(a1, yb);
+        else eliminate_below(a0, ya);
+        // the factored panel's full columns (window rows 0..191) for the backward sweep,
+        // and its rows, row-major, as MFMA operands
         {
+            T* Lb = Lp + (long long)P * (16 * R) + lane + (wv == 0 ? 0 : 128);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) Lb[c * R] = a0[c];
+            T (*prow)[QS] = pan + (wv == 0 ? 0 : 128) + lane;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) prow[0][c] = a0[c];
+            if (wv == 0) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) Lb[c * R + 64] = a1[c];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) prow[64][c] = a1[c];
+            }
+        }
+        lds_barrier();
+        if (wv == 0) {
             // pivots of the panel (checked once per panel) and D^{-1} L^{-1} f of its rows,
             // stored by every lane (rows past the end repeat the last row's value)
             const T dl = pan[lane & 15][lane & 15];
@@ -1256,11 +1287,13 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
                 neg |= dl < T(0);
             }
             const int zr = min(lane & 15, nl - 1 - base);
-            const T zv = __shfl(y[0] * MT::recip(dl), zr, 64);
+            const T zv = __shfl(ya * MT::recip(dl), zr, 64);
             z[base + zr] = zv;
         }
-        // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T, read from and
-        // written back to their ring slots (the next panel's tile (I - 1, J - 1))
+        // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T; tile-rows
+        // {1, 2, 5, 6, 9, 10} on wave 0 and {3, 4, 7, 8, 11} on wave 1 (33 tiles each).
+        // Per tile-row: its tiles are read together, their MFMAs interleaved, then written
+        // back to their ring slots (the next panel's tiles (I - 1, J - 1)).
         T dcol[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) dcol[k] = pan[4 * lg + k][4 * lg + k];
@@ -1271,11 +1304,10 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
 #pragma unroll
             for (int k = 0; k < 4; ++k) bop[J][k] = src[k];
         }
-        // per tile-row: its tiles are read together, their MFMAs interleaved (no
-        // dependent pair back to back), then written back
 #pragma clang loop unroll(full)
         for (int I = 1; I < NT; ++I) {
-            if (I <= imax) {                               // uniform
+            const int owner = ((I - 1) >> 1) & 1;          // 1,2 -> 0; 3,4 -> 1; 5,6 -> 0; ...
+            if (I <= imax && wv == owner) {                // uniform per wave
                 T aop[4];
 #pragma clang loop unroll(full)
                 for (int k = 0; k < 4; ++k) aop[k] = -bop[I][k] * dcol[k];
@@ -1291,16 +1323,27 @@ __global__ __launch_bounds__(64) void local_band_wide_kernel(
             }
         }
         // shift the right-hand side by 16 window rows; fresh rows enter at the bottom
-#pragma unroll
-        for (int k = 0; k < NS; ++k) vec[64 * k + lane] = y[k];
-        wave_sync();
-        y[0] = vec[lane + 16];
-        y[1] = vec[80 + lane];
-        y[2] = (lane < 48) ? vec[min(144 + lane, R - 1)] : ((rnew < nl) ? fraw : T(0));
-        wave_sync();
+        if (wv == 0) {
+            vec[lane] = ya;
+            vec[64 + lane] = yb;
+        } else {
+            vec[128 + lane] = ya;
+        }
+        lds_barrier();
+        if (wv == 0) {
+            ya = vec[lane + 16];
+            yb = vec[80 + lane];
+        } else {
+            ya = (lane < 48) ? vec[min(144 + lane, R - 1)] : ((rnew < nl) ? fraw : T(0));
+        }
+        lds_barrier();                                     // tiles and vec complete for the next panel
     }
+    __syncthreads();                                       // wave 1's factor columns are in memory
+    if (wv != 0) return;
 
-    // backward sweep with L^T, panel by panel from the end; zw holds z of the window rows
+    // backward sweep with L^T (wave 0), panel by panel from the end; zw holds z of the
+    // window rows (three row sets)
+    constexpr int NS = 3;
     T zw[NS] = {T(0), T(0), T(0)};
     T (*bt)[PS] = reinterpret_cast<T (*)[PS]>(tiles);
     T bufA[NS][16], bufB[NS][16];
@@ -1389,7 +1432,7 @@ static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s,
     } else if (nt == WIDE_NT) {
         if constexpr (sizeof(T) == 4) {
             auto wide = [&](auto kernel) {
-                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, subptr, bw, sd, sv, lam, Floc,
+                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(128), 0, st, s, E, subptr, bw, sd, sv, lam, Floc,
                                    sumN, zloc, Lwork, Loff, status, negflag);
             };
             if (mode == 0) wide(local_band_wide_kernel<0>);
