@@ -1,6 +1,7 @@
 // Block linear algebra on n x c row-major FP64 blocks: fused SpMM with K and M,
 // residual block, Gram products, tall-times-small products.  All reductions are
 // two-pass with a fixed summation order, so results do not depend on timing.
+#include <algorithm>
 #include <cstdint>
 
 #include "common.h"
@@ -408,6 +409,185 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, con
             }
 }
 
+// The same Gram product for the blocked layout with whole runs (ld = bw, a and b multiples
+// of bw, 16-byte aligned block bases, bs even): the workgroup's chunk is taken in
+// sub-tiles of GM_ROWS rows whose runs of A and B are copied into LDS by direct
+// global-to-LDS loads (16 bytes per lane), double-buffered: the copy of sub-tile i + 1 is
+// in flight while sub-tile i is multiplied.  Wavefront w takes k-steps w and w + 4 of each
+// sub-tile, so every accumulator sees the rows in the order gram_mfma_kernel uses, and
+// the wavefronts' accumulators are added in the same order: both give identical results.
+constexpr int GM_ROWS = 32;
+
+// direct global-to-LDS copies: lane l's 16 (4) bytes at g land at l + 16 (4) * lane bytes,
+// l the same for the whole wavefront; completion is counted by vmcnt
+__device__ inline void lds_dma16(const double* g, double* l) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g),
+                                     (__attribute__((address_space(3))) void*)(l), 16, 0, 0);
+}
+__device__ inline void lds_dma4(const unsigned* g, unsigned* l) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g),
+                                     (__attribute__((address_space(3))) void*)(l), 4, 0, 0);
+}
+
+__device__ inline void lds_copy_runs(const double* src, long long bs, long long goff, int cnt, double* dst,
+                                     int runl, int nrun, int w, int lane, int t) {
+    const int npair = cnt >> 1;
+    const int nch = (npair + 63) >> 6;
+    for (int j = w; j < nrun * nch; j += 4) {
+        const int jb = j / nch, ch = j - jb * nch;
+        const int e2 = 64 * ch + lane;
+        if (e2 < npair) lds_dma16(src + jb * bs + goff + 2 * e2, dst + jb * runl + 128 * ch);
+    }
+    if (cnt & 1)
+        for (int jb = t; jb < nrun; jb += 256) dst[jb * runl + cnt - 1] = src[jb * bs + goff + cnt - 1];
+}
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TA * TB >= 16 ? 2 : 3))) void gram_flat_kernel(
+    int n, int a, int b, const double* __restrict__ A,
+                                                        const double* __restrict__ B, int bw, long long bs,
+                                                        int chunk, double* __restrict__ partial) {
+    extern __shared__ __align__(16) double gm_smem[];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63, lr = lane & 15, lk = lane >> 4;
+    const int runl = GM_ROWS * bw;
+    const int nra = a / bw, nrb = b / bw;
+    const int bufsz = GM_ROWS * (a + b);       // one sub-tile: A's runs, then B's
+    const int r0 = blockIdx.x * chunk;
+    const int r1 = min(n, r0 + chunk);
+    const int nst = (r1 - r0 + GM_ROWS - 1) / GM_ROWS;
+    // LDS offsets of this lane's columns within a sub-tile (-1: past a or b)
+    int oa[TA], ob[TB];
+#pragma unroll
+    for (int p = 0; p < TA; ++p) {
+        const int c = 16 * p + lr, jb = c / bw;
+        oa[p] = (c < a) ? jb * runl + (c - jb * bw) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < TB; ++q) {
+        const int c = 16 * q + lr, jb = c / bw;
+        ob[q] = (c < b) ? GM_ROWS * a + jb * runl + (c - jb * bw) : -1;
+    }
+    auto fetch = [&](int i) {
+        const int rs = r0 + GM_ROWS * i;
+        const int cnt = min(GM_ROWS, r1 - rs) * bw;
+        double* buf = gm_smem + (i & 1) * bufsz;
+        lds_copy_runs(A, bs, (long long)rs * bw, cnt, buf, runl, nra, w, lane, t);
+        lds_copy_runs(B, bs, (long long)rs * bw, cnt, buf + GM_ROWS * a, runl, nrb, w, lane, t);
+    };
+    dx4_t acc[TA][TB];
+#pragma unroll
+    for (int p = 0; p < TA; ++p)
+#pragma unroll
+        for (int q = 0; q < TB; ++q) acc[p][q] = dx4_t{0.0, 0.0, 0.0, 0.0};
+    if (nst > 0) fetch(0);
+    for (int i = 0; i < nst; ++i) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();                       // sub-tile i is in; sub-tile i - 1's buffer is free
+        if (i + 1 < nst) fetch(i + 1);
+        const double* buf = gm_smem + (i & 1) * bufsz;
+        const int rows = min(GM_ROWS, r1 - (r0 + GM_ROWS * i));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 4 * (w + 4 * h) + lk;
+            const bool rok = row < rows;
+            double av[TA], bv[TB];
+#pragma unroll
+            for (int p = 0; p < TA; ++p) av[p] = (rok && oa[p] >= 0) ? buf[oa[p] + row * bw] : 0.0;
+#pragma unroll
+            for (int q = 0; q < TB; ++q) bv[q] = (rok && ob[q] >= 0) ? buf[ob[q] + row * bw] : 0.0;
+#pragma unroll
+            for (int p = 0; p < TA; ++p)
+#pragma unroll
+                for (int q = 0; q < TB; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+        }
+    }
+    // wavefronts 1..3 hand their accumulators over in two rounds (LDS of the sub-tile
+    // buffers); wavefront 0 adds them in the order 1, 2, 3
+    constexpr int NE = TA * TB * 4;
+    double* red = gm_smem;                     // [2][NE][64]
+    __syncthreads();                           // every sub-tile read is done
+    if (w == 1 || w == 2) {
+#pragma unroll
+        for (int p = 0; p < TA; ++p)
+#pragma unroll
+            for (int q = 0; q < TB; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[((w - 1) * NE + (p * TB + q) * 4 + i) * 64 + lane] = acc[p][q][i];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int p = 0; p < TA; ++p)
+#pragma unroll
+            for (int q = 0; q < TB; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = (p * TB + q) * 4 + i;
+                    acc[p][q][i] = (acc[p][q][i] + red[e * 64 + lane]) + red[(NE + e) * 64 + lane];
+                }
+    }
+    __syncthreads();
+    if (w == 3) {
+#pragma unroll
+        for (int p = 0; p < TA; ++p)
+#pragma unroll
+            for (int q = 0; q < TB; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[((p * TB + q) * 4 + i) * 64 + lane] = acc[p][q][i];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    // FP64 accumulator element i of lane l: row l/16 + 4 i, column l%16 of the 16x16 tile
+#pragma unroll
+    for (int p = 0; p < TA; ++p)
+#pragma unroll
+        for (int q = 0; q < TB; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = (p * TB + q) * 4 + i;
+                const double v = acc[p][q][i] + red[e * 64 + lane];
+                const int row = 16 * p + lk + 4 * i, col = 16 * q + lr;
+                if (row < a && col < b) partial[(long long)(row * b + col) * gridDim.x + blockIdx.x] = v;
+            }
+}
+
+// Workgroups of `kernel` resident at once on the current device (0 if unknown).
+template <typename K>
+static int resident_blocks(K kernel, size_t smem) {
+    int dev = 0, cu = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, smem) != hipSuccess) return 0;
+    return nb * cu;
+}
+
+// The flat Gram's rows are split into as many chunks as workgroups fit on the device at
+// once (at most npart; whole sub-tiles per chunk): every chunk then runs in the first
+// and only round, with no tail round of a few long workgroups.  Returns the grid.
+template <int TA, int TB>
+static int gram_flat_launch(hipStream_t st, size_t smem, int n, int a, int b, const double* A, const double* B,
+                            int bw, long long bs, int npart, double* partial) {
+    auto kernel = gram_flat_kernel<TA, TB>;
+    int groups = resident_blocks(kernel, smem);
+    groups = (groups <= 0) ? npart : std::min(groups, npart);
+    const int chunk = (((n + groups - 1) / groups) + GM_ROWS - 1) / GM_ROWS * GM_ROWS;
+    const int grid = std::max(1, (n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), smem, st, n, a, b, A, B, bw, bs, chunk, partial);
+    return grid;
+}
+
+template <int TA>
+static int gram_flat_dispatch_b(hipStream_t st, int TB, size_t smem, int n, int a, int b, const double* A,
+                                const double* B, int bw, long long bs, int npart, double* partial) {
+    switch (TB) {
+        case 1: return gram_flat_launch<TA, 1>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
+        case 2: return gram_flat_launch<TA, 2>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
+        case 3: return gram_flat_launch<TA, 3>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
+        default: return gram_flat_launch<TA, 4>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
+    }
+}
+
 template <int TA>
 static void gram_dispatch_b(hipStream_t st, int TB, int grid, int n, int a, int b, const double* A,
                             const double* B, BlockGeom g, int chunk, double* partial) {
@@ -427,6 +607,21 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, const dou
     while ((n + chunk - 1) / chunk > npart) chunk *= 2;
     const int grid = (n + chunk - 1) / chunk;
     const int TA = (a + 15) / 16, TB = (b + 15) / 16;
+    // the flat form: whole runs of the blocked layout, 16-byte aligned; LDS for two
+    // sub-tiles, or for the accumulator hand-over when that is larger
+    const size_t smem = sizeof(double) * std::max<size_t>(2 * (size_t)GM_ROWS * (a + b), 2 * (size_t)TA * TB * 256);
+    if (g.ld == g.bw && g.bw >= 1 && a % g.bw == 0 && b % g.bw == 0 && g.bs % 2 == 0 && smem <= 65536 &&
+        ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0) {
+        int fgrid;
+        switch (TA) {
+            case 1: fgrid = gram_flat_dispatch_b<1>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            case 2: fgrid = gram_flat_dispatch_b<2>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            case 3: fgrid = gram_flat_dispatch_b<3>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            default: fgrid = gram_flat_dispatch_b<4>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+        }
+        launch_reduce(st, fgrid, a * b, partial, C);
+        return;
+    }
     switch (TA) {
         case 1: gram_dispatch_b<1>(st, TB, grid, n, a, b, A, B, g, chunk, partial); break;
         case 2: gram_dispatch_b<2>(st, TB, grid, n, a, b, A, B, g, chunk, partial); break;
@@ -593,6 +788,125 @@ __global__ __launch_bounds__(256) void gemm_rows_kernel(int n, int a, int b, dou
     }
 }
 
+// The same product for the blocked layout with whole runs (ld = bw >= 4, a and b
+// multiples of bw, 16-byte aligned block bases, bs even): a block's rows of each n x bw
+// block of A (and of Y when beta != 0) form one contiguous run of GR_ROWS * bw values,
+// copied into LDS as it lies in memory by direct global-to-LDS loads of 16 bytes per lane
+// (C too, or 4 bytes per lane when C is only 8-byte aligned), every load of the tile
+// issued before the first is waited for.  The MFMAs read the
+// runs in place (lane l's column k lies in run k / bw at column k % bw, advanced by four
+// per k-step), in the same k-order as gemm_rows_kernel, so both give identical results.
+// The result is laid out as Y's runs in LDS (over A's) and written with 16-byte stores.
+
+__global__ __launch_bounds__(256) void gemm_flat_kernel(int n, int a, int b, double alpha, Triple T, int bw,
+                                                        long long bs, const double* __restrict__ C, double beta) {
+    extern __shared__ __align__(16) double gf_smem[];
+    const int runl = GR_ROWS * bw;             // LDS stride of the runs
+    const int nra = a / bw, nrb = b / bw;
+    double* sA = gf_smem;                      // A's runs, then Y's
+    double* sO = sA + GR_ROWS * max(a, b);     // old Y's runs (beta != 0)
+    double* sC = sO + (beta != 0.0 ? GR_ROWS * b : 0);   // C, a x b row-major
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int r0 = blockIdx.x * GR_ROWS;
+    const int rows = min(GR_ROWS, n - r0);
+    const int cnt = rows * bw;                 // values per run (odd only in the last block)
+    const int npair = cnt >> 1;
+    const int nch = (npair + 63) >> 6;         // 64-pair chunks per run
+    const double* A = T.A[blockIdx.y];
+    double* Y = T.Y[blockIdx.y];
+    const long long goff = (long long)r0 * bw;
+    // wave w copies chunks w, w + 4, ... of the runs; the odd last value by a plain load
+    auto copy_runs = [&](const double* src, double* dst, int nrun) {
+        for (int j = w; j < nrun * nch; j += 4) {
+            const int jb = j / nch, ch = j - jb * nch;
+            const int e2 = 64 * ch + lane;
+            if (e2 < npair) lds_dma16(src + jb * bs + goff + 2 * e2, dst + jb * runl + 128 * ch);
+        }
+        if (cnt & 1)
+            for (int jb = t; jb < nrun; jb += 256) dst[jb * runl + cnt - 1] = src[jb * bs + goff + cnt - 1];
+    };
+    copy_runs(A, sA, nra);
+    if (beta != 0.0) copy_runs(Y, sO, nrb);
+    if ((reinterpret_cast<uintptr_t>(C) & 15) == 0) {
+        // C in 16-byte pieces (the odd last value by a plain load)
+        const int np = (a * b) >> 1;
+        for (int j = w; 64 * j < np; j += 4)
+            if (64 * j + lane < np) lds_dma16(C + 2 * (64 * j + lane), sC + 128 * j);
+        if (((a * b) & 1) && t == 0) sC[a * b - 1] = C[a * b - 1];
+    } else {
+        // C as 32-bit words, 4 bytes per lane (any 8-byte aligned C)
+        const int nw = 2 * a * b;
+        const unsigned* cw = reinterpret_cast<const unsigned*>(C);
+        unsigned* scw = reinterpret_cast<unsigned*>(sC);
+        for (int j = w; 64 * j < nw; j += 4)
+            if (64 * j + lane < nw) lds_dma4(cw + 64 * j + lane, scw + 64 * j);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ak = (a + 3) & ~3;
+    const double* arow = sA + (16 * w + lr) * bw;
+    int kb = 0, kc = lk;                       // run and column of this lane's k (bw >= 4)
+    dx4_t acc[GR_MAXC / 16];
+#pragma unroll
+    for (int qt = 0; qt < GR_MAXC / 16; ++qt) acc[qt] = dx4_t{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < ak; k0 += 4) {
+        const int k = k0 + lk;
+        const double av = (k < a) ? arow[kb * runl + kc] : 0.0;
+#pragma unroll
+        for (int qt = 0; qt < GR_MAXC / 16; ++qt) {
+            const int q = 16 * qt + lr;
+            if (16 * qt < b) {
+                const double cv = (k < a && q < b) ? sC[k * b + q] : 0.0;
+                acc[qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cv, acc[qt], 0, 0, 0);
+            }
+        }
+        kc += 4;
+        if (kc >= bw) {
+            kc -= bw;
+            ++kb;
+        }
+    }
+    __syncthreads();                           // every MFMA operand has been read
+    // element i of lane l is row l / 16 + 4 i, column l % 16 of a tile
+#pragma unroll
+    for (int qt = 0; qt < GR_MAXC / 16; ++qt) {
+        const int q = 16 * qt + lr;
+        if (16 * qt < b && q < b) {
+            const int jq = q / bw;
+            double* dst = sA + jq * runl + (q - jq * bw) + (16 * w + lk) * bw;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dst[4 * i * bw] = acc[qt][i];
+        }
+    }
+    __syncthreads();
+    for (int jb = 0; jb < nrb; ++jb) {
+        const double* l = sA + jb * runl;
+        const double* lo = sO + jb * runl;
+        double* g = Y + jb * bs + goff;
+        for (int e2 = t; e2 < npair; e2 += 256) {
+            const double2 v = *reinterpret_cast<const double2*>(l + 2 * e2);
+            double2 o;
+            if (beta == 0.0) {
+                o = make_double2(alpha * v.x, alpha * v.y);
+            } else {
+                const double2 old = *reinterpret_cast<const double2*>(lo + 2 * e2);
+                o = make_double2(fma(beta, old.x, alpha * v.x), fma(beta, old.y, alpha * v.y));
+            }
+            *reinterpret_cast<double2*>(g + 2 * e2) = o;
+        }
+        if ((cnt & 1) && t == 0) {
+            const double v = l[cnt - 1];
+            g[cnt - 1] = (beta == 0.0) ? alpha * v : fma(beta, lo[cnt - 1], alpha * v);
+        }
+    }
+}
+
+static size_t gemm_flat_smem(int a, int b, double beta) {
+    return sizeof(double) * ((size_t)GR_ROWS * (a > b ? a : b) + (beta != 0.0 ? (size_t)GR_ROWS * b : 0) +
+                             (size_t)a * b);
+}
+
 static size_t gemm_rows_smem(int a, int b) {
     const size_t ak = (a + 3) & ~3, bq = (b + 15) & ~15;
     const size_t rowsz = ak + 1 > bq + 1 ? ak + 1 : bq + 1;
@@ -615,6 +929,11 @@ void launch_gemm_rows(hipStream_t st, int n, int a, int b, double alpha, const d
         T.Y[k] = Y[k];
     }
     const int flat = gemm_rows_flat(a, b, g, A, Y, count);
+    if (flat && g.bw >= 4 && gemm_flat_smem(a, b, beta) <= 65536) {
+        hipLaunchKernelGGL(gemm_flat_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_flat_smem(a, b, beta),
+                           st, n, a, b, alpha, T, g.bw, g.bs, C, beta);
+        return;
+    }
     hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(a, b), st, n, a,
                        b, alpha, T, g, C, beta, flat);
 }
@@ -626,6 +945,11 @@ void launch_rightmul_rows(hipStream_t st, int n, int b, double* const* Y, int co
         T.Y[k] = Y[k];
     }
     const int flat = gemm_rows_flat(b, b, g, Y, Y, count);
+    if (flat && g.bw >= 4 && gemm_flat_smem(b, b, 0.0) <= 65536) {
+        hipLaunchKernelGGL(gemm_flat_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_flat_smem(b, b, 0.0),
+                           st, n, b, b, 1.0, T, g.bw, g.bs, C, 0.0);
+        return;
+    }
     hipLaunchKernelGGL(gemm_rows_kernel, dim3(grid_for(n, GR_ROWS), count), dim3(256), gemm_rows_smem(b, b), st, n, b,
                        b, 1.0, T, g, C, 0.0, flat);
 }
