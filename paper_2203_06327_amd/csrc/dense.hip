@@ -617,16 +617,45 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double*
         const double* vk = Vh + (long long)k * n;
         double* row = A + (long long)j * n;
         double acc = 0.0;
+        // the loads of U consecutive lane strides are issued together (this loop is a chain
+        // of L2 round trips otherwise); the sum keeps the order i = k + 1 + lane, + 64, ...
+        constexpr int U = 8;
         if (k >= 1) {
             const double* vp = Vh + (long long)(k - 1) * n;
             const double vj = vp[j], wj = wbuf[j];
-            for (int i = k + 1 + lane; i < n; i += 64) {
-                const double a = row[i] - (vj * wbuf[i] + wj * vp[i]);
-                row[i] = a;
-                acc = fma(a, vk[i], acc);
+            for (int i0 = k + 1 + lane; i0 < n; i0 += 64 * U) {
+                double rv[U], wv[U], pv[U], kv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = min(i0 + 64 * u, n - 1);
+                    rv[u] = row[i];
+                    wv[u] = wbuf[i];
+                    pv[u] = vp[i];
+                    kv[u] = vk[i];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + 64 * u;
+                    if (i < n) {
+                        const double a = rv[u] - (vj * wv[u] + wj * pv[u]);
+                        row[i] = a;
+                        acc = fma(a, kv[u], acc);
+                    }
+                }
             }
         } else {
-            for (int i = k + 1 + lane; i < n; i += 64) acc = fma(row[i], vk[i], acc);
+            for (int i0 = 1 + lane; i0 < n; i0 += 64 * U) {
+                double rv[U], kv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = min(i0 + 64 * u, n - 1);
+                    rv[u] = row[i];
+                    kv[u] = vk[i];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (i0 + 64 * u < n) acc = fma(rv[u], kv[u], acc);
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
