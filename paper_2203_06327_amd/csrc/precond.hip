@@ -119,8 +119,21 @@ __global__ void coarse_coef_kernel(int nH, int s, const double* __restrict__ YT,
     for (int i0 = 0; i0 < s; i0 += 4) {
         const int i = i0 + ig;
         double acc = 0.0;
-        if (i < s)
-            for (int b = rs; b < nH; b += 16) acc = fma(yrow[b], G[b * s + i], acc);
+        if (i < s) {
+            constexpr int U = 4;               // loads of U row steps together, same sum order
+            for (int b0 = rs; b0 < nH; b0 += 16 * U) {
+                double yv[U], gv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int b = min(b0 + 16 * u, nH - 1);
+                    yv[u] = yrow[b];
+                    gv[u] = G[b * s + i];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (b0 + 16 * u < nH) acc = fma(yv[u], gv[u], acc);
+            }
+        }
         red[rs][ig] = acc;
         __syncthreads();
         if (rs == 0 && i < s) {
@@ -142,20 +155,34 @@ __global__ __launch_bounds__(64) void coarse_back_kernel(int nH, int s, const do
     double acc[BPJD_MAX_BLOCK];
 #pragma unroll
     for (int i = 0; i < BPJD_MAX_BLOCK; ++i) acc[i] = 0.0;
-    for (int j = s + lane; j < nH; j += 64) {
-        const double y = yrow[j];
-        const double* c = Cw + j * s;
+    for (int j0 = s + lane; j0 < nH; j0 += 128) {
+        // two row steps whose loads are issued together; the sum keeps the order of j
+        const int j1 = min(j0 + 64, nH - 1);
+        const double y0 = yrow[j0], y1 = yrow[j1];
+        const double* c0 = Cw + j0 * s;
+        const double* c1 = Cw + j1 * s;
+        double cv0[BPJD_MAX_BLOCK], cv1[BPJD_MAX_BLOCK];
+#pragma unroll
+        for (int i = 0; i < BPJD_MAX_BLOCK; ++i) {
+            cv0[i] = (i < s) ? c0[i] : 0.0;
+            cv1[i] = (i < s) ? c1[i] : 0.0;
+        }
 #pragma unroll
         for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
-            if (i < s) acc[i] = fma(y, c[i], acc[i]);
+            if (i < s) acc[i] = fma(y0, cv0[i], acc[i]);
+        if (j0 + 64 < nH)
+#pragma unroll
+            for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+                if (i < s) acc[i] = fma(y1, cv1[i], acc[i]);
     }
 #pragma unroll
     for (int i = 0; i < BPJD_MAX_BLOCK; ++i) {
-        if (i >= s) break;
-        double v = acc[i];
+        if (i < s) {
+            double v = acc[i];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) Zhat[b * s + i] = v;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) Zhat[b * s + i] = v;
+        }
     }
 }
 
@@ -181,7 +208,24 @@ __global__ __launch_bounds__(256) void restrict_cols_kernel(int s, int nchunk, i
     const int q1 = min(q0 + chunk, PTptr[a + 1]);
     double acc = 0.0;
     if (e < slots) {
-        for (int q = q0 + e; q < q1; q += slots) acc = fma(PTval[q], F[(long long)PTcol[q] * ldf + c], acc);
+        // U entries at a time: their indices, then their F values, are loaded together
+        // (a chain of dependent loads per entry otherwise); the sum keeps the entry order
+        constexpr int U = 8;
+        for (int qb = q0 + e; qb < q1; qb += U * slots) {
+            int col[U];
+            double w[U], f[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = min(qb + u * slots, q1 - 1);
+                col[u] = PTcol[q];
+                w[u] = PTval[q];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) f[u] = F[(long long)col[u] * ldf + c];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (qb + u * slots < q1) acc = fma(w[u], f[u], acc);
+        }
     }
     red[t] = acc;
     __syncthreads();
@@ -1504,18 +1548,35 @@ __global__ __launch_bounds__(256) void scatter_kernel(int n, int s, long long su
 #pragma unroll
         for (int i = 0; i < BPJD_MAX_BLOCK; ++i) acc[i] = 0.0;
         const int p0 = Pptr[d], p1 = Pptr[d + 1], e0 = rptr[d], e1 = rptr[d + 1];
-        for (int q = p0; q < p1; ++q) {
-            const int pc = Pcol[q];
-            const double pv = Pval[q];
+        // the indices (and weights) of four entries, and of four copies, are loaded
+        // together before their values; the sums keep the entry and copy order
+        constexpr int U = 4;
+        for (int qb = p0; qb < p1; qb += U) {
+            int pc[U];
+            double pv[U];
 #pragma unroll
-            for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
-                if (i < s) acc[i] = fma(pv, Zhat[pc * s + i], acc[i]);
+            for (int u = 0; u < U; ++u) {
+                const int q = min(qb + u, p1 - 1);
+                pc[u] = Pcol[q];
+                pv[u] = Pval[q];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (qb + u < p1)
+#pragma unroll
+                    for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+                        if (i < s) acc[i] = fma(pv[u], Zhat[pc[u] * s + i], acc[i]);
         }
-        for (int e = e0; e < e1; ++e) {
-            const int ri = ridx[e];
+        for (int eb = e0; eb < e1; eb += U) {
+            int ri[U];
 #pragma unroll
-            for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
-                if (i < s) acc[i] += (double)zloc[(long long)i * sumN + ri];
+            for (int u = 0; u < U; ++u) ri[u] = ridx[min(eb + u, e1 - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (eb + u < e1)
+#pragma unroll
+                    for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
+                        if (i < s) acc[i] += (double)zloc[(long long)i * sumN + ri[u]];
         }
 #pragma unroll
         for (int i = 0; i < BPJD_MAX_BLOCK; ++i)
