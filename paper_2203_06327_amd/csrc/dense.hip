@@ -1335,6 +1335,33 @@ __device__ inline void wave_lds_sync() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// S[c] = sum over the wavefront's 64 lanes of v[c] for c < cnt (<= RR_S_MAX), every lane
+// receiving every sum.  Sixteen columns at a time through an LDS transpose (buf: 64 x 17
+// doubles): lane l adds column l % 16 over rows l / 16, l / 16 + 4, ... (four chains),
+// then two lane exchanges combine the four lane groups, in a fixed order.
+__device__ inline void wave_sums16(const double (&v)[RR_S_MAX], double (&S)[RR_S_MAX], int cnt, double* buf,
+                                   int lane) {
+#pragma unroll
+    for (int base = 0; base < RR_S_MAX; base += 16) {
+        if (base < cnt) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) buf[lane * 17 + c] = (base + c < RR_S_MAX) ? v[base + c] : 0.0;
+            wave_lds_sync();
+            const int c = lane & 15, r0 = lane >> 4;
+            double part[4] = {0.0, 0.0, 0.0, 0.0};     // four chains, added pairwise
+#pragma unroll
+            for (int r = 0; r < 16; ++r) part[r & 3] += buf[(r0 + 4 * r) * 17 + c];
+            double acc = (part[0] + part[1]) + (part[2] + part[3]);
+            wave_lds_sync();
+            acc += __shfl_xor(acc, 16, 64);
+            acc += __shfl_xor(acc, 32, 64);
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (base + k < RR_S_MAX) S[base + k] = lane_bcast(acc, k);
+        }
+    }
+}
+
 template <int NM>
 __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, const double* __restrict__ H,
                                                       const int* __restrict__ drop_in, int* __restrict__ drop_out,
@@ -1351,6 +1378,7 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     __shared__ double iu0[RR_S_MAX * NM], iu1[RR_S_MAX * NM], iu2[RR_S_MAX * NM], iy[RR_S_MAX * NM];
     __shared__ int keep_idx[NM];
     __shared__ int mk;
+    __shared__ double tbuf[64 * 17];               // wave_sums16's transposition
     const int t = threadIdx.x, lane = t & 63;
     const bool w0 = t < 64;
     if (t == 0) {
@@ -1527,42 +1555,56 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
     }
     __syncthreads();
     if (!w0) return;
-    // Steps 4 to 6 run in wavefront 0 on LDS-resident vectors.  The inner products of a
-    // step are taken one per lane (a serial sum over the rows), so a step costs one LDS
-    // round trip instead of one cross-lane reduction per product.
-    // 4. two CGS passes over the ns vectors (columns of Zs), then Z <- H_0 ... H_{n-3} Z
+    // Steps 4 to 6 run in wavefront 0 with row i of every vector in registers of lane i
+    // (compile-time column loops, guarded by the uniform counts); the inner products of
+    // a step are lane-parallel products summed together by wave_sums16.
+    // 4. two CGS passes over the ns vectors (columns of Z), then Z <- H_0 ... H_{n-3} Z
+    double z[RR_S_MAX], pr[RR_S_MAX], S[RR_S_MAX];
+#pragma unroll
+    for (int c = 0; c < RR_S_MAX; ++c) {
+        z[c] = (lane < n && c < ns) ? Zs[lane * SD + c] : 0.0;
+        S[c] = 0.0;
+    }
     for (int j = 0; j < ns; ++j) {
-        for (int pass = 0; pass < 2; ++pass) {
-            if (j > 0) {
-                if (lane < j) cL[lane] = dot_strided(Zs + lane, SD, Zs + j, SD, n);
-                wave_lds_sync();
-                if (lane < n) Zs[lane * SD + j] -= dot_strided(cL, 1, Zs + lane * SD, 1, j);
-                wave_lds_sync();
-            }
+        double zj = 0.0;
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c)
+            if (c == j) zj = z[c];
+        for (int pass = 0; pass < 2 && j > 0; ++pass) {
+#pragma unroll
+            for (int c = 0; c < RR_S_MAX; ++c) pr[c] = (c < j) ? z[c] * zj : 0.0;
+            wave_sums16(pr, S, j, tbuf, lane);
+            double upd = 0.0;
+#pragma unroll
+            for (int c = 0; c < RR_S_MAX; ++c)
+                if (c < j) upd = fma(S[c], z[c], upd);
+            zj -= upd;
         }
-        if (lane == 0) cL[0] = 1.0 / sqrt(dot_strided(Zs + j, SD, Zs + j, SD, n));
-        wave_lds_sync();
-        if (lane < n) Zs[lane * SD + j] *= cL[0];
-        wave_lds_sync();
+        zj *= 1.0 / sqrt(wave_sum_dpp(zj * zj));
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c)
+            if (c == j) z[c] = zj;
     }
     for (int k = n - 3; k >= 0; --k) {
         const double tk = tauv[k];
         if (tk == 0.0) continue;
-        // d_c = tau_k v_k^T Z[:, c] (v_k is zero above row k + 1)
-        if (lane < ns) cL[lane] = tk * dot_strided(&Vk[k][k + 1], 1, Zs + (k + 1) * SD + lane, SD, n - k - 1);
-        wave_lds_sync();
-        if (lane < n && lane > k) {
-            const double vi = Vk[k][lane];
-            for (int c = 0; c < ns; ++c) Zs[lane * SD + c] -= cL[c] * vi;
-        }
-        wave_lds_sync();
+        // Z -= v_k (tau_k v_k^T Z); v_k is zero outside rows k + 1 .. n - 1
+        const double vi = (lane < n) ? Vk[k][lane] : 0.0;
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c) pr[c] = (c < ns) ? vi * z[c] : 0.0;
+        wave_sums16(pr, S, ns, tbuf, lane);
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c)
+            if (c < ns) z[c] -= (tk * S[c]) * vi;
     }
     // 5. Q_s in all coordinates (row r in lane r); missing pairs (fewer kept columns
     //    than s) are unit vectors of dropped coordinates with an infinite value
     for (int e = lane; e < m * SD; e += 64) Qs[e] = 0.0;
     wave_lds_sync();
     if (lane < n)
-        for (int c = 0; c < ns; ++c) Qs[keep_idx[lane] * SD + c] = Zs[lane * SD + c];
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c)
+            if (c < ns) Qs[keep_idx[lane] * SD + c] = z[c];
     if (lane == 0) {
         int c = ns;
         for (int i = 0; i < m && c < s; ++i)
@@ -1580,28 +1622,47 @@ __global__ __launch_bounds__(256) void rr_coef_kernel(int m, int s, int with_p, 
         for (int c = 0; c < s; ++c) Cfull[lane * cw + c] = Qs[lane * SD + c];
     if (lane < cw) drop_out[lane] = 0;
     if (!with_p) return;
-    // 6. C_p: b_j = e_j - Q_s Q_s[j, :]^T, two CGS passes against Q_s and C_p so far
-    //    (C_p column c in Vk[c])
+    // 6. C_p: b_j = e_j - Q_s Q_s[j, :]^T, two CGS passes against Q_s and the C_p columns
+    //    so far; row lane of Q_s in q, of C_p in cp
+    double q[RR_S_MAX], cp[RR_S_MAX], S2[RR_S_MAX];
+#pragma unroll
+    for (int c = 0; c < RR_S_MAX; ++c) {
+        q[c] = (lane < m && c < s) ? Qs[lane * SD + c] : 0.0;
+        cp[c] = 0.0;
+        S2[c] = 0.0;
+    }
     for (int j = 0; j < s; ++j) {
-        if (lane < m) bL[lane] = ((lane == j) ? 1.0 : 0.0) - dot_strided(Qs + lane * SD, 1, Qs + j * SD, 1, s);
-        wave_lds_sync();
+        double dq = 0.0;
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c)
+            if (c < s) dq = fma(q[c], Qs[j * SD + c], dq);
+        double bj = (lane < m) ? (((lane == j) ? 1.0 : 0.0) - dq) : 0.0;
         for (int pass = 0; pass < 2; ++pass) {
-            if (lane < s) cL[lane] = dot_strided(bL, 1, Qs + lane, SD, m);
-            else if (lane < s + j) cL[lane] = dot_strided(bL, 1, Vk[lane - s], 1, m);
-            wave_lds_sync();
-            if (lane < m)
-                bL[lane] -= dot_strided(cL, 1, Qs + lane * SD, 1, s) + dot_strided(cL + s, 1, &Vk[0][lane], 64, j);
-            wave_lds_sync();
+#pragma unroll
+            for (int c = 0; c < RR_S_MAX; ++c) pr[c] = (c < s) ? bj * q[c] : 0.0;
+            wave_sums16(pr, S, s, tbuf, lane);
+            if (j > 0) {
+#pragma unroll
+                for (int c = 0; c < RR_S_MAX; ++c) pr[c] = (c < j) ? bj * cp[c] : 0.0;
+                wave_sums16(pr, S2, j, tbuf, lane);
+            }
+            double upd = 0.0;
+#pragma unroll
+            for (int c = 0; c < RR_S_MAX; ++c)
+                if (c < s) upd = fma(S[c], q[c], upd);
+#pragma unroll
+            for (int c = 0; c < RR_S_MAX; ++c)
+                if (c < j) upd = fma(S2[c], cp[c], upd);
+            bj -= upd;
         }
-        if (lane == 0) cL[2 * RR_S_MAX] = sqrt(dot_strided(bL, 1, bL, 1, m));
-        wave_lds_sync();
-        const double nrm = cL[2 * RR_S_MAX];
+        const double nrm = sqrt(wave_sum_dpp(bj * bj));
         const bool keep = nrm > 1e-12;
-        const double cpj = (lane < m && keep) ? bL[lane] * (1.0 / nrm) : 0.0;
-        Vk[j][lane] = cpj;
+        const double cpj = (lane < m && keep) ? bj * (1.0 / nrm) : 0.0;
+#pragma unroll
+        for (int c = 0; c < RR_S_MAX; ++c)
+            if (c == j) cp[c] = cpj;
         if (lane == 0) drop_out[s + j] = keep ? 0 : 1;
         if (lane < m) Cfull[lane * cw + s + j] = cpj;
-        wave_lds_sync();
     }
 }
 
