@@ -351,6 +351,41 @@ def test_plate_preconditioner_wide_band(B, ctx, name, prec, threads):
     prob.close()
 
 
+@pytest.mark.parametrize("name", ["p128", "wide139"])
+def test_plate_preconditioner_wide_mfma(B, ctx, name):
+    """The blocked FP32 solver with the 192-row window (mixed precision with the solver
+    left to its rule: half-bandwidths 49..176, at most 20 lower entries per row) element by
+    element against the oracle: p128 (half-bandwidths 91-99, 512 systems) and wide139
+    (half-bandwidth 139: every trailing tile-row of the window is live)."""
+    _case(f"plate preconditioner {name} mixed, 192-row blocked window")
+    if name in WIDE:
+        cfg = dict(WIDE[name])
+        pl = w.bfs_plate(cfg["N"], "clamped", cfg["coarse"], cfg["L"])
+    else:
+        pl, cfg = w.config_plate(name)
+    s = cfg["k"] + cfg["guard"]
+    prob = _problem(B, ctx, pl, cfg, B.PREC_MIXED, autotune=False)
+    nl, bw = prob.local_sizes()
+    print(f"  local sizes {nl.min()}-{nl.max()}, half-bandwidths {bw.min()}-{bw.max()}", flush=True)
+    assert 49 <= bw.min() and bw.max() <= 176
+    prob.setup()
+    dd = _oracle_dd(pl, cfg)
+    cs = o.coarse_setup(pl.K, pl.M, dd.P)
+    ls = o.local_setup(pl.K, pl.M, dd.subs)
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((pl.n, s))
+    lam = cs.lamH[:s] * (1.0 - 0.05 * rng.random(s))
+    Zg = prob.apply_preconditioner(X, lam)
+    F = (pl.M @ X) * lam - pl.K @ X
+    Zo = o.precondition(F, lam, cs, ls, s)
+    err = _rel_err_by_kind(Zg, Zo, pl.kind)
+    tol, kap = _fp32_bound_sparse(name + " mfma", ls, lam.max())
+    print(f"  scaled local condition {kap:.3e}", flush=True)
+    print(f"  max rel err per kind {err:.3e} (bound {tol:.1e})", flush=True)
+    assert err < tol
+    prob.close()
+
+
 def test_plate_p128_fp64_iteration_count(B, ctx):
     """p128 (64,516 dofs, half-bandwidths 91-99) in FP64: the count equals the oracle's
     within one (same subspace choice and stop rule)."""
