@@ -1113,18 +1113,19 @@ __host__ __device__ constexpr int wide_ring_base(int d) { return WIDE_NT * d - d
 __host__ __device__ constexpr int wide_ring_size(int d) { return WIDE_NT - d; }
 
 template <int MODE>
-__global__ __launch_bounds__(128) void local_band_wide_kernel(
+__global__ __launch_bounds__(256) void local_band_wide_kernel(
     int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
     const double2* __restrict__ sv,
     const double* __restrict__ lam, const float* __restrict__ Floc, long long ldF, float* __restrict__ zloc,
     float* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
     int* __restrict__ negflag) {
-    // Two wavefronts per system.  Wave 0 holds window rows 0..127 (row sets 0 and 1),
-    // wave 1 rows 128..191 (set 2) and brings in the entering tile-rows while wave 0
-    // eliminates rows 0..63; the trailing tile-rows are split between the waves
-    // (33 tiles each); the backward sweep runs on wave 0.  Barriers are LDS-only
-    // except one full barrier after the forward sweep (the factor columns wave 1 stored
-    // are read back by wave 0).
+    // Four wavefronts per system, one per SIMD.  Wave w < 3 holds window rows 64 w ..
+    // 64 w + 63 (row set w); wave 3 brings in the entering tile-rows.  Wave 0 eliminates
+    // the pivot block (and its rows 16..63) while wave 3 places the next tile-row; waves 1
+    // and 2 then apply the recorded steps to rows 64..191.  The trailing tile-rows are
+    // split over the four waves (16-17 tiles each at a full band); the backward sweep
+    // runs on wave 0.  Barriers are LDS-only except one full barrier after the forward
+    // sweep (the factor columns waves 1 and 2 stored are read back by wave 0).
     using T = float;
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
@@ -1228,29 +1229,22 @@ __global__ __launch_bounds__(128) void local_band_wide_kernel(
         }
     };
 
-    // the first window: wave 0 clears the tiles, wave 1 brings in rows 0..191
-    if (wv == 0) {
+    // the first window: wave w clears and fills tile-rows 3 w .. 3 w + 2 (a tile-row's
+    // entries all lie in its own tiles)
 #pragma unroll
-        for (int I = 0; I < NT; ++I) zero_row_tiles(0, I);
+    for (int u = 0; u < 3; ++u) {
+        const int I = 3 * wv + u;
+        zero_row_tiles(0, I);
+        fetch(16 * I);
+        wave_sync();
+        place(0, I, 16 * I);
     }
-    lds_barrier();
-    if (wv == 1) {
-#pragma unroll
-        for (int I = 0; I < NT; ++I) {
-            fetch(16 * I);
-            place(0, I, 16 * I);
-        }
-    }
-    // right-hand sides: wave 0 rows 0..127 (ya, yb), wave 1 rows 128..191 (ya)
-    T ya, yb = T(0);
-    {
-        const int r0 = wv == 0 ? lane : 128 + lane;
+    // right-hand sides: wave w < 3 holds rows 64 w .. 64 w + 63
+    T ya = T(0);
+    if (wv < 3) {
+        const int r0 = 64 * wv + lane;
         const T fa = f[min(r0, nl - 1)];                    // unconditional, clamped, then selected
         ya = (r0 < nl) ? fa : T(0);
-        if (wv == 0) {
-            const T fb = f[min(64 + lane, nl - 1)];
-            yb = (64 + lane < nl) ? fb : T(0);
-        }
     }
     lds_barrier();
     int bad = 0, neg = 0;
@@ -1259,18 +1253,11 @@ __global__ __launch_bounds__(128) void local_band_wide_kernel(
         const int base = 16 * P;
         const int rnew = base + 16 + 128 + lane;           // set 2 row after the slide (lanes 48..63)
         T fraw = T(0);
-        if (wv == 1) {
-            fetch(base + R);                               // the tile-row entering after this panel
-            fraw = f[min(rnew, nl - 1)];
-        }
-        // panel rows: row 64 k + lane is row lr of tile (4 k + lg, 0)
-        T a0[16], a1[16];
-        if (wv == 0) {
-            read_row(P, lg, a0);
-            read_row(P, 4 + lg, a1);
-        } else {
-            read_row(P, 8 + lg, a0);
-        }
+        if (wv == 3) fetch(base + R);                      // the tile-row entering after this panel
+        if (wv == 2) fraw = f[min(rnew, nl - 1)];
+        // panel rows: row 64 w + lane is row lr of tile (4 w + lg, 0)
+        T a0[16];
+        if (wv < 3) read_row(P, 4 * wv + lg, a0);
         lds_barrier();                                     // the panel tiles are free
         if (wv == 0) {
             // rows 0..63: elimination with lane broadcasts; step c's column (rows c..15),
@@ -1295,31 +1282,24 @@ __global__ __launch_bounds__(128) void local_band_wide_kernel(
                 if (lane > c) ya -= lt * yc;
                 a0[c] = (lane == c) ? dc : lt;
             }
-        } else if (P + 1 < npan) {
+        } else if (wv == 3 && P + 1 < npan) {
             // the next tile-row takes the panel tiles' slots
             zero_row_tiles(P + 1, NT - 1);
             wave_sync();
             place(P + 1, NT - 1, base + R);
         }
         lds_barrier();
-        // rows 64..127 (wave 0) and 128..191 (wave 1) lie below the panel
-        if (wv == 0) eliminate_below(a1, yb);
-        else eliminate_below(a0, ya);
+        // rows 64..127 (wave 1) and 128..191 (wave 2) lie below the panel
+        if (wv == 1 || wv == 2) eliminate_below(a0, ya);
         // the factored panel's full columns (window rows 0..191) for the backward sweep,
         // and its rows, row-major, as MFMA operands
-        {
-            T* Lb = Lp + (long long)P * (16 * R) + lane + (wv == 0 ? 0 : 128);
+        if (wv < 3) {
+            T* Lb = Lp + (long long)P * (16 * R) + lane + 64 * wv;
 #pragma unroll
             for (int c = 0; c < 16; ++c) Lb[c * R] = a0[c];
-            T (*prow)[QS] = pan + (wv == 0 ? 0 : 128) + lane;
+            T (*prow)[QS] = pan + 64 * wv + lane;
 #pragma unroll
             for (int c = 0; c < 16; ++c) prow[0][c] = a0[c];
-            if (wv == 0) {
-#pragma unroll
-                for (int c = 0; c < 16; ++c) Lb[c * R + 64] = a1[c];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) prow[64][c] = a1[c];
-            }
         }
         lds_barrier();
         if (wv == 0) {
@@ -1335,7 +1315,8 @@ __global__ __launch_bounds__(128) void local_band_wide_kernel(
             z[base + zr] = zv;
         }
         // trailing update of tiles (I, J), 1 <= J <= I: -= L_I D L_J^T; tile-rows
-        // {1, 2, 5, 6, 9, 10} on wave 0 and {3, 4, 7, 8, 11} on wave 1 (33 tiles each).
+        // {1, 5, 11} on wave 0, {6, 10} on wave 1, {7, 9} on wave 2 and {2, 3, 4, 8} on
+        // wave 3 (16-17 tiles each).
         // Per tile-row: its tiles are read together, their MFMAs interleaved, then written
         // back to their ring slots (the next panel's tiles (I - 1, J - 1)).
         T dcol[4];
@@ -1350,7 +1331,8 @@ __global__ __launch_bounds__(128) void local_band_wide_kernel(
         }
 #pragma clang loop unroll(full)
         for (int I = 1; I < NT; ++I) {
-            const int owner = ((I - 1) >> 1) & 1;          // 1,2 -> 0; 3,4 -> 1; 5,6 -> 0; ...
+            constexpr long long kOwner = 0x0123'2103'3300LL;   // nibble I: the wave of tile-row I
+            const int owner = (int)((kOwner >> (4 * I)) & 15);
             if (I <= imax && wv == owner) {                // uniform per wave
                 T aop[4];
 #pragma clang loop unroll(full)
@@ -1367,22 +1349,13 @@ __global__ __launch_bounds__(128) void local_band_wide_kernel(
             }
         }
         // shift the right-hand side by 16 window rows; fresh rows enter at the bottom
-        if (wv == 0) {
-            vec[lane] = ya;
-            vec[64 + lane] = yb;
-        } else {
-            vec[128 + lane] = ya;
-        }
+        if (wv < 3) vec[64 * wv + lane] = ya;
         lds_barrier();
-        if (wv == 0) {
-            ya = vec[lane + 16];
-            yb = vec[80 + lane];
-        } else {
-            ya = (lane < 48) ? vec[min(144 + lane, R - 1)] : ((rnew < nl) ? fraw : T(0));
-        }
+        if (wv < 2) ya = vec[64 * wv + 16 + lane];
+        else if (wv == 2) ya = (lane < 48) ? vec[144 + lane] : ((rnew < nl) ? fraw : T(0));
         lds_barrier();                                     // tiles and vec complete for the next panel
     }
-    __syncthreads();                                       // wave 1's factor columns are in memory
+    __syncthreads();                                       // waves 1 and 2's factor columns are in memory
     if (wv != 0) return;
 
     // backward sweep with L^T (wave 0), panel by panel from the end; zw holds z of the
@@ -1476,7 +1449,7 @@ static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s,
     } else if (nt == WIDE_NT) {
         if constexpr (sizeof(T) == 4) {
             auto wide = [&](auto kernel) {
-                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(128), 0, st, s, E, subptr, bw, sd, sv, lam, Floc,
+                hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(256), 0, st, s, E, subptr, bw, sd, sv, lam, Floc,
                                    sumN, zloc, Lwork, Loff, status, negflag);
             };
             if (mode == 0) wide(local_band_wide_kernel<0>);
