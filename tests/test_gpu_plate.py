@@ -386,6 +386,76 @@ def test_plate_preconditioner_wide_mfma(B, ctx, name):
     prob.close()
 
 
+def _lowest_local(Kl, Ml):
+    import scipy.sparse.linalg as spla
+    if Kl.shape[0] <= 800:
+        return sla.eigh(Kl.toarray(), Ml.toarray(), eigvals_only=True, subset_by_index=[0, 0])[0]
+    return float(np.min(spla.eigsh(Kl.tocsc(), k=1, M=Ml.tocsc(), sigma=0.0, which="LM", return_eigenvectors=False)))
+
+
+def _scaled_condition(A):
+    """Condition number of the diagonally scaled SPD matrix A (dense below 800 rows)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    d = 1.0 / np.sqrt(A.diagonal())
+    if A.shape[0] <= 800:
+        ev = np.linalg.eigvalsh(A.toarray() * d[:, None] * d[None, :])
+        return ev[-1] / ev[0]
+    D = sp.diags(d)
+    S = (D @ A @ D).tocsc()
+    top = spla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+    bot = spla.eigsh(S, k=1, sigma=0.0, which="LM", return_eigenvectors=False, tol=1e-6)[0]
+    return top / bot
+
+
+@pytest.mark.parametrize("name", ["b32", "wide139"])
+def test_plate_preconditioner_indefinite_wide_mfma(B, ctx, name):
+    """Shifts above some subdomains' lowest local eigenvalue on the 192-row blocked FP32
+    solver: its second launch redoes the systems found indefinite with shift 0 (reading
+    R13), element by element against the oracle."""
+    _case(f"plate preconditioner indefinite {name} mixed, 192-row blocked window")
+    if name in WIDE:
+        cfg = dict(WIDE[name])
+        pl = w.bfs_plate(cfg["N"], "clamped", cfg["coarse"], cfg["L"])
+    else:
+        pl, cfg = w.config_plate(name)
+    s = cfg["k"] + cfg["guard"]
+    prob = _problem(B, ctx, pl, cfg, B.PREC_MIXED, autotune=False)
+    nl, bw = prob.local_sizes()
+    assert 49 <= bw.max() <= 176
+    prob.setup()
+    dd = _oracle_dd(pl, cfg)
+    cs = o.coarse_setup(pl.K, pl.M, dd.P)
+    ls = o.local_setup(pl.K, pl.M, dd.subs)
+    mus = np.array([_lowest_local(Kl, Ml) for Kl, Ml in zip(ls.K_loc, ls.M_loc)])
+    # shifts over [0.5, 2.5] x the smallest local minimum, each at least 5 % away from
+    # every local minimum and every coarse eigenvalue (the definiteness decision is the
+    # same in FP32, FP64 and exact arithmetic)
+    lam = np.linspace(0.5, 2.5, s) * mus.min()
+    avoid = np.concatenate([mus, cs.lamH])
+    for q in range(s):
+        while np.min(np.abs(lam[q] / avoid - 1.0)) < 0.05:
+            lam[q] *= 1.013
+    n_indef = sum(int(np.sum(lam[q] > mus)) for q in range(s))
+    assert n_indef > 0
+    X = np.random.default_rng(12).standard_normal((pl.n, s))
+    Zg = prob.apply_preconditioner(X, lam)
+    F = (pl.M @ X) * lam - pl.K @ X
+    Zo = o.precondition(F, lam, cs, ls, s)
+    err = _rel_err_by_kind(Zg, Zo, pl.kind)
+    # the FP32 bound over the matrices actually factored: K_l - lambda_i M_l, or K_l itself
+    kap = 0.0
+    for l, (Kl, Ml) in enumerate(zip(ls.K_loc, ls.M_loc)):
+        shifts = sorted({0.0 if lam[q] > mus[l] else float(lam[q]) for q in range(s)})
+        for sh in shifts:
+            kap = max(kap, _scaled_condition((Kl - sh * Ml).tocsr()))
+    tol = 4.0 * 2.0 ** -24 * kap
+    print(f"  indefinite local systems {n_indef} of {len(mus) * s}, scaled local condition {kap:.3e}", flush=True)
+    print(f"  max rel err per kind {err:.3e} (bound {tol:.1e})", flush=True)
+    assert err < tol
+    prob.close()
+
+
 def test_plate_p128_fp64_iteration_count(B, ctx):
     """p128 (64,516 dofs, half-bandwidths 91-99) in FP64: the count equals the oracle's
     within one (same subspace choice and stop rule)."""
