@@ -235,8 +235,8 @@ static void dev_free(bpjd_problem* p, const DevBlock& b) {
 
 struct HostCSR {
     int n = 0;
-    std::vector<int> ptr, col;
-    std::vector<double> val;
+    fillvec<int> ptr, col;      // every element written by the copy in read_csr
+    fillvec<double> val;
 };
 
 static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out, hipStream_t st) {
@@ -258,12 +258,24 @@ static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out, hipStream
     out.col.resize(A->nnz);
     out.val.resize(A->nnz);
     if (A->mem == BPJD_MEM_DEVICE) {
+        // touch the fresh pages on every planning thread first, so that the copy does not
+        // take their first-use faults one by one
+        parallel_chunks(A->nnz, [&](long long lo, long long hi, int) {
+            for (long long q = lo; q < hi; q += 512) {
+                out.col[q] = 0;
+                out.val[q] = 0.0;
+            }
+        });
         BPJD_HIP(hipMemcpyAsync(out.col.data(), A->col, sizeof(int) * A->nnz, hipMemcpyDeviceToHost, st));
         BPJD_HIP(hipMemcpyAsync(out.val.data(), A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost, st));
         BPJD_HIP(hipStreamSynchronize(st));
     } else {
-        std::memcpy(out.col.data(), A->col, sizeof(int) * A->nnz);
-        std::memcpy(out.val.data(), A->val, sizeof(double) * A->nnz);
+        const int* cs = A->col;
+        const double* vs = A->val;
+        parallel_chunks(A->nnz, [&](long long lo, long long hi, int) {
+            std::memcpy(out.col.data() + lo, cs + lo, sizeof(int) * (hi - lo));
+            std::memcpy(out.val.data() + lo, vs + lo, sizeof(double) * (hi - lo));
+        });
     }
     FirstBad bad;
     parallel_chunks(n, [&](long long lo, long long hi, int t) {
@@ -289,8 +301,9 @@ static int read_csr(const bpjd_csr* A, const char* name, HostCSR& out, hipStream
 // Union pattern of K and M with the position maps of both inputs.
 struct Pattern {
     int n = 0;
-    std::vector<int> ptr, col;
-    std::vector<long long> Kmap, Mmap;
+    std::vector<int> ptr;
+    fillvec<int> col;                 // every element written by build_union
+    fillvec<long long> Kmap, Mmap;
 };
 
 // Row i of the union pattern: merge of the sorted columns of K and M; with emit, the
@@ -537,10 +550,11 @@ static int alloc_dev(bpjd_problem* p, T** dst, size_t count) {
 
 // Host-side result of planning a problem: every array the device copy needs.
 struct HostPlan {
-    std::vector<int> rowptr, col;
+    std::vector<int> rowptr;
+    fillvec<int> col;
     std::vector<double2> km;
-    std::vector<int> Pptr, Pcol;
-    std::vector<double> Pval;
+    fillvec<int> Pptr, Pcol;
+    fillvec<double> Pval;
     std::vector<int> PTptr, PTcol;
     std::vector<double> PTval;
     std::vector<int> kpptr, kpcol, khptr, khcol;

@@ -223,6 +223,29 @@ struct bpjd_ctx {
     std::string last_error;            // message of the last failed ABI call on this context
 };
 
+// Host arrays that are filled right after they are sized: resize leaves their elements
+// uninitialised (no zero pass over tens of megabytes before the copy that overwrites it).
+template <typename T>
+struct DefaultInitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = DefaultInitAlloc<U>;
+    };
+    DefaultInitAlloc() = default;
+    template <typename U>
+    DefaultInitAlloc(const DefaultInitAlloc<U>&) noexcept {}
+    template <typename U>
+    void construct(U* q) noexcept {
+        ::new (static_cast<void*>(q)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U* q, Args&&... args) {
+        ::new (static_cast<void*>(q)) U(std::forward<Args>(args)...);
+    }
+};
+template <typename T>
+using fillvec = std::vector<T, DefaultInitAlloc<T>>;
+
 struct bpjd_problem {
     bpjd_ctx* ctx = nullptr;
     bpjd_opts opts{};
@@ -231,7 +254,7 @@ struct bpjd_problem {
     long long sumN = 0;                // sum of subdomain sizes
     int maxN = 0, maxBW = 0, maxC = 0;
     long long nnzK = 0, nnzM = 0;
-    std::vector<long long> Kmap, Mmap; // original nnz position -> union position
+    fillvec<long long> Kmap, Mmap;     // original nnz position -> union position
     std::vector<double> X_init;        // n x s (host copy), optional
     int n_init = 0;
 
