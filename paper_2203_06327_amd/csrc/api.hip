@@ -552,7 +552,7 @@ static int alloc_dev(bpjd_problem* p, T** dst, size_t count) {
 struct HostPlan {
     std::vector<int> rowptr;
     fillvec<int> col;
-    std::vector<double2> km;
+    fillvec<double2> km;        // every element written when the plan is made
     fillvec<int> Pptr, Pcol;
     fillvec<double> Pval;
     std::vector<int> PTptr, PTcol;
