@@ -282,6 +282,33 @@ def test_solve_largest_block(B, ctx):
     assert np.max(np.abs(G - np.eye(req["k"]))) < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_preconditioner_c3_full_size_sampled(B, ctx, prec):
+    """The two-level preconditioner at full size on the 1,056,759-dof rectangle (13,312
+    local systems in one launch, as the benchmark runs them) against the oracle's values at
+    256 sampled rows, stored with their inputs by tests/golden/make_c3_precond_sample.py."""
+    import os
+    _case(f"preconditioner c3 full size, sampled rows, {prec}")
+    mesh, cfg = w.config_mesh("c3")
+    s = cfg["k"] + cfg["guard"]
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_precond_sample.txt")
+    lines = [line.split() for line in open(path) if not line.startswith("#")]
+    assert lines[0][0] == "lam"
+    lam = np.array([float(v) for v in lines[0][1:]])
+    rows = np.array([int(t[0]) for t in lines[1:]])
+    Zo = np.array([[float(v) for v in t[1:]] for t in lines[1:]])
+    assert lam.shape == (s,) and Zo.shape == (len(rows), s)
+    precision = B.PREC_FP64 if prec == "fp64" else B.PREC_MIXED
+    prob = B.problem_from_mesh(ctx, mesh, cfg["L"], k=cfg["k"], guard=cfg["guard"], precision=precision)
+    prob.setup()
+    X = np.random.default_rng(2203).standard_normal((mesh.n, s))
+    Zg = prob.apply_preconditioner(X, lam)
+    err = np.abs(Zg[rows] - Zo).max() / np.abs(Zo).max()
+    print(f"  {len(rows)} rows, max rel err {err:.3e}", flush=True)
+    assert err < (1e-12 if prec == "fp64" else _fp32_tolerance(prob))
+    prob.close()
+
+
 def test_solve_c3_full_size(B, ctx):
     """The 1,056,759-dof rectangle (32 x 32 subdomains, uneven last row, k = 12 with one
     guard vector) with FP32 local solves: eigenvalues against the stored oracle
