@@ -206,6 +206,37 @@ def test_plate_c4_full_size(B, ctx):
     np.testing.assert_allclose(X.T @ (pl.M @ X), np.eye(k), atol=1e-10)
 
 
+def test_plate_c4_preconditioner_sampled(B, ctx):
+    """The preconditioner at full C4 size (512 systems of up to 6,084 rows, half-bandwidth
+    163, on the 192-row blocked solver as the benchmark runs it) against the oracle's values
+    at 32 sampled rows, per dof kind, within 4 u kappa; values, inputs and kappa stored by
+    tests/golden/make_c4_precond_sample.py."""
+    _case("plate c4 preconditioner, sampled rows, mixed")
+    pl, cfg = w.config_plate("c4")
+    s = cfg["k"] + cfg["guard"]
+    lines = [line.split() for line in open(os.path.join(GOLDEN_DIR, "c4_precond_sample.txt"))
+             if not line.startswith("#")]
+    assert lines[0][0] == "lam" and lines[1][0] == "kappa"
+    lam = np.array([float(v) for v in lines[0][1:]])
+    kap = float(lines[1][1])
+    rows = np.array([int(t[0]) for t in lines[2:]])
+    Zo = np.array([[float(v) for v in t[1:]] for t in lines[2:]])
+    assert lam.shape == (s,) and Zo.shape == (len(rows), s)
+    prob = _problem(B, ctx, pl, cfg, B.PREC_MIXED)
+    _, bw = prob.local_sizes()
+    assert 49 <= bw.max() <= 176
+    prob.setup()
+    X = np.random.default_rng(2204).standard_normal((pl.n, s))
+    Zg = prob.apply_preconditioner(X, lam)[rows]
+    kind = pl.kind[rows]
+    kinds = tuple(q for q in range(4) if np.any(kind == q))
+    err = _rel_err_by_kind(Zg, Zo, kind, kinds)
+    tol = 4.0 * 2.0 ** -24 * kap
+    print(f"  {len(rows)} rows, max rel err per kind {err:.3e} (bound {tol:.1e})", flush=True)
+    assert err < tol
+    prob.close()
+
+
 def test_plate_c4_fp64_window_does_not_fit(B, ctx):
     """With FP64 local solves the band-163 window (164^2 doubles) exceeds the LDS of a
     workgroup: the library says so when the problem is created, before any launch."""
