@@ -1088,20 +1088,20 @@ void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr
 
 // Local solves, blocked, wide bands (FP32): the blocked LDL^T above with a window of
 // 192 rows (12 tile-rows, half-bandwidths up to 176) and up to 20 lower entries per row
-// (fourth-order and three-dimensional elements).  One wavefront per (subdomain, shift).
-// The 78 lower tiles of the window live in LDS (16 x 16 FP32 in accumulator order:
+// (fourth-order and three-dimensional elements).  One workgroup of four wavefronts per
+// (subdomain, shift).  The 78 lower tiles of the window live in LDS (16 x 16 FP32 in accumulator order:
 // element (r, c) at 4 (16 (r / 4) + c) + r % 4, so that lane l's four accumulator values,
 // rows 4 (l / 16) + 0..3 of column l % 16, are the 16 bytes at 16 l), one ring per tile
 // diagonal d = I - J: the tiles of diagonal d
 // belong to absolute tile-rows TR = P + d .. P + 11 and take slot TR mod (12 - d) of the
 // ring, so when the window slides the retiring panel tile of each ring frees exactly the
 // slot its entering tile needs (TR = P + 12 = P + d mod 12 - d) and nothing moves.  Per
-// panel: the panel tiles are read to one row per lane (three row sets: rows lane,
-// 64 + lane, 128 + lane) and factored with lane broadcasts (one pivot row serves the
-// three sets); the next tile-row is scattered into the freed slots; the factored panel
-// goes to HBM (full 192-row columns) and, row-major, to LDS as MFMA operands; each of
-// the 66 trailing tiles is read, takes -L_I D L_J^T with four 16x16x4 MFMAs and is
-// written back.  The right-hand side shifts through LDS; the backward sweep sums the
+// panel: the panel tiles are read to one row per lane (three row sets, rows 64 w + lane
+// on wave w < 3) and factored with lane broadcasts (wave 0 records each step of the pivot
+// block for the two other sets); wave 3 scatters the next tile-row into the freed slots;
+// the factored panel goes to HBM (full 192-row columns) and, row-major, to LDS as MFMA
+// operands; each of the 66 trailing tiles is read, takes -L_I D L_J^T with four 16x16x4
+// MFMAs and is written back.  The right-hand side shifts through LDS; the backward sweep sums the
 // contributions of the 176 rows below each panel through a column-major LDS copy.
 constexpr int WIDE_NT = 12;                 // tile-rows of the window
 constexpr int WIDE_R = 16 * WIDE_NT;        // window rows (192)
