@@ -539,12 +539,35 @@ __device__ void tridiag_head(int n, int k, const double* __restrict__ A, double*
         const int kp = k - 1;
         const double tp = tau[kp];
         const double* vp = Vh + (long long)kp * n;
+        // this thread's rows (at most four: n <= 1024, at least 256 threads): p, v and row
+        // k of A are loaded together up front, not once per phase
+        constexpr int MAXI = 4;
+        double pv[MAXI], vv[MAXI], av[MAXI], wv[MAXI];
+#pragma unroll
+        for (int j = 0; j < MAXI; ++j) {
+            const int i = min(k + t + j * bd, n - 1);
+            pv[j] = pbuf[i];
+            vv[j] = vp[i];
+            av[j] = A[(long long)k * n + i];
+        }
         double acc = 0.0;
-        for (int i = k + t; i < n; i += bd) acc = fma(tp * pbuf[i], vp[i], acc);
+#pragma unroll
+        for (int j = 0; j < MAXI; ++j)
+            if (k + t + j * bd < n) acc = fma(tp * pv[j], vv[j], acc);
         const double half_tpv = 0.5 * tp * block_sum_fast(acc, wred);
-        for (int i = k + t; i < n; i += bd) wbuf[i] = tp * pbuf[i] - half_tpv * vp[i];
+#pragma unroll
+        for (int j = 0; j < MAXI; ++j) {
+            const int i = k + t + j * bd;
+            wv[j] = tp * pv[j] - half_tpv * vv[j];
+            if (i < n) wbuf[i] = wv[j];
+        }
         __syncthreads();
-        for (int i = k + t; i < n; i += bd) r[i] = A[(long long)k * n + i] - (vp[k] * wbuf[i] + wbuf[k] * vp[i]);
+        const double vk = vp[k], wk = wbuf[k];
+#pragma unroll
+        for (int j = 0; j < MAXI; ++j) {
+            const int i = k + t + j * bd;
+            if (i < n) r[i] = av[j] - (vk * wv[j] + wk * vv[j]);
+        }
     } else {
         for (int i = t; i < n; i += bd) r[i] = A[i];
     }
