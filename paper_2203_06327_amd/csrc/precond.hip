@@ -823,15 +823,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T,
 #pragma unroll
             for (int c = 0; c < 16; ++c) a2[c] = panT[c][min(64 + lane, R - 1)];
         }
+        // column c: the broadcasts of row c are all issued before the updates that use
+        // them (a scheduling barrier keeps them apart), so each lands in an SGPR of its own
+        // and no update waits out the SGPR-write hazard of the broadcast just before it
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const T u = a[c];
             const T dc = MT::bcast(u, c);
             const T rc = MT::recip(dc);
+            T bc[16];
+#pragma unroll
+            for (int c2 = c + 1; c2 < 16; ++c2) bc[c2] = MT::bcast(u, c2);
+            const T yc = MT::bcast(y, c);
+            __builtin_amdgcn_sched_barrier(0);
             const T lt = u * rc;
 #pragma unroll
-            for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * MT::bcast(u, c2);
-            const T yc = MT::bcast(y, c);
+            for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= lt * bc[c2];
             if (lane > c) y -= lt * yc;
             a[c] = (lane == c) ? dc : lt;
             if constexpr (TWO) {       // rows 64.. lie below the panel: plain elimination
@@ -1033,16 +1040,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T,
             acc = quad_sum(acc);
             if (qq == 0) CSUM(c) = acc;
         }
+        // multipliers L(r, lane) of the rows r above which this lane's row lies, zero
+        // elsewhere (selected here, off the dependent chain of the solve below)
         T lt[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) lt[r] = bt[lr][r];
+        for (int r = 0; r < 16; ++r) {
+            const T v = bt[lr][r];
+            lt[r] = (lane < r) ? v : T(0);
+        }
         wave_sync();
         // unit upper triangular solve with the panel's 16 x 16 block, one row per step
+        // (a lane at or below row r subtracts 0 * z_r, which leaves its value unchanged)
         T val = zc0 - CSUM(lr);
 #pragma unroll
         for (int r = 15; r > 0; --r) {
             const T zr = MT::bcast(val, r);
-            if (lane < r) val -= lt[r] * zr;
+            val -= lt[r] * zr;
         }
         if (lane < 16) zw = val;
         if constexpr (sizeof(T) == 4) {
