@@ -859,10 +859,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T,
         // (BWS == R); FP64: full columns or the masked band part
         if constexpr (sizeof(T) == 4 && !TWO) {
             T* Lb = Lp + (long long)P * (16 * BWS);
+            // the 16 shuffles are all issued before the first store (one LDS wait, not 16)
+            T sv[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) sv[c] = __shfl(a[c], min(max(lane, c), c + BWS - 1), 64);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 const int lc = min(max(lane, c), c + BWS - 1);
-                Lb[c * BWS + (lc - c)] = __shfl(a[c], lc, 64);
+                Lb[c * BWS + (lc - c)] = sv[c];
             }
         } else if (sizeof(T) == 4 || BWS >= R) {
 #pragma unroll
@@ -938,6 +943,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T,
                 aop[I][k] = -lv * dcol[k];
             }
         }
+        __builtin_amdgcn_sched_barrier(0);      // every operand read is issued before the first MFMA
 #pragma unroll
         for (int I = 1; I < NT; ++I)
 #pragma unroll
