@@ -1014,21 +1014,145 @@ __device__ inline double wave_sum_d(double v) {
 
 // Eigenvectors of clustered eigenvalues (consecutive gaps below 1e-3 |T|) from
 // inverse iteration span the cluster's invariant subspace but are not individually
-// accurate.  One wavefront per run of clustered eigenvalues (runs are found from the
-// unrefined values w_in, split into chunks of at most 32): two Gram-Schmidt passes,
-// then a Rayleigh-Ritz step on the chunk (Jacobi on X_c^T T X_c) that rotates the
-// basis into eigenvectors and refines the eigenvalues (written to w).  Xn: n x n
-// scratch; rows start .. start + cs - 1 of it hold the chunk's columns of X
-// contiguously (one strided read and one strided write of X per chunk; every pass
-// in between reads contiguous vectors).
-__global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const double* __restrict__ dg,
-                                                              const double* __restrict__ eg,
-                                                              const double* __restrict__ w_in, double* __restrict__ w,
-                                                              double* __restrict__ X, double* __restrict__ Xn) {
-    __shared__ double Tc_all[4][32 * 33];
-    __shared__ double Qc_all[4][32 * 33];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = blockIdx.x * 4 + wave;
+// accurate.  One wavefront (one workgroup) per run of clustered eigenvalues (runs are
+// found from the unrefined values w_in, split into chunks of at most 32): two
+// Gram-Schmidt passes, then a Rayleigh-Ritz step on the chunk (Jacobi on X_c^T T X_c)
+// that rotates the basis into eigenvectors and refines the eigenvalues (written to w).
+// The chunk's columns are held contiguously (one strided read and one strided write of
+// X per chunk; every pass in between reads contiguous vectors): in LDS for chunks of up
+// to CLUSTER_LDS_COLS columns, so the chains of dependent dot products wait on LDS
+// rather than on memory; wider chunks use rows start .. start + cs - 1 of the n x n
+// scratch Xn.  Both forms do the same operations in the same order.
+constexpr int CLUSTER_LDS_COLS = 16;
+
+__device__ __forceinline__ void cluster_chunk(int n, int start, int cs, double* xc0, const double* __restrict__ dg,
+                                              const double* __restrict__ eg, double* __restrict__ w,
+                                              double* __restrict__ X, double* Tc, double* Qc, int lane) {
+    // the chunk's columns, contiguous: xc(q) = column start + q of X
+    auto xc = [&](const int q) { return xc0 + (long long)q * n; };
+    for (int i = lane; i < n; i += 64)
+        for (int q = 0; q < cs; ++q) xc(q)[i] = X[(long long)i * n + start + q];
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // two Gram-Schmidt passes over the chunk's columns
+    for (int c = 0; c < cs; ++c) {
+        double* vc = xc(c);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < c; ++q) {
+                const double* vq = xc(q);
+                double acc = 0.0;
+                for (int i = lane; i < n; i += 64) acc = fma(vq[i], vc[i], acc);
+                const double cq = wave_sum_d(acc);
+                for (int i = lane; i < n; i += 64) vc[i] -= cq * vq[i];
+            }
+        double acc = 0.0;
+        for (int i = lane; i < n; i += 64) acc = fma(vc[i], vc[i], acc);
+        const double inv = 1.0 / sqrt(wave_sum_d(acc));
+        for (int i = lane; i < n; i += 64) vc[i] *= inv;
+    }
+    // the product with T reads neighbours that other lanes wrote: their stores complete first
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    // Tc = X_c^T T X_c
+    for (int pp = 0; pp < cs; ++pp)
+        for (int qq = pp; qq < cs; ++qq) {
+            const double* vp = xc(pp);
+            const double* vq = xc(qq);
+            double acc = 0.0;
+            for (int i = lane; i < n; i += 64) {
+                double tx = dg[i] * vq[i];
+                if (i > 0) tx = fma(eg[i - 1], vq[i - 1], tx);
+                if (i + 1 < n) tx = fma(eg[i], vq[i + 1], tx);
+                acc = fma(vp[i], tx, acc);
+            }
+            const double v = wave_sum_d(acc);
+            if (lane == 0) {
+                Tc[pp * 33 + qq] = v;
+                Tc[qq * 33 + pp] = v;
+            }
+        }
+    __builtin_amdgcn_wave_barrier();
+    // cyclic Jacobi on the cs x cs matrix: every lane computes the same rotation and
+    // lane k updates entry k of the two rows and columns (each rotation applies the
+    // column updates, then the row updates, as a serial sweep would)
+    for (int e2 = lane; e2 < cs * 33; e2 += 64) Qc[e2] = (e2 % 33 == e2 / 33) ? 1.0 : 0.0;
+    wave_sync_fence();
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        bool rot = false;
+        for (int pp = 0; pp < cs; ++pp)
+            for (int qq = pp + 1; qq < cs; ++qq) {
+                const double apq = Tc[pp * 33 + qq];
+                const double app = Tc[pp * 33 + pp], aqq = Tc[qq * 33 + qq];
+                if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
+                rot = true;
+                const double tau = (aqq - app) / (2.0 * apq);
+                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+                const int k = lane;
+                if (k < cs) {
+                    const double akp = Tc[k * 33 + pp], akq = Tc[k * 33 + qq];
+                    Tc[k * 33 + pp] = c * akp - sn * akq;
+                    Tc[k * 33 + qq] = sn * akp + c * akq;
+                }
+                wave_sync_fence();
+                if (k < cs) {
+                    const double apk = Tc[pp * 33 + k], aqk = Tc[qq * 33 + k];
+                    const double vkp = Qc[k * 33 + pp], vkq = Qc[k * 33 + qq];
+                    Qc[k * 33 + pp] = c * vkp - sn * vkq;
+                    Qc[k * 33 + qq] = sn * vkp + c * vkq;
+                    Tc[pp * 33 + k] = c * apk - sn * aqk;
+                    Tc[qq * 33 + k] = sn * apk + c * aqk;
+                }
+                wave_sync_fence();
+                if (lane == 0) {
+                    Tc[pp * 33 + qq] = 0.0;
+                    Tc[qq * 33 + pp] = 0.0;
+                }
+                wave_sync_fence();
+            }
+        if (!rot) break;
+    }
+    if (lane == 0) {
+        for (int pp = 0; pp < cs; ++pp) {          // selection sort of the pairs
+            int best = pp;
+            for (int qq = pp + 1; qq < cs; ++qq)
+                if (Tc[qq * 33 + qq] < Tc[best * 33 + best]) best = qq;
+            if (best != pp) {
+                const double tmp = Tc[pp * 33 + pp];
+                Tc[pp * 33 + pp] = Tc[best * 33 + best];
+                Tc[best * 33 + best] = tmp;
+                for (int k = 0; k < cs; ++k) {
+                    const double v = Qc[k * 33 + pp];
+                    Qc[k * 33 + pp] = Qc[k * 33 + best];
+                    Qc[k * 33 + best] = v;
+                }
+            }
+            w[start + pp] = Tc[pp * 33 + pp];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // X_c <- X_c Q_c, from the contiguous copy into the columns of X
+    for (int i = lane; i < n; i += 64)
+        for (int q = 0; q < cs; ++q) {
+            double v = 0.0;
+            for (int pp = 0; pp < cs; ++pp) v = fma(xc(pp)[i], Qc[pp * 33 + q], v);
+            X[(long long)i * n + start + q] = v;
+        }
+    // the next chunk of the run overwrites the LDS copy
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__global__ __launch_bounds__(64) void tridiag_cluster_kernel(int n, const double* __restrict__ dg,
+                                                             const double* __restrict__ eg,
+                                                             const double* __restrict__ w_in, double* __restrict__ w,
+                                                             double* __restrict__ X, double* __restrict__ Xn) {
+    __shared__ double xs[CLUSTER_LDS_COLS * 1024];    // n <= 1024
+    __shared__ double Tc[32 * 33];
+    __shared__ double Qc[32 * 33];
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x;
     if (j >= n) return;
     const double tn = fmax(fabs(w_in[0]), fabs(w_in[n - 1]));
     const double gap_tol = 1e-3 * tn;
@@ -1036,123 +1160,13 @@ __global__ __launch_bounds__(256) void tridiag_cluster_kernel(int n, const doubl
     int e = j + 1;
     while (e < n && w_in[e] - w_in[e - 1] <= gap_tol) ++e;
     if (e - j == 1) return;
-    double* Tc = Tc_all[wave];
-    double* Qc = Qc_all[wave];
     for (int start = j; start < e; start += 32) {
         const int cs = min(32, e - start);
         if (cs < 2) break;
-        // the chunk's columns, contiguous: xc(q) = column start + q of X
-        double* xc0 = Xn + (long long)start * n;
-        auto xc = [&](const int q) { return xc0 + (long long)q * n; };
-        for (int i = lane; i < n; i += 64)
-            for (int q = 0; q < cs; ++q) xc(q)[i] = X[(long long)i * n + start + q];
-        __builtin_amdgcn_wave_barrier();
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // two Gram-Schmidt passes over the chunk's columns
-        for (int c = 0; c < cs; ++c) {
-            double* vc = xc(c);
-            for (int pass = 0; pass < 2; ++pass)
-                for (int q = 0; q < c; ++q) {
-                    const double* vq = xc(q);
-                    double acc = 0.0;
-                    for (int i = lane; i < n; i += 64) acc = fma(vq[i], vc[i], acc);
-                    const double cq = wave_sum_d(acc);
-                    for (int i = lane; i < n; i += 64) vc[i] -= cq * vq[i];
-                }
-            double acc = 0.0;
-            for (int i = lane; i < n; i += 64) acc = fma(vc[i], vc[i], acc);
-            const double inv = 1.0 / sqrt(wave_sum_d(acc));
-            for (int i = lane; i < n; i += 64) vc[i] *= inv;
-        }
-        // the product with T reads neighbours that other lanes wrote: their stores complete first
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        // Tc = X_c^T T X_c
-        for (int pp = 0; pp < cs; ++pp)
-            for (int qq = pp; qq < cs; ++qq) {
-                const double* vp = xc(pp);
-                const double* vq = xc(qq);
-                double acc = 0.0;
-                for (int i = lane; i < n; i += 64) {
-                    double tx = dg[i] * vq[i];
-                    if (i > 0) tx = fma(eg[i - 1], vq[i - 1], tx);
-                    if (i + 1 < n) tx = fma(eg[i], vq[i + 1], tx);
-                    acc = fma(vp[i], tx, acc);
-                }
-                const double v = wave_sum_d(acc);
-                if (lane == 0) {
-                    Tc[pp * 33 + qq] = v;
-                    Tc[qq * 33 + pp] = v;
-                }
-            }
-        __builtin_amdgcn_wave_barrier();
-        // cyclic Jacobi on the cs x cs matrix: every lane computes the same rotation and
-        // lane k updates entry k of the two rows and columns (each rotation applies the
-        // column updates, then the row updates, as a serial sweep would)
-        for (int e2 = lane; e2 < cs * 33; e2 += 64) Qc[e2] = (e2 % 33 == e2 / 33) ? 1.0 : 0.0;
-        wave_sync_fence();
-        for (int sweep = 0; sweep < 50; ++sweep) {
-            bool rot = false;
-            for (int pp = 0; pp < cs; ++pp)
-                for (int qq = pp + 1; qq < cs; ++qq) {
-                    const double apq = Tc[pp * 33 + qq];
-                    const double app = Tc[pp * 33 + pp], aqq = Tc[qq * 33 + qq];
-                    if (!(fabs(apq) > 2.3e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) continue;
-                    rot = true;
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
-                    const int k = lane;
-                    if (k < cs) {
-                        const double akp = Tc[k * 33 + pp], akq = Tc[k * 33 + qq];
-                        Tc[k * 33 + pp] = c * akp - sn * akq;
-                        Tc[k * 33 + qq] = sn * akp + c * akq;
-                    }
-                    wave_sync_fence();
-                    if (k < cs) {
-                        const double apk = Tc[pp * 33 + k], aqk = Tc[qq * 33 + k];
-                        const double vkp = Qc[k * 33 + pp], vkq = Qc[k * 33 + qq];
-                        Qc[k * 33 + pp] = c * vkp - sn * vkq;
-                        Qc[k * 33 + qq] = sn * vkp + c * vkq;
-                        Tc[pp * 33 + k] = c * apk - sn * aqk;
-                        Tc[qq * 33 + k] = sn * apk + c * aqk;
-                    }
-                    wave_sync_fence();
-                    if (lane == 0) {
-                        Tc[pp * 33 + qq] = 0.0;
-                        Tc[qq * 33 + pp] = 0.0;
-                    }
-                    wave_sync_fence();
-                }
-            if (!rot) break;
-        }
-        if (lane == 0) {
-            for (int pp = 0; pp < cs; ++pp) {          // selection sort of the pairs
-                int best = pp;
-                for (int qq = pp + 1; qq < cs; ++qq)
-                    if (Tc[qq * 33 + qq] < Tc[best * 33 + best]) best = qq;
-                if (best != pp) {
-                    const double tmp = Tc[pp * 33 + pp];
-                    Tc[pp * 33 + pp] = Tc[best * 33 + best];
-                    Tc[best * 33 + best] = tmp;
-                    for (int k = 0; k < cs; ++k) {
-                        const double v = Qc[k * 33 + pp];
-                        Qc[k * 33 + pp] = Qc[k * 33 + best];
-                        Qc[k * 33 + best] = v;
-                    }
-                }
-                w[start + pp] = Tc[pp * 33 + pp];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // X_c <- X_c Q_c, from the contiguous copy into the columns of X
-        for (int i = lane; i < n; i += 64)
-            for (int q = 0; q < cs; ++q) {
-                double v = 0.0;
-                for (int pp = 0; pp < cs; ++pp) v = fma(xc(pp)[i], Qc[pp * 33 + q], v);
-                X[(long long)i * n + start + q] = v;
-            }
+        if (cs <= CLUSTER_LDS_COLS)
+            cluster_chunk(n, start, cs, xs, dg, eg, w, X, Tc, Qc, lane);
+        else
+            cluster_chunk(n, start, cs, Xn + (long long)start * n, dg, eg, w, X, Tc, Qc, lane);
     }
 }
 
@@ -1244,8 +1258,7 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
     hipLaunchKernelGGL(tridiag_invit_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, n, diag, off, w0, V, scratch,
                        scratch + n2, scratch + 2 * n2, scratch + 3 * n2, scratch + 4 * n2, scratch + 5 * n2);
     (void)hipMemcpyAsync(w, w0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
-    hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st, n, diag, off, w0, w, V,
-                       scratch);
+    hipLaunchKernelGGL(tridiag_cluster_kernel, dim3(n), dim3(64), 0, st, n, diag, off, w0, w, V, scratch);
     if (n <= 256)
         hipLaunchKernelGGL((tridiag_back_kernel<4, 8>), dim3(grid_for(n, 4)), dim3(256), 0, st, n, work, tau, V);
     else if (n <= 512)
