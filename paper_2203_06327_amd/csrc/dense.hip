@@ -661,7 +661,10 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double*
                     const int i = i0 + 64 * u;
                     if (i < n) {
                         const double a = rv[u] - (vj * wv[u] + wj * pv[u]);
-                        row[i] = a;
+                        // written through to the device coherence point at once, so the
+                        // fence before the completion count finds no dirty lines to
+                        // write back (it would write back this compute unit's whole L2)
+                        __hip_atomic_store(row + i, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         acc = fma(a, kv[u], acc);
                     }
                 }
@@ -682,17 +685,18 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double*
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0) pbuf[j] = acc;
+        if (lane == 0) __hip_atomic_store(pbuf + j, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        // release only: the rows and p of this workgroup are complete before it is counted
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned int prev = atomicAdd(counter, 1u);
         last = (prev == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the last one sees every workgroup's rows and p
     if (threadIdx.x == 0) *counter = 0u;
     tridiag_head(n, k + 1, A, Vh, tau, pbuf, wbuf, diag, off, r, wred);
 }
