@@ -521,13 +521,13 @@ __global__ __launch_bounds__(512) void tridiag_kernel(int n, double* __restrict_
 // Householder reduction of the symmetric A (n x n) to tridiagonal form T = Q^T A Q,
 // one reflector H_k = I - tau_k v v^T (v_0 = 1) per column, with the trailing update
 // A22 <- A22 - v w^T - w v^T (p = tau A22 v, w = p - (tau/2)(p^T v) v) applied lazily:
-//   tridiag_head (one workgroup): finishes w_{k-1} from p, forms row k of the current
-//     matrix with the pending update of step k-1 applied on the fly, and builds v_k;
-//   tridiag_sweep (one wavefront per trailing row j, all compute units): applies the
+//   the head of step k: finishes w_{k-1} from p, forms row k of the current matrix with
+//     the pending update of step k-1 applied on the fly, and builds v_k;
+//   the sweep (one wavefront per trailing row j, all compute units): applies the
 //     pending update of step k-1 to row j of A22 and forms (A22 v_k)_j.
 // A is symmetric, so rows stand for columns and every access is row-contiguous.
 // Outputs: diag, off (T), the reflectors Vh (row k = v_k, from column k+1), tau.
-// pbuf and wbuf (n each) carry A22 v_k and w_k between the two kernels.
+// pbuf (n) carries A22 v_k from one launch to the next; wbuf receives w_k.
 // Head of step k (any block size): finishes w_{k-1} from p, forms row k of the current
 // matrix with the pending update of step k-1 applied on the fly, and builds v_k.
 __device__ void tridiag_head(int n, int k, const double* __restrict__ A, double* __restrict__ Vh,
@@ -615,90 +615,134 @@ __global__ __launch_bounds__(1024) void tridiag_head_kernel(int n, int k, const 
                                                             double* __restrict__ Vh, double* __restrict__ tau,
                                                             const double* __restrict__ pbuf,
                                                             double* __restrict__ wbuf, double* __restrict__ diag,
-                                                            double* __restrict__ off, unsigned int* counter) {
+                                                            double* __restrict__ off) {
     __shared__ double r[1024];            // row k of the current matrix, r[i] for i >= k
     __shared__ double wred[16];
-    if (threadIdx.x == 0) *counter = 0u;
     tridiag_head(n, k, A, Vh, tau, pbuf, wbuf, diag, off, r, wred);
 }
 
-// Step k: one wavefront per trailing row j applies the pending update of step k-1 to
-// row j of A22 and forms (A22 v_k)_j; the last workgroup to finish (atomic counter,
-// with fences on both sides) then runs the head of step k+1, so each column costs
+// Step k (1 <= k <= n - 3; step 0 takes v_0 from tridiag_head_kernel): every workgroup
+// first forms the head of step k in LDS, the same operations as tridiag_head with 256
+// threads: w_{k-1} from p_{k-1} (pin), row k of the current matrix with the pending
+// update of step k-1 applied, and the reflector v_k; workgroup 0 also stores v_k, tau_k,
+// diag[k] and off[k].  Then one wavefront per trailing row j > k applies the pending
+// update of step k-1 to row j of A22 and forms (A22 v_k)_j into pout.  Nothing passes
+// between the workgroups of one launch (p alternates between two buffers, so a
+// workgroup that starts late still reads the previous step's p), and each column costs
 // one launch.
 __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double* __restrict__ A,
                                                            double* __restrict__ Vh, double* __restrict__ tau,
-                                                           double* __restrict__ pbuf, double* __restrict__ wbuf,
-                                                           double* __restrict__ diag, double* __restrict__ off,
-                                                           unsigned int* counter) {
-    __shared__ double r[1024];
+                                                           const double* __restrict__ pin, double* __restrict__ pout,
+                                                           double* __restrict__ diag, double* __restrict__ off) {
+    __shared__ double sw[1024];    // w_{k-1}
+    __shared__ double svp[1024];   // v_{k-1}
+    __shared__ double svk[1024];   // v_k
+    __shared__ double r[1024];     // row k of the current matrix
     __shared__ double wred[16];
-    __shared__ int last;
-    const int lane = threadIdx.x & 63;
-    const int j = k + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j < n) {
-        const double* vk = Vh + (long long)k * n;
-        double* row = A + (long long)j * n;
+    const int t = threadIdx.x, bd = blockDim.x;
+    const bool writer = blockIdx.x == 0;
+    if (k >= 1) {
+        // w_{k-1} = tau p - (tau/2)(tau p^T v) v over rows k..n-1
+        const int kp = k - 1;
+        const double tp = tau[kp];
+        const double* vp = Vh + (long long)kp * n;
+        constexpr int MAXI = 4;              // rows per thread (n <= 1024, 256 threads)
+        double pv[MAXI], vv[MAXI], av[MAXI], wv[MAXI];
+#pragma unroll
+        for (int jj = 0; jj < MAXI; ++jj) {
+            const int i = min(k + t + jj * bd, n - 1);
+            pv[jj] = pin[i];
+            vv[jj] = vp[i];
+            av[jj] = A[(long long)k * n + i];
+        }
         double acc = 0.0;
-        // the loads of U consecutive lane strides are issued together (this loop is a chain
-        // of L2 round trips otherwise); the sum keeps the order i = k + 1 + lane, + 64, ...
-        constexpr int U = 8;
-        if (k >= 1) {
-            const double* vp = Vh + (long long)(k - 1) * n;
-            const double vj = vp[j], wj = wbuf[j];
-            for (int i0 = k + 1 + lane; i0 < n; i0 += 64 * U) {
-                double rv[U], wv[U], pv[U], kv[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int i = min(i0 + 64 * u, n - 1);
-                    rv[u] = row[i];
-                    wv[u] = wbuf[i];
-                    pv[u] = vp[i];
-                    kv[u] = vk[i];
-                }
+        for (int jj = 0; jj < MAXI; ++jj)
+            if (k + t + jj * bd < n) acc = fma(tp * pv[jj], vv[jj], acc);
+        const double half_tpv = 0.5 * tp * block_sum_fast(acc, wred);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int i = i0 + 64 * u;
-                    if (i < n) {
-                        const double a = rv[u] - (vj * wv[u] + wj * pv[u]);
-                        // written through to the device coherence point at once, so the
-                        // fence before the completion count finds no dirty lines to
-                        // write back (it would write back this compute unit's whole L2)
-                        __hip_atomic_store(row + i, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        acc = fma(a, kv[u], acc);
-                    }
-                }
-            }
-        } else {
-            for (int i0 = 1 + lane; i0 < n; i0 += 64 * U) {
-                double rv[U], kv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int i = min(i0 + 64 * u, n - 1);
-                    rv[u] = row[i];
-                    kv[u] = vk[i];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (i0 + 64 * u < n) acc = fma(rv[u], kv[u], acc);
+        for (int jj = 0; jj < MAXI; ++jj) {
+            const int i = k + t + jj * bd;
+            wv[jj] = tp * pv[jj] - half_tpv * vv[jj];
+            if (i < n) {
+                sw[i] = wv[jj];
+                svp[i] = vv[jj];
             }
         }
+        __syncthreads();
+        const double vk = svp[k], wk = sw[k];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0) __hip_atomic_store(pbuf + j, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int jj = 0; jj < MAXI; ++jj) {
+            const int i = k + t + jj * bd;
+            if (i < n) r[i] = av[jj] - (vk * wv[jj] + wk * vv[jj]);
+        }
+        __syncthreads();
+        // the reflector of row k (k + 2 < n)
+        acc = 0.0;
+        for (int i = k + 2 + t; i < n; i += bd) acc = fma(r[i], r[i], acc);
+        const double xn2 = block_sum_fast(acc, wred);
+        const double alpha = r[k + 1];
+        double tk, scale, beta;
+        if (xn2 == 0.0) {
+            tk = 0.0;
+            scale = 0.0;
+            beta = alpha;
+        } else {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tk = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (writer && t == 0) {
+            tau[k] = tk;
+            off[k] = beta;
+            diag[k] = r[k];
+        }
+        for (int i = k + 1 + t; i < n; i += bd) {
+            const double v = (i == k + 1) ? 1.0 : r[i] * scale;
+            svk[i] = v;
+            if (writer) Vh[(long long)k * n + i] = v;
+        }
+    } else {
+        for (int i = 1 + t; i < n; i += bd) svk[i] = Vh[i];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // release only: the rows and p of this workgroup are complete before it is counted
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned int prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1) ? 1 : 0;
+    const int lane = t & 63;
+    const int j = k + 1 + blockIdx.x * 4 + (t >> 6);
+    if (j >= n) return;
+    double* row = A + (long long)j * n;
+    double acc = 0.0;
+    // the loads of U consecutive lane strides are issued together (this loop is a chain
+    // of memory round trips otherwise); the sum keeps the order i = k + 1 + lane, + 64, ...
+    constexpr int U = 8;
+    if (k >= 1) {
+        const double vj = svp[j], wj = sw[j];
+        for (int i0 = k + 1 + lane; i0 < n; i0 += 64 * U) {
+            double rv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = row[min(i0 + 64 * u, n - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < n) {
+                    const double a = rv[u] - (vj * sw[i] + wj * svp[i]);
+                    row[i] = a;
+                    acc = fma(a, svk[i], acc);
+                }
+            }
+        }
+    } else {
+        for (int i0 = 1 + lane; i0 < n; i0 += 64 * U) {
+            double rv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = row[min(i0 + 64 * u, n - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + 64 * u < n) acc = fma(rv[u], svk[i0 + 64 * u], acc);
+        }
     }
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the last one sees every workgroup's rows and p
-    if (threadIdx.x == 0) *counter = 0u;
-    tridiag_head(n, k + 1, A, Vh, tau, pbuf, wbuf, diag, off, r, wred);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) pout[j] = acc;
 }
 
 // Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e,
@@ -1236,8 +1280,8 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(int n, const double* 
 
 void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, double* work, double* small,
                     double* scratch, int* status) {
-    // work: n*n (reflectors); small: 6n + 1 (tau, diag, off, unrefined eigenvalues, p, w, a
-    // completion counter);
+    // work: n*n (reflectors); small: 6n + 1 (tau, diag, off, unrefined eigenvalues, the two
+    // buffers of A22 v, one spare entry);
     // scratch: 6 n*n (inverse iteration, then the cluster rotation)
     double* tau = small;
     double* diag = small + n;
@@ -1249,12 +1293,15 @@ void launch_sym_eig(hipStream_t st, int n, double* A, double* w, double* V, doub
         // small matrices: one workgroup does every step (no per-column launches)
         hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(512), 0, st, n, A, work, tau, diag, off);
     } else {
-        unsigned int* counter = reinterpret_cast<unsigned int*>(small + 6 * n);
-        hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, 0, A, work, tau, pbuf, wbuf, diag, off,
-                           counter);
+        // p of step k goes to pb[k & 1]; the last 2 x 2 block is the head of step n - 2,
+        // with 256 threads like the heads formed inside the steps
+        double* pb[2] = {pbuf, wbuf};
+        hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(1024), 0, st, n, 0, A, work, tau, pbuf, wbuf, diag, off);
         for (int k = 0; k + 2 < n; ++k)
             hipLaunchKernelGGL(tridiag_step_kernel, dim3(grid_for(n - k - 1, 4)), dim3(256), 0, st, n, k, A, work,
-                               tau, pbuf, wbuf, diag, off, counter);
+                               tau, pb[(k + 1) & 1], pb[k & 1], diag, off);
+        hipLaunchKernelGGL(tridiag_head_kernel, dim3(1), dim3(256), 0, st, n, n - 2, A, work, tau, pb[(n - 3) & 1],
+                           pb[(n - 2) & 1], diag, off);
     }
     hipLaunchKernelGGL(tridiag_bisect_kernel, dim3(grid_for((long long)n * BISECT_G, 256)), dim3(256), 0, st, n, diag,
                        off, w0);
