@@ -641,6 +641,16 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double*
     __shared__ double wred[16];
     const int t = threadIdx.x, bd = blockDim.x;
     const bool writer = blockIdx.x == 0;
+    // this wavefront's trailing row j (rows past the end read row n - 1 and store nothing):
+    // its loads are issued first, one lane stride each (64 U >= n), and are in flight
+    // while the head is formed
+    const int lane = t & 63;
+    const int j = k + 1 + blockIdx.x * 4 + (t >> 6);
+    double* row = A + (long long)min(j, n - 1) * n;
+    constexpr int U = 16;
+    double rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rv[u] = row[min(k + 1 + lane + 64 * u, n - 1)];
     if (k >= 1) {
         // w_{k-1} = tau p - (tau/2)(tau p^T v) v over rows k..n-1
         const int kp = k - 1;
@@ -706,38 +716,25 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double*
         for (int i = 1 + t; i < n; i += bd) svk[i] = Vh[i];
     }
     __syncthreads();
-    const int lane = t & 63;
-    const int j = k + 1 + blockIdx.x * 4 + (t >> 6);
     if (j >= n) return;
-    double* row = A + (long long)j * n;
+    // the sum keeps the order i = k + 1 + lane, + 64, ...
     double acc = 0.0;
-    // the loads of U consecutive lane strides are issued together (this loop is a chain
-    // of memory round trips otherwise); the sum keeps the order i = k + 1 + lane, + 64, ...
-    constexpr int U = 8;
     if (k >= 1) {
         const double vj = svp[j], wj = sw[j];
-        for (int i0 = k + 1 + lane; i0 < n; i0 += 64 * U) {
-            double rv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) rv[u] = row[min(i0 + 64 * u, n - 1)];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + 64 * u;
-                if (i < n) {
-                    const double a = rv[u] - (vj * sw[i] + wj * svp[i]);
-                    row[i] = a;
-                    acc = fma(a, svk[i], acc);
-                }
+        for (int u = 0; u < U; ++u) {
+            const int i = k + 1 + lane + 64 * u;
+            if (i < n) {
+                const double a = rv[u] - (vj * sw[i] + wj * svp[i]);
+                row[i] = a;
+                acc = fma(a, svk[i], acc);
             }
         }
     } else {
-        for (int i0 = 1 + lane; i0 < n; i0 += 64 * U) {
-            double rv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) rv[u] = row[min(i0 + 64 * u, n - 1)];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (i0 + 64 * u < n) acc = fma(rv[u], svk[i0 + 64 * u], acc);
+        for (int u = 0; u < U; ++u) {
+            const int i = 1 + lane + 64 * u;
+            if (i < n) acc = fma(rv[u], svk[i], acc);
         }
     }
 #pragma unroll
