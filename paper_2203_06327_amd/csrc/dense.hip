@@ -893,7 +893,7 @@ __global__ __launch_bounds__(256) void tridiag_bisect_kernel(int n, const double
 // alternating buffers, so the recurrences wait on arithmetic, not on memory.  Each solve's right-hand side is the
 // previous solution scaled to unit norm.
 // Output: X[i][j] = component i of eigenvector j (unit 2-norm).
-constexpr int INVIT_B = 8;
+constexpr int INVIT_B = 16;
 __global__ __launch_bounds__(64) void tridiag_invit_kernel(int n, const double* __restrict__ dg,
                                                            const double* __restrict__ eg,
                                                            const double* __restrict__ w, double* __restrict__ X,
