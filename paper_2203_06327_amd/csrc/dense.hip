@@ -518,6 +518,36 @@ __global__ __launch_bounds__(512) void tridiag_kernel(int n, double* __restrict_
     }
 }
 
+// the value of lane l of a wavefront, in every lane
+__device__ inline double lane_bcast(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront with DPP row operations (no LDS traffic); the
+// total is returned in every lane.  Lanes of rows excluded by a row mask add zero.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double wave_sum_dpp(double v) {
+    v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror: sums of 8
+    v += dpp_f64<0x140, 0xF>(v);   // row_mirror: sums of the 16-lane row
+    v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Householder reduction of the symmetric A (n x n) to tridiagonal form T = Q^T A Q,
 // one reflector H_k = I - tau_k v v^T (v_0 = 1) per column, with the trailing update
 // A22 <- A22 - v w^T - w v^T (p = tau A22 v, w = p - (tau/2)(p^T v) v) applied lazily:
@@ -621,125 +651,118 @@ __global__ __launch_bounds__(1024) void tridiag_head_kernel(int n, int k, const 
     tridiag_head(n, k, A, Vh, tau, pbuf, wbuf, diag, off, r, wred);
 }
 
-// Step k (1 <= k <= n - 3; step 0 takes v_0 from tridiag_head_kernel): every workgroup
-// first forms the head of step k in LDS, the same operations as tridiag_head with 256
-// threads: w_{k-1} from p_{k-1} (pin), row k of the current matrix with the pending
-// update of step k-1 applied, and the reflector v_k; workgroup 0 also stores v_k, tau_k,
-// diag[k] and off[k].  Then one wavefront per trailing row j > k applies the pending
-// update of step k-1 to row j of A22 and forms (A22 v_k)_j into pout.  Nothing passes
-// between the workgroups of one launch (p alternates between two buffers, so a
-// workgroup that starts late still reads the previous step's p), and each column costs
-// one launch.
+// Step k (1 <= k <= n - 3; step 0 takes v_0 from tridiag_head_kernel): one wavefront
+// per trailing row j > k, each working alone (no LDS, no barriers).  The wavefront first
+// forms the head of step k over the rows i = k + 1 + lane + 64 u, u < U (64 U >= n): w_{k-1}
+// from p_{k-1} (pin), row k of the current matrix with the pending update of step k-1
+// applied, and the reflector v_k, with its sums over the wavefront by DPP (every
+// wavefront adds in the same order, so all hold the same v_k); wave 0 of workgroup 0
+// (row k + 1) stores v_k, tau_k, diag[k] and off[k].  Then it applies the pending
+// update of step k-1 to row j of A22 and forms (A22 v_k)_j into pout.  p alternates
+// between two buffers, so a wavefront that starts late still reads the previous step's;
+// each column costs one launch.  All of row j's and the head's loads are issued first.
 __global__ __launch_bounds__(256) void tridiag_step_kernel(int n, int k, double* __restrict__ A,
                                                            double* __restrict__ Vh, double* __restrict__ tau,
                                                            const double* __restrict__ pin, double* __restrict__ pout,
                                                            double* __restrict__ diag, double* __restrict__ off) {
-    __shared__ double sw[1024];    // w_{k-1}
-    __shared__ double svp[1024];   // v_{k-1}
-    __shared__ double svk[1024];   // v_k
-    __shared__ double r[1024];     // row k of the current matrix
-    __shared__ double wred[16];
-    const int t = threadIdx.x, bd = blockDim.x;
-    const bool writer = blockIdx.x == 0;
-    // this wavefront's trailing row j (rows past the end read row n - 1 and store nothing):
-    // its loads are issued first, one lane stride each (64 U >= n), and are in flight
-    // while the head is formed
-    const int lane = t & 63;
-    const int j = k + 1 + blockIdx.x * 4 + (t >> 6);
-    double* row = A + (long long)min(j, n - 1) * n;
+    const int lane = threadIdx.x & 63;
+    const int j = k + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;                    // row k + 1 (the writer's) is always in range
+    const bool writer = blockIdx.x == 0 && threadIdx.x < 64;
+    double* row = A + (long long)j * n;
     constexpr int U = 16;
+    const int i0 = k + 1 + lane;
     double rv[U];
+    if (k == 0) {
+        double kv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) rv[u] = row[min(k + 1 + lane + 64 * u, n - 1)];
-    if (k >= 1) {
-        // w_{k-1} = tau p - (tau/2)(tau p^T v) v over rows k..n-1
-        const int kp = k - 1;
-        const double tp = tau[kp];
-        const double* vp = Vh + (long long)kp * n;
-        constexpr int MAXI = 4;              // rows per thread (n <= 1024, 256 threads)
-        double pv[MAXI], vv[MAXI], av[MAXI], wv[MAXI];
-#pragma unroll
-        for (int jj = 0; jj < MAXI; ++jj) {
-            const int i = min(k + t + jj * bd, n - 1);
-            pv[jj] = pin[i];
-            vv[jj] = vp[i];
-            av[jj] = A[(long long)k * n + i];
+        for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + 64 * u, n - 1);
+            rv[u] = row[i];
+            kv[u] = Vh[i];
         }
         double acc = 0.0;
 #pragma unroll
-        for (int jj = 0; jj < MAXI; ++jj)
-            if (k + t + jj * bd < n) acc = fma(tp * pv[jj], vv[jj], acc);
-        const double half_tpv = 0.5 * tp * block_sum_fast(acc, wred);
+        for (int u = 0; u < U; ++u)
+            if (i0 + 64 * u < n) acc = fma(rv[u], kv[u], acc);
+        acc = wave_sum_dpp(acc);
+        if (lane == 0) pout[j] = acc;
+        return;
+    }
+    const double* vp = Vh + (long long)(k - 1) * n;
+    const double* ak_row = A + (long long)k * n;
+    double pv[U], vv[U], av[U];
 #pragma unroll
-        for (int jj = 0; jj < MAXI; ++jj) {
-            const int i = k + t + jj * bd;
-            wv[jj] = tp * pv[jj] - half_tpv * vv[jj];
-            if (i < n) {
-                sw[i] = wv[jj];
-                svp[i] = vv[jj];
-            }
-        }
-        __syncthreads();
-        const double vk = svp[k], wk = sw[k];
+    for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + 64 * u, n - 1);
+        rv[u] = row[i];
+        pv[u] = pin[i];
+        vv[u] = vp[i];
+        av[u] = ak_row[i];
+    }
+    const double tp = tau[k - 1];
+    const double pk = pin[k], vk = vp[k], ak = ak_row[k];
+    const double pj = pin[j], vj = vp[j];
+    // w_{k-1} = tau p - (tau/2)(tau p^T v) v over rows k..n-1
+    double acc = (lane == 0) ? tp * pk * vk : 0.0;
 #pragma unroll
-        for (int jj = 0; jj < MAXI; ++jj) {
-            const int i = k + t + jj * bd;
-            if (i < n) r[i] = av[jj] - (vk * wv[jj] + wk * vv[jj]);
-        }
-        __syncthreads();
-        // the reflector of row k (k + 2 < n)
-        acc = 0.0;
-        for (int i = k + 2 + t; i < n; i += bd) acc = fma(r[i], r[i], acc);
-        const double xn2 = block_sum_fast(acc, wred);
-        const double alpha = r[k + 1];
-        double tk, scale, beta;
-        if (xn2 == 0.0) {
-            tk = 0.0;
-            scale = 0.0;
-            beta = alpha;
-        } else {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tk = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        if (writer && t == 0) {
+    for (int u = 0; u < U; ++u)
+        if (i0 + 64 * u < n) acc = fma(tp * pv[u], vv[u], acc);
+    const double half_tpv = 0.5 * tp * wave_sum_dpp(acc);
+    const double wk = tp * pk - half_tpv * vk;
+    const double wj = tp * pj - half_tpv * vj;
+    double wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) wv[u] = tp * pv[u] - half_tpv * vv[u];
+    // row k of the current matrix (entries k + 1 ..) and the reflector of row k
+    double r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = av[u] - (vk * wv[u] + wk * vv[u]);
+    double xs = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = i0 + 64 * u;
+        if (i > k + 1 && i < n) xs = fma(r[u], r[u], xs);
+    }
+    const double xn2 = wave_sum_dpp(xs);
+    const double alpha = lane_bcast(r[0], 0);          // entry k + 1
+    double tk, scale, beta;
+    if (xn2 == 0.0) {
+        tk = 0.0;
+        scale = 0.0;
+        beta = alpha;
+    } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tk = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    double vkn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) vkn[u] = (i0 + 64 * u == k + 1) ? 1.0 : r[u] * scale;
+    if (writer) {
+        if (lane == 0) {
             tau[k] = tk;
             off[k] = beta;
-            diag[k] = r[k];
+            diag[k] = ak - (vk * wk + wk * vk);
         }
-        for (int i = k + 1 + t; i < n; i += bd) {
-            const double v = (i == k + 1) ? 1.0 : r[i] * scale;
-            svk[i] = v;
-            if (writer) Vh[(long long)k * n + i] = v;
-        }
-    } else {
-        for (int i = 1 + t; i < n; i += bd) svk[i] = Vh[i];
+        double* vrow = Vh + (long long)k * n;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + 64 * u < n) vrow[i0 + 64 * u] = vkn[u];
     }
-    __syncthreads();
-    if (j >= n) return;
-    // the sum keeps the order i = k + 1 + lane, + 64, ...
-    double acc = 0.0;
-    if (k >= 1) {
-        const double vj = svp[j], wj = sw[j];
+    // row j: the pending update of step k-1, then (A22 v_k)_j
+    double pacc = 0.0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = k + 1 + lane + 64 * u;
-            if (i < n) {
-                const double a = rv[u] - (vj * sw[i] + wj * svp[i]);
-                row[i] = a;
-                acc = fma(a, svk[i], acc);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = 1 + lane + 64 * u;
-            if (i < n) acc = fma(rv[u], svk[i], acc);
+    for (int u = 0; u < U; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n) {
+            const double a = rv[u] - (vj * wv[u] + wj * vv[u]);
+            row[i] = a;
+            pacc = fma(a, vkn[u], pacc);
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) pout[j] = acc;
+    pacc = wave_sum_dpp(pacc);
+    if (lane == 0) pout[j] = pacc;
 }
 
 // Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e,
@@ -798,28 +821,6 @@ __device__ inline double dot_strided(const double* a, int sa, const double* b, i
     }
     for (; i < len; ++i) acc[0] = fma(a[i * sa], b[i * sb], acc[0]);
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
-}
-
-// Sum over the 64 lanes of a wavefront with DPP row operations (no LDS traffic); the
-// total is returned in every lane.  Lanes of rows excluded by a row mask add zero.
-template <int CTRL, int ROWMASK>
-__device__ inline double dpp_f64(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWMASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ inline double wave_sum_dpp(double v) {
-    v += dpp_f64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141, 0xF>(v);   // row_half_mirror: sums of 8
-    v += dpp_f64<0x140, 0xF>(v);   // row_mirror: sums of the 16-lane row
-    v += dpp_f64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp_f64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3: lane 63 holds the total
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Bisection with 32-way multisection: 32 threads per eigenvalue (several workgroups)
@@ -1407,12 +1408,6 @@ void launch_cholqr_coef(hipStream_t st, int b, const double* G, double* C, int* 
 // Outputs theta[0..s) ascending (theta[s..m) = +inf) and Cfull = [Q_s | C_p] (m x cw).
 constexpr int RR_S_MAX = BPJD_MAX_BLOCK;
 
-__device__ inline double lane_bcast(double v, int l) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 __device__ inline void wave_lds_sync() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();
