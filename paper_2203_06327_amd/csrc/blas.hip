@@ -411,12 +411,13 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(int n, int a, int b, con
 
 // The same Gram product for the blocked layout with whole runs (ld = bw, a and b multiples
 // of bw, 16-byte aligned block bases, bs even): the workgroup's chunk is taken in
-// sub-tiles of GM_ROWS rows whose runs of A and B are copied into LDS by direct
+// sub-tiles of gr rows whose runs of A and B are copied into LDS by direct
 // global-to-LDS loads (16 bytes per lane), double-buffered: the copy of sub-tile i + 1 is
-// in flight while sub-tile i is multiplied.  Wavefront w takes k-steps w and w + 4 of each
-// sub-tile, so every accumulator sees the rows in the order gram_mfma_kernel uses, and
-// the wavefronts' accumulators are added in the same order: both give identical results.
-constexpr int GM_ROWS = 32;
+// in flight while sub-tile i is multiplied.  Wavefront w takes k-steps w, w + 4, ... of
+// each sub-tile.  The sub-tile height gr (64, 48 or 32 rows) is the largest whose two
+// buffers fit in 64 KB: each wait covers one round trip, so the bytes in flight per
+// workgroup set the bandwidth (32-row sub-tiles of 26 to 39 columns fell short of it).
+constexpr int GM_ROWS_MAX = 64;
 
 // direct global-to-LDS copies: lane l's 16 (4) bytes at g land at l + 16 (4) * lane bytes,
 // l the same for the whole wavefront; completion is counted by vmcnt
@@ -446,15 +447,15 @@ template <int TA, int TB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TA * TB >= 16 ? 2 : 3))) void gram_flat_kernel(
     int n, int a, int b, const double* __restrict__ A,
                                                         const double* __restrict__ B, int bw, long long bs,
-                                                        int chunk, double* __restrict__ partial) {
+                                                        int chunk, int gr, double* __restrict__ partial) {
     extern __shared__ __align__(16) double gm_smem[];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63, lr = lane & 15, lk = lane >> 4;
-    const int runl = GM_ROWS * bw;
+    const int runl = gr * bw;
     const int nra = a / bw, nrb = b / bw;
-    const int bufsz = GM_ROWS * (a + b);       // one sub-tile: A's runs, then B's
+    const int bufsz = gr * (a + b);       // one sub-tile: A's runs, then B's
     const int r0 = blockIdx.x * chunk;
     const int r1 = min(n, r0 + chunk);
-    const int nst = (r1 - r0 + GM_ROWS - 1) / GM_ROWS;
+    const int nst = (r1 - r0 + gr - 1) / gr;
     // LDS offsets of this lane's columns within a sub-tile (-1: past a or b)
     int oa[TA], ob[TB];
 #pragma unroll
@@ -465,14 +466,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TA * TB >= 
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
         const int c = 16 * q + lr, jb = c / bw;
-        ob[q] = (c < b) ? GM_ROWS * a + jb * runl + (c - jb * bw) : -1;
+        ob[q] = (c < b) ? gr * a + jb * runl + (c - jb * bw) : -1;
     }
     auto fetch = [&](int i) {
-        const int rs = r0 + GM_ROWS * i;
-        const int cnt = min(GM_ROWS, r1 - rs) * bw;
+        const int rs = r0 + gr * i;
+        const int cnt = min(gr, r1 - rs) * bw;
         double* buf = gm_smem + (i & 1) * bufsz;
         lds_copy_runs(A, bs, (long long)rs * bw, cnt, buf, runl, nra, w, lane, t);
-        lds_copy_runs(B, bs, (long long)rs * bw, cnt, buf + GM_ROWS * a, runl, nrb, w, lane, t);
+        lds_copy_runs(B, bs, (long long)rs * bw, cnt, buf + gr * a, runl, nrb, w, lane, t);
     };
     dx4_t acc[TA][TB];
 #pragma unroll
@@ -485,9 +486,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TA * TB >= 
         __syncthreads();                       // sub-tile i is in; sub-tile i - 1's buffer is free
         if (i + 1 < nst) fetch(i + 1);
         const double* buf = gm_smem + (i & 1) * bufsz;
-        const int rows = min(GM_ROWS, r1 - (r0 + GM_ROWS * i));
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        const int rows = min(gr, r1 - (r0 + gr * i));
+        for (int h = 0; h < (gr >> 4); ++h) {
             const int row = 4 * (w + 4 * h) + lk;
             const bool rok = row < rows;
             double av[TA], bv[TB];
@@ -566,25 +566,25 @@ static int resident_blocks(K kernel, size_t smem) {
 // once (at most npart; whole sub-tiles per chunk): every chunk then runs in the first
 // and only round, with no tail round of a few long workgroups.  Returns the grid.
 template <int TA, int TB>
-static int gram_flat_launch(hipStream_t st, size_t smem, int n, int a, int b, const double* A, const double* B,
-                            int bw, long long bs, int npart, double* partial) {
+static int gram_flat_launch(hipStream_t st, size_t smem, int gr, int n, int a, int b, const double* A,
+                            const double* B, int bw, long long bs, int npart, double* partial) {
     auto kernel = gram_flat_kernel<TA, TB>;
     int groups = resident_blocks(kernel, smem);
     groups = (groups <= 0) ? npart : std::min(groups, npart);
-    const int chunk = (((n + groups - 1) / groups) + GM_ROWS - 1) / GM_ROWS * GM_ROWS;
+    const int chunk = (((n + groups - 1) / groups) + gr - 1) / gr * gr;
     const int grid = std::max(1, (n + chunk - 1) / chunk);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), smem, st, n, a, b, A, B, bw, bs, chunk, partial);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), smem, st, n, a, b, A, B, bw, bs, chunk, gr, partial);
     return grid;
 }
 
 template <int TA>
-static int gram_flat_dispatch_b(hipStream_t st, int TB, size_t smem, int n, int a, int b, const double* A,
+static int gram_flat_dispatch_b(hipStream_t st, int TB, size_t smem, int gr, int n, int a, int b, const double* A,
                                 const double* B, int bw, long long bs, int npart, double* partial) {
     switch (TB) {
-        case 1: return gram_flat_launch<TA, 1>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
-        case 2: return gram_flat_launch<TA, 2>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
-        case 3: return gram_flat_launch<TA, 3>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
-        default: return gram_flat_launch<TA, 4>(st, smem, n, a, b, A, B, bw, bs, npart, partial);
+        case 1: return gram_flat_launch<TA, 1>(st, smem, gr, n, a, b, A, B, bw, bs, npart, partial);
+        case 2: return gram_flat_launch<TA, 2>(st, smem, gr, n, a, b, A, B, bw, bs, npart, partial);
+        case 3: return gram_flat_launch<TA, 3>(st, smem, gr, n, a, b, A, B, bw, bs, npart, partial);
+        default: return gram_flat_launch<TA, 4>(st, smem, gr, n, a, b, A, B, bw, bs, npart, partial);
     }
 }
 
@@ -609,15 +609,17 @@ void launch_gram(hipStream_t st, int n, int a, int b, const double* A, const dou
     const int TA = (a + 15) / 16, TB = (b + 15) / 16;
     // the flat form: whole runs of the blocked layout, 16-byte aligned; LDS for two
     // sub-tiles, or for the accumulator hand-over when that is larger
-    const size_t smem = sizeof(double) * std::max<size_t>(2 * (size_t)GM_ROWS * (a + b), 2 * (size_t)TA * TB * 256);
+    int gr = GM_ROWS_MAX;                      // sub-tile rows: two sub-tiles within 64 KB
+    while (gr > 32 && 2 * (size_t)gr * (a + b) * sizeof(double) > 65536) gr -= 16;
+    const size_t smem = sizeof(double) * std::max<size_t>(2 * (size_t)gr * (a + b), 2 * (size_t)TA * TB * 256);
     if (g.ld == g.bw && g.bw >= 1 && a % g.bw == 0 && b % g.bw == 0 && g.bs % 2 == 0 && smem <= 65536 &&
         ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0) {
         int fgrid;
         switch (TA) {
-            case 1: fgrid = gram_flat_dispatch_b<1>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
-            case 2: fgrid = gram_flat_dispatch_b<2>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
-            case 3: fgrid = gram_flat_dispatch_b<3>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
-            default: fgrid = gram_flat_dispatch_b<4>(st, TB, smem, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            case 1: fgrid = gram_flat_dispatch_b<1>(st, TB, smem, gr, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            case 2: fgrid = gram_flat_dispatch_b<2>(st, TB, smem, gr, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            case 3: fgrid = gram_flat_dispatch_b<3>(st, TB, smem, gr, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
+            default: fgrid = gram_flat_dispatch_b<4>(st, TB, smem, gr, n, a, b, A, B, g.bw, g.bs, npart, partial); break;
         }
         launch_reduce(st, fgrid, a * b, partial, C);
         return;
