@@ -560,6 +560,7 @@ struct HostPlan {
     std::vector<int> kpptr, kpcol, khptr, khcol;
     std::vector<int> sptr, sidx, bw, lptr, ldd, lpos, rptr, ridx;
     std::vector<long long> Loff;
+    std::vector<int> sysord;    // launch order of the (subdomain, shift) systems
     bool blocked = false;
     int maxE = 0, bws = 64;
     long long Ltot = 0;
@@ -610,6 +611,7 @@ static int device_layout(bpjd_problem* p, const HostPlan& h, Op&& op) {
     put(&p->rptr, h.rptr);
     put(&p->ridx, h.ridx);
     put(&p->Loff, h.Loff);
+    put(&p->sysord, h.sysord);
     zero(&p->sd, (size_t)p->sumN * h.maxE);
     zero(&p->sv, (size_t)p->sumN * h.maxE);
     const size_t nH2 = (size_t)nH * nH;
@@ -824,6 +826,17 @@ static int finish_create(bpjd_ctx* ctx, HostCSR& K, HostCSR& M, Pattern& U, Host
         const long long nl = sptr[l + 1] - sptr[l];
         Ltot += blocked ? (long long)s * ((nl + 15) / 16) * 16 * bws : (long long)s * nl * (bw[l] + 1);
     }
+    // the local solvers take system sysord[b] in workgroup b: larger subdomains first, so
+    // the last systems to start, which run while the device empties, are the smallest
+    std::vector<int> sysord((size_t)nsub * s);
+    {
+        std::vector<int> byl(nsub);
+        std::iota(byl.begin(), byl.end(), 0);
+        std::stable_sort(byl.begin(), byl.end(),
+                         [&](int x, int y) { return sptr[x + 1] - sptr[x] > sptr[y + 1] - sptr[y]; });
+        for (int q = 0; q < nsub; ++q)
+            for (int i = 0; i < s; ++i) sysord[(size_t)q * s + i] = byl[q] * s + i;
+    }
 
     clk.mark("reverse_map");
     // P^T and Galerkin patterns
@@ -956,6 +969,7 @@ static int finish_create(bpjd_ctx* ctx, HostCSR& K, HostCSR& M, Pattern& U, Host
     h->rptr = std::move(rptr);
     h->ridx = std::move(ridx);
     h->Loff = std::move(Loff);
+    h->sysord = std::move(sysord);
     h->blocked = blocked;
     h->maxE = maxE;
     h->bws = bws;
@@ -1145,11 +1159,11 @@ static void apply_precond(bpjd_problem* p, const double* F, double* Z, int ldz, 
         if (mixed)
             launch_local_solve_f32(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->mfma_nt,
                                    p->slotE, p->bws, p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
-                                   (float*)p->Lwork, p->Loff, p->status, p->negflag, p->ldlt_threads);
+                                   (float*)p->Lwork, p->Loff, p->sysord, p->status, p->negflag, p->ldlt_threads);
         else
             launch_local_solve_f64(st, mode, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, p->mfma_nt,
                                    p->slotE, p->bws, p->sd, p->sv, p->lam, (const double*)p->Floc,
-                                   (double*)p->zloc, (double*)p->Lwork, p->Loff, p->status, p->negflag,
+                                   (double*)p->zloc, (double*)p->Lwork, p->Loff, p->sysord, p->status, p->negflag,
                                    p->ldlt_threads);
         if (mode == 0) PH_END(T);
     }
@@ -1593,11 +1607,11 @@ static int autotune(bpjd_problem* p) {
             if (mixed)
                 launch_local_solve_f32(st, 0, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, 0, p->slotE, p->bws,
                                        p->sd, p->sv, p->lam, (const float*)p->Floc, (float*)p->zloc,
-                                       (float*)p->Lwork, p->Loff, p->status, p->negflag, th);
+                                       (float*)p->Lwork, p->Loff, p->sysord, p->status, p->negflag, th);
             else
                 launch_local_solve_f64(st, 0, p->nsub, s, p->maxC, p->sumN, p->subptr, p->bw, 0, p->slotE, p->bws,
                                        p->sd, p->sv, p->lam, (const double*)p->Floc, (double*)p->zloc,
-                                       (double*)p->Lwork, p->Loff, p->status, p->negflag, th);
+                                       (double*)p->Lwork, p->Loff, p->sysord, p->status, p->negflag, th);
         }, &p->ldlt_threads));
     }
     return BPJD_OK;

@@ -143,12 +143,14 @@ void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv,
                             const double* lam, const double* Floc, double* zloc, double* Lwork,
-                            const long long* Loff, int* status, int* negflag, int threads = 256);
+                            const long long* Loff, const int* sysord, int* status, int* negflag,
+                            int threads = 256);
 void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv,
                             const double* lam, const float* Floc, float* zloc, float* Lwork,
-                            const long long* Loff, int* status, int* negflag, int threads = 256);
+                            const long long* Loff, const int* sysord, int* status, int* negflag,
+                            int threads = 256);
 // Numeric local extraction: fixed-slot lower entries (offset, (K, M)) of every local row.
 void launch_extract_local(hipStream_t st, long long sumN, int E, const int* lptr, const int* ldd, const int* lpos,
                           const double2* km, int* sd, double2* sv);
@@ -269,6 +271,7 @@ struct bpjd_problem {
     int *lptr = nullptr, *ldd = nullptr, *lpos = nullptr;
     int *rptr = nullptr, *ridx = nullptr;
     long long* Loff = nullptr;
+    int* sysord = nullptr;             // launch order of the local systems (larger subdomains first)
     int slotE = 0;                     // fixed slots per local row (lower entries incl. the diagonal)
     bool blocked = false;              // local solver: blocked MFMA (true) or windowed
     int mfma_nt = 0;                   // blocked solver's window tile-rows (4 or 6), 0 = windowed

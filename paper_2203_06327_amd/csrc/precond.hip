@@ -687,8 +687,8 @@ template <typename T, int MODE, int NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T, NT>::value, 8))) void local_band_mfma_kernel(
     int s, int E, int BWS, const int* __restrict__ subptr, const int* __restrict__ sd, const double2* __restrict__ sv,
     const double* __restrict__ lam, const T* __restrict__ Floc, long long ldF, T* __restrict__ zloc,
-    T* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
-    int* __restrict__ negflag) {
+    T* __restrict__ Lwork, const long long* __restrict__ Loff, const int* __restrict__ sysord,
+    int* __restrict__ status, int* __restrict__ negflag) {
     constexpr int mode = MODE;
     using MT = MfmaTile<T>;
     using acc_t = typename MT::acc;
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BandWaves<T,
     __shared__ T colsum[16];
     auto VEC = [&](const int r) -> T& { return vec[r]; };
     auto CSUM = [&](const int c) -> T& { return colsum[c]; };
-    const int sys = blockIdx.x;
+    const int sys = sysord[blockIdx.x];        // larger subdomains first (host-planned order)
     // mode 0: shift lambda_i, and negflag[sys] records a negative pivot (K_l - lambda_i M_l
     // indefinite); mode 1: only the recorded systems, again with shift 0
     if (mode && !negflag[sys]) return;
@@ -1136,8 +1136,8 @@ __global__ __launch_bounds__(256) void local_band_wide_kernel(
     int s, int E, const int* __restrict__ subptr, const int* __restrict__ bwv, const int* __restrict__ sd,
     const double2* __restrict__ sv,
     const double* __restrict__ lam, const float* __restrict__ Floc, long long ldF, float* __restrict__ zloc,
-    float* __restrict__ Lwork, const long long* __restrict__ Loff, int* __restrict__ status,
-    int* __restrict__ negflag) {
+    float* __restrict__ Lwork, const long long* __restrict__ Loff, const int* __restrict__ sysord,
+    int* __restrict__ status, int* __restrict__ negflag) {
     // Four wavefronts per system, one per SIMD.  Wave w < 3 holds window rows 64 w ..
     // 64 w + 63 (row set w); wave 3 brings in the entering tile-rows.  Wave 0 eliminates
     // the pivot block (and its rows 16..63) while wave 3 places the next tile-row; waves 1
@@ -1158,7 +1158,7 @@ __global__ __launch_bounds__(256) void local_band_wide_kernel(
     __shared__ T colsum[16];
     __shared__ T ucol[16][17];                 // column c of the panel at elimination step c
     __shared__ T urc[16], uyc[16];             // pivot reciprocal and y_c of step c
-    const int sys = blockIdx.x;
+    const int sys = sysord[blockIdx.x];        // larger subdomains first (host-planned order)
     if (MODE && !negflag[sys]) return;         // uniform over the workgroup
     const int l = sys / s;
     const int i = sys - l * s;
@@ -1454,13 +1454,13 @@ __global__ __launch_bounds__(256) void local_band_wide_kernel(
 template <typename T>
 static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s, int E, int bws, long long sumN,
                               const int* subptr, const int* bw, const int* sd, const double2* sv, const double* lam, const T* Floc,
-                              T* zloc, T* Lwork, const long long* Loff, int* status, int* negflag) {
+                              T* zloc, T* Lwork, const long long* Loff, const int* sysord, int* status, int* negflag) {
     // mode 0: every system with shift lambda_i; mode 1: the systems found indefinite,
     // again with shift 0 (its waves return at once when no system was flagged).
     // nt: window tile-rows (4 or 6; 12: the wide FP32 kernel, whose stored columns are full)
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(64), 0, st, s, E, bws, subptr, sd, sv, lam, Floc, sumN, zloc,
-                           Lwork, Loff, status, negflag);
+                           Lwork, Loff, sysord, status, negflag);
     };
     if (nt == 4) {
         if (mode == 0) go(local_band_mfma_kernel<T, 0, 4>);
@@ -1469,7 +1469,7 @@ static void launch_local_mfma(hipStream_t st, int mode, int nt, int nsub, int s,
         if constexpr (sizeof(T) == 4) {
             auto wide = [&](auto kernel) {
                 hipLaunchKernelGGL(kernel, dim3(nsub * s), dim3(256), 0, st, s, E, subptr, bw, sd, sv, lam, Floc,
-                                   sumN, zloc, Lwork, Loff, status, negflag);
+                                   sumN, zloc, Lwork, Loff, sysord, status, negflag);
             };
             if (mode == 0) wide(local_band_wide_kernel<0>);
             else wide(local_band_wide_kernel<1>);
@@ -1492,10 +1492,10 @@ static void launch_local(hipStream_t st, int nsub, int s, int maxC, long long su
 void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv, const double* lam, const double* Floc, double* zloc, double* Lwork,
-                            const long long* Loff, int* status, int* negflag, int threads) {
+                            const long long* Loff, const int* sysord, int* status, int* negflag, int threads) {
     if (blocked) {
         launch_local_mfma<double>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, bw, sd, sv, lam, Floc, zloc, Lwork, Loff,
-                               status, negflag);
+                               sysord, status, negflag);
         return;
     }
     if (mode == 0)   // the windowed solver takes its second pass inside the kernel
@@ -1506,10 +1506,10 @@ void launch_local_solve_f64(hipStream_t st, int mode, int nsub, int s, int maxC,
 void launch_local_solve_f32(hipStream_t st, int mode, int nsub, int s, int maxC, long long sumN,
                             const int* subptr, const int* bw, int blocked, int E, int bws, const int* sd,
                             const double2* sv, const double* lam, const float* Floc, float* zloc, float* Lwork,
-                            const long long* Loff, int* status, int* negflag, int threads) {
+                            const long long* Loff, const int* sysord, int* status, int* negflag, int threads) {
     if (blocked) {
         launch_local_mfma<float>(st, mode, blocked, nsub, s, E, bws, sumN, subptr, bw, sd, sv, lam, Floc, zloc, Lwork, Loff,
-                               status, negflag);
+                               sysord, status, negflag);
         return;
     }
     if (mode == 0)   // the windowed solver takes its second pass inside the kernel
